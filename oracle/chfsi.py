@@ -13,7 +13,8 @@ paper is silent (it cites the method rather than stating it):
 * orthonormalization: Cholesky-Gram-Schmidt Q = Y L^-*, L L^* = Y^* Y (the
   R factor of a QR factorization with positive diagonal), formed from the
   Jacobi-scaled Gram matrix (identical Q in exact arithmetic), repeated once
-  when max|Q^* Q - I| > 1e-12;
+  when max|Q^* Q - I| > 1e-12; breakdown is declared when a squared pivot of
+  the scaled (unit-diagonal) Gram matrix is at or below n * 2^-52;
 * Rayleigh-Ritz in the symmetric form: Q^* Q = I so the projected overlap is
   the identity; the next block is the Ritz vectors Q U (same span as Q);
 * pass 1 uses a = (a0 + b) / 2; later passes a0 = theta_1, a = theta_nv of the
@@ -116,6 +117,11 @@ def cholgs_once(Y: np.ndarray):
                 col = j - 1
                 break
         raise CholeskyBreakdown(col)
+    # numerical rank deficiency: a pivot of the unit-diagonal scaled Gram matrix at or below n u
+    piv = np.real(np.diag(Ls)) ** 2
+    small = np.nonzero(~(piv > Gs.shape[0] * np.finfo(float).eps))[0]
+    if small.size:
+        raise CholeskyBreakdown(int(small[0]))
     # Q = (Y d) Ls^-*  <=>  Ls Q^* = (Y d)^*
     QH = sla.solve_triangular(Ls, np.conj((Y * d[None, :]).T), lower=True)
     return np.conj(QH.T), (Ls / d[:, None])
