@@ -1,0 +1,186 @@
+/*
+ * oefe.h -- C ABI of the MI355X library for the Chebyshev-filtered subspace
+ * iteration (ChFSI) on the orthogonalized-enriched finite-element (OEFE)
+ * Kohn-Sham operator (Rufus, Kanungo, Gavini, arXiv 2010.09701).
+ *
+ * Operator.  The discrete generalized problem H u = eps M u (eqnKSEigGenDiscrete)
+ * with block-diagonal overlap M = diag(M^cc, M^oo) (eqnMOEFE, eqnMOEFEInv) is
+ * used in the symmetric standard form
+ *
+ *     Ht = M^-1/2 H M^-1/2,   M^-1/2 = diag(m^-1/2) (+) S,  S = (M^oo)^-1/2,
+ *
+ * which has the eigenvalues of (M^O)^-1 H^O (eqnKSEignStandDiscrete).  H is
+ * 1/2 int grad N* . grad N + int V N* N (eqnHOEFEelelements) over the basis of
+ * spectral (GLL) Lagrange elements plus orthogonalized enrichment functions
+ * N^O = N^A - N^B (eqnUOEFESplit, eqnUOEFEAtomic, eqnKSAtomicTrunc,
+ * eqnorthCGLL).  At a Bloch wavevector k the basis functions carry the Bloch
+ * phase (the FE gather is phase-twisted) and the operator is Hermitian.
+ *
+ * Conventions (all entry points):
+ *  - Return value: OEFE_OK (0) or a negative oefe_status.  Argument checks are
+ *    synchronous; oefe_last_error() gives a message for the last failure on the
+ *    calling thread.
+ *  - Vectors are row-major blocks [n_tot x ld] of device memory, ld >= nv,
+ *    FE rows first (global FE index g = i + n j + n^2 k, n = nc p), then the
+ *    enrichment rows in the order of the enrichment list.  Complex blocks are
+ *    interleaved (re, im); ld and nv count complex elements.
+ *  - Device buffers (vectors, `work`, outputs marked "device") are owned by the
+ *    caller; the library never allocates in the compute calls.  `work` must hold
+ *    at least oefe_work_size(op, prec, nv) bytes, 256-byte aligned.
+ *  - All compute calls are ordered on the caller's HIP stream; calls that
+ *    return host values (lanczos_bounds, cholgs) synchronize that stream.
+ *  - An oefe_op handle is not thread-safe; one handle per device.
+ */
+#ifndef OEFE_H
+#define OEFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* oefe_stream; /* a hipStream_t (NULL = default stream) */
+
+typedef enum {
+  OEFE_OK = 0,
+  OEFE_EINVAL = -1,       /* bad shape, pointer, leading dimension or precision */
+  OEFE_ENOMEM = -2,       /* device allocation failed in oefe_op_create */
+  OEFE_EDEVICE = -3,      /* HIP runtime error (message via oefe_last_error) */
+  OEFE_ENOTSPD = -4,      /* Cholesky breakdown: Gram matrix not positive definite */
+  OEFE_ENOCONV = -5,      /* dense eigensolver did not converge */
+  OEFE_EUNSUPPORTED = -6  /* precision / degree / operator kind not supported */
+} oefe_status;
+
+/* Element type and arithmetic of the vector block.
+ *  F64   real float64 (Gamma-point operator)
+ *  F32   real float32 vectors and float32 arithmetic in the filter / H apply
+ *  BF16  real float32 vectors; the cell-level contractions take bfloat16
+ *        operands (round-to-nearest-even) with float32 accumulation
+ *  C128  complex128 (Bloch operator)
+ *  C64   complex64 (Bloch operator, float32 arithmetic)
+ * cholgs / rayleigh_ritz / lanczos_bounds run in float64 (F64 or C128). */
+typedef enum { OEFE_F64 = 0, OEFE_F32 = 1, OEFE_BF16 = 2, OEFE_C128 = 3, OEFE_C64 = 4 } oefe_prec;
+
+/* System description (host memory; copied by oefe_op_create).
+ * Periodic cube [0, L)^3 with nc^3 hex cells of degree p (p + 1 GLL nodes per
+ * edge; p in {2, 3, 4}).  Atoms at pos[3*I .. 3*I+2] with charge Z[I]; the
+ * potential at the Gauss points is V = sum_I -Z_I erf(r_I / sigma) / r_I with
+ * r_I the nearest-image distance (replace it with oefe_op_set_potential).
+ * Enrichment function nu: atom enr_atom[nu], radial factor
+ * r^enr_power[nu] exp(-enr_zeta[nu] r), times d_x/d_y/d_z if enr_axis[nu] is
+ * 0/1/2 (-1: none), times the smooth cutoff h(r) = 1 (r <= r0), 0 (r >= r1),
+ * 1 / (1 + exp(1/x - 1/(1-x))), x = (r1 - r)/(r1 - r0) in between
+ * (eqnKSAtomicTrunc, eqnCutoffProperties); requires r1 < L / 2.
+ * kvec: NULL for the real Gamma-point operator, else the Bloch wavevector [3]. */
+typedef struct {
+  double L;
+  int32_t nc, p;
+  int32_t n_atoms;
+  const double* pos;
+  const double* Z;
+  double sigma, r0, r1;
+  int32_t n_enr;
+  const int32_t* enr_atom;
+  const int32_t* enr_power;
+  const double* enr_zeta;
+  const int32_t* enr_axis;
+  const double* kvec;
+} oefe_system_desc;
+
+typedef struct oefe_op_s* oefe_op;
+
+/* Build the operator on the current HIP device: quadrature rules, lumped GLL
+ * mass (eqnMcc), potential, orthogonalized enrichment (eqnorthC, eqnorthCGLL),
+ * blocks M^oo (eqnMoo), H^co, H^oo, S = (M^oo)^-1/2; uploads device data.
+ * Errors: EINVAL (bad description), EUNSUPPORTED (p), ENOMEM, EDEVICE. */
+int oefe_op_create(const oefe_system_desc* desc, oefe_op* out);
+
+/* Test operator Ht = diag(lambda) (n real entries, host memory), no mesh. */
+int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out);
+
+int oefe_op_destroy(oefe_op op);
+
+/* dims[0..7] = n_fe, n_enr, n_tot, n_cells, nq, nc, p, is_complex. */
+int oefe_op_dims(oefe_op op, int64_t* dims);
+
+/* Replace the potential at the quadrature points: V[n_cells * nq] (cell-major,
+ * point index qx + (p+1) qy + (p+1)^2 qz), host memory.  Rebuilds the potential
+ * parts of H^cc, H^co, H^oo (the overlap and S do not depend on V).  Synchronous. */
+int oefe_op_set_potential(oefe_op op, const double* V_host);
+
+/* Copy the current potential and the quadrature weights W_{e,q} to host
+ * arrays of n_cells * nq doubles (either pointer may be NULL). */
+int oefe_op_get_potential(oefe_op op, double* V_host, double* W_host);
+
+/* Copy S = (M^oo)^-1/2 (n_enr^2, row-major; complex interleaved) and the
+ * eigenvalues of M^oo (n_enr) to host (either may be NULL). */
+int oefe_op_get_enrichment(oefe_op op, double* S_host, double* Moo_eigs_host);
+
+/* Bytes of `work` needed by the compute calls below for a block of nv vectors. */
+size_t oefe_work_size(oefe_op op, oefe_prec prec, int32_t nv);
+
+/* Y = Ht X (X, Y device [n_tot x ld], must not overlap).  prec: F64/F32/BF16 for a
+ * real operator, C128/C64 for a Bloch operator. */
+int ham_apply(oefe_op op, oefe_prec prec, const void* X, void* Y, int64_t ld, int32_t nv,
+              void* work, oefe_stream stream);
+
+/* In place X <- T_m(tau(Ht)) X / T_m(tau(a0)), tau(t) = (t - c)/e, e = (b - a)/2,
+ * c = (b + a)/2, by the scaled three-term Chebyshev recurrence (Sec. IV: the
+ * filter maps the unwanted spectrum [a, b] to [-1, 1]).  m >= 1 applications of
+ * Ht; the recurrence scalars are computed in float64.  Requires a < b, a0 < a. */
+int chebyshev_filter(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, int32_t m,
+                     double a, double b, double a0, void* work, oefe_stream stream);
+
+/* Mixed-precision filter on a float64 block: X (F64 or C128 layout, device) is
+ * rounded to float32 (round-to-nearest-even), filtered with prec_filter (F32 or
+ * BF16 for a real operator, C64 for a Bloch operator) as in chebyshev_filter,
+ * and widened back into X.  Same requirements and `work` size rule
+ * (oefe_work_size(op, prec_filter, nv)). */
+int chebyshev_filter_mixed(oefe_op op, oefe_prec prec_filter, void* X, int64_t ld, int32_t nv, int32_t m, double a,
+                           double b, double a0, void* work, oefe_stream stream);
+
+/* k-step Lanczos with full reorthogonalization from v0 (device, n_tot real, or
+ * complex interleaved for a Bloch operator) in float64; out[0] = smallest Ritz
+ * value of T_k, out[1] = largest + beta_k (an upper bound of the spectrum).
+ * out is host memory; synchronizes `stream`.  1 <= k <= 64. */
+int lanczos_bounds(oefe_op op, int32_t k, const double* v0, double* out, void* work, oefe_stream stream);
+
+/* Cholesky-Gram-Schmidt (float64): G = X^* X, G = L L^* (from the Jacobi-scaled
+ * G), X <- X L^-* (the Q of a QR factorization with positive diagonal R),
+ * repeated once when max|Q^* Q - I| > 1e-12.  prec F64 or C128.  On breakdown
+ * returns OEFE_ENOTSPD and, if dev_status (device int32[2]) is given, writes
+ * {OEFE_ENOTSPD, column}.  Synchronizes `stream`. */
+int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
+           oefe_stream stream);
+
+/* Rayleigh-Ritz (eqnProjKS in symmetric form, Q^* Q = I): W = Ht Q,
+ * Hq = Q^* W (Hermitian part), Hq = U diag(theta) U^*, Q <- Q U.
+ * eigvals: device float64 [nv], ascending.  prec F64 or C128. */
+int rayleigh_ritz(oefe_op op, oefe_prec prec, void* Q, int64_t ld, int32_t nv, double* eigvals, void* work,
+                  oefe_stream stream);
+
+/* Band energy E = sum_i f_i x_i^* Ht x_i (device scalar, float64) and its
+ * gradients: dE_dV[e,q] = W_{e,q} sum_i f_i |psi_i(x_{e,q})|^2 (device float64
+ * [n_cells * nq]; psi_i the field of M^-1/2 x_i, the density of eqnrho times W),
+ * dE_dX = 2 Ht X diag(f) (device, layout of X).  f: device float64 [nv].
+ * dE_dV / dE_dX may be NULL.  prec F64/F32 (real) or C128/C64 (Bloch). */
+int band_energy_grad(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* f,
+                     double* E, double* dE_dV, void* dE_dX, void* work, oefe_stream stream);
+
+/* Instrumentation: while enabled, every launch of the cell-level kernel (the
+ * sum-factorized H^cc stage of ham_apply / chebyshev_filter) is bracketed by
+ * HIP events on the caller's stream.  oefe_kernel_timer_read synchronizes,
+ * returns the number of bracketed launches and their summed duration (ms),
+ * and clears the record. */
+int oefe_kernel_timer(oefe_op op, int enable);
+int oefe_kernel_timer_read(oefe_op op, int64_t* launches, double* total_ms);
+
+const char* oefe_strerror(int code);
+const char* oefe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OEFE_H */

@@ -1,0 +1,43 @@
+"""ChFSI driver over the C ABI (Sec. IV of the paper).
+
+A pass is: Chebyshev filter (float64, or float32 / bf16-operand arithmetic on
+a float64 block), Cholesky-Gram-Schmidt (float64), Rayleigh-Ritz (float64).
+Bounds: k-step Lanczos once per operator; pass 1 cuts at a = (a0 + b) / 2,
+later passes use a0 = theta_1 and a = theta_nv of the previous pass.  Only
+scalars (bounds, Ritz values) cross to the host, once per pass.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import oefe
+
+
+def chfsi_run(op: "oefe.Operator", X0: torch.Tensor, v0: torch.Tensor, m: int, passes: int, lanczos_k: int = 10,
+              filter_prec: str = "f64", bounds: Optional[tuple] = None, callback=None) -> dict:
+    """Run `passes` ChFSI passes from X0 (float64 / complex128, on device); returns bounds and Ritz values."""
+    if bounds is None:
+        a0L, b = oefe.lanczos_bounds(op, v0, lanczos_k)
+    else:
+        a0L, b = bounds
+    a0, a = a0L, 0.5 * (a0L + b)
+    X = X0.clone()
+    hist = []
+    for it in range(passes):
+        if filter_prec == "f64":
+            oefe.chebyshev_filter(op, X, m, a, b, a0)
+        elif filter_prec in ("f32", "c64"):
+            oefe.chebyshev_filter_mixed(op, X, m, a, b, a0)
+        elif filter_prec == "bf16":
+            oefe.chebyshev_filter_mixed(op, X, m, a, b, a0, bf16=True)
+        else:
+            raise ValueError(filter_prec)
+        oefe.cholgs(op, X)
+        th = oefe.rayleigh_ritz(op, X).cpu().numpy()
+        hist.append(dict(a=a, b=b, a0=a0, theta=th))
+        if callback is not None:
+            callback(it, X, th)
+        a0, a = float(th[0]), float(th[-1])
+    return dict(a0_lanczos=a0L, b=b, passes=hist, X=X, theta=hist[-1]["theta"])

@@ -1,0 +1,758 @@
+// C ABI entry points (include/oefe.h): operator handles, device upload, and the
+// compute calls built from the kernels in oefe_ops.hip / oefe_linalg.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "oefe_kernels.h"
+
+namespace oefe {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename T>
+int dalloc(T** p, size_t count, std::string& err) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    err = std::string("hipMalloc failed: ") + hipGetErrorString(e);
+    return OEFE_ENOMEM;
+  }
+  return OEFE_OK;
+}
+template <typename T>
+int dput(T** p, const std::vector<T>& h, std::string& err) {
+  int rc = dalloc(p, h.size(), err);
+  if (rc) return rc;
+  if (!h.empty()) {
+    hipError_t e = hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      err = std::string("hipMemcpy failed: ") + hipGetErrorString(e);
+      return OEFE_EDEVICE;
+    }
+  }
+  return OEFE_OK;
+}
+template <typename T>
+int dset(T* p, const std::vector<T>& h, std::string& err) {
+  if (h.empty()) return OEFE_OK;
+  hipError_t e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    err = std::string("hipMemcpy failed: ") + hipGetErrorString(e);
+    return OEFE_EDEVICE;
+  }
+  return OEFE_OK;
+}
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+std::vector<float> to_float(const std::vector<double>& v) {
+  std::vector<float> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+  return o;
+}
+
+// complex host vector -> interleaved doubles (or real parts only)
+std::vector<double> flatten(const std::vector<cplx>& v, bool cplx) {
+  std::vector<double> o(v.size() * (cplx ? 2 : 1));
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (cplx) {
+      o[2 * i] = v[i].real();
+      o[2 * i + 1] = v[i].imag();
+    } else {
+      o[i] = v[i].real();
+    }
+  }
+  return o;
+}
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return OEFE_EDEVICE;
+}
+
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+bool prec_real(int prec) { return prec == OEFE_F64 || prec == OEFE_F32 || prec == OEFE_BF16; }
+bool prec_fp32(int prec) { return prec == OEFE_F32 || prec == OEFE_BF16 || prec == OEFE_C64; }
+
+int check_prec(const oefe_op_s* op, int prec) {
+  if (prec < OEFE_F64 || prec > OEFE_C64) return fail(OEFE_EINVAL, "unknown precision");
+  if (op->cplx && prec_real(prec)) return fail(OEFE_EINVAL, "Bloch operator needs a complex precision (C128/C64)");
+  if (!op->cplx && !prec_real(prec)) return fail(OEFE_EINVAL, "Gamma-point operator needs a real precision");
+  return OEFE_OK;
+}
+
+// ---- layout of `work` beyond the operator step
+struct Layout {
+  StepWork step;
+  size_t step_bytes;
+  char* vecA;  // [n_tot x nv] complex-or-real doubles (E)
+  char* vecB;
+  double* G;       // nv*nv*E
+  double* Rinv;    // nv*nv*E + nv
+  double* U;       // nv*nv*E
+  double* lam;     // nv
+  double* gscr;    // gram scratch
+  double* jscr;    // jacobi scratch
+  double* misc;    // 512 doubles
+  int32_t* status; // 4 ints
+  double* dens;    // density partials
+  size_t total;
+};
+
+int ncols_blocks(int ncr) { return (ncr + 63) / 64; }
+
+Layout layout(const oefe_op_s* op, int prec, int nv, void* work) {
+  Layout L{};
+  const bool cplx = op->cplx;
+  const int E = cplx ? 2 : 1;
+  const int eb = prec_fp32(prec) ? 4 : 8;
+  char* p = (char*)work;
+  int ldc;
+  L.step_bytes = al256(step_work_bytes(op, eb, cplx, nv, &ldc));
+  if (work) L.step = carve_step_work(op, eb, cplx, nv, work);
+  p += L.step_bytes;
+  const size_t vb = al256((size_t)op->n_tot * nv * E * sizeof(double));
+  L.vecA = p; p += vb;
+  L.vecB = p; p += vb;
+  const size_t sq = al256((size_t)nv * nv * E * sizeof(double));
+  L.G = (double*)p; p += sq;
+  L.Rinv = (double*)p; p += sq + al256(nv * sizeof(double));
+  L.U = (double*)p; p += sq;
+  L.lam = (double*)p; p += al256(nv * sizeof(double));
+  const size_t gs = al256(std::max(gram_scratch_bytes(cplx, nv, nv, op->n_tot),
+                                   (size_t)128 * nv * sizeof(double)));
+  L.gscr = (double*)p; p += gs;
+  L.jscr = (double*)p; p += al256(jacobi_scratch_bytes(cplx, nv));
+  L.misc = (double*)p; p += 512 * sizeof(double);
+  L.status = (int32_t*)p; p += 256;
+  const size_t db = op->diagonal ? 256 : al256((size_t)ncols_blocks(cplx ? 2 * nv : nv) * op->n_cells * op->nq * sizeof(double));
+  L.dens = (double*)p; p += db;
+  L.total = (size_t)(p - (char*)work);
+  return L;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int upload_potential_parts(oefe_op_s* op, std::string& err) {
+  const bool cplx = op->cplx;
+  // W V at quadrature points
+  std::vector<double> wv(op->V.size());
+  for (size_t i = 0; i < wv.size(); ++i) wv[i] = op->W[i] * op->V[i];
+  int rc;
+  if (!op->d.WV) {
+    if ((rc = dalloc(&op->d.WV, wv.size(), err))) return rc;
+    if ((rc = dalloc(&op->d.WVf, wv.size(), err))) return rc;
+  }
+  if ((rc = dset(op->d.WV, wv, err))) return rc;
+  if ((rc = dset(op->d.WVf, to_float(wv), err))) return rc;
+  if (op->n_enr == 0) return OEFE_OK;
+  // H^co block values
+  const int E = cplx ? 2 : 1;
+  std::vector<double> hv((size_t)op->n_hrows * op->FMAX * E, 0.0);
+  int64_t base = 0;
+  for (auto& b : op->blocks) {
+    std::vector<std::complex<double>> vals;
+    block_hco_values(op, b, vals);
+    for (size_t r = 0; r < b.rows.size(); ++r)
+      for (int f = 0; f < b.nf; ++f) {
+        const std::complex<double> v = vals[r * b.nf + f];
+        const size_t o = ((size_t)(base + r) * op->FMAX + f) * E;
+        hv[o] = v.real();
+        if (cplx) hv[o + 1] = v.imag();
+      }
+    base += (int64_t)b.rows.size();
+  }
+  if (!op->d.hv) {
+    if ((rc = dalloc(&op->d.hv, hv.size(), err))) return rc;
+    if ((rc = dalloc(&op->d.hvf, hv.size(), err))) return rc;
+    if ((rc = dalloc(&op->d.Hoo, (size_t)op->n_enr * op->n_enr * E, err))) return rc;
+    if ((rc = dalloc(&op->d.Hoof, (size_t)op->n_enr * op->n_enr * E, err))) return rc;
+  }
+  if ((rc = dset(op->d.hv, hv, err))) return rc;
+  if ((rc = dset(op->d.hvf, to_float(hv), err))) return rc;
+  std::vector<double> hoo = flatten(op->Hoo, cplx);
+  if ((rc = dset(op->d.Hoo, hoo, err))) return rc;
+  if ((rc = dset(op->d.Hoof, to_float(hoo), err))) return rc;
+  return OEFE_OK;
+}
+
+int upload_operator(oefe_op_s* op, std::string& err) {
+  int rc;
+  const bool cplx = op->cplx;
+  const int E = cplx ? 2 : 1;
+  if (op->n_enr > 0) {
+    const int nb = (int)op->blocks.size();
+    std::vector<int32_t> fn0(nb), nf(nb), fn_blk(op->n_enr), blk_chunk0(nb + 1);
+    std::vector<int64_t> rptr(nb + 1, 0);
+    std::vector<int32_t> rows;
+    std::vector<int32_t> chunk_blk;
+    std::vector<int64_t> chunk_r0, chunk_r1;
+    for (int b = 0; b < nb; ++b) {
+      auto& B = op->blocks[b];
+      fn0[b] = B.fn0;
+      nf[b] = B.nf;
+      for (int f = 0; f < B.nf; ++f) fn_blk[B.fn0 + f] = b;
+      rptr[b + 1] = rptr[b] + (int64_t)B.rows.size();
+      rows.insert(rows.end(), B.rows.begin(), B.rows.end());
+      blk_chunk0[b] = (int32_t)chunk_blk.size();
+      for (int64_t r = 0; r < (int64_t)B.rows.size(); r += op->chunk_rows) {
+        chunk_blk.push_back(b);
+        chunk_r0.push_back(r);
+        chunk_r1.push_back(std::min<int64_t>((int64_t)B.rows.size(), r + op->chunk_rows));
+      }
+    }
+    blk_chunk0[nb] = (int32_t)chunk_blk.size();
+    op->n_hrows = rptr[nb];
+    op->n_chunks = (int64_t)chunk_blk.size();
+    // row lists
+    std::vector<int64_t> row_ptr(op->N + 1, 0);
+    for (int b = 0; b < nb; ++b)
+      for (int32_t g : op->blocks[b].rows) row_ptr[g + 1]++;
+    for (int64_t g = 0; g < op->N; ++g) row_ptr[g + 1] += row_ptr[g];
+    std::vector<int32_t> row_blk(row_ptr[op->N]);
+    std::vector<int64_t> row_pos(row_ptr[op->N]);
+    std::vector<int64_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+    for (int b = 0; b < nb; ++b) {
+      auto& B = op->blocks[b];
+      for (size_t r = 0; r < B.rows.size(); ++r) {
+        const int64_t k = fill[B.rows[r]]++;
+        row_blk[k] = b;
+        row_pos[k] = rptr[b] + (int64_t)r;
+      }
+    }
+    // N^O at quadrature points by cell
+    std::vector<int64_t> cph_ptr(op->n_cells + 1, 0);
+    for (auto& B : op->blocks)
+      for (int64_t e : B.cells) cph_ptr[e + 1]++;
+    for (int64_t e = 0; e < op->n_cells; ++e) cph_ptr[e + 1] += cph_ptr[e];
+    std::vector<int32_t> cph_blk(cph_ptr[op->n_cells]);
+    std::vector<int64_t> cph_off(cph_ptr[op->n_cells]);
+    std::vector<int64_t> cfill(cph_ptr.begin(), cph_ptr.end() - 1);
+    int64_t total_cells = 0;
+    for (auto& B : op->blocks) total_cells += (int64_t)B.cells.size();
+    std::vector<double> phi((size_t)total_cells * op->nq * op->FMAX * E, 0.0);
+    int64_t off = 0;
+    for (int b = 0; b < nb; ++b) {
+      auto& B = op->blocks[b];
+      for (size_t ci = 0; ci < B.cells.size(); ++ci) {
+        const int64_t k = cfill[B.cells[ci]]++;
+        cph_blk[k] = b;
+        cph_off[k] = off + (int64_t)ci;
+        for (int q = 0; q < op->nq; ++q)
+          for (int f = 0; f < B.nf; ++f) {
+            const std::complex<double> v = B.phi[(ci * op->nq + q) * B.nf + f];
+            const size_t o = (((size_t)(off + ci) * op->nq + q) * op->FMAX + f) * E;
+            phi[o] = v.real();
+            if (cplx) phi[o + 1] = v.imag();
+          }
+      }
+      off += (int64_t)B.cells.size();
+    }
+    if ((rc = dput(&op->d.blk_fn0, fn0, err))) return rc;
+    if ((rc = dput(&op->d.blk_nf, nf, err))) return rc;
+    if ((rc = dput(&op->d.fn_blk, fn_blk, err))) return rc;
+    if ((rc = dput(&op->d.blk_rptr, rptr, err))) return rc;
+    if ((rc = dput(&op->d.blk_rows, rows, err))) return rc;
+    if ((rc = dput(&op->d.blk_chunk0, blk_chunk0, err))) return rc;
+    if ((rc = dput(&op->d.chunk_blk, chunk_blk, err))) return rc;
+    if ((rc = dput(&op->d.chunk_r0, chunk_r0, err))) return rc;
+    if ((rc = dput(&op->d.chunk_r1, chunk_r1, err))) return rc;
+    if ((rc = dput(&op->d.row_ptr, row_ptr, err))) return rc;
+    if ((rc = dput(&op->d.row_blk, row_blk, err))) return rc;
+    if ((rc = dput(&op->d.row_pos, row_pos, err))) return rc;
+    if ((rc = dput(&op->d.cph_ptr, cph_ptr, err))) return rc;
+    if ((rc = dput(&op->d.cph_blk, cph_blk, err))) return rc;
+    if ((rc = dput(&op->d.cph_off, cph_off, err))) return rc;
+    if ((rc = dput(&op->d.phi, phi, err))) return rc;
+    std::vector<double> S = flatten(op->S, cplx);
+    if ((rc = dput(&op->d.S, S, err))) return rc;
+    std::vector<float> Sf = to_float(S);
+    if ((rc = dput(&op->d.Sf, Sf, err))) return rc;
+  } else {
+    // empty row lists so the node kernel can run without enrichment
+    std::vector<int64_t> row_ptr(op->N + 1, 0);
+    if ((rc = dput(&op->d.row_ptr, row_ptr, err))) return rc;
+  }
+  return upload_potential_parts(op, err);
+}
+
+void free_device(oefe_op_s* op) {
+  auto& d = op->d;
+  dfree(d.WV); dfree(d.WVf); dfree(d.blk_fn0); dfree(d.blk_nf); dfree(d.blk_rptr); dfree(d.blk_rows);
+  dfree(d.hv); dfree(d.hvf); dfree(d.row_ptr); dfree(d.row_blk); dfree(d.row_pos); dfree(d.chunk_blk);
+  dfree(d.chunk_r0); dfree(d.chunk_r1); dfree(d.blk_chunk0); dfree(d.fn_blk); dfree(d.S); dfree(d.Hoo);
+  dfree(d.Sf); dfree(d.Hoof); dfree(d.cph_ptr); dfree(d.cph_blk); dfree(d.cph_off); dfree(d.phi);
+  dfree(d.lambda); dfree(d.lambdaf);
+}
+
+}  // namespace oefe
+
+using namespace oefe;
+
+namespace {
+
+template <typename T>
+int filter_impl(oefe_op_s* op, bool bf16, T* X, int64_t ld, int nv, int m, double a, double b, double a0,
+                const Layout& L, hipStream_t s) {
+  const double e = (b - a) / 2.0, c = (b + a) / 2.0;
+  const double s1 = e / (a0 - c);
+  const int64_t ldw = nv;  // second buffer is packed
+  T* B = (T*)L.vecA;
+  // the recurrence runs on (X, B) with in-place overwrite of the older iterate.
+  // Buffers hold blocks with leading dimensions ld (X) and ldw (B); to keep one ld per
+  // step, copy X into B's layout when ld != nv.
+  T* cur;
+  T* old;
+  int64_t ldu;
+  T* C = (T*)L.vecB;
+  if (ld == ldw) {
+    cur = X;
+    old = B;
+    ldu = ld;
+  } else {
+    // pack X into C
+    const int E = op->cplx ? 2 : 1;
+    int rc = cast_block(X, sizeof(T) == 4, C, sizeof(T) == 4, op->n_tot, ld * E, ldw * E, nv * E, s);
+    if (rc) return rc;
+    cur = C;
+    old = B;
+    ldu = ldw;
+  }
+  // Y_1 = (s1/e)(H x - c x)  -> old buffer
+  int rc = apply_step<T>(op, bf16, cur, ldu, nullptr, old, ldu, nv, s1 / e, c, 0.0, L.step, s);
+  if (rc) return rc;
+  std::swap(cur, old);  // cur = Y1, old = Y0
+  double sig = s1;
+  for (int k = 1; k < m; ++k) {
+    const double sn = 1.0 / (2.0 / s1 - sig);
+    rc = apply_step<T>(op, bf16, cur, ldu, old, old, ldu, nv, 2.0 * sn / e, c, sig * sn, L.step, s);
+    if (rc) return rc;
+    std::swap(cur, old);
+    sig = sn;
+  }
+  if (cur != X) {
+    const int E = op->cplx ? 2 : 1;
+    rc = cast_block(cur, sizeof(T) == 4, X, sizeof(T) == 4, op->n_tot, ldu * E, ld * E, nv * E, s);
+    if (rc) return rc;
+  }
+  return OEFE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* oefe_strerror(int code) {
+  switch (code) {
+    case OEFE_OK: return "ok";
+    case OEFE_EINVAL: return "invalid argument";
+    case OEFE_ENOMEM: return "out of device memory";
+    case OEFE_EDEVICE: return "HIP runtime error";
+    case OEFE_ENOTSPD: return "Gram matrix not positive definite (Cholesky breakdown)";
+    case OEFE_ENOCONV: return "dense eigensolver did not converge";
+    case OEFE_EUNSUPPORTED: return "unsupported precision, degree or operator kind";
+    default: return "unknown status";
+  }
+}
+
+const char* oefe_last_error(void) { return g_last_error.c_str(); }
+
+int oefe_kernel_timer(oefe_op op, int enable) {
+  if (!op) return fail(OEFE_EINVAL, "null operator");
+  op->timer_on = enable != 0;
+  return OEFE_OK;
+}
+
+int oefe_kernel_timer_read(oefe_op op, int64_t* launches, double* total_ms) {
+  if (!op || !launches || !total_ms) return fail(OEFE_EINVAL, "null argument");
+  double tot = 0.0;
+  int64_t n = 0;
+  int rc = OEFE_OK;
+  for (auto& pr : op->timer_events) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) rc = hip_fail(e, "oefe_kernel_timer_read");
+    tot += ms;
+    ++n;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  op->timer_events.clear();
+  *launches = n;
+  *total_ms = tot;
+  return rc;
+}
+
+int oefe_op_create(const oefe_system_desc* desc, oefe_op* out) {
+  if (!desc || !out) return fail(OEFE_EINVAL, "null argument");
+  *out = nullptr;
+  if (desc->n_atoms < 0 || desc->n_enr < 0 || (desc->n_atoms > 0 && (!desc->pos || !desc->Z)) ||
+      (desc->n_enr > 0 && (!desc->enr_atom || !desc->enr_power || !desc->enr_zeta || !desc->enr_axis)))
+    return fail(OEFE_EINVAL, "inconsistent system description");
+  for (int nu = 0; nu < desc->n_enr; ++nu)
+    if (desc->enr_power[nu] < 0 || desc->enr_axis[nu] < -1 || desc->enr_axis[nu] > 2 || !(desc->enr_zeta[nu] > 0))
+      return fail(OEFE_EINVAL, "bad enrichment function parameters");
+  oefe_op_s* op = new (std::nothrow) oefe_op_s();
+  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  std::string err;
+  int rc = build_operator(op, desc, err);
+  if (rc == OEFE_OK) {
+    if (hipGetDevice(&op->device) != hipSuccess) {
+      rc = OEFE_EDEVICE;
+      err = "no HIP device";
+    }
+  }
+  if (rc == OEFE_OK) rc = upload_operator(op, err);
+  if (rc != OEFE_OK) {
+    free_device(op);
+    delete op;
+    return fail(rc, err);
+  }
+  *out = op;
+  return OEFE_OK;
+}
+
+int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out) {
+  if (!lambda || !out || n <= 0) return fail(OEFE_EINVAL, "bad diagonal operator arguments");
+  oefe_op_s* op = new (std::nothrow) oefe_op_s();
+  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  op->diagonal = true;
+  op->N = n;
+  op->n_tot = n;
+  std::vector<double> l(lambda, lambda + n);
+  std::string err;
+  int rc = dput(&op->d.lambda, l, err);
+  if (!rc) rc = dput(&op->d.lambdaf, to_float(l), err);
+  if (rc) {
+    free_device(op);
+    delete op;
+    return fail(rc, err);
+  }
+  (void)hipGetDevice(&op->device);
+  *out = op;
+  return OEFE_OK;
+}
+
+int oefe_op_destroy(oefe_op op) {
+  if (!op) return OEFE_OK;
+  free_device(op);
+  delete op;
+  return OEFE_OK;
+}
+
+int oefe_op_dims(oefe_op op, int64_t* dims) {
+  if (!op || !dims) return fail(OEFE_EINVAL, "null argument");
+  dims[0] = op->N;
+  dims[1] = op->n_enr;
+  dims[2] = op->n_tot;
+  dims[3] = op->n_cells;
+  dims[4] = op->nq;
+  dims[5] = op->nc;
+  dims[6] = op->p;
+  dims[7] = op->cplx ? 1 : 0;
+  return OEFE_OK;
+}
+
+int oefe_op_set_potential(oefe_op op, const double* V_host) {
+  if (!op || !V_host || op->diagonal) return fail(OEFE_EINVAL, "bad arguments");
+  std::copy(V_host, V_host + op->V.size(), op->V.begin());
+  std::string err;
+  int rc = rebuild_potential_parts(op, err);
+  if (!rc) rc = upload_potential_parts(op, err);
+  return rc ? fail(rc, err) : OEFE_OK;
+}
+
+int oefe_op_get_potential(oefe_op op, double* V_host, double* W_host) {
+  if (!op || op->diagonal) return fail(OEFE_EINVAL, "bad arguments");
+  if (V_host) std::copy(op->V.begin(), op->V.end(), V_host);
+  if (W_host) std::copy(op->W.begin(), op->W.end(), W_host);
+  return OEFE_OK;
+}
+
+int oefe_op_get_enrichment(oefe_op op, double* S_host, double* eig_host) {
+  if (!op || op->diagonal) return fail(OEFE_EINVAL, "bad arguments");
+  const int n = op->n_enr;
+  if (S_host)
+    for (size_t i = 0; i < (size_t)n * n; ++i) {
+      if (op->cplx) {
+        S_host[2 * i] = op->S[i].real();
+        S_host[2 * i + 1] = op->S[i].imag();
+      } else {
+        S_host[i] = op->S[i].real();
+      }
+    }
+  if (eig_host) std::copy(op->Moo_eigs.begin(), op->Moo_eigs.end(), eig_host);
+  return OEFE_OK;
+}
+
+size_t oefe_work_size(oefe_op op, oefe_prec prec, int32_t nv) {
+  if (!op || nv <= 0) return 0;
+  return layout(op, prec, nv, nullptr).total + 256;
+}
+
+int ham_apply(oefe_op op, oefe_prec prec, const void* X, void* Y, int64_t ld, int32_t nv, void* work,
+              oefe_stream stream) {
+  if (!op || !X || !Y || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
+  if (int rc = check_prec(op, prec)) return rc;
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (prec_fp32(prec))
+    rc = apply_step<float>(op, prec == OEFE_BF16, (const float*)X, ld, nullptr, (float*)Y, ld, nv, 1.0, 0.0, 0.0,
+                           L.step, s);
+  else
+    rc = apply_step<double>(op, false, (const double*)X, ld, nullptr, (double*)Y, ld, nv, 1.0, 0.0, 0.0, L.step, s);
+  if (rc == OEFE_EUNSUPPORTED) return fail(rc, "precision not supported by ham_apply");
+  if (rc) return fail(rc, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return OEFE_OK;
+}
+
+int chebyshev_filter(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, int32_t m, double a, double b,
+                     double a0, void* work, oefe_stream stream) {
+  if (!op || !X || !work || nv <= 0 || ld < nv || m < 1) return fail(OEFE_EINVAL, "bad arguments");
+  if (!(a < b) || !(a0 < a) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(a0))
+    return fail(OEFE_EINVAL, "need a0 < a < b (finite)");
+  if (int rc = check_prec(op, prec)) return rc;
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (prec_fp32(prec))
+    rc = filter_impl<float>(op, prec == OEFE_BF16, (float*)X, ld, nv, m, a, b, a0, L, s);
+  else
+    rc = filter_impl<double>(op, false, (double*)X, ld, nv, m, a, b, a0, L, s);
+  if (rc == OEFE_EUNSUPPORTED) return fail(rc, "precision not supported by chebyshev_filter");
+  if (rc) return fail(rc, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return OEFE_OK;
+}
+
+int chebyshev_filter_mixed(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, int32_t m, double a,
+                           double b, double a0, void* work, oefe_stream stream) {
+  if (!op || !X || !work || nv <= 0 || ld < nv || m < 1) return fail(OEFE_EINVAL, "bad arguments");
+  if (!(a < b) || !(a0 < a) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(a0))
+    return fail(OEFE_EINVAL, "need a0 < a < b (finite)");
+  if (!prec_fp32(prec)) return fail(OEFE_EINVAL, "chebyshev_filter_mixed needs a float32 filter precision");
+  if (int rc = check_prec(op, prec)) return rc;
+  const int E = op->cplx ? 2 : 1;
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  float* Xf = (float*)L.vecB;  // packed float32 copy
+  int rc = cast_block(X, false, Xf, true, op->n_tot, ld * E, (int64_t)nv * E, nv * E, s);
+  if (!rc) rc = filter_impl<float>(op, prec == OEFE_BF16, Xf, nv, nv, m, a, b, a0, L, s);
+  if (!rc) rc = cast_block(Xf, true, X, false, op->n_tot, (int64_t)nv * E, ld * E, nv * E, s);
+  if (rc == OEFE_EUNSUPPORTED) return fail(rc, "precision not supported by chebyshev_filter_mixed");
+  if (rc) return fail(rc, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return OEFE_OK;
+}
+
+int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
+           oefe_stream stream) {
+  if (!op || !X || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
+  if (prec != OEFE_F64 && prec != OEFE_C128) return fail(OEFE_EINVAL, "cholgs runs in float64 (F64 or C128)");
+  if (int rc = check_prec(op, prec)) return rc;
+  const bool cplx = op->cplx;
+  const int E = cplx ? 2 : 1;
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  double* Xd = (double*)X;
+  double* tmp = (double*)L.vecA;
+  for (int it = 0; it < 2; ++it) {
+    int rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
+    if (!rc) rc = hermitian_part(cplx, L.G, nv, s);
+    if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, L.status, s);
+    if (rc) return fail(rc, "cholgs: kernel launch failed");
+    int32_t st[2];
+    hipError_t he = hipMemcpyAsync(st, L.status, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return hip_fail(he, "cholgs");
+    if (st[0] != 0) {
+      if (dev_status) (void)hipMemcpyAsync(dev_status, L.status, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+      (void)hipStreamSynchronize(s);
+      return fail(OEFE_ENOTSPD, "cholgs: Gram matrix not positive definite at column " + std::to_string(st[1]));
+    }
+    rc = gemm_nn(cplx, Xd, ld, L.Rinv, nv, tmp, nv, op->n_tot, nv, nv, s);
+    if (!rc) rc = copy_block(tmp, (int64_t)nv * E, Xd, ld * E, op->n_tot, nv * E, s);
+    // orthogonality check
+    if (!rc) rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
+    if (!rc) rc = max_offdiag_identity(cplx, L.G, nv, L.misc, s);
+    if (rc) return fail(rc, "cholgs: kernel launch failed");
+    double errv = 0;
+    he = hipMemcpyAsync(&errv, L.misc, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return hip_fail(he, "cholgs");
+    if (!(errv > 1e-12)) break;
+  }
+  if (dev_status) {
+    int32_t ok[2] = {0, -1};
+    (void)hipMemcpyAsync(dev_status, ok, sizeof(ok), hipMemcpyHostToDevice, s);
+    (void)hipStreamSynchronize(s);
+  }
+  return OEFE_OK;
+}
+
+int rayleigh_ritz(oefe_op op, oefe_prec prec, void* Q, int64_t ld, int32_t nv, double* eigvals, void* work,
+                  oefe_stream stream) {
+  if (!op || !Q || !eigvals || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
+  if (prec != OEFE_F64 && prec != OEFE_C128) return fail(OEFE_EINVAL, "rayleigh_ritz runs in float64 (F64 or C128)");
+  if (int rc = check_prec(op, prec)) return rc;
+  const bool cplx = op->cplx;
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  double* Qd = (double*)Q;
+  double* W = (double*)L.vecA;  // packed [n_tot x nv]
+  // W = Ht Q
+  int rc = apply_step<double>(op, false, Qd, ld, nullptr, W, nv, nv, 1.0, 0.0, 0.0, L.step, s);
+  if (rc) return fail(rc, "rayleigh_ritz: operator step failed");
+  // Hq = Q^* W (Hermitian part), Hq = U diag(theta) U^*
+  rc = gram(cplx, Qd, ld, nv, W, nv, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
+  if (!rc) rc = hermitian_part(cplx, L.G, nv, s);
+  if (!rc) rc = jacobi_eig(cplx, L.G, nv, eigvals, L.U, L.jscr, L.status, s);
+  // Q <- Q U  (through the packed buffer)
+  if (!rc) rc = gemm_nn(cplx, Qd, ld, L.U, nv, W, nv, op->n_tot, nv, nv, s);
+  if (!rc) rc = copy_block(W, (int64_t)nv * (cplx ? 2 : 1), Qd, ld * (cplx ? 2 : 1), op->n_tot, nv * (cplx ? 2 : 1), s);
+  if (rc) return fail(rc, "rayleigh_ritz: kernel launch failed");
+  return OEFE_OK;
+}
+
+int lanczos_bounds(oefe_op op, int32_t k, const double* v0, double* out, void* work, oefe_stream stream) {
+  if (!op || !v0 || !out || !work || k < 1 || k > 64) return fail(OEFE_EINVAL, "bad arguments");
+  const bool cplx = op->cplx;
+  const int E = cplx ? 2 : 1;
+  const int prec = cplx ? OEFE_C128 : OEFE_F64;
+  const int kb = k + 2;  // block width of the Lanczos basis
+  Layout L = layout(op, prec, kb, work);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = op->n_tot;
+  double* Vb = (double*)L.vecA;  // [n x kb]
+  double* w = (double*)L.vecB;   // [n x 1] (uses the first n*E doubles)
+  double* t = w + n * E;         // [n x 1]
+  StepWork sw = carve_step_work(op, 8, cplx, 1, work);
+  double* a_d = L.misc;       // alpha_j at misc[2 j] (complex slot), beta_j at misc[256 + j], norm at misc[511]
+  double* h = L.G;            // reorth coefficients [kb]
+  // v_1 = v0 / ||v0||
+  int rc = copy_block(v0, E, Vb, (int64_t)kb * E, n, E, s);
+  if (!rc) rc = dot_columns<double>(cplx, Vb, kb, Vb, kb, n, 1, nullptr, a_d + 511, L.gscr, s);
+  if (!rc) rc = sqrt_inplace(a_d + 511, s);
+  if (!rc) rc = lanczos_scale(cplx, Vb, kb, Vb, a_d + 511, n, s);
+  if (rc) return fail(rc, "lanczos: kernel launch failed");
+  std::vector<double> alpha, beta;
+  double scale = 0;
+  for (int j = 0; j < k; ++j) {
+    rc = apply_step<double>(op, false, Vb + (int64_t)j * E, kb, nullptr, w, 1, 1, 1.0, 0.0, 0.0, sw, s);
+    if (rc) return fail(rc, "lanczos: operator step failed");
+    // alpha_j = Re(v_j^* w)
+    if (!rc) rc = gram(cplx, Vb + (int64_t)j * E, kb, 1, w, 1, 1, n, a_d + 2 * j, 1, L.gscr, (size_t)1 << 62, s);
+    // w -= alpha_j v_j + beta_{j-1} v_{j-1}
+    if (!rc)
+      rc = lanczos_axpy(cplx, w, Vb + (int64_t)j * E, j > 0 ? Vb + (int64_t)(j - 1) * E : nullptr, a_d + 2 * j,
+                        j > 0 ? a_d + 256 + (j - 1) : nullptr, n, kb, s);
+    // full reorthogonalization, twice: w -= V (V^* w)
+    for (int r = 0; r < 2 && !rc; ++r) {
+      rc = gram(cplx, Vb, kb, j + 1, w, 1, 1, n, h, 1, L.gscr, (size_t)1 << 62, s);
+      if (!rc) rc = gemm_nn(cplx, Vb, kb, h, 1, t, 1, n, j + 1, 1, s);
+      if (!rc) rc = sub_block(cplx, w, t, n, s);
+    }
+    // beta_j = ||w||
+    if (!rc) rc = dot_columns<double>(cplx, w, 1, w, 1, n, 1, nullptr, a_d + 256 + j, L.gscr, s);
+    if (!rc) rc = sqrt_inplace(a_d + 256 + j, s);
+    if (rc) return fail(rc, "lanczos: kernel launch failed");
+    double ab[2];
+    hipError_t he = hipMemcpyAsync(&ab[0], a_d + 2 * j, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(&ab[1], a_d + 256 + j, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return hip_fail(he, "lanczos");
+    alpha.push_back(ab[0]);
+    beta.push_back(ab[1]);
+    for (double x : alpha) scale = std::max(scale, std::fabs(x));
+    for (double x : beta) scale = std::max(scale, std::fabs(x));
+    if (ab[1] < 1e-14 * scale || j == k - 1) break;
+    rc = lanczos_scale(cplx, Vb + (int64_t)(j + 1) * E, kb, w, a_d + 256 + j, n, s);
+    if (rc) return fail(rc, "lanczos: kernel launch failed");
+  }
+  // eigenvalues of the tridiagonal T (float64 Jacobi on the device)
+  const int m = (int)alpha.size();
+  std::vector<double> T((size_t)m * m * E, 0.0);
+  for (int i = 0; i < m; ++i) {
+    T[((size_t)i * m + i) * E] = alpha[i];
+    if (i + 1 < m) {
+      T[((size_t)i * m + i + 1) * E] = beta[i];
+      T[((size_t)(i + 1) * m + i) * E] = beta[i];
+    }
+  }
+  hipError_t he = hipMemcpyAsync(L.Rinv, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (he != hipSuccess) return hip_fail(he, "lanczos");
+  rc = jacobi_eig(cplx, L.Rinv, m, L.lam, L.U, L.jscr, L.status, s);
+  if (rc) return fail(rc, "lanczos: eigensolver launch failed");
+  std::vector<double> th(m);
+  he = hipMemcpyAsync(th.data(), L.lam, m * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return hip_fail(he, "lanczos");
+  out[0] = th[0];
+  out[1] = th[m - 1] + beta[m - 1];
+  return OEFE_OK;
+}
+
+int band_energy_grad(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* f, double* E,
+                     double* dE_dV, void* dE_dX, void* work, oefe_stream stream) {
+  if (!op || !X || !f || !E || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
+  if (int rc = check_prec(op, prec)) return rc;
+  if (op->diagonal && dE_dV) return fail(OEFE_EINVAL, "diagonal operator has no potential");
+  const bool cplx = op->cplx;
+  const bool f32 = prec_fp32(prec);
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  // H X (precision of X) into dE_dX (leading dimension ld) or into packed scratch
+  void* HX = dE_dX ? dE_dX : (void*)L.vecA;
+  const int64_t ldh = dE_dX ? ld : nv;
+  int rc;
+  if (f32)
+    rc = apply_step<float>(op, prec == OEFE_BF16, (const float*)X, ld, nullptr, (float*)HX, ldh, nv, 1.0, 0.0, 0.0,
+                           L.step, s);
+  else
+    rc = apply_step<double>(op, false, (const double*)X, ld, nullptr, (double*)HX, ldh, nv, 1.0, 0.0, 0.0, L.step, s);
+  if (rc) return fail(rc, "band_energy_grad: operator step failed");
+  // E = sum_i f_i Re(x_i^* (H x)_i), accumulated in float64
+  if (f32)
+    rc = dot_columns<float>(cplx, (const float*)X, ld, (const float*)HX, ldh, op->n_tot, nv, f, E, L.gscr, s);
+  else
+    rc = dot_columns<double>(cplx, (const double*)X, ld, (const double*)HX, ldh, op->n_tot, nv, f, E, L.gscr, s);
+  if (rc) return fail(rc, "band_energy_grad: reduction failed");
+  if (dE_dV) {
+    const int ncr = cplx ? 2 * nv : nv;
+    if (f32) {
+      rc = zo_only<float>(op, (const float*)X, ld, nv, (float*)L.step.zo, ncr, s);
+      if (!rc) rc = density_partial<float>(op, (const float*)X, ld, nv, f, (const float*)L.step.zo, ncr, L.dens, s);
+    } else {
+      rc = zo_only<double>(op, (const double*)X, ld, nv, (double*)L.step.zo, ncr, s);
+      if (!rc) rc = density_partial<double>(op, (const double*)X, ld, nv, f, (const double*)L.step.zo, ncr, L.dens, s);
+    }
+    if (!rc) rc = density_final(op, L.dens, ncols_blocks(ncr), dE_dV, s);
+    if (rc) return fail(rc, "band_energy_grad: density kernels failed");
+  }
+  if (dE_dX) {
+    rc = scale_grad(cplx, dE_dX, ld, op->n_tot, nv, f, f32, s);
+    if (rc) return fail(rc, "band_energy_grad: scaling failed");
+  }
+  return OEFE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Internal definitions shared by the host setup and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/oefe.h"
+
+namespace oefe {
+
+constexpr int kMaxP1 = 5;  // supported GLL nodes per edge: 3, 4, 5 (degree 2..4)
+
+using cplx = std::complex<double>;
+
+// 1D reference data in the form the cell kernel uses (q = p + 1 Gauss points).
+//  B1[qi][a]   Lagrange basis on GLL nodes at Gauss point qi
+//  L1[qi][qj]  collocation Laplacian at Gauss points: Dh^T diag(w) Dh, Dh = D1 B1^-1
+//  BtL[a][qj]  sum_k B1[k][a] L1[k][qj]
+//  BtW[a][qi]  B1[qi][a] w[qi]
+//  w[q]        Gauss weights
+//  om[a]       1/sqrt(w'_{a mod p}) with w'_0 = 2 what_0 (lumped-mass factor per local index)
+template <typename T>
+struct CellCoef {
+  T B1[kMaxP1][kMaxP1];
+  T L1[kMaxP1][kMaxP1];
+  T BtL[kMaxP1][kMaxP1];
+  T BtW[kMaxP1][kMaxP1];
+  T w[kMaxP1];
+  T om[kMaxP1];
+  T kappa;  // h / 4: scale of the reference kinetic form
+  T mscale; // (h/2)^(-3/2): scale of m^-1/2
+};
+
+struct DeviceArrays {
+  // potential times weight at quadrature points [n_cells * nq]
+  double* WV = nullptr;
+  float* WVf = nullptr;
+  // enrichment, atom-blocked H^co: block b has nf[b] functions starting at fn0[b],
+  // rows rows[rptr[b] .. rptr[b+1]) (global FE index) and values
+  // hv[(rptr[b] + r) * FMAX + f] (complex: 2 doubles per entry)
+  int32_t* blk_fn0 = nullptr;
+  int32_t* blk_nf = nullptr;
+  int64_t* blk_rptr = nullptr;
+  int32_t* blk_rows = nullptr;
+  double* hv = nullptr;
+  float* hvf = nullptr;
+  // per FE row: list of (block, position p into the concatenated block rows)
+  int64_t* row_ptr = nullptr;
+  int32_t* row_blk = nullptr;
+  int64_t* row_pos = nullptr;
+  // transposed-product chunks: chunk c covers block chunk_blk[c], rows [chunk_r0[c], chunk_r1[c])
+  int32_t* chunk_blk = nullptr;
+  int64_t* chunk_r0 = nullptr;
+  int64_t* chunk_r1 = nullptr;
+  int32_t* blk_chunk0 = nullptr;  // first chunk of each block [nblk + 1]
+  int32_t* fn_blk = nullptr;      // block of each enrichment function [n_enr]
+  // dense enrichment matrices (n_enr^2, complex interleaved when complex)
+  double* S = nullptr;
+  double* Hoo = nullptr;
+  float* Sf = nullptr;
+  float* Hoof = nullptr;
+  // N^O at quadrature points by cell: cell e has entries cph_ptr[e]..cph_ptr[e+1]),
+  // entry j: block cph_blk[j], values phi[(cph_off[j] * nq + q) * FMAX + f]
+  int64_t* cph_ptr = nullptr;
+  int32_t* cph_blk = nullptr;
+  int64_t* cph_off = nullptr;
+  double* phi = nullptr;
+  // diagonal test operator
+  double* lambda = nullptr;
+  float* lambdaf = nullptr;
+};
+
+struct AtomBlock {
+  int atom;
+  int fn0, nf;
+  std::vector<int64_t> cells;      // sorted, N^O support (dilated)
+  std::vector<cplx> phi;           // [ncell][nq][nf]
+  std::vector<cplx> gphi;          // [ncell][nq][nf][3]
+  std::vector<int32_t> rows;       // sorted FE rows where H^co is nonzero
+  std::vector<cplx> hkin;          // kinetic part of H^co on rows [rows][nf]
+};
+
+}  // namespace oefe
+
+struct oefe_op_s {
+  bool diagonal = false;
+  bool cplx = false;
+  int device = 0;
+  // geometry
+  double L = 0, h = 0;
+  int nc = 0, p = 0, P1 = 0, n = 0, nd = 0, nq = 0;
+  int64_t N = 0, n_cells = 0, n_tot = 0;
+  int n_enr = 0;
+  double kvec[3] = {0, 0, 0};
+  double phase[3][2] = {{1, 0}, {1, 0}, {1, 0}};  // exp(i k_d L)
+  // 1D data
+  oefe::CellCoef<double> cd;
+  oefe::CellCoef<float> cf;
+  double gll_w[8], gauss_x[8], gauss_w[8];
+  double B1[8][8], D1[8][8];
+  // host copies
+  std::vector<double> V, W;  // [n_cells * nq]
+  std::vector<double> mdiag;
+  std::vector<oefe::AtomBlock> blocks;
+  std::vector<oefe::cplx> Moo, Hoo_kin, Hoo, S;
+  std::vector<double> Moo_eigs;
+  int FMAX = 1;
+  int64_t n_hrows = 0;  // total rows over blocks
+  int64_t n_chunks = 0;
+  int chunk_rows = 256;
+  oefe::DeviceArrays d;
+  // instrumentation (oefe_kernel_timer)
+  bool timer_on = false;
+  mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;
+};
+
+namespace oefe {
+// host setup (oefe_setup.cpp)
+int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err);
+int rebuild_potential_parts(oefe_op_s* op, std::string& err);
+void hermitian_eig(int n, std::vector<cplx>& A, std::vector<double>& lam, std::vector<cplx>& U);
+void block_hco_values(const oefe_op_s* op, const AtomBlock& b, std::vector<cplx>& out);
+// device upload (oefe_api.hip)
+int upload_operator(oefe_op_s* op, std::string& err);
+int upload_potential_parts(oefe_op_s* op, std::string& err);
+void set_error(const std::string& msg);
+}  // namespace oefe

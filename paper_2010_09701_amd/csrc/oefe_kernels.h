@@ -1,0 +1,73 @@
+// Launchers of the HIP kernels (device code in oefe_ops.hip and oefe_linalg.hip).
+#pragma once
+
+#include "oefe_internal.h"
+
+namespace oefe {
+
+// Work layout for the operator step of a block with `ncv` vectors (complex or real).
+struct StepWork {
+  void* ycell;    // [n_cells * nd * ldc] real columns, element T
+  int ldc;        // real columns per cell node (padded)
+  void* zo;       // [n_enr * ncr] S X^O
+  void* part;     // [n_chunks * FMAX * ncr] partial H^co^* Z^C
+  void* wp;       // [n_enr * ncr]
+};
+
+size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, int* ldc_out);
+StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, void* work);
+
+// out = alpha (Ht x - c x) - beta prev   (prev may be null when beta == 0)
+// T = double or float; x: [n_tot x ld], prev and out: [n_tot x ldo] (complex: interleaved, leading
+// dimensions in complex elements).  prev may alias out.
+template <typename T>
+int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
+               double alpha, double c, double beta, const StepWork& w, hipStream_t s);
+// Z^O = S X^O only (for the density)
+template <typename T>
+int zo_only(const oefe_op_s* op, const T* x, int64_t ld, int nv, T* zo, int ncr, hipStream_t s);
+// density partials per 64-column block: dens[blk][e][q] = sum_cols f_v psi_col(x_eq)^2
+template <typename T>
+int density_partial(const oefe_op_s* op, const T* x, int64_t ld, int nv, const double* f, const T* zo, int ncr,
+                    double* dens, hipStream_t s);
+// dEdV[e][q] = W_eq sum_blk dens[blk][e][q]
+int density_final(const oefe_op_s* op, const double* dens, int nblk, double* dEdV, hipStream_t s);
+
+// ---- dense linear algebra (float64, real or complex-interleaved), oefe_linalg.hip
+// G[i][j] = sum_g conj(A[g][i]) B[g][j]  (na x nb, row-major ldg), rows 0..n-1.
+int gram(bool cplx, const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, int64_t n,
+         double* G, int ldg, double* scratch, size_t scratch_bytes, hipStream_t s);
+size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n);
+// C = A * B, A [n x k] (lda), B [k x m] (ldb, small), C [n x m] (ldc)
+int gemm_nn(bool cplx, const double* A, int64_t lda, const double* B, int ldb, double* C, int64_t ldc, int64_t n,
+            int k, int m, hipStream_t s);
+// in-place Cholesky of Jacobi-scaled Hermitian G (n x n): writes Rinv = (D^-1 L)^-* ... see linalg source
+int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s);
+// Hermitian eigensolver (cyclic Jacobi, one workgroup): A overwritten; lam ascending, U columns.
+int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status,
+               hipStream_t s);
+size_t jacobi_scratch_bytes(bool cplx, int n);
+// max |G - I| into *err (device double)
+int max_offdiag_identity(bool cplx, const double* G, int n, double* err, hipStream_t s);
+// symmetrize (Hermitian part) in place
+int hermitian_part(bool cplx, double* G, int n, hipStream_t s);
+// copies / casts between blocks [n_rows x ld] (only the first ncols real columns)
+int copy_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n_rows, int ncols, hipStream_t s);
+// out = sum_j f_j Re sum_g conj(A[g][j]) B[g][j]  (f may be null: all ones), accumulated in float64
+template <typename T>
+int dot_columns(bool cplx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n, int nv, const double* f,
+                double* out, double* scratch, hipStream_t s);
+// dst (ldd) <- src (lds), n_rows x ncols real elements, with float/double conversion
+int cast_block(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t n_rows, int64_t lds, int64_t ldd,
+               int ncols, hipStream_t s);
+// dE/dX = 2 f_j (H x)_j in place
+int scale_grad(bool cplx, void* g, int64_t ld, int64_t n, int nv, const double* f, bool f32, hipStream_t s);
+// Lanczos helpers (float64, vectors [n] packed or strided by ldv complex elements)
+int lanczos_axpy(bool cplx, double* w, const double* v, const double* vprev, const double* alpha,
+                 const double* beta, int64_t n, int64_t ldv, hipStream_t s);
+int lanczos_scale(bool cplx, double* dst, int64_t ldd, const double* w, const double* beta, int64_t n,
+                  hipStream_t s);
+int sub_block(bool cplx, double* w, const double* t, int64_t n, hipStream_t s);
+int sqrt_inplace(double* x, hipStream_t s);
+
+}  // namespace oefe

@@ -1,0 +1,734 @@
+// Dense float64 linear algebra for Cholesky-Gram-Schmidt, Rayleigh-Ritz and
+// Lanczos (gfx950): tall-skinny Gram products, tall x small products, a
+// one-workgroup Cholesky with triangular inverse, and a one-workgroup cyclic
+// Jacobi eigensolver for Hermitian matrices.  Complex data is interleaved.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "oefe_kernels.h"
+
+namespace oefe {
+
+namespace {
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Z {
+  double r, i;
+};
+__device__ __forceinline__ Z zmul(Z a, Z b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ Z zcjmul(Z a, Z b) { return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r}; }
+
+// ---- Gram: partial[chunk][i][j] = sum_{g in chunk} conj(A[g][i]) B[g][j]; 16x16 tile per block
+template <bool CPLX>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const double* __restrict__ A, int64_t lda, int na,
+                                                           const double* __restrict__ B, int64_t ldb, int nb,
+                                                           int64_t n, int64_t rows_per_chunk,
+                                                           double* __restrict__ part) {
+  constexpr int TS = 16, KB = 32;
+  constexpr int E = CPLX ? 2 : 1;
+  __shared__ double As[KB][TS * E + 1];
+  __shared__ double Bs[KB][TS * E + 1];
+  const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+  const int i0 = blockIdx.y * TS, j0 = blockIdx.z * TS;
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t g1 = min(n, g0 + rows_per_chunk);
+  double ar = 0, ai = 0;
+  for (int64_t gb = g0; gb < g1; gb += KB) {
+    for (int t = threadIdx.x; t < KB * TS * E; t += 256) {
+      const int r = t / (TS * E), cc = t % (TS * E);
+      const int64_t g = gb + r;
+      const int col = cc / E;
+      double va = 0, vb = 0;
+      if (g < g1) {
+        if (i0 + col < na) va = A[g * lda * E + (int64_t)(i0 + col) * E + cc % E];
+        if (j0 + col < nb) vb = B[g * ldb * E + (int64_t)(j0 + col) * E + cc % E];
+      }
+      As[r][cc] = va;
+      Bs[r][cc] = vb;
+    }
+    __syncthreads();
+    const int kmax = (int)min<int64_t>(KB, g1 - gb);
+    if constexpr (!CPLX) {
+      for (int k = 0; k < kmax; ++k) ar += As[k][ty] * Bs[k][tx];
+    } else {
+      for (int k = 0; k < kmax; ++k) {
+        Z t = zcjmul(Z{As[k][2 * ty], As[k][2 * ty + 1]}, Z{Bs[k][2 * tx], Bs[k][2 * tx + 1]});
+        ar += t.r;
+        ai += t.i;
+      }
+    }
+    __syncthreads();
+  }
+  const int i = i0 + ty, j = j0 + tx;
+  if (i < na && j < nb) {
+    double* o = part + ((int64_t)blockIdx.x * na * nb + (int64_t)i * nb + j) * E;
+    o[0] = ar;
+    if (CPLX) o[1] = ai;
+  }
+}
+
+template <bool CPLX>
+__global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks, int na, int nb,
+                                   double* __restrict__ G, int ldg) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= na * nb) return;
+  const int i = idx / nb, j = idx % nb;
+  double sr = 0, si = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    const double* p = part + ((int64_t)c * na * nb + idx) * E;
+    sr += p[0];
+    if (CPLX) si += p[1];
+  }
+  G[((int64_t)i * ldg + j) * E] = sr;
+  if (CPLX) G[((int64_t)i * ldg + j) * E + 1] = si;
+}
+
+// ---- C = A * B : A [n x k], B [k x m] (small); 64x64 output tile, 4x4 per thread
+template <bool CPLX>
+__global__ __launch_bounds__(256) void gemm_nn_kernel(const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ B, int ldb, double* __restrict__ C,
+                                                      int64_t ldc, int64_t n, int k, int m) {
+  constexpr int E = CPLX ? 2 : 1;
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ double As[TK][TM * E + E];
+  __shared__ double Bs[TK][TN * E + E];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int64_t r0 = (int64_t)blockIdx.x * TM;
+  const int c0 = blockIdx.y * TN;
+  double acc[4][4][E];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[a][b][e] = 0;
+  for (int k0 = 0; k0 < k; k0 += TK) {
+    for (int t = threadIdx.x; t < TM * TK * E; t += 256) {
+      const int rr = t / (TK * E), kk = (t % (TK * E)) / E, e = t % E;
+      const int64_t g = r0 + rr;
+      As[kk][rr * E + e] = (g < n && k0 + kk < k) ? A[g * lda * E + (int64_t)(k0 + kk) * E + e] : 0.0;
+    }
+    for (int t = threadIdx.x; t < TK * TN * E; t += 256) {
+      const int kk = t / (TN * E), cc = (t % (TN * E)) / E, e = t % E;
+      Bs[kk][cc * E + e] = (k0 + kk < k && c0 + cc < m) ? B[((int64_t)(k0 + kk) * ldb + c0 + cc) * E + e] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TK; ++kk) {
+      double a[4][E], b[4][E];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          a[q][e] = As[kk][(ty + 16 * q) * E + e];
+          b[q][e] = Bs[kk][(tx + 16 * q) * E + e];
+        }
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+          if constexpr (!CPLX) {
+            acc[qa][qb][0] += a[qa][0] * b[qb][0];
+          } else {
+            acc[qa][qb][0] += a[qa][0] * b[qb][0] - a[qa][E - 1] * b[qb][E - 1];
+            acc[qa][qb][E - 1] += a[qa][0] * b[qb][E - 1] + a[qa][E - 1] * b[qb][0];
+          }
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+      const int64_t g = r0 + ty + 16 * qa;
+      const int cc = c0 + tx + 16 * qb;
+      if (g < n && cc < m)
+#pragma unroll
+        for (int e = 0; e < E; ++e) C[g * ldc * E + (int64_t)cc * E + e] = acc[qa][qb][e];
+    }
+}
+
+// ---- Cholesky of the Jacobi-scaled matrix and R^-1 = diag(d) L^-*  (one workgroup)
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int ldg, int n, double* __restrict__ Rinv,
+                                                    double* __restrict__ dsc, int32_t* __restrict__ status) {
+  constexpr int E = CPLX ? 2 : 1;
+  __shared__ int bad;
+  __shared__ double piv;
+  const int tid = threadIdx.x;
+  auto re = [&](int i, int j) -> double& { return G[((int64_t)i * ldg + j) * E]; };
+  auto im = [&](int i, int j) -> double& { return G[((int64_t)i * ldg + j) * E + (E - 1)]; };
+  if (tid == 0) bad = -1;
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) {
+    const double gii = re(i, i);
+    if (!(gii > 0.0)) atomicMax(&bad, i);
+    dsc[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+  }
+  __syncthreads();
+  if (bad >= 0) {
+    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
+    return;
+  }
+  for (int t = tid; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t % n;
+    re(i, j) *= dsc[i] * dsc[j];
+    if (CPLX) im(i, j) *= dsc[i] * dsc[j];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      // breakdown: a pivot of the unit-diagonal (Jacobi-scaled) Gram matrix at or below
+      // n * 2^-52, i.e. numerically rank deficient in float64
+      const double d = re(k, k);
+      if (!(d > n * 2.220446049250313e-16) || !isfinite(d)) {
+        bad = k;
+        piv = 1.0;
+      } else {
+        piv = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (bad >= 0) break;
+    const double l = piv;
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) {
+      re(i, k) /= l;
+      if (CPLX) im(i, k) /= l;
+    }
+    if (tid == 0) {
+      re(k, k) = l;
+      if (CPLX) im(k, k) = 0.0;
+    }
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int t = tid; t < m * m; t += blockDim.x) {
+      const int i = k + 1 + t / m, j = k + 1 + t % m;
+      if (j > i) continue;
+      if constexpr (!CPLX) {
+        re(i, j) -= re(i, k) * re(j, k);
+      } else {
+        // G[i][j] -= L[i][k] conj(L[j][k])
+        const double ar = re(i, k), ai = im(i, k), br = re(j, k), bi = im(j, k);
+        re(i, j) -= ar * br + ai * bi;
+        im(i, j) -= ai * br - ar * bi;
+      }
+    }
+    __syncthreads();
+  }
+  if (bad >= 0) {
+    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
+    return;
+  }
+  // Linv (lower) by forward substitution, one column per thread; stored in the upper
+  // part of Rinv temporarily as Rinv[i][j] = d_i conj(Linv[j][i]).
+  for (int j = tid; j < n; j += blockDim.x) {
+    // solve L y = e_j for y (entries i >= j)
+    for (int i = 0; i < j; ++i) {
+      Rinv[((int64_t)i * n + j) * E] = 0.0;  // placeholder, overwritten below
+      if (CPLX) Rinv[((int64_t)i * n + j) * E + 1] = 0.0;
+    }
+    for (int i = j; i < n; ++i) {
+      double sr = (i == j) ? 1.0 : 0.0, si = 0.0;
+      for (int kk = j; kk < i; ++kk) {
+        // y_kk stored as Rinv[j][kk] = d_j conj(Linv[kk][j]) ... keep a raw copy instead:
+        const double yr = Rinv[((int64_t)kk * n + j) * E];
+        const double yi = CPLX ? Rinv[((int64_t)kk * n + j) * E + 1] : 0.0;
+        const double lr = re(i, kk), li = CPLX ? im(i, kk) : 0.0;
+        sr -= lr * yr - li * yi;
+        si -= lr * yi + li * yr;
+      }
+      const double lii = re(i, i);
+      Rinv[((int64_t)i * n + j) * E] = sr / lii;
+      if (CPLX) Rinv[((int64_t)i * n + j) * E + 1] = si / lii;
+    }
+  }
+  __syncthreads();
+  // Rinv currently holds Linv (lower, row-major).  Transform in place to diag(d) Linv^*:
+  // out[i][j] = d_i conj(Linv[j][i]).  Swap pairs (i < j) once.
+  for (int t = tid; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t % n;
+    if (i > j) continue;
+    const double lij_r = Rinv[((int64_t)i * n + j) * E], lij_i = CPLX ? Rinv[((int64_t)i * n + j) * E + 1] : 0.0;
+    const double lji_r = Rinv[((int64_t)j * n + i) * E], lji_i = CPLX ? Rinv[((int64_t)j * n + i) * E + 1] : 0.0;
+    // new[i][j] = d_i conj(L[j][i]);  new[j][i] = d_j conj(L[i][j])
+    Rinv[((int64_t)i * n + j) * E] = dsc[i] * lji_r;
+    if (CPLX) Rinv[((int64_t)i * n + j) * E + 1] = -dsc[i] * lji_i;
+    if (i != j) {
+      Rinv[((int64_t)j * n + i) * E] = dsc[j] * lij_r;
+      if (CPLX) Rinv[((int64_t)j * n + i) * E + 1] = -dsc[j] * lij_i;
+    }
+  }
+  if (tid == 0) { status[0] = 0; status[1] = -1; }
+}
+
+// ---- cyclic Jacobi (round-robin parallel ordering), one workgroup
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, int n, double* __restrict__ lam,
+                                                      double* __restrict__ U, double* __restrict__ V,
+                                                      double* __restrict__ rot, int32_t* __restrict__ status) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
+  const int npair = NN / 2, m = NN - 1;
+  __shared__ double red[1024];
+  __shared__ int done;
+  auto A_ = [&](int i, int j) -> double* { return A + ((int64_t)i * n + j) * E; };
+  for (int t = tid; t < n * n; t += nth) {
+    V[(int64_t)t * E] = (t / n == t % n) ? 1.0 : 0.0;
+    if (CPLX) V[(int64_t)t * E + 1] = 0.0;
+  }
+  if (tid == 0) done = 0;
+  __syncthreads();
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
+    // convergence test: off-diagonal vs diagonal (squared Frobenius)
+    double off = 0, dia = 0;
+    for (int t = tid; t < n * n; t += nth) {
+      const int i = t / n, j = t % n;
+      const double* a = A_(i, j);
+      const double v = a[0] * a[0] + (CPLX ? a[E - 1] * a[E - 1] : 0.0);
+      if (i == j) dia += v;
+      else off += v;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int s = nth / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[tid] = dia;
+    __syncthreads();
+    for (int s = nth / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const double dias = red[0];
+    __syncthreads();
+    if (offs <= 1e-30 * dias || offs == 0.0) break;
+    for (int st = 0; st < m; ++st) {
+      // (a) rotation per pair: rot[k] = {c, s, er, ei, p, q} (er+i ei = e^{i phi})
+      for (int k = tid; k < npair; k += nth) {
+        int p, q;
+        if (k == 0) {
+          p = 0;
+          q = 1 + st % m;
+        } else {
+          p = 1 + (st + k) % m;
+          q = 1 + (st - k + m) % m;
+        }
+        if (p > q) { int t = p; p = q; q = t; }
+        double c = 1, s = 0, er = 1, ei = 0;
+        if (q < n) {
+          const double* apq = A_(p, q);
+          const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
+          const double r = sqrt(br * br + bi * bi);
+          const double al = A_(p, p)[0], ga = A_(q, q)[0];
+          if (r > 1e-300 && r > 1e-18 * sqrt(fabs(al * ga))) {
+            er = br / r;
+            ei = bi / r;
+            const double tau = (ga - al) / (2.0 * r);
+            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        double* R = rot + 6 * k;
+        R[0] = c; R[1] = s; R[2] = er; R[3] = ei; R[4] = p; R[5] = q;
+      }
+      __syncthreads();
+      // (b) columns: A <- A G,  G = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
+      for (int t = tid; t < n * npair; t += nth) {
+        const int r = t / npair, k = t % npair;
+        const double* R = rot + 6 * k;
+        const int p = (int)R[4], q = (int)R[5];
+        if (q >= n || R[1] == 0.0) continue;
+        const double c = R[0], s = R[1];
+        double* ap = A_(r, p);
+        double* aq = A_(r, q);
+        if constexpr (!CPLX) {
+          const double x = ap[0], y = aq[0] * R[2];  // R[2] = sign(a_pq)
+          ap[0] = x * c - y * s;
+          aq[0] = x * s + y * c;
+        } else {
+          const Z emi{R[2], -R[3]};
+          const Z x{ap[0], ap[1]}, y{aq[0], aq[1]};
+          const Z ye = zmul(y, emi);
+          ap[0] = x.r * c - ye.r * s; ap[1] = x.i * c - ye.i * s;
+          aq[0] = x.r * s + ye.r * c; aq[1] = x.i * s + ye.i * c;
+        }
+      }
+      __syncthreads();
+      // (c) rows: A <- G^* A
+      for (int t = tid; t < n * npair; t += nth) {
+        const int r = t / npair, k = t % npair;
+        const double* R = rot + 6 * k;
+        const int p = (int)R[4], q = (int)R[5];
+        if (q >= n || R[1] == 0.0) continue;
+        const double c = R[0], s = R[1];
+        double* ap = A_(p, r);
+        double* aq = A_(q, r);
+        if constexpr (!CPLX) {
+          const double x = ap[0], y = R[2] * aq[0];
+          ap[0] = c * x - s * y;
+          aq[0] = s * x + c * y;
+        } else {
+          const Z eph{R[2], R[3]};
+          const Z x{ap[0], ap[1]}, y{aq[0], aq[1]};
+          const Z ye = zmul(eph, y);
+          ap[0] = c * x.r - s * ye.r; ap[1] = c * x.i - s * ye.i;
+          aq[0] = s * x.r + c * ye.r; aq[1] = s * x.i + c * ye.i;
+        }
+      }
+      __syncthreads();
+      // (d) V <- V G ; zero the rotated pair
+      for (int t = tid; t < n * npair; t += nth) {
+        const int r = t / npair, k = t % npair;
+        const double* R = rot + 6 * k;
+        const int p = (int)R[4], q = (int)R[5];
+        if (q >= n || R[1] == 0.0) continue;
+        const double c = R[0], s = R[1];
+        double* vp = V + ((int64_t)r * n + p) * E;
+        double* vq = V + ((int64_t)r * n + q) * E;
+        if constexpr (!CPLX) {
+          const double x = vp[0], y = vq[0] * R[2];
+          vp[0] = x * c - y * s;
+          vq[0] = x * s + y * c;
+        } else {
+          const Z emi{R[2], -R[3]};
+          const Z x{vp[0], vp[1]}, y{vq[0], vq[1]};
+          const Z ye = zmul(y, emi);
+          vp[0] = x.r * c - ye.r * s; vp[1] = x.i * c - ye.i * s;
+          vq[0] = x.r * s + ye.r * c; vq[1] = x.i * s + ye.i * c;
+        }
+        if (r == 0) {
+          double* apq = A_(p, q);
+          double* aqp = A_(q, p);
+          apq[0] = 0; aqp[0] = 0;
+          if (CPLX) { apq[1] = 0; aqp[1] = 0; }
+          A_(p, p)[E - 1] = CPLX ? 0.0 : A_(p, p)[0];
+          A_(q, q)[E - 1] = CPLX ? 0.0 : A_(q, q)[0];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) { status[0] = sweep < 60 ? 0 : OEFE_ENOCONV; status[1] = sweep; }
+  // sort ascending by rank
+  for (int i = tid; i < n; i += nth) {
+    const double li = A_(i, i)[0];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = A_(j, j)[0];
+      if (lj < li || (lj == li && j < i)) ++rank;
+    }
+    lam[rank] = li;
+    for (int r = 0; r < n; ++r) {
+      U[((int64_t)r * n + rank) * E] = V[((int64_t)r * n + i) * E];
+      if (CPLX) U[((int64_t)r * n + rank) * E + 1] = V[((int64_t)r * n + i) * E + 1];
+    }
+  }
+}
+
+template <bool CPLX>
+__global__ void max_dev_identity_kernel(const double* __restrict__ G, int n, double* __restrict__ err) {
+  constexpr int E = CPLX ? 2 : 1;
+  __shared__ double red[256];
+  double mx = 0;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t % n;
+    const double r = G[(int64_t)t * E] - (i == j ? 1.0 : 0.0);
+    const double im = CPLX ? G[(int64_t)t * E + 1] : 0.0;
+    mx = fmax(mx, sqrt(r * r + im * im));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *err = red[0];
+}
+
+template <bool CPLX>
+__global__ void hermitian_part_kernel(double* __restrict__ G, int n) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int i = t / n, j = t % n;
+  if (i > j) return;
+  double* a = G + ((int64_t)i * n + j) * E;
+  double* b = G + ((int64_t)j * n + i) * E;
+  const double r = 0.5 * (a[0] + b[0]);
+  a[0] = r;
+  b[0] = r;
+  if (CPLX) {
+    const double im = 0.5 * (a[1] - b[1]);
+    a[1] = (i == j) ? 0.0 : im;
+    b[1] = (i == j) ? 0.0 : -im;
+  }
+}
+
+__global__ void copy_block_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst, int64_t ldd,
+                                  int64_t n, int ncols) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * ncols) return;
+  const int64_t r = t / ncols;
+  const int c = (int)(t % ncols);
+  dst[r * ldd + c] = src[r * lds + c];
+}
+
+// per-column partial dot products: part[chunk][j] = sum_g Re(conj(A[g][j]) B[g][j]) in float64
+template <typename T, bool CPLX>
+__global__ void dot_partial_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                   int64_t n, int nv, int64_t rows_per_chunk, double* __restrict__ part) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= nv) return;
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t g1 = min(n, g0 + rows_per_chunk);
+  double s = 0;
+  for (int64_t g = g0; g < g1; ++g) {
+    const T* a = A + (g * lda + j) * E;
+    const T* b = B + (g * ldb + j) * E;
+    s += (double)a[0] * (double)b[0] + (CPLX ? (double)a[E - 1] * (double)b[E - 1] : 0.0);
+  }
+  part[(int64_t)blockIdx.x * nv + j] = s;
+}
+
+__global__ void dot_final_kernel(const double* __restrict__ part, int nchunks, int nv, const double* __restrict__ f,
+                                 double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+    double cs = 0;
+    for (int c = 0; c < nchunks; ++c) cs += part[(int64_t)c * nv + j];
+    s += (f ? f[j] : 1.0) * cs;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+template <typename S, typename D>
+__global__ void cast_block_kernel(const S* __restrict__ src, int64_t lds, D* __restrict__ dst, int64_t ldd, int64_t n,
+                                  int ncols) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * ncols) return;
+  const int64_t r = t / ncols;
+  const int c = (int)(t % ncols);
+  dst[r * ldd + c] = (D)src[r * lds + c];
+}
+
+template <typename T, bool CPLX>
+__global__ void scale_grad_kernel(T* __restrict__ g, int64_t ld, int64_t n, int nv, const double* __restrict__ f) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nv * E) return;
+  const int64_t r = t / (nv * E);
+  const int c = (int)(t % (nv * E));
+  const int v = c / E;
+  g[r * ld * E + c] = (T)(2.0 * f[v]) * g[r * ld * E + c];
+}
+
+// w -= alpha v + beta vprev  (v, vprev strided by ldv complex elements; w packed)
+template <bool CPLX>
+__global__ void lanczos_axpy_kernel(double* __restrict__ w, const double* __restrict__ v,
+                                    const double* __restrict__ vprev, const double* __restrict__ alpha,
+                                    const double* __restrict__ beta, int64_t n, int64_t ldv) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * E) return;
+  const int64_t r = t / E;
+  const int e = (int)(t % E);
+  double x = w[t] - alpha[0] * v[r * ldv * E + e];
+  if (vprev) x -= beta[0] * vprev[r * ldv * E + e];
+  w[t] = x;
+}
+
+template <bool CPLX>
+__global__ void lanczos_scale_kernel(double* __restrict__ dst, int64_t ldd, const double* __restrict__ w,
+                                     const double* __restrict__ beta, int64_t n) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * E) return;
+  const int64_t r = t / E;
+  const int e = (int)(t % E);
+  // w may be strided like dst when dst == w (in-place normalization of a strided column)
+  dst[r * ldd * E + e] = w[(dst == w ? r * ldd * E : r * E) + e] / beta[0];
+}
+
+__global__ void sub_kernel(double* __restrict__ w, const double* __restrict__ t, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] -= t[i];
+}
+
+__global__ void sqrt_kernel(double* x) { x[0] = sqrt(x[0]); }
+
+int check() { return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE; }
+
+int gram_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(128, cdiv(n, 512))); }
+
+}  // namespace
+
+size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n) {
+  return (size_t)gram_chunks(n) * na * nb * (cplx ? 2 : 1) * sizeof(double);
+}
+
+int gram(bool cplx, const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, int64_t n, double* G,
+         int ldg, double* scratch, size_t scratch_bytes, hipStream_t s) {
+  const int nch = gram_chunks(n);
+  if (gram_scratch_bytes(cplx, na, nb, n) > scratch_bytes) return OEFE_EINVAL;
+  const int64_t rpc = cdiv(n, nch);
+  dim3 grid(nch, (unsigned)cdiv(na, 16), (unsigned)cdiv(nb, 16));
+  if (cplx) {
+    hipLaunchKernelGGL(gram_partial_kernel<true>, grid, dim3(256), 0, s, A, lda, na, B, ldb, nb, n, rpc, scratch);
+    hipLaunchKernelGGL(gram_reduce_kernel<true>, dim3((unsigned)cdiv((int64_t)na * nb, 256)), dim3(256), 0, s,
+                       scratch, nch, na, nb, G, ldg);
+  } else {
+    hipLaunchKernelGGL(gram_partial_kernel<false>, grid, dim3(256), 0, s, A, lda, na, B, ldb, nb, n, rpc, scratch);
+    hipLaunchKernelGGL(gram_reduce_kernel<false>, dim3((unsigned)cdiv((int64_t)na * nb, 256)), dim3(256), 0, s,
+                       scratch, nch, na, nb, G, ldg);
+  }
+  return check();
+}
+
+int gemm_nn(bool cplx, const double* A, int64_t lda, const double* B, int ldb, double* C, int64_t ldc, int64_t n,
+            int k, int m, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(m, 64));
+  if (cplx)
+    hipLaunchKernelGGL(gemm_nn_kernel<true>, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, n, k, m);
+  else
+    hipLaunchKernelGGL(gemm_nn_kernel<false>, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, n, k, m);
+  return check();
+}
+
+int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s) {
+  // dsc stored after Rinv (caller reserves n extra doubles)
+  double* dsc = Rinv + (size_t)n * n * (cplx ? 2 : 1);
+  if (cplx)
+    hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(1024), 0, s, G, ldg, n, Rinv, dsc, status);
+  else
+    hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(1024), 0, s, G, ldg, n, Rinv, dsc, status);
+  return check();
+}
+
+size_t jacobi_scratch_bytes(bool cplx, int n) {
+  const int NN = n + 1;
+  return ((size_t)n * n * (cplx ? 2 : 1) + 6 * (size_t)(NN / 2 + 1)) * sizeof(double);
+}
+
+int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s) {
+  double* V = scratch;
+  double* rot = scratch + (size_t)n * n * (cplx ? 2 : 1);
+  if (cplx)
+    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(1024), 0, s, A, n, lam, U, V, rot, status);
+  else
+    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(1024), 0, s, A, n, lam, U, V, rot, status);
+  return check();
+}
+
+int max_offdiag_identity(bool cplx, const double* G, int n, double* err, hipStream_t s) {
+  if (cplx)
+    hipLaunchKernelGGL(max_dev_identity_kernel<true>, dim3(1), dim3(256), 0, s, G, n, err);
+  else
+    hipLaunchKernelGGL(max_dev_identity_kernel<false>, dim3(1), dim3(256), 0, s, G, n, err);
+  return check();
+}
+
+int hermitian_part(bool cplx, double* G, int n, hipStream_t s) {
+  dim3 grid((unsigned)cdiv((int64_t)n * n, 256));
+  if (cplx)
+    hipLaunchKernelGGL(hermitian_part_kernel<true>, grid, dim3(256), 0, s, G, n);
+  else
+    hipLaunchKernelGGL(hermitian_part_kernel<false>, grid, dim3(256), 0, s, G, n);
+  return check();
+}
+
+int copy_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n_rows, int ncols, hipStream_t s) {
+  hipLaunchKernelGGL(copy_block_kernel, dim3((unsigned)cdiv(n_rows * ncols, 256)), dim3(256), 0, s, src, lds, dst,
+                     ldd, n_rows, ncols);
+  return check();
+}
+
+template <typename T>
+int dot_columns(bool cplx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n, int nv, const double* f,
+                double* out, double* scratch, hipStream_t s) {
+  const int nch = gram_chunks(n);
+  const int64_t rpc = cdiv(n, nch);
+  dim3 grid(nch, (unsigned)cdiv(nv, 64));
+  if (cplx)
+    hipLaunchKernelGGL((dot_partial_kernel<T, true>), grid, dim3(64), 0, s, A, lda, B, ldb, n, nv, rpc, scratch);
+  else
+    hipLaunchKernelGGL((dot_partial_kernel<T, false>), grid, dim3(64), 0, s, A, lda, B, ldb, n, nv, rpc, scratch);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, scratch, nch, nv, f, out);
+  return check();
+}
+template int dot_columns<double>(bool, const double*, int64_t, const double*, int64_t, int64_t, int, const double*,
+                                 double*, double*, hipStream_t);
+template int dot_columns<float>(bool, const float*, int64_t, const float*, int64_t, int64_t, int, const double*,
+                                double*, double*, hipStream_t);
+
+int cast_block(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t n_rows, int64_t lds, int64_t ldd,
+               int ncols, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(n_rows * ncols, 256));
+  if (src_f32 && dst_f32)
+    hipLaunchKernelGGL((cast_block_kernel<float, float>), grid, dim3(256), 0, s, (const float*)src, lds, (float*)dst, ldd, n_rows, ncols);
+  else if (src_f32)
+    hipLaunchKernelGGL((cast_block_kernel<float, double>), grid, dim3(256), 0, s, (const float*)src, lds, (double*)dst, ldd, n_rows, ncols);
+  else if (dst_f32)
+    hipLaunchKernelGGL((cast_block_kernel<double, float>), grid, dim3(256), 0, s, (const double*)src, lds, (float*)dst, ldd, n_rows, ncols);
+  else
+    hipLaunchKernelGGL((cast_block_kernel<double, double>), grid, dim3(256), 0, s, (const double*)src, lds, (double*)dst, ldd, n_rows, ncols);
+  return check();
+}
+
+int scale_grad(bool cplx, void* g, int64_t ld, int64_t n, int nv, const double* f, bool f32, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(n * nv * (cplx ? 2 : 1), 256));
+  if (f32) {
+    if (cplx) hipLaunchKernelGGL((scale_grad_kernel<float, true>), grid, dim3(256), 0, s, (float*)g, ld, n, nv, f);
+    else hipLaunchKernelGGL((scale_grad_kernel<float, false>), grid, dim3(256), 0, s, (float*)g, ld, n, nv, f);
+  } else {
+    if (cplx) hipLaunchKernelGGL((scale_grad_kernel<double, true>), grid, dim3(256), 0, s, (double*)g, ld, n, nv, f);
+    else hipLaunchKernelGGL((scale_grad_kernel<double, false>), grid, dim3(256), 0, s, (double*)g, ld, n, nv, f);
+  }
+  return check();
+}
+
+int lanczos_axpy(bool cplx, double* w, const double* v, const double* vprev, const double* alpha,
+                 const double* beta, int64_t n, int64_t ldv, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(n * (cplx ? 2 : 1), 256));
+  if (cplx) hipLaunchKernelGGL(lanczos_axpy_kernel<true>, grid, dim3(256), 0, s, w, v, vprev, alpha, beta, n, ldv);
+  else hipLaunchKernelGGL(lanczos_axpy_kernel<false>, grid, dim3(256), 0, s, w, v, vprev, alpha, beta, n, ldv);
+  return check();
+}
+
+int lanczos_scale(bool cplx, double* dst, int64_t ldd, const double* w, const double* beta, int64_t n,
+                  hipStream_t s) {
+  dim3 grid((unsigned)cdiv(n * (cplx ? 2 : 1), 256));
+  if (cplx) hipLaunchKernelGGL(lanczos_scale_kernel<true>, grid, dim3(256), 0, s, dst, ldd, w, beta, n);
+  else hipLaunchKernelGGL(lanczos_scale_kernel<false>, grid, dim3(256), 0, s, dst, ldd, w, beta, n);
+  return check();
+}
+
+int sub_block(bool cplx, double* w, const double* t, int64_t n, hipStream_t s) {
+  const int64_t m = n * (cplx ? 2 : 1);
+  hipLaunchKernelGGL(sub_kernel, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, w, t, m);
+  return check();
+}
+
+int sqrt_inplace(double* x, hipStream_t s) {
+  hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, s, x);
+  return check();
+}
+
+}  // namespace oefe

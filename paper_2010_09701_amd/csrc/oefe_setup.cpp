@@ -1,0 +1,715 @@
+// Host-side construction of the OEFE operator data (untimed setup).
+//
+// Everything here follows Sec. III.A of the paper: spectral Lagrange elements
+// on GLL nodes with a diagonal GLL mass (eqnMcc, eqnorthCGLL), atomic
+// enrichment functions with a smooth cutoff (eqnUOEFEAtomic,
+// eqnKSAtomicTrunc, eqnCutoffProperties), their orthogonalization against the
+// FE space (eqnUOEFEOrtho, eqnorthC, eqnorthCGLL), and the enrichment blocks
+// M^oo (eqnMoo), H^co and H^oo (eqnHOEFEelelements).  Integrals of H use one
+// tensor Gauss rule with p + 1 points per direction; the numerator of c uses
+// the same rule and the denominator the GLL mass.  Cell-level transforms are
+// sum-factorized (tensor-product 1D passes).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "oefe_internal.h"
+
+namespace oefe {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// P_n(x) and P_{n-1}(x) by the three-term recurrence.
+void legendre_pair(int n, double x, double& pn, double& pn1) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) { pn = 1.0; pn1 = 0.0; return; }
+  for (int k = 1; k < n; ++k) {
+    double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  pn1 = p0;
+}
+
+// GLL nodes: -1, 1 and the zeros of x P_p - P_{p-1} (equivalently of P_p');
+// weights 2 / (p (p+1) P_p^2).
+void gll_rule(int p, double* x, double* w) {
+  for (int j = 0; j <= p; ++j) x[j] = -std::cos(kPi * j / p);
+  for (int j = 1; j < p; ++j) {
+    for (int it = 0; it < 100; ++it) {
+      double pn, pn1;
+      legendre_pair(p, x[j], pn, pn1);
+      double f = x[j] * pn - pn1;
+      double dx = f / ((p + 1) * pn);
+      x[j] -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+  }
+  x[0] = -1.0;
+  x[p] = 1.0;
+  for (int j = 0; j <= p; ++j) {
+    double pn, pn1;
+    legendre_pair(p, x[j], pn, pn1);
+    w[j] = 2.0 / (p * (p + 1) * pn * pn);
+  }
+}
+
+// Gauss-Legendre: zeros of P_q, weights 2 / ((1 - x^2) P_q'(x)^2).
+void gauss_rule(int q, double* x, double* w) {
+  for (int j = 0; j < q; ++j) {
+    double z = -std::cos(kPi * (j + 0.75) / (q + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double pn, pn1;
+      legendre_pair(q, z, pn, pn1);
+      double dp = q * (z * pn - pn1) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double pn, pn1;
+    legendre_pair(q, z, pn, pn1);
+    double dp = q * (z * pn - pn1) / (z * z - 1.0);
+    x[j] = z;
+    w[j] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Lagrange basis on `nodes` (count n): value and derivative of ell_a at t.
+void lagrange(int n, const double* nodes, int a, double t, double& val, double& der) {
+  double denom = 1.0, num = 1.0;
+  for (int j = 0; j < n; ++j)
+    if (j != a) {
+      denom *= nodes[a] - nodes[j];
+      num *= t - nodes[j];
+    }
+  val = num / denom;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (k == a) continue;
+    double pr = 1.0;
+    for (int j = 0; j < n; ++j)
+      if (j != a && j != k) pr *= t - nodes[j];
+    s += pr;
+  }
+  der = s / denom;
+}
+
+// In-place inverse of a small dense matrix (Gauss-Jordan, partial pivoting).
+bool invert(int n, double* A) {
+  std::vector<double> M(2 * n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) M[i * 2 * n + j] = A[i * n + j];
+    M[i * 2 * n + n + i] = 1.0;
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[r * 2 * n + c]) > std::fabs(M[piv * 2 * n + c])) piv = r;
+    if (M[piv * 2 * n + c] == 0.0) return false;
+    if (piv != c)
+      for (int j = 0; j < 2 * n; ++j) std::swap(M[c * 2 * n + j], M[piv * 2 * n + j]);
+    double d = M[c * 2 * n + c];
+    for (int j = 0; j < 2 * n; ++j) M[c * 2 * n + j] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = M[r * 2 * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < 2 * n; ++j) M[r * 2 * n + j] -= f * M[c * 2 * n + j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[i * n + j] = M[i * 2 * n + n + j];
+  return true;
+}
+
+// erf(r/sigma)/r with its small-r series.
+double erf_over_r(double r, double sigma) {
+  if (r < 1e-6 * sigma) {
+    double x = r / sigma;
+    return 2.0 / (sigma * std::sqrt(kPi)) * (1.0 - x * x / 3.0 + x * x * x * x / 10.0);
+  }
+  return std::erf(r / sigma) / r;
+}
+
+// Smooth cutoff h(r) and h'(r): 1 below r0, 0 above r1, 1/(1 + exp(1/x - 1/(1-x))) between.
+void cutoff(double r, double r0, double r1, double& h, double& dh) {
+  if (r <= r0) { h = 1.0; dh = 0.0; return; }
+  if (r >= r1) { h = 0.0; dh = 0.0; return; }
+  double x = (r1 - r) / (r1 - r0);
+  double u = 1.0 / x - 1.0 / (1.0 - x);
+  double s;
+  if (u > 0) {
+    double e = std::exp(-u);
+    s = e / (1.0 + e);
+  } else {
+    s = 1.0 / (1.0 + std::exp(u));
+  }
+  h = s;
+  double dsdx = s * (1.0 - s) * (1.0 / (x * x) + 1.0 / ((1.0 - x) * (1.0 - x)));
+  dh = -dsdx / (r1 - r0);
+}
+
+// Atomic function r^pw exp(-zeta r) [d_axis] h(r) and its gradient at displacement d.
+void atomic_fn(const double d[3], int pw, double zeta, int axis, double r0, double r1, double& val,
+               double grad[3]) {
+  double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double e = std::exp(-zeta * r);
+  double rp = pw == 0 ? 1.0 : std::pow(r, pw);
+  double f = rp * e;
+  double fp = (pw == 0 ? 0.0 : pw * std::pow(r, pw - 1)) * e - zeta * f;
+  double h, dh;
+  cutoff(r, r0, r1, h, dh);
+  double radial = fp * h + f * dh;  // d/dr of f h
+  if (axis < 0) {
+    val = f * h;
+    for (int k = 0; k < 3; ++k) grad[k] = radial * d[k] / r;
+  } else {
+    double P = d[axis];
+    val = P * f * h;
+    for (int k = 0; k < 3; ++k) grad[k] = P * radial * d[k] / r;
+    grad[axis] += f * h;
+  }
+}
+
+// Tensor-product transforms on one cell (P1 = q = p + 1 points per direction).
+// fwd: out[qz][qy][qx] = sum Mz[qz][az] My[qy][ay] Mx[qx][ax] in[az][ay][ax]
+template <typename S>
+void tp_forward(int P1, const double* Mx, const double* My, const double* Mz, const S* in, S* out) {
+  S t1[125], t2[125];
+  for (int az = 0; az < P1; ++az)
+    for (int ay = 0; ay < P1; ++ay)
+      for (int qx = 0; qx < P1; ++qx) {
+        S s = 0;
+        for (int ax = 0; ax < P1; ++ax) s += Mx[qx * 8 + ax] * in[(az * P1 + ay) * P1 + ax];
+        t1[(az * P1 + ay) * P1 + qx] = s;
+      }
+  for (int az = 0; az < P1; ++az)
+    for (int qy = 0; qy < P1; ++qy)
+      for (int qx = 0; qx < P1; ++qx) {
+        S s = 0;
+        for (int ay = 0; ay < P1; ++ay) s += My[qy * 8 + ay] * t1[(az * P1 + ay) * P1 + qx];
+        t2[(az * P1 + qy) * P1 + qx] = s;
+      }
+  for (int qz = 0; qz < P1; ++qz)
+    for (int qy = 0; qy < P1; ++qy)
+      for (int qx = 0; qx < P1; ++qx) {
+        S s = 0;
+        for (int az = 0; az < P1; ++az) s += Mz[qz * 8 + az] * t2[(az * P1 + qy) * P1 + qx];
+        out[(qz * P1 + qy) * P1 + qx] = s;
+      }
+}
+
+// bwd (transpose): out[az][ay][ax] = sum Mz[qz][az] My[qy][ay] Mx[qx][ax] in[qz][qy][qx]
+template <typename S>
+void tp_backward(int P1, const double* Mx, const double* My, const double* Mz, const S* in, S* out) {
+  S t1[125], t2[125];
+  for (int qz = 0; qz < P1; ++qz)
+    for (int qy = 0; qy < P1; ++qy)
+      for (int ax = 0; ax < P1; ++ax) {
+        S s = 0;
+        for (int qx = 0; qx < P1; ++qx) s += Mx[qx * 8 + ax] * in[(qz * P1 + qy) * P1 + qx];
+        t1[(qz * P1 + qy) * P1 + ax] = s;
+      }
+  for (int qz = 0; qz < P1; ++qz)
+    for (int ay = 0; ay < P1; ++ay)
+      for (int ax = 0; ax < P1; ++ax) {
+        S s = 0;
+        for (int qy = 0; qy < P1; ++qy) s += My[qy * 8 + ay] * t1[(qz * P1 + qy) * P1 + ax];
+        t2[(qz * P1 + ay) * P1 + ax] = s;
+      }
+  for (int az = 0; az < P1; ++az)
+    for (int ay = 0; ay < P1; ++ay)
+      for (int ax = 0; ax < P1; ++ax) {
+        S s = 0;
+        for (int qz = 0; qz < P1; ++qz) s += Mz[qz * 8 + az] * t2[(qz * P1 + ay) * P1 + ax];
+        out[(az * P1 + ay) * P1 + ax] = s;
+      }
+}
+
+struct Geo {
+  const oefe_op_s* op;
+  int64_t cell_of(int cx, int cy, int cz) const {
+    int nc = op->nc;
+    cx = ((cx % nc) + nc) % nc;
+    cy = ((cy % nc) + nc) % nc;
+    cz = ((cz % nc) + nc) % nc;
+    return cx + (int64_t)nc * (cy + (int64_t)nc * cz);
+  }
+  // global FE index and Bloch phase of local node a of cell e
+  void dof(int64_t e, int a, int64_t& g, cplx& th) const {
+    int nc = op->nc, p = op->p, P1 = op->P1, n = op->n;
+    int cx = e % nc, cy = (e / nc) % nc, cz = e / ((int64_t)nc * nc);
+    int ax = a % P1, ay = (a / P1) % P1, az = a / (P1 * P1);
+    int ix = cx * p + ax, iy = cy * p + ay, iz = cz * p + az;
+    th = cplx(1.0, 0.0);
+    if (ix >= n) { ix -= n; th *= cplx(op->phase[0][0], op->phase[0][1]); }
+    if (iy >= n) { iy -= n; th *= cplx(op->phase[1][0], op->phase[1][1]); }
+    if (iz >= n) { iz -= n; th *= cplx(op->phase[2][0], op->phase[2][1]); }
+    g = ix + (int64_t)n * (iy + (int64_t)n * iz);
+  }
+  void quad_point(int64_t e, int q, double x[3]) const {
+    int nc = op->nc, P1 = op->P1;
+    int c[3] = {(int)(e % nc), (int)((e / nc) % nc), (int)(e / ((int64_t)nc * nc))};
+    int qq[3] = {q % P1, (q / P1) % P1, q / (P1 * P1)};
+    for (int d = 0; d < 3; ++d) x[d] = c[d] * op->h + (op->gauss_x[qq[d]] + 1.0) * op->h / 2.0;
+  }
+};
+
+}  // namespace
+
+// Hermitian eigendecomposition by cyclic complex Jacobi: A = U diag(lam) U^*, ascending.
+void hermitian_eig(int n, std::vector<cplx>& A, std::vector<double>& lam, std::vector<cplx>& U) {
+  U.assign((size_t)n * n, cplx(0, 0));
+  for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> cplx& { return A[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        if (i == j) diag += std::norm(a(i, j));
+        else off += std::norm(a(i, j));
+      }
+    if (off <= 1e-30 * diag || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        cplx b = a(p, q);
+        double r = std::abs(b);
+        if (r == 0.0) continue;
+        double al = a(p, p).real(), ga = a(q, q).real();
+        if (r < 1e-300) continue;
+        cplx eph = b / r;  // e^{i phi}
+        double tau = (ga - al) / (2.0 * r);
+        double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        cplx emi = std::conj(eph);  // e^{-i phi}
+        // A <- A G (columns p, q), G = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
+        for (int k = 0; k < n; ++k) {
+          cplx akp = a(k, p), akq = a(k, q);
+          a(k, p) = akp * c - akq * s * emi;
+          a(k, q) = akp * s + akq * c * emi;
+        }
+        // A <- G^* A (rows p, q)
+        for (int k = 0; k < n; ++k) {
+          cplx apk = a(p, k), aqk = a(q, k);
+          a(p, k) = c * apk - s * eph * aqk;
+          a(q, k) = s * apk + c * eph * aqk;
+        }
+        a(p, q) = 0.0;
+        a(q, p) = 0.0;
+        a(p, p) = al - t * r;
+        a(q, q) = ga + t * r;
+        for (int k = 0; k < n; ++k) {
+          cplx ukp = U[(size_t)k * n + p], ukq = U[(size_t)k * n + q];
+          U[(size_t)k * n + p] = ukp * c - ukq * s * emi;
+          U[(size_t)k * n + q] = ukp * s + ukq * c * emi;
+        }
+      }
+  }
+  lam.resize(n);
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a(x, x).real() < a(y, y).real(); });
+  std::vector<cplx> U2((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    lam[j] = a(idx[j], idx[j]).real();
+    for (int k = 0; k < n; ++k) U2[(size_t)k * n + j] = U[(size_t)k * n + idx[j]];
+  }
+  U.swap(U2);
+}
+
+int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err) {
+  const int p = desc->p;
+  if (p < 2 || p > 4) { err = "degree p must be 2, 3 or 4"; return OEFE_EUNSUPPORTED; }
+  if (desc->nc < 2 || desc->L <= 0) { err = "need nc >= 2 and L > 0"; return OEFE_EINVAL; }
+  if (desc->n_enr > 0 && !(desc->r1 > desc->r0 && desc->r0 > 0 && desc->r1 < 0.5 * desc->L)) {
+    err = "need 0 < r0 < r1 < L/2";
+    return OEFE_EINVAL;
+  }
+  op->L = desc->L;
+  op->nc = desc->nc;
+  op->p = p;
+  op->P1 = p + 1;
+  op->n = op->nc * p;
+  op->nd = op->P1 * op->P1 * op->P1;
+  op->nq = op->nd;
+  op->h = op->L / op->nc;
+  op->N = (int64_t)op->n * op->n * op->n;
+  op->n_cells = (int64_t)op->nc * op->nc * op->nc;
+  op->n_enr = desc->n_enr;
+  op->n_tot = op->N + op->n_enr;
+  op->cplx = desc->kvec != nullptr;
+  if (op->cplx) {
+    for (int d = 0; d < 3; ++d) {
+      op->kvec[d] = desc->kvec[d];
+      op->phase[d][0] = std::cos(desc->kvec[d] * op->L);
+      op->phase[d][1] = std::sin(desc->kvec[d] * op->L);
+    }
+  }
+  const int P1 = op->P1;
+  const double h = op->h;
+  // ---- 1D data
+  double xi[8], what[8];
+  gll_rule(p, xi, what);
+  gauss_rule(P1, op->gauss_x, op->gauss_w);
+  for (int j = 0; j <= p; ++j) op->gll_w[j] = what[j];
+  for (int qi = 0; qi < P1; ++qi)
+    for (int a = 0; a < P1; ++a) lagrange(P1, xi, a, op->gauss_x[qi], op->B1[qi][a], op->D1[qi][a]);
+  double Binv[25], Dh[25], L1[25];
+  for (int i = 0; i < P1; ++i)
+    for (int j = 0; j < P1; ++j) Binv[i * P1 + j] = op->B1[i][j];
+  if (!invert(P1, Binv)) { err = "singular interpolation matrix"; return OEFE_EINVAL; }
+  for (int i = 0; i < P1; ++i)
+    for (int j = 0; j < P1; ++j) {
+      double s = 0;
+      for (int k = 0; k < P1; ++k) s += op->D1[i][k] * Binv[k * P1 + j];
+      Dh[i * P1 + j] = s;
+    }
+  for (int i = 0; i < P1; ++i)
+    for (int j = 0; j < P1; ++j) {
+      double s = 0;
+      for (int k = 0; k < P1; ++k) s += Dh[k * P1 + i] * op->gauss_w[k] * Dh[k * P1 + j];
+      L1[i * P1 + j] = s;
+    }
+  std::memset(&op->cd, 0, sizeof(op->cd));
+  for (int i = 0; i < P1; ++i) {
+    op->cd.w[i] = op->gauss_w[i];
+    double wp = what[i % p] * (i % p == 0 ? 2.0 : 1.0);
+    op->cd.om[i] = 1.0 / std::sqrt(wp);
+    for (int j = 0; j < P1; ++j) {
+      op->cd.B1[i][j] = op->B1[i][j];
+      op->cd.L1[i][j] = L1[i * P1 + j];
+      op->cd.BtW[i][j] = op->B1[j][i] * op->gauss_w[j];
+      double s = 0;
+      for (int k = 0; k < P1; ++k) s += op->B1[k][i] * L1[k * P1 + j];
+      op->cd.BtL[i][j] = s;
+    }
+  }
+  op->cd.kappa = h / 4.0;
+  op->cd.mscale = std::pow(h / 2.0, -1.5);
+  {
+    auto& f = op->cf;
+    auto& c = op->cd;
+    for (int i = 0; i < kMaxP1; ++i) {
+      f.w[i] = (float)c.w[i];
+      f.om[i] = (float)c.om[i];
+      for (int j = 0; j < kMaxP1; ++j) {
+        f.B1[i][j] = (float)c.B1[i][j];
+        f.L1[i][j] = (float)c.L1[i][j];
+        f.BtL[i][j] = (float)c.BtL[i][j];
+        f.BtW[i][j] = (float)c.BtW[i][j];
+      }
+    }
+    f.kappa = (float)c.kappa;
+    f.mscale = (float)c.mscale;
+  }
+  // ---- lumped GLL mass m_g = (h/2)^3 prod_d w'(i_d mod p)
+  const int n = op->n;
+  op->mdiag.resize(op->N);
+  for (int64_t g = 0; g < op->N; ++g) {
+    int ix = g % n, iy = (g / n) % n, iz = g / ((int64_t)n * n);
+    double m = std::pow(h / 2.0, 3);
+    int ii[3] = {ix % p, iy % p, iz % p};
+    for (int d = 0; d < 3; ++d) m *= what[ii[d]] * (ii[d] == 0 ? 2.0 : 1.0);
+    op->mdiag[g] = m;
+  }
+  Geo geo{op};
+  const int nq = op->nq;
+  // ---- quadrature weights and potential
+  op->W.resize(op->n_cells * nq);
+  op->V.resize(op->n_cells * nq);
+  const double h3 = std::pow(h / 2.0, 3);
+  for (int64_t e = 0; e < op->n_cells; ++e)
+    for (int q = 0; q < nq; ++q) {
+      int qx = q % P1, qy = (q / P1) % P1, qz = q / (P1 * P1);
+      op->W[e * nq + q] = h3 * op->gauss_w[qx] * op->gauss_w[qy] * op->gauss_w[qz];
+      double x[3];
+      geo.quad_point(e, q, x);
+      double v = 0.0;
+      for (int I = 0; I < desc->n_atoms; ++I) {
+        double d2 = 0;
+        for (int k = 0; k < 3; ++k) {
+          double dd = x[k] - desc->pos[3 * I + k];
+          dd -= op->L * std::nearbyint(dd / op->L);
+          d2 += dd * dd;
+        }
+        v -= desc->Z[I] * erf_over_r(std::sqrt(d2), desc->sigma);
+      }
+      op->V[e * nq + q] = v;
+    }
+  // ---- enrichment blocks (one per atom with functions)
+  op->blocks.clear();
+  if (op->n_enr > 0) {
+    for (int nu = 0; nu < op->n_enr; ++nu) {
+      int I = desc->enr_atom[nu];
+      if (I < 0 || I >= desc->n_atoms) { err = "enrichment atom index out of range"; return OEFE_EINVAL; }
+      if (nu > 0 && desc->enr_atom[nu] < desc->enr_atom[nu - 1]) {
+        err = "enrichment list must be grouped by atom in ascending order";
+        return OEFE_EINVAL;
+      }
+    }
+    int nu = 0;
+    while (nu < op->n_enr) {
+      AtomBlock b;
+      b.atom = desc->enr_atom[nu];
+      b.fn0 = nu;
+      while (nu < op->n_enr && desc->enr_atom[nu] == b.atom) ++nu;
+      b.nf = nu - b.fn0;
+      op->blocks.push_back(std::move(b));
+    }
+  }
+  int FMAX = 1;
+  for (auto& b : op->blocks) FMAX = std::max(FMAX, b.nf);
+  if (FMAX > 8) { err = "at most 8 enrichment functions per atom are supported"; return OEFE_EUNSUPPORTED; }
+  op->FMAX = FMAX;
+  // matrices for the sum-factorized transforms (stride 8)
+  double Bm[64], Dm[64];
+  for (int i = 0; i < P1; ++i)
+    for (int j = 0; j < P1; ++j) {
+      Bm[i * 8 + j] = op->B1[i][j];
+      Dm[i * 8 + j] = op->D1[i][j];
+    }
+  const double s2h = 2.0 / h;
+  std::vector<cplx> dacc;   // [N][nf] accumulation of d (reused)
+  std::vector<char> touched;
+  for (auto& b : op->blocks) {
+    const double* R = &desc->pos[3 * b.atom];
+    // core cells: box within r1 of the atom (nearest image); support: core dilated by one layer
+    std::vector<char> core(op->n_cells, 0), sup(op->n_cells, 0);
+    for (int64_t e = 0; e < op->n_cells; ++e) {
+      int c[3] = {(int)(e % op->nc), (int)((e / op->nc) % op->nc), (int)(e / ((int64_t)op->nc * op->nc))};
+      double dist2 = 0;
+      for (int k = 0; k < 3; ++k) {
+        double dd = R[k] - (c[k] + 0.5) * h;
+        dd -= op->L * std::nearbyint(dd / op->L);
+        double ex = std::max(std::fabs(dd) - h / 2.0, 0.0);
+        dist2 += ex * ex;
+      }
+      if (dist2 < desc->r1 * desc->r1) core[e] = 1;
+    }
+    for (int64_t e = 0; e < op->n_cells; ++e) {
+      if (!core[e]) continue;
+      int cx = e % op->nc, cy = (e / op->nc) % op->nc, cz = e / ((int64_t)op->nc * op->nc);
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) sup[geo.cell_of(cx + dx, cy + dy, cz + dz)] = 1;
+    }
+    for (int64_t e = 0; e < op->n_cells; ++e)
+      if (sup[e]) b.cells.push_back(e);
+    const int nf = b.nf;
+    const size_t ncb = b.cells.size();
+    // N^A and grad N^A at the quadrature points of the support cells
+    std::vector<cplx> NA(ncb * nq * nf), gNA(ncb * nq * nf * 3);
+    for (size_t ci = 0; ci < ncb; ++ci) {
+      int64_t e = b.cells[ci];
+      for (int q = 0; q < nq; ++q) {
+        double x[3], d[3], t[3];
+        geo.quad_point(e, q, x);
+        for (int k = 0; k < 3; ++k) {
+          double dr = x[k] - R[k];
+          t[k] = std::nearbyint(dr / op->L);
+          d[k] = dr - op->L * t[k];
+        }
+        cplx ph(1.0, 0.0);
+        if (op->cplx) {
+          double arg = op->L * (op->kvec[0] * t[0] + op->kvec[1] * t[1] + op->kvec[2] * t[2]);
+          ph = cplx(std::cos(arg), std::sin(arg));
+        }
+        for (int f = 0; f < nf; ++f) {
+          int fn = b.fn0 + f;
+          double val, gr[3];
+          atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
+          NA[(ci * nq + q) * nf + f] = ph * val;
+          for (int k = 0; k < 3; ++k) gNA[((ci * nq + q) * nf + f) * 3 + k] = ph * gr[k];
+        }
+      }
+    }
+    // d_g = sum_{(e,a)->g} conj(theta_ea) sum_q W B[q,a] N^A ; c_g = d_g / m_g
+    dacc.assign((size_t)op->N * nf, cplx(0, 0));
+    std::vector<cplx> tin(nq), tout(nq);
+    for (size_t ci = 0; ci < ncb; ++ci) {
+      int64_t e = b.cells[ci];
+      for (int f = 0; f < nf; ++f) {
+        for (int q = 0; q < nq; ++q) tin[q] = op->W[e * nq + q] * NA[(ci * nq + q) * nf + f];
+        tp_backward<cplx>(P1, Bm, Bm, Bm, tin.data(), tout.data());
+        for (int a = 0; a < op->nd; ++a) {
+          int64_t g;
+          cplx th;
+          geo.dof(e, a, g, th);
+          dacc[(size_t)g * nf + f] += std::conj(th) * tout[a];
+        }
+      }
+    }
+    // orthogonalized values and gradients
+    b.phi.assign(ncb * nq * nf, cplx(0, 0));
+    b.gphi.assign(ncb * nq * nf * 3, cplx(0, 0));
+    std::vector<cplx> ce(op->nd), o(nq);
+    for (size_t ci = 0; ci < ncb; ++ci) {
+      int64_t e = b.cells[ci];
+      for (int f = 0; f < nf; ++f) {
+        for (int a = 0; a < op->nd; ++a) {
+          int64_t g;
+          cplx th;
+          geo.dof(e, a, g, th);
+          ce[a] = th * (dacc[(size_t)g * nf + f] / op->mdiag[g]);
+        }
+        tp_forward<cplx>(P1, Bm, Bm, Bm, ce.data(), o.data());
+        for (int q = 0; q < nq; ++q) b.phi[(ci * nq + q) * nf + f] = NA[(ci * nq + q) * nf + f] - o[q];
+        for (int dd = 0; dd < 3; ++dd) {
+          const double* Mx = dd == 0 ? Dm : Bm;
+          const double* My = dd == 1 ? Dm : Bm;
+          const double* Mz = dd == 2 ? Dm : Bm;
+          tp_forward<cplx>(P1, Mx, My, Mz, ce.data(), o.data());
+          for (int q = 0; q < nq; ++q)
+            b.gphi[((ci * nq + q) * nf + f) * 3 + dd] = gNA[((ci * nq + q) * nf + f) * 3 + dd] - s2h * o[q];
+        }
+      }
+    }
+    // rows of H^co: all FE nodes of the support cells
+    touched.assign(op->N, 0);
+    for (size_t ci = 0; ci < ncb; ++ci)
+      for (int a = 0; a < op->nd; ++a) {
+        int64_t g;
+        cplx th;
+        geo.dof(b.cells[ci], a, g, th);
+        touched[g] = 1;
+      }
+    b.rows.clear();
+    for (int64_t g = 0; g < op->N; ++g)
+      if (touched[g]) b.rows.push_back((int32_t)g);
+    // kinetic part of H^co: sum_q W 1/2 (2/h) G_d[q,a] dPhi_d
+    dacc.assign((size_t)op->N * nf, cplx(0, 0));
+    for (size_t ci = 0; ci < ncb; ++ci) {
+      int64_t e = b.cells[ci];
+      for (int f = 0; f < nf; ++f) {
+        std::vector<cplx> acc(op->nd, cplx(0, 0));
+        for (int dd = 0; dd < 3; ++dd) {
+          for (int q = 0; q < nq; ++q)
+            tin[q] = 0.5 * s2h * op->W[e * nq + q] * b.gphi[((ci * nq + q) * nf + f) * 3 + dd];
+          const double* Mx = dd == 0 ? Dm : Bm;
+          const double* My = dd == 1 ? Dm : Bm;
+          const double* Mz = dd == 2 ? Dm : Bm;
+          tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
+          for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+        }
+        for (int a = 0; a < op->nd; ++a) {
+          int64_t g;
+          cplx th;
+          geo.dof(e, a, g, th);
+          dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
+        }
+      }
+    }
+    b.hkin.resize(b.rows.size() * nf);
+    for (size_t r = 0; r < b.rows.size(); ++r)
+      for (int f = 0; f < nf; ++f) b.hkin[r * nf + f] = dacc[(size_t)b.rows[r] * nf + f];
+  }
+  // ---- M^oo and the kinetic part of H^oo over common support cells
+  const int nO = op->n_enr;
+  op->Moo.assign((size_t)nO * nO, cplx(0, 0));
+  op->Hoo_kin.assign((size_t)nO * nO, cplx(0, 0));
+  for (auto& bi : op->blocks)
+    for (auto& bj : op->blocks) {
+      size_t i = 0, j = 0;
+      while (i < bi.cells.size() && j < bj.cells.size()) {
+        if (bi.cells[i] < bj.cells[j]) { ++i; continue; }
+        if (bi.cells[i] > bj.cells[j]) { ++j; continue; }
+        int64_t e = bi.cells[i];
+        for (int q = 0; q < nq; ++q) {
+          double Wq = op->W[e * nq + q];
+          for (int f = 0; f < bi.nf; ++f) {
+            cplx a = std::conj(bi.phi[(i * nq + q) * bi.nf + f]);
+            const cplx* ga = &bi.gphi[((i * nq + q) * bi.nf + f) * 3];
+            for (int g2 = 0; g2 < bj.nf; ++g2) {
+              cplx bb = bj.phi[(j * nq + q) * bj.nf + g2];
+              const cplx* gb = &bj.gphi[((j * nq + q) * bj.nf + g2) * 3];
+              size_t ix = (size_t)(bi.fn0 + f) * nO + (bj.fn0 + g2);
+              op->Moo[ix] += Wq * a * bb;
+              op->Hoo_kin[ix] +=
+                  0.5 * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
+            }
+          }
+        }
+        ++i;
+        ++j;
+      }
+    }
+  // ---- S = (M^oo)^-1/2
+  if (nO > 0) {
+    std::vector<cplx> A(op->Moo), U;
+    for (int i = 0; i < nO; ++i)
+      for (int j = 0; j < nO; ++j) A[(size_t)i * nO + j] = 0.5 * (op->Moo[(size_t)i * nO + j] + std::conj(op->Moo[(size_t)j * nO + i]));
+    hermitian_eig(nO, A, op->Moo_eigs, U);
+    if (op->Moo_eigs[0] <= 0.0) { err = "enrichment overlap M^oo is not positive definite"; return OEFE_EINVAL; }
+    op->S.assign((size_t)nO * nO, cplx(0, 0));
+    for (int i = 0; i < nO; ++i)
+      for (int j = 0; j < nO; ++j) {
+        cplx s = 0;
+        for (int k = 0; k < nO; ++k) s += U[(size_t)i * nO + k] * (1.0 / std::sqrt(op->Moo_eigs[k])) * std::conj(U[(size_t)j * nO + k]);
+        op->S[(size_t)i * nO + j] = s;
+      }
+  }
+  return rebuild_potential_parts(op, err);
+}
+
+// Potential-dependent parts: H^oo = H^oo_kin + sum W V conj(Phi) Phi and the H^co values are
+// recomputed by the upload step from the stored kinetic part plus sum_q B[q,a] W V Phi.
+int rebuild_potential_parts(oefe_op_s* op, std::string& err) {
+  (void)err;
+  const int nO = op->n_enr, nq = op->nq, P1 = op->P1;
+  op->Hoo = op->Hoo_kin;
+  for (auto& bi : op->blocks)
+    for (auto& bj : op->blocks) {
+      size_t i = 0, j = 0;
+      while (i < bi.cells.size() && j < bj.cells.size()) {
+        if (bi.cells[i] < bj.cells[j]) { ++i; continue; }
+        if (bi.cells[i] > bj.cells[j]) { ++j; continue; }
+        int64_t e = bi.cells[i];
+        for (int q = 0; q < nq; ++q) {
+          double wv = op->W[e * nq + q] * op->V[e * nq + q];
+          for (int f = 0; f < bi.nf; ++f) {
+            cplx a = std::conj(bi.phi[(i * nq + q) * bi.nf + f]);
+            for (int g2 = 0; g2 < bj.nf; ++g2)
+              op->Hoo[(size_t)(bi.fn0 + f) * nO + (bj.fn0 + g2)] += wv * a * bj.phi[(j * nq + q) * bj.nf + g2];
+          }
+        }
+        ++i;
+        ++j;
+      }
+    }
+  (void)P1;
+  return OEFE_OK;
+}
+
+// H^co values on the rows of block b: kinetic part + potential part.
+void block_hco_values(const oefe_op_s* op, const AtomBlock& b, std::vector<cplx>& out) {
+  const int nq = op->nq, P1 = op->P1, nf = b.nf;
+  double Bm[64];
+  for (int i = 0; i < P1; ++i)
+    for (int j = 0; j < P1; ++j) Bm[i * 8 + j] = op->B1[i][j];
+  Geo geo{op};
+  std::vector<cplx> acc((size_t)op->N * 0 + 1);
+  // local row index of every global row of this block
+  std::vector<int32_t> local(op->N, -1);
+  for (size_t r = 0; r < b.rows.size(); ++r) local[b.rows[r]] = (int32_t)r;
+  out.assign(b.rows.size() * nf, cplx(0, 0));
+  std::vector<cplx> tin(nq), tout(nq);
+  for (size_t ci = 0; ci < b.cells.size(); ++ci) {
+    int64_t e = b.cells[ci];
+    for (int f = 0; f < nf; ++f) {
+      for (int q = 0; q < nq; ++q) tin[q] = op->W[e * nq + q] * op->V[e * nq + q] * b.phi[(ci * nq + q) * nf + f];
+      tp_backward<cplx>(P1, Bm, Bm, Bm, tin.data(), tout.data());
+      for (int a = 0; a < op->nd; ++a) {
+        int64_t g;
+        cplx th;
+        geo.dof(e, a, g, th);
+        out[(size_t)local[g] * nf + f] += std::conj(th) * tout[a];
+      }
+    }
+  }
+  for (size_t k = 0; k < out.size(); ++k) out[k] += b.hkin[k];
+}
+
+}  // namespace oefe

@@ -1,0 +1,309 @@
+"""Python binding of liboefe.so (the C ABI in include/oefe.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  Vector blocks are torch tensors on the HIP device (row-major
+[n_tot, nv] with unit column stride; complex dtypes for a Bloch operator);
+calls are ordered on torch's current stream.  There is no CPU fallback: if
+the library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import workloads
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboefe.so")
+
+F64, F32, BF16, C128, C64 = 0, 1, 2, 3, 4
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTSPD", -5: "ENOCONV", -6: "EUNSUPPORTED"}
+
+
+class OefeError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {_STATUS.get(code, code)} ({msg})")
+        self.code = code
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_double),
+        ("nc", ctypes.c_int32),
+        ("p", ctypes.c_int32),
+        ("n_atoms", ctypes.c_int32),
+        ("pos", ctypes.POINTER(ctypes.c_double)),
+        ("Z", ctypes.POINTER(ctypes.c_double)),
+        ("sigma", ctypes.c_double),
+        ("r0", ctypes.c_double),
+        ("r1", ctypes.c_double),
+        ("n_enr", ctypes.c_int32),
+        ("enr_atom", ctypes.POINTER(ctypes.c_int32)),
+        ("enr_power", ctypes.POINTER(ctypes.c_int32)),
+        ("enr_zeta", ctypes.POINTER(ctypes.c_double)),
+        ("enr_axis", ctypes.POINTER(ctypes.c_int32)),
+        ("kvec", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2010_09701_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "oefe_op_create": ([ctypes.POINTER(_Desc), ctypes.POINTER(vp)], i32),
+        "oefe_op_create_diagonal": ([vp, i64, ctypes.POINTER(vp)], i32),
+        "oefe_op_destroy": ([vp], i32),
+        "oefe_op_dims": ([vp, vp], i32),
+        "oefe_op_set_potential": ([vp, vp], i32),
+        "oefe_op_get_potential": ([vp, vp, vp], i32),
+        "oefe_op_get_enrichment": ([vp, vp, vp], i32),
+        "oefe_work_size": ([vp, i32, i32], ctypes.c_size_t),
+        "ham_apply": ([vp, i32, vp, vp, i64, i32, vp, vp], i32),
+        "chebyshev_filter": ([vp, i32, vp, i64, i32, i32, dbl, dbl, dbl, vp, vp], i32),
+        "chebyshev_filter_mixed": ([vp, i32, vp, i64, i32, i32, dbl, dbl, dbl, vp, vp], i32),
+        "lanczos_bounds": ([vp, i32, vp, vp, vp, vp], i32),
+        "cholgs": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
+        "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
+        "band_energy_grad": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
+        "oefe_kernel_timer": ([vp, i32], i32),
+        "oefe_kernel_timer_read": ([vp, vp, vp], i32),
+        "oefe_strerror": ([i32], ctypes.c_char_p),
+        "oefe_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = [
+    "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
+    "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
+    "chebyshev_filter_mixed", "lanczos_bounds", "cholgs", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
+    "oefe_kernel_timer_read", "oefe_strerror", "oefe_last_error",
+]
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise OefeError(rc, where, _lib.oefe_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _prec(t: torch.Tensor, bf16: bool = False) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return BF16 if bf16 else F32
+    if t.dtype == torch.complex128:
+        return C128
+    if t.dtype == torch.complex64:
+        return C64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _block(X: torch.Tensor, n_tot: int) -> Tuple[int, int]:
+    if not X.is_cuda:
+        raise ValueError("vector blocks must live on the HIP device")
+    if X.dim() != 2 or X.shape[0] != n_tot or X.stride(1) != 1:
+        raise ValueError(f"expected a [n_tot={n_tot}, nv] block with unit column stride, got {tuple(X.shape)}")
+    return X.stride(0), X.shape[1]
+
+
+class Operator:
+    """Device-resident OEFE operator (or a diagonal test operator)."""
+
+    def __init__(self, system: Optional[workloads.System] = None, _handle=None):
+        self._h = ctypes.c_void_p(0)
+        if _handle is not None:
+            self._h = _handle
+        else:
+            s = system
+            atom, power, zeta, axis = s.enr_arrays()
+            self._keep = [np.ascontiguousarray(s.pos, dtype=np.float64).ravel(),
+                          np.ascontiguousarray(s.Z, dtype=np.float64), atom, power, zeta, axis]
+            kv = None if s.kvec is None else np.ascontiguousarray(s.kvec, dtype=np.float64)
+            self._keep.append(kv)
+            P = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t)) if a is not None and a.size else None
+            d = _Desc(
+                s.L, s.nc, s.p, s.n_atoms, P(self._keep[0], ctypes.c_double), P(self._keep[1], ctypes.c_double),
+                s.sigma, s.r0, s.r1, s.n_enr, P(atom, ctypes.c_int32), P(power, ctypes.c_int32),
+                P(zeta, ctypes.c_double), P(axis, ctypes.c_int32), P(kv, ctypes.c_double) if kv is not None else None)
+            if not torch.cuda.is_available():
+                raise RuntimeError("no HIP device")
+            torch.cuda.current_device()
+            _check(_lib.oefe_op_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create")
+        dims = (ctypes.c_int64 * 8)()
+        _check(_lib.oefe_op_dims(self._h, dims), "oefe_op_dims")
+        self.n_fe, self.n_enr, self.n_tot, self.n_cells, self.nq, self.nc, self.p, cx = [int(x) for x in dims]
+        self.is_complex = bool(cx)
+        self._work = {}
+
+    @classmethod
+    def diagonal(cls, lam: np.ndarray) -> "Operator":
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        torch.cuda.current_device()
+        h = ctypes.c_void_p(0)
+        _check(_lib.oefe_op_create_diagonal(lam.ctypes.data_as(ctypes.c_void_p), lam.size, ctypes.byref(h)),
+               "oefe_op_create_diagonal")
+        return cls(_handle=h)
+
+    def close(self):
+        if self._h:
+            _lib.oefe_op_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def work_size(self, prec: int, nv: int) -> int:
+        return int(_lib.oefe_work_size(self._h, prec, nv))
+
+    def work(self, prec: int, nv: int) -> torch.Tensor:
+        """A cached device work buffer of at least work_size(prec, nv) bytes."""
+        need = self.work_size(prec, nv)
+        w = self._work.get("buf")
+        if w is None or w.numel() < need:
+            w = torch.empty(need, dtype=torch.uint8, device="cuda")
+            self._work["buf"] = w
+        return w
+
+    def kernel_timer(self, enable: bool):
+        _check(_lib.oefe_kernel_timer(self._h, 1 if enable else 0), "oefe_kernel_timer")
+
+    def kernel_timer_read(self):
+        """(launches, total milliseconds) of the bracketed cell-kernel launches since the last read."""
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(_lib.oefe_kernel_timer_read(self._h, ctypes.byref(n), ctypes.byref(ms)), "oefe_kernel_timer_read")
+        return int(n.value), float(ms.value)
+
+    def set_potential(self, V: np.ndarray):
+        V = np.ascontiguousarray(V, dtype=np.float64).ravel()
+        if V.size != self.n_cells * self.nq:
+            raise ValueError("V must have n_cells * nq entries")
+        _check(_lib.oefe_op_set_potential(self._h, V.ctypes.data_as(ctypes.c_void_p)), "oefe_op_set_potential")
+
+    def get_potential(self):
+        V = np.empty(self.n_cells * self.nq)
+        W = np.empty(self.n_cells * self.nq)
+        _check(_lib.oefe_op_get_potential(self._h, V.ctypes.data_as(ctypes.c_void_p),
+                                          W.ctypes.data_as(ctypes.c_void_p)), "oefe_op_get_potential")
+        return V.reshape(self.n_cells, self.nq), W.reshape(self.n_cells, self.nq)
+
+    def get_enrichment(self):
+        n = self.n_enr
+        S = np.empty(n * n * (2 if self.is_complex else 1))
+        ev = np.empty(n)
+        _check(_lib.oefe_op_get_enrichment(self._h, S.ctypes.data_as(ctypes.c_void_p),
+                                           ev.ctypes.data_as(ctypes.c_void_p)), "oefe_op_get_enrichment")
+        if self.is_complex:
+            S = S.reshape(n, n, 2)
+            S = S[..., 0] + 1j * S[..., 1]
+        return S.reshape(n, n), ev
+
+
+def ham_apply(op: Operator, X: torch.Tensor, Y: Optional[torch.Tensor] = None, bf16: bool = False) -> torch.Tensor:
+    ld, nv = _block(X, op.n_tot)
+    if Y is None:
+        Y = torch.empty_like(X)
+    ldy, _ = _block(Y, op.n_tot)
+    if ldy != ld:
+        raise ValueError("X and Y must share the leading dimension")
+    prec = _prec(X, bf16)
+    w = op.work(prec, nv)
+    _check(_lib.ham_apply(op.handle, prec, _ptr(X), _ptr(Y), ld, nv, _ptr(w), _stream()), "ham_apply")
+    return Y
+
+
+def chebyshev_filter(op: Operator, X: torch.Tensor, m: int, a: float, b: float, a0: float,
+                     bf16: bool = False) -> torch.Tensor:
+    ld, nv = _block(X, op.n_tot)
+    prec = _prec(X, bf16)
+    w = op.work(prec, nv)
+    _check(_lib.chebyshev_filter(op.handle, prec, _ptr(X), ld, nv, int(m), float(a), float(b), float(a0),
+                                 _ptr(w), _stream()), "chebyshev_filter")
+    return X
+
+
+def chebyshev_filter_mixed(op: Operator, X: torch.Tensor, m: int, a: float, b: float, a0: float,
+                           bf16: bool = False) -> torch.Tensor:
+    """Filter a float64 (complex128) block with float32 (or bf16-operand) arithmetic, in place."""
+    ld, nv = _block(X, op.n_tot)
+    if X.dtype == torch.float64:
+        prec = BF16 if bf16 else F32
+    elif X.dtype == torch.complex128:
+        prec = C64
+    else:
+        raise TypeError("chebyshev_filter_mixed takes a float64 or complex128 block")
+    w = op.work(prec, nv)
+    _check(_lib.chebyshev_filter_mixed(op.handle, prec, _ptr(X), ld, nv, int(m), float(a), float(b), float(a0),
+                                       _ptr(w), _stream()), "chebyshev_filter_mixed")
+    return X
+
+
+def lanczos_bounds(op: Operator, v0: torch.Tensor, k: int = 10) -> Tuple[float, float]:
+    if v0.dim() != 1 or v0.shape[0] != op.n_tot:
+        raise ValueError("v0 must be a vector of length n_tot")
+    dt = torch.complex128 if op.is_complex else torch.float64
+    v0 = v0.to(dtype=dt).contiguous()
+    prec = C128 if op.is_complex else F64
+    w = op.work(prec, k + 2)
+    out = (ctypes.c_double * 2)()
+    _check(_lib.lanczos_bounds(op.handle, int(k), _ptr(v0), out, _ptr(w), _stream()), "lanczos_bounds")
+    return float(out[0]), float(out[1])
+
+
+def cholgs(op: Operator, X: torch.Tensor, status: Optional[torch.Tensor] = None) -> torch.Tensor:
+    ld, nv = _block(X, op.n_tot)
+    prec = _prec(X)
+    w = op.work(prec, nv)
+    _check(_lib.cholgs(op.handle, prec, _ptr(X), ld, nv, _ptr(w), _ptr(status), _stream()), "cholgs")
+    return X
+
+
+def rayleigh_ritz(op: Operator, Q: torch.Tensor) -> torch.Tensor:
+    ld, nv = _block(Q, op.n_tot)
+    prec = _prec(Q)
+    w = op.work(prec, nv)
+    ev = torch.empty(nv, dtype=torch.float64, device=Q.device)
+    _check(_lib.rayleigh_ritz(op.handle, prec, _ptr(Q), ld, nv, _ptr(ev), _ptr(w), _stream()), "rayleigh_ritz")
+    return ev
+
+
+def band_energy_grad(op: Operator, X: torch.Tensor, f: torch.Tensor, want_dV: bool = True, want_dX: bool = True,
+                     bf16: bool = False):
+    """(E, dE/dV [n_cells, nq] or None, dE/dX or None)."""
+    ld, nv = _block(X, op.n_tot)
+    prec = _prec(X, bf16)
+    f = f.to(device=X.device, dtype=torch.float64).contiguous()
+    E = torch.empty((), dtype=torch.float64, device=X.device)
+    dV = torch.empty(op.n_cells, op.nq, dtype=torch.float64, device=X.device) if want_dV else None
+    dX = torch.empty_like(X) if want_dX else None
+    w = op.work(prec, nv)
+    _check(_lib.band_energy_grad(op.handle, prec, _ptr(X), ld, nv, _ptr(f), _ptr(E), _ptr(dV), _ptr(dX), _ptr(w),
+                                 _stream()), "band_energy_grad")
+    return E, dV, dX

@@ -1,0 +1,66 @@
+"""Write the stored oracle values used by the full-size GPU parity tests.
+
+Every value here comes from the CPU oracle (oracle/) on the seeded synthetic
+workloads of paper_2010_09701_amd/workloads.py; nothing is read from the HIP
+library.  The paper prints no values that apply to these synthetic operators.
+
+    python tests/golden/make_golden.py diamond8     (about 10 min on 8 cores)
+    python tests/golden/make_golden.py diamond64    (about 15 min, ~40 GB RAM)
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import chfsi as ch  # noqa: E402
+from oracle.operator import OEFEOperator  # noqa: E402
+from paper_2010_09701_amd import workloads as wl  # noqa: E402
+
+
+def sample_rows(n_fe: int, n_enr: int, count: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    fe = np.sort(rng.choice(n_fe, size=count, replace=False))
+    return np.concatenate([fe, n_fe + np.arange(n_enr)]).astype(np.int64)
+
+
+def diamond8():
+    cfg = wl.config("diamond8")
+    t = time.time()
+    op = OEFEOperator(cfg.system)
+    print("operator", time.time() - t, flush=True)
+    X0 = wl.start_block(op.n_tot, cfg.nv, cfg.x0_seed)
+    v0 = wl.lanczos_start(op.n_tot, cfg.v0_seed)
+    rows = sample_rows(op.N, op.n_enr, 200, 17)
+    HX = op.apply(X0)
+    a0L, b, _, _ = ch.lanczos_bounds(op.apply, v0, cfg.lanczos_k)
+    print("bounds", a0L, b, flush=True)
+    a = 0.5 * (a0L + b)
+    Y1 = ch.chebyshev_filter(op.apply, X0, cfg.m, a, b, a0L)
+    r = ch.chfsi(op.apply, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k)
+    thetas = np.stack([p["theta"] for p in r["passes"]])
+    print("passes", thetas[:, :4], flush=True)
+    np.savez_compressed(os.path.join(HERE, "diamond8_oracle.npz"), rows=rows, hx_rows=HX[rows], a0L=a0L, b=b,
+                        filt1_rows=Y1[rows], filt1_colnorm=np.linalg.norm(Y1, axis=0), thetas=thetas,
+                        hx_colnorm=np.linalg.norm(HX, axis=0))
+
+
+def diamond64():
+    cfg = wl.config("diamond64")
+    t = time.time()
+    op = OEFEOperator(cfg.system)
+    print("operator", time.time() - t, flush=True)
+    X0 = wl.start_block(op.n_tot, cfg.nv, cfg.x0_seed)
+    rows = sample_rows(op.N, op.n_enr, 400, 19)
+    HX = op.apply(X0)
+    np.savez_compressed(os.path.join(HERE, "diamond64_oracle.npz"), rows=rows, hx_rows=HX[rows],
+                        hx_colnorm=np.linalg.norm(HX, axis=0), Moo_eigs=op.enr.Moo_eigs)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["diamond8"]
+    for w in which:
+        {"diamond8": diamond8, "diamond64": diamond64}[w]()

@@ -1,0 +1,304 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Tolerances (float64): element/column-wise relative 1e-10 for one operator
+application and for a filter from random vectors; Ritz values to
+1e-10 max(1, |theta|); subspaces per gap-separated multiplet (sine of the
+largest principal angle) to 1e-8.  Sizes span several cell tiles and ragged
+vector blocks.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import adjoint as adj
+from oracle import chfsi as och
+from oracle.operator import OEFEOperator
+from paper_2010_09701_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2010_09701_amd import oefe
+    return oefe
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _colrel(A, B):
+    num = np.linalg.norm(A - B, axis=0)
+    den = np.maximum(np.linalg.norm(B, axis=0), 1e-300)
+    return float((num / den).max())
+
+
+SYSTEMS = {
+    "single_atom": lambda: wl.single_atom(),
+    "tiny2": lambda: wl.tiny_system(nc=2, p=2, n_atoms=2, seed=7, L=5.0, r0=0.8, r1=2.0),
+    "p3": lambda: wl.tiny_system(nc=3, p=3, n_atoms=2, seed=11, L=7.0, r0=1.0, r1=2.5),
+    "diamond_nc4": lambda: wl.diamond8(nc=4, p=4),
+}
+
+
+@pytest.mark.parametrize("name,nv", [("single_atom", 8), ("single_atom", 13), ("tiny2", 5), ("p3", 24),
+                                     ("diamond_nc4", 72), ("diamond_nc4", 17)])
+def test_ham_apply_f64(lib, name, nv):
+    sysm = SYSTEMS[name]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    assert gop.n_tot == op.n_tot
+    X = wl.start_block(op.n_tot, nv, 0)
+    Y = lib.ham_apply(gop, _dev(X)).cpu().numpy()
+    assert _colrel(Y, op.apply(X)) < 1e-10
+
+
+def test_ham_apply_leading_dimension(lib):
+    import torch
+    sysm = SYSTEMS["single_atom"]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    X = wl.start_block(op.n_tot, 20, 0)
+    Xd = _dev(X)[:, 3:14]  # ld = 20, nv = 11
+    Yd = torch.zeros(op.n_tot, 20, dtype=torch.float64, device="cuda")[:, 3:14]
+    lib.ham_apply(gop, Xd, Yd)
+    assert _colrel(Yd.cpu().numpy(), op.apply(X[:, 3:14])) < 1e-10
+
+
+@pytest.mark.parametrize("name,nv", [("single_atom", 8), ("tiny2", 6), ("p3", 16)])
+def test_ham_apply_bloch_c128(lib, name, nv):
+    k = np.array([0.21, -0.37, 0.13])
+    sysm = SYSTEMS[name]().with_k(k)
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    X = wl.start_block(op.n_tot, nv, 3, complex_=True)
+    Y = lib.ham_apply(gop, _dev(X)).cpu().numpy()
+    assert _colrel(Y, op.apply(X)) < 1e-10
+
+
+def test_ham_apply_f32(lib):
+    import torch
+    sysm = SYSTEMS["diamond_nc4"]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    X = wl.start_block(op.n_tot, 40, 0)
+    Y = lib.ham_apply(gop, _dev(X, torch.float32)).cpu().numpy().astype(np.float64)
+    # float32 arithmetic: relative error a few 1e-7 times the operator's spread
+    assert _colrel(Y, op.apply(X.astype(np.float32).astype(np.float64))) < 5e-5
+
+
+@pytest.mark.parametrize("name,nv,m", [("single_atom", 8, 20), ("diamond_nc4", 24, 30)])
+def test_filter_f64(lib, name, nv, m):
+    sysm = SYSTEMS[name]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    X = wl.start_block(op.n_tot, nv, 0)
+    H = None
+    a0, b, _, _ = och.lanczos_bounds(op.apply, wl.lanczos_start(op.n_tot, 2), 10)
+    a = 0.5 * (a0 + b)
+    Xd = _dev(X)
+    lib.chebyshev_filter(gop, Xd, m, a, b, a0)
+    Y = och.chebyshev_filter(op.apply, X, m, a, b, a0)
+    assert _colrel(Xd.cpu().numpy(), Y) < 1e-10
+
+
+def test_filter_on_diagonal_operator_matches_closed_form(lib):
+    rng = np.random.default_rng(0)
+    lam = np.sort(rng.uniform(-3, 50, 777))
+    gop = lib.Operator.diagonal(lam)
+    X = rng.standard_normal((777, 9))
+    m, a0, a, b = 33, lam[0], lam[40], 51.0
+    Xd = _dev(X)
+    lib.chebyshev_filter(gop, Xd, m, a, b, a0)
+    e, c = (b - a) / 2, (b + a) / 2
+    gain = och.chebyshev_T(m, (lam - c) / e) / och.chebyshev_T(m, np.array([(a0 - c) / e]))[0]
+    np.testing.assert_allclose(Xd.cpu().numpy(), gain[:, None] * X, rtol=1e-11, atol=1e-13)
+
+
+def test_lanczos_bounds(lib):
+    sysm = SYSTEMS["single_atom"]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    v0 = wl.lanczos_start(op.n_tot, 2)
+    a0, b, _, _ = och.lanczos_bounds(op.apply, v0, 10)
+    ga0, gb = lib.lanczos_bounds(gop, _dev(v0), 10)
+    assert abs(ga0 - a0) < 1e-9 * abs(b) and abs(gb - b) < 1e-9 * abs(b)
+
+
+def test_cholgs_matches_oracle(lib):
+    sysm = SYSTEMS["diamond_nc4"]()
+    gop = lib.Operator(sysm)
+    rng = np.random.default_rng(5)
+    Y = rng.standard_normal((gop.n_tot, 37)) @ np.diag(np.logspace(0, 4, 37))
+    Q, _ = och.cholgs(Y)
+    Yd = _dev(Y)
+    lib.cholgs(gop, Yd)
+    Qg = Yd.cpu().numpy()
+    np.testing.assert_allclose(Qg, Q, atol=1e-10)
+    np.testing.assert_allclose(Qg.T @ Qg, np.eye(37), atol=1e-12)
+
+
+def test_cholgs_breakdown_is_reported(lib):
+    import torch
+    sysm = SYSTEMS["single_atom"]()
+    gop = lib.Operator(sysm)
+    rng = np.random.default_rng(6)
+    Y = rng.standard_normal((gop.n_tot, 6))
+    Y[:, 4] = Y[:, 1] + Y[:, 2]
+    st = torch.zeros(2, dtype=torch.int32, device="cuda")
+    with pytest.raises(lib.OefeError) as ei:
+        lib.cholgs(gop, _dev(Y), st)
+    assert ei.value.code == -4
+    assert int(st[1]) == 4
+
+
+def _multiplet_angles(th, Xa, Xb, tol=1e-6):
+    """Largest sine of principal angles between Xa and Xb restricted to each gap-separated multiplet."""
+    groups = np.split(np.arange(len(th)), np.nonzero(np.diff(th) > tol * max(1, np.abs(th).max()))[0] + 1)
+    worst = 0.0
+    for g in groups[:-1]:  # the last group may straddle the block edge
+        A, B = Xa[:, g], Xb[:, g]
+        s = np.linalg.norm(B - A @ (A.T @ B), 2)
+        worst = max(worst, s)
+    return worst
+
+
+def test_rayleigh_ritz_matches_oracle(lib):
+    sysm = SYSTEMS["single_atom"]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    H = op.dense()
+    lam, U = np.linalg.eigh(H)
+    rng = np.random.default_rng(7)
+    Q, _ = och.cholgs(U[:, :10] + 1e-3 * rng.standard_normal((op.n_tot, 10)))
+    th, Xr = och.rayleigh_ritz(op.apply, Q)
+    Qd = _dev(Q)
+    thg = lib.rayleigh_ritz(gop, Qd).cpu().numpy()
+    assert np.abs(thg - th).max() < 1e-10 * max(1, np.abs(th).max())
+    assert _multiplet_angles(th, Xr, Qd.cpu().numpy()) < 1e-8
+
+
+def test_chfsi_single_atom_passes(lib):
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    cfg = wl.config("single_atom")
+    op = OEFEOperator(cfg.system)
+    gop = lib.Operator(cfg.system)
+    X0 = wl.start_block(op.n_tot, cfg.nv, 0)
+    v0 = wl.lanczos_start(op.n_tot, 2)
+    r = och.chfsi(op.apply, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k)
+    g = chfsi_run(gop, _dev(X0), _dev(v0), cfg.m, cfg.passes, cfg.lanczos_k)
+    assert abs(g["b"] - r["b"]) < 1e-9 * abs(r["b"])
+    for pg, po in zip(g["passes"], r["passes"]):
+        assert np.abs(pg["theta"] - po["theta"]).max() < 1e-10 * max(1.0, np.abs(po["theta"]).max())
+
+
+@pytest.mark.parametrize("kvec", [None, np.array([0.2, 0.3, -0.1])])
+def test_band_energy_grad(lib, kvec):
+    sysm = SYSTEMS["tiny2"]().with_k(kvec)
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    nv = 5
+    X = wl.start_block(op.n_tot, nv, 1, complex_=kvec is not None)
+    f = wl.occupations(nv, 3)
+    import torch
+    E, dV, dX = lib.band_energy_grad(gop, _dev(X), torch.from_numpy(f))
+    Eo = adj.band_energy(op, X, f)
+    assert abs(float(E) - Eo) < 1e-10 * abs(Eo)
+    gv = adj.grad_V(op, X, f)
+    np.testing.assert_allclose(dV.cpu().numpy(), gv, rtol=1e-10, atol=1e-12 * np.abs(gv).max())
+    assert _colrel(dX.cpu().numpy(), adj.grad_X(op, X, f)) < 1e-10
+
+
+def test_band_energy_grad_p4(lib):
+    import torch
+    sysm = SYSTEMS["diamond_nc4"]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    nv = 70
+    X = wl.start_block(op.n_tot, nv, 1)
+    f = wl.occupations(nv, 3)
+    E, dV, dX = lib.band_energy_grad(gop, _dev(X), torch.from_numpy(f))
+    gv = adj.grad_V(op, X, f)
+    np.testing.assert_allclose(dV.cpu().numpy(), gv, rtol=1e-10, atol=1e-12 * np.abs(gv).max())
+    assert abs(float(E) - adj.band_energy(op, X, f)) < 1e-10 * abs(float(E))
+
+
+def test_set_potential(lib):
+    sysm = SYSTEMS["tiny2"]()
+    gop = lib.Operator(sysm)
+    V0, W = gop.get_potential()
+    op0 = OEFEOperator(sysm)
+    np.testing.assert_allclose(V0, op0.V, rtol=1e-13, atol=1e-13)
+    dV = wl.potential_perturbation(op0.mesh.n_cells, op0.mesh.nq, 101)
+    gop.set_potential(V0 + 0.3 * dV)
+    op = OEFEOperator(sysm, V=op0.V + 0.3 * dV)
+    X = wl.start_block(op.n_tot, 7, 2)
+    Y = lib.ham_apply(gop, _dev(X)).cpu().numpy()
+    assert _colrel(Y, op.apply(X)) < 1e-10
+
+
+def test_enrichment_overlap_and_S(lib):
+    sysm = SYSTEMS["diamond_nc4"]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    S, ev = gop.get_enrichment()
+    np.testing.assert_allclose(ev, op.enr.Moo_eigs, rtol=1e-9)
+    np.testing.assert_allclose(S, op.enr.S, atol=1e-9 * np.abs(op.enr.S).max())
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "diamond8_oracle.npz")), reason="golden file missing")
+def test_diamond8_full_size(lib):
+    """Workload diamond8 (12^3 cells, p = 4, 72 vectors): sampled rows of Ht X0, the bounds, and
+    pass-1 filter rows against stored oracle values."""
+    cfg = wl.config("diamond8")
+    g = np.load(os.path.join(GOLD, "diamond8_oracle.npz"))
+    gop = lib.Operator(cfg.system)
+    X0 = wl.start_block(gop.n_tot, cfg.nv, 0)
+    Y = lib.ham_apply(gop, _dev(X0)).cpu().numpy()
+    rows = g["rows"]
+    scale = g["hx_colnorm"][None, :] / np.sqrt(gop.n_tot)
+    assert np.abs(Y[rows] - g["hx_rows"]).max() / np.abs(g["hx_rows"]).max() < 1e-10
+    a0, b = lib.lanczos_bounds(gop, _dev(wl.lanczos_start(gop.n_tot, 2)), 10)
+    assert abs(a0 - float(g["a0L"])) < 1e-9 * abs(b) and abs(b - float(g["b"])) < 1e-9 * abs(b)
+    Xd = _dev(X0)
+    a0o, bo = float(g["a0L"]), float(g["b"])
+    lib.chebyshev_filter(gop, Xd, cfg.m, 0.5 * (a0o + bo), bo, a0o)
+    Yf = Xd.cpu().numpy()
+    assert np.abs(Yf[rows] - g["filt1_rows"]).max() / np.abs(g["filt1_rows"]).max() < 1e-9
+    np.testing.assert_allclose(np.linalg.norm(Yf, axis=0), g["filt1_colnorm"], rtol=1e-9)
+    del scale
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "diamond8_oracle.npz")), reason="golden file missing")
+def test_diamond8_chfsi_ritz_values(lib):
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    cfg = wl.config("diamond8")
+    g = np.load(os.path.join(GOLD, "diamond8_oracle.npz"))
+    gop = lib.Operator(cfg.system)
+    X0 = wl.start_block(gop.n_tot, cfg.nv, 0)
+    v0 = wl.lanczos_start(gop.n_tot, 2)
+    r = chfsi_run(gop, _dev(X0), _dev(v0), cfg.m, cfg.passes, cfg.lanczos_k)
+    th = np.stack([p["theta"] for p in r["passes"]])
+    assert np.abs(th - g["thetas"]).max() < 1e-10 * np.abs(g["thetas"]).max()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "diamond64_oracle.npz")), reason="golden file missing")
+def test_diamond64_full_size_rows(lib):
+    """Workload diamond64 (24^3 cells, 320 enrichment functions, 320 vectors): sampled rows of Ht X0."""
+    cfg = wl.config("diamond64")
+    g = np.load(os.path.join(GOLD, "diamond64_oracle.npz"))
+    gop = lib.Operator(cfg.system)
+    X0 = wl.start_block(gop.n_tot, cfg.nv, 0)
+    Y = lib.ham_apply(gop, _dev(X0)).cpu().numpy()
+    rows = g["rows"]
+    assert np.abs(Y[rows] - g["hx_rows"]).max() / np.abs(g["hx_rows"]).max() < 1e-10
