@@ -165,30 +165,52 @@ int upload_potential_parts(oefe_op_s* op, std::string& err) {
   if ((rc = dset(op->d.WV, wv, err))) return rc;
   if ((rc = dset(op->d.WVf, to_float(wv), err))) return rc;
   if (op->n_enr == 0) return OEFE_OK;
-  // H^co block values
+  // H^co values, scaled by m_g^-1/2 of their FE row: block-row layout and per-row CSR
   const int E = cplx ? 2 : 1;
   std::vector<double> hv((size_t)op->n_hrows * op->FMAX * E, 0.0);
+  std::vector<double> frv((size_t)op->fr_nnz * E, 0.0);
   int64_t base = 0;
-  for (auto& b : op->blocks) {
+  for (size_t bi = 0; bi < op->blocks.size(); ++bi) {
+    auto& b = op->blocks[bi];
     std::vector<std::complex<double>> vals;
     block_hco_values(op, b, vals);
-    for (size_t r = 0; r < b.rows.size(); ++r)
+    for (size_t r = 0; r < b.rows.size(); ++r) {
+      const double ms = 1.0 / std::sqrt(op->mdiag[b.rows[r]]);
       for (int f = 0; f < b.nf; ++f) {
-        const std::complex<double> v = vals[r * b.nf + f];
+        const std::complex<double> v = ms * vals[r * b.nf + f];
         const size_t o = ((size_t)(base + r) * op->FMAX + f) * E;
         hv[o] = v.real();
         if (cplx) hv[o + 1] = v.imag();
+        const size_t k = (size_t)(op->fr_pos[bi][r] + f) * E;
+        frv[k] = v.real();
+        if (cplx) frv[k + 1] = v.imag();
       }
+    }
     base += (int64_t)b.rows.size();
   }
   if (!op->d.hv) {
     if ((rc = dalloc(&op->d.hv, hv.size(), err))) return rc;
     if ((rc = dalloc(&op->d.hvf, hv.size(), err))) return rc;
+    if ((rc = dalloc(&op->d.fr_val, frv.size(), err))) return rc;
+    if ((rc = dalloc(&op->d.fr_valf, frv.size(), err))) return rc;
     if ((rc = dalloc(&op->d.Hoo, (size_t)op->n_enr * op->n_enr * E, err))) return rc;
     if ((rc = dalloc(&op->d.Hoof, (size_t)op->n_enr * op->n_enr * E, err))) return rc;
   }
   if ((rc = dset(op->d.hv, hv, err))) return rc;
   if ((rc = dset(op->d.hvf, to_float(hv), err))) return rc;
+  if ((rc = dset(op->d.fr_val, frv, err))) return rc;
+  if ((rc = dset(op->d.fr_valf, to_float(frv), err))) return rc;
+  {
+    std::vector<double> tv((size_t)op->tile_slots * kTileRows * E, 0.0);
+    for (int64_t k = 0; k < op->fr_nnz; ++k)
+      for (int e = 0; e < E; ++e) tv[(size_t)op->csr_to_tile[k] * E + e] = frv[(size_t)k * E + e];
+    if (!op->d.tile_val) {
+      if ((rc = dalloc(&op->d.tile_val, tv.size(), err))) return rc;
+      if ((rc = dalloc(&op->d.tile_valf, tv.size(), err))) return rc;
+    }
+    if ((rc = dset(op->d.tile_val, tv, err))) return rc;
+    if ((rc = dset(op->d.tile_valf, to_float(tv), err))) return rc;
+  }
   std::vector<double> hoo = flatten(op->Hoo, cplx);
   if ((rc = dset(op->d.Hoo, hoo, err))) return rc;
   if ((rc = dset(op->d.Hoof, to_float(hoo), err))) return rc;
@@ -223,21 +245,67 @@ int upload_operator(oefe_op_s* op, std::string& err) {
     blk_chunk0[nb] = (int32_t)chunk_blk.size();
     op->n_hrows = rptr[nb];
     op->n_chunks = (int64_t)chunk_blk.size();
-    // row lists
-    std::vector<int64_t> row_ptr(op->N + 1, 0);
+    // forward CSR by FE row: entries ordered by block, then function
+    std::vector<int64_t> fr_ptr(op->N + 1, 0);
     for (int b = 0; b < nb; ++b)
-      for (int32_t g : op->blocks[b].rows) row_ptr[g + 1]++;
-    for (int64_t g = 0; g < op->N; ++g) row_ptr[g + 1] += row_ptr[g];
-    std::vector<int32_t> row_blk(row_ptr[op->N]);
-    std::vector<int64_t> row_pos(row_ptr[op->N]);
-    std::vector<int64_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+      for (int32_t g : op->blocks[b].rows) fr_ptr[g + 1] += op->blocks[b].nf;
+    for (int64_t g = 0; g < op->N; ++g) fr_ptr[g + 1] += fr_ptr[g];
+    op->fr_nnz = fr_ptr[op->N];
+    std::vector<int32_t> fr_fn(op->fr_nnz);
+    std::vector<int64_t> fill(fr_ptr.begin(), fr_ptr.end() - 1);
+    op->fr_pos.assign(nb, {});
     for (int b = 0; b < nb; ++b) {
       auto& B = op->blocks[b];
+      op->fr_pos[b].resize(B.rows.size());
       for (size_t r = 0; r < B.rows.size(); ++r) {
-        const int64_t k = fill[B.rows[r]]++;
-        row_blk[k] = b;
-        row_pos[k] = rptr[b] + (int64_t)r;
+        const int64_t k = fill[B.rows[r]];
+        fill[B.rows[r]] += B.nf;
+        op->fr_pos[b][r] = k;
+        for (int f = 0; f < B.nf; ++f) fr_fn[k + f] = B.fn0 + f;
       }
+    }
+    // enrichment tiles: union of functions over kTileRows consecutive rows
+    {
+      op->n_tiles = (op->N + kTileRows - 1) / kTileRows;
+      std::vector<int32_t> tfptr(op->n_tiles + 1, 0), tfns;
+      std::vector<int32_t> slot(op->n_enr, -1);
+      op->csr_to_tile.assign(op->fr_nnz, 0);
+      int fpmax = 0;
+      for (int64_t t = 0; t < op->n_tiles; ++t) {
+        const int64_t g0 = t * kTileRows, g1 = std::min<int64_t>(op->N, g0 + kTileRows);
+        std::vector<int32_t> fl;
+        for (int64_t g = g0; g < g1; ++g)
+          for (int64_t k = fr_ptr[g]; k < fr_ptr[g + 1]; ++k)
+            if (slot[fr_fn[k]] < 0) {
+              slot[fr_fn[k]] = 0;
+              fl.push_back(fr_fn[k]);
+            }
+        std::sort(fl.begin(), fl.end());
+        const int F = (int)fl.size(), FP = (F + 3) / 4 * 4;
+        for (int j = 0; j < F; ++j) slot[fl[j]] = j;
+        for (int64_t g = g0; g < g1; ++g)
+          for (int64_t k = fr_ptr[g]; k < fr_ptr[g + 1]; ++k)
+            op->csr_to_tile[k] = (int64_t)tfptr[t] * kTileRows + (g - g0) * FP + slot[fr_fn[k]];
+        for (int j = 0; j < FP; ++j) tfns.push_back(j < F ? fl[j] : -1);
+        for (int32_t f : fl) slot[f] = -1;
+        tfptr[t + 1] = tfptr[t] + FP;
+        fpmax = std::max(fpmax, FP);
+      }
+      op->tile_slots = tfptr[op->n_tiles];
+      op->tile_fpmax = fpmax;
+      // per function: its (tile, slot) partial positions, in tile order
+      std::vector<int32_t> fpp(op->n_enr + 1, 0);
+      for (int32_t f : tfns)
+        if (f >= 0) fpp[f + 1]++;
+      for (int f = 0; f < op->n_enr; ++f) fpp[f + 1] += fpp[f];
+      std::vector<int32_t> fpo(fpp[op->n_enr]);
+      std::vector<int32_t> ff(fpp.begin(), fpp.end() - 1);
+      for (size_t q = 0; q < tfns.size(); ++q)
+        if (tfns[q] >= 0) fpo[ff[tfns[q]]++] = (int32_t)q;
+      if ((rc = dput(&op->d.tile_fptr, tfptr, err))) return rc;
+      if ((rc = dput(&op->d.tile_fns, tfns, err))) return rc;
+      if ((rc = dput(&op->d.fn_pptr, fpp, err))) return rc;
+      if ((rc = dput(&op->d.fn_poff, fpo, err))) return rc;
     }
     // N^O at quadrature points by cell
     std::vector<int64_t> cph_ptr(op->n_cells + 1, 0);
@@ -276,9 +344,8 @@ int upload_operator(oefe_op_s* op, std::string& err) {
     if ((rc = dput(&op->d.chunk_blk, chunk_blk, err))) return rc;
     if ((rc = dput(&op->d.chunk_r0, chunk_r0, err))) return rc;
     if ((rc = dput(&op->d.chunk_r1, chunk_r1, err))) return rc;
-    if ((rc = dput(&op->d.row_ptr, row_ptr, err))) return rc;
-    if ((rc = dput(&op->d.row_blk, row_blk, err))) return rc;
-    if ((rc = dput(&op->d.row_pos, row_pos, err))) return rc;
+    if ((rc = dput(&op->d.fr_ptr, fr_ptr, err))) return rc;
+    if ((rc = dput(&op->d.fr_fn, fr_fn, err))) return rc;
     if ((rc = dput(&op->d.cph_ptr, cph_ptr, err))) return rc;
     if ((rc = dput(&op->d.cph_blk, cph_blk, err))) return rc;
     if ((rc = dput(&op->d.cph_off, cph_off, err))) return rc;
@@ -289,8 +356,8 @@ int upload_operator(oefe_op_s* op, std::string& err) {
     if ((rc = dput(&op->d.Sf, Sf, err))) return rc;
   } else {
     // empty row lists so the node kernel can run without enrichment
-    std::vector<int64_t> row_ptr(op->N + 1, 0);
-    if ((rc = dput(&op->d.row_ptr, row_ptr, err))) return rc;
+    std::vector<int64_t> fr_ptr(op->N + 1, 0);
+    if ((rc = dput(&op->d.fr_ptr, fr_ptr, err))) return rc;
   }
   return upload_potential_parts(op, err);
 }
@@ -298,7 +365,8 @@ int upload_operator(oefe_op_s* op, std::string& err) {
 void free_device(oefe_op_s* op) {
   auto& d = op->d;
   dfree(d.WV); dfree(d.WVf); dfree(d.blk_fn0); dfree(d.blk_nf); dfree(d.blk_rptr); dfree(d.blk_rows);
-  dfree(d.hv); dfree(d.hvf); dfree(d.row_ptr); dfree(d.row_blk); dfree(d.row_pos); dfree(d.chunk_blk);
+  dfree(d.tile_fptr); dfree(d.tile_fns); dfree(d.tile_val); dfree(d.tile_valf); dfree(d.fn_pptr);
+  dfree(d.fn_poff); dfree(d.hv); dfree(d.hvf); dfree(d.fr_ptr); dfree(d.fr_fn); dfree(d.fr_val); dfree(d.fr_valf); dfree(d.chunk_blk);
   dfree(d.chunk_r0); dfree(d.chunk_r1); dfree(d.blk_chunk0); dfree(d.fn_blk); dfree(d.S); dfree(d.Hoo);
   dfree(d.Sf); dfree(d.Hoof); dfree(d.cph_ptr); dfree(d.cph_blk); dfree(d.cph_off); dfree(d.phi);
   dfree(d.lambda); dfree(d.lambdaf);

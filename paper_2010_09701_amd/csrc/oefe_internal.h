@@ -14,6 +14,7 @@
 namespace oefe {
 
 constexpr int kMaxP1 = 5;  // supported GLL nodes per edge: 3, 4, 5 (degree 2..4)
+constexpr int kTileRows = 64;  // FE rows per enrichment tile
 
 using cplx = std::complex<double>;
 
@@ -49,10 +50,23 @@ struct DeviceArrays {
   int32_t* blk_rows = nullptr;
   double* hv = nullptr;
   float* hvf = nullptr;
-  // per FE row: list of (block, position p into the concatenated block rows)
-  int64_t* row_ptr = nullptr;
-  int32_t* row_blk = nullptr;
-  int64_t* row_pos = nullptr;
+  // forward product by FE row (CSR): row g has entries fr_ptr[g]..fr_ptr[g+1]) of
+  // (function fr_fn[k], value fr_val[k] = m_g^-1/2 H^co[g, fn]); hv above is scaled the same way
+  int64_t* fr_ptr = nullptr;
+  int32_t* fr_fn = nullptr;
+  double* fr_val = nullptr;
+  float* fr_valf = nullptr;
+  // tile-dense enrichment coupling: FE rows in tiles of kTileRows; tile t couples to the
+  // functions tile_fns[tile_fptr[t] .. tile_fptr[t+1]) (padded to a multiple of 4 with -1)
+  // with dense values tile_val[(tile_fptr[t] * kTileRows + r * FP_t + j)] (complex: x2),
+  // pre-scaled by m_g^-1/2.  Transposed partials are reduced per function over the list
+  // fn_poff[fn_pptr[nu] .. fn_pptr[nu+1]) of (tile_fptr[t] + j) slots.
+  int32_t* tile_fptr = nullptr;
+  int32_t* tile_fns = nullptr;
+  double* tile_val = nullptr;
+  float* tile_valf = nullptr;
+  int32_t* fn_pptr = nullptr;
+  int32_t* fn_poff = nullptr;
   // transposed-product chunks: chunk c covers block chunk_blk[c], rows [chunk_r0[c], chunk_r1[c])
   int32_t* chunk_blk = nullptr;
   int64_t* chunk_r0 = nullptr;
@@ -113,6 +127,11 @@ struct oefe_op_s {
   int64_t n_hrows = 0;  // total rows over blocks
   int64_t n_chunks = 0;
   int chunk_rows = 256;
+  int64_t fr_nnz = 0;
+  std::vector<std::vector<int64_t>> fr_pos;  // per block, per row: CSR position of its first function
+  std::vector<int64_t> csr_to_tile;           // CSR entry -> index into tile_val
+  int64_t n_tiles = 0, tile_slots = 0;        // tiles, total padded (tile, function) slots
+  int tile_fpmax = 0;
   oefe::DeviceArrays d;
   // instrumentation (oefe_kernel_timer)
   bool timer_on = false;

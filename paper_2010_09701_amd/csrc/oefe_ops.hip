@@ -250,25 +250,32 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Node kernel: FE rows.  Thread per (FE node g, vector v).
+// Node kernel: FE rows.  Workgroup = RB nodes x NVB vector lanes (2D), thread
+// per (FE node g, vector v): fixed-order sum of the (up to 8) cell results that
+// share g, times m_g^-1/2, plus the enrichment term sum_nu (m^-1/2 H^co)[g,nu]
+// Z^O[nu][v] (pre-scaled per-row CSR), then the recurrence epilogue.
+// Z^O is staged in LDS when it fits.
 // ---------------------------------------------------------------------------
 template <typename T, bool CPLX>
-__global__ __launch_bounds__(256) void fe_node_kernel(const T* __restrict__ Yc, int ldc, const T* __restrict__ X,
-                                                      const T* __restrict__ prev, T* __restrict__ out, int64_t ldx,
-                                                      int64_t ldo,
-                                                      int nv, int nc, int p, int n, int P1, CellCoef<T> cf,
-                                                      Phase3<T> ph, const T* __restrict__ zo, int ncr,
-                                                      const int64_t* __restrict__ row_ptr,
-                                                      const int32_t* __restrict__ row_blk,
-                                                      const int64_t* __restrict__ row_pos,
-                                                      const int32_t* __restrict__ blk_fn0,
-                                                      const int32_t* __restrict__ blk_nf, const T* __restrict__ hv,
-                                                      int FMAX, T alpha, T c, T beta, int64_t N) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= N * nv) return;
-  const int64_t g = idx / nv;
-  const int vv = (int)(idx % nv);
-  const int ix = (int)(g % n), iy = (int)((g / n) % n), iz = (int)(g / ((int64_t)n * n));
+__global__ __launch_bounds__(256) void fe_node_kernel(
+    const T* __restrict__ Yc, int ldc, const T* __restrict__ X, const T* __restrict__ prev, T* __restrict__ out,
+    int64_t ldx, int64_t ldo, int nv, int nvb, int nc, int p, int n, int P1, CellCoef<T> cf, Phase3<T> ph,
+    const T* __restrict__ zo, int ncr, int nO, int zo_in_lds, const int64_t* __restrict__ fr_ptr,
+    const int32_t* __restrict__ fr_fn, const T* __restrict__ fr_val, T alpha, T c, T beta, int N) {
+  extern __shared__ unsigned char smem_raw[];
+  T* zs = reinterpret_cast<T*>(smem_raw);
+  const int tx = threadIdx.x % nvb, ty = threadIdx.x / nvb;
+  const int RB = blockDim.x / nvb;
+  if (zo_in_lds) {
+    const int tot = nO * ncr;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) zs[t] = zo[t];
+    __syncthreads();
+  }
+  const T* zsrc = zo_in_lds ? zs : zo;
+  const int g = blockIdx.x * RB + ty;
+  const int vv = blockIdx.y * nvb + tx;
+  if (ty >= RB || g >= N || vv >= nv) return;
+  const int ix = g % n, iy = (g / n) % n, iz = g / (n * n);
   const int nd = P1 * P1 * P1;
   int cxs[2], axs[2], wxs[2], nxs = 1;
   int cys[2], ays[2], wys[2], nys = 1;
@@ -280,33 +287,32 @@ __global__ __launch_bounds__(256) void fe_node_kernel(const T* __restrict__ Yc, 
   czs[0] = iz / p; azs[0] = iz % p; wzs[0] = 0;
   if (azs[0] == 0) { czs[1] = (czs[0] + nc - 1) % nc; azs[1] = p; wzs[1] = (czs[1] == nc - 1); nzs = 2; }
   const T msc = cf.mscale * cf.om[ix % p] * cf.om[iy % p] * cf.om[iz % p];
+  const int64_t k0 = fr_ptr[g], k1 = fr_ptr[g + 1];
   if constexpr (!CPLX) {
     T acc = 0;
     for (int kz = 0; kz < nzs; ++kz)
       for (int ky = 0; ky < nys; ++ky)
         for (int kx = 0; kx < nxs; ++kx) {
-          int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
-          int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
+          const int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
+          const int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
           acc += Yc[(e * nd + a) * (int64_t)ldc + vv];
         }
-    for (int64_t k = row_ptr[g]; k < row_ptr[g + 1]; ++k) {
-      const int b = row_blk[k];
-      const int64_t pos = row_pos[k];
-      const int f0 = blk_fn0[b], nf = blk_nf[b];
-      for (int f = 0; f < nf; ++f) acc += hv[pos * FMAX + f] * zo[(int64_t)(f0 + f) * ncr + vv];
-    }
-    const T hx = msc * acc;
-    const T xv = X[g * ldx + vv];
+    T en = 0;
+#pragma unroll 8
+    for (int64_t k = k0; k < k1; ++k) en += fr_val[k] * zsrc[fr_fn[k] * ncr + vv];
+    const T hx = msc * acc + en;
+    const int64_t gi = (int64_t)g;
+    const T xv = X[gi * ldx + vv];
     T r = alpha * (hx - c * xv);
-    if (beta != T(0)) r -= beta * prev[g * ldo + vv];
-    out[g * ldo + vv] = r;
+    if (beta != T(0)) r -= beta * prev[gi * ldo + vv];
+    out[gi * ldo + vv] = r;
   } else {
     C2<T> acc{0, 0};
     for (int kz = 0; kz < nzs; ++kz)
       for (int ky = 0; ky < nys; ++ky)
         for (int kx = 0; kx < nxs; ++kx) {
-          int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
-          int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
+          const int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
+          const int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
           const T* py = Yc + (e * nd + a) * (int64_t)ldc + 2 * vv;
           C2<T> z{py[0], py[1]};
           // scatter phase conj(theta)
@@ -316,180 +322,374 @@ __global__ __launch_bounds__(256) void fe_node_kernel(const T* __restrict__ Yc, 
           acc.r += z.r;
           acc.i += z.i;
         }
-    for (int64_t k = row_ptr[g]; k < row_ptr[g + 1]; ++k) {
-      const int b = row_blk[k];
-      const int64_t pos = row_pos[k];
-      const int f0 = blk_fn0[b], nf = blk_nf[b];
-      for (int f = 0; f < nf; ++f) {
-        C2<T> h{hv[2 * (pos * FMAX + f)], hv[2 * (pos * FMAX + f) + 1]};
-        const T* pz = zo + (int64_t)(f0 + f) * ncr + 2 * vv;
-        C2<T> zz = cmul(h, C2<T>{pz[0], pz[1]});
-        acc.r += zz.r;
-        acc.i += zz.i;
-      }
+    C2<T> en{0, 0};
+#pragma unroll 4
+    for (int64_t k = k0; k < k1; ++k) {
+      const T* pz = zsrc + fr_fn[k] * ncr + 2 * vv;
+      const C2<T> zz = cmul(C2<T>{fr_val[2 * k], fr_val[2 * k + 1]}, C2<T>{pz[0], pz[1]});
+      en.r += zz.r;
+      en.i += zz.i;
     }
-    const T* px = X + g * ldx + 2 * vv;
-    T rr = alpha * (msc * acc.r - c * px[0]);
-    T ri = alpha * (msc * acc.i - c * px[1]);
+    const int64_t gi = (int64_t)g;
+    const T* px = X + gi * ldx + 2 * vv;
+    T rr = alpha * (msc * acc.r + en.r - c * px[0]);
+    T ri = alpha * (msc * acc.i + en.i - c * px[1]);
     if (beta != T(0)) {
-      const T* pp = prev + g * ldo + 2 * vv;
+      const T* pp = prev + gi * ldo + 2 * vv;
       rr -= beta * pp[0];
       ri -= beta * pp[1];
     }
-    T* po = out + g * ldo + 2 * vv;
+    T* po = out + gi * ldo + 2 * vv;
     po[0] = rr;
     po[1] = ri;
   }
 }
 
-// Z^O = S X^O ; thread per (nu, real column).  X^O rows start at row N of x.
+// ---------------------------------------------------------------------------
+// Tiled node kernel: FE rows.  Workgroup = one tile of kTileRows consecutive FE
+// rows x CB real columns, 4 row groups.  For each output (row g, column j):
+//   fixed-order sum of the (up to 8) cell results sharing g, times m_g^-1/2,
+//   + sum_f Ht[g][f] Z^O[fn_f][j]  (dense tile block of m^-1/2 H^co, LDS-staged
+//     16 functions at a time together with the matching Z^O rows),
+//   then the recurrence epilogue alpha (y - c x) - beta prev.
+// ---------------------------------------------------------------------------
 template <typename T, bool CPLX>
-__global__ void enr_zo_kernel(const T* __restrict__ S, const T* __restrict__ x, int64_t ldx, int64_t N, int nO,
-                              int nv, T* __restrict__ zo, int ncr) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nO * nv) return;
-  const int nu = idx / nv, vv = idx % nv;
-  if constexpr (!CPLX) {
-    T s = 0;
-    for (int mu = 0; mu < nO; ++mu) s += S[(int64_t)nu * nO + mu] * x[(N + mu) * ldx + vv];
-    zo[(int64_t)nu * ncr + vv] = s;
-  } else {
-    C2<T> s{0, 0};
-    for (int mu = 0; mu < nO; ++mu) {
-      C2<T> a{S[2 * ((int64_t)nu * nO + mu)], S[2 * ((int64_t)nu * nO + mu) + 1]};
-      const T* px = x + (N + mu) * ldx + 2 * vv;
-      C2<T> z = cmul(a, C2<T>{px[0], px[1]});
-      s.r += z.r;
-      s.i += z.i;
+__global__ __launch_bounds__(512) void fe_node_tile_kernel(
+    const T* __restrict__ Yc, int ldc, const T* __restrict__ X, const T* __restrict__ prev, T* __restrict__ out,
+    int64_t ldx, int64_t ldo, int ncr, int CB, int nc, int p, int n, int P1, CellCoef<T> cf, Phase3<T> ph,
+    const T* __restrict__ zo, const int32_t* __restrict__ tile_fptr, const int32_t* __restrict__ tile_fns,
+    const T* __restrict__ tile_val, T alpha, T c, T beta, int N) {
+  constexpr int TR = kTileRows, RG = 4, RPT = TR / RG, JC = 16;
+  constexpr int E = CPLX ? 2 : 1;
+  extern __shared__ unsigned char smem_raw[];
+  T* Hs = reinterpret_cast<T*>(smem_raw);  // [TR][JC][E]
+  T* zs = Hs + TR * JC * E;                // [JC][CB]
+  const int cl = threadIdx.x % CB, rg = threadIdx.x / CB;
+  const int t = blockIdx.x;
+  const int j = blockIdx.y * CB + cl;  // real column
+  // no enrichment: tile_fptr is null and the tile couples to no function
+  const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
+  const T* tv = tile_val + (int64_t)f0 * TR * E;
+  T en[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) en[i] = 0;
+  for (int j0 = 0; j0 < FP; j0 += JC) {
+    const int jn = min(JC, FP - j0);
+    for (int q = threadIdx.x; q < TR * JC * E; q += blockDim.x) {
+      const int r = q / (JC * E), jj = (q / E) % JC, e = q % E;
+      Hs[q] = jj < jn ? tv[((int64_t)r * FP + j0 + jj) * E + e] : T(0);
     }
-    zo[(int64_t)nu * ncr + 2 * vv] = s.r;
-    zo[(int64_t)nu * ncr + 2 * vv + 1] = s.i;
+    for (int q = threadIdx.x; q < JC * CB; q += blockDim.x) {
+      const int jj = q / CB, cc = q % CB;
+      const int fn = jj < jn ? tile_fns[f0 + j0 + jj] : -1;
+      const int col = blockIdx.y * CB + cc;
+      zs[q] = (fn >= 0 && col < ncr) ? zo[(int64_t)fn * ncr + col] : T(0);
+    }
+    __syncthreads();
+    for (int jj = 0; jj < jn; ++jj) {
+      if constexpr (!CPLX) {
+        const T z = zs[jj * CB + cl];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) en[i] += Hs[(rg + RG * i) * JC + jj] * z;
+      } else {
+        const T zr = zs[jj * CB + (cl & ~1)], zi = zs[jj * CB + (cl | 1)];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const T hr = Hs[((rg + RG * i) * JC + jj) * 2], hi = Hs[((rg + RG * i) * JC + jj) * 2 + 1];
+          en[i] += (cl & 1) ? (hr * zi + hi * zr) : (hr * zr - hi * zi);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (j >= ncr) return;
+  const int nd = P1 * P1 * P1;
+#pragma unroll 1
+  for (int i = 0; i < RPT; ++i) {
+    const int g = t * TR + rg + RG * i;
+    if (g >= N) break;
+    const int ix = g % n, iy = (g / n) % n, iz = g / (n * n);
+    int cxs[2], axs[2], wxs[2], nxs = 1;
+    int cys[2], ays[2], wys[2], nys = 1;
+    int czs[2], azs[2], wzs[2], nzs = 1;
+    cxs[0] = ix / p; axs[0] = ix % p; wxs[0] = 0;
+    if (axs[0] == 0) { cxs[1] = (cxs[0] + nc - 1) % nc; axs[1] = p; wxs[1] = (cxs[1] == nc - 1); nxs = 2; }
+    cys[0] = iy / p; ays[0] = iy % p; wys[0] = 0;
+    if (ays[0] == 0) { cys[1] = (cys[0] + nc - 1) % nc; ays[1] = p; wys[1] = (cys[1] == nc - 1); nys = 2; }
+    czs[0] = iz / p; azs[0] = iz % p; wzs[0] = 0;
+    if (azs[0] == 0) { czs[1] = (czs[0] + nc - 1) % nc; azs[1] = p; wzs[1] = (czs[1] == nc - 1); nzs = 2; }
+    const T msc = cf.mscale * cf.om[ix % p] * cf.om[iy % p] * cf.om[iz % p];
+    T acc = 0;
+    for (int kz = 0; kz < nzs; ++kz)
+      for (int ky = 0; ky < nys; ++ky)
+        for (int kx = 0; kx < nxs; ++kx) {
+          const int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
+          const int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
+          if constexpr (!CPLX) {
+            acc += Yc[(e * nd + a) * (int64_t)ldc + j];
+          } else {
+            const T* py = Yc + (e * nd + a) * (int64_t)ldc + (j & ~1);
+            C2<T> z{py[0], py[1]};
+            if (wxs[kx]) z = cjmul(C2<T>{ph.re[0], ph.im[0]}, z);
+            if (wys[ky]) z = cjmul(C2<T>{ph.re[1], ph.im[1]}, z);
+            if (wzs[kz]) z = cjmul(C2<T>{ph.re[2], ph.im[2]}, z);
+            acc += (j & 1) ? z.i : z.r;
+          }
+        }
+    const int64_t gi = (int64_t)g;
+    T r = alpha * (msc * acc + en[i] - c * X[gi * ldx + j]);
+    if (beta != T(0)) r -= beta * prev[gi * ldo + j];
+    out[gi * ldo + j] = r;
   }
 }
 
-// Partial transposed product per row chunk of an atom block:
-// part[c][f][v] = sum_{r in chunk} conj(hv[r][f]) m_r^-1/2 x[row_r][v]
+// Transposed enrichment product per tile:
+//   part[(tile_fptr[t] + s)][j] = sum_{r in tile} conj(Ht[r][s]) x[r][j]
+// Workgroup = one tile x CB real columns, 4 slot groups; rows staged 16 at a time.
 template <typename T, bool CPLX>
-__global__ __launch_bounds__(64) void enr_partial_kernel(
-    const T* __restrict__ x, int64_t ldx, int nv, const int32_t* __restrict__ chunk_blk,
+__global__ __launch_bounds__(512) void enr_tile_partial_kernel(
+    const T* __restrict__ x, int64_t ldx, int ncr, int CB, const int32_t* __restrict__ tile_fptr,
+    const T* __restrict__ tile_val, T* __restrict__ part, int N) {
+  constexpr int TR = kTileRows, SG = 4, RC = 16, SMAX = 16;
+  constexpr int E = CPLX ? 2 : 1;
+  extern __shared__ unsigned char smem_raw[];
+  T* xs = reinterpret_cast<T*>(smem_raw);  // [RC][CB]
+  T* Hs = xs + RC * CB;                     // [RC][FP][E]
+  const int cl = threadIdx.x % CB, sg = threadIdx.x / CB;
+  const int t = blockIdx.x;
+  const int j = blockIdx.y * CB + cl;
+  const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;
+  const T* tv = tile_val + (int64_t)f0 * TR * E;
+  for (int s0 = 0; s0 < FP; s0 += SG * SMAX) {  // slots in groups of 64
+    T acc[SMAX];
+#pragma unroll
+    for (int i = 0; i < SMAX; ++i) acc[i] = 0;
+    for (int r0 = 0; r0 < TR; r0 += RC) {
+      for (int q = threadIdx.x; q < RC * CB; q += blockDim.x) {
+        const int rr = q / CB, cc = q % CB;
+        const int g = t * TR + r0 + rr;
+        const int col = blockIdx.y * CB + cc;
+        xs[q] = (g < N && col < ncr) ? x[(int64_t)g * ldx + col] : T(0);
+      }
+      for (int q = threadIdx.x; q < RC * FP * E; q += blockDim.x) Hs[q] = tv[(int64_t)r0 * FP * E + q];
+      __syncthreads();
+      for (int rr = 0; rr < RC; ++rr) {
+        if constexpr (!CPLX) {
+          const T xv = xs[rr * CB + cl];
+#pragma unroll
+          for (int i = 0; i < SMAX; ++i) {
+            const int sl = s0 + sg + SG * i;
+            if (sl < FP) acc[i] += Hs[rr * FP + sl] * xv;
+          }
+        } else {
+          const T xr = xs[rr * CB + (cl & ~1)], xi = xs[rr * CB + (cl | 1)];
+#pragma unroll
+          for (int i = 0; i < SMAX; ++i) {
+            const int sl = s0 + sg + SG * i;
+            if (sl < FP) {
+              const T hr = Hs[(rr * FP + sl) * 2], hi = Hs[(rr * FP + sl) * 2 + 1];
+              acc[i] += (cl & 1) ? (hr * xi - hi * xr) : (hr * xr + hi * xi);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (j < ncr) {
+#pragma unroll
+      for (int i = 0; i < SMAX; ++i) {
+        const int sl = s0 + sg + SG * i;
+        if (sl < FP) part[(int64_t)(f0 + sl) * ncr + j] = acc[i];
+      }
+    }
+  }
+}
+
+// W'[nu][j] = sum over the tiles coupling to nu of their partial slot, in tile order.
+// Workgroup per (nu, 64 real columns): 16 groups sum strided subsets, fixed LDS tree.
+template <typename T>
+__global__ __launch_bounds__(1024) void enr_tile_reduce_kernel(const T* __restrict__ part,
+                                                               const int32_t* __restrict__ fn_pptr,
+                                                               const int32_t* __restrict__ fn_poff, int ncr,
+                                                               T* __restrict__ wp) {
+  __shared__ T red[16][64];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int nu = blockIdx.x;
+  const int j = blockIdx.y * 64 + lane;
+  const int e0 = fn_pptr[nu], e1 = fn_pptr[nu + 1];
+  T s0 = 0, s1 = 0;
+  if (j < ncr) {
+    int e = e0 + grp;
+    for (; e + 16 < e1; e += 32) {
+      s0 += part[(int64_t)fn_poff[e] * ncr + j];
+      s1 += part[(int64_t)fn_poff[e + 16] * ncr + j];
+    }
+    if (e < e1) s0 += part[(int64_t)fn_poff[e] * ncr + j];
+  }
+  red[grp][lane] = s0 + s1;
+  __syncthreads();
+  for (int st = 8; st > 0; st >>= 1) {
+    if (grp < st) red[grp][lane] += red[grp + st][lane];
+    __syncthreads();
+  }
+  if (grp == 0 && j < ncr) wp[(int64_t)nu * ncr + j] = red[0][lane];
+}
+
+// Partial transposed enrichment product per row chunk of an atom block:
+//   part[c][f][v] = sum_{r in chunk} conj((m^-1/2 H^co)[r, f]) x[row_r][v]
+// Workgroup = RG row groups x NVB vector lanes; the row groups are reduced in LDS.
+template <typename T, bool CPLX>
+__global__ __launch_bounds__(512) void enr_partial_kernel(
+    const T* __restrict__ x, int64_t ldx, int nv, int nvb, const int32_t* __restrict__ chunk_blk,
     const int64_t* __restrict__ chunk_r0, const int64_t* __restrict__ chunk_r1, const int32_t* __restrict__ blk_nf,
     const int64_t* __restrict__ blk_rptr, const int32_t* __restrict__ rows, const T* __restrict__ hv, int FMAX,
-    CellCoef<T> cf, int n, int p, T* __restrict__ part, int ncr) {
+    T* __restrict__ part, int ncr) {
+  constexpr int FM = 8;
+  constexpr int E = CPLX ? 2 : 1;
+  extern __shared__ unsigned char smem_raw[];
+  T* red = reinterpret_cast<T*>(smem_raw);  // [RG][FMAX][nvb][E]
+  const int tx = threadIdx.x % nvb, ty = threadIdx.x / nvb;
+  const int RG = blockDim.x / nvb;
   const int c = blockIdx.x;
-  const int vv = blockIdx.y * 64 + threadIdx.x;
-  if (vv >= nv) return;
+  const int vv = blockIdx.y * nvb + tx;
+  const bool active = ty < RG && vv < nv;
   const int b = chunk_blk[c];
   const int nf = blk_nf[b];
   const int64_t base = blk_rptr[b];
-  constexpr int FM = 8;
-  if constexpr (!CPLX) {
-    T acc[FM];
+  T ar[FM], ai[FM];
 #pragma unroll
-    for (int f = 0; f < FM; ++f) acc[f] = 0;
-    for (int64_t r = chunk_r0[c]; r < chunk_r1[c]; ++r) {
+  for (int f = 0; f < FM; ++f) ar[f] = ai[f] = 0;
+  if (active) {
+    const int64_t r1 = chunk_r1[c];
+#pragma unroll 4
+    for (int64_t r = chunk_r0[c] + ty; r < r1; r += RG) {
       const int64_t g = rows[base + r];
-      const int ix = (int)(g % n), iy = (int)((g / n) % n), iz = (int)(g / ((int64_t)n * n));
-      const T z = cf.mscale * cf.om[ix % p] * cf.om[iy % p] * cf.om[iz % p] * x[g * ldx + vv];
-      const T* h = hv + (base + r) * FMAX;
+      const T* h = hv + (base + r) * FMAX * E;
+      if constexpr (!CPLX) {
+        const T z = x[g * ldx + vv];
 #pragma unroll
-      for (int f = 0; f < FM; ++f)
-        if (f < nf) acc[f] += h[f] * z;
+        for (int f = 0; f < FM; ++f)
+          if (f < nf) ar[f] += h[f] * z;
+      } else {
+        const T* px = x + g * ldx + 2 * vv;
+        const C2<T> z{px[0], px[1]};
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+          if (f < nf) {
+            const C2<T> t = cjmul(C2<T>{h[2 * f], h[2 * f + 1]}, z);
+            ar[f] += t.r;
+            ai[f] += t.i;
+          }
+      }
     }
-    for (int f = 0; f < nf; ++f) part[((int64_t)c * FMAX + f) * ncr + vv] = acc[f];
-  } else {
-    C2<T> acc[FM];
-#pragma unroll
-    for (int f = 0; f < FM; ++f) acc[f] = C2<T>{0, 0};
-    for (int64_t r = chunk_r0[c]; r < chunk_r1[c]; ++r) {
-      const int64_t g = rows[base + r];
-      const int ix = (int)(g % n), iy = (int)((g / n) % n), iz = (int)(g / ((int64_t)n * n));
-      const T sc = cf.mscale * cf.om[ix % p] * cf.om[iy % p] * cf.om[iz % p];
-      const T* px = x + g * ldx + 2 * vv;
-      C2<T> z{sc * px[0], sc * px[1]};
-      const T* h = hv + 2 * (base + r) * FMAX;
-#pragma unroll
-      for (int f = 0; f < FM; ++f)
-        if (f < nf) {
-          C2<T> t = cjmul(C2<T>{h[2 * f], h[2 * f + 1]}, z);
-          acc[f].r += t.r;
-          acc[f].i += t.i;
-        }
-    }
+  }
+  if (ty < RG) {
     for (int f = 0; f < nf; ++f) {
-      part[((int64_t)c * FMAX + f) * ncr + 2 * vv] = acc[f].r;
-      part[((int64_t)c * FMAX + f) * ncr + 2 * vv + 1] = acc[f].i;
+      red[((ty * FMAX + f) * nvb + tx) * E] = ar[f];
+      if (CPLX) red[((ty * FMAX + f) * nvb + tx) * E + (E - 1)] = ai[f];
+    }
+  }
+  __syncthreads();
+  if (ty == 0 && vv < nv) {
+    for (int f = 0; f < nf; ++f) {
+      T sr = 0, si = 0;
+      for (int g2 = 0; g2 < RG; ++g2) {
+        sr += red[((g2 * FMAX + f) * nvb + tx) * E];
+        if (CPLX) si += red[((g2 * FMAX + f) * nvb + tx) * E + (E - 1)];
+      }
+      part[((int64_t)c * FMAX + f) * ncr + E * vv] = sr;
+      if (CPLX) part[((int64_t)c * FMAX + f) * ncr + E * vv + 1] = si;
     }
   }
 }
 
-// W'[nu][v] = sum over the chunks of nu's block of part + sum_mu H^oo[nu][mu] Z^O[mu][v]
-template <typename T, bool CPLX>
-__global__ void enr_wprime_kernel(const T* __restrict__ part, const T* __restrict__ Hoo, const T* __restrict__ zo,
-                                  const int32_t* __restrict__ fn_blk, const int32_t* __restrict__ blk_fn0,
-                                  const int32_t* __restrict__ blk_chunk0, int FMAX, int nO, int nv, int ncr,
-                                  T* __restrict__ wp) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nO * nv) return;
-  const int nu = idx / nv, vv = idx % nv;
+// W'[nu][j] = sum over the chunks of nu's block of part, in a fixed order.
+// Workgroup per (nu, 64 real columns): 16 groups of 64 lanes each sum a strided
+// subset of the chunks, then a fixed LDS tree combines the groups.
+template <typename T>
+__global__ __launch_bounds__(1024) void enr_reduce_kernel(const T* __restrict__ part,
+                                                          const int32_t* __restrict__ fn_blk,
+                                                          const int32_t* __restrict__ blk_fn0,
+                                                          const int32_t* __restrict__ blk_chunk0, int FMAX, int nO,
+                                                          int ncr, T* __restrict__ wp) {
+  __shared__ T red[16][64];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int nu = blockIdx.x;
+  const int j = blockIdx.y * 64 + lane;
   const int b = fn_blk[nu];
   const int f = nu - blk_fn0[b];
-  if constexpr (!CPLX) {
-    T s = 0;
-    for (int c = blk_chunk0[b]; c < blk_chunk0[b + 1]; ++c) s += part[((int64_t)c * FMAX + f) * ncr + vv];
-    for (int mu = 0; mu < nO; ++mu) s += Hoo[(int64_t)nu * nO + mu] * zo[(int64_t)mu * ncr + vv];
-    wp[(int64_t)nu * ncr + vv] = s;
-  } else {
-    C2<T> s{0, 0};
-    for (int c = blk_chunk0[b]; c < blk_chunk0[b + 1]; ++c) {
-      s.r += part[((int64_t)c * FMAX + f) * ncr + 2 * vv];
-      s.i += part[((int64_t)c * FMAX + f) * ncr + 2 * vv + 1];
+  const int c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1];
+  T s0 = 0, s1 = 0;
+  if (j < ncr) {
+    int c = c0 + grp;
+    for (; c + 16 < c1; c += 32) {
+      s0 += part[((int64_t)c * FMAX + f) * ncr + j];
+      s1 += part[((int64_t)(c + 16) * FMAX + f) * ncr + j];
     }
-    for (int mu = 0; mu < nO; ++mu) {
-      C2<T> a{Hoo[2 * ((int64_t)nu * nO + mu)], Hoo[2 * ((int64_t)nu * nO + mu) + 1]};
-      C2<T> z = cmul(a, C2<T>{zo[(int64_t)mu * ncr + 2 * vv], zo[(int64_t)mu * ncr + 2 * vv + 1]});
-      s.r += z.r;
-      s.i += z.i;
-    }
-    wp[(int64_t)nu * ncr + 2 * vv] = s.r;
-    wp[(int64_t)nu * ncr + 2 * vv + 1] = s.i;
+    if (c < c1) s0 += part[((int64_t)c * FMAX + f) * ncr + j];
   }
+  red[grp][lane] = s0 + s1;
+  __syncthreads();
+  for (int st = 8; st > 0; st >>= 1) {
+    if (grp < st) red[grp][lane] += red[grp + st][lane];
+    __syncthreads();
+  }
+  if (grp == 0 && j < ncr) wp[(int64_t)nu * ncr + j] = red[0][lane];
 }
 
-// enrichment rows: hx = S W'; out = alpha (hx - c x) - beta prev
+// Small dense products on the enrichment rows (n x k times k x m, complex
+// interleaved when CPLX), 16x16 output tile per workgroup, LDS-staged K tiles.
+//   mode 0: C = A B        mode 1: C += A B
+//   mode 2: recurrence epilogue  out[N+i][j] = alpha (A B - c x[N+i][j]) - beta prev[N+i][j]
 template <typename T, bool CPLX>
-__global__ void enr_final_kernel(const T* __restrict__ S, const T* __restrict__ wp, const T* __restrict__ x,
-                                 const T* __restrict__ prev, T* __restrict__ out, int64_t ldx, int64_t ldo,
-                                 int64_t N, int nO,
-                                 int nv, int ncr, T alpha, T c, T beta) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nO * nv) return;
-  const int nu = idx / nv, vv = idx % nv;
-  if constexpr (!CPLX) {
-    T s = 0;
-    for (int mu = 0; mu < nO; ++mu) s += S[(int64_t)nu * nO + mu] * wp[(int64_t)mu * ncr + vv];
-    const int64_t o = (N + nu) * ldx + vv;
-    const int64_t oo = (N + nu) * ldo + vv;
-    T r = alpha * (s - c * x[o]);
-    if (beta != T(0)) r -= beta * prev[oo];
-    out[oo] = r;
+__global__ __launch_bounds__(256) void small_gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, int64_t ldb,
+                                                         T* __restrict__ C, int64_t ldc, int n, int k, int m, int mode,
+                                                         const T* __restrict__ x, const T* __restrict__ prev,
+                                                         int64_t ldx, int64_t ldo, T alpha, T cc, T beta) {
+  constexpr int E = CPLX ? 2 : 1;
+  constexpr int TS = 16;
+  __shared__ T As[TS][TS * E + 1];
+  __shared__ T Bs[TS][TS * E + 1];
+  const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+  const int i = blockIdx.y * TS + ty;  // row of C
+  const int j = blockIdx.x * TS + tx;  // column of C (complex element)
+  T sr = 0, si = 0;
+  for (int k0 = 0; k0 < k; k0 += TS) {
+    for (int e = 0; e < E; ++e) {
+      const int ka = k0 + tx, kb = k0 + ty;
+      As[ty][tx * E + e] = (i < n && ka < k) ? A[((int64_t)i * k + ka) * E + e] : T(0);
+      Bs[ty][tx * E + e] = (kb < k && j < m) ? B[(int64_t)kb * ldb + (int64_t)j * E + e] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TS; ++kk) {
+      if constexpr (!CPLX) {
+        sr += As[ty][kk] * Bs[kk][tx];
+      } else {
+        const C2<T> t = cmul(C2<T>{As[ty][2 * kk], As[ty][2 * kk + 1]}, C2<T>{Bs[kk][2 * tx], Bs[kk][2 * tx + 1]});
+        sr += t.r;
+        si += t.i;
+      }
+    }
+    __syncthreads();
+  }
+  if (i >= n || j >= m) return;
+  if (mode == 0) {
+    C[(int64_t)i * ldc + (int64_t)j * E] = sr;
+    if (CPLX) C[(int64_t)i * ldc + (int64_t)j * E + 1] = si;
+  } else if (mode == 1) {
+    C[(int64_t)i * ldc + (int64_t)j * E] += sr;
+    if (CPLX) C[(int64_t)i * ldc + (int64_t)j * E + 1] += si;
   } else {
-    C2<T> s{0, 0};
-    for (int mu = 0; mu < nO; ++mu) {
-      C2<T> a{S[2 * ((int64_t)nu * nO + mu)], S[2 * ((int64_t)nu * nO + mu) + 1]};
-      C2<T> z = cmul(a, C2<T>{wp[(int64_t)mu * ncr + 2 * vv], wp[(int64_t)mu * ncr + 2 * vv + 1]});
-      s.r += z.r;
-      s.i += z.i;
+    const int64_t ox = (int64_t)i * ldx + (int64_t)j * E, oo = (int64_t)i * ldo + (int64_t)j * E;
+    T r = alpha * (sr - cc * x[ox]);
+    if (beta != T(0)) r -= beta * prev[oo];
+    C[oo] = r;
+    if (CPLX) {
+      T r2 = alpha * (si - cc * x[ox + 1]);
+      if (beta != T(0)) r2 -= beta * prev[oo + 1];
+      C[oo + 1] = r2;
     }
-    const int64_t o = (N + nu) * ldx + 2 * vv;
-    const int64_t oo = (N + nu) * ldo + 2 * vv;
-    T rr = alpha * (s.r - c * x[o]);
-    T ri = alpha * (s.i - c * x[o + 1]);
-    if (beta != T(0)) {
-      rr -= beta * prev[oo];
-      ri -= beta * prev[oo + 1];
-    }
-    out[oo] = rr;
-    out[oo + 1] = ri;
   }
 }
 
@@ -713,17 +913,25 @@ const CellCoef<float>& coef<float>(const oefe_op_s* op) { return op->cf; }
 
 template <typename T>
 struct DevPtrs {
-  const T *WV, *hv, *S, *Hoo, *lambda;
+  const T *WV, *hv, *S, *Hoo, *lambda, *frv, *tv;
 };
 template <typename T>
 DevPtrs<T> devptrs(const oefe_op_s* op);
 template <>
 DevPtrs<double> devptrs<double>(const oefe_op_s* op) {
-  return {op->d.WV, op->d.hv, op->d.S, op->d.Hoo, op->d.lambda};
+  return {op->d.WV, op->d.hv, op->d.S, op->d.Hoo, op->d.lambda, op->d.fr_val, op->d.tile_val};
 }
 template <>
 DevPtrs<float> devptrs<float>(const oefe_op_s* op) {
-  return {op->d.WVf, op->d.hvf, op->d.Sf, op->d.Hoof, op->d.lambdaf};
+  return {op->d.WVf, op->d.hvf, op->d.Sf, op->d.Hoof, op->d.lambdaf, op->d.fr_valf, op->d.tile_valf};
+}
+
+template <typename T, bool CPLX>
+void small_gemm(const T* A, const T* B, int64_t ldb, T* C, int64_t ldc, int n, int k, int m, int mode, const T* x,
+                const T* prev, int64_t ldx, int64_t ldo, double alpha, double c, double beta, hipStream_t s) {
+  dim3 grid((unsigned)cdiv(m, 16), (unsigned)cdiv(n, 16));
+  hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), grid, dim3(256), 0, s, A, B, ldb, C, ldc, n, k, m, mode, x, prev,
+                     ldx, ldo, (T)alpha, (T)c, (T)beta);
 }
 
 template <typename T, bool CPLX>
@@ -749,9 +957,9 @@ int apply_step_impl(const oefe_op_s* op, const T* x, int64_t ld, const T* prev, 
   T* zo = (T*)w.zo;
   T* part = (T*)w.part;
   T* wp = (T*)w.wp;
+  // Z^O = S X^O
   if (nO > 0)
-    hipLaunchKernelGGL((enr_zo_kernel<T, CPLX>), dim3((unsigned)cdiv((int64_t)nO * nv, 128)), dim3(128), 0, s, dp.S,
-                       x, ldx, op->N, nO, nv, zo, ncr);
+    small_gemm<T, CPLX>(dp.S, x + op->N * ldx, ldx, zo, ncr, nO, nO, nv, 0, nullptr, nullptr, 0, 0, 0, 0, 0, s);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (op->timer_on && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess)
     (void)hipEventRecord(ev0, s);
@@ -760,19 +968,29 @@ int apply_step_impl(const oefe_op_s* op, const T* x, int64_t ld, const T* prev, 
     (void)hipEventRecord(ev1, s);
     op->timer_events.emplace_back(ev0, ev1);
   }
-  if (nO > 0)
-    hipLaunchKernelGGL((enr_partial_kernel<T, CPLX>), dim3((unsigned)op->n_chunks, (unsigned)cdiv(nv, 64)), dim3(64),
-                       0, s, x, ldx, nv, op->d.chunk_blk, op->d.chunk_r0, op->d.chunk_r1, op->d.blk_nf,
-                       op->d.blk_rptr, op->d.blk_rows, dp.hv, op->FMAX, cf, op->n, op->p, part, ncr);
-  hipLaunchKernelGGL((fe_node_kernel<T, CPLX>), dim3((unsigned)cdiv(op->N * nv, 256)), dim3(256), 0, s,
-                     (const T*)w.ycell, w.ldc, x, prev, out, ldx, ldo, nv, op->nc, op->p, op->n, op->P1, cf, ph, zo, ncr,
-                     op->d.row_ptr, op->d.row_blk, op->d.row_pos, op->d.blk_fn0, op->d.blk_nf, dp.hv, op->FMAX,
-                     (T)alpha, (T)c, (T)beta, op->N);
+  // column block of the tiled kernels: all real columns up to 128, else near-equal blocks
+  int CB = ncr <= 128 ? ncr : (int)cdiv(ncr, cdiv(ncr, 128));
+  CB = (int)cdiv(CB, 8) * 8;
+  const int ncb = (int)cdiv(ncr, CB);
   if (nO > 0) {
-    hipLaunchKernelGGL((enr_wprime_kernel<T, CPLX>), dim3((unsigned)cdiv((int64_t)nO * nv, 128)), dim3(128), 0, s,
-                       part, dp.Hoo, zo, op->d.fn_blk, op->d.blk_fn0, op->d.blk_chunk0, op->FMAX, nO, nv, ncr, wp);
-    hipLaunchKernelGGL((enr_final_kernel<T, CPLX>), dim3((unsigned)cdiv((int64_t)nO * nv, 128)), dim3(128), 0, s,
-                       dp.S, wp, x, prev, out, ldx, ldo, op->N, nO, nv, ncr, (T)alpha, (T)c, (T)beta);
+    const size_t lds = (size_t)(16 * CB + 16 * op->tile_fpmax * (CPLX ? 2 : 1)) * sizeof(T);
+    hipLaunchKernelGGL((enr_tile_partial_kernel<T, CPLX>), dim3((unsigned)op->n_tiles, (unsigned)ncb), dim3(4 * CB),
+                       lds, s, x, ldx, ncr, CB, op->d.tile_fptr, dp.tv, part, (int)op->N);
+  }
+  {
+    const size_t lds = (size_t)(kTileRows * 16 * (CPLX ? 2 : 1) + 16 * CB) * sizeof(T);
+    hipLaunchKernelGGL((fe_node_tile_kernel<T, CPLX>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb),
+                       dim3(4 * CB), lds, s, (const T*)w.ycell, w.ldc, x, prev, out, ldx, ldo, ncr, CB, op->nc,
+                       op->p, op->n, op->P1, cf, ph, zo, op->d.tile_fptr, op->d.tile_fns, dp.tv, (T)alpha, (T)c,
+                       (T)beta, (int)op->N);
+  }
+  if (nO > 0) {
+    hipLaunchKernelGGL((enr_tile_reduce_kernel<T>), dim3((unsigned)nO, (unsigned)cdiv(ncr, 64)), dim3(1024), 0, s,
+                       part, op->d.fn_pptr, op->d.fn_poff, ncr, wp);
+    // W' += H^oo Z^O ;  enrichment rows: alpha (S W' - c x) - beta prev
+    small_gemm<T, CPLX>(dp.Hoo, zo, ncr, wp, ncr, nO, nO, nv, 1, nullptr, nullptr, 0, 0, 0, 0, 0, s);
+    small_gemm<T, CPLX>(dp.S, wp, ncr, out + op->N * ldo, ldo, nO, nO, nv, 2, x + op->N * ldx,
+                        prev ? prev + op->N * ldo : nullptr, ldx, ldo, alpha, c, beta, s);
   }
   return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
 }
@@ -787,7 +1005,7 @@ size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, i
   size_t bytes = 0;
   if (!op->diagonal) bytes += al((size_t)op->n_cells * op->nd * ldc * elem_bytes);
   bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                      // zo
-  bytes += al((size_t)std::max<int64_t>(op->n_chunks, 1) * op->FMAX * ncr * elem_bytes);  // part
+  bytes += al((size_t)std::max<int64_t>(op->tile_slots, 1) * ncr * elem_bytes);  // part
   bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                      // wp
   return bytes;
 }
@@ -807,7 +1025,7 @@ StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv,
   w.zo = p;
   p += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);
   w.part = p;
-  p += al((size_t)std::max<int64_t>(op->n_chunks, 1) * op->FMAX * ncr * elem_bytes);
+  p += al((size_t)std::max<int64_t>(op->tile_slots, 1) * ncr * elem_bytes);
   w.wp = p;
   return w;
 }
@@ -831,11 +1049,9 @@ int zo_only(const oefe_op_s* op, const T* x, int64_t ld, int nv, T* zo, int ncr,
   const DevPtrs<T> dp = devptrs<T>(op);
   const int nO = op->n_enr;
   if (op->cplx)
-    hipLaunchKernelGGL((enr_zo_kernel<T, true>), dim3((unsigned)cdiv((int64_t)nO * nv, 128)), dim3(128), 0, s, dp.S,
-                       x, 2 * ld, op->N, nO, nv, zo, ncr);
+    small_gemm<T, true>(dp.S, x + op->N * 2 * ld, 2 * ld, zo, ncr, nO, nO, nv, 0, nullptr, nullptr, 0, 0, 0, 0, 0, s);
   else
-    hipLaunchKernelGGL((enr_zo_kernel<T, false>), dim3((unsigned)cdiv((int64_t)nO * nv, 128)), dim3(128), 0, s, dp.S,
-                       x, ld, op->N, nO, nv, zo, ncr);
+    small_gemm<T, false>(dp.S, x + op->N * ld, ld, zo, ncr, nO, nO, nv, 0, nullptr, nullptr, 0, 0, 0, 0, 0, s);
   return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
 }
 
