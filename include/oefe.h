@@ -141,6 +141,24 @@ int chebyshev_filter(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv
 int chebyshev_filter_mixed(oefe_op op, oefe_prec prec_filter, void* X, int64_t ld, int32_t nv, int32_t m, double a,
                            double b, double a0, void* work, oefe_stream stream);
 
+/* Chebyshev filters of nk operators sharing one mesh and enrichment layout (the
+ * Bloch k-points of one system), advanced in lockstep: each stage of each degree
+ * is a single launch covering all operators, so uneven blocks (different nv[q])
+ * fill the device together.  Operator q filters X[q] (device [n_tot x ld[q]],
+ * nv[q] vectors, in place) with its own bounds abc[3q], abc[3q+1], abc[3q+2] =
+ * (a, b, a0) as in chebyshev_filter; all use degree m.  prec as for
+ * chebyshev_filter (C128/C64 for Bloch operators).  work: at least
+ * oefe_batched_work_size(nk, ops, prec, nv) bytes.  Errors: EINVAL when the
+ * operators do not share the mesh / enrichment layout. */
+int chebyshev_filter_batched(int32_t nk, const oefe_op* ops, oefe_prec prec, void* const* X, const int64_t* ld,
+                             const int32_t* nv, int32_t m, const double* abc, void* work, oefe_stream stream);
+size_t oefe_batched_work_size(int32_t nk, const oefe_op* ops, oefe_prec prec, const int32_t* nv);
+
+/* Launch-shape overrides chosen by an autotuner: cell-kernel column width
+ * cw in {8, 16, 32, 64} (0 = built-in choice) and the column block of the node
+ * and enrichment kernels cb (multiple of 8, <= 128; 0 = built-in). */
+int oefe_set_launch_shape(oefe_op op, int32_t cw, int32_t cb);
+
 /* k-step Lanczos with full reorthogonalization from v0 (device, n_tot real, or
  * complex interleaved for a Bloch operator) in float64; out[0] = smallest Ritz
  * value of T_k, out[1] = largest + beta_k (an upper bound of the spectrum).

@@ -632,6 +632,128 @@ int chebyshev_filter_mixed(oefe_op op, oefe_prec prec, void* X, int64_t ld, int3
   return OEFE_OK;
 }
 
+size_t oefe_batched_work_size(int32_t nk, const oefe_op* ops, oefe_prec prec, const int32_t* nv) {
+  if (nk <= 0 || !ops || !nv) return 0;
+  const int eb = prec_fp32(prec) ? 4 : 8;
+  size_t tot = 0;
+  for (int q = 0; q < nk; ++q) {
+    if (!ops[q] || nv[q] <= 0) return 0;
+    const int E = ops[q]->cplx ? 2 : 1;
+    tot += al256(step_work_bytes(ops[q], eb, ops[q]->cplx, nv[q], nullptr));
+    tot += 2 * al256((size_t)ops[q]->n_tot * nv[q] * E * eb);
+  }
+  return tot + 256;
+}
+
+int oefe_set_launch_shape(oefe_op op, int32_t cw, int32_t cb) {
+  if (!op) return fail(OEFE_EINVAL, "null operator");
+  if (!(cw == 0 || cw == 8 || cw == 16 || cw == 32 || cw == 64)) return fail(OEFE_EINVAL, "cw must be 0, 8, 16, 32 or 64");
+  if (cb < 0 || cb > 128 || cb % 8) return fail(OEFE_EINVAL, "cb must be a multiple of 8 in [0, 128]");
+  op->tune_cw = cw;
+  op->tune_cb = cb;
+  return OEFE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+int filter_batched_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const int64_t* ld, const int32_t* nv,
+                        int m, const double* abc, void* work, hipStream_t s) {
+  const int eb = sizeof(T);
+  std::vector<StepWork> sw(nk);
+  std::vector<T*> A(nk), B(nk);
+  std::vector<int> nvv(nk);
+  std::vector<int64_t> ldp(nk);
+  char* p = (char*)work;
+  for (int q = 0; q < nk; ++q) {
+    const int E = ops[q]->cplx ? 2 : 1;
+    sw[q] = carve_step_work(ops[q], eb, ops[q]->cplx, nv[q], p);
+    p += al256(step_work_bytes(ops[q], eb, ops[q]->cplx, nv[q], nullptr));
+    A[q] = (T*)p;
+    p += al256((size_t)ops[q]->n_tot * nv[q] * E * eb);
+    B[q] = (T*)p;
+    p += al256((size_t)ops[q]->n_tot * nv[q] * E * eb);
+    nvv[q] = nv[q];
+    ldp[q] = nv[q];
+    int rc = cast_block(X[q], eb == 4, A[q], eb == 4, ops[q]->n_tot, ld[q] * E, (int64_t)nv[q] * E, nv[q] * E, s);
+    if (rc) return rc;
+  }
+  std::vector<double> e(nk), c(nk), s1(nk), sig(nk), al(nk), be(nk);
+  for (int q = 0; q < nk; ++q) {
+    const double a = abc[3 * q], b = abc[3 * q + 1], a0 = abc[3 * q + 2];
+    e[q] = (b - a) / 2.0;
+    c[q] = (b + a) / 2.0;
+    s1[q] = e[q] / (a0 - c[q]);
+    sig[q] = s1[q];
+  }
+  std::vector<const T*> xin(nk), pin(nk);
+  std::vector<T*> outp(nk);
+  const oefe_op_s* const* opp = (const oefe_op_s* const*)ops;
+  // Y_1 = (s1/e)(H x - c x): cur = A, result into B
+  for (int q = 0; q < nk; ++q) {
+    xin[q] = A[q];
+    pin[q] = nullptr;
+    outp[q] = B[q];
+    al[q] = s1[q] / e[q];
+    be[q] = 0.0;
+  }
+  int rc = apply_step_batch<T>(opp, nk, bf16, xin.data(), ldp.data(), pin.data(), outp.data(), ldp.data(), nvv.data(),
+                               al.data(), c.data(), be.data(), sw.data(), s);
+  if (rc) return rc;
+  T** cur = B.data();
+  T** old = A.data();
+  for (int k = 1; k < m; ++k) {
+    for (int q = 0; q < nk; ++q) {
+      const double sn = 1.0 / (2.0 / s1[q] - sig[q]);
+      xin[q] = cur[q];
+      pin[q] = old[q];
+      outp[q] = old[q];
+      al[q] = 2.0 * sn / e[q];
+      be[q] = sig[q] * sn;
+      sig[q] = sn;
+    }
+    rc = apply_step_batch<T>(opp, nk, bf16, xin.data(), ldp.data(), pin.data(), outp.data(), ldp.data(), nvv.data(),
+                             al.data(), c.data(), be.data(), sw.data(), s);
+    if (rc) return rc;
+    std::swap(cur, old);
+  }
+  for (int q = 0; q < nk; ++q) {
+    const int E = ops[q]->cplx ? 2 : 1;
+    rc = cast_block(cur[q], eb == 4, X[q], eb == 4, ops[q]->n_tot, (int64_t)nv[q] * E, ld[q] * E, nv[q] * E, s);
+    if (rc) return rc;
+  }
+  return OEFE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int chebyshev_filter_batched(int32_t nk, const oefe_op* ops, oefe_prec prec, void* const* X, const int64_t* ld,
+                             const int32_t* nv, int32_t m, const double* abc, void* work, oefe_stream stream) {
+  if (nk <= 0 || !ops || !X || !ld || !nv || !abc || !work || m < 1) return fail(OEFE_EINVAL, "bad arguments");
+  for (int q = 0; q < nk; ++q) {
+    if (!ops[q] || !X[q] || nv[q] <= 0 || ld[q] < nv[q]) return fail(OEFE_EINVAL, "bad per-operator arguments");
+    if (int rc = check_prec(ops[q], prec)) return rc;
+    const oefe_op_s* a = ops[0];
+    const oefe_op_s* b = ops[q];
+    if (b->diagonal || a->diagonal || b->nc != a->nc || b->p != a->p || b->L != a->L || b->n_enr != a->n_enr ||
+        b->n_tiles != a->n_tiles || b->tile_slots != a->tile_slots || b->tile_fpmax != a->tile_fpmax)
+      return fail(OEFE_EINVAL, "batched operators must share the mesh and the enrichment layout");
+    const double aa = abc[3 * q], bb = abc[3 * q + 1], a0 = abc[3 * q + 2];
+    if (!(aa < bb) || !(a0 < aa)) return fail(OEFE_EINVAL, "need a0 < a < b for every operator");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (prec_fp32(prec))
+    rc = filter_batched_impl<float>(nk, ops, prec == OEFE_BF16, X, ld, nv, m, abc, work, s);
+  else
+    rc = filter_batched_impl<double>(nk, ops, false, X, ld, nv, m, abc, work, s);
+  if (rc == OEFE_EUNSUPPORTED) return fail(rc, "precision not supported by chebyshev_filter_batched");
+  if (rc) return fail(rc, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return OEFE_OK;
+}
+
 int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
            oefe_stream stream) {
   if (!op || !X || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");

@@ -133,6 +133,8 @@ struct oefe_op_s {
   int64_t n_tiles = 0, tile_slots = 0;        // tiles, total padded (tile, function) slots
   int tile_fpmax = 0;
   oefe::DeviceArrays d;
+  // launch shape overrides (autotuner): cell-kernel column width, node/partial column block
+  int tune_cw = 0, tune_cb = 0;
   // instrumentation (oefe_kernel_timer)
   bool timer_on = false;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;

@@ -23,6 +23,11 @@ StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv,
 template <typename T>
 int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
                double alpha, double c, double beta, const StepWork& w, hipStream_t s);
+// Batched steps of nk operators sharing one mesh / enrichment layout (k-points), in lockstep.
+template <typename T>
+int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* const* x, const int64_t* ld,
+                     const T* const* prev, T* const* out, const int64_t* ldo, const int* nv, const double* alpha,
+                     const double* c, const double* beta, const StepWork* w, hipStream_t s);
 // Z^O = S X^O only (for the density)
 template <typename T>
 int zo_only(const oefe_op_s* op, const T* x, int64_t ld, int nv, T* zo, int ncr, hipStream_t s);

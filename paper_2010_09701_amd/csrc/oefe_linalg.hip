@@ -267,14 +267,12 @@ __global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int 
 
 // ---- cyclic Jacobi (round-robin parallel ordering), one workgroup
 template <bool CPLX>
-__global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, int n, double* __restrict__ lam,
-                                                      double* __restrict__ U, double* __restrict__ V,
-                                                      double* __restrict__ rot, int32_t* __restrict__ status) {
+__device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* __restrict__ U, double* V,
+                            double* rot, int32_t* __restrict__ status, double* red) {
   constexpr int E = CPLX ? 2 : 1;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
   const int npair = NN / 2, m = NN - 1;
-  __shared__ double red[1024];
   __shared__ int done;
   auto A_ = [&](int i, int j) -> double* { return A + ((int64_t)i * n + j) * E; };
   for (int t = tid; t < n * n; t += nth) {
@@ -433,6 +431,30 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, in
       if (CPLX) U[((int64_t)r * n + rank) * E + 1] = V[((int64_t)r * n + i) * E + 1];
     }
   }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, int n, double* __restrict__ lam,
+                                                      double* __restrict__ U, double* __restrict__ V,
+                                                      double* __restrict__ rot, int32_t* __restrict__ status) {
+  __shared__ double red[1024];
+  jacobi_body<CPLX>(A, n, lam, U, V, rot, status, red);
+}
+
+// Same solver with the matrix, the rotations and the accumulated vectors in LDS (small n).
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restrict__ A, int n,
+                                                          double* __restrict__ lam, double* __restrict__ U,
+                                                          int32_t* __restrict__ status) {
+  constexpr int E = CPLX ? 2 : 1;
+  extern __shared__ double sm[];
+  double* As = sm;                       // n*n*E
+  double* Vs = As + (size_t)n * n * E;   // n*n*E
+  double* rot = Vs + (size_t)n * n * E;  // 6 * (n/2 + 1)
+  double* red = rot + 6 * (n / 2 + 1);   // 1024
+  for (int t = threadIdx.x; t < n * n * E; t += blockDim.x) As[t] = A[t];
+  __syncthreads();
+  jacobi_body<CPLX>(As, n, lam, U, Vs, rot, status, red);
 }
 
 template <bool CPLX>
@@ -628,6 +650,24 @@ size_t jacobi_scratch_bytes(bool cplx, int n) {
 }
 
 int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s) {
+  const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + 6 * (n / 2 + 1) + 1024) * sizeof(double);
+  if (lds <= 160 * 1024) {
+    static bool attr_set[2] = {false, false};
+    if (!attr_set[cplx]) {
+      if (cplx)
+        (void)hipFuncSetAttribute((const void*)jacobi_lds_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+      else
+        (void)hipFuncSetAttribute((const void*)jacobi_lds_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+      attr_set[cplx] = true;
+    }
+    if (cplx)
+      hipLaunchKernelGGL(jacobi_lds_kernel<true>, dim3(1), dim3(1024), lds, s, A, n, lam, U, status);
+    else
+      hipLaunchKernelGGL(jacobi_lds_kernel<false>, dim3(1), dim3(1024), lds, s, A, n, lam, U, status);
+    return check();
+  }
   double* V = scratch;
   double* rot = scratch + (size_t)n * n * (cplx ? 2 : 1);
   if (cplx)

@@ -2,13 +2,16 @@
 // scaled Chebyshev recurrence step built on it (gfx950, wave64).
 //
 // One operator step (out = alpha (Ht x - c x) - beta prev) is:
-//   1. zo      Z^O = S X^O                                   (small dense)
-//   2. cell    per cell: z_e = m^-1/2 (theta o X)|_e, y_e = K_e z_e + B^T diag(W V) B z_e
-//              (sum-factorized, see fe_cell_kernel) -> per-cell buffer
-//   3. partial per atom block / row chunk: sum_r conj(H^co[r, f]) m_r^-1/2 X[r]
-//   4. node    per FE node: sum of the (up to 8) cell results sharing it (fixed order,
-//              no atomics), + H^co Z^O, times m^-1/2, recurrence epilogue
-//   5. wprime  W' = sum of partials + H^oo Z^O ;  6. final  S W', recurrence epilogue
+//   1. zo       Z^O = S X^O                                   (small dense)
+//   2. cell     per cell: z_e = m^-1/2 (theta o X)|_e, y_e = K_e z_e + B^T diag(W V) B z_e
+//               (sum-factorized, see fe_cell_kernel) -> per-cell buffer
+//   3. partial  per 64-row tile: conj(m^-1/2 H^co)^T X over the tile's rows
+//   4. node     per FE node: fixed-order sum of the (up to 8) cell results sharing it
+//               (no atomics), times m^-1/2, + (m^-1/2 H^co) Z^O, recurrence epilogue
+//   5. reduce   W' = sum of the tile partials of each function (fixed order)
+//   6. gemm     W' += H^oo Z^O ;  enrichment rows alpha (S W' - c x) - beta prev
+// Every launch can cover several operators of one mesh at once (k-points): the
+// per-operator arguments travel in a KBatch and blockIdx.z selects the operator.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +40,34 @@ struct Phase3 {
   T re[3], im[3];
 };
 
+constexpr int KMAX = 8;  // operators per batched launch
+
+// Per-operator arguments of one recurrence step (leading dimensions in elements of T).
+template <typename T>
+struct KP {
+  const T* x;
+  const T* prev;
+  T* out;
+  int64_t ldx, ldo;
+  int nv, ncr;  // vectors (complex elements when complex) and real columns
+  T* ycell;
+  int ldc;
+  T* zo;
+  T* part;
+  T* wp;
+  const T* tv;
+  const T* S;
+  const T* Hoo;
+  T alpha, c, beta;
+  Phase3<T> ph;
+};
+
+template <typename T>
+struct KBatch {
+  int nk;
+  KP<T> k[KMAX];
+};
+
 // ---------------------------------------------------------------------------
 // Cell kernel.
 //
@@ -51,13 +82,19 @@ struct Phase3 {
 // equals K_e z + B^T diag(W V) B z with the exact (Gauss) cell stiffness.
 // ---------------------------------------------------------------------------
 template <typename T, int P1, int CW, bool CPLX>
-__global__ __launch_bounds__(64 * P1) void fe_cell_kernel(const T* __restrict__ X, int64_t ldx, int ncr,
-                                                          T* __restrict__ Yc, int ldc, const T* __restrict__ WV,
-                                                          CellCoef<T> cf, int nc, int p, int n, int64_t n_cells,
-                                                          Phase3<T> ph) {
+__global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, const T* __restrict__ WV, CellCoef<T> cf,
+                                                          int nc, int p, int n, int64_t n_cells) {
   constexpr int NP = P1 * P1;
   constexpr int CPT = 64 / CW;
   __shared__ T lds[NP * P1][64];
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int ncr = P.ncr;
+  if ((int)blockIdx.y * CW >= ncr) return;  // column block beyond this operator's width
+  const T* __restrict__ X = P.x;
+  const int64_t ldx = P.ldx;
+  T* __restrict__ Yc = P.ycell;
+  const int ldc = P.ldc;
+  const Phase3<T> ph = P.ph;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int cl = lane / CW, col = lane % CW;
@@ -250,102 +287,6 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Node kernel: FE rows.  Workgroup = RB nodes x NVB vector lanes (2D), thread
-// per (FE node g, vector v): fixed-order sum of the (up to 8) cell results that
-// share g, times m_g^-1/2, plus the enrichment term sum_nu (m^-1/2 H^co)[g,nu]
-// Z^O[nu][v] (pre-scaled per-row CSR), then the recurrence epilogue.
-// Z^O is staged in LDS when it fits.
-// ---------------------------------------------------------------------------
-template <typename T, bool CPLX>
-__global__ __launch_bounds__(256) void fe_node_kernel(
-    const T* __restrict__ Yc, int ldc, const T* __restrict__ X, const T* __restrict__ prev, T* __restrict__ out,
-    int64_t ldx, int64_t ldo, int nv, int nvb, int nc, int p, int n, int P1, CellCoef<T> cf, Phase3<T> ph,
-    const T* __restrict__ zo, int ncr, int nO, int zo_in_lds, const int64_t* __restrict__ fr_ptr,
-    const int32_t* __restrict__ fr_fn, const T* __restrict__ fr_val, T alpha, T c, T beta, int N) {
-  extern __shared__ unsigned char smem_raw[];
-  T* zs = reinterpret_cast<T*>(smem_raw);
-  const int tx = threadIdx.x % nvb, ty = threadIdx.x / nvb;
-  const int RB = blockDim.x / nvb;
-  if (zo_in_lds) {
-    const int tot = nO * ncr;
-    for (int t = threadIdx.x; t < tot; t += blockDim.x) zs[t] = zo[t];
-    __syncthreads();
-  }
-  const T* zsrc = zo_in_lds ? zs : zo;
-  const int g = blockIdx.x * RB + ty;
-  const int vv = blockIdx.y * nvb + tx;
-  if (ty >= RB || g >= N || vv >= nv) return;
-  const int ix = g % n, iy = (g / n) % n, iz = g / (n * n);
-  const int nd = P1 * P1 * P1;
-  int cxs[2], axs[2], wxs[2], nxs = 1;
-  int cys[2], ays[2], wys[2], nys = 1;
-  int czs[2], azs[2], wzs[2], nzs = 1;
-  cxs[0] = ix / p; axs[0] = ix % p; wxs[0] = 0;
-  if (axs[0] == 0) { cxs[1] = (cxs[0] + nc - 1) % nc; axs[1] = p; wxs[1] = (cxs[1] == nc - 1); nxs = 2; }
-  cys[0] = iy / p; ays[0] = iy % p; wys[0] = 0;
-  if (ays[0] == 0) { cys[1] = (cys[0] + nc - 1) % nc; ays[1] = p; wys[1] = (cys[1] == nc - 1); nys = 2; }
-  czs[0] = iz / p; azs[0] = iz % p; wzs[0] = 0;
-  if (azs[0] == 0) { czs[1] = (czs[0] + nc - 1) % nc; azs[1] = p; wzs[1] = (czs[1] == nc - 1); nzs = 2; }
-  const T msc = cf.mscale * cf.om[ix % p] * cf.om[iy % p] * cf.om[iz % p];
-  const int64_t k0 = fr_ptr[g], k1 = fr_ptr[g + 1];
-  if constexpr (!CPLX) {
-    T acc = 0;
-    for (int kz = 0; kz < nzs; ++kz)
-      for (int ky = 0; ky < nys; ++ky)
-        for (int kx = 0; kx < nxs; ++kx) {
-          const int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
-          const int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
-          acc += Yc[(e * nd + a) * (int64_t)ldc + vv];
-        }
-    T en = 0;
-#pragma unroll 8
-    for (int64_t k = k0; k < k1; ++k) en += fr_val[k] * zsrc[fr_fn[k] * ncr + vv];
-    const T hx = msc * acc + en;
-    const int64_t gi = (int64_t)g;
-    const T xv = X[gi * ldx + vv];
-    T r = alpha * (hx - c * xv);
-    if (beta != T(0)) r -= beta * prev[gi * ldo + vv];
-    out[gi * ldo + vv] = r;
-  } else {
-    C2<T> acc{0, 0};
-    for (int kz = 0; kz < nzs; ++kz)
-      for (int ky = 0; ky < nys; ++ky)
-        for (int kx = 0; kx < nxs; ++kx) {
-          const int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
-          const int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
-          const T* py = Yc + (e * nd + a) * (int64_t)ldc + 2 * vv;
-          C2<T> z{py[0], py[1]};
-          // scatter phase conj(theta)
-          if (wxs[kx]) z = cjmul(C2<T>{ph.re[0], ph.im[0]}, z);
-          if (wys[ky]) z = cjmul(C2<T>{ph.re[1], ph.im[1]}, z);
-          if (wzs[kz]) z = cjmul(C2<T>{ph.re[2], ph.im[2]}, z);
-          acc.r += z.r;
-          acc.i += z.i;
-        }
-    C2<T> en{0, 0};
-#pragma unroll 4
-    for (int64_t k = k0; k < k1; ++k) {
-      const T* pz = zsrc + fr_fn[k] * ncr + 2 * vv;
-      const C2<T> zz = cmul(C2<T>{fr_val[2 * k], fr_val[2 * k + 1]}, C2<T>{pz[0], pz[1]});
-      en.r += zz.r;
-      en.i += zz.i;
-    }
-    const int64_t gi = (int64_t)g;
-    const T* px = X + gi * ldx + 2 * vv;
-    T rr = alpha * (msc * acc.r + en.r - c * px[0]);
-    T ri = alpha * (msc * acc.i + en.i - c * px[1]);
-    if (beta != T(0)) {
-      const T* pp = prev + gi * ldo + 2 * vv;
-      rr -= beta * pp[0];
-      ri -= beta * pp[1];
-    }
-    T* po = out + gi * ldo + 2 * vv;
-    po[0] = rr;
-    po[1] = ri;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Tiled node kernel: FE rows.  Workgroup = one tile of kTileRows consecutive FE
 // rows x CB real columns, 4 row groups.  For each output (row g, column j):
 //   fixed-order sum of the (up to 8) cell results sharing g, times m_g^-1/2,
@@ -354,22 +295,24 @@ __global__ __launch_bounds__(256) void fe_node_kernel(
 //   then the recurrence epilogue alpha (y - c x) - beta prev.
 // ---------------------------------------------------------------------------
 template <typename T, bool CPLX>
-__global__ __launch_bounds__(512) void fe_node_tile_kernel(
-    const T* __restrict__ Yc, int ldc, const T* __restrict__ X, const T* __restrict__ prev, T* __restrict__ out,
-    int64_t ldx, int64_t ldo, int ncr, int CB, int nc, int p, int n, int P1, CellCoef<T> cf, Phase3<T> ph,
-    const T* __restrict__ zo, const int32_t* __restrict__ tile_fptr, const int32_t* __restrict__ tile_fns,
-    const T* __restrict__ tile_val, T alpha, T c, T beta, int N) {
+__global__ __launch_bounds__(512) void fe_node_tile_kernel(KBatch<T> kb, int CB, int nc, int p, int n, int P1,
+                                                           CellCoef<T> cf, const int32_t* __restrict__ tile_fptr,
+                                                           const int32_t* __restrict__ tile_fns, int N) {
   constexpr int TR = kTileRows, RG = 4, RPT = TR / RG, JC = 16;
   constexpr int E = CPLX ? 2 : 1;
   extern __shared__ unsigned char smem_raw[];
   T* Hs = reinterpret_cast<T*>(smem_raw);  // [TR][JC][E]
   T* zs = Hs + TR * JC * E;                // [JC][CB]
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int ncr = P.ncr;
+  if ((int)blockIdx.y * CB >= ncr) return;
   const int cl = threadIdx.x % CB, rg = threadIdx.x / CB;
   const int t = blockIdx.x;
   const int j = blockIdx.y * CB + cl;  // real column
   // no enrichment: tile_fptr is null and the tile couples to no function
   const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
-  const T* tv = tile_val + (int64_t)f0 * TR * E;
+  const T* tv = P.tv + (int64_t)f0 * TR * E;
+  const T* zo = P.zo;
   T en[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) en[i] = 0;
@@ -403,6 +346,10 @@ __global__ __launch_bounds__(512) void fe_node_tile_kernel(
     __syncthreads();
   }
   if (j >= ncr) return;
+  const T* __restrict__ Yc = P.ycell;
+  const int64_t ldc = P.ldc;
+  const Phase3<T> ph = P.ph;
+  const T alpha = P.alpha, c = P.c, beta = P.beta;
   const int nd = P1 * P1 * P1;
 #pragma unroll 1
   for (int i = 0; i < RPT; ++i) {
@@ -426,9 +373,9 @@ __global__ __launch_bounds__(512) void fe_node_tile_kernel(
           const int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
           const int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
           if constexpr (!CPLX) {
-            acc += Yc[(e * nd + a) * (int64_t)ldc + j];
+            acc += Yc[(e * nd + a) * ldc + j];
           } else {
-            const T* py = Yc + (e * nd + a) * (int64_t)ldc + (j & ~1);
+            const T* py = Yc + (e * nd + a) * ldc + (j & ~1);
             C2<T> z{py[0], py[1]};
             if (wxs[kx]) z = cjmul(C2<T>{ph.re[0], ph.im[0]}, z);
             if (wys[ky]) z = cjmul(C2<T>{ph.re[1], ph.im[1]}, z);
@@ -437,9 +384,9 @@ __global__ __launch_bounds__(512) void fe_node_tile_kernel(
           }
         }
     const int64_t gi = (int64_t)g;
-    T r = alpha * (msc * acc + en[i] - c * X[gi * ldx + j]);
-    if (beta != T(0)) r -= beta * prev[gi * ldo + j];
-    out[gi * ldo + j] = r;
+    T r = alpha * (msc * acc + en[i] - c * P.x[gi * P.ldx + j]);
+    if (beta != T(0)) r -= beta * P.prev[gi * P.ldo + j];
+    P.out[gi * P.ldo + j] = r;
   }
 }
 
@@ -447,19 +394,23 @@ __global__ __launch_bounds__(512) void fe_node_tile_kernel(
 //   part[(tile_fptr[t] + s)][j] = sum_{r in tile} conj(Ht[r][s]) x[r][j]
 // Workgroup = one tile x CB real columns, 4 slot groups; rows staged 16 at a time.
 template <typename T, bool CPLX>
-__global__ __launch_bounds__(512) void enr_tile_partial_kernel(
-    const T* __restrict__ x, int64_t ldx, int ncr, int CB, const int32_t* __restrict__ tile_fptr,
-    const T* __restrict__ tile_val, T* __restrict__ part, int N) {
+__global__ __launch_bounds__(512) void enr_tile_partial_kernel(KBatch<T> kb, int CB,
+                                                               const int32_t* __restrict__ tile_fptr, int N) {
   constexpr int TR = kTileRows, SG = 4, RC = 16, SMAX = 16;
   constexpr int E = CPLX ? 2 : 1;
   extern __shared__ unsigned char smem_raw[];
   T* xs = reinterpret_cast<T*>(smem_raw);  // [RC][CB]
   T* Hs = xs + RC * CB;                     // [RC][FP][E]
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int ncr = P.ncr;
+  if ((int)blockIdx.y * CB >= ncr) return;
   const int cl = threadIdx.x % CB, sg = threadIdx.x / CB;
   const int t = blockIdx.x;
   const int j = blockIdx.y * CB + cl;
   const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;
-  const T* tv = tile_val + (int64_t)f0 * TR * E;
+  const T* tv = P.tv + (int64_t)f0 * TR * E;
+  const T* __restrict__ x = P.x;
+  const int64_t ldx = P.ldx;
   for (int s0 = 0; s0 < FP; s0 += SG * SMAX) {  // slots in groups of 64
     T acc[SMAX];
 #pragma unroll
@@ -499,7 +450,7 @@ __global__ __launch_bounds__(512) void enr_tile_partial_kernel(
 #pragma unroll
       for (int i = 0; i < SMAX; ++i) {
         const int sl = s0 + sg + SG * i;
-        if (sl < FP) part[(int64_t)(f0 + sl) * ncr + j] = acc[i];
+        if (sl < FP) P.part[(int64_t)(f0 + sl) * ncr + j] = acc[i];
       }
     }
   }
@@ -508,11 +459,13 @@ __global__ __launch_bounds__(512) void enr_tile_partial_kernel(
 // W'[nu][j] = sum over the tiles coupling to nu of their partial slot, in tile order.
 // Workgroup per (nu, 64 real columns): 16 groups sum strided subsets, fixed LDS tree.
 template <typename T>
-__global__ __launch_bounds__(1024) void enr_tile_reduce_kernel(const T* __restrict__ part,
-                                                               const int32_t* __restrict__ fn_pptr,
-                                                               const int32_t* __restrict__ fn_poff, int ncr,
-                                                               T* __restrict__ wp) {
+__global__ __launch_bounds__(1024) void enr_tile_reduce_kernel(KBatch<T> kb, const int32_t* __restrict__ fn_pptr,
+                                                               const int32_t* __restrict__ fn_poff) {
   __shared__ T red[16][64];
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int ncr = P.ncr;
+  if ((int)blockIdx.y * 64 >= ncr) return;
+  const T* __restrict__ part = P.part;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int nu = blockIdx.x;
   const int j = blockIdx.y * 64 + lane;
@@ -532,133 +485,35 @@ __global__ __launch_bounds__(1024) void enr_tile_reduce_kernel(const T* __restri
     if (grp < st) red[grp][lane] += red[grp + st][lane];
     __syncthreads();
   }
-  if (grp == 0 && j < ncr) wp[(int64_t)nu * ncr + j] = red[0][lane];
+  if (grp == 0 && j < ncr) P.wp[(int64_t)nu * ncr + j] = red[0][lane];
 }
 
-// Partial transposed enrichment product per row chunk of an atom block:
-//   part[c][f][v] = sum_{r in chunk} conj((m^-1/2 H^co)[r, f]) x[row_r][v]
-// Workgroup = RG row groups x NVB vector lanes; the row groups are reduced in LDS.
+// Small dense products on the enrichment rows (n = n_enr; complex interleaved when
+// CPLX), 16x16 output tile per workgroup, LDS-staged K tiles.
+//   mode 0: zo = S x^O       mode 1: wp += H^oo zo
+//   mode 2: out^O = alpha (S wp - c x^O) - beta prev^O
 template <typename T, bool CPLX>
-__global__ __launch_bounds__(512) void enr_partial_kernel(
-    const T* __restrict__ x, int64_t ldx, int nv, int nvb, const int32_t* __restrict__ chunk_blk,
-    const int64_t* __restrict__ chunk_r0, const int64_t* __restrict__ chunk_r1, const int32_t* __restrict__ blk_nf,
-    const int64_t* __restrict__ blk_rptr, const int32_t* __restrict__ rows, const T* __restrict__ hv, int FMAX,
-    T* __restrict__ part, int ncr) {
-  constexpr int FM = 8;
-  constexpr int E = CPLX ? 2 : 1;
-  extern __shared__ unsigned char smem_raw[];
-  T* red = reinterpret_cast<T*>(smem_raw);  // [RG][FMAX][nvb][E]
-  const int tx = threadIdx.x % nvb, ty = threadIdx.x / nvb;
-  const int RG = blockDim.x / nvb;
-  const int c = blockIdx.x;
-  const int vv = blockIdx.y * nvb + tx;
-  const bool active = ty < RG && vv < nv;
-  const int b = chunk_blk[c];
-  const int nf = blk_nf[b];
-  const int64_t base = blk_rptr[b];
-  T ar[FM], ai[FM];
-#pragma unroll
-  for (int f = 0; f < FM; ++f) ar[f] = ai[f] = 0;
-  if (active) {
-    const int64_t r1 = chunk_r1[c];
-#pragma unroll 4
-    for (int64_t r = chunk_r0[c] + ty; r < r1; r += RG) {
-      const int64_t g = rows[base + r];
-      const T* h = hv + (base + r) * FMAX * E;
-      if constexpr (!CPLX) {
-        const T z = x[g * ldx + vv];
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-          if (f < nf) ar[f] += h[f] * z;
-      } else {
-        const T* px = x + g * ldx + 2 * vv;
-        const C2<T> z{px[0], px[1]};
-#pragma unroll
-        for (int f = 0; f < FM; ++f)
-          if (f < nf) {
-            const C2<T> t = cjmul(C2<T>{h[2 * f], h[2 * f + 1]}, z);
-            ar[f] += t.r;
-            ai[f] += t.i;
-          }
-      }
-    }
-  }
-  if (ty < RG) {
-    for (int f = 0; f < nf; ++f) {
-      red[((ty * FMAX + f) * nvb + tx) * E] = ar[f];
-      if (CPLX) red[((ty * FMAX + f) * nvb + tx) * E + (E - 1)] = ai[f];
-    }
-  }
-  __syncthreads();
-  if (ty == 0 && vv < nv) {
-    for (int f = 0; f < nf; ++f) {
-      T sr = 0, si = 0;
-      for (int g2 = 0; g2 < RG; ++g2) {
-        sr += red[((g2 * FMAX + f) * nvb + tx) * E];
-        if (CPLX) si += red[((g2 * FMAX + f) * nvb + tx) * E + (E - 1)];
-      }
-      part[((int64_t)c * FMAX + f) * ncr + E * vv] = sr;
-      if (CPLX) part[((int64_t)c * FMAX + f) * ncr + E * vv + 1] = si;
-    }
-  }
-}
-
-// W'[nu][j] = sum over the chunks of nu's block of part, in a fixed order.
-// Workgroup per (nu, 64 real columns): 16 groups of 64 lanes each sum a strided
-// subset of the chunks, then a fixed LDS tree combines the groups.
-template <typename T>
-__global__ __launch_bounds__(1024) void enr_reduce_kernel(const T* __restrict__ part,
-                                                          const int32_t* __restrict__ fn_blk,
-                                                          const int32_t* __restrict__ blk_fn0,
-                                                          const int32_t* __restrict__ blk_chunk0, int FMAX, int nO,
-                                                          int ncr, T* __restrict__ wp) {
-  __shared__ T red[16][64];
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int nu = blockIdx.x;
-  const int j = blockIdx.y * 64 + lane;
-  const int b = fn_blk[nu];
-  const int f = nu - blk_fn0[b];
-  const int c0 = blk_chunk0[b], c1 = blk_chunk0[b + 1];
-  T s0 = 0, s1 = 0;
-  if (j < ncr) {
-    int c = c0 + grp;
-    for (; c + 16 < c1; c += 32) {
-      s0 += part[((int64_t)c * FMAX + f) * ncr + j];
-      s1 += part[((int64_t)(c + 16) * FMAX + f) * ncr + j];
-    }
-    if (c < c1) s0 += part[((int64_t)c * FMAX + f) * ncr + j];
-  }
-  red[grp][lane] = s0 + s1;
-  __syncthreads();
-  for (int st = 8; st > 0; st >>= 1) {
-    if (grp < st) red[grp][lane] += red[grp + st][lane];
-    __syncthreads();
-  }
-  if (grp == 0 && j < ncr) wp[(int64_t)nu * ncr + j] = red[0][lane];
-}
-
-// Small dense products on the enrichment rows (n x k times k x m, complex
-// interleaved when CPLX), 16x16 output tile per workgroup, LDS-staged K tiles.
-//   mode 0: C = A B        mode 1: C += A B
-//   mode 2: recurrence epilogue  out[N+i][j] = alpha (A B - c x[N+i][j]) - beta prev[N+i][j]
-template <typename T, bool CPLX>
-__global__ __launch_bounds__(256) void small_gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, int64_t ldb,
-                                                         T* __restrict__ C, int64_t ldc, int n, int k, int m, int mode,
-                                                         const T* __restrict__ x, const T* __restrict__ prev,
-                                                         int64_t ldx, int64_t ldo, T alpha, T cc, T beta) {
+__global__ __launch_bounds__(256) void small_gemm_kernel(KBatch<T> kb, int mode, int64_t N, int n) {
   constexpr int E = CPLX ? 2 : 1;
   constexpr int TS = 16;
   __shared__ T As[TS][TS * E + 1];
   __shared__ T Bs[TS][TS * E + 1];
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int m = P.nv;
+  if ((int)blockIdx.x * TS >= m) return;
+  const int k = n;
+  const T* __restrict__ A = mode == 1 ? P.Hoo : P.S;
+  const T* __restrict__ B = mode == 0 ? P.x + N * P.ldx : (mode == 1 ? P.zo : P.wp);
+  const int64_t ldb = mode == 0 ? P.ldx : (int64_t)P.ncr;
   const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-  const int i = blockIdx.y * TS + ty;  // row of C
-  const int j = blockIdx.x * TS + tx;  // column of C (complex element)
+  const int i = blockIdx.y * TS + ty;   // row
+  const int jc = blockIdx.x * TS + tx;  // column (complex element)
   T sr = 0, si = 0;
   for (int k0 = 0; k0 < k; k0 += TS) {
     for (int e = 0; e < E; ++e) {
-      const int ka = k0 + tx, kb = k0 + ty;
+      const int ka = k0 + tx, kr = k0 + ty;
       As[ty][tx * E + e] = (i < n && ka < k) ? A[((int64_t)i * k + ka) * E + e] : T(0);
-      Bs[ty][tx * E + e] = (kb < k && j < m) ? B[(int64_t)kb * ldb + (int64_t)j * E + e] : T(0);
+      Bs[ty][tx * E + e] = (kr < k && jc < m) ? B[(int64_t)kr * ldb + (int64_t)jc * E + e] : T(0);
     }
     __syncthreads();
 #pragma unroll
@@ -673,22 +528,22 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(const T* __restrict__ A
     }
     __syncthreads();
   }
-  if (i >= n || j >= m) return;
+  if (i >= n || jc >= m) return;
   if (mode == 0) {
-    C[(int64_t)i * ldc + (int64_t)j * E] = sr;
-    if (CPLX) C[(int64_t)i * ldc + (int64_t)j * E + 1] = si;
+    P.zo[(int64_t)i * P.ncr + (int64_t)jc * E] = sr;
+    if (CPLX) P.zo[(int64_t)i * P.ncr + (int64_t)jc * E + 1] = si;
   } else if (mode == 1) {
-    C[(int64_t)i * ldc + (int64_t)j * E] += sr;
-    if (CPLX) C[(int64_t)i * ldc + (int64_t)j * E + 1] += si;
+    P.wp[(int64_t)i * P.ncr + (int64_t)jc * E] += sr;
+    if (CPLX) P.wp[(int64_t)i * P.ncr + (int64_t)jc * E + 1] += si;
   } else {
-    const int64_t ox = (int64_t)i * ldx + (int64_t)j * E, oo = (int64_t)i * ldo + (int64_t)j * E;
-    T r = alpha * (sr - cc * x[ox]);
-    if (beta != T(0)) r -= beta * prev[oo];
-    C[oo] = r;
+    const int64_t ox = (N + i) * P.ldx + (int64_t)jc * E, oo = (N + i) * P.ldo + (int64_t)jc * E;
+    T r = P.alpha * (sr - P.c * P.x[ox]);
+    if (P.beta != T(0)) r -= P.beta * P.prev[oo];
+    P.out[oo] = r;
     if (CPLX) {
-      T r2 = alpha * (si - cc * x[ox + 1]);
-      if (beta != T(0)) r2 -= beta * prev[oo + 1];
-      C[oo + 1] = r2;
+      T r2 = P.alpha * (si - P.c * P.x[ox + 1]);
+      if (P.beta != T(0)) r2 -= P.beta * P.prev[oo + 1];
+      P.out[oo + 1] = r2;
     }
   }
 }
@@ -874,36 +729,6 @@ int pick_cw(int ncr) {
   return 8;
 }
 
-template <typename T, int P1, int CW, bool CPLX>
-void launch_cell_cw(const oefe_op_s* op, const T* x, int64_t ldx, int ncr, T* yc, int ldc, const T* wv,
-                    const CellCoef<T>& cf, const Phase3<T>& ph, hipStream_t s) {
-  constexpr int CPT = 64 / CW;
-  dim3 grid((unsigned)cdiv(op->n_cells, CPT), (unsigned)cdiv(ncr, CW));
-  hipLaunchKernelGGL((fe_cell_kernel<T, P1, CW, CPLX>), grid, dim3(64 * P1), 0, s, x, ldx, ncr, yc, ldc, wv, cf,
-                     op->nc, op->p, op->n, op->n_cells, ph);
-}
-
-template <typename T, int P1, bool CPLX>
-void launch_cell_p(const oefe_op_s* op, const T* x, int64_t ldx, int ncr, T* yc, int ldc, const T* wv,
-                   const CellCoef<T>& cf, const Phase3<T>& ph, hipStream_t s) {
-  switch (pick_cw(ncr)) {
-    case 64: launch_cell_cw<T, P1, 64, CPLX>(op, x, ldx, ncr, yc, ldc, wv, cf, ph, s); break;
-    case 32: launch_cell_cw<T, P1, 32, CPLX>(op, x, ldx, ncr, yc, ldc, wv, cf, ph, s); break;
-    case 16: launch_cell_cw<T, P1, 16, CPLX>(op, x, ldx, ncr, yc, ldc, wv, cf, ph, s); break;
-    default: launch_cell_cw<T, P1, 8, CPLX>(op, x, ldx, ncr, yc, ldc, wv, cf, ph, s); break;
-  }
-}
-
-template <typename T, bool CPLX>
-void launch_cell(const oefe_op_s* op, const T* x, int64_t ldx, int ncr, T* yc, int ldc, const T* wv,
-                 const CellCoef<T>& cf, const Phase3<T>& ph, hipStream_t s) {
-  switch (op->P1) {
-    case 3: launch_cell_p<T, 3, CPLX>(op, x, ldx, ncr, yc, ldc, wv, cf, ph, s); break;
-    case 4: launch_cell_p<T, 4, CPLX>(op, x, ldx, ncr, yc, ldc, wv, cf, ph, s); break;
-    default: launch_cell_p<T, 5, CPLX>(op, x, ldx, ncr, yc, ldc, wv, cf, ph, s); break;
-  }
-}
-
 template <typename T>
 const CellCoef<T>& coef(const oefe_op_s* op);
 template <>
@@ -913,86 +738,138 @@ const CellCoef<float>& coef<float>(const oefe_op_s* op) { return op->cf; }
 
 template <typename T>
 struct DevPtrs {
-  const T *WV, *hv, *S, *Hoo, *lambda, *frv, *tv;
+  const T *WV, *S, *Hoo, *lambda, *tv;
 };
 template <typename T>
 DevPtrs<T> devptrs(const oefe_op_s* op);
 template <>
 DevPtrs<double> devptrs<double>(const oefe_op_s* op) {
-  return {op->d.WV, op->d.hv, op->d.S, op->d.Hoo, op->d.lambda, op->d.fr_val, op->d.tile_val};
+  return {op->d.WV, op->d.S, op->d.Hoo, op->d.lambda, op->d.tile_val};
 }
 template <>
 DevPtrs<float> devptrs<float>(const oefe_op_s* op) {
-  return {op->d.WVf, op->d.hvf, op->d.Sf, op->d.Hoof, op->d.lambdaf, op->d.fr_valf, op->d.tile_valf};
+  return {op->d.WVf, op->d.Sf, op->d.Hoof, op->d.lambdaf, op->d.tile_valf};
 }
 
-template <typename T, bool CPLX>
-void small_gemm(const T* A, const T* B, int64_t ldb, T* C, int64_t ldc, int n, int k, int m, int mode, const T* x,
-                const T* prev, int64_t ldx, int64_t ldo, double alpha, double c, double beta, hipStream_t s) {
-  dim3 grid((unsigned)cdiv(m, 16), (unsigned)cdiv(n, 16));
-  hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), grid, dim3(256), 0, s, A, B, ldb, C, ldc, n, k, m, mode, x, prev,
-                     ldx, ldo, (T)alpha, (T)c, (T)beta);
+template <typename T, int P1, int CW, bool CPLX>
+void launch_cell_cw(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, hipStream_t s) {
+  constexpr int CPT = 64 / CW;
+  dim3 grid((unsigned)cdiv(op->n_cells, CPT), (unsigned)cdiv(max_ncr, CW), (unsigned)kb.nk);
+  hipLaunchKernelGGL((fe_cell_kernel<T, P1, CW, CPLX>), grid, dim3(64 * P1), 0, s, kb, devptrs<T>(op).WV,
+                     coef<T>(op), op->nc, op->p, op->n, op->n_cells);
 }
 
-template <typename T, bool CPLX>
-int apply_step_impl(const oefe_op_s* op, const T* x, int64_t ld, const T* prev, T* out, int64_t ldout, int nv,
-                    double alpha, double c, double beta, const StepWork& w, hipStream_t s) {
-  const DevPtrs<T> dp = devptrs<T>(op);
-  const int64_t ldx = CPLX ? 2 * ld : ld;
-  const int64_t ldo = CPLX ? 2 * ldout : ldout;
-  const int ncr = CPLX ? 2 * nv : nv;
-  if (op->diagonal) {
-    const int64_t tot = op->N * nv;
-    hipLaunchKernelGGL((diag_step_kernel<T>), dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, dp.lambda, x, prev,
-                       out, ldx, ldo, nv, op->N, (T)alpha, (T)c, (T)beta);
-    return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
+template <typename T, int P1, bool CPLX>
+void launch_cell_p(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, hipStream_t s) {
+  switch (cw) {
+    case 64: launch_cell_cw<T, P1, 64, CPLX>(op, kb, max_ncr, s); break;
+    case 32: launch_cell_cw<T, P1, 32, CPLX>(op, kb, max_ncr, s); break;
+    case 16: launch_cell_cw<T, P1, 16, CPLX>(op, kb, max_ncr, s); break;
+    default: launch_cell_cw<T, P1, 8, CPLX>(op, kb, max_ncr, s); break;
   }
+}
+
+template <typename T, bool CPLX>
+void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, hipStream_t s) {
+  switch (op->P1) {
+    case 3: launch_cell_p<T, 3, CPLX>(op, kb, max_ncr, cw, s); break;
+    case 4: launch_cell_p<T, 4, CPLX>(op, kb, max_ncr, cw, s); break;
+    default: launch_cell_p<T, 5, CPLX>(op, kb, max_ncr, cw, s); break;
+  }
+}
+
+// Steps of several operators sharing one mesh and enrichment layout, in lockstep.
+template <typename T, bool CPLX>
+int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipStream_t s) {
+  const oefe_op_s* op = ops[0];
+  int max_ncr = 0, max_nv = 0;
+  for (int q = 0; q < kb.nk; ++q) {
+    max_ncr = std::max(max_ncr, kb.k[q].ncr);
+    max_nv = std::max(max_nv, kb.k[q].nv);
+  }
+  const unsigned nk = (unsigned)kb.nk;
+  const int nO = op->n_enr;
+  if (nO > 0)
+    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
+                       dim3(256), 0, s, kb, 0, op->N, nO);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (op->timer_on && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess)
+    (void)hipEventRecord(ev0, s);
+  launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw > 0 ? op->tune_cw : pick_cw(max_ncr), s);
+  if (ev1) {
+    (void)hipEventRecord(ev1, s);
+    op->timer_events.emplace_back(ev0, ev1);
+  }
+  // column block of the tiled kernels: all real columns up to cbm, else near-equal blocks
+  const int cbm = op->tune_cb > 0 ? op->tune_cb : 128;
+  int CB = max_ncr <= cbm ? max_ncr : (int)cdiv(max_ncr, cdiv(max_ncr, cbm));
+  CB = (int)cdiv(CB, 8) * 8;
+  const int ncb = (int)cdiv(max_ncr, CB);
+  if (nO > 0) {
+    const size_t lds = (size_t)(16 * CB + 16 * op->tile_fpmax * (CPLX ? 2 : 1)) * sizeof(T);
+    hipLaunchKernelGGL((enr_tile_partial_kernel<T, CPLX>), dim3((unsigned)op->n_tiles, (unsigned)ncb, nk),
+                       dim3(4 * CB), lds, s, kb, CB, op->d.tile_fptr, (int)op->N);
+  }
+  {
+    const size_t lds = (size_t)(kTileRows * 16 * (CPLX ? 2 : 1) + 16 * CB) * sizeof(T);
+    hipLaunchKernelGGL((fe_node_tile_kernel<T, CPLX>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb, nk),
+                       dim3(4 * CB), lds, s, kb, CB, op->nc, op->p, op->n, op->P1, coef<T>(op), op->d.tile_fptr,
+                       op->d.tile_fns, (int)op->N);
+  }
+  if (nO > 0) {
+    hipLaunchKernelGGL((enr_tile_reduce_kernel<T>), dim3((unsigned)nO, (unsigned)cdiv(max_ncr, 64), nk), dim3(1024),
+                       0, s, kb, op->d.fn_pptr, op->d.fn_poff);
+    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
+                       dim3(256), 0, s, kb, 1, op->N, nO);
+    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
+                       dim3(256), 0, s, kb, 2, op->N, nO);
+  }
+  return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
+}
+
+template <typename T>
+KP<T> make_kp(const oefe_op_s* op, const T* x, int64_t ld, const T* prev, T* out, int64_t ldout, int nv,
+              double alpha, double c, double beta, const StepWork& w) {
+  const bool cx = op->cplx;
+  const DevPtrs<T> dp = devptrs<T>(op);
+  KP<T> P{};
+  P.x = x;
+  P.prev = prev;
+  P.out = out;
+  P.ldx = cx ? 2 * ld : ld;
+  P.ldo = cx ? 2 * ldout : ldout;
+  P.nv = nv;
+  P.ncr = cx ? 2 * nv : nv;
+  P.ycell = (T*)w.ycell;
+  P.ldc = w.ldc;
+  P.zo = (T*)w.zo;
+  P.part = (T*)w.part;
+  P.wp = (T*)w.wp;
+  P.tv = dp.tv;
+  P.S = dp.S;
+  P.Hoo = dp.Hoo;
+  P.alpha = (T)alpha;
+  P.c = (T)c;
+  P.beta = (T)beta;
+  for (int d = 0; d < 3; ++d) {
+    P.ph.re[d] = (T)op->phase[d][0];
+    P.ph.im[d] = (T)op->phase[d][1];
+  }
+  return P;
+}
+
+template <typename T, int P1, bool CPLX>
+void launch_density(const oefe_op_s* op, const T* x, int64_t ldx, int ncr, const double* f, const T* zo, double* dens,
+                    hipStream_t s) {
   Phase3<T> ph;
   for (int d = 0; d < 3; ++d) {
     ph.re[d] = (T)op->phase[d][0];
     ph.im[d] = (T)op->phase[d][1];
   }
-  const CellCoef<T>& cf = coef<T>(op);
-  const int nO = op->n_enr;
-  T* zo = (T*)w.zo;
-  T* part = (T*)w.part;
-  T* wp = (T*)w.wp;
-  // Z^O = S X^O
-  if (nO > 0)
-    small_gemm<T, CPLX>(dp.S, x + op->N * ldx, ldx, zo, ncr, nO, nO, nv, 0, nullptr, nullptr, 0, 0, 0, 0, 0, s);
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (op->timer_on && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess)
-    (void)hipEventRecord(ev0, s);
-  launch_cell<T, CPLX>(op, x, ldx, ncr, (T*)w.ycell, w.ldc, dp.WV, cf, ph, s);
-  if (ev1) {
-    (void)hipEventRecord(ev1, s);
-    op->timer_events.emplace_back(ev0, ev1);
-  }
-  // column block of the tiled kernels: all real columns up to 128, else near-equal blocks
-  int CB = ncr <= 128 ? ncr : (int)cdiv(ncr, cdiv(ncr, 128));
-  CB = (int)cdiv(CB, 8) * 8;
-  const int ncb = (int)cdiv(ncr, CB);
-  if (nO > 0) {
-    const size_t lds = (size_t)(16 * CB + 16 * op->tile_fpmax * (CPLX ? 2 : 1)) * sizeof(T);
-    hipLaunchKernelGGL((enr_tile_partial_kernel<T, CPLX>), dim3((unsigned)op->n_tiles, (unsigned)ncb), dim3(4 * CB),
-                       lds, s, x, ldx, ncr, CB, op->d.tile_fptr, dp.tv, part, (int)op->N);
-  }
-  {
-    const size_t lds = (size_t)(kTileRows * 16 * (CPLX ? 2 : 1) + 16 * CB) * sizeof(T);
-    hipLaunchKernelGGL((fe_node_tile_kernel<T, CPLX>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb),
-                       dim3(4 * CB), lds, s, (const T*)w.ycell, w.ldc, x, prev, out, ldx, ldo, ncr, CB, op->nc,
-                       op->p, op->n, op->P1, cf, ph, zo, op->d.tile_fptr, op->d.tile_fns, dp.tv, (T)alpha, (T)c,
-                       (T)beta, (int)op->N);
-  }
-  if (nO > 0) {
-    hipLaunchKernelGGL((enr_tile_reduce_kernel<T>), dim3((unsigned)nO, (unsigned)cdiv(ncr, 64)), dim3(1024), 0, s,
-                       part, op->d.fn_pptr, op->d.fn_poff, ncr, wp);
-    // W' += H^oo Z^O ;  enrichment rows: alpha (S W' - c x) - beta prev
-    small_gemm<T, CPLX>(dp.Hoo, zo, ncr, wp, ncr, nO, nO, nv, 1, nullptr, nullptr, 0, 0, 0, 0, 0, s);
-    small_gemm<T, CPLX>(dp.S, wp, ncr, out + op->N * ldo, ldo, nO, nO, nv, 2, x + op->N * ldx,
-                        prev ? prev + op->N * ldo : nullptr, ldx, ldo, alpha, c, beta, s);
-  }
-  return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
+  dim3 grid((unsigned)op->n_cells, (unsigned)cdiv(ncr, 64));
+  hipLaunchKernelGGL((density_kernel<T, P1, CPLX>), grid, dim3(64 * P1), 0, s, x, ldx, ncr, f, zo, coef<T>(op),
+                     op->nc, op->p, op->n, ph, op->d.cph_ptr, op->d.cph_blk, op->d.cph_off, op->d.blk_fn0,
+                     op->d.blk_nf, op->d.phi, op->FMAX, op->n_enr, dens, op->n_cells);
 }
 
 }  // namespace
@@ -1004,9 +881,9 @@ size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, i
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t bytes = 0;
   if (!op->diagonal) bytes += al((size_t)op->n_cells * op->nd * ldc * elem_bytes);
-  bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                      // zo
+  bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                 // zo
   bytes += al((size_t)std::max<int64_t>(op->tile_slots, 1) * ncr * elem_bytes);  // part
-  bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                      // wp
+  bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                 // wp
   return bytes;
 }
 
@@ -1034,8 +911,19 @@ template <typename T>
 int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
                double alpha, double c, double beta, const StepWork& w, hipStream_t s) {
   if (bf16) return OEFE_EUNSUPPORTED;
-  if (op->cplx) return apply_step_impl<T, true>(op, x, ld, prev, out, ldo, nv, alpha, c, beta, w, s);
-  return apply_step_impl<T, false>(op, x, ld, prev, out, ldo, nv, alpha, c, beta, w, s);
+  if (op->diagonal) {
+    const DevPtrs<T> dp = devptrs<T>(op);
+    const int64_t tot = op->N * nv;
+    hipLaunchKernelGGL((diag_step_kernel<T>), dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, dp.lambda, x, prev,
+                       out, ld, ldo, nv, op->N, (T)alpha, (T)c, (T)beta);
+    return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
+  }
+  KBatch<T> kb{};
+  kb.nk = 1;
+  kb.k[0] = make_kp<T>(op, x, ld, prev, out, ldo, nv, alpha, c, beta, w);
+  const oefe_op_s* ops[1] = {op};
+  if (op->cplx) return apply_step_batch_impl<T, true>(ops, kb, s);
+  return apply_step_batch_impl<T, false>(ops, kb, s);
 }
 
 template int apply_step<double>(const oefe_op_s*, bool, const double*, int64_t, const double*, double*, int64_t, int,
@@ -1044,30 +932,50 @@ template int apply_step<float>(const oefe_op_s*, bool, const float*, int64_t, co
                                double, double, double, const StepWork&, hipStream_t);
 
 template <typename T>
+int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* const* x, const int64_t* ld,
+                     const T* const* prev, T* const* out, const int64_t* ldo, const int* nv, const double* alpha,
+                     const double* c, const double* beta, const StepWork* w, hipStream_t s) {
+  if (bf16) return OEFE_EUNSUPPORTED;
+  for (int q0 = 0; q0 < nk; q0 += KMAX) {
+    KBatch<T> kb{};
+    kb.nk = std::min(KMAX, nk - q0);
+    for (int q = 0; q < kb.nk; ++q)
+      kb.k[q] = make_kp<T>(ops[q0 + q], x[q0 + q], ld[q0 + q], prev[q0 + q], out[q0 + q], ldo[q0 + q], nv[q0 + q],
+                           alpha[q0 + q], c[q0 + q], beta[q0 + q], w[q0 + q]);
+    const int rc = ops[0]->cplx ? apply_step_batch_impl<T, true>(ops + q0, kb, s)
+                                : apply_step_batch_impl<T, false>(ops + q0, kb, s);
+    if (rc) return rc;
+  }
+  return OEFE_OK;
+}
+
+template int apply_step_batch<double>(const oefe_op_s* const*, int, bool, const double* const*, const int64_t*,
+                                      const double* const*, double* const*, const int64_t*, const int*, const double*,
+                                      const double*, const double*, const StepWork*, hipStream_t);
+template int apply_step_batch<float>(const oefe_op_s* const*, int, bool, const float* const*, const int64_t*,
+                                     const float* const*, float* const*, const int64_t*, const int*, const double*,
+                                     const double*, const double*, const StepWork*, hipStream_t);
+
+template <typename T>
 int zo_only(const oefe_op_s* op, const T* x, int64_t ld, int nv, T* zo, int ncr, hipStream_t s) {
   if (op->n_enr == 0) return OEFE_OK;
-  const DevPtrs<T> dp = devptrs<T>(op);
-  const int nO = op->n_enr;
+  StepWork w{};
+  w.zo = zo;
+  KBatch<T> kb{};
+  kb.nk = 1;
+  kb.k[0] = make_kp<T>(op, x, ld, nullptr, nullptr, ld, nv, 0, 0, 0, w);
+  kb.k[0].ncr = ncr;
   if (op->cplx)
-    small_gemm<T, true>(dp.S, x + op->N * 2 * ld, 2 * ld, zo, ncr, nO, nO, nv, 0, nullptr, nullptr, 0, 0, 0, 0, 0, s);
+    hipLaunchKernelGGL((small_gemm_kernel<T, true>), dim3((unsigned)cdiv(nv, 16), (unsigned)cdiv(op->n_enr, 16), 1),
+                       dim3(256), 0, s, kb, 0, op->N, op->n_enr);
   else
-    small_gemm<T, false>(dp.S, x + op->N * ld, ld, zo, ncr, nO, nO, nv, 0, nullptr, nullptr, 0, 0, 0, 0, 0, s);
+    hipLaunchKernelGGL((small_gemm_kernel<T, false>), dim3((unsigned)cdiv(nv, 16), (unsigned)cdiv(op->n_enr, 16), 1),
+                       dim3(256), 0, s, kb, 0, op->N, op->n_enr);
   return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
 }
 
-template <typename T, int P1, bool CPLX>
-void launch_density(const oefe_op_s* op, const T* x, int64_t ldx, int ncr, const double* f, const T* zo, double* dens,
-                    hipStream_t s) {
-  Phase3<T> ph;
-  for (int d = 0; d < 3; ++d) {
-    ph.re[d] = (T)op->phase[d][0];
-    ph.im[d] = (T)op->phase[d][1];
-  }
-  dim3 grid((unsigned)op->n_cells, (unsigned)cdiv(ncr, 64));
-  hipLaunchKernelGGL((density_kernel<T, P1, CPLX>), grid, dim3(64 * P1), 0, s, x, ldx, ncr, f, zo, coef<T>(op),
-                     op->nc, op->p, op->n, ph, op->d.cph_ptr, op->d.cph_blk, op->d.cph_off, op->d.blk_fn0,
-                     op->d.blk_nf, op->d.phi, op->FMAX, op->n_enr, dens, op->n_cells);
-}
+template int zo_only<double>(const oefe_op_s*, const double*, int64_t, int, double*, int, hipStream_t);
+template int zo_only<float>(const oefe_op_s*, const float*, int64_t, int, float*, int, hipStream_t);
 
 template <typename T>
 int density_partial(const oefe_op_s* op, const T* x, int64_t ld, int nv, const double* f, const T* zo, int ncr,
@@ -1092,8 +1000,6 @@ int density_final(const oefe_op_s* op, const double* dens, int nblk, double* dEd
   return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
 }
 
-template int zo_only<double>(const oefe_op_s*, const double*, int64_t, int, double*, int, hipStream_t);
-template int zo_only<float>(const oefe_op_s*, const float*, int64_t, int, float*, int, hipStream_t);
 template int density_partial<double>(const oefe_op_s*, const double*, int64_t, int, const double*, const double*, int,
                                      double*, hipStream_t);
 template int density_partial<float>(const oefe_op_s*, const float*, int64_t, int, const double*, const float*, int,

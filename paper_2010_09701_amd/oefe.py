@@ -67,6 +67,9 @@ def _load():
         "ham_apply": ([vp, i32, vp, vp, i64, i32, vp, vp], i32),
         "chebyshev_filter": ([vp, i32, vp, i64, i32, i32, dbl, dbl, dbl, vp, vp], i32),
         "chebyshev_filter_mixed": ([vp, i32, vp, i64, i32, i32, dbl, dbl, dbl, vp, vp], i32),
+        "chebyshev_filter_batched": ([i32, vp, i32, vp, vp, vp, i32, vp, vp, vp], i32),
+        "oefe_batched_work_size": ([i32, vp, i32, vp], ctypes.c_size_t),
+        "oefe_set_launch_shape": ([vp, i32, i32], i32),
         "lanczos_bounds": ([vp, i32, vp, vp, vp, vp], i32),
         "cholgs": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
@@ -88,7 +91,8 @@ _lib = _load()
 EXPORTED = [
     "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
-    "chebyshev_filter_mixed", "lanczos_bounds", "cholgs", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
+    "chebyshev_filter_mixed", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
+    "lanczos_bounds", "cholgs", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_strerror", "oefe_last_error",
 ]
 
@@ -263,6 +267,41 @@ def chebyshev_filter_mixed(op: Operator, X: torch.Tensor, m: int, a: float, b: f
     _check(_lib.chebyshev_filter_mixed(op.handle, prec, _ptr(X), ld, nv, int(m), float(a), float(b), float(a0),
                                        _ptr(w), _stream()), "chebyshev_filter_mixed")
     return X
+
+
+def chebyshev_filter_batched(ops, Xs, m: int, abc, bf16: bool = False):
+    """Filter several blocks (one per operator of the same mesh, e.g. k-points) in lockstep, in place.
+
+    abc: sequence of (a, b, a0) per operator.  All blocks share one dtype.
+    """
+    nk = len(ops)
+    if nk != len(Xs) or nk != len(abc):
+        raise ValueError("ops, Xs and abc must have the same length")
+    prec = _prec(Xs[0], bf16)
+    lds, nvs = [], []
+    for op, X in zip(ops, Xs):
+        if X.dtype != Xs[0].dtype:
+            raise TypeError("all blocks must share one dtype")
+        ld, nv = _block(X, op.n_tot)
+        lds.append(ld)
+        nvs.append(nv)
+    H = (ctypes.c_void_p * nk)(*[o.handle.value if isinstance(o.handle, ctypes.c_void_p) else o.handle for o in ops])
+    P = (ctypes.c_void_p * nk)(*[X.data_ptr() for X in Xs])
+    LD = (ctypes.c_int64 * nk)(*lds)
+    NV = (ctypes.c_int32 * nk)(*nvs)
+    ABC = (ctypes.c_double * (3 * nk))(*[float(v) for t in abc for v in t])
+    need = int(_lib.oefe_batched_work_size(nk, H, prec, NV))
+    w = ops[0]._work.get("batched")
+    if w is None or w.numel() < need:
+        w = torch.empty(need, dtype=torch.uint8, device="cuda")
+        ops[0]._work["batched"] = w
+    _check(_lib.chebyshev_filter_batched(nk, H, prec, P, LD, NV, int(m), ABC, _ptr(w), _stream()),
+           "chebyshev_filter_batched")
+    return Xs
+
+
+def set_launch_shape(op: Operator, cw: int = 0, cb: int = 0):
+    _check(_lib.oefe_set_launch_shape(op.handle, int(cw), int(cb)), "oefe_set_launch_shape")
 
 
 def lanczos_bounds(op: Operator, v0: torch.Tensor, k: int = 10) -> Tuple[float, float]:
