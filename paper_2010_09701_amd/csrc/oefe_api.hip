@@ -302,6 +302,8 @@ int upload_operator(oefe_op_s* op, std::string& err) {
       std::vector<int32_t> ff(fpp.begin(), fpp.end() - 1);
       for (size_t q = 0; q < tfns.size(); ++q)
         if (tfns[q] >= 0) fpo[ff[tfns[q]]++] = (int32_t)q;
+      op->fn_smax = 0;
+      for (int f = 0; f < op->n_enr; ++f) op->fn_smax = std::max(op->fn_smax, fpp[f + 1] - fpp[f]);
       if ((rc = dput(&op->d.tile_fptr, tfptr, err))) return rc;
       if ((rc = dput(&op->d.tile_fns, tfns, err))) return rc;
       if ((rc = dput(&op->d.fn_pptr, fpp, err))) return rc;

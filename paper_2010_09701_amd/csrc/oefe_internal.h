@@ -132,6 +132,7 @@ struct oefe_op_s {
   std::vector<int64_t> csr_to_tile;           // CSR entry -> index into tile_val
   int64_t n_tiles = 0, tile_slots = 0;        // tiles, total padded (tile, function) slots
   int tile_fpmax = 0;
+  int fn_smax = 0;  // most tile partials of one enrichment function
   oefe::DeviceArrays d;
   // launch shape overrides (autotuner): cell-kernel column width, node/partial column block
   int tune_cw = 0, tune_cb = 0;

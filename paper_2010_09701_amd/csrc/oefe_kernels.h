@@ -10,7 +10,8 @@ struct StepWork {
   void* ycell;    // [n_cells * nd * ldc] real columns, element T
   int ldc;        // real columns per cell node (padded)
   void* zo;       // [n_enr * ncr] S X^O
-  void* part;     // [n_chunks * FMAX * ncr] partial H^co^* Z^C
+  void* part;     // [tile_slots * ncr] per-tile partials of (m^-1/2 H^co)^* X
+  void* part2;    // [n_enr * n_rchunks * ncr] partials folded over chunks of tiles
   void* wp;       // [n_enr * ncr]
 };
 

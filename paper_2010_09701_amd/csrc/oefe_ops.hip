@@ -54,6 +54,8 @@ struct KP {
   int ldc;
   T* zo;
   T* part;
+  T* part2;
+  int nch;  // chunks per function in part2
   T* wp;
   const T* tv;
   const T* S;
@@ -278,219 +280,321 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, const T*
       y[ay * P1 + ax] += s;
     }
   }
-  // 10. store plane az = w of y_e
+  // 10. store plane az = w of y_e into the node-slot grid: local node a of cell c
+  //     goes to slot (c (p+1) + a + 1) mod S per dimension, S = nc (p+1)
   if (valid) {
-    T* out = Yc + (e * (NP * P1) + w * NP) * (int64_t)ldc + j;
+    const int S = nc * P1;
+    int sz = cz * P1 + w + 1;
+    if (sz >= S) sz -= S;
 #pragma unroll
-    for (int a = 0; a < NP; ++a) out[(int64_t)a * ldc] = y[a];
+    for (int ay = 0; ay < P1; ++ay) {
+      int sy = cy * P1 + ay + 1;
+      if (sy >= S) sy -= S;
+      const int64_t rowyz = (int64_t)S * (sy + (int64_t)S * sz);
+#pragma unroll
+      for (int ax = 0; ax < P1; ++ax) {
+        int sx = cx * P1 + ax + 1;
+        if (sx >= S) sx -= S;
+        Yc[(rowyz + sx) * ldc + j] = y[ay * P1 + ax];
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Tiled node kernel: FE rows.  Workgroup = one tile of kTileRows consecutive FE
-// rows x CB real columns, 4 row groups.  For each output (row g, column j):
-//   fixed-order sum of the (up to 8) cell results sharing g, times m_g^-1/2,
-//   + sum_f Ht[g][f] Z^O[fn_f][j]  (dense tile block of m^-1/2 H^co, LDS-staged
-//     16 functions at a time together with the matching Z^O rows),
-//   then the recurrence epilogue alpha (y - c x) - beta prev.
+// Node kernel: FE rows, one workgroup (4 waves) per tile of kTileRows consecutive
+// FE rows x 16 NB real columns.  Three parts, the two dense ones on the matrix cores
+// (16x16x4 MFMA, float64 or float32):
+//   en   = Ht_t Z^O                 (Ht_t: the tile's dense block of m^-1/2 H^co)
+//   part = Ht_t^* X_t               -> per-tile partial of W' (reduced later)
+//   out  = alpha (m^-1/2 sum_slots(Y) + en - c x) - beta prev
+// sum_slots adds, in a fixed order, the (up to 8) cell results stored for the node
+// in the node-slot grid (no atomics).  Complex columns are interleaved (re, im);
+// a complex product is two real MFMA passes over the real and imaginary parts of
+// Ht with the matching (swapped, signed) columns of Z^O or X.
 // ---------------------------------------------------------------------------
-template <typename T, bool CPLX>
-__global__ __launch_bounds__(512) void fe_node_tile_kernel(KBatch<T> kb, int CB, int nc, int p, int n, int P1,
-                                                           CellCoef<T> cf, const int32_t* __restrict__ tile_fptr,
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double V4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V4 op(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16x16 result held by lane l in element v (column l % 16)
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V4 op(float a, float b, V4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+constexpr int kNodeNBMax = 8;  // 16-column blocks per node workgroup (128 real columns)
+
+template <typename T, int NB, bool CPLX>
+__global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<T> kb, int nc, int p, int n, int P1, CellCoef<T> cf,
+                                                           const int32_t* __restrict__ tile_fptr,
                                                            const int32_t* __restrict__ tile_fns, int N) {
-  constexpr int TR = kTileRows, RG = 4, RPT = TR / RG, JC = 16;
-  constexpr int E = CPLX ? 2 : 1;
-  extern __shared__ unsigned char smem_raw[];
-  T* Hs = reinterpret_cast<T*>(smem_raw);  // [TR][JC][E]
-  T* zs = Hs + TR * JC * E;                // [JC][CB]
+  using M = Mfma<T>;
+  using V4 = typename M::V4;
+  constexpr int TR = kTileRows, E = CPLX ? 2 : 1;
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
-  if ((int)blockIdx.y * CB >= ncr) return;
-  const int cl = threadIdx.x % CB, rg = threadIdx.x / CB;
+  const int cb0 = blockIdx.y * NB * 16;
+  if (cb0 >= ncr) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int t = blockIdx.x;
-  const int j = blockIdx.y * CB + cl;  // real column
-  // no enrichment: tile_fptr is null and the tile couples to no function
+  const int g0 = t * TR;
   const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
-  const T* tv = P.tv + (int64_t)f0 * TR * E;
-  const T* zo = P.zo;
-  T en[RPT];
+  const T* __restrict__ tv = P.tv + (int64_t)f0 * TR * E;  // [TR][FP][E]
+  const T* __restrict__ zo = P.zo;                         // [n_enr][ncr]
+  const T* __restrict__ x = P.x;
+  const int64_t ldx = P.ldx;
+  // Loads below are unconditional, from clamped in-bounds addresses, with the
+  // unwanted values replaced by selects, so that each batch is issued at once.
+  int colc[NB];
+  bool colok[NB];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) en[i] = 0;
-  for (int j0 = 0; j0 < FP; j0 += JC) {
-    const int jn = min(JC, FP - j0);
-    for (int q = threadIdx.x; q < TR * JC * E; q += blockDim.x) {
-      const int r = q / (JC * E), jj = (q / E) % JC, e = q % E;
-      Hs[q] = jj < jn ? tv[((int64_t)r * FP + j0 + jj) * E + e] : T(0);
+  for (int nb = 0; nb < NB; ++nb) {
+    const int col = cb0 + nb * 16 + li;
+    colok[nb] = col < ncr;
+    colc[nb] = colok[nb] ? col : ncr - 1;
+  }
+  // complex: the second real pass pairs Im(H) with the partner column, signed
+  const T sgn_en = (li & 1) ? T(1) : T(-1);
+
+  // ---- en = Ht_t Z^O: rows w*16 .. w*16+15 of the tile
+  V4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = V4{0, 0, 0, 0};
+  {
+    constexpr int KCE = CPLX ? 2 : 4;  // k-steps per load batch
+    const int rA = w * 16 + li;
+    for (int k0 = 0; k0 < FP; k0 += 4 * KCE) {
+      int fn[KCE];
+#pragma unroll
+      for (int ks = 0; ks < KCE; ++ks) {
+        const int f = min(k0 + ks * 4 + lk, FP - 1);
+        fn[ks] = tile_fns[f0 + f];
+      }
+      T a[KCE][E], b[KCE][E][NB];
+#pragma unroll
+      for (int ks = 0; ks < KCE; ++ks) {
+        const int f = k0 + ks * 4 + lk;
+        const bool on = f < FP && fn[ks] >= 0;
+        const int fc = min(f, FP - 1);
+        const T* zr = zo + (int64_t)max(fn[ks], 0) * ncr;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const T av = tv[((int64_t)rA * FP + fc) * E + e];
+          a[ks][e] = on ? av : T(0);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            if (!CPLX || e == 0) b[ks][e][nb] = zr[colc[nb]];
+            else b[ks][e][nb] = sgn_en * zr[colc[nb] ^ 1];
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ks = 0; ks < KCE; ++ks)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a[ks][e], b[ks][e][nb], acc[nb]);
     }
-    for (int q = threadIdx.x; q < JC * CB; q += blockDim.x) {
-      const int jj = q / CB, cc = q % CB;
-      const int fn = jj < jn ? tile_fns[f0 + j0 + jj] : -1;
-      const int col = blockIdx.y * CB + cc;
-      zs[q] = (fn >= 0 && col < ncr) ? zo[(int64_t)fn * ncr + col] : T(0);
-    }
-    __syncthreads();
-    for (int jj = 0; jj < jn; ++jj) {
-      if constexpr (!CPLX) {
-        const T z = zs[jj * CB + cl];
+  }
+
+  // ---- part = Ht_t^* X_t: (function block mb, column block nb) pairs over the 4 waves
+  if (FP > 0) {
+    const int MB = (FP + 15) / 16;
+    const T sgn_pt = (li & 1) ? T(-1) : T(1);
+    for (int q = w; q < MB * NB; q += 4) {
+      const int mb = q / NB, nb = q - mb * NB;
+      const int f = mb * 16 + li;
+      const bool fok = f < FP;
+      const int fc = fok ? f : FP - 1;
+      const int col = cb0 + nb * 16 + li;
+      const bool cok = col < ncr;
+      const int cc = cok ? col : ncr - 1;
+      V4 pc = V4{0, 0, 0, 0};
+      constexpr int KC = CPLX ? 4 : 8;  // k-steps per load batch
+      for (int kc = 0; kc < TR / 4; kc += KC) {
+        T a[KC][E], b[KC][E];
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) en[i] += Hs[(rg + RG * i) * JC + jj] * z;
-      } else {
-        const T zr = zs[jj * CB + (cl & ~1)], zi = zs[jj * CB + (cl | 1)];
+        for (int ks = 0; ks < KC; ++ks) {
+          const int r = (kc + ks) * 4 + lk;
+          const int g = g0 + r;
+          const bool ok = g < N && cok;
+          const T* xr = x + (int64_t)(g < N ? g : N - 1) * ldx;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          const T hr = Hs[((rg + RG * i) * JC + jj) * 2], hi = Hs[((rg + RG * i) * JC + jj) * 2 + 1];
-          en[i] += (cl & 1) ? (hr * zi + hi * zr) : (hr * zr - hi * zi);
+          for (int e = 0; e < E; ++e) {
+            const T av = tv[((int64_t)r * FP + fc) * E + e];
+            a[ks][e] = fok ? av : T(0);
+            const T bv = (!CPLX || e == 0) ? xr[cc] : sgn_pt * xr[cc ^ 1];
+            b[ks][e] = ok ? bv : T(0);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < KC; ++ks)
+#pragma unroll
+          for (int e = 0; e < E; ++e) pc = M::op(a[ks][e], b[ks][e], pc);
+      }
+      if (cok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int fi = mb * 16 + M::row(lane, v);
+          if (fi < FP) P.part[(int64_t)(f0 + fi) * ncr + col] = pc[v];
         }
       }
     }
-    __syncthreads();
   }
-  if (j >= ncr) return;
+
+  // ---- node-slot gather + recurrence epilogue on the en layout
   const T* __restrict__ Yc = P.ycell;
   const int64_t ldc = P.ldc;
   const Phase3<T> ph = P.ph;
   const T alpha = P.alpha, c = P.c, beta = P.beta;
-  const int nd = P1 * P1 * P1;
-#pragma unroll 1
-  for (int i = 0; i < RPT; ++i) {
-    const int g = t * TR + rg + RG * i;
-    if (g >= N) break;
-    const int ix = g % n, iy = (g / n) % n, iz = g / (n * n);
-    int cxs[2], axs[2], wxs[2], nxs = 1;
-    int cys[2], ays[2], wys[2], nys = 1;
-    int czs[2], azs[2], wzs[2], nzs = 1;
-    cxs[0] = ix / p; axs[0] = ix % p; wxs[0] = 0;
-    if (axs[0] == 0) { cxs[1] = (cxs[0] + nc - 1) % nc; axs[1] = p; wxs[1] = (cxs[1] == nc - 1); nxs = 2; }
-    cys[0] = iy / p; ays[0] = iy % p; wys[0] = 0;
-    if (ays[0] == 0) { cys[1] = (cys[0] + nc - 1) % nc; ays[1] = p; wys[1] = (cys[1] == nc - 1); nys = 2; }
-    czs[0] = iz / p; azs[0] = iz % p; wzs[0] = 0;
-    if (azs[0] == 0) { czs[1] = (czs[0] + nc - 1) % nc; azs[1] = p; wzs[1] = (czs[1] == nc - 1); nzs = 2; }
-    const T msc = cf.mscale * cf.om[ix % p] * cf.om[iy % p] * cf.om[iz % p];
-    T acc = 0;
-    for (int kz = 0; kz < nzs; ++kz)
-      for (int ky = 0; ky < nys; ++ky)
-        for (int kx = 0; kx < nxs; ++kx) {
-          const int64_t e = cxs[kx] + (int64_t)nc * (cys[ky] + (int64_t)nc * czs[kz]);
-          const int a = axs[kx] + P1 * (ays[ky] + P1 * azs[kz]);
-          if constexpr (!CPLX) {
-            acc += Yc[(e * nd + a) * ldc + j];
-          } else {
-            const T* py = Yc + (e * nd + a) * ldc + (j & ~1);
-            C2<T> z{py[0], py[1]};
-            if (wxs[kx]) z = cjmul(C2<T>{ph.re[0], ph.im[0]}, z);
-            if (wys[ky]) z = cjmul(C2<T>{ph.re[1], ph.im[1]}, z);
-            if (wzs[kz]) z = cjmul(C2<T>{ph.re[2], ph.im[2]}, z);
-            acc += (j & 1) ? z.i : z.r;
-          }
-        }
-    const int64_t gi = (int64_t)g;
-    T r = alpha * (msc * acc + en[i] - c * P.x[gi * P.ldx + j]);
-    if (beta != T(0)) r -= beta * P.prev[gi * P.ldo + j];
-    P.out[gi * P.ldo + j] = r;
-  }
-}
-
-// Transposed enrichment product per tile:
-//   part[(tile_fptr[t] + s)][j] = sum_{r in tile} conj(Ht[r][s]) x[r][j]
-// Workgroup = one tile x CB real columns, 4 slot groups; rows staged 16 at a time.
-template <typename T, bool CPLX>
-__global__ __launch_bounds__(512) void enr_tile_partial_kernel(KBatch<T> kb, int CB,
-                                                               const int32_t* __restrict__ tile_fptr, int N) {
-  constexpr int TR = kTileRows, SG = 4, RC = 16, SMAX = 16;
-  constexpr int E = CPLX ? 2 : 1;
-  extern __shared__ unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);  // [RC][CB]
-  T* Hs = xs + RC * CB;                     // [RC][FP][E]
-  const KP<T>& P = kb.k[blockIdx.z];
-  const int ncr = P.ncr;
-  if ((int)blockIdx.y * CB >= ncr) return;
-  const int cl = threadIdx.x % CB, sg = threadIdx.x / CB;
-  const int t = blockIdx.x;
-  const int j = blockIdx.y * CB + cl;
-  const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;
-  const T* tv = P.tv + (int64_t)f0 * TR * E;
-  const T* __restrict__ x = P.x;
-  const int64_t ldx = P.ldx;
-  for (int s0 = 0; s0 < FP; s0 += SG * SMAX) {  // slots in groups of 64
-    T acc[SMAX];
+  const T* __restrict__ prev = P.prev;
+  T* __restrict__ out = P.out;
+  const int64_t ldo = P.ldo;
+  const int S = nc * P1;
+  // slots of node i per dimension: a shared node (i mod p == 0) has two, the one from
+  // the lower cell first; slot 0 holds the periodic image of the last cell
+  int bx[4], by[4], bz[4], gc[4];
+  bool x2[4], y2[4], z2[4], ok[4];
+  T msc[4];
 #pragma unroll
-    for (int i = 0; i < SMAX; ++i) acc[i] = 0;
-    for (int r0 = 0; r0 < TR; r0 += RC) {
-      for (int q = threadIdx.x; q < RC * CB; q += blockDim.x) {
-        const int rr = q / CB, cc = q % CB;
-        const int g = t * TR + r0 + rr;
-        const int col = blockIdx.y * CB + cc;
-        xs[q] = (g < N && col < ncr) ? x[(int64_t)g * ldx + col] : T(0);
-      }
-      for (int q = threadIdx.x; q < RC * FP * E; q += blockDim.x) Hs[q] = tv[(int64_t)r0 * FP * E + q];
-      __syncthreads();
-      for (int rr = 0; rr < RC; ++rr) {
+  for (int v = 0; v < 4; ++v) {
+    const int gv = g0 + w * 16 + M::row(lane, v);
+    ok[v] = gv < N;
+    const int g = ok[v] ? gv : N - 1;
+    gc[v] = g;
+    const int iz = g / (n * n), rem = g - iz * n * n, iy = rem / n, ix = rem - iy * n;
+    const int qx = ix / p, rx = ix - qx * p, qy = iy / p, ry = iy - qy * p, qz = iz / p, rz = iz - qz * p;
+    bx[v] = qx * P1 + (rx ? rx + 1 : 0);
+    by[v] = qy * P1 + (ry ? ry + 1 : 0);
+    bz[v] = qz * P1 + (rz ? rz + 1 : 0);
+    x2[v] = rx == 0;
+    y2[v] = ry == 0;
+    z2[v] = rz == 0;
+    msc[v] = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
+  }
+  T sum[4][NB];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) sum[v][nb] = 0;
+  // (ky, kz) slot pairs in a fixed order; a pair is visited when some lane of the
+  // wave needs it, lanes that do not need it reload their first slot (in bounds,
+  // cached) and discard it
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int ky = kk & 1, kz = kk >> 1;
+    bool need[4];
+    int anyv = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      need[v] = ok[v] && (ky == 0 || y2[v]) && (kz == 0 || z2[v]);
+      anyv |= need[v];
+    }
+    if (kk > 0 && !__any(anyv)) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int sy = by[v] + (need[v] ? ky : 0), sz = bz[v] + (need[v] ? kz : 0);
+      const int64_t row = bx[v] + (int64_t)S * (sy + (int64_t)S * sz);
+      const int64_t row2 = x2[v] ? row + 1 : row;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int j = colc[nb];
         if constexpr (!CPLX) {
-          const T xv = xs[rr * CB + cl];
-#pragma unroll
-          for (int i = 0; i < SMAX; ++i) {
-            const int sl = s0 + sg + SG * i;
-            if (sl < FP) acc[i] += Hs[rr * FP + sl] * xv;
-          }
+          const T v0 = Yc[row * ldc + j];
+          const T v1 = Yc[row2 * ldc + j];
+          const T add = v0 + (x2[v] ? v1 : T(0));
+          sum[v][nb] += need[v] ? add : T(0);
         } else {
-          const T xr = xs[rr * CB + (cl & ~1)], xi = xs[rr * CB + (cl | 1)];
-#pragma unroll
-          for (int i = 0; i < SMAX; ++i) {
-            const int sl = s0 + sg + SG * i;
-            if (sl < FP) {
-              const T hr = Hs[(rr * FP + sl) * 2], hi = Hs[(rr * FP + sl) * 2 + 1];
-              acc[i] += (cl & 1) ? (hr * xi - hi * xr) : (hr * xr + hi * xi);
-            }
+          const int jr = j & ~1;
+          C2<T> z0{Yc[row * ldc + jr], Yc[row * ldc + jr + 1]};
+          C2<T> z1{Yc[row2 * ldc + jr], Yc[row2 * ldc + jr + 1]};
+          // periodic images: slot 0 of a dimension came from the last cell
+          if (bx[v] == 0) z0 = cjmul(C2<T>{ph.re[0], ph.im[0]}, z0);
+          if (sy == 0) {
+            z0 = cjmul(C2<T>{ph.re[1], ph.im[1]}, z0);
+            z1 = cjmul(C2<T>{ph.re[1], ph.im[1]}, z1);
           }
+          if (sz == 0) {
+            z0 = cjmul(C2<T>{ph.re[2], ph.im[2]}, z0);
+            z1 = cjmul(C2<T>{ph.re[2], ph.im[2]}, z1);
+          }
+          const T add = (j & 1) ? (z0.i + (x2[v] ? z1.i : T(0))) : (z0.r + (x2[v] ? z1.r : T(0)));
+          sum[v][nb] += need[v] ? add : T(0);
         }
       }
-      __syncthreads();
     }
-    if (j < ncr) {
+  }
 #pragma unroll
-      for (int i = 0; i < SMAX; ++i) {
-        const int sl = s0 + sg + SG * i;
-        if (sl < FP) P.part[(int64_t)(f0 + sl) * ncr + j] = acc[i];
-      }
+  for (int v = 0; v < 4; ++v) {
+    T xv[NB], pv[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) xv[nb] = x[(int64_t)gc[v] * ldx + colc[nb]];
+    if (beta != T(0)) {  // prev may be null when beta is zero
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) pv[nb] = prev[(int64_t)gc[v] * ldo + colc[nb]];
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) pv[nb] = 0;
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      T r = alpha * (msc[v] * sum[v][nb] + acc[nb][v] - c * xv[nb]);
+      if (beta != T(0)) r -= beta * pv[nb];
+      if (ok[v] && colok[nb]) out[(int64_t)gc[v] * ldo + colc[nb]] = r;
     }
   }
 }
 
-// W'[nu][j] = sum over the tiles coupling to nu of their partial slot, in tile order.
-// Workgroup per (nu, 64 real columns): 16 groups sum strided subsets, fixed LDS tree.
+// First fold of the tile partials: part2[nu][ch][j] = sum of the partials of function
+// nu with list positions in chunk ch (kReduceChunk entries), in list order within
+// 4 interleaved groups and a fixed 4-way tree.  Chunks past the list hold 0.
+constexpr int kReduceChunk = 64;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void enr_tile_reduce_kernel(KBatch<T> kb, const int32_t* __restrict__ fn_pptr,
-                                                               const int32_t* __restrict__ fn_poff) {
-  __shared__ T red[16][64];
+__global__ __launch_bounds__(256) void enr_reduce1_kernel(KBatch<T> kb, int nch, const int32_t* __restrict__ fn_pptr,
+                                                          const int32_t* __restrict__ fn_poff) {
+  __shared__ T red[4][64];
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
   if ((int)blockIdx.y * 64 >= ncr) return;
   const T* __restrict__ part = P.part;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int nu = blockIdx.x;
+  const int nu = blockIdx.x / nch, ch = blockIdx.x - nu * nch;
   const int j = blockIdx.y * 64 + lane;
-  const int e0 = fn_pptr[nu], e1 = fn_pptr[nu + 1];
+  const int e1 = fn_pptr[nu + 1];
+  const int es = fn_pptr[nu] + ch * kReduceChunk, ee = min(e1, es + kReduceChunk);
   T s0 = 0, s1 = 0;
   if (j < ncr) {
-    int e = e0 + grp;
-    for (; e + 16 < e1; e += 32) {
+    int e = es + grp;
+    for (; e + 4 < ee; e += 8) {
       s0 += part[(int64_t)fn_poff[e] * ncr + j];
-      s1 += part[(int64_t)fn_poff[e + 16] * ncr + j];
+      s1 += part[(int64_t)fn_poff[e + 4] * ncr + j];
     }
-    if (e < e1) s0 += part[(int64_t)fn_poff[e] * ncr + j];
+    if (e < ee) s0 += part[(int64_t)fn_poff[e] * ncr + j];
   }
   red[grp][lane] = s0 + s1;
   __syncthreads();
-  for (int st = 8; st > 0; st >>= 1) {
-    if (grp < st) red[grp][lane] += red[grp + st][lane];
-    __syncthreads();
-  }
-  if (grp == 0 && j < ncr) P.wp[(int64_t)nu * ncr + j] = red[0][lane];
+  if (grp == 0 && j < ncr)
+    P.part2[((int64_t)nu * nch + ch) * ncr + j] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // Small dense products on the enrichment rows (n = n_enr; complex interleaved when
 // CPLX), 16x16 output tile per workgroup, LDS-staged K tiles.
-//   mode 0: zo = S x^O       mode 1: wp += H^oo zo
+//   mode 0: zo = S x^O       mode 1: wp = (sum of the folded tile partials) + H^oo zo
 //   mode 2: out^O = alpha (S wp - c x^O) - beta prev^O
 template <typename T, bool CPLX>
 __global__ __launch_bounds__(256) void small_gemm_kernel(KBatch<T> kb, int mode, int64_t N, int n) {
@@ -533,8 +637,14 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(KBatch<T> kb, int mode,
     P.zo[(int64_t)i * P.ncr + (int64_t)jc * E] = sr;
     if (CPLX) P.zo[(int64_t)i * P.ncr + (int64_t)jc * E + 1] = si;
   } else if (mode == 1) {
-    P.wp[(int64_t)i * P.ncr + (int64_t)jc * E] += sr;
-    if (CPLX) P.wp[(int64_t)i * P.ncr + (int64_t)jc * E + 1] += si;
+    const T* p2 = P.part2 + (int64_t)i * P.nch * P.ncr + (int64_t)jc * E;
+    T wr = 0, wi = 0;
+    for (int ch = 0; ch < P.nch; ++ch) {
+      wr += p2[(int64_t)ch * P.ncr];
+      if (CPLX) wi += p2[(int64_t)ch * P.ncr + 1];
+    }
+    P.wp[(int64_t)i * P.ncr + (int64_t)jc * E] = wr + sr;
+    if (CPLX) P.wp[(int64_t)i * P.ncr + (int64_t)jc * E + 1] = wi + si;
   } else {
     const int64_t ox = (N + i) * P.ldx + (int64_t)jc * E, oo = (N + i) * P.ldo + (int64_t)jc * E;
     T r = P.alpha * (sr - P.c * P.x[ox]);
@@ -778,6 +888,29 @@ void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, 
   }
 }
 
+template <typename T, int NB, bool CPLX>
+void launch_node_nb(const oefe_op_s* op, const KBatch<T>& kb, int ncb, hipStream_t s) {
+  hipLaunchKernelGGL((fe_node_mfma_kernel<T, NB, CPLX>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb,
+                     (unsigned)kb.nk), dim3(256), 0, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op),
+                     op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N);
+}
+
+template <typename T, bool CPLX>
+void launch_node(const oefe_op_s* op, const KBatch<T>& kb, int NB, int ncb, hipStream_t s) {
+  switch (NB) {
+    case 1: launch_node_nb<T, 1, CPLX>(op, kb, ncb, s); break;
+    case 2: launch_node_nb<T, 2, CPLX>(op, kb, ncb, s); break;
+    case 3: launch_node_nb<T, 3, CPLX>(op, kb, ncb, s); break;
+    case 4: launch_node_nb<T, 4, CPLX>(op, kb, ncb, s); break;
+    case 5: launch_node_nb<T, 5, CPLX>(op, kb, ncb, s); break;
+    case 6: launch_node_nb<T, 6, CPLX>(op, kb, ncb, s); break;
+    case 7: launch_node_nb<T, 7, CPLX>(op, kb, ncb, s); break;
+    default: launch_node_nb<T, 8, CPLX>(op, kb, ncb, s); break;
+  }
+}
+
+inline int reduce_chunks(const oefe_op_s* op) { return std::max(1, (int)cdiv(op->fn_smax, kReduceChunk)); }
+
 // Steps of several operators sharing one mesh and enrichment layout, in lockstep.
 template <typename T, bool CPLX>
 int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipStream_t s) {
@@ -800,25 +933,16 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
     (void)hipEventRecord(ev1, s);
     op->timer_events.emplace_back(ev0, ev1);
   }
-  // column block of the tiled kernels: all real columns up to cbm, else near-equal blocks
-  const int cbm = op->tune_cb > 0 ? op->tune_cb : 128;
-  int CB = max_ncr <= cbm ? max_ncr : (int)cdiv(max_ncr, cdiv(max_ncr, cbm));
-  CB = (int)cdiv(CB, 8) * 8;
-  const int ncb = (int)cdiv(max_ncr, CB);
+  // node workgroup width: 16-column blocks, all real columns up to the cap, else near-equal
+  const int nbcap = std::max(1, std::min(kNodeNBMax, op->tune_cb > 0 ? op->tune_cb / 16 : kNodeNBMax));
+  const int nb_all = (int)cdiv(max_ncr, 16);
+  const int ncb = (int)cdiv(nb_all, nbcap);
+  const int NB = (int)cdiv(nb_all, ncb);
+  launch_node<T, CPLX>(op, kb, NB, ncb, s);
   if (nO > 0) {
-    const size_t lds = (size_t)(16 * CB + 16 * op->tile_fpmax * (CPLX ? 2 : 1)) * sizeof(T);
-    hipLaunchKernelGGL((enr_tile_partial_kernel<T, CPLX>), dim3((unsigned)op->n_tiles, (unsigned)ncb, nk),
-                       dim3(4 * CB), lds, s, kb, CB, op->d.tile_fptr, (int)op->N);
-  }
-  {
-    const size_t lds = (size_t)(kTileRows * 16 * (CPLX ? 2 : 1) + 16 * CB) * sizeof(T);
-    hipLaunchKernelGGL((fe_node_tile_kernel<T, CPLX>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb, nk),
-                       dim3(4 * CB), lds, s, kb, CB, op->nc, op->p, op->n, op->P1, coef<T>(op), op->d.tile_fptr,
-                       op->d.tile_fns, (int)op->N);
-  }
-  if (nO > 0) {
-    hipLaunchKernelGGL((enr_tile_reduce_kernel<T>), dim3((unsigned)nO, (unsigned)cdiv(max_ncr, 64), nk), dim3(1024),
-                       0, s, kb, op->d.fn_pptr, op->d.fn_poff);
+    const int nch = reduce_chunks(op);
+    hipLaunchKernelGGL((enr_reduce1_kernel<T>), dim3((unsigned)(nO * nch), (unsigned)cdiv(max_ncr, 64), nk),
+                       dim3(256), 0, s, kb, nch, op->d.fn_pptr, op->d.fn_poff);
     hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
                        dim3(256), 0, s, kb, 1, op->N, nO);
     hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
@@ -844,6 +968,8 @@ KP<T> make_kp(const oefe_op_s* op, const T* x, int64_t ld, const T* prev, T* out
   P.ldc = w.ldc;
   P.zo = (T*)w.zo;
   P.part = (T*)w.part;
+  P.part2 = (T*)w.part2;
+  P.nch = reduce_chunks(op);
   P.wp = (T*)w.wp;
   P.tv = dp.tv;
   P.S = dp.S;
@@ -876,13 +1002,14 @@ void launch_density(const oefe_op_s* op, const T* x, int64_t ldx, int ncr, const
 
 size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, int* ldc_out) {
   const int ncr = cplx ? 2 * nv : nv;
-  const int ldc = (int)cdiv(ncr, 64) * 64;
+  const int ldc = (int)cdiv(ncr, 8) * 8;
   if (ldc_out) *ldc_out = ldc;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t bytes = 0;
   if (!op->diagonal) bytes += al((size_t)op->n_cells * op->nd * ldc * elem_bytes);
   bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                 // zo
   bytes += al((size_t)std::max<int64_t>(op->tile_slots, 1) * ncr * elem_bytes);  // part
+  bytes += al((size_t)std::max(op->n_enr, 1) * reduce_chunks(op) * ncr * elem_bytes);  // part2
   bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                 // wp
   return bytes;
 }
@@ -903,6 +1030,8 @@ StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv,
   p += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);
   w.part = p;
   p += al((size_t)std::max<int64_t>(op->tile_slots, 1) * ncr * elem_bytes);
+  w.part2 = p;
+  p += al((size_t)std::max(op->n_enr, 1) * reduce_chunks(op) * ncr * elem_bytes);
   w.wp = p;
   return w;
 }
@@ -911,6 +1040,7 @@ template <typename T>
 int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
                double alpha, double c, double beta, const StepWork& w, hipStream_t s) {
   if (bf16) return OEFE_EUNSUPPORTED;
+  if (!x || !out || (beta != 0.0 && !prev)) return OEFE_EINVAL;  // prev is read only when beta != 0
   if (op->diagonal) {
     const DevPtrs<T> dp = devptrs<T>(op);
     const int64_t tot = op->N * nv;
@@ -936,6 +1066,8 @@ int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* co
                      const T* const* prev, T* const* out, const int64_t* ldo, const int* nv, const double* alpha,
                      const double* c, const double* beta, const StepWork* w, hipStream_t s) {
   if (bf16) return OEFE_EUNSUPPORTED;
+  for (int q = 0; q < nk; ++q)  // the kernels read prev only when beta is nonzero
+    if (!x[q] || !out[q] || (beta[q] != 0.0 && !prev[q])) return OEFE_EINVAL;
   for (int q0 = 0; q0 < nk; q0 += KMAX) {
     KBatch<T> kb{};
     kb.nk = std::min(KMAX, nk - q0);
