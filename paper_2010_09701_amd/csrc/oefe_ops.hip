@@ -335,27 +335,39 @@ struct Mfma<float> {
 
 constexpr int kNodeNBMax = 8;  // 16-column blocks per node workgroup (128 real columns)
 
+// LDS of the node kernel: the tile's rows of X (its column block) and its dense
+// block of m^-1/2 H^co, each row padded by one element.
 template <typename T, int NB, bool CPLX>
-__global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<T> kb, int nc, int p, int n, int P1, CellCoef<T> cf,
-                                                           const int32_t* __restrict__ tile_fptr,
-                                                           const int32_t* __restrict__ tile_fns, int N) {
+constexpr size_t node_lds_bytes(int fpmax) {
+  return (size_t)kTileRows * ((NB * 16 + 1) + (fpmax * (CPLX ? 2 : 1) + 1)) * sizeof(T);
+}
+
+template <typename T, int NB, bool CPLX>
+__global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<T> kb, int nc, int p, int n, int P1,
+                                                                         CellCoef<T> cf,
+                                                                         const int32_t* __restrict__ tile_fptr,
+                                                                         const int32_t* __restrict__ tile_fns, int N) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
-  constexpr int TR = kTileRows, E = CPLX ? 2 : 1;
+  constexpr int TR = kTileRows, E = CPLX ? 2 : 1, CBW = NB * 16, XS = CBW + 1;
+  extern __shared__ unsigned char smem_raw[];
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
-  const int cb0 = blockIdx.y * NB * 16;
+  const int cb0 = blockIdx.y * CBW;
   if (cb0 >= ncr) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int t = blockIdx.x;
   const int g0 = t * TR;
   const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
+  const int HS = FP * E + 1;
+  T* xs = reinterpret_cast<T*>(smem_raw);  // [TR][XS]: x rows of the tile, zero past N
+  T* hs = xs + TR * XS;                     // [TR][HS]: the tile's block, (re, im) per function
   const T* __restrict__ tv = P.tv + (int64_t)f0 * TR * E;  // [TR][FP][E]
   const T* __restrict__ zo = P.zo;                         // [n_enr][ncr]
   const T* __restrict__ x = P.x;
   const int64_t ldx = P.ldx;
-  // Loads below are unconditional, from clamped in-bounds addresses, with the
+  // Global loads below are unconditional, from clamped in-bounds addresses, with
   // unwanted values replaced by selects, so that each batch is issued at once.
   int colc[NB];
   bool colok[NB];
@@ -365,10 +377,42 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
     colok[nb] = col < ncr;
     colc[nb] = colok[nb] ? col : ncr - 1;
   }
+
+  // ---- stage the x tile and the H tile in LDS (one batch of coalesced loads each)
+  {
+    constexpr int XPT = TR * CBW / 256;
+    T xv[XPT];
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
+      const int g = min(g0 + r, N - 1), col = min(cb0 + cl, ncr - 1);
+      xv[i] = x[(int64_t)g * ldx + col];
+    }
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
+      xs[r * XS + cl] = g0 + r < N ? xv[i] : T(0);
+    }
+    const int nh = TR * FP * E;
+    for (int q0 = 0; q0 < nh; q0 += 256 * 8) {
+      T hv[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) hv[i] = tv[min(q0 + (int)threadIdx.x + 256 * i, nh - 1)];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int q = q0 + threadIdx.x + 256 * i;
+        if (q < nh) {
+          const int r = q / (FP * E);
+          hs[r * HS + (q - r * FP * E)] = hv[i];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- en = Ht_t Z^O: rows w*16 .. w*16+15 of the tile (A from LDS, B from Z^O)
   // complex: the second real pass pairs Im(H) with the partner column, signed
   const T sgn_en = (li & 1) ? T(1) : T(-1);
-
-  // ---- en = Ht_t Z^O: rows w*16 .. w*16+15 of the tile
   V4 acc[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) acc[nb] = V4{0, 0, 0, 0};
@@ -378,10 +422,7 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
     for (int k0 = 0; k0 < FP; k0 += 4 * KCE) {
       int fn[KCE];
 #pragma unroll
-      for (int ks = 0; ks < KCE; ++ks) {
-        const int f = min(k0 + ks * 4 + lk, FP - 1);
-        fn[ks] = tile_fns[f0 + f];
-      }
+      for (int ks = 0; ks < KCE; ++ks) fn[ks] = tile_fns[f0 + min(k0 + ks * 4 + lk, FP - 1)];
       T a[KCE][E], b[KCE][E][NB];
 #pragma unroll
       for (int ks = 0; ks < KCE; ++ks) {
@@ -391,7 +432,7 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
         const T* zr = zo + (int64_t)max(fn[ks], 0) * ncr;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          const T av = tv[((int64_t)rA * FP + fc) * E + e];
+          const T av = hs[rA * HS + fc * E + e];
           a[ks][e] = on ? av : T(0);
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
@@ -410,7 +451,7 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
     }
   }
 
-  // ---- part = Ht_t^* X_t: (function block mb, column block nb) pairs over the 4 waves
+  // ---- part = Ht_t^* X_t from LDS: (function block mb, column block nb) pairs over the 4 waves
   if (FP > 0) {
     const int MB = (FP + 15) / 16;
     const T sgn_pt = (li & 1) ? T(-1) : T(1);
@@ -419,34 +460,21 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
       const int f = mb * 16 + li;
       const bool fok = f < FP;
       const int fc = fok ? f : FP - 1;
-      const int col = cb0 + nb * 16 + li;
-      const bool cok = col < ncr;
-      const int cc = cok ? col : ncr - 1;
+      const int cl = nb * 16 + li;  // LDS column; past ncr it holds a duplicate, never stored
       V4 pc = V4{0, 0, 0, 0};
-      constexpr int KC = CPLX ? 4 : 8;  // k-steps per load batch
-      for (int kc = 0; kc < TR / 4; kc += KC) {
-        T a[KC][E], b[KC][E];
+#pragma unroll 4
+      for (int ks = 0; ks < TR / 4; ++ks) {
+        const int r = ks * 4 + lk;
 #pragma unroll
-        for (int ks = 0; ks < KC; ++ks) {
-          const int r = (kc + ks) * 4 + lk;
-          const int g = g0 + r;
-          const bool ok = g < N && cok;
-          const T* xr = x + (int64_t)(g < N ? g : N - 1) * ldx;
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const T av = tv[((int64_t)r * FP + fc) * E + e];
-            a[ks][e] = fok ? av : T(0);
-            const T bv = (!CPLX || e == 0) ? xr[cc] : sgn_pt * xr[cc ^ 1];
-            b[ks][e] = ok ? bv : T(0);
-          }
+        for (int e = 0; e < E; ++e) {
+          const T av = hs[r * HS + fc * E + e];
+          const T a = fok ? av : T(0);
+          const T b = (!CPLX || e == 0) ? xs[r * XS + cl] : sgn_pt * xs[r * XS + (cl ^ 1)];
+          pc = M::op(a, b, pc);
         }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int ks = 0; ks < KC; ++ks)
-#pragma unroll
-          for (int e = 0; e < E; ++e) pc = M::op(a[ks][e], b[ks][e], pc);
       }
-      if (cok) {
+      const int col = cb0 + cl;
+      if (col < ncr) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int fi = mb * 16 + M::row(lane, v);
@@ -541,8 +569,9 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     T xv[NB], pv[NB];
+    const int rl = w * 16 + M::row(lane, v);
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) xv[nb] = x[(int64_t)gc[v] * ldx + colc[nb]];
+    for (int nb = 0; nb < NB; ++nb) xv[nb] = xs[rl * XS + nb * 16 + li];
     if (beta != T(0)) {  // prev may be null when beta is zero
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) pv[nb] = prev[(int64_t)gc[v] * ldo + colc[nb]];
@@ -890,8 +919,15 @@ void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, 
 
 template <typename T, int NB, bool CPLX>
 void launch_node_nb(const oefe_op_s* op, const KBatch<T>& kb, int ncb, hipStream_t s) {
+  const size_t lds = node_lds_bytes<T, NB, CPLX>(op->n_enr > 0 ? op->tile_fpmax : 0);
+  static bool attr_set = false;  // per instantiation; the limit is the CU's 160 KB
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fe_node_mfma_kernel<T, NB, CPLX>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
   hipLaunchKernelGGL((fe_node_mfma_kernel<T, NB, CPLX>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb,
-                     (unsigned)kb.nk), dim3(256), 0, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op),
+                     (unsigned)kb.nk), dim3(256), lds, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op),
                      op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N);
 }
 
