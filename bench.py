@@ -9,16 +9,28 @@ functions, 72 vectors, Chebyshev degree 50.  Synthetic, seeded inputs.
 A step is one ChFSI pass in float64: Chebyshev filter (50 applications of
 M^-1/2 H M^-1/2), Cholesky-Gram-Schmidt, Rayleigh-Ritz.  The spectrum bounds
 (Lanczos, once per operator) and the operator setup are outside the timed
-region.  value = N_tot * nv * m / (seconds per step), in DoF*vec*deg/s.
+region; inputs are resident in device memory.
+value = N_tot * nv * m / (seconds per step), in DoF*vec*deg/s.
 
 Also reported: the filter-only rate, the float32-arithmetic filter's speedup
-and its Ritz-value error against the float64 path after 5 passes, the cell
-kernel's roofline figures (HIP events bracketing each launch on the stream it
-runs on), and the CPU oracle on a bounded sample.
+and its Ritz-value error against the float64 path after 5 passes, the node
+kernel's memory roofline and the cell kernel's arithmetic roofline (HIP events
+bracketing each launch on the stream it runs on), and the CPU oracle on a
+bounded sample.
+
+Helpers for the committed profile summaries (they read rocprofv3 output):
+    python bench.py --summarize-trace DIR           kernel-trace statistics table
+    python bench.py --summarize-traffic FETCH_DIR WRITE_DIR
+                                                    HBM bytes per node-kernel launch from
+                                                    FETCH_SIZE / WRITE_SIZE, calibrated on
+                                                    the device-to-device copy of --calib-copy
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -30,7 +42,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published peaks used for the roofline fraction
+# MI355X published peaks used for the roofline fractions
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_VECTOR_TFLOPS = 157.3
@@ -41,6 +53,10 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 # Laplacian) = 7250 FMA = 14500 flops.
 CELL_FLOPS_P4 = 14500.0
 
+OPS_SOURCE = os.path.join(ROOT, "paper_2010_09701_amd", "csrc", "oefe_ops.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fe_node_mfma_kernel_diamond8_traffic.md")
+CALIB_BYTES = 512 * 2**20
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -50,6 +66,10 @@ def parse():
     ap.add_argument("--workload", default="diamond8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with one 512 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--summarize-trace", metavar="DIR")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     return ap.parse_args()
 
 
@@ -57,7 +77,44 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, degrees=3):
+def ops_source_hash() -> str:
+    with open(OPS_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def node_kernel_bytes(gop, ncr: int, m: int) -> float:
+    """Algorithmic HBM bytes of one node-kernel launch inside the filter, averaged over its m steps.
+
+    Per launch: the cell results of every node slot ((nc (p+1))^3 rows), X and the
+    output (N rows each), the previous iterate (N rows, read in m-1 of the m steps),
+    the dense coupling blocks (tile_slots x tile_rows, once per column block) and
+    the tile partials written (tile_slots rows), all x ncr real columns of 8 bytes.
+    """
+    slots = (gop.nc * (gop.p + 1)) ** 3
+    nb_all = -(-ncr // 16)
+    ncb = -(-nb_all // 8)
+    rows = slots + 2 * gop.n_fe + gop.n_fe * (m - 1) / m + gop.tile_slots
+    return 8.0 * (rows * ncr + gop.tile_slots * gop.tile_rows * ncb)
+
+
+def load_traffic():
+    """HBM bytes per node-kernel launch from the committed counter summary, if the kernel source is unchanged."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().split()[0]
+    if vals.get("source_sha256_16") != ops_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg, degrees=8):
     """The oracle's float64 filter on the same workload, a few Chebyshev degrees on the host."""
     from oracle import chfsi as och
     from oracle.operator import OEFEOperator
@@ -78,16 +135,89 @@ def cpu_baseline(cfg, degrees=3):
     dt = time.perf_counter() - t
     rate = op.n_tot * cfg.nv * degrees / dt
     cores = len(os.sched_getaffinity(0))
-    return {"value": rate, "unit": "DoF*vec*deg/s", "cores": int(max(cores, blas_threads)), "kind": "oracle",
+    return {"value": rate, "unit": "DoF*vec*deg/s", "cores": int(min(cores, max(blas_threads, 1))), "kind": "oracle",
             "sample": f"{cfg.system.name}: {degrees} Chebyshev degrees of the float64 oracle filter on all "
-                      f"{cfg.nv} vectors ({dt:.1f} s), numpy/scipy, {cores} host cores available, "
-                      f"{blas_threads} BLAS threads"}
+                      f"{cfg.nv} vectors ({dt:.1f} s; numpy/scipy with {blas_threads} BLAS threads, "
+                      f"{cores} host cores available)"}
+
+
+def summarize_trace(d):
+    f = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
+    if not f:
+        sys.exit(f"no kernel_stats.csv under {d}")
+    print("| kernel | calls | avg us | min us | max us | share % |")
+    print("|---|---:|---:|---:|---:|---:|")
+    for r in list(csv.DictReader(open(f[0])))[:16]:
+        print(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+              f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+
+
+def _short(name):
+    n = name.replace("void ", "").replace("oefe::(anonymous namespace)::", "").replace("oefe::", "")
+    out, depth = "", 0
+    for ch in n:
+        if ch == "(" and depth == 0:
+            break
+        depth += (ch == "<") - (ch == ">")
+        out += ch
+    return out
+
+
+def _counter_rows(d):
+    f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+    if not f:
+        sys.exit(f"no counter_collection.csv under {d}")
+    return list(csv.DictReader(open(f[0])))
+
+
+def _per_kernel(rows, counter):
+    """kernel short name -> list of per-dispatch values (KiB) of one counter."""
+    acc = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (_short(r["Kernel_Name"]), r["Dispatch_Id"])
+        acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for (k, _), v in acc.items():
+        out.setdefault(k, []).append(v)
+    return out
+
+
+def summarize_traffic(fetch_dir, write_dir):
+    fe = _per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
+    wr = _per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
+    # the filter's node-kernel instance is the float64 one launched most often
+    node = sorted((k for k in fe if k.startswith("fe_node_mfma_kernel<double")), key=lambda k: -len(fe[k]))
+    copy = [k for k in fe if "copyBuffer" in k or "copy_kernel" in k]
+    if not node or not copy:
+        sys.exit(f"kernels not found: {sorted(fe)}")
+    k, c = node[0], copy[0]
+    cf = max(fe[c]) * 1024.0 / CALIB_BYTES  # the largest dispatch is the 512 MiB calibration copy
+    cw = max(wr[c]) * 1024.0 / CALIB_BYTES
+    f_kib, w_kib = float(np.median(fe[k])), float(np.median(wr[k]))
+    hbm = f_kib * 1024.0 / cf + w_kib * 1024.0 / cw
+    print(f"- kernel: {k}")
+    print(f"- dispatches: {len(fe[k])}")
+    print(f"- fetch_kib_median: {f_kib:.0f}")
+    print(f"- write_kib_median: {w_kib:.0f}")
+    print(f"- calib_kernel: {c}")
+    print(f"- calib_fetch_factor: {cf:.4f} (FETCH_SIZE bytes / bytes copied, 512 MiB copy)")
+    print(f"- calib_write_factor: {cw:.4f} (WRITE_SIZE bytes / bytes copied)")
+    print(f"- hbm_bytes_per_launch: {hbm:.0f}")
+    print(f"- source_sha256_16: {ops_source_hash()}")
 
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark measures one GPU; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
@@ -132,7 +262,7 @@ def main():
     value = work / (ms / 1e3)
     log(f"pass: {ms:.3f} ms, {value:.3e} DoF*vec*deg/s")
 
-    # filter-only rate and cell-kernel timing (events bracketing each launch)
+    # filter-only rate
     Xf = X0.clone()
     reps = max(2, args.steps)
     torch.cuda.synchronize()
@@ -143,18 +273,32 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     filt_ms = e0.elapsed_time(e1) / reps
-    gop.kernel_timer(True)
-    oefe.chebyshev_filter(gop, Xf, cfg.m, 0.5 * (a0L + b), b, a0L)
-    n_launch, tot_ms = gop.kernel_timer_read()
-    gop.kernel_timer(False)
-    cell_ms = tot_ms / max(n_launch, 1)
+
+    # per-launch durations of the node and cell kernels: HIP events recorded by the
+    # library around each launch, on the stream the kernel runs on
+    def stage_ms(which):
+        gop.kernel_timer(which)
+        oefe.chebyshev_filter(gop, Xf, cfg.m, 0.5 * (a0L + b), b, a0L)
+        n_launch, tot_ms = gop.kernel_timer_read()
+        gop.kernel_timer("off")
+        Xf.copy_(X0)
+        return tot_ms / max(n_launch, 1), n_launch
+
+    node_ms, node_n = stage_ms("node")
+    cell_ms, cell_n = stage_ms("cell")
+    node_bytes = node_kernel_bytes(gop, cfg.nv, cfg.m)
+    node_gbs = node_bytes / (node_ms / 1e3) / 1e9
     cell_flops = CELL_FLOPS_P4 * (sysm.p + 1) ** 3 / 125.0 * gop.n_cells * cfg.nv
-    achieved = cell_flops / (cell_ms / 1e3) / 1e12
-    log(f"filter: {filt_ms:.3f} ms; cell kernel avg {cell_ms * 1e3:.1f} us over {n_launch} launches, "
-        f"{achieved:.2f} TFLOP/s")
+    cell_tfs = cell_flops / (cell_ms / 1e3) / 1e12
+    traffic = load_traffic()
+    log(f"filter: {filt_ms:.3f} ms; node kernel avg {node_ms * 1e3:.1f} us ({node_n} launches), "
+        f"{node_gbs:.0f} GB/s algorithmic; cell kernel avg {cell_ms * 1e3:.1f} us, {cell_tfs:.2f} TFLOP/s")
 
     extra = {"filter_ms": filt_ms, "filter_rate": work / (filt_ms / 1e3), "pass_ms": ms,
-             "lanczos_bounds": [a0L, b], "n_tot": gop.n_tot, "n_fe": gop.n_fe, "n_enr": gop.n_enr}
+             "lanczos_bounds": [a0L, b], "n_tot": gop.n_tot, "n_fe": gop.n_fe, "n_enr": gop.n_enr,
+             "cell_kernel": {"bound": "alu", "kernel": "fe_cell_kernel<double,5>", "achieved": cell_tfs,
+                             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": cell_tfs / PEAK_FP64_TFLOPS,
+                             "avg_launch_us": cell_ms * 1e3, "flops_per_launch": cell_flops}}
 
     if not args.no_fp32:
         from paper_2010_09701_amd.chfsi import chfsi_run
@@ -192,15 +336,22 @@ def main():
         "config": {"workload": f"{sysm.name}: {sysm.nc}^3 cells p={sysm.p}, {gop.n_fe} FE + {gop.n_enr} "
                                f"enrichment DoF, {cfg.nv} vectors, Chebyshev degree {cfg.m}",
                    "global_batch": cfg.nv, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "fe_cell_kernel<double,5>", "achieved": achieved,
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": None, "avg_launch_us": cell_ms * 1e3},
+        "roofline": {"bound": "hbm", "kernel": "fe_node_mfma_kernel<double>", "achieved": node_gbs,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": node_gbs / PEAK_HBM_GBS,
+                     "traffic": traffic, "avg_launch_us": node_ms * 1e3, "bytes_per_launch": node_bytes},
         "extra": extra,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(cfg)
         log(f"cpu baseline {out['cpu_baseline']['value']:.3e}")
+    if args.calib_copy:
+        a = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
     print(json.dumps(out), flush=True)
 
 

@@ -102,7 +102,10 @@ int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out);
 
 int oefe_op_destroy(oefe_op op);
 
-/* dims[0..7] = n_fe, n_enr, n_tot, n_cells, nq, nc, p, is_complex. */
+/* dims[0..9] = n_fe, n_enr, n_tot, n_cells, nq, nc, p, is_complex,
+ * coupling-tile slots (sum over the tiles of tile_rows consecutive FE rows of
+ * the number of enrichment functions each couples to, padded to 4), tile_rows.
+ * dims must hold 10 entries. */
 int oefe_op_dims(oefe_op op, int64_t* dims);
 
 /* Replace the potential at the quadrature points: V[n_cells * nq] (cell-major,
@@ -187,12 +190,15 @@ int rayleigh_ritz(oefe_op op, oefe_prec prec, void* Q, int64_t ld, int32_t nv, d
 int band_energy_grad(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* f,
                      double* E, double* dE_dV, void* dE_dX, void* work, oefe_stream stream);
 
-/* Instrumentation: while enabled, every launch of the cell-level kernel (the
- * sum-factorized H^cc stage of ham_apply / chebyshev_filter) is bracketed by
- * HIP events on the caller's stream.  oefe_kernel_timer_read synchronizes,
- * returns the number of bracketed launches and their summed duration (ms),
- * and clears the record. */
-int oefe_kernel_timer(oefe_op op, int enable);
+/* Instrumentation.  While a kernel is selected, each of its launches inside
+ * ham_apply / chebyshev_filter* is bracketed by HIP events on the stream it is
+ * launched on.  which: OEFE_TIMER_OFF, OEFE_TIMER_CELL (the sum-factorized
+ * H^cc cell stage) or OEFE_TIMER_NODE (the node stage: slot gather, coupling
+ * blocks, recurrence epilogue).  oefe_kernel_timer_read synchronizes, returns
+ * the number of bracketed launches and their summed duration (ms), and clears
+ * the record.  Selecting a kernel discards events not yet read. */
+typedef enum { OEFE_TIMER_OFF = 0, OEFE_TIMER_CELL = 1, OEFE_TIMER_NODE = 2 } oefe_timer_kind;
+int oefe_kernel_timer(oefe_op op, int which);
 int oefe_kernel_timer_read(oefe_op op, int64_t* launches, double* total_ms);
 
 const char* oefe_strerror(int code);

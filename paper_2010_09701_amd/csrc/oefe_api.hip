@@ -446,9 +446,15 @@ const char* oefe_strerror(int code) {
 
 const char* oefe_last_error(void) { return g_last_error.c_str(); }
 
-int oefe_kernel_timer(oefe_op op, int enable) {
+int oefe_kernel_timer(oefe_op op, int which) {
   if (!op) return fail(OEFE_EINVAL, "null operator");
-  op->timer_on = enable != 0;
+  if (which < OEFE_TIMER_OFF || which > OEFE_TIMER_NODE) return fail(OEFE_EINVAL, "unknown timer kind");
+  for (auto& pr : op->timer_events) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  op->timer_events.clear();
+  op->timer_kind = which;
   return OEFE_OK;
 }
 
@@ -540,6 +546,8 @@ int oefe_op_dims(oefe_op op, int64_t* dims) {
   dims[5] = op->nc;
   dims[6] = op->p;
   dims[7] = op->cplx ? 1 : 0;
+  dims[8] = op->n_enr > 0 ? op->tile_slots : 0;
+  dims[9] = kTileRows;
   return OEFE_OK;
 }
 

@@ -137,7 +137,7 @@ struct oefe_op_s {
   // launch shape overrides (autotuner): cell-kernel column width, node/partial column block
   int tune_cw = 0, tune_cb = 0;
   // instrumentation (oefe_kernel_timer)
-  bool timer_on = false;
+  int timer_kind = 0;  // oefe_timer_kind
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;
 };
 

@@ -961,20 +961,25 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
   if (nO > 0)
     hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
                        dim3(256), 0, s, kb, 0, op->N, nO);
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (op->timer_on && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess)
-    (void)hipEventRecord(ev0, s);
-  launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw > 0 ? op->tune_cw : pick_cw(max_ncr), s);
-  if (ev1) {
-    (void)hipEventRecord(ev1, s);
-    op->timer_events.emplace_back(ev0, ev1);
-  }
+  // optional HIP events around one stage (oefe_kernel_timer)
+  auto timed = [&](int kind, auto&& launch) {
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const bool on = op->timer_kind == kind && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
+    if (on) (void)hipEventRecord(ev0, s);
+    launch();
+    if (on) {
+      (void)hipEventRecord(ev1, s);
+      op->timer_events.emplace_back(ev0, ev1);
+    }
+  };
+  timed(OEFE_TIMER_CELL,
+        [&] { launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw > 0 ? op->tune_cw : pick_cw(max_ncr), s); });
   // node workgroup width: 16-column blocks, all real columns up to the cap, else near-equal
   const int nbcap = std::max(1, std::min(kNodeNBMax, op->tune_cb > 0 ? op->tune_cb / 16 : kNodeNBMax));
   const int nb_all = (int)cdiv(max_ncr, 16);
   const int ncb = (int)cdiv(nb_all, nbcap);
   const int NB = (int)cdiv(nb_all, ncb);
-  launch_node<T, CPLX>(op, kb, NB, ncb, s);
+  timed(OEFE_TIMER_NODE, [&] { launch_node<T, CPLX>(op, kb, NB, ncb, s); });
   if (nO > 0) {
     const int nch = reduce_chunks(op);
     hipLaunchKernelGGL((enr_reduce1_kernel<T>), dim3((unsigned)(nO * nch), (unsigned)cdiv(max_ncr, 64), nk),

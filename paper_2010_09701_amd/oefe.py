@@ -153,9 +153,10 @@ class Operator:
                 raise RuntimeError("no HIP device")
             torch.cuda.current_device()
             _check(_lib.oefe_op_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create")
-        dims = (ctypes.c_int64 * 8)()
+        dims = (ctypes.c_int64 * 10)()
         _check(_lib.oefe_op_dims(self._h, dims), "oefe_op_dims")
-        self.n_fe, self.n_enr, self.n_tot, self.n_cells, self.nq, self.nc, self.p, cx = [int(x) for x in dims]
+        (self.n_fe, self.n_enr, self.n_tot, self.n_cells, self.nq, self.nc, self.p, cx, self.tile_slots,
+         self.tile_rows) = [int(x) for x in dims]
         self.is_complex = bool(cx)
         self._work = {}
 
@@ -195,11 +196,18 @@ class Operator:
             self._work["buf"] = w
         return w
 
-    def kernel_timer(self, enable: bool):
-        _check(_lib.oefe_kernel_timer(self._h, 1 if enable else 0), "oefe_kernel_timer")
+    TIMER_KINDS = {"off": 0, "cell": 1, "node": 2}
+
+    def kernel_timer(self, which="cell"):
+        """Bracket the launches of one stage ("cell", "node"; "off"/None/False stops) with HIP events."""
+        if which is True:
+            which = "cell"
+        if which in (None, False):
+            which = "off"
+        _check(_lib.oefe_kernel_timer(self._h, self.TIMER_KINDS[which]), "oefe_kernel_timer")
 
     def kernel_timer_read(self):
-        """(launches, total milliseconds) of the bracketed cell-kernel launches since the last read."""
+        """(launches, total milliseconds) of the bracketed launches since the last read."""
         n = ctypes.c_int64(0)
         ms = ctypes.c_double(0.0)
         _check(_lib.oefe_kernel_timer_read(self._h, ctypes.byref(n), ctypes.byref(ms)), "oefe_kernel_timer_read")
