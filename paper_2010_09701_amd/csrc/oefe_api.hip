@@ -380,6 +380,21 @@ using namespace oefe;
 
 namespace {
 
+// Side stream and events of the overlapped recurrence (created once per operator).
+int overlap_setup(const oefe_op_s* op, Overlap* ov) {
+  if (!op->side_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&op->side_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_node, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_zo, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "overlap stream setup");
+  }
+  ov->side = op->side_stream;
+  ov->ev_node = op->ev_node;
+  ov->ev_zo = op->ev_zo;
+  ov->first = ov->last = false;
+  return OEFE_OK;
+}
+
 template <typename T>
 int filter_impl(oefe_op_s* op, bool bf16, T* X, int64_t ld, int nv, int m, double a, double b, double a0,
                 const Layout& L, hipStream_t s) {
@@ -407,15 +422,26 @@ int filter_impl(oefe_op_s* op, bool bf16, T* X, int64_t ld, int nv, int m, doubl
     old = B;
     ldu = ldw;
   }
+  Overlap ov;
+  if (int rc = overlap_setup(op, &ov)) return rc;
+  // on an error the main stream still waits for the side chain already queued
+  auto bail = [&](int rc) {
+    if (rc != OEFE_EINVAL) (void)hipStreamWaitEvent(s, ov.ev_zo, 0);
+    return rc;
+  };
   // Y_1 = (s1/e)(H x - c x)  -> old buffer
-  int rc = apply_step<T>(op, bf16, cur, ldu, nullptr, old, ldu, nv, s1 / e, c, 0.0, L.step, s);
-  if (rc) return rc;
+  ov.first = true;
+  ov.last = m == 1;
+  int rc = apply_step<T>(op, bf16, cur, ldu, nullptr, old, ldu, nv, s1 / e, c, 0.0, L.step, s, &ov);
+  if (rc) return bail(rc);
   std::swap(cur, old);  // cur = Y1, old = Y0
   double sig = s1;
   for (int k = 1; k < m; ++k) {
     const double sn = 1.0 / (2.0 / s1 - sig);
-    rc = apply_step<T>(op, bf16, cur, ldu, old, old, ldu, nv, 2.0 * sn / e, c, sig * sn, L.step, s);
-    if (rc) return rc;
+    ov.first = false;
+    ov.last = k == m - 1;
+    rc = apply_step<T>(op, bf16, cur, ldu, old, old, ldu, nv, 2.0 * sn / e, c, sig * sn, L.step, s, &ov);
+    if (rc) return bail(rc);
     std::swap(cur, old);
     sig = sn;
   }
@@ -531,6 +557,12 @@ int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out) {
 
 int oefe_op_destroy(oefe_op op) {
   if (!op) return OEFE_OK;
+  if (op->side_stream) {
+    (void)hipStreamSynchronize(op->side_stream);
+    (void)hipStreamDestroy(op->side_stream);
+    (void)hipEventDestroy(op->ev_node);
+    (void)hipEventDestroy(op->ev_zo);
+  }
   free_device(op);
   delete op;
   return OEFE_OK;
@@ -708,12 +740,22 @@ int filter_batched_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, c
     al[q] = s1[q] / e[q];
     be[q] = 0.0;
   }
+  Overlap ov;
+  if (int rc = overlap_setup(opp[0], &ov)) return rc;
+  auto bail = [&](int rc) {
+    if (rc != OEFE_EINVAL) (void)hipStreamWaitEvent(s, ov.ev_zo, 0);
+    return rc;
+  };
+  ov.first = true;
+  ov.last = m == 1;
   int rc = apply_step_batch<T>(opp, nk, bf16, xin.data(), ldp.data(), pin.data(), outp.data(), ldp.data(), nvv.data(),
-                               al.data(), c.data(), be.data(), sw.data(), s);
-  if (rc) return rc;
+                               al.data(), c.data(), be.data(), sw.data(), s, &ov);
+  if (rc) return bail(rc);
   T** cur = B.data();
   T** old = A.data();
   for (int k = 1; k < m; ++k) {
+    ov.first = false;
+    ov.last = k == m - 1;
     for (int q = 0; q < nk; ++q) {
       const double sn = 1.0 / (2.0 / s1[q] - sig[q]);
       xin[q] = cur[q];
@@ -724,8 +766,8 @@ int filter_batched_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, c
       sig[q] = sn;
     }
     rc = apply_step_batch<T>(opp, nk, bf16, xin.data(), ldp.data(), pin.data(), outp.data(), ldp.data(), nvv.data(),
-                             al.data(), c.data(), be.data(), sw.data(), s);
-    if (rc) return rc;
+                             al.data(), c.data(), be.data(), sw.data(), s, &ov);
+    if (rc) return bail(rc);
     std::swap(cur, old);
   }
   for (int q = 0; q < nk; ++q) {

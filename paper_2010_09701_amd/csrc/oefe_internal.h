@@ -138,6 +138,9 @@ struct oefe_op_s {
   int tune_cw = 0, tune_cb = 0;
   // instrumentation (oefe_kernel_timer)
   int timer_kind = 0;  // oefe_timer_kind
+  // side stream and events of the overlapped recurrence (created on first use)
+  mutable hipStream_t side_stream = nullptr;
+  mutable hipEvent_t ev_node = nullptr, ev_zo = nullptr;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;
 };
 

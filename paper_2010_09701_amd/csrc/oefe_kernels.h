@@ -15,20 +15,41 @@ struct StepWork {
   void* wp;       // [n_enr * ncr]
 };
 
+// Allows a kernel `dynamic_bytes` of dynamic LDS (above the 64 KB default the
+// attribute must be raised; the limit is the CU's 160 KB including static LDS).
+// Returns hipSuccess or the error of hipFuncSetAttribute.
+inline hipError_t allow_dynamic_lds(const void* kernel, size_t dynamic_bytes) {
+  if (dynamic_bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes);
+}
+
 size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, int* ldc_out);
 StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, void* work);
+
+// Overlap of a recurrence: the enrichment-row chain of step k (partial fold,
+// W', enrichment rows of out, and Z^O of step k+1) runs on `side` while the main
+// stream starts the cell stage of step k+1; the node stage of step k+1 waits for it.
+// first: this step computes its own Z^O on the main stream; last: the main stream
+// waits for the chain at the end of the step.
+struct Overlap {
+  hipStream_t side;
+  hipEvent_t ev_node, ev_zo;
+  bool first, last;
+};
 
 // out = alpha (Ht x - c x) - beta prev   (prev may be null when beta == 0)
 // T = double or float; x: [n_tot x ld], prev and out: [n_tot x ldo] (complex: interleaved, leading
 // dimensions in complex elements).  prev may alias out.
 template <typename T>
 int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
-               double alpha, double c, double beta, const StepWork& w, hipStream_t s);
+               double alpha, double c, double beta, const StepWork& w, hipStream_t s,
+               const Overlap* ov = nullptr);
 // Batched steps of nk operators sharing one mesh / enrichment layout (k-points), in lockstep.
 template <typename T>
 int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* const* x, const int64_t* ld,
                      const T* const* prev, T* const* out, const int64_t* ldo, const int* nv, const double* alpha,
-                     const double* c, const double* beta, const StepWork* w, hipStream_t s);
+                     const double* c, const double* beta, const StepWork* w, hipStream_t s,
+                     const Overlap* ov = nullptr);
 // Z^O = S X^O only (for the density)
 template <typename T>
 int zo_only(const oefe_op_s* op, const T* x, int64_t ld, int nv, T* zo, int ncr, hipStream_t s);

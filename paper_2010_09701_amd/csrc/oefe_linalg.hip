@@ -441,20 +441,306 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, in
   jacobi_body<CPLX>(A, n, lam, U, V, rot, status, red);
 }
 
-// Same solver with the matrix, the rotations and the accumulated vectors in LDS (small n).
+// Same method with the matrix, the rotations and the accumulated vectors in LDS
+// (small n).  One round of the round-robin ordering rotates n/2 disjoint pairs at
+// once, so A <- G^* A G factors into independent 2x2 blocks: block (k1, k2) of
+// rows (p1, q1) and columns (p2, q2) becomes G_k1^* B G_k2.  A round is therefore
+// two barrier-separated phases: (a) the rotations, (b) the block updates of A and
+// the column updates of V.  Same rotations, same order of operations per entry
+// as the global-memory version (columns, then rows).
 template <bool CPLX>
-__global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restrict__ A, int n,
-                                                          double* __restrict__ lam, double* __restrict__ U,
-                                                          int32_t* __restrict__ status) {
+__global__ __launch_bounds__(512) void jacobi_lds_kernel(const double* __restrict__ A, int n,
+                                                         double* __restrict__ lam, double* __restrict__ U,
+                                                         int32_t* __restrict__ status) {
   constexpr int E = CPLX ? 2 : 1;
   extern __shared__ double sm[];
+  const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
+  const int npair = NN / 2, m = NN - 1;
   double* As = sm;                       // n*n*E
   double* Vs = As + (size_t)n * n * E;   // n*n*E
-  double* rot = Vs + (size_t)n * n * E;  // 6 * (n/2 + 1)
-  double* red = rot + 6 * (n / 2 + 1);   // 1024
-  for (int t = threadIdx.x; t < n * n * E; t += blockDim.x) As[t] = A[t];
+  double* rot = Vs + (size_t)n * n * E;  // 6 * npair: c, s, er, ei, p, q
+  double* red = rot + 6 * npair;         // 16
+  const int tid = threadIdx.x, nth = blockDim.x;
+  auto a_ = [&](int i, int j) -> double* { return As + ((int64_t)i * n + j) * E; };
+  for (int t = tid; t < n * n * E; t += nth) As[t] = A[t];
+  for (int t = tid; t < n * n; t += nth) {
+    Vs[(int64_t)t * E] = (t / n == t % n) ? 1.0 : 0.0;
+    if (CPLX) Vs[(int64_t)t * E + 1] = 0.0;
+  }
   __syncthreads();
-  jacobi_body<CPLX>(As, n, lam, U, Vs, rot, status, red);
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
+    // convergence test: squared Frobenius norms of the off-diagonal and diagonal parts
+    double off = 0, dia = 0;
+    for (int t = tid; t < n * n; t += nth) {
+      const int i = t / n, j = t - i * n;
+      const double* a = As + (int64_t)t * E;
+      const double v = a[0] * a[0] + (CPLX ? a[1] * a[1] : 0.0);
+      if (i == j) dia += v;
+      else off += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      dia += __shfl_xor(dia, o);
+    }
+    if ((tid & 63) == 0) {
+      red[2 * (tid >> 6)] = off;
+      red[2 * (tid >> 6) + 1] = dia;
+    }
+    __syncthreads();
+    double offs = 0, dias = 0;
+    for (int w = 0; w < nth / 64; ++w) {
+      offs += red[2 * w];
+      dias += red[2 * w + 1];
+    }
+    __syncthreads();
+    if (offs <= 1e-30 * dias || offs == 0.0) break;
+    for (int st = 0; st < m; ++st) {
+      // (a) rotation per pair (er + i ei = e^{i phi} of a_pq; real: er = sign)
+      for (int k = tid; k < npair; k += nth) {
+        int p, q;
+        if (k == 0) {
+          p = 0;
+          q = 1 + st % m;
+        } else {
+          p = 1 + (st + k) % m;
+          q = 1 + (st - k + m) % m;
+        }
+        if (p > q) { int t = p; p = q; q = t; }
+        double c = 1, sn = 0, er = 1, ei = 0;
+        if (q < n) {
+          const double* apq = a_(p, q);
+          const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
+          const double r = sqrt(br * br + bi * bi);
+          const double al = a_(p, p)[0], ga = a_(q, q)[0];
+          if (r > 1e-300 && r > 1e-18 * sqrt(fabs(al * ga))) {
+            er = br / r;
+            ei = bi / r;
+            const double tau = (ga - al) / (2.0 * r);
+            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+          }
+        }
+        double* R = rot + 6 * k;
+        R[0] = c; R[1] = sn; R[2] = er; R[3] = ei; R[4] = p; R[5] = q;
+      }
+      __syncthreads();
+      // (b) 2x2 blocks of A: columns by G_k2, then rows by G_k1^*
+      for (int t = tid; t < npair * npair; t += nth) {
+        const int k1 = t / npair, k2 = t - k1 * npair;
+        const double* R1 = rot + 6 * k1;
+        const double* R2 = rot + 6 * k2;
+        const bool on1 = R1[1] != 0.0, on2 = R2[1] != 0.0;
+        if (!on1 && !on2) continue;
+        const int p1 = (int)R1[4], q1 = (int)R1[5], p2 = (int)R2[4], q2 = (int)R2[5];
+        const bool r2 = q1 < n, c2 = q2 < n;  // second row / column exists
+        if constexpr (!CPLX) {
+          double b00 = *a_(p1, p2), b01 = c2 ? *a_(p1, q2) : 0.0;
+          double b10 = r2 ? *a_(q1, p2) : 0.0, b11 = (r2 && c2) ? *a_(q1, q2) : 0.0;
+          if (on2) {
+            const double c = R2[0], sn = R2[1], sg = R2[2];
+            double x = b00, y = b01 * sg;
+            b00 = x * c - y * sn; b01 = x * sn + y * c;
+            x = b10; y = b11 * sg;
+            b10 = x * c - y * sn; b11 = x * sn + y * c;
+          }
+          if (on1) {
+            const double c = R1[0], sn = R1[1], sg = R1[2];
+            double x = b00, y = sg * b10;
+            b00 = c * x - sn * y; b10 = sn * x + c * y;
+            x = b01; y = sg * b11;
+            b01 = c * x - sn * y; b11 = sn * x + c * y;
+          }
+          if (k1 == k2) b01 = b10 = 0.0;  // the rotated pair
+          *a_(p1, p2) = b00;
+          if (c2) *a_(p1, q2) = b01;
+          if (r2) *a_(q1, p2) = b10;
+          if (r2 && c2) *a_(q1, q2) = b11;
+        } else {
+          auto ld = [&](bool ok, int i, int j) { return ok ? Z{a_(i, j)[0], a_(i, j)[1]} : Z{0.0, 0.0}; };
+          Z b00 = ld(true, p1, p2), b01 = ld(c2, p1, q2), b10 = ld(r2, q1, p2), b11 = ld(r2 && c2, q1, q2);
+          if (on2) {
+            const double c = R2[0], sn = R2[1];
+            const Z emi{R2[2], -R2[3]};
+            Z x = b00, ye = zmul(b01, emi);
+            b00 = {x.r * c - ye.r * sn, x.i * c - ye.i * sn};
+            b01 = {x.r * sn + ye.r * c, x.i * sn + ye.i * c};
+            x = b10; ye = zmul(b11, emi);
+            b10 = {x.r * c - ye.r * sn, x.i * c - ye.i * sn};
+            b11 = {x.r * sn + ye.r * c, x.i * sn + ye.i * c};
+          }
+          if (on1) {
+            const double c = R1[0], sn = R1[1];
+            const Z eph{R1[2], R1[3]};
+            Z x = b00, ye = zmul(eph, b10);
+            b00 = {c * x.r - sn * ye.r, c * x.i - sn * ye.i};
+            b10 = {sn * x.r + c * ye.r, sn * x.i + c * ye.i};
+            x = b01; ye = zmul(eph, b11);
+            b01 = {c * x.r - sn * ye.r, c * x.i - sn * ye.i};
+            b11 = {sn * x.r + c * ye.r, sn * x.i + c * ye.i};
+          }
+          if (k1 == k2) {  // the rotated pair; the diagonal stays real
+            b01 = b10 = Z{0.0, 0.0};
+            b00.i = 0.0;
+            b11.i = 0.0;
+          }
+          auto st2 = [&](bool ok, int i, int j, Z v) {
+            if (ok) { a_(i, j)[0] = v.r; a_(i, j)[1] = v.i; }
+          };
+          st2(true, p1, p2, b00); st2(c2, p1, q2, b01); st2(r2, q1, p2, b10); st2(r2 && c2, q1, q2, b11);
+        }
+      }
+      // (b') V <- V G
+      for (int t = tid; t < n * npair; t += nth) {
+        const int r = t / npair, k = t - r * npair;
+        const double* R = rot + 6 * k;
+        const int p = (int)R[4], q = (int)R[5];
+        if (q >= n || R[1] == 0.0) continue;
+        const double c = R[0], sn = R[1];
+        double* vp = Vs + ((int64_t)r * n + p) * E;
+        double* vq = Vs + ((int64_t)r * n + q) * E;
+        if constexpr (!CPLX) {
+          const double x = vp[0], y = vq[0] * R[2];
+          vp[0] = x * c - y * sn;
+          vq[0] = x * sn + y * c;
+        } else {
+          const Z emi{R[2], -R[3]};
+          const Z x{vp[0], vp[1]}, y{vq[0], vq[1]};
+          const Z ye = zmul(y, emi);
+          vp[0] = x.r * c - ye.r * sn; vp[1] = x.i * c - ye.i * sn;
+          vq[0] = x.r * sn + ye.r * c; vq[1] = x.i * sn + ye.i * c;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) { status[0] = sweep < 60 ? 0 : OEFE_ENOCONV; status[1] = sweep; }
+  // ascending order by rank
+  for (int i = tid; i < n; i += nth) {
+    const double li = a_(i, i)[0];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = a_(j, j)[0];
+      if (lj < li || (lj == li && j < i)) ++rank;
+    }
+    lam[rank] = li;
+    for (int r = 0; r < n; ++r) {
+      U[((int64_t)r * n + rank) * E] = Vs[((int64_t)r * n + i) * E];
+      if (CPLX) U[((int64_t)r * n + rank) * E + 1] = Vs[((int64_t)r * n + i) * E + 1];
+    }
+  }
+}
+
+// ---- Cholesky of the Jacobi-scaled Gram matrix and triangular inverse in LDS (small n).
+// Same scaling, pivots and breakdown rule as chol_kernel; G is only read.
+template <bool CPLX>
+__global__ __launch_bounds__(512) void chol_lds_kernel(const double* __restrict__ G, int ldg, int n,
+                                                       double* __restrict__ Rinv, double* __restrict__ dsc,
+                                                       int32_t* __restrict__ status) {
+  constexpr int E = CPLX ? 2 : 1;
+  extern __shared__ double sm[];
+  double* L = sm;                        // [n][n] lower factor (row-major)
+  double* Li = L + (size_t)n * n * E;    // [n][n] its inverse (lower)
+  double* d = Li + (size_t)n * n * E;    // [n] Jacobi scaling
+  __shared__ int bad;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (tid == 0) bad = -1;
+  __syncthreads();
+  for (int i = tid; i < n; i += nth) {
+    const double gii = G[((int64_t)i * ldg + i) * E];
+    if (!(gii > 0.0)) atomicMax(&bad, i);
+    d[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+    dsc[i] = d[i];
+  }
+  __syncthreads();
+  if (bad >= 0) {
+    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
+    return;
+  }
+  for (int t = tid; t < n * n; t += nth) {
+    const int i = t / n, j = t - i * n;
+    const double sc = d[i] * d[j];
+    L[(int64_t)t * E] = G[((int64_t)i * ldg + j) * E] * sc;
+    if (CPLX) L[(int64_t)t * E + 1] = G[((int64_t)i * ldg + j) * E + 1] * sc;
+    Li[(int64_t)t * E] = 0.0;
+    if (CPLX) Li[(int64_t)t * E + 1] = 0.0;
+  }
+  __syncthreads();
+  auto re = [&](int i, int j) -> double& { return L[((int64_t)i * n + j) * E]; };
+  auto im = [&](int i, int j) -> double& { return L[((int64_t)i * n + j) * E + (E - 1)]; };
+  for (int k = 0; k < n; ++k) {
+    // breakdown: a pivot of the unit-diagonal (Jacobi-scaled) Gram matrix at or below
+    // n * 2^-52, i.e. numerically rank deficient in float64 (every thread sees the same value)
+    const double dk = re(k, k);
+    if (!(dk > n * 2.220446049250313e-16) || !isfinite(dk)) {
+      if (tid == 0) bad = k;
+      break;
+    }
+    const double l = sqrt(dk);
+    for (int i = k + 1 + tid; i < n; i += nth) {
+      re(i, k) /= l;
+      if (CPLX) im(i, k) /= l;
+    }
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int t = tid; t < m * m; t += nth) {
+      const int ii = t / m, jj = t - ii * m;
+      if (jj > ii) continue;
+      const int i = k + 1 + ii, j = k + 1 + jj;
+      if constexpr (!CPLX) {
+        re(i, j) -= re(i, k) * re(j, k);
+      } else {
+        const double ar = re(i, k), ai = im(i, k), br = re(j, k), bi = im(j, k);
+        re(i, j) -= ar * br + ai * bi;
+        im(i, j) -= ai * br - ar * bi;
+      }
+    }
+    if (tid == 0) {
+      re(k, k) = l;
+      if (CPLX) im(k, k) = 0.0;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (bad >= 0) {
+    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
+    return;
+  }
+  // L^-1 row by row: Li[i][j] = -(sum_{k=j}^{i-1} L[i][k] Li[k][j]) / L[i][i], Li[i][i] = 1 / L[i][i];
+  // 8 lanes per entry, partial sums combined by lane shuffles
+  const int sub = tid & 7;
+  for (int i = 0; i < n; ++i) {
+    const double lii = re(i, i);
+    for (int j0 = 0; j0 <= i; j0 += nth / 8) {
+      const int j = j0 + (tid >> 3);
+      double sr = 0.0, si = 0.0;
+      if (j < i)
+        for (int k = j + sub; k < i; k += 8) {
+          const double lr = re(i, k), lm = CPLX ? im(i, k) : 0.0;
+          const double yr = Li[((int64_t)k * n + j) * E], yi = CPLX ? Li[((int64_t)k * n + j) * E + 1] : 0.0;
+          sr += lr * yr - lm * yi;
+          si += lr * yi + lm * yr;
+        }
+      for (int o = 4; o > 0; o >>= 1) {
+        sr += __shfl_xor(sr, o, 8);
+        si += __shfl_xor(si, o, 8);
+      }
+      if (sub == 0 && j <= i) {
+        Li[((int64_t)i * n + j) * E] = (j == i ? 1.0 : -sr) / lii;
+        if (CPLX) Li[((int64_t)i * n + j) * E + 1] = (j == i ? 0.0 : -si) / lii;
+      }
+    }
+    __syncthreads();
+  }
+  // Rinv = diag(d) Linv^*: Rinv[i][j] = d_i conj(Li[j][i]) (upper triangular)
+  for (int t = tid; t < n * n; t += nth) {
+    const int i = t / n, j = t - i * n;
+    const double* y = Li + ((int64_t)j * n + i) * E;
+    Rinv[(int64_t)t * E] = d[i] * y[0];
+    if (CPLX) Rinv[(int64_t)t * E + 1] = -d[i] * y[1];
+  }
+  if (tid == 0) { status[0] = 0; status[1] = -1; }
 }
 
 template <bool CPLX>
@@ -637,6 +923,16 @@ int gemm_nn(bool cplx, const double* A, int64_t lda, const double* B, int ldb, d
 int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s) {
   // dsc stored after Rinv (caller reserves n extra doubles)
   double* dsc = Rinv + (size_t)n * n * (cplx ? 2 : 1);
+  const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + n) * sizeof(double);
+  if (lds <= 150 * 1024) {
+    const void* fn = cplx ? (const void*)chol_lds_kernel<true> : (const void*)chol_lds_kernel<false>;
+    if (allow_dynamic_lds(fn, lds) != hipSuccess) return OEFE_EDEVICE;
+    if (cplx)
+      hipLaunchKernelGGL(chol_lds_kernel<true>, dim3(1), dim3(512), lds, s, G, ldg, n, Rinv, dsc, status);
+    else
+      hipLaunchKernelGGL(chol_lds_kernel<false>, dim3(1), dim3(512), lds, s, G, ldg, n, Rinv, dsc, status);
+    return check();
+  }
   if (cplx)
     hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(1024), 0, s, G, ldg, n, Rinv, dsc, status);
   else
@@ -650,22 +946,14 @@ size_t jacobi_scratch_bytes(bool cplx, int n) {
 }
 
 int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s) {
-  const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + 6 * (n / 2 + 1) + 1024) * sizeof(double);
-  if (lds <= 160 * 1024) {
-    static bool attr_set[2] = {false, false};
-    if (!attr_set[cplx]) {
-      if (cplx)
-        (void)hipFuncSetAttribute((const void*)jacobi_lds_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-      else
-        (void)hipFuncSetAttribute((const void*)jacobi_lds_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-      attr_set[cplx] = true;
-    }
+  const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + 6 * (n / 2 + 1) + 16) * sizeof(double);
+  if (lds <= 150 * 1024) {
+    const void* fn = cplx ? (const void*)jacobi_lds_kernel<true> : (const void*)jacobi_lds_kernel<false>;
+    if (allow_dynamic_lds(fn, lds) != hipSuccess) return OEFE_EDEVICE;
     if (cplx)
-      hipLaunchKernelGGL(jacobi_lds_kernel<true>, dim3(1), dim3(1024), lds, s, A, n, lam, U, status);
+      hipLaunchKernelGGL(jacobi_lds_kernel<true>, dim3(1), dim3(512), lds, s, A, n, lam, U, status);
     else
-      hipLaunchKernelGGL(jacobi_lds_kernel<false>, dim3(1), dim3(1024), lds, s, A, n, lam, U, status);
+      hipLaunchKernelGGL(jacobi_lds_kernel<false>, dim3(1), dim3(512), lds, s, A, n, lam, U, status);
     return check();
   }
   double* V = scratch;

@@ -625,6 +625,7 @@ __global__ __launch_bounds__(256) void enr_reduce1_kernel(KBatch<T> kb, int nch,
 // CPLX), 16x16 output tile per workgroup, LDS-staged K tiles.
 //   mode 0: zo = S x^O       mode 1: wp = (sum of the folded tile partials) + H^oo zo
 //   mode 2: out^O = alpha (S wp - c x^O) - beta prev^O
+//   mode 3: zo = S out^O      (Z^O of the next recurrence step)
 template <typename T, bool CPLX>
 __global__ __launch_bounds__(256) void small_gemm_kernel(KBatch<T> kb, int mode, int64_t N, int n) {
   constexpr int E = CPLX ? 2 : 1;
@@ -636,8 +637,10 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(KBatch<T> kb, int mode,
   if ((int)blockIdx.x * TS >= m) return;
   const int k = n;
   const T* __restrict__ A = mode == 1 ? P.Hoo : P.S;
-  const T* __restrict__ B = mode == 0 ? P.x + N * P.ldx : (mode == 1 ? P.zo : P.wp);
-  const int64_t ldb = mode == 0 ? P.ldx : (int64_t)P.ncr;
+  const T* __restrict__ B = mode == 0 ? P.x + N * P.ldx
+                           : mode == 3 ? P.out + N * P.ldo
+                                       : (mode == 1 ? P.zo : P.wp);
+  const int64_t ldb = mode == 0 ? P.ldx : mode == 3 ? P.ldo : (int64_t)P.ncr;
   const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
   const int i = blockIdx.y * TS + ty;   // row
   const int jc = blockIdx.x * TS + tx;  // column (complex element)
@@ -662,7 +665,7 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(KBatch<T> kb, int mode,
     __syncthreads();
   }
   if (i >= n || jc >= m) return;
-  if (mode == 0) {
+  if (mode == 0 || mode == 3) {
     P.zo[(int64_t)i * P.ncr + (int64_t)jc * E] = sr;
     if (CPLX) P.zo[(int64_t)i * P.ncr + (int64_t)jc * E + 1] = si;
   } else if (mode == 1) {
@@ -920,12 +923,7 @@ void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, 
 template <typename T, int NB, bool CPLX>
 void launch_node_nb(const oefe_op_s* op, const KBatch<T>& kb, int ncb, hipStream_t s) {
   const size_t lds = node_lds_bytes<T, NB, CPLX>(op->n_enr > 0 ? op->tile_fpmax : 0);
-  static bool attr_set = false;  // per instantiation; the limit is the CU's 160 KB
-  if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fe_node_mfma_kernel<T, NB, CPLX>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
+  if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_node_mfma_kernel<T, NB, CPLX>), lds) != hipSuccess) return;
   hipLaunchKernelGGL((fe_node_mfma_kernel<T, NB, CPLX>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb,
                      (unsigned)kb.nk), dim3(256), lds, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op),
                      op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N);
@@ -949,7 +947,7 @@ inline int reduce_chunks(const oefe_op_s* op) { return std::max(1, (int)cdiv(op-
 
 // Steps of several operators sharing one mesh and enrichment layout, in lockstep.
 template <typename T, bool CPLX>
-int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipStream_t s) {
+int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipStream_t s, const Overlap* ov) {
   const oefe_op_s* op = ops[0];
   int max_ncr = 0, max_nv = 0;
   for (int q = 0; q < kb.nk; ++q) {
@@ -958,7 +956,8 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
   }
   const unsigned nk = (unsigned)kb.nk;
   const int nO = op->n_enr;
-  if (nO > 0)
+  const bool ovl = ov != nullptr && nO > 0;
+  if (nO > 0 && (!ovl || ov->first))
     hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
                        dim3(256), 0, s, kb, 0, op->N, nO);
   // optional HIP events around one stage (oefe_kernel_timer)
@@ -979,15 +978,27 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
   const int nb_all = (int)cdiv(max_ncr, 16);
   const int ncb = (int)cdiv(nb_all, nbcap);
   const int NB = (int)cdiv(nb_all, ncb);
+  // the node stage needs this step's Z^O, computed by the previous step's side chain
+  if (ovl && !ov->first) (void)hipStreamWaitEvent(s, ov->ev_zo, 0);
   timed(OEFE_TIMER_NODE, [&] { launch_node<T, CPLX>(op, kb, NB, ncb, s); });
   if (nO > 0) {
+    hipStream_t se = s;
+    if (ovl) {
+      (void)hipEventRecord(ov->ev_node, s);
+      (void)hipStreamWaitEvent(ov->side, ov->ev_node, 0);
+      se = ov->side;
+    }
     const int nch = reduce_chunks(op);
+    const dim3 gg((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk);
     hipLaunchKernelGGL((enr_reduce1_kernel<T>), dim3((unsigned)(nO * nch), (unsigned)cdiv(max_ncr, 64), nk),
-                       dim3(256), 0, s, kb, nch, op->d.fn_pptr, op->d.fn_poff);
-    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
-                       dim3(256), 0, s, kb, 1, op->N, nO);
-    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
-                       dim3(256), 0, s, kb, 2, op->N, nO);
+                       dim3(256), 0, se, kb, nch, op->d.fn_pptr, op->d.fn_poff);
+    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 1, op->N, nO);
+    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 2, op->N, nO);
+    if (ovl) {
+      if (!ov->last) hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 3, op->N, nO);
+      (void)hipEventRecord(ov->ev_zo, se);
+      if (ov->last) (void)hipStreamWaitEvent(s, ov->ev_zo, 0);
+    }
   }
   return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
 }
@@ -1079,7 +1090,7 @@ StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv,
 
 template <typename T>
 int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
-               double alpha, double c, double beta, const StepWork& w, hipStream_t s) {
+               double alpha, double c, double beta, const StepWork& w, hipStream_t s, const Overlap* ov) {
   if (bf16) return OEFE_EUNSUPPORTED;
   if (!x || !out || (beta != 0.0 && !prev)) return OEFE_EINVAL;  // prev is read only when beta != 0
   if (op->diagonal) {
@@ -1093,19 +1104,19 @@ int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* 
   kb.nk = 1;
   kb.k[0] = make_kp<T>(op, x, ld, prev, out, ldo, nv, alpha, c, beta, w);
   const oefe_op_s* ops[1] = {op};
-  if (op->cplx) return apply_step_batch_impl<T, true>(ops, kb, s);
-  return apply_step_batch_impl<T, false>(ops, kb, s);
+  if (op->cplx) return apply_step_batch_impl<T, true>(ops, kb, s, ov);
+  return apply_step_batch_impl<T, false>(ops, kb, s, ov);
 }
 
 template int apply_step<double>(const oefe_op_s*, bool, const double*, int64_t, const double*, double*, int64_t, int,
-                                double, double, double, const StepWork&, hipStream_t);
+                                double, double, double, const StepWork&, hipStream_t, const Overlap*);
 template int apply_step<float>(const oefe_op_s*, bool, const float*, int64_t, const float*, float*, int64_t, int,
-                               double, double, double, const StepWork&, hipStream_t);
+                               double, double, double, const StepWork&, hipStream_t, const Overlap*);
 
 template <typename T>
 int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* const* x, const int64_t* ld,
                      const T* const* prev, T* const* out, const int64_t* ldo, const int* nv, const double* alpha,
-                     const double* c, const double* beta, const StepWork* w, hipStream_t s) {
+                     const double* c, const double* beta, const StepWork* w, hipStream_t s, const Overlap* ov) {
   if (bf16) return OEFE_EUNSUPPORTED;
   for (int q = 0; q < nk; ++q)  // the kernels read prev only when beta is nonzero
     if (!x[q] || !out[q] || (beta[q] != 0.0 && !prev[q])) return OEFE_EINVAL;
@@ -1115,8 +1126,10 @@ int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* co
     for (int q = 0; q < kb.nk; ++q)
       kb.k[q] = make_kp<T>(ops[q0 + q], x[q0 + q], ld[q0 + q], prev[q0 + q], out[q0 + q], ldo[q0 + q], nv[q0 + q],
                            alpha[q0 + q], c[q0 + q], beta[q0 + q], w[q0 + q]);
-    const int rc = ops[0]->cplx ? apply_step_batch_impl<T, true>(ops + q0, kb, s)
-                                : apply_step_batch_impl<T, false>(ops + q0, kb, s);
+    // overlap only when the whole batch is one launch group
+    const Overlap* o = nk <= KMAX ? ov : nullptr;
+    const int rc = ops[0]->cplx ? apply_step_batch_impl<T, true>(ops + q0, kb, s, o)
+                                : apply_step_batch_impl<T, false>(ops + q0, kb, s, o);
     if (rc) return rc;
   }
   return OEFE_OK;
@@ -1124,10 +1137,10 @@ int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* co
 
 template int apply_step_batch<double>(const oefe_op_s* const*, int, bool, const double* const*, const int64_t*,
                                       const double* const*, double* const*, const int64_t*, const int*, const double*,
-                                      const double*, const double*, const StepWork*, hipStream_t);
+                                      const double*, const double*, const StepWork*, hipStream_t, const Overlap*);
 template int apply_step_batch<float>(const oefe_op_s* const*, int, bool, const float* const*, const int64_t*,
                                      const float* const*, float* const*, const int64_t*, const int*, const double*,
-                                     const double*, const double*, const StepWork*, hipStream_t);
+                                     const double*, const double*, const StepWork*, hipStream_t, const Overlap*);
 
 template <typename T>
 int zo_only(const oefe_op_s* op, const T* x, int64_t ld, int nv, T* zo, int ncr, hipStream_t s) {
