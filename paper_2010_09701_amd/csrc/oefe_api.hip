@@ -699,6 +699,81 @@ int oefe_set_launch_shape(oefe_op op, int32_t cw, int32_t cb) {
 }  // extern "C"
 
 namespace {
+// Launch-shape tuner: times one batched operator step (out = alpha (Ht x - c x) - beta out,
+// the filter's access pattern, bounded values) for each candidate cell-tile width cw and
+// node vector-block width cb, and keeps the fastest on every operator.
+template <typename T>
+int autotune_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const int64_t* ld, const int32_t* nv,
+                  int reps, void* work, int32_t* cw_out, int32_t* cb_out, double* ms_out, hipStream_t s) {
+  const int eb = sizeof(T);
+  std::vector<StepWork> sw(nk);
+  std::vector<const T*> xin(nk), pin(nk);
+  std::vector<T*> outp(nk);
+  std::vector<int> nvv(nk);
+  std::vector<int64_t> ldp(nk);
+  std::vector<double> al(nk, 1e-3), cc(nk, 0.0), be(nk, 0.5);
+  char* p = (char*)work;
+  for (int q = 0; q < nk; ++q) {
+    const int E = ops[q]->cplx ? 2 : 1;
+    sw[q] = carve_step_work(ops[q], eb, ops[q]->cplx, nv[q], p);
+    p += al256(step_work_bytes(ops[q], eb, ops[q]->cplx, nv[q], nullptr));
+    T* A = (T*)p;
+    p += al256((size_t)ops[q]->n_tot * nv[q] * E * eb);
+    T* B = (T*)p;
+    p += al256((size_t)ops[q]->n_tot * nv[q] * E * eb);
+    int rc = cast_block(X[q], eb == 4, A, eb == 4, ops[q]->n_tot, ld[q] * E, (int64_t)nv[q] * E, nv[q] * E, s);
+    if (!rc) rc = cast_block(X[q], eb == 4, B, eb == 4, ops[q]->n_tot, ld[q] * E, (int64_t)nv[q] * E, nv[q] * E, s);
+    if (rc) return rc;
+    xin[q] = A;
+    pin[q] = B;
+    outp[q] = B;
+    nvv[q] = nv[q];
+    ldp[q] = nv[q];
+  }
+  const oefe_op_s* const* opp = (const oefe_op_s* const*)ops;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return OEFE_EDEVICE;
+  const int cws[4] = {8, 16, 32, 64};
+  const int cbs[4] = {32, 64, 96, 128};
+  double best = 1e300;
+  int bcw = 0, bcb = 0, rc = OEFE_OK;
+  for (int a = 0; a < 4 && !rc; ++a)
+    for (int b = 0; b < 4 && !rc; ++b) {
+      for (int q = 0; q < nk; ++q) {
+        ops[q]->tune_cw = cws[a];
+        ops[q]->tune_cb = cbs[b];
+      }
+      auto step = [&] {
+        return apply_step_batch<T>(opp, nk, bf16, xin.data(), ldp.data(), pin.data(), outp.data(), ldp.data(),
+                                   nvv.data(), al.data(), cc.data(), be.data(), sw.data(), s);
+      };
+      rc = step();  // warm-up (first launch of this instantiation)
+      if (rc) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps && !rc; ++r) rc = step();
+      (void)hipEventRecord(e1, s);
+      float ms = 0.f;
+      if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = OEFE_EDEVICE;
+      if (!rc && ms / reps < best) {
+        best = ms / reps;
+        bcw = cws[a];
+        bcb = cbs[b];
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int q = 0; q < nk; ++q) {
+    ops[q]->tune_cw = rc ? 0 : bcw;
+    ops[q]->tune_cb = rc ? 0 : bcb;
+  }
+  if (rc) return rc;
+  if (cw_out) *cw_out = bcw;
+  if (cb_out) *cb_out = bcb;
+  if (ms_out) *ms_out = best;
+  return OEFE_OK;
+}
+
 template <typename T>
 int filter_batched_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const int64_t* ld, const int32_t* nv,
                         int m, const double* abc, void* work, hipStream_t s) {
@@ -803,6 +878,30 @@ int chebyshev_filter_batched(int32_t nk, const oefe_op* ops, oefe_prec prec, voi
     rc = filter_batched_impl<double>(nk, ops, false, X, ld, nv, m, abc, work, s);
   if (rc == OEFE_EUNSUPPORTED) return fail(rc, "precision not supported by chebyshev_filter_batched");
   if (rc) return fail(rc, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return OEFE_OK;
+}
+
+int oefe_autotune(int32_t nk, const oefe_op* ops, oefe_prec prec, void* const* X, const int64_t* ld, const int32_t* nv,
+                  int32_t reps, void* work, int32_t* cw_out, int32_t* cb_out, double* ms_per_step,
+                  oefe_stream stream) {
+  if (nk <= 0 || !ops || !X || !ld || !nv || !work || reps <= 0) return fail(OEFE_EINVAL, "bad arguments");
+  for (int q = 0; q < nk; ++q) {
+    if (!ops[q] || ops[q]->diagonal || !X[q] || nv[q] <= 0 || ld[q] < nv[q]) return fail(OEFE_EINVAL, "bad block");
+    if (int rc = check_prec(ops[q], prec)) return rc;
+    const oefe_op_s* a = ops[0];
+    const oefe_op_s* b = ops[q];
+    if (b->nc != a->nc || b->p != a->p || b->L != a->L || b->n_enr != a->n_enr || b->cplx != a->cplx ||
+        b->n_tiles != a->n_tiles || b->tile_slots != a->tile_slots || b->tile_fpmax != a->tile_fpmax)
+      return fail(OEFE_EINVAL, "operators must share mesh and enrichment layout");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (prec_fp32(prec))
+    rc = autotune_impl<float>(nk, ops, prec == OEFE_BF16, X, ld, nv, reps, work, cw_out, cb_out, ms_per_step, s);
+  else
+    rc = autotune_impl<double>(nk, ops, false, X, ld, nv, reps, work, cw_out, cb_out, ms_per_step, s);
+  if (rc == OEFE_EUNSUPPORTED) return fail(rc, "precision not supported by oefe_autotune");
+  if (rc) return fail(rc, "oefe_autotune failed");
   return OEFE_OK;
 }
 

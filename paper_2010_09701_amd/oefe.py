@@ -70,6 +70,7 @@ def _load():
         "chebyshev_filter_batched": ([i32, vp, i32, vp, vp, vp, i32, vp, vp, vp], i32),
         "oefe_batched_work_size": ([i32, vp, i32, vp], ctypes.c_size_t),
         "oefe_set_launch_shape": ([vp, i32, i32], i32),
+        "oefe_autotune": ([i32, vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp], i32),
         "lanczos_bounds": ([vp, i32, vp, vp, vp, vp], i32),
         "cholgs": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
@@ -92,6 +93,7 @@ EXPORTED = [
     "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
     "chebyshev_filter_mixed", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
+    "oefe_autotune",
     "lanczos_bounds", "cholgs", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_strerror", "oefe_last_error",
 ]
@@ -310,6 +312,63 @@ def chebyshev_filter_batched(ops, Xs, m: int, abc, bf16: bool = False):
 
 def set_launch_shape(op: Operator, cw: int = 0, cb: int = 0):
     _check(_lib.oefe_set_launch_shape(op.handle, int(cw), int(cb)), "oefe_set_launch_shape")
+
+
+def _tune_key(ops, Xs, prec) -> str:
+    o = ops[0]
+    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    nvs = ",".join(str(_block(X, op.n_tot)[1]) for op, X in zip(ops, Xs))
+    return (f"{dev}|nc={o.nc}|p={o.p}|n_enr={o.n_enr}|slots={o.tile_slots}|cplx={int(o.is_complex)}|prec={prec}"
+            f"|nv={nvs}")
+
+
+def autotune(ops, Xs, reps: int = 3, cache: Optional[str] = None, bf16: bool = False):
+    """Choose the launch shape (cell-tile width cw, node vector-block width cb) for a batch.
+
+    The library times each candidate on copies of the blocks (oefe_autotune) and sets the
+    fastest on every operator.  With `cache` (a JSON file), a shape measured before for the
+    same device, mesh, enrichment layout, precision and block widths is reused without timing.
+    Returns {"cw", "cb", "ms_per_step", "cached"}.
+    """
+    import json
+    nk = len(ops)
+    if nk == 0 or nk != len(Xs):
+        raise ValueError("ops and Xs must be non-empty and of equal length")
+    prec = _prec(Xs[0], bf16)
+    key = _tune_key(ops, Xs, prec)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+        if key in table:
+            r = table[key]
+            for op in ops:
+                set_launch_shape(op, r["cw"], r["cb"])
+            return dict(r, cached=True)
+    lds, nvs = [], []
+    for op, X in zip(ops, Xs):
+        ld, nv = _block(X, op.n_tot)
+        lds.append(ld)
+        nvs.append(nv)
+    H = (ctypes.c_void_p * nk)(*[o.handle.value if isinstance(o.handle, ctypes.c_void_p) else o.handle for o in ops])
+    P = (ctypes.c_void_p * nk)(*[X.data_ptr() for X in Xs])
+    LD = (ctypes.c_int64 * nk)(*lds)
+    NV = (ctypes.c_int32 * nk)(*nvs)
+    need = int(_lib.oefe_batched_work_size(nk, H, prec, NV))
+    w = torch.empty(need, dtype=torch.uint8, device="cuda")
+    cw, cb, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(_lib.oefe_autotune(nk, H, prec, P, LD, NV, int(reps), _ptr(w), ctypes.byref(cw), ctypes.byref(cb),
+                              ctypes.byref(ms), _stream()), "oefe_autotune")
+    r = {"cw": int(cw.value), "cb": int(cb.value), "ms_per_step": float(ms.value)}
+    if cache:
+        table[key] = r
+        d = os.path.dirname(os.path.abspath(cache))
+        os.makedirs(d, exist_ok=True)
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return dict(r, cached=False)
 
 
 def lanczos_bounds(op: Operator, v0: torch.Tensor, k: int = 10) -> Tuple[float, float]:

@@ -6,6 +6,7 @@ library.  The paper prints no values that apply to these synthetic operators.
 
     python tests/golden/make_golden.py diamond8     (about 10 min on 8 cores)
     python tests/golden/make_golden.py diamond64    (about 20 min)
+    python tests/golden/make_golden.py kpoints      (about 5 min)
 """
 import os
 import sys
@@ -67,7 +68,28 @@ def diamond64():
                         hx_colnorm=hx_colnorm, Moo_eigs=op.enr.Moo_eigs)
 
 
+def kpoints():
+    """diamond8 at the 8 k-points of the 2x2x2 Monkhorst-Pack grid, uneven complex blocks."""
+    base = wl.config("diamond8").system
+    ks = wl.monkhorst_pack_2(base.L)
+    out = {}
+    t = time.time()
+    for q, kv in enumerate(ks):
+        op = OEFEOperator(base.with_k(kv))
+        nv = wl.KPOINT_NV[q]
+        X0 = wl.start_block(op.n_tot, nv, 10 + q, complex_=True)
+        rows = sample_rows(op.N, op.n_enr, 100, 30 + q)
+        hx_rows = np.empty((rows.size, nv), dtype=np.complex128)
+        for j0 in range(0, nv, 32):
+            hx_rows[:, j0:j0 + 32] = op.apply(X0[:, j0:j0 + 32])[rows]
+        out[f"k{q}"] = kv
+        out[f"rows{q}"] = rows
+        out[f"hx_rows{q}"] = hx_rows
+        print("k-point", q, nv, time.time() - t, flush=True)
+    np.savez_compressed(os.path.join(HERE, "kpoints_oracle.npz"), **out)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["diamond8"]
     for w in which:
-        {"diamond8": diamond8, "diamond64": diamond64}[w]()
+        {"diamond8": diamond8, "diamond64": diamond64, "kpoints": kpoints}[w]()

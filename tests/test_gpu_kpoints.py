@@ -1,0 +1,135 @@
+"""Bloch k-points in one batched filter (chebyshev_filter_batched) and the launch-shape autotuner.
+
+* small system, 3 k-points with uneven blocks: the batched complex128 / complex64
+  filter against the oracle's filter of each k-point;
+* diamond8 at the 8 k-points of the 2x2x2 Monkhorst-Pack grid with 48..96 vectors:
+  the operator on sampled rows against stored oracle values, and the batched filter
+  against one filter per operator (the same arithmetic, so equal to rounding);
+* the autotuner: the chosen shape is one of the candidates, results do not depend on
+  the shape, and a JSON cache entry is reused.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import chfsi as och
+from oracle.operator import OEFEOperator
+from paper_2010_09701_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2010_09701_amd import oefe
+    return oefe
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _colrel(A, B):
+    return float((np.linalg.norm(A - B, axis=0) / np.linalg.norm(B, axis=0)).max())
+
+
+def _small_kpoints():
+    base = wl.tiny_system(nc=3, p=2, n_atoms=2, seed=13, L=6.0, r0=1.0, r1=2.3)
+    ks = [np.array([0.3, -0.2, 0.1]), np.array([-0.5, 0.25, 0.4]), np.zeros(3) + 0.05]
+    return [base.with_k(k) for k in ks], [3, 5, 7]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_batched_filter_matches_oracle_small(lib, prec):
+    import torch
+    systems, nvs = _small_kpoints()
+    m = 6
+    ops, Xs, abc, ref = [], [], [], []
+    for q, (sysk, nv) in enumerate(zip(systems, nvs)):
+        oop = OEFEOperator(sysk)
+        lam = np.linalg.eigvalsh(oop.dense())
+        a0, b = lam[0] - 0.1, lam[-1] + 0.5
+        a = lam[nv + 1]
+        X0 = wl.start_block(oop.n_tot, nv, 40 + q, complex_=True)
+        ref.append(och.chebyshev_filter(oop.apply, X0, m, a, b, a0))
+        ops.append(lib.Operator(sysk))
+        Xs.append(_dev(X0, torch.complex128 if prec == "c128" else torch.complex64))
+        abc.append((a, b, a0))
+    lib.chebyshev_filter_batched(ops, Xs, m, abc)
+    tol = 1e-10 if prec == "c128" else 2e-4
+    for X, R in zip(Xs, ref):
+        assert _colrel(X.cpu().numpy().astype(np.complex128), R) < tol
+
+
+@pytest.fixture(scope="module")
+def mp_ops(lib):
+    base = wl.config("diamond8").system
+    ks = wl.monkhorst_pack_2(base.L)
+    return [lib.Operator(base.with_k(k)) for k in ks]
+
+
+def _mp_blocks(ops):
+    return [wl.start_block(op.n_tot, wl.KPOINT_NV[q], 10 + q, complex_=True) for q, op in enumerate(ops)]
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "kpoints_oracle.npz")), reason="golden file missing")
+def test_mp_grid_operator_rows(lib, mp_ops):
+    import torch
+    g = np.load(os.path.join(GOLD, "kpoints_oracle.npz"))
+    for q, (op, X0) in enumerate(zip(mp_ops, _mp_blocks(mp_ops))):
+        Y = lib.ham_apply(op, _dev(X0, torch.complex128)).cpu().numpy()
+        rows, ref = g[f"rows{q}"], g[f"hx_rows{q}"]
+        assert np.abs(Y[rows] - ref).max() / np.abs(ref).max() < 1e-10, q
+
+
+def _bounds(lib, ops):
+    import torch
+    out = []
+    for op in ops:
+        v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, 2)).cuda()
+        a0, b = lib.lanczos_bounds(op, v0, 10)
+        out.append((0.5 * (a0 + b), b, a0))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_mp_grid_batched_equals_per_operator(lib, mp_ops, prec):
+    import torch
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    blocks = _mp_blocks(mp_ops)
+    abc = _bounds(lib, mp_ops)
+    m = 4
+    Xb = [_dev(X, dt) for X in blocks]
+    lib.chebyshev_filter_batched(mp_ops, Xb, m, abc)
+    for q, op in enumerate(mp_ops):
+        Xs = _dev(blocks[q], dt)
+        lib.chebyshev_filter(op, Xs, m, *abc[q])
+        a, b = Xb[q].cpu().numpy(), Xs.cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max(), q
+
+
+def test_autotune_shape_and_cache(lib, mp_ops, tmp_path):
+    import torch
+    blocks = _mp_blocks(mp_ops)
+    abc = _bounds(lib, mp_ops)
+    m = 3
+    Xa = [_dev(X, torch.complex128) for X in blocks]
+    lib.chebyshev_filter_batched(mp_ops, Xa, m, abc)  # built-in shape
+    cache = str(tmp_path / "tune.json")
+    r = lib.autotune(mp_ops, [_dev(X, torch.complex128) for X in blocks], reps=2, cache=cache)
+    assert r["cw"] in (8, 16, 32, 64) and r["cb"] in (32, 64, 96, 128) and r["ms_per_step"] > 0
+    assert not r["cached"]
+    Xt = [_dev(X, torch.complex128) for X in blocks]
+    lib.chebyshev_filter_batched(mp_ops, Xt, m, abc)  # tuned shape
+    for a, b in zip(Xa, Xt):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    r2 = lib.autotune(mp_ops, [_dev(X, torch.complex128) for X in blocks], cache=cache)
+    assert r2["cached"] and (r2["cw"], r2["cb"]) == (r["cw"], r["cb"])
+    for op in mp_ops:
+        lib.set_launch_shape(op, 0, 0)
