@@ -217,10 +217,72 @@ int upload_potential_parts(oefe_op_s* op, std::string& err) {
   return OEFE_OK;
 }
 
+// Round-to-nearest-even float -> bf16 bit pattern (finite inputs).
+uint16_t to_bf16_bits(double x) {
+  const float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Dense cell matrices of the BF16 cell stage, padded to 128 x 128, in the A-fragment
+// order of the 16x16x32 bf16 MFMA: entry (mb, kb, lane, t) = A[16 mb + lane % 16][32 kb + 8 (lane / 16) + t].
+//   0: B   [q][a] = B1[qx][ax] B1[qy][ay] B1[qz][az]          (values at Gauss points)
+//   1: K   [a][b] = kappa (S1 x M1 x M1 + M1 x S1 x M1 + M1 x M1 x S1)   (exact Gauss stiffness)
+//   2: B^T [a][q] with the quadrature index of each 32-block in the order the MFMA
+//      result of B Z leaves it in the lanes: position 8g + t is point 4g + t (t < 4)
+//      or 16 + 4g + t - 4 (t >= 4) of the block.
+std::vector<uint16_t> bf16_cell_matrices(const oefe_op_s* op) {
+  const int P1 = op->P1, nd = P1 * P1 * P1;
+  double M1[8][8] = {}, S1[8][8] = {};
+  for (int a = 0; a < P1; ++a)
+    for (int b = 0; b < P1; ++b)
+      for (int q = 0; q < P1; ++q) {
+        M1[a][b] += op->gauss_w[q] * op->B1[q][a] * op->B1[q][b];
+        S1[a][b] += op->gauss_w[q] * op->D1[q][a] * op->D1[q][b];
+      }
+  const double kappa = op->h / 4.0;
+  auto dec = [&](int a, int& x, int& y, int& z) { x = a % P1; y = (a / P1) % P1; z = a / (P1 * P1); };
+  auto Bm = [&](int q, int a) {
+    if (q >= nd || a >= nd) return 0.0;
+    int qx, qy, qz, ax, ay, az;
+    dec(q, qx, qy, qz);
+    dec(a, ax, ay, az);
+    return op->B1[qx][ax] * op->B1[qy][ay] * op->B1[qz][az];
+  };
+  auto Km = [&](int a, int b) {
+    if (a >= nd || b >= nd) return 0.0;
+    int ax, ay, az, bx, by, bz;
+    dec(a, ax, ay, az);
+    dec(b, bx, by, bz);
+    return kappa * (S1[ax][bx] * M1[ay][by] * M1[az][bz] + M1[ax][bx] * S1[ay][by] * M1[az][bz] +
+                    M1[ax][bx] * M1[ay][by] * S1[az][bz]);
+  };
+  std::vector<uint16_t> out(3 * 8 * 4 * 64 * 8);
+  for (int w = 0; w < 3; ++w)
+    for (int mb = 0; mb < 8; ++mb)
+      for (int kb = 0; kb < 4; ++kb)
+        for (int l = 0; l < 64; ++l)
+          for (int t = 0; t < 8; ++t) {
+            const int i = 16 * mb + l % 16, g = l / 16;
+            const int k = 32 * kb + 8 * g + t;
+            double v;
+            if (w == 0) v = Bm(i, k);
+            else if (w == 1) v = Km(i, k);
+            else v = Bm(32 * kb + (t < 4 ? 4 * g + t : 16 + 4 * g + t - 4), i);
+            out[((((size_t)w * 8 + mb) * 4 + kb) * 64 + l) * 8 + t] = to_bf16_bits(v);
+          }
+  return out;
+}
+
 int upload_operator(oefe_op_s* op, std::string& err) {
   int rc;
   const bool cplx = op->cplx;
   const int E = cplx ? 2 : 1;
+  if (!cplx) {
+    if ((rc = dput(&op->d.bf_mats, bf16_cell_matrices(op), err))) return rc;
+  }
   if (op->n_enr > 0) {
     const int nb = (int)op->blocks.size();
     std::vector<int32_t> fn0(nb), nf(nb), fn_blk(op->n_enr), blk_chunk0(nb + 1);
@@ -371,7 +433,7 @@ void free_device(oefe_op_s* op) {
   dfree(d.fn_poff); dfree(d.hv); dfree(d.hvf); dfree(d.fr_ptr); dfree(d.fr_fn); dfree(d.fr_val); dfree(d.fr_valf); dfree(d.chunk_blk);
   dfree(d.chunk_r0); dfree(d.chunk_r1); dfree(d.blk_chunk0); dfree(d.fn_blk); dfree(d.S); dfree(d.Hoo);
   dfree(d.Sf); dfree(d.Hoof); dfree(d.cph_ptr); dfree(d.cph_blk); dfree(d.cph_off); dfree(d.phi);
-  dfree(d.lambda); dfree(d.lambdaf);
+  dfree(d.lambda); dfree(d.lambdaf); dfree(d.bf_mats);
 }
 
 }  // namespace oefe

@@ -65,6 +65,9 @@ struct DeviceArrays {
   int32_t* tile_fns = nullptr;
   double* tile_val = nullptr;
   float* tile_valf = nullptr;
+  // the three dense cell matrices of the BF16 cell stage (B, K, B^T with permuted
+  // quadrature order), bf16 bit patterns in MFMA A-fragment order, 3 x 8 x 4 x 64 x 8
+  uint16_t* bf_mats = nullptr;
   int32_t* fn_pptr = nullptr;
   int32_t* fn_poff = nullptr;
   // transposed-product chunks: chunk c covers block chunk_blk[c], rows [chunk_r0[c], chunk_r1[c])

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "oefe_kernels.h"
 
@@ -296,6 +297,140 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, const T*
         int sx = cx * P1 + ax + 1;
         if (sx >= S) sx -= S;
         Yc[(rowyz + sx) * ldc + j] = y[ay * P1 + ax];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 cell kernel (real operators, float32 vectors): the cell operator in dense form
+//   U = B Z,  T = (W V) o U,  Y = K Z + B^T T
+// on the matrix cores (16x16x32 bf16 MFMA, float32 accumulation), with B, K, B^T
+// (128 x 128, zero-padded) held in LDS in A-fragment order.  Z (nodes x 16 columns of
+// one cell, m^-1/2 pre-scaled) and T are rounded to bf16; U and Y stay float32.  The
+// lane layout of the result of B Z is the operand layout of B^T T up to a fixed
+// permutation of each 32-point block, which is built into the stored B^T.  Each wave
+// takes (cell, 16-column block) tasks in turn; Y goes to the node-slot grid.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBf16MatElems = 8 * 4 * 64 * 8;  // one 128 x 128 matrix in fragment order
+
+__global__ __launch_bounds__(1024) void fe_cell_bf16_kernel(KBatch<float> kb, const uint16_t* __restrict__ mats,
+                                                           const float* __restrict__ WV, CellCoef<float> cf, int nc,
+                                                           int p, int n, int P1, int64_t n_cells) {
+  extern __shared__ unsigned char smem_raw[];
+  bf16x8* frag = reinterpret_cast<bf16x8*>(smem_raw);  // [3][8][4][64]
+  // per local node a < 128: (ax, ay, az) packed in 8-bit fields, and the m^-1/2 factor
+  int* ncode = reinterpret_cast<int*>(smem_raw + 3 * kBf16MatElems * sizeof(uint16_t));
+  float* nscale = reinterpret_cast<float*>(ncode + 128);
+  const int nd = P1 * P1 * P1;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(mats);
+    uint4* dst = reinterpret_cast<uint4*>(smem_raw);
+    for (int i = threadIdx.x; i < 3 * kBf16MatElems / 8; i += blockDim.x) dst[i] = src[i];
+    if (threadIdx.x < 128) {
+      const int a = threadIdx.x;
+      const int ax = a % P1, ay = (a / P1) % P1, az = a / (P1 * P1);
+      float om[kMaxP1];
+#pragma unroll
+      for (int i = 0; i < kMaxP1; ++i) om[i] = cf.om[i];
+      float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+      for (int i = 0; i < kMaxP1; ++i) {
+        sx = i == ax ? om[i] : sx;
+        sy = i == ay ? om[i] : sy;
+        sz = i == az ? om[i] : sz;
+      }
+      ncode[a] = a < nd ? (ax | (ay << 8) | (az << 16)) : 0;
+      nscale[a] = a < nd ? cf.mscale * sx * sy * sz : 0.0f;
+    }
+  }
+  __syncthreads();
+  const bf16x8* fB = frag;
+  const bf16x8* fK = frag + kBf16MatElems / 8;
+  const bf16x8* fBT = frag + 2 * kBf16MatElems / 8;
+  const KP<float>& P = kb.k[blockIdx.z];
+  const int ncr = P.ncr;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int ncb = (ncr + 15) / 16;
+  const int64_t ntask = n_cells * ncb;
+  const float* __restrict__ X = P.x;
+  const int64_t ldx = P.ldx;
+  float* __restrict__ Yc = P.ycell;
+  const int64_t ldc = P.ldc;
+  const int S = nc * P1;
+  for (int64_t task = (int64_t)blockIdx.x * nw + w; task < ntask; task += (int64_t)gridDim.x * nw) {
+    const int64_t e = task / ncb;
+    const int col = (int)(task - e * ncb) * 16 + c;
+    const bool cok = col < ncr;
+    const int cc = cok ? col : ncr - 1;
+    const int cx = (int)(e % nc), cy = (int)((e / nc) % nc), cz = (int)(e / ((int64_t)nc * nc));
+    const int bx = cx * p, by = cy * p, bz = cz * p;
+    // Z: node 32 k4 + 8 g + t of the cell, column col, scaled by m^-1/2 (one batch of loads)
+    bf16x8 z[4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // two batches of 16 loads
+      float zv[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int a = 32 * (2 * h + (i >> 3)) + 8 * g + (i & 7);
+        const int code = ncode[a];
+        int ix = bx + (code & 255), iy = by + ((code >> 8) & 255), iz = bz + (code >> 16);
+        ix -= ix >= n ? n : 0;
+        iy -= iy >= n ? n : 0;
+        iz -= iz >= n ? n : 0;
+        zv[i] = X[(ix + (int64_t)n * (iy + (int64_t)n * iz)) * ldx + cc];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        z[2 * h + (i >> 3)][i & 7] = (__bf16)(zv[i] * nscale[32 * (2 * h + (i >> 3)) + 8 * g + (i & 7)]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // U = B Z
+    f32x4 u[8];
+#pragma unroll
+    for (int mb = 0; mb < 8; ++mb) {
+      u[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4)
+        u[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fB[(mb * 4 + k4) * 64 + lane], z[k4], u[mb], 0, 0, 0);
+    }
+    // T = (W V) o U, as the operand of B^T T (point 16 mb + 4 g + v of U sits in lane g, element v)
+    const float* wv = WV + e * nd;
+    bf16x8 tq[4];
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q0 = 32 * k4 + 4 * g + v, q1 = q0 + 16;
+        const float w0 = wv[q0 < nd ? q0 : 0], w1 = wv[q1 < nd ? q1 : 0];
+        tq[k4][v] = (__bf16)(q0 < nd ? w0 * u[2 * k4][v] : 0.0f);
+        tq[k4][4 + v] = (__bf16)(q1 < nd ? w1 * u[2 * k4 + 1][v] : 0.0f);
+      }
+    // Y = K Z + B^T T, stored to the node-slot grid
+#pragma unroll 2
+    for (int mb = 0; mb < 8; ++mb) {
+      f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fK[(mb * 4 + k4) * 64 + lane], z[k4], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fBT[(mb * 4 + k4) * 64 + lane], tq[k4], y, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * mb + 4 * g + v;
+        if (cok && a < nd) {
+          const int code = ncode[a];
+          int sx = cx * P1 + (code & 255) + 1, sy = cy * P1 + ((code >> 8) & 255) + 1,
+              sz = cz * P1 + (code >> 16) + 1;
+          sx -= sx >= S ? S : 0;
+          sy -= sy >= S ? S : 0;
+          sz -= sz >= S ? S : 0;
+          Yc[(sx + (int64_t)S * (sy + (int64_t)S * sz)) * ldc + col] = y[v];
+        }
       }
     }
   }
@@ -946,8 +1081,19 @@ void launch_node(const oefe_op_s* op, const KBatch<T>& kb, int NB, int ncb, hipS
 inline int reduce_chunks(const oefe_op_s* op) { return std::max(1, (int)cdiv(op->fn_smax, kReduceChunk)); }
 
 // Steps of several operators sharing one mesh and enrichment layout, in lockstep.
+void launch_cell_bf16(const oefe_op_s* op, const KBatch<float>& kb, hipStream_t s) {
+  const size_t lds = 3 * (size_t)kBf16MatElems * sizeof(uint16_t) + 128 * (sizeof(int) + sizeof(float));
+  if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_cell_bf16_kernel), lds) != hipSuccess) return;
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipLaunchKernelGGL(fe_cell_bf16_kernel, dim3((unsigned)std::max(1, cus / kb.nk), 1, (unsigned)kb.nk), dim3(1024),
+                     lds, s, kb, op->d.bf_mats, op->d.WVf, op->cf, op->nc, op->p, op->n, op->P1, op->n_cells);
+}
+
 template <typename T, bool CPLX>
-int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipStream_t s, const Overlap* ov) {
+int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipStream_t s, const Overlap* ov,
+                          bool bf16) {
   const oefe_op_s* op = ops[0];
   int max_ncr = 0, max_nv = 0;
   for (int q = 0; q < kb.nk; ++q) {
@@ -971,8 +1117,15 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
       op->timer_events.emplace_back(ev0, ev1);
     }
   };
-  timed(OEFE_TIMER_CELL,
-        [&] { launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw > 0 ? op->tune_cw : pick_cw(max_ncr), s); });
+  timed(OEFE_TIMER_CELL, [&] {
+    if constexpr (std::is_same<T, float>::value && !CPLX) {
+      if (bf16) {
+        launch_cell_bf16(op, kb, s);
+        return;
+      }
+    }
+    launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw > 0 ? op->tune_cw : pick_cw(max_ncr), s);
+  });
   // node workgroup width: 16-column blocks, all real columns up to the cap, else near-equal
   const int nbcap = std::max(1, std::min(kNodeNBMax, op->tune_cb > 0 ? op->tune_cb / 16 : kNodeNBMax));
   const int nb_all = (int)cdiv(max_ncr, 16);
@@ -1091,7 +1244,8 @@ StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv,
 template <typename T>
 int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
                double alpha, double c, double beta, const StepWork& w, hipStream_t s, const Overlap* ov) {
-  if (bf16) return OEFE_EUNSUPPORTED;
+  // BF16 cell stage: real operators with float32 vectors and the dense-cell matrices
+  if (bf16 && (sizeof(T) != 4 || op->cplx || op->diagonal || !op->d.bf_mats)) return OEFE_EUNSUPPORTED;
   if (!x || !out || (beta != 0.0 && !prev)) return OEFE_EINVAL;  // prev is read only when beta != 0
   if (op->diagonal) {
     const DevPtrs<T> dp = devptrs<T>(op);
@@ -1104,8 +1258,8 @@ int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* 
   kb.nk = 1;
   kb.k[0] = make_kp<T>(op, x, ld, prev, out, ldo, nv, alpha, c, beta, w);
   const oefe_op_s* ops[1] = {op};
-  if (op->cplx) return apply_step_batch_impl<T, true>(ops, kb, s, ov);
-  return apply_step_batch_impl<T, false>(ops, kb, s, ov);
+  if (op->cplx) return apply_step_batch_impl<T, true>(ops, kb, s, ov, false);
+  return apply_step_batch_impl<T, false>(ops, kb, s, ov, bf16);
 }
 
 template int apply_step<double>(const oefe_op_s*, bool, const double*, int64_t, const double*, double*, int64_t, int,
@@ -1117,7 +1271,9 @@ template <typename T>
 int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* const* x, const int64_t* ld,
                      const T* const* prev, T* const* out, const int64_t* ldo, const int* nv, const double* alpha,
                      const double* c, const double* beta, const StepWork* w, hipStream_t s, const Overlap* ov) {
-  if (bf16) return OEFE_EUNSUPPORTED;
+  if (bf16)
+    for (int q = 0; q < nk; ++q)
+      if (sizeof(T) != 4 || ops[q]->cplx || ops[q]->diagonal || !ops[q]->d.bf_mats) return OEFE_EUNSUPPORTED;
   for (int q = 0; q < nk; ++q)  // the kernels read prev only when beta is nonzero
     if (!x[q] || !out[q] || (beta[q] != 0.0 && !prev[q])) return OEFE_EINVAL;
   for (int q0 = 0; q0 < nk; q0 += KMAX) {
@@ -1128,8 +1284,8 @@ int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* co
                            alpha[q0 + q], c[q0 + q], beta[q0 + q], w[q0 + q]);
     // overlap only when the whole batch is one launch group
     const Overlap* o = nk <= KMAX ? ov : nullptr;
-    const int rc = ops[0]->cplx ? apply_step_batch_impl<T, true>(ops + q0, kb, s, o)
-                                : apply_step_batch_impl<T, false>(ops + q0, kb, s, o);
+    const int rc = ops[0]->cplx ? apply_step_batch_impl<T, true>(ops + q0, kb, s, o, false)
+                                : apply_step_batch_impl<T, false>(ops + q0, kb, s, o, bf16);
     if (rc) return rc;
   }
   return OEFE_OK;

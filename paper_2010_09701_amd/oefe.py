@@ -113,6 +113,8 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def _prec(t: torch.Tensor, bf16: bool = False) -> int:
+    if bf16 and t.dtype != torch.float32:
+        raise TypeError("bf16 operands apply to float32 blocks of real operators")
     if t.dtype == torch.float64:
         return F64
     if t.dtype == torch.float32:
