@@ -16,8 +16,15 @@ from . import oefe
 
 
 def chfsi_run(op: "oefe.Operator", X0: torch.Tensor, v0: torch.Tensor, m: int, passes: int, lanczos_k: int = 10,
-              filter_prec: str = "f64", bounds: Optional[tuple] = None, callback=None) -> dict:
-    """Run `passes` ChFSI passes from X0 (float64 / complex128, on device); returns bounds and Ritz values."""
+              filter_prec="f64", bounds: Optional[tuple] = None, callback=None) -> dict:
+    """Run `passes` ChFSI passes from X0 (float64 / complex128, on device); returns bounds and Ritz values.
+
+    filter_prec: "f64", "f32" / "c64" or "bf16" for every pass, or a sequence with one entry per
+    pass (a precision schedule, e.g. bf16 for the first passes and f32 for the last).
+    """
+    sched = [filter_prec] * passes if isinstance(filter_prec, str) else list(filter_prec)
+    if len(sched) != passes:
+        raise ValueError("one filter precision per pass")
     if bounds is None:
         a0L, b = oefe.lanczos_bounds(op, v0, lanczos_k)
     else:
@@ -26,14 +33,15 @@ def chfsi_run(op: "oefe.Operator", X0: torch.Tensor, v0: torch.Tensor, m: int, p
     X = X0.clone()
     hist = []
     for it in range(passes):
-        if filter_prec == "f64":
+        fp = sched[it]
+        if fp == "f64":
             oefe.chebyshev_filter(op, X, m, a, b, a0)
-        elif filter_prec in ("f32", "c64"):
+        elif fp in ("f32", "c64"):
             oefe.chebyshev_filter_mixed(op, X, m, a, b, a0)
-        elif filter_prec == "bf16":
+        elif fp == "bf16":
             oefe.chebyshev_filter_mixed(op, X, m, a, b, a0, bf16=True)
         else:
-            raise ValueError(filter_prec)
+            raise ValueError(fp)
         oefe.cholgs(op, X)
         th = oefe.rayleigh_ritz(op, X).cpu().numpy()
         hist.append(dict(a=a, b=b, a0=a0, theta=th))

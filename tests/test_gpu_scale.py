@@ -1,0 +1,95 @@
+"""Differentiation at scale: diamond64 (2x2x2 supercell of diamond8: 64 atoms, 24^3 cells
+p = 4, 884,736 FE DoF + 320 enrichment functions), 320 vectors, float32 filter of degree 60.
+
+* 5 ChFSI passes with the float32 filter (float64 CholGS / Rayleigh-Ritz) against the same
+  passes with the float64 filter, whose operator is pinned to the oracle on sampled rows
+  (stored oracle values) at this size;
+* the band-energy adjoint at the float32-filtered Ritz vectors against central finite
+  differences (h = 1e-5, float64 energies) on 16 random potential perturbations
+  (seeds 100..115) and 4 random vector perturbations.  E is linear in V and quadratic in X,
+  so the differences are exact up to rounding, ~ u |E| / h.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2010_09701_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def d64():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2010_09701_amd import oefe
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    cfg = wl.config("diamond64")
+    gop = oefe.Operator(cfg.system)
+    X0 = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
+    v0 = torch.from_numpy(wl.lanczos_start(gop.n_tot, cfg.v0_seed)).cuda()
+    bounds = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k)
+    r32 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f32", bounds=bounds)
+    del X0
+    return oefe, cfg, gop, v0, bounds, r32
+
+
+def test_diamond64_float32_passes_vs_float64(d64):
+    import torch
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    oefe, cfg, gop, v0, bounds, r32 = d64
+    X0 = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
+    r64 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f64", bounds=bounds)
+    n_occ = 256  # 64 atoms x 4 valence orbitals
+    err = [float(np.abs(p["theta"][:n_occ] - q["theta"][:n_occ]).max()) for p, q in zip(r32["passes"], r64["passes"])]
+    print("diamond64 float32 vs float64 filter, per-pass eigenvalue error (Ha):", ["%.1e" % e for e in err])
+    assert all(np.isfinite(p["theta"]).all() for p in r32["passes"])
+    assert err[-1] <= 1e-6
+
+
+def test_diamond64_potential_gradient_fd(d64):
+    import torch
+    oefe, cfg, gop, v0, bounds, r32 = d64
+    X = r32["X"]
+    f = torch.full((cfg.nv,), 2.0, dtype=torch.float64)
+    V0, _ = gop.get_potential()
+    gop.set_potential(V0)
+    E, dV, _ = oefe.band_energy_grad(gop, X, f, want_dV=True, want_dX=False)
+    g = dV.cpu().numpy()
+    E = float(E)
+    h = 1e-5
+    # the energies are float64 reductions over ~3e8 terms: relative rounding ~1e-13
+    tol = 1000 * np.finfo(float).eps * abs(E) / h
+    worst = 0.0
+    for j in range(16):
+        dVj = wl.potential_perturbation(gop.n_cells, gop.nq, 100 + j)
+        gop.set_potential(V0 + h * dVj)
+        Ep = float(oefe.band_energy_grad(gop, X, f, want_dV=False, want_dX=False)[0])
+        gop.set_potential(V0 - h * dVj)
+        Em = float(oefe.band_energy_grad(gop, X, f, want_dV=False, want_dX=False)[0])
+        fd = (Ep - Em) / (2 * h)
+        an = float(np.sum(g * dVj))
+        worst = max(worst, abs(fd - an))
+        assert abs(fd - an) < tol, (j, fd, an, tol)
+    gop.set_potential(V0)
+    print(f"diamond64 dE/dV: worst |FD - adjoint| = {worst:.2e} (bound {tol:.2e}, |E| = {abs(E):.3e})")
+
+
+def test_diamond64_vector_gradient_fd(d64):
+    import torch
+    oefe, cfg, gop, v0, bounds, r32 = d64
+    X = r32["X"]
+    f = torch.full((cfg.nv,), 2.0, dtype=torch.float64)
+    E, _, dX = oefe.band_energy_grad(gop, X, f, want_dV=False, want_dX=True)
+    h = 1e-5
+    for j in range(4):
+        d = torch.from_numpy(np.random.default_rng(200 + j).uniform(-1, 1, tuple(X.shape))).cuda()
+        Ep = float(oefe.band_energy_grad(gop, X + h * d, f, False, False)[0])
+        Em = float(oefe.band_energy_grad(gop, X - h * d, f, False, False)[0])
+        fd = (Ep - Em) / (2 * h)
+        an = float(torch.sum(dX * d))
+        # E is quadratic in X: the central difference is exact up to rounding of E (~u |E| / h)
+        # and of the O(h^2) term, which vanishes for a quadratic
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (j, fd, an)
