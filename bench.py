@@ -65,7 +65,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="diamond8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the float32 / bf16 filter measurements")
+    ap.add_argument("--no-kpoints", action="store_true", help="skip the batched k-point filter measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DIR")
@@ -139,6 +140,39 @@ def cpu_baseline(cfg, degrees=8):
             "sample": f"{cfg.system.name}: {degrees} Chebyshev degrees of the float64 oracle filter on all "
                       f"{cfg.nv} vectors ({dt:.1f} s; numpy/scipy with {blas_threads} BLAS threads, "
                       f"{cores} host cores available)"}
+
+
+def kpoint_bench(oefe, wl, torch, base, m, reps):
+    """The 8 k-points of the 2x2x2 Monkhorst-Pack grid, 48..96 vectors each, in one batched
+    filter per precision (complex128, complex64), after the launch-shape autotuner."""
+    ks = wl.monkhorst_pack_2(base.L)
+    ops = [oefe.Operator(base.with_k(k)) for k in ks]
+    blocks = [torch.from_numpy(wl.start_block(op.n_tot, wl.KPOINT_NV[q], 10 + q, complex_=True)).cuda()
+              for q, op in enumerate(ops)]
+    abc = []
+    for op in ops:
+        v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, 2)).cuda()
+        a0, bb = oefe.lanczos_bounds(op, v0, 10)
+        abc.append((0.5 * (a0 + bb), bb, a0))
+    work = sum(op.n_tot * nv for op, nv in zip(ops, wl.KPOINT_NV)) * m
+    res = {"k_points": len(ops), "nv": wl.KPOINT_NV, "m": m}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        Xs = [X.to(dt) for X in blocks]
+        tune = oefe.autotune(ops, Xs, reps=3)
+        oefe.chebyshev_filter_batched(ops, Xs, m, abc)  # warm-up (the filter is scaled: values stay bounded)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            oefe.chebyshev_filter_batched(ops, Xs, m, abc)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"filter_ms": ms, "rate": work / (ms / 1e3), "shape": {"cw": tune["cw"], "cb": tune["cb"]}}
+        log(f"k-points {name}: batched filter {ms:.3f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s, shape {tune}")
+    res["unit"] = "DoF*vec*deg/s (complex vectors)"
+    return res
 
 
 def summarize_trace(d):
@@ -302,23 +336,33 @@ def main():
 
     if not args.no_fp32:
         from paper_2010_09701_amd.chfsi import chfsi_run
-        Xm = X0.clone()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for i in range(reps):
-            oefe.chebyshev_filter_mixed(gop, Xm, cfg.m, 0.5 * (a0L + b), b, a0L)
-            Xm.copy_(X0)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        f32_ms = e0.elapsed_time(e1) / reps
         r64 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f64", bounds=(a0L, b))
-        r32 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f32", bounds=(a0L, b))
         n_occ = cfg.nv - 16
-        err = [float(np.abs(p32["theta"][:n_occ] - p64["theta"][:n_occ]).max())
-               for p32, p64 in zip(r32["passes"], r64["passes"])]
-        extra.update({"fp32_filter_ms": f32_ms, "fp32_filter_speedup": filt_ms / f32_ms,
-                      "fp32_ritz_err_vs_fp64_per_pass_Ha": err, "fp32_occupied_states": n_occ})
-        log(f"fp32 filter {f32_ms:.3f} ms (x{filt_ms / f32_ms:.2f}); Ritz err per pass {err}")
+        Q64 = r64["X"][:, :n_occ]
+        for name, bf in (("fp32", False), ("bf16", True)):
+            Xm = X0.clone()
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(reps):
+                oefe.chebyshev_filter_mixed(gop, Xm, cfg.m, 0.5 * (a0L + b), b, a0L, bf16=bf)
+                Xm.copy_(X0)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            mixed_ms = e0.elapsed_time(e1) / reps
+            rm = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "bf16" if bf else "f32", bounds=(a0L, b))
+            err = [float(np.abs(pm["theta"][:n_occ] - p64["theta"][:n_occ]).max())
+                   for pm, p64 in zip(rm["passes"], r64["passes"])]
+            Q = rm["X"][:, :n_occ]
+            sin_angle = float(torch.linalg.matrix_norm(Q - Q64 @ (Q64.T @ Q), ord=2))
+            extra.update({f"{name}_filter_ms": mixed_ms, f"{name}_filter_speedup": filt_ms / mixed_ms,
+                          f"{name}_ritz_err_vs_fp64_per_pass_Ha": err,
+                          f"{name}_subspace_sin_angle_vs_fp64": sin_angle})
+            log(f"{name} filter {mixed_ms:.3f} ms (x{filt_ms / mixed_ms:.2f}); Ritz err per pass "
+                f"{['%.1e' % x for x in err]}; sin(max angle) {sin_angle:.1e}")
+        extra["mixed_occupied_states"] = n_occ
+
+    if not args.no_kpoints and sysm.name == "diamond8":
+        extra["kpoints"] = kpoint_bench(oefe, wl, torch, sysm, cfg.m, reps)
 
     out = {
         "metric": "ChFSI filter DoF*vec*deg/s (one float64 ChFSI pass: filter + CholGS + Rayleigh-Ritz)",
