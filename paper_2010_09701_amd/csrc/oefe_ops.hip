@@ -472,9 +472,13 @@ constexpr int kNodeNBMax = 8;  // 16-column blocks per node workgroup (128 real 
 
 // LDS of the node kernel: the tile's rows of X (its column block) and its dense
 // block of m^-1/2 H^co, each row padded by one element.
+// Row strides (in elements) of the node kernel's LDS tiles, padded to 16 mod 32 so that the
+// two row groups of a half-wave in the MFMA operand reads fall into disjoint banks.
+constexpr int lds_row_stride(int w) { return w + (((16 - w % 32) % 32) + 32) % 32; }
+
 template <typename T, int NB, bool CPLX>
 constexpr size_t node_lds_bytes(int fpmax) {
-  return (size_t)kTileRows * ((NB * 16 + 1) + (fpmax * (CPLX ? 2 : 1) + 1)) * sizeof(T);
+  return (size_t)kTileRows * (lds_row_stride(NB * 16) + lds_row_stride(fpmax * (CPLX ? 2 : 1))) * sizeof(T);
 }
 
 template <typename T, int NB, bool CPLX>
@@ -484,7 +488,7 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
                                                                          const int32_t* __restrict__ tile_fns, int N) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
-  constexpr int TR = kTileRows, E = CPLX ? 2 : 1, CBW = NB * 16, XS = CBW + 1;
+  constexpr int TR = kTileRows, E = CPLX ? 2 : 1, CBW = NB * 16, XS = lds_row_stride(CBW);
   extern __shared__ unsigned char smem_raw[];
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
   const int t = blockIdx.x;
   const int g0 = t * TR;
   const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
-  const int HS = FP * E + 1;
+  const int HS = lds_row_stride(FP * E);
   T* xs = reinterpret_cast<T*>(smem_raw);  // [TR][XS]: x rows of the tile, zero past N
   T* hs = xs + TR * XS;                     // [TR][HS]: the tile's block, (re, im) per function
   const T* __restrict__ tv = P.tv + (int64_t)f0 * TR * E;  // [TR][FP][E]
@@ -590,30 +594,47 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
   if (FP > 0) {
     const int MB = (FP + 15) / 16;
     const T sgn_pt = (li & 1) ? T(-1) : T(1);
-    for (int q = w; q < MB * NB; q += 4) {
-      const int mb = q / NB, nb = q - mb * NB;
-      const int f = mb * 16 + li;
-      const bool fok = f < FP;
-      const int fc = fok ? f : FP - 1;
-      const int cl = nb * 16 + li;  // LDS column; past ncr it holds a duplicate, never stored
-      V4 pc = V4{0, 0, 0, 0};
+    // two (mb, nb) blocks per wave at a time: independent accumulator chains
+    for (int q0 = w; q0 < MB * NB; q0 += 8) {
+      const bool two = q0 + 4 < MB * NB;
+      int fcs[2], cls[2];
+      bool foks[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = (h == 0 || two) ? q0 + 4 * h : q0;
+        const int mb = q / NB, nb = q - mb * NB;
+        const int f = mb * 16 + li;
+        foks[h] = f < FP;
+        fcs[h] = foks[h] ? f : FP - 1;
+        cls[h] = nb * 16 + li;  // LDS column; past ncr it holds a duplicate, never stored
+      }
+      V4 pc[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}};
 #pragma unroll 4
       for (int ks = 0; ks < TR / 4; ++ks) {
         const int r = ks * 4 + lk;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          const T av = hs[r * HS + fc * E + e];
-          const T a = fok ? av : T(0);
-          const T b = (!CPLX || e == 0) ? xs[r * XS + cl] : sgn_pt * xs[r * XS + (cl ^ 1)];
-          pc = M::op(a, b, pc);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const T av = hs[r * HS + fcs[h] * E + e];
+            const T a = foks[h] ? av : T(0);
+            const T b = (!CPLX || e == 0) ? xs[r * XS + cls[h]] : sgn_pt * xs[r * XS + (cls[h] ^ 1)];
+            pc[h] = M::op(a, b, pc[h]);
+          }
         }
       }
-      const int col = cb0 + cl;
-      if (col < ncr) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int fi = mb * 16 + M::row(lane, v);
-          if (fi < FP) P.part[(int64_t)(f0 + fi) * ncr + col] = pc[v];
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && !two) break;
+        const int q = q0 + 4 * h;
+        const int mb = q / NB;
+        const int col = cb0 + cls[h];
+        if (col < ncr) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int fi = mb * 16 + M::row(lane, v);
+            if (fi < FP) P.part[(int64_t)(f0 + fi) * ncr + col] = pc[h][v];
+          }
         }
       }
     }
