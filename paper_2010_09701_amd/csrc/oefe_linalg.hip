@@ -274,6 +274,7 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
   const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
   const int npair = NN / 2, m = NN - 1;
   __shared__ int done;
+  __shared__ int nrot;  // rotations applied in the current sweep
   auto A_ = [&](int i, int j) -> double* { return A + ((int64_t)i * n + j) * E; };
   for (int t = tid; t < n * n; t += nth) {
     V[(int64_t)t * E] = (t / n == t % n) ? 1.0 : 0.0;
@@ -309,6 +310,8 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
     const double dias = red[0];
     __syncthreads();
     if (offs <= 1e-30 * dias || offs == 0.0) break;
+    if (tid == 0) nrot = 0;
+    __syncthreads();
     for (int st = 0; st < m; ++st) {
       // (a) rotation per pair: rot[k] = {c, s, er, ei, p, q} (er+i ei = e^{i phi})
       for (int k = tid; k < npair; k += nth) {
@@ -327,7 +330,9 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
           const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
           const double r = sqrt(br * br + bi * bi);
           const double al = A_(p, p)[0], ga = A_(q, q)[0];
-          if (r > 1e-300 && r > 1e-18 * sqrt(fabs(al * ga))) {
+          // rotate only when the pair is coupled above float64 rounding of its diagonal
+          if (r > 1e-300 && r > 2.220446049250313e-16 * sqrt(fabs(al * ga))) {
+            atomicAdd(&nrot, 1);
             er = br / r;
             ei = bi / r;
             const double tau = (ga - al) / (2.0 * r);
@@ -415,6 +420,11 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
       }
       __syncthreads();
     }
+    // a sweep that found no pair coupled above rounding: converged
+    if (nrot == 0) {
+      ++sweep;
+      break;
+    }
   }
   if (tid == 0) { status[0] = sweep < 60 ? 0 : OEFE_ENOCONV; status[1] = sweep; }
   // sort ascending by rank
@@ -449,7 +459,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, in
 // the column updates of V.  Same rotations, same order of operations per entry
 // as the global-memory version (columns, then rows).
 template <bool CPLX>
-__global__ __launch_bounds__(512) void jacobi_lds_kernel(const double* __restrict__ A, int n,
+__global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restrict__ A, int n,
                                                          double* __restrict__ lam, double* __restrict__ U,
                                                          int32_t* __restrict__ status) {
   constexpr int E = CPLX ? 2 : 1;
@@ -459,7 +469,8 @@ __global__ __launch_bounds__(512) void jacobi_lds_kernel(const double* __restric
   double* As = sm;                       // n*n*E
   double* Vs = As + (size_t)n * n * E;   // n*n*E
   double* rot = Vs + (size_t)n * n * E;  // 6 * npair: c, s, er, ei, p, q
-  double* red = rot + 6 * npair;         // 16
+  double* red = rot + 6 * npair;         // 2 per wave (<= 32)
+  __shared__ int nrot;                   // rotations applied in the current sweep
   const int tid = threadIdx.x, nth = blockDim.x;
   auto a_ = [&](int i, int j) -> double* { return As + ((int64_t)i * n + j) * E; };
   for (int t = tid; t < n * n * E; t += nth) As[t] = A[t];
@@ -493,6 +504,7 @@ __global__ __launch_bounds__(512) void jacobi_lds_kernel(const double* __restric
       offs += red[2 * w];
       dias += red[2 * w + 1];
     }
+    if (tid == 0) nrot = 0;
     __syncthreads();
     if (offs <= 1e-30 * dias || offs == 0.0) break;
     for (int st = 0; st < m; ++st) {
@@ -513,7 +525,9 @@ __global__ __launch_bounds__(512) void jacobi_lds_kernel(const double* __restric
           const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
           const double r = sqrt(br * br + bi * bi);
           const double al = a_(p, p)[0], ga = a_(q, q)[0];
-          if (r > 1e-300 && r > 1e-18 * sqrt(fabs(al * ga))) {
+          // rotate only when the pair is coupled above float64 rounding of its diagonal
+          if (r > 1e-300 && r > 2.220446049250313e-16 * sqrt(fabs(al * ga))) {
+            atomicAdd(&nrot, 1);
             er = br / r;
             ei = bi / r;
             const double tau = (ga - al) / (2.0 * r);
@@ -613,6 +627,11 @@ __global__ __launch_bounds__(512) void jacobi_lds_kernel(const double* __restric
         }
       }
       __syncthreads();
+    }
+    // a sweep that found no pair coupled above rounding: converged
+    if (nrot == 0) {
+      ++sweep;
+      break;
     }
   }
   if (tid == 0) { status[0] = sweep < 60 ? 0 : OEFE_ENOCONV; status[1] = sweep; }
@@ -946,14 +965,14 @@ size_t jacobi_scratch_bytes(bool cplx, int n) {
 }
 
 int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s) {
-  const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + 6 * (n / 2 + 1) + 16) * sizeof(double);
+  const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + 6 * (n / 2 + 1) + 32) * sizeof(double);
   if (lds <= 150 * 1024) {
     const void* fn = cplx ? (const void*)jacobi_lds_kernel<true> : (const void*)jacobi_lds_kernel<false>;
     if (allow_dynamic_lds(fn, lds) != hipSuccess) return OEFE_EDEVICE;
     if (cplx)
-      hipLaunchKernelGGL(jacobi_lds_kernel<true>, dim3(1), dim3(512), lds, s, A, n, lam, U, status);
+      hipLaunchKernelGGL(jacobi_lds_kernel<true>, dim3(1), dim3(1024), lds, s, A, n, lam, U, status);
     else
-      hipLaunchKernelGGL(jacobi_lds_kernel<false>, dim3(1), dim3(512), lds, s, A, n, lam, U, status);
+      hipLaunchKernelGGL(jacobi_lds_kernel<false>, dim3(1), dim3(1024), lds, s, A, n, lam, U, status);
     return check();
   }
   double* V = scratch;
