@@ -978,9 +978,12 @@ int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* wo
   hipStream_t s = (hipStream_t)stream;
   double* Xd = (double*)X;
   double* tmp = (double*)L.vecA;
+  // Pass 1 factors the Gram matrix of X; its orthogonality check computes Q^* Q, which is
+  // exactly the Gram matrix the (at most one) repeated pass factors.
+  int rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
+  if (rc) return fail(rc, "cholgs: kernel launch failed");
   for (int it = 0; it < 2; ++it) {
-    int rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
-    if (!rc) rc = hermitian_part(cplx, L.G, nv, s);
+    rc = hermitian_part(cplx, L.G, nv, s);
     if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, L.status, s);
     if (rc) return fail(rc, "cholgs: kernel launch failed");
     int32_t st[2];
@@ -994,8 +997,10 @@ int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* wo
     }
     rc = gemm_nn(cplx, Xd, ld, L.Rinv, nv, tmp, nv, op->n_tot, nv, nv, s);
     if (!rc) rc = copy_block(tmp, (int64_t)nv * E, Xd, ld * E, op->n_tot, nv * E, s);
-    // orthogonality check
-    if (!rc) rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
+    if (rc) return fail(rc, "cholgs: kernel launch failed");
+    if (it == 1) break;  // repeated once at most
+    // orthogonality check on Q^* Q
+    rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
     if (!rc) rc = max_offdiag_identity(cplx, L.G, nv, L.misc, s);
     if (rc) return fail(rc, "cholgs: kernel launch failed");
     double errv = 0;

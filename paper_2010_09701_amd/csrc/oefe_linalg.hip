@@ -308,6 +308,7 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
       __syncthreads();
     }
     const double dias = red[0];
+    const double nrm_n = sqrt(offs + dias) / n;  // Frobenius norm / n
     __syncthreads();
     if (offs <= 1e-30 * dias || offs == 0.0) break;
     if (tid == 0) nrot = 0;
@@ -330,8 +331,9 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
           const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
           const double r = sqrt(br * br + bi * bi);
           const double al = A_(p, p)[0], ga = A_(q, q)[0];
-          // rotate only when the pair is coupled above float64 rounding of its diagonal
-          if (r > 1e-300 && r > 2.220446049250313e-16 * sqrt(fabs(al * ga))) {
+          // rotate only when the pair is coupled above float64 rounding, measured on its
+          // diagonal entries or on the matrix norm (whichever is larger)
+          if (r > 1e-300 && r > 2.220446049250313e-16 * fmax(sqrt(fabs(al * ga)), nrm_n)) {
             atomicAdd(&nrot, 1);
             er = br / r;
             ei = bi / r;
@@ -504,6 +506,7 @@ __global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restri
       offs += red[2 * w];
       dias += red[2 * w + 1];
     }
+    const double nrm_n = sqrt(offs + dias) / n;  // Frobenius norm / n
     if (tid == 0) nrot = 0;
     __syncthreads();
     if (offs <= 1e-30 * dias || offs == 0.0) break;
@@ -525,8 +528,9 @@ __global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restri
           const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
           const double r = sqrt(br * br + bi * bi);
           const double al = a_(p, p)[0], ga = a_(q, q)[0];
-          // rotate only when the pair is coupled above float64 rounding of its diagonal
-          if (r > 1e-300 && r > 2.220446049250313e-16 * sqrt(fabs(al * ga))) {
+          // rotate only when the pair is coupled above float64 rounding, measured on its
+          // diagonal entries or on the matrix norm (whichever is larger)
+          if (r > 1e-300 && r > 2.220446049250313e-16 * fmax(sqrt(fabs(al * ga)), nrm_n)) {
             atomicAdd(&nrot, 1);
             er = br / r;
             ei = bi / r;
