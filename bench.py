@@ -181,7 +181,7 @@ def summarize_trace(d):
         sys.exit(f"no kernel_stats.csv under {d}")
     print("| kernel | calls | avg us | min us | max us | share % |")
     print("|---|---:|---:|---:|---:|---:|")
-    for r in list(csv.DictReader(open(f[0])))[:16]:
+    for r in list(csv.DictReader(open(f[0])))[:24]:
         print(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
               f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
 
