@@ -157,16 +157,17 @@ int chebyshev_filter_batched(int32_t nk, const oefe_op* ops, oefe_prec prec, voi
                              const int32_t* nv, int32_t m, const double* abc, void* work, oefe_stream stream);
 size_t oefe_batched_work_size(int32_t nk, const oefe_op* ops, oefe_prec prec, const int32_t* nv);
 
-/* Launch shape of the operator stages: cell-tile width cw in {8, 16, 32, 64}
- * (real columns per cell in a 64-lane cell tile, so 64/cw cells per tile;
- * 0 = built-in choice) and the node-stage vector-block width cb (real columns
- * per workgroup, used in 16-column units, <= 128; 0 = built-in).  Results do
- * not depend on the shape. */
+/* Launch shape of the operator stages.  cw selects the cell-stage tiling:
+ * 0 (built-in) puts the (p+1) planes of a cell tensor in the lanes of one wave
+ * (64/(p+1) columns, rounded down to even, per wave); 8, 16, 32 or 64 put one
+ * plane per wave with cw real columns per cell in a 64-lane tile (64/cw cells).
+ * cb is the node-stage vector-block width (real columns per workgroup, used in
+ * 16-column units, <= 128; 0 = built-in).  Results do not depend on the shape. */
 int oefe_set_launch_shape(oefe_op op, int32_t cw, int32_t cb);
 
 /* Autotuner of the launch shape for a batch of operators (nk >= 1, same rules
  * as chebyshev_filter_batched).  Times `reps` batched recurrence steps on
- * copies of the blocks X[q] for each cw in {8, 16, 32, 64} and cb in
+ * copies of the blocks X[q] for each cw in {0, 8, 16, 32, 64} and cb in
  * {32, 64, 96, 128}, with HIP events on `stream`, and sets the fastest shape on
  * every operator.  X is not modified.  work: oefe_batched_work_size(nk, ops,
  * prec, nv) bytes.  Outputs (host, may be NULL): the chosen cw, cb and the

@@ -795,11 +795,11 @@ int autotune_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const i
   const oefe_op_s* const* opp = (const oefe_op_s* const*)ops;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return OEFE_EDEVICE;
-  const int cws[4] = {8, 16, 32, 64};
+  const int cws[5] = {0, 8, 16, 32, 64};
   const int cbs[4] = {32, 64, 96, 128};
   double best = 1e300;
   int bcw = 0, bcb = 0, rc = OEFE_OK;
-  for (int a = 0; a < 4 && !rc; ++a)
+  for (int a = 0; a < 5 && !rc; ++a)
     for (int b = 0; b < 4 && !rc; ++b) {
       for (int q = 0; q < nk; ++q) {
         ops[q]->tune_cw = cws[a];

@@ -302,6 +302,241 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, const T*
   }
 }
 
+// Cell kernel with the planes in the lanes of one wave: lane = r * CWc + g holds plane r of
+// the cell tensor for column g of a CWc-column block (CWc = 64 / P1 rounded down to even;
+// the 64 - P1 CWc spare lanes repeat the last plane's work and store nothing).  A wave
+// owns one (cell, column block) and its own LDS region, so the three transposes need no
+// workgroup barrier and the four waves of a workgroup carry equal work.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int P1>
+constexpr int lanes_cw() { return (64 / P1) & ~1; }
+
+template <typename T, int P1, bool CPLX>
+__global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const T* __restrict__ WV, CellCoef<T> cf,
+                                                            int nc, int p, int n, int64_t n_cells) {
+  constexpr int NP = P1 * P1;
+  constexpr int CWc = lanes_cw<P1>();
+  __shared__ T lds_all[4][NP * P1 * CWc];
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int ncr = P.ncr;
+  if ((int)blockIdx.y * CWc >= ncr) return;  // column block beyond this operator's width
+  const T* __restrict__ X = P.x;
+  const int64_t ldx = P.ldx;
+  T* __restrict__ Yc = P.ycell;
+  const int ldc = P.ldc;
+  const Phase3<T> ph = P.ph;
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const bool active = lane < P1 * CWc;
+  const int w = min(lane / CWc, P1 - 1);  // plane of this lane
+  const int g = active ? lane % CWc : lane - P1 * CWc;  // spare lanes repeat a last-plane lane
+  T* lds = lds_all[wid];
+  const int64_t e = (int64_t)blockIdx.x * 4 + wid;
+  const int j = blockIdx.y * CWc + g;
+  const bool valid = (e < n_cells) && (j < ncr);
+  const int64_t ee = valid ? e : 0;
+  const int cx = (int)(ee % nc), cy = (int)((ee / nc) % nc), cz = (int)(ee / ((int64_t)nc * nc));
+
+  // 1. gather plane az = w with the m^-1/2 pre-scale (and Bloch phase)
+  T v[NP];
+  {
+    const int az = w;
+    int iz = cz * p + az;
+    bool wz = iz >= n;
+    if (wz) iz -= n;
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) {
+      int iy = cy * p + ay;
+      bool wy = iy >= n;
+      if (wy) iy -= n;
+#pragma unroll
+      for (int ax = 0; ax < P1; ++ax) {
+        int ix = cx * p + ax;
+        bool wx = ix >= n;
+        if (wx) ix -= n;
+        const int64_t g = ix + (int64_t)n * (iy + (int64_t)n * iz);
+        const T sc = cf.mscale * cf.om[ax] * cf.om[ay] * cf.om[az];
+        T val = 0;
+        if (valid) {
+          if constexpr (!CPLX) {
+            val = X[g * ldx + j];
+          } else {
+            const T* px = X + g * ldx + (j & ~1);
+            C2<T> z{px[0], px[1]};
+            if (wx) z = cmul(z, C2<T>{ph.re[0], ph.im[0]});
+            if (wy) z = cmul(z, C2<T>{ph.re[1], ph.im[1]});
+            if (wz) z = cmul(z, C2<T>{ph.re[2], ph.im[2]});
+            val = (j & 1) ? z.i : z.r;
+          }
+        }
+        v[ay * P1 + ax] = sc * val;
+      }
+    }
+  }
+  // 2. x- then y-pass with B1 (in registers)
+  T t[NP];
+#pragma unroll
+  for (int ay = 0; ay < P1; ++ay)
+#pragma unroll
+    for (int qx = 0; qx < P1; ++qx) {
+      T s = 0;
+#pragma unroll
+      for (int ax = 0; ax < P1; ++ax) s += cf.B1[qx][ax] * v[ay * P1 + ax];
+      t[ay * P1 + qx] = s;
+    }
+#pragma unroll
+  for (int qy = 0; qy < P1; ++qy)
+#pragma unroll
+    for (int qx = 0; qx < P1; ++qx) {
+      T s = 0;
+#pragma unroll
+      for (int ay = 0; ay < P1; ++ay) s += cf.B1[qy][ay] * t[ay * P1 + qx];
+      v[qy * P1 + qx] = s;
+    }
+  // 3. transpose z-planes -> x-planes: lds[(az*P1 + qy)*P1 + qx]
+#pragma unroll
+  for (int qy = 0; qy < P1; ++qy)
+#pragma unroll
+    for (int qx = 0; qx < P1; ++qx) lds[((w * P1 + qy) * P1 + qx) * CWc + g] = v[qy * P1 + qx];
+  wave_sync();
+  // this wave now owns qx = w; u[az][qy]
+#pragma unroll
+  for (int az = 0; az < P1; ++az)
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy) t[az * P1 + qy] = lds[((az * P1 + qy) * P1 + w) * CWc + g];
+  // 4. z-pass -> u[qz][qy]
+  T u[NP];
+#pragma unroll
+  for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy) {
+      T s = 0;
+#pragma unroll
+      for (int az = 0; az < P1; ++az) s += cf.B1[qz][az] * t[az * P1 + qy];
+      u[qz * P1 + qy] = s;
+    }
+  // 5. quadrature-point terms: potential + y/z kinetic
+  const int qx = w;
+  const T kx = cf.kappa * cf.w[qx];
+  const T* wv = WV + ee * (NP * P1);
+#pragma unroll
+  for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy) {
+      T ly = 0, lz = 0;
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        ly += cf.L1[qy][k] * u[qz * P1 + k];
+        lz += cf.L1[qz][k] * u[k * P1 + qy];
+      }
+      t[qz * P1 + qy] = wv[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
+    }
+  // 6. t' = (B^T)_y (B^T)_z t  -> indexed [az][ay]
+  T tp[NP];
+#pragma unroll
+  for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) {
+      T s = 0;
+#pragma unroll
+      for (int qy = 0; qy < P1; ++qy) s += cf.B1[qy][ay] * t[qz * P1 + qy];
+      v[qz * P1 + ay] = s;
+    }
+#pragma unroll
+  for (int az = 0; az < P1; ++az)
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) {
+      T s = 0;
+#pragma unroll
+      for (int qz = 0; qz < P1; ++qz) s += cf.B1[qz][az] * v[qz * P1 + ay];
+      tp[az * P1 + ay] = s;
+    }
+  // 7. s = kappa (B^T W)_y (B^T W)_z u  (the x kinetic term before its x-pass)
+#pragma unroll
+  for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) {
+      T s = 0;
+#pragma unroll
+      for (int qy = 0; qy < P1; ++qy) s += cf.BtW[ay][qy] * u[qz * P1 + qy];
+      v[qz * P1 + ay] = s;
+    }
+#pragma unroll
+  for (int az = 0; az < P1; ++az)
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) {
+      T s = 0;
+#pragma unroll
+      for (int qz = 0; qz < P1; ++qz) s += cf.BtW[az][qz] * v[qz * P1 + ay];
+      u[az * P1 + ay] = cf.kappa * s;
+    }
+  // 8. transpose t' back to z-planes, x-pass with B^T
+  wave_sync();
+#pragma unroll
+  for (int az = 0; az < P1; ++az)
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) lds[((az * P1 + ay) * P1 + w) * CWc + g] = tp[az * P1 + ay];
+  wave_sync();
+  T y[NP];
+#pragma unroll
+  for (int ay = 0; ay < P1; ++ay) {
+    T r[P1];
+#pragma unroll
+    for (int q = 0; q < P1; ++q) r[q] = lds[((w * P1 + ay) * P1 + q) * CWc + g];
+#pragma unroll
+    for (int ax = 0; ax < P1; ++ax) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < P1; ++q) s += cf.B1[q][ax] * r[q];
+      y[ay * P1 + ax] = s;
+    }
+  }
+  // 9. transpose s, x-pass with B^T L1, accumulate
+  wave_sync();
+#pragma unroll
+  for (int az = 0; az < P1; ++az)
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) lds[((az * P1 + ay) * P1 + w) * CWc + g] = u[az * P1 + ay];
+  wave_sync();
+#pragma unroll
+  for (int ay = 0; ay < P1; ++ay) {
+    T r[P1];
+#pragma unroll
+    for (int q = 0; q < P1; ++q) r[q] = lds[((w * P1 + ay) * P1 + q) * CWc + g];
+#pragma unroll
+    for (int ax = 0; ax < P1; ++ax) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < P1; ++q) s += cf.BtL[ax][q] * r[q];
+      y[ay * P1 + ax] += s;
+    }
+  }
+  // 10. store plane az = w of y_e into the node-slot grid: local node a of cell c
+  //     goes to slot (c (p+1) + a + 1) mod S per dimension, S = nc (p+1)
+  if (valid && active) {
+    const int S = nc * P1;
+    int sz = cz * P1 + w + 1;
+    if (sz >= S) sz -= S;
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) {
+      int sy = cy * P1 + ay + 1;
+      if (sy >= S) sy -= S;
+      const int64_t rowyz = (int64_t)S * (sy + (int64_t)S * sz);
+#pragma unroll
+      for (int ax = 0; ax < P1; ++ax) {
+        int sx = cx * P1 + ax + 1;
+        if (sx >= S) sx -= S;
+        Yc[(rowyz + sx) * ldc + j] = y[ay * P1 + ax];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // BF16 cell kernel (real operators, float32 vectors): the cell operator in dense form
 //   U = B Z,  T = (W V) o U,  Y = K Z + B^T T
@@ -1067,8 +1302,25 @@ void launch_cell_p(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw
   }
 }
 
+template <typename T, int P1, bool CPLX>
+void launch_cell_lanes(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, hipStream_t s) {
+  constexpr int CWc = lanes_cw<P1>();
+  dim3 grid((unsigned)cdiv(op->n_cells, 4), (unsigned)cdiv(max_ncr, CWc), (unsigned)kb.nk);
+  hipLaunchKernelGGL((fe_cell_lanes_kernel<T, P1, CPLX>), grid, dim3(256), 0, s, kb, devptrs<T>(op).WV, coef<T>(op),
+                     op->nc, op->p, op->n, op->n_cells);
+}
+
+// cw = 0: planes-in-lanes kernel; 8, 16, 32, 64: plane-per-wave kernel with cw columns per cell
 template <typename T, bool CPLX>
 void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, hipStream_t s) {
+  if (cw == 0) {
+    switch (op->P1) {
+      case 3: launch_cell_lanes<T, 3, CPLX>(op, kb, max_ncr, s); break;
+      case 4: launch_cell_lanes<T, 4, CPLX>(op, kb, max_ncr, s); break;
+      default: launch_cell_lanes<T, 5, CPLX>(op, kb, max_ncr, s); break;
+    }
+    return;
+  }
   switch (op->P1) {
     case 3: launch_cell_p<T, 3, CPLX>(op, kb, max_ncr, cw, s); break;
     case 4: launch_cell_p<T, 4, CPLX>(op, kb, max_ncr, cw, s); break;
@@ -1145,7 +1397,7 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
         return;
       }
     }
-    launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw > 0 ? op->tune_cw : pick_cw(max_ncr), s);
+    launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw, s);
   });
   // node workgroup width: 16-column blocks, all real columns up to the cap, else near-equal
   const int nbcap = std::max(1, std::min(kNodeNBMax, op->tune_cb > 0 ? op->tune_cb / 16 : kNodeNBMax));

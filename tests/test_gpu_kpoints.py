@@ -122,7 +122,7 @@ def test_autotune_shape_and_cache(lib, mp_ops, tmp_path):
     lib.chebyshev_filter_batched(mp_ops, Xa, m, abc)  # built-in shape
     cache = str(tmp_path / "tune.json")
     r = lib.autotune(mp_ops, [_dev(X, torch.complex128) for X in blocks], reps=2, cache=cache)
-    assert r["cw"] in (8, 16, 32, 64) and r["cb"] in (32, 64, 96, 128) and r["ms_per_step"] > 0
+    assert r["cw"] in (0, 8, 16, 32, 64) and r["cb"] in (32, 64, 96, 128) and r["ms_per_step"] > 0
     assert not r["cached"]
     Xt = [_dev(X, torch.complex128) for X in blocks]
     lib.chebyshev_filter_batched(mp_ops, Xt, m, abc)  # tuned shape
