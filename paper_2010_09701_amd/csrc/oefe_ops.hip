@@ -784,44 +784,50 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
   }
   __syncthreads();
 
-  // ---- en = Ht_t Z^O: rows w*16 .. w*16+15 of the tile (A from LDS, B from Z^O)
-  // complex: the second real pass pairs Im(H) with the partner column, signed
-  const T sgn_en = (li & 1) ? T(1) : T(-1);
-  V4 acc[NB];
+  // ---- node-slot gather + recurrence epilogue on the en layout
+  const T* __restrict__ Yc = P.ycell;
+  const int64_t ldc = P.ldc;
+  const Phase3<T> ph = P.ph;
+  const T alpha = P.alpha, c = P.c, beta = P.beta;
+  const T* __restrict__ prev = P.prev;
+  T* __restrict__ out = P.out;
+  const int64_t ldo = P.ldo;
+  const int S = nc * P1;
+  // slots of node i per dimension: a shared node (i mod p == 0) has two, the one from
+  // the lower cell first; slot 0 holds the periodic image of the last cell
+  int bx[4], by[4], bz[4], gc[4];
+  bool x2[4], y2[4], z2[4], ok[4];
+  T msc[4];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = V4{0, 0, 0, 0};
-  {
-    constexpr int KCE = CPLX ? 2 : 4;  // k-steps per load batch
-    const int rA = w * 16 + li;
-    for (int k0 = 0; k0 < FP; k0 += 4 * KCE) {
-      int fn[KCE];
+  for (int v = 0; v < 4; ++v) {
+    const int gv = g0 + w * 16 + M::row(lane, v);
+    ok[v] = gv < N;
+    const int g = ok[v] ? gv : N - 1;
+    gc[v] = g;
+    const int iz = g / (n * n), rem = g - iz * n * n, iy = rem / n, ix = rem - iy * n;
+    const int qx = ix / p, rx = ix - qx * p, qy = iy / p, ry = iy - qy * p, qz = iz / p, rz = iz - qz * p;
+    bx[v] = qx * P1 + (rx ? rx + 1 : 0);
+    by[v] = qy * P1 + (ry ? ry + 1 : 0);
+    bz[v] = qz * P1 + (rz ? rz + 1 : 0);
+    x2[v] = rx == 0;
+    y2[v] = ry == 0;
+    z2[v] = rz == 0;
+    msc[v] = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
+  }
+  // real float32 blocks: the first slot pair's loads are issued now and land during the MFMA
+  // phases (float64 has no registers to spare for them)
+  constexpr bool kEarly = !CPLX && sizeof(T) == 4;
+  T gA[4][NB], gB[4][NB];
+  if constexpr (kEarly) {
 #pragma unroll
-      for (int ks = 0; ks < KCE; ++ks) fn[ks] = tile_fns[f0 + min(k0 + ks * 4 + lk, FP - 1)];
-      T a[KCE][E], b[KCE][E][NB];
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = bx[v] + (int64_t)S * (by[v] + (int64_t)S * bz[v]);
+      const int64_t row2 = x2[v] ? row + 1 : row;
 #pragma unroll
-      for (int ks = 0; ks < KCE; ++ks) {
-        const int f = k0 + ks * 4 + lk;
-        const bool on = f < FP && fn[ks] >= 0;
-        const int fc = min(f, FP - 1);
-        const T* zr = zo + (int64_t)max(fn[ks], 0) * ncr;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const T av = hs[rA * HS + fc * E + e];
-          a[ks][e] = on ? av : T(0);
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            if (!CPLX || e == 0) b[ks][e][nb] = zr[colc[nb]];
-            else b[ks][e][nb] = sgn_en * zr[colc[nb] ^ 1];
-          }
-        }
+      for (int nb = 0; nb < NB; ++nb) {
+        gA[v][nb] = Yc[row * ldc + colc[nb]];
+        gB[v][nb] = Yc[row2 * ldc + colc[nb]];
       }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int ks = 0; ks < KCE; ++ks)
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a[ks][e], b[ks][e][nb], acc[nb]);
     }
   }
 
@@ -875,46 +881,67 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
     }
   }
 
-  // ---- node-slot gather + recurrence epilogue on the en layout
-  const T* __restrict__ Yc = P.ycell;
-  const int64_t ldc = P.ldc;
-  const Phase3<T> ph = P.ph;
-  const T alpha = P.alpha, c = P.c, beta = P.beta;
-  const T* __restrict__ prev = P.prev;
-  T* __restrict__ out = P.out;
-  const int64_t ldo = P.ldo;
-  const int S = nc * P1;
-  // slots of node i per dimension: a shared node (i mod p == 0) has two, the one from
-  // the lower cell first; slot 0 holds the periodic image of the last cell
-  int bx[4], by[4], bz[4], gc[4];
-  bool x2[4], y2[4], z2[4], ok[4];
-  T msc[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int gv = g0 + w * 16 + M::row(lane, v);
-    ok[v] = gv < N;
-    const int g = ok[v] ? gv : N - 1;
-    gc[v] = g;
-    const int iz = g / (n * n), rem = g - iz * n * n, iy = rem / n, ix = rem - iy * n;
-    const int qx = ix / p, rx = ix - qx * p, qy = iy / p, ry = iy - qy * p, qz = iz / p, rz = iz - qz * p;
-    bx[v] = qx * P1 + (rx ? rx + 1 : 0);
-    by[v] = qy * P1 + (ry ? ry + 1 : 0);
-    bz[v] = qz * P1 + (rz ? rz + 1 : 0);
-    x2[v] = rx == 0;
-    y2[v] = ry == 0;
-    z2[v] = rz == 0;
-    msc[v] = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
-  }
   T sum[4][NB];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) sum[v][nb] = 0;
+  if constexpr (kEarly) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const T add = gA[v][nb] + (x2[v] ? gB[v][nb] : T(0));
+        sum[v][nb] += ok[v] ? add : T(0);
+      }
+  }
+
+  // ---- en = Ht_t Z^O: rows w*16 .. w*16+15 of the tile (A from LDS, B from Z^O)
+  // complex: the second real pass pairs Im(H) with the partner column, signed
+  const T sgn_en = (li & 1) ? T(1) : T(-1);
+  V4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = V4{0, 0, 0, 0};
+  {
+    constexpr int KCE = CPLX ? 2 : 4;  // k-steps per load batch
+    const int rA = w * 16 + li;
+    for (int k0 = 0; k0 < FP; k0 += 4 * KCE) {
+      int fn[KCE];
+#pragma unroll
+      for (int ks = 0; ks < KCE; ++ks) fn[ks] = tile_fns[f0 + min(k0 + ks * 4 + lk, FP - 1)];
+      T a[KCE][E], b[KCE][E][NB];
+#pragma unroll
+      for (int ks = 0; ks < KCE; ++ks) {
+        const int f = k0 + ks * 4 + lk;
+        const bool on = f < FP && fn[ks] >= 0;
+        const int fc = min(f, FP - 1);
+        const T* zr = zo + (int64_t)max(fn[ks], 0) * ncr;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const T av = hs[rA * HS + fc * E + e];
+          a[ks][e] = on ? av : T(0);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            if (!CPLX || e == 0) b[ks][e][nb] = zr[colc[nb]];
+            else b[ks][e][nb] = sgn_en * zr[colc[nb] ^ 1];
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ks = 0; ks < KCE; ++ks)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a[ks][e], b[ks][e][nb], acc[nb]);
+    }
+  }
+
   // (ky, kz) slot pairs in a fixed order; a pair is visited when some lane of the
   // wave needs it, lanes that do not need it reload their first slot (in bounds,
   // cached) and discard it
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
+  for (int kk = kEarly ? 1 : 0; kk < 4; ++kk) {
     const int ky = kk & 1, kz = kk >> 1;
     bool need[4];
     int anyv = 0;
