@@ -552,7 +552,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBf16MatElems = 8 * 4 * 64 * 8;  // one 128 x 128 matrix in fragment order
 
-__global__ __launch_bounds__(1024) void fe_cell_bf16_kernel(KBatch<float> kb, const uint16_t* __restrict__ mats,
+__global__ __launch_bounds__(768) void fe_cell_bf16_kernel(KBatch<float> kb, const uint16_t* __restrict__ mats,
                                                            const float* __restrict__ WV, CellCoef<float> cf, int nc,
                                                            int p, int n, int P1, int64_t n_cells) {
   extern __shared__ unsigned char smem_raw[];
@@ -560,6 +560,10 @@ __global__ __launch_bounds__(1024) void fe_cell_bf16_kernel(KBatch<float> kb, co
   // per local node a < 128: (ax, ay, az) packed in 8-bit fields, and the m^-1/2 factor
   int* ncode = reinterpret_cast<int*>(smem_raw + 3 * kBf16MatElems * sizeof(uint16_t));
   float* nscale = reinterpret_cast<float*>(ncode + 128);
+  // offsets of local node a from the cell's first node (global rows) and first slot (grid
+  // rows), valid for cells that do not touch the upper periodic boundary
+  int* noff = reinterpret_cast<int*>(nscale + 128);
+  int* soff = noff + 128;
   const int nd = P1 * P1 * P1;
   {
     const uint4* src = reinterpret_cast<const uint4*>(mats);
@@ -580,6 +584,8 @@ __global__ __launch_bounds__(1024) void fe_cell_bf16_kernel(KBatch<float> kb, co
       }
       ncode[a] = a < nd ? (ax | (ay << 8) | (az << 16)) : 0;
       nscale[a] = a < nd ? cf.mscale * sx * sy * sz : 0.0f;
+      noff[a] = a < nd ? ax + n * (ay + n * az) : 0;
+      soff[a] = a < nd ? ax + nc * P1 * (ay + nc * P1 * az) : 0;
     }
   }
   __syncthreads();
@@ -604,20 +610,42 @@ __global__ __launch_bounds__(1024) void fe_cell_bf16_kernel(KBatch<float> kb, co
     const int cc = cok ? col : ncr - 1;
     const int cx = (int)(e % nc), cy = (int)((e / nc) % nc), cz = (int)(e / ((int64_t)nc * nc));
     const int bx = cx * p, by = cy * p, bz = cz * p;
-    // Z: node 32 k4 + 8 g + t of the cell, column col, scaled by m^-1/2 (one batch of loads)
+    // Z: node 32 k4 + 8 g + t of the cell, column col, scaled by m^-1/2 (one batch of loads);
+    // a cell away from the upper periodic boundary (wave-uniform) indexes by table offsets
+    const bool interior = cx < nc - 1 && cy < nc - 1 && cz < nc - 1;
+    const int64_t gbase = bx + (int64_t)n * (by + (int64_t)n * bz);
+    // W V of this lane's quadrature points, loaded with the gather (used after U = B Z)
+    const float* wv = WV + e * nd;
+    float wq[4][8];
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q0 = 32 * k4 + 4 * g + v, q1 = q0 + 16;
+        wq[k4][v] = wv[q0 < nd ? q0 : 0];
+        wq[k4][4 + v] = wv[q1 < nd ? q1 : 0];
+      }
     bf16x8 z[4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {  // two batches of 16 loads
       float zv[16];
+      if (interior) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int a = 32 * (2 * h + (i >> 3)) + 8 * g + (i & 7);
-        const int code = ncode[a];
-        int ix = bx + (code & 255), iy = by + ((code >> 8) & 255), iz = bz + (code >> 16);
-        ix -= ix >= n ? n : 0;
-        iy -= iy >= n ? n : 0;
-        iz -= iz >= n ? n : 0;
-        zv[i] = X[(ix + (int64_t)n * (iy + (int64_t)n * iz)) * ldx + cc];
+        for (int i = 0; i < 16; ++i) {
+          const int a = 32 * (2 * h + (i >> 3)) + 8 * g + (i & 7);
+          zv[i] = X[(gbase + noff[a]) * ldx + cc];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int a = 32 * (2 * h + (i >> 3)) + 8 * g + (i & 7);
+          const int code = ncode[a];
+          int ix = bx + (code & 255), iy = by + ((code >> 8) & 255), iz = bz + (code >> 16);
+          ix -= ix >= n ? n : 0;
+          iy -= iy >= n ? n : 0;
+          iz -= iz >= n ? n : 0;
+          zv[i] = X[(ix + (int64_t)n * (iy + (int64_t)n * iz)) * ldx + cc];
+        }
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i)
@@ -634,16 +662,14 @@ __global__ __launch_bounds__(1024) void fe_cell_bf16_kernel(KBatch<float> kb, co
         u[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fB[(mb * 4 + k4) * 64 + lane], z[k4], u[mb], 0, 0, 0);
     }
     // T = (W V) o U, as the operand of B^T T (point 16 mb + 4 g + v of U sits in lane g, element v)
-    const float* wv = WV + e * nd;
     bf16x8 tq[4];
 #pragma unroll
     for (int k4 = 0; k4 < 4; ++k4)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int q0 = 32 * k4 + 4 * g + v, q1 = q0 + 16;
-        const float w0 = wv[q0 < nd ? q0 : 0], w1 = wv[q1 < nd ? q1 : 0];
-        tq[k4][v] = (__bf16)(q0 < nd ? w0 * u[2 * k4][v] : 0.0f);
-        tq[k4][4 + v] = (__bf16)(q1 < nd ? w1 * u[2 * k4 + 1][v] : 0.0f);
+        tq[k4][v] = (__bf16)(q0 < nd ? wq[k4][v] * u[2 * k4][v] : 0.0f);
+        tq[k4][4 + v] = (__bf16)(q1 < nd ? wq[k4][4 + v] * u[2 * k4 + 1][v] : 0.0f);
       }
     // Y = K Z + B^T T, stored to the node-slot grid
 #pragma unroll 2
@@ -654,17 +680,26 @@ __global__ __launch_bounds__(1024) void fe_cell_bf16_kernel(KBatch<float> kb, co
         y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fK[(mb * 4 + k4) * 64 + lane], z[k4], y, 0, 0, 0);
         y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fBT[(mb * 4 + k4) * 64 + lane], tq[k4], y, 0, 0, 0);
       }
+      if (interior) {
+        const int64_t sbase = (cx * P1 + 1) + (int64_t)S * ((cy * P1 + 1) + (int64_t)S * (cz * P1 + 1));
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = 16 * mb + 4 * g + v;
-        if (cok && a < nd) {
-          const int code = ncode[a];
-          int sx = cx * P1 + (code & 255) + 1, sy = cy * P1 + ((code >> 8) & 255) + 1,
-              sz = cz * P1 + (code >> 16) + 1;
-          sx -= sx >= S ? S : 0;
-          sy -= sy >= S ? S : 0;
-          sz -= sz >= S ? S : 0;
-          Yc[(sx + (int64_t)S * (sy + (int64_t)S * sz)) * ldc + col] = y[v];
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * mb + 4 * g + v;
+          if (cok && a < nd) Yc[(sbase + soff[a]) * ldc + col] = y[v];
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * mb + 4 * g + v;
+          if (cok && a < nd) {
+            const int code = ncode[a];
+            int sx = cx * P1 + (code & 255) + 1, sy = cy * P1 + ((code >> 8) & 255) + 1,
+                sz = cz * P1 + (code >> 16) + 1;
+            sx -= sx >= S ? S : 0;
+            sy -= sy >= S ? S : 0;
+            sz -= sz >= S ? S : 0;
+            Yc[(sx + (int64_t)S * (sy + (int64_t)S * sz)) * ldc + col] = y[v];
+          }
         }
       }
     }
@@ -1382,12 +1417,12 @@ inline int reduce_chunks(const oefe_op_s* op) { return std::max(1, (int)cdiv(op-
 
 // Steps of several operators sharing one mesh and enrichment layout, in lockstep.
 void launch_cell_bf16(const oefe_op_s* op, const KBatch<float>& kb, hipStream_t s) {
-  const size_t lds = 3 * (size_t)kBf16MatElems * sizeof(uint16_t) + 128 * (sizeof(int) + sizeof(float));
+  const size_t lds = 3 * (size_t)kBf16MatElems * sizeof(uint16_t) + 128 * (3 * sizeof(int) + sizeof(float));
   if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_cell_bf16_kernel), lds) != hipSuccess) return;
   int cus = 256;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  hipLaunchKernelGGL(fe_cell_bf16_kernel, dim3((unsigned)std::max(1, cus / kb.nk), 1, (unsigned)kb.nk), dim3(1024),
+  hipLaunchKernelGGL(fe_cell_bf16_kernel, dim3((unsigned)std::max(1, cus / kb.nk), 1, (unsigned)kb.nk), dim3(768),
                      lds, s, kb, op->d.bf_mats, op->d.WVf, op->cf, op->nc, op->p, op->n, op->P1, op->n_cells);
 }
 
