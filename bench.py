@@ -54,7 +54,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 CELL_FLOPS_P4 = 14500.0
 
 OPS_SOURCE = os.path.join(ROOT, "paper_2010_09701_amd", "csrc", "oefe_ops.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fe_node_mfma_kernel_diamond8_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fe_node_fused_kernel_diamond8_traffic.md")
 CALIB_BYTES = 512 * 2**20
 
 
@@ -169,8 +169,19 @@ def kpoint_bench(oefe, wl, torch, base, m, reps):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        res[name] = {"filter_ms": ms, "rate": work / (ms / 1e3), "shape": {"cw": tune["cw"], "cb": tune["cb"]}}
-        log(f"k-points {name}: batched filter {ms:.3f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s, shape {tune}")
+        # per-launch stage durations (HIP events on the stream each stage runs on; the
+        # coupling kernel runs on the side stream beside the cell stage)
+        stages = {}
+        for which in ("cell", "node", "coupling"):
+            ops[0].kernel_timer(which)
+            oefe.chebyshev_filter_batched(ops, Xs, m, abc)
+            n_launch, tot_ms = ops[0].kernel_timer_read()
+            ops[0].kernel_timer("off")
+            stages[which + "_us"] = tot_ms / max(n_launch, 1) * 1e3
+        res[name] = {"filter_ms": ms, "rate": work / (ms / 1e3), "shape": {"cw": tune["cw"], "cb": tune["cb"]},
+                     "stage_avg_us": stages}
+        log(f"k-points {name}: batched filter {ms:.3f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s, shape {tune}, "
+            + ", ".join(f"{k} {v:.1f}" for k, v in stages.items()))
     res["unit"] = "DoF*vec*deg/s (complex vectors)"
     return res
 
@@ -222,7 +233,7 @@ def summarize_traffic(fetch_dir, write_dir):
     fe = _per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
     wr = _per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
     # the filter's node-kernel instance is the float64 one launched most often
-    node = sorted((k for k in fe if k.startswith("fe_node_mfma_kernel<double")), key=lambda k: -len(fe[k]))
+    node = sorted((k for k in fe if k.startswith("fe_node_fused_kernel<double")), key=lambda k: -len(fe[k]))
     copy = [k for k in fe if "copyBuffer" in k or "copy_kernel" in k]
     if not node or not copy:
         sys.exit(f"kernels not found: {sorted(fe)}")
@@ -380,7 +391,7 @@ def main():
         "config": {"workload": f"{sysm.name}: {sysm.nc}^3 cells p={sysm.p}, {gop.n_fe} FE + {gop.n_enr} "
                                f"enrichment DoF, {cfg.nv} vectors, Chebyshev degree {cfg.m}",
                    "global_batch": cfg.nv, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "fe_node_mfma_kernel<double>", "achieved": node_gbs,
+        "roofline": {"bound": "hbm", "kernel": "fe_node_fused_kernel<double>", "achieved": node_gbs,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": node_gbs / PEAK_HBM_GBS,
                      "traffic": traffic, "avg_launch_us": node_ms * 1e3, "bytes_per_launch": node_bytes},
         "extra": extra,

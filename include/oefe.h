@@ -161,14 +161,19 @@ size_t oefe_batched_work_size(int32_t nk, const oefe_op* ops, oefe_prec prec, co
  * 0 (built-in) puts the (p+1) planes of a cell tensor in the lanes of one wave
  * (64/(p+1) columns, rounded down to even, per wave); 8, 16, 32 or 64 put one
  * plane per wave with cw real columns per cell in a 64-lane tile (64/cw cells).
- * cb is the node-stage vector-block width (real columns per workgroup, used in
- * 16-column units, <= 128; 0 = built-in).  Results do not depend on the shape. */
+ * cb (a multiple of 16 up to 128; 0 = built-in) is the real-column width of one
+ * unit of the node stage: the workgroup of the fused node kernel of a real
+ * operator (at most 80 columns are used: built-in, all columns up to 80, else
+ * near-equal blocks), or one
+ * wave of the coupling kernel (the H^co products) of a Bloch operator, where 16,
+ * 32 and 64 are used (larger values act as 64; built-in 16).  Results do not
+ * depend on the shape. */
 int oefe_set_launch_shape(oefe_op op, int32_t cw, int32_t cb);
 
 /* Autotuner of the launch shape for a batch of operators (nk >= 1, same rules
  * as chebyshev_filter_batched).  Times `reps` batched recurrence steps on
  * copies of the blocks X[q] for each cw in {0, 8, 16, 32, 64} and cb in
- * {32, 64, 96, 128}, with HIP events on `stream`, and sets the fastest shape on
+ * {16, 32, 64, 128}, with HIP events on `stream`, and sets the fastest shape on
  * every operator.  X is not modified.  work: oefe_batched_work_size(nk, ops,
  * prec, nv) bytes.  Outputs (host, may be NULL): the chosen cw, cb and the
  * time of one batched step in ms.  Synchronizes the stream. */
@@ -207,11 +212,20 @@ int band_energy_grad(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int3
 /* Instrumentation.  While a kernel is selected, each of its launches inside
  * ham_apply / chebyshev_filter* is bracketed by HIP events on the stream it is
  * launched on.  which: OEFE_TIMER_OFF, OEFE_TIMER_CELL (the sum-factorized
- * H^cc cell stage) or OEFE_TIMER_NODE (the node stage: slot gather, coupling
- * blocks, recurrence epilogue).  oefe_kernel_timer_read synchronizes, returns
- * the number of bracketed launches and their summed duration (ms), and clears
- * the record.  Selecting a kernel discards events not yet read. */
-typedef enum { OEFE_TIMER_OFF = 0, OEFE_TIMER_CELL = 1, OEFE_TIMER_NODE = 2 } oefe_timer_kind;
+ * H^cc cell stage), OEFE_TIMER_NODE (the node stage on the main stream: for a
+ * real operator the fused kernel with the slot gather, the H^co products and the
+ * recurrence epilogue; for a Bloch operator the node assembly, slot gather and
+ * epilogue) or OEFE_TIMER_COUPLING (the H^co products of a Bloch operator, on
+ * the filter's side stream).  oefe_kernel_timer_read
+ * synchronizes, returns the number of bracketed launches and their summed
+ * duration (ms), and clears the record.  Selecting a kernel discards events not
+ * yet read. */
+typedef enum {
+  OEFE_TIMER_OFF = 0,
+  OEFE_TIMER_CELL = 1,
+  OEFE_TIMER_NODE = 2,
+  OEFE_TIMER_COUPLING = 3
+} oefe_timer_kind;
 int oefe_kernel_timer(oefe_op op, int which);
 int oefe_kernel_timer_read(oefe_op op, int64_t* launches, double* total_ms);
 

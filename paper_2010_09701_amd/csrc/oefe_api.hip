@@ -447,11 +447,13 @@ int overlap_setup(const oefe_op_s* op, Overlap* ov) {
   if (!op->side_stream) {
     hipError_t e = hipStreamCreateWithFlags(&op->side_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_node, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_k1, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_zo, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "overlap stream setup");
   }
   ov->side = op->side_stream;
   ov->ev_node = op->ev_node;
+  ov->ev_k1 = op->ev_k1;
   ov->ev_zo = op->ev_zo;
   ov->first = ov->last = false;
   return OEFE_OK;
@@ -536,7 +538,7 @@ const char* oefe_last_error(void) { return g_last_error.c_str(); }
 
 int oefe_kernel_timer(oefe_op op, int which) {
   if (!op) return fail(OEFE_EINVAL, "null operator");
-  if (which < OEFE_TIMER_OFF || which > OEFE_TIMER_NODE) return fail(OEFE_EINVAL, "unknown timer kind");
+  if (which < OEFE_TIMER_OFF || which > OEFE_TIMER_COUPLING) return fail(OEFE_EINVAL, "unknown timer kind");
   for (auto& pr : op->timer_events) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
@@ -623,6 +625,7 @@ int oefe_op_destroy(oefe_op op) {
     (void)hipStreamSynchronize(op->side_stream);
     (void)hipStreamDestroy(op->side_stream);
     (void)hipEventDestroy(op->ev_node);
+    (void)hipEventDestroy(op->ev_k1);
     (void)hipEventDestroy(op->ev_zo);
   }
   free_device(op);
@@ -752,7 +755,7 @@ size_t oefe_batched_work_size(int32_t nk, const oefe_op* ops, oefe_prec prec, co
 int oefe_set_launch_shape(oefe_op op, int32_t cw, int32_t cb) {
   if (!op) return fail(OEFE_EINVAL, "null operator");
   if (!(cw == 0 || cw == 8 || cw == 16 || cw == 32 || cw == 64)) return fail(OEFE_EINVAL, "cw must be 0, 8, 16, 32 or 64");
-  if (cb < 0 || cb > 128 || cb % 8) return fail(OEFE_EINVAL, "cb must be a multiple of 8 in [0, 128]");
+  if (cb < 0 || cb > 128 || cb % 16) return fail(OEFE_EINVAL, "cb must be a multiple of 16 in [0, 128]");
   op->tune_cw = cw;
   op->tune_cb = cb;
   return OEFE_OK;
@@ -762,8 +765,8 @@ int oefe_set_launch_shape(oefe_op op, int32_t cw, int32_t cb) {
 
 namespace {
 // Launch-shape tuner: times one batched operator step (out = alpha (Ht x - c x) - beta out,
-// the filter's access pattern, bounded values) for each candidate cell-tile width cw and
-// node vector-block width cb, and keeps the fastest on every operator.
+// the filter's access pattern and stream overlap, bounded values) for each candidate
+// cell-tile width cw and node-stage column width cb, and keeps the fastest on every operator.
 template <typename T>
 int autotune_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const int64_t* ld, const int32_t* nv,
                   int reps, void* work, int32_t* cw_out, int32_t* cb_out, double* ms_out, hipStream_t s) {
@@ -796,7 +799,10 @@ int autotune_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const i
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return OEFE_EDEVICE;
   const int cws[5] = {0, 8, 16, 32, 64};
-  const int cbs[4] = {32, 64, 96, 128};
+  const int cbs[4] = {16, 32, 64, 128};
+  Overlap ov;
+  if (int e = overlap_setup(opp[0], &ov)) return e;
+  ov.first = ov.last = true;  // each timed step is a whole overlapped step
   double best = 1e300;
   int bcw = 0, bcb = 0, rc = OEFE_OK;
   for (int a = 0; a < 5 && !rc; ++a)
@@ -807,7 +813,7 @@ int autotune_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const i
       }
       auto step = [&] {
         return apply_step_batch<T>(opp, nk, bf16, xin.data(), ldp.data(), pin.data(), outp.data(), ldp.data(),
-                                   nvv.data(), al.data(), cc.data(), be.data(), sw.data(), s);
+                                   nvv.data(), al.data(), cc.data(), be.data(), sw.data(), s, &ov);
       };
       rc = step();  // warm-up (first launch of this instantiation)
       if (rc) break;
@@ -823,6 +829,7 @@ int autotune_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const i
         bcb = cbs[b];
       }
     }
+  (void)hipStreamWaitEvent(s, ov.ev_zo, 0);  // side work of a step that stopped early
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (int q = 0; q < nk; ++q) {

@@ -143,7 +143,7 @@ struct oefe_op_s {
   int timer_kind = 0;  // oefe_timer_kind
   // side stream and events of the overlapped recurrence (created on first use)
   mutable hipStream_t side_stream = nullptr;
-  mutable hipEvent_t ev_node = nullptr, ev_zo = nullptr;
+  mutable hipEvent_t ev_node = nullptr, ev_k1 = nullptr, ev_zo = nullptr;
   mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;
 };
 

@@ -26,14 +26,15 @@ inline hipError_t allow_dynamic_lds(const void* kernel, size_t dynamic_bytes) {
 size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, int* ldc_out);
 StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, void* work);
 
-// Overlap of a recurrence: the enrichment-row chain of step k (partial fold,
-// W', enrichment rows of out, and Z^O of step k+1) runs on `side` while the main
-// stream starts the cell stage of step k+1; the node stage of step k+1 waits for it.
-// first: this step computes its own Z^O on the main stream; last: the main stream
-// waits for the chain at the end of the step.
+// Overlap of a recurrence: the enrichment side of step k (the coupling kernel, then
+// the partial fold, W', the enrichment rows of out and Z^O of step k+1) runs on `side`
+// beside the cell stage of step k; the node assembly of step k waits for the coupling
+// kernel (ev_k1), and the side work of step k+1 waits for that assembly (ev_node).
+// first: this step computes its own Z^O; last: the main stream waits for the side
+// chain (ev_zo) at the end of the step.
 struct Overlap {
   hipStream_t side;
-  hipEvent_t ev_node, ev_zo;
+  hipEvent_t ev_node, ev_k1, ev_zo;
   bool first, last;
 };
 

@@ -707,16 +707,25 @@ __global__ __launch_bounds__(768) void fe_cell_bf16_kernel(KBatch<float> kb, con
 }
 
 // ---------------------------------------------------------------------------
-// Node kernel: FE rows, one workgroup (4 waves) per tile of kTileRows consecutive
-// FE rows x 16 NB real columns.  Three parts, the two dense ones on the matrix cores
-// (16x16x4 MFMA, float64 or float32):
-//   en   = Ht_t Z^O                 (Ht_t: the tile's dense block of m^-1/2 H^co)
-//   part = Ht_t^* X_t               -> per-tile partial of W' (reduced later)
-//   out  = alpha (m^-1/2 sum_slots(Y) + en - c x) - beta prev
-// sum_slots adds, in a fixed order, the (up to 8) cell results stored for the node
-// in the node-slot grid (no atomics).  Complex columns are interleaved (re, im);
-// a complex product is two real MFMA passes over the real and imaginary parts of
-// Ht with the matching (swapped, signed) columns of Z^O or X.
+// Node stage, split in two kernels so that the dense coupling work leaves the
+// critical path:
+//
+// fe_coupling_kernel (side stream, beside the cell stage; needs only X and Z^O):
+//   for each tile t of kTileRows consecutive FE rows and each group of 16 NBW real columns
+//     part_t = Ht_t^* X_t              -> per-tile partial of W' (reduced later)
+//     out_t  = alpha Ht_t Z^O - beta prev_t
+//   (Ht_t: the tile's dense block of m^-1/2 H^co) on the matrix cores (16x16x4 MFMA,
+//   float64 or float32).  One wave per (tile, column group), no LDS and no barriers: the
+//   tile's block and Z^O are read through the caches, shared by the waves of a tile.
+//
+// fe_assemble_kernel (main stream, after the cell stage), one element per thread:
+//   out = alpha (m^-1/2 sum_slots(Y) - c x) + base,  base = out (the coupling kernel's
+//   result) or -beta prev when the operator has no enrichment.
+//   sum_slots adds, in a fixed order, the (up to 8) cell results stored for the node in
+//   the node-slot grid (no atomics).
+//
+// Complex columns are interleaved (re, im); a complex product is two real MFMA passes
+// over the real and imaginary parts of Ht with the matching (swapped, signed) columns.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Mfma;
@@ -738,27 +747,323 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-constexpr int kNodeNBMax = 8;  // 16-column blocks per node workgroup (128 real columns)
+constexpr int kCoupleNBWMax = 4;  // 16-column blocks per coupling wave
 
-// LDS of the node kernel: the tile's rows of X (its column block) and its dense
-// block of m^-1/2 H^co, each row padded by one element.
+// part columns of NQ blocks of 16 functions (from function m0) over the tile's TR rows:
+// pc[q][nb] += Ht_t[r][m0 + 16 q + .]^* x[r][cols of block nb], k-steps of 4 rows issued
+// in batches of 4 (loads first, then the MFMAs)
+template <typename T, int NQ, int NBW, bool CPLX>
+__device__ __forceinline__ void coupling_part(const T* __restrict__ tv, const T* __restrict__ x, int64_t ldx,
+                                              int g0, int N, int FP, int m0, const int (&colc)[NBW], int li,
+                                              int lk, typename Mfma<T>::V4 (&pc)[4][NBW]) {
+  using M = Mfma<T>;
+  constexpr int TR = kTileRows, E = CPLX ? 2 : 1, KB = 4;
+  const T sgn = (li & 1) ? T(-1) : T(1);
+  int fcl[NQ];
+  bool fok[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int f = m0 + q * 16 + li;
+    fok[q] = f < FP;
+    fcl[q] = fok[q] ? f : FP - 1;
+  }
+  for (int ks0 = 0; ks0 < TR / 4; ks0 += KB) {
+    T b[KB][E][NBW], a[KB][NQ][E];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int r = (ks0 + j) * 4 + lk;
+      const bool rok = g0 + r < N;
+      const int64_t g = rok ? g0 + r : N - 1;
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        const T xv = x[g * ldx + colc[nb]];
+        b[j][0][nb] = rok ? xv : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const T av = tv[((int64_t)r * FP + fcl[q]) * E + e];
+          a[j][q][e] = fok[q] ? av : T(0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if constexpr (CPLX) {
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) b[j][1][nb] = sgn * __shfl_xor(b[j][0][nb], 1);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int nb = 0; nb < NBW; ++nb) pc[q][nb] = M::op(a[j][q][e], b[j][e][nb], pc[q][nb]);
+    }
+  }
+}
+
+template <typename T, int NBW, bool CPLX>
+__global__ __launch_bounds__(256) void fe_coupling_kernel(KBatch<T> kb, const int32_t* __restrict__ tile_fptr,
+                                                          const int32_t* __restrict__ tile_fns, int n_tiles,
+                                                          int ngrp, int N) {
+  using M = Mfma<T>;
+  using V4 = typename M::V4;
+  constexpr int TR = kTileRows, E = CPLX ? 2 : 1, RB = TR / 16;
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int ncr = P.ncr;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= n_tiles * ngrp) return;
+  const int t = item / ngrp, grp = item - t * ngrp;
+  const int cb0 = grp * 16 * NBW;
+  if (cb0 >= ncr) return;  // column group beyond this operator's width
+  const int g0 = t * TR;
+  const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;  // FP: a multiple of 4
+  const T* __restrict__ tv = P.tv + (int64_t)f0 * TR * E;   // [TR][FP][E], zero rows past N
+  const T* __restrict__ x = P.x;
+  const T* __restrict__ zo = P.zo;  // [n_enr][ncr]
+  const int64_t ldx = P.ldx, ldo = P.ldo;
+  // Loads are unconditional, from clamped in-bounds addresses, with unwanted values
+  // replaced by selects, so that each batch is issued at once.
+  int colc[NBW];
+  bool colok[NBW];
+#pragma unroll
+  for (int nb = 0; nb < NBW; ++nb) {
+    const int col = cb0 + nb * 16 + li;
+    colok[nb] = col < ncr;
+    colc[nb] = colok[nb] ? col : ncr - 1;
+  }
+
+  // ---- part = Ht_t^* X_t, up to 4 blocks of 16 functions at a time
+  // (complex: e = 1 pairs Im(H) with the partner column, signed)
+  for (int m0 = 0; m0 < FP; m0 += 64) {
+    V4 pc[4][NBW];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) pc[q][nb] = V4{0, 0, 0, 0};
+    const int nq = min(4, (FP - m0 + 15) / 16);
+    switch (nq) {
+      case 4: coupling_part<T, 4, NBW, CPLX>(tv, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+      case 3: coupling_part<T, 3, NBW, CPLX>(tv, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+      case 2: coupling_part<T, 2, NBW, CPLX>(tv, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+      default: coupling_part<T, 1, NBW, CPLX>(tv, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q >= nq) break;
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) {
+        if (!colok[nb]) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int fi = m0 + q * 16 + M::row(lane, v);
+          if (fi < FP) P.part[(int64_t)(f0 + fi) * ncr + colc[nb]] = pc[q][nb][v];
+        }
+      }
+    }
+  }
+
+  // ---- en = Ht_t Z^O for the RB 16-row blocks of the tile, k-steps of 4 functions in
+  // batches of KB (a k-step past the list multiplies zero columns of Z^O); the function
+  // list is held one entry per lane and broadcast
+  V4 acc[RB][NBW];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) acc[rb][nb] = V4{0, 0, 0, 0};
+  {
+    constexpr int KB = 2;
+    const T sgn = (li & 1) ? T(1) : T(-1);
+    for (int c0 = 0; c0 < FP; c0 += 64) {
+      const int fnl = c0 + lane < FP ? tile_fns[f0 + c0 + lane] : -1;
+      const int kc = min(64, FP - c0);
+      for (int k0 = 0; k0 < kc; k0 += 4 * KB) {
+        T b[KB][E][NBW], a[KB][RB][E];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+          const int kl = min(k0 + 4 * j + lk, 63);
+          const int fn = __shfl(fnl, kl);  // -1 past the list
+          const int f = min(c0 + kl, FP - 1);
+          const T* __restrict__ zr = zo + (int64_t)max(fn, 0) * ncr;
+#pragma unroll
+          for (int nb = 0; nb < NBW; ++nb) {
+            const T zv = zr[colc[nb]];
+            b[j][0][nb] = fn >= 0 ? zv : T(0);
+          }
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int e = 0; e < E; ++e) a[j][rb][e] = tv[((int64_t)(rb * 16 + li) * FP + f) * E + e];
+        }
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+          if constexpr (CPLX) {
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) b[j][1][nb] = sgn * __shfl_xor(b[j][0][nb], 1);
+          }
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+              for (int nb = 0; nb < NBW; ++nb) acc[rb][nb] = M::op(a[j][rb][e], b[j][e][nb], acc[rb][nb]);
+        }
+      }
+    }
+  }
+
+  // ---- out = alpha en - beta prev (prev may be the same array as out: all of this
+  // lane's elements are read before any is written)
+  const T alpha = P.alpha, beta = P.beta;
+  T pv[RB][4][NBW];
+  if (beta != T(0)) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t g = min(g0 + rb * 16 + M::row(lane, v), N - 1);
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) pv[rb][v][nb] = beta * P.prev[g * ldo + colc[nb]];
+      }
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) pv[rb][v][nb] = T(0);
+  }
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gv = g0 + rb * 16 + M::row(lane, v);
+      if (gv >= N) continue;
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb)
+        if (colok[nb]) P.out[(int64_t)gv * ldo + colc[nb]] = alpha * acc[rb][nb][v] - pv[rb][v][nb];
+    }
+}
+
+// Flat element index -> (row, column) for rows of nel elements, without a 64-bit
+// integer division: a float64 quotient corrected by one step.
+__device__ __forceinline__ int64_t row_of(int64_t i, int nel, double rnel) {
+  int64_t g = (int64_t)((double)i * rnel);
+  const int64_t r = i - g * nel;
+  g += r < 0 ? -1 : (r >= nel ? 1 : 0);
+  return g;
+}
+
+template <typename T, bool CPLX>
+__device__ __forceinline__ void assemble_one(const KP<T>& P, int64_t i, int nel, double rnel, int nc, int p, int n,
+                                             int P1, const CellCoef<T>& cf, int base_in_out);
+
+template <typename T, bool CPLX>
+__global__ __launch_bounds__(256) void fe_assemble_kernel(KBatch<T> kb, int nc, int p, int n, int P1, CellCoef<T> cf,
+                                                          int N, int base_in_out) {
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int nel = CPLX ? P.nv : P.ncr;  // elements per row: complex pairs or real columns
+  const int64_t total = (int64_t)N * nel;
+  const double rnel = 1.0 / nel;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+    assemble_one<T, CPLX>(P, i, nel, rnel, nc, p, n, P1, cf, base_in_out);
+}
+
+template <typename T, bool CPLX>
+__device__ __forceinline__ void assemble_one(const KP<T>& P, int64_t i, int nel, double rnel, int nc, int p, int n,
+                                             int P1, const CellCoef<T>& cf, int base_in_out) {
+  const int64_t g = row_of(i, nel, rnel);
+  const int j = (int)(i - g * nel);
+  const int gi = (int)g;
+  const int iz = gi / (n * n), rem = gi - iz * n * n, iy = rem / n, ix = rem - iy * n;
+  const int qx = ix / p, rx = ix - qx * p, qy = iy / p, ry = iy - qy * p, qz = iz / p, rz = iz - qz * p;
+  const int S = nc * P1;
+  const int bx = qx * P1 + (rx ? rx + 1 : 0), by = qy * P1 + (ry ? ry + 1 : 0), bz = qz * P1 + (rz ? rz + 1 : 0);
+  const T msc = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
+  const T* __restrict__ Yc = P.ycell;
+  const int64_t ldc = P.ldc;
+  const T alpha = P.alpha, c = P.c, beta = P.beta;
+  // (ky, kz) slot pairs in a fixed order, each the lower-x slot then (shared x node) the next one
+  if constexpr (!CPLX) {
+    T s = 0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int ky = kk & 1, kz = kk >> 1;
+      if ((ky && ry) || (kz && rz)) continue;
+      const int64_t r0 = bx + (int64_t)S * (by + ky + (int64_t)S * (bz + kz));
+      T add = Yc[r0 * ldc + j];
+      if (rx == 0) add += Yc[(r0 + 1) * ldc + j];
+      s += add;
+    }
+    const int64_t io = g * P.ldo + j;
+    const T base = base_in_out ? P.out[io] : (beta != T(0) ? -beta * P.prev[io] : T(0));
+    P.out[io] = alpha * (msc * s - c * P.x[g * P.ldx + j]) + base;
+  } else {
+    const Phase3<T> ph = P.ph;
+    C2<T> s{0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int ky = kk & 1, kz = kk >> 1;
+      if ((ky && ry) || (kz && rz)) continue;
+      const int sy = by + ky, sz = bz + kz;
+      const int64_t r0 = bx + (int64_t)S * (sy + (int64_t)S * sz);
+      C2<T> z0{Yc[r0 * ldc + 2 * j], Yc[r0 * ldc + 2 * j + 1]};
+      C2<T> z1{0, 0};
+      if (rx == 0) z1 = C2<T>{Yc[(r0 + 1) * ldc + 2 * j], Yc[(r0 + 1) * ldc + 2 * j + 1]};
+      // periodic images: slot 0 of a dimension came from the last cell
+      if (bx == 0) z0 = cjmul(C2<T>{ph.re[0], ph.im[0]}, z0);
+      if (sy == 0) {
+        z0 = cjmul(C2<T>{ph.re[1], ph.im[1]}, z0);
+        z1 = cjmul(C2<T>{ph.re[1], ph.im[1]}, z1);
+      }
+      if (sz == 0) {
+        z0 = cjmul(C2<T>{ph.re[2], ph.im[2]}, z0);
+        z1 = cjmul(C2<T>{ph.re[2], ph.im[2]}, z1);
+      }
+      s.r += z0.r + z1.r;
+      s.i += z0.i + z1.i;
+    }
+    const int64_t io = g * P.ldo + 2 * j, ix2 = g * P.ldx + 2 * j;
+    C2<T> base{0, 0};
+    if (base_in_out) base = C2<T>{P.out[io], P.out[io + 1]};
+    else if (beta != T(0)) base = C2<T>{-beta * P.prev[io], -beta * P.prev[io + 1]};
+    P.out[io] = alpha * (msc * s.r - c * P.x[ix2]) + base.r;
+    P.out[io + 1] = alpha * (msc * s.i - c * P.x[ix2 + 1]) + base.i;
+  }
+}
+
+// Node stage of real operators in one kernel, fe_node_fused_kernel: one workgroup (4
+// waves) per tile of kTileRows FE rows x 16 NB real columns computes part, the slot
+// gather and out = alpha (m^-1/2 sum_slots(Y) + Ht_t Z^O - c x) - beta prev.  Order within
+// the workgroup: one batch of loads (x tile, H tile, function list; float32 also the
+// first slot pair of the gather, which lands during the matrix-core phase), part on the
+// matrix cores, the gather, acc = m^-1/2 sum - c x, then Ht_t Z^O accumulated onto acc
+// from Z^O rows staged in LDS, with the previous iterate loaded beside them.
+// LDS of the node kernel: the tile's rows of X (its column block; reused afterwards
+// for chunks of up to kTileRows rows of Z^O), its dense block of m^-1/2 H^co, and the
+// tile's function list.
 // Row strides (in elements) of the node kernel's LDS tiles, padded to 16 mod 32 so that the
 // two row groups of a half-wave in the MFMA operand reads fall into disjoint banks.
 constexpr int lds_row_stride(int w) { return w + (((16 - w % 32) % 32) + 32) % 32; }
 
-template <typename T, int NB, bool CPLX>
+constexpr int kNodeNBMax = 5;  // 16-column blocks per fused node workgroup (80 real columns: no spills)
+
+template <typename T, int NB>
 constexpr size_t node_lds_bytes(int fpmax) {
-  return (size_t)kTileRows * (lds_row_stride(NB * 16) + lds_row_stride(fpmax * (CPLX ? 2 : 1))) * sizeof(T);
+  return (size_t)kTileRows * (lds_row_stride(NB * 16) + lds_row_stride(fpmax)) * sizeof(T) +
+         (size_t)fpmax * sizeof(int32_t);
 }
 
-template <typename T, int NB, bool CPLX>
-__global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<T> kb, int nc, int p, int n, int P1,
-                                                                         CellCoef<T> cf,
-                                                                         const int32_t* __restrict__ tile_fptr,
-                                                                         const int32_t* __restrict__ tile_fns, int N) {
+template <typename T, int NB>
+__global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int nc, int p, int n, int P1,
+                                                               CellCoef<T> cf, const int32_t* __restrict__ tile_fptr,
+                                                               const int32_t* __restrict__ tile_fns, int N) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
-  constexpr int TR = kTileRows, E = CPLX ? 2 : 1, CBW = NB * 16, XS = lds_row_stride(CBW);
+  constexpr int TR = kTileRows, CBW = NB * 16, XS = lds_row_stride(CBW);
+  constexpr int XPT = TR * CBW / 256;  // staged elements per thread of one TR x CBW block
   extern __shared__ unsigned char smem_raw[];
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
@@ -769,13 +1074,21 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
   const int t = blockIdx.x;
   const int g0 = t * TR;
   const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
-  const int HS = lds_row_stride(FP * E);
-  T* xs = reinterpret_cast<T*>(smem_raw);  // [TR][XS]: x rows of the tile, zero past N
-  T* hs = xs + TR * XS;                     // [TR][HS]: the tile's block, (re, im) per function
-  const T* __restrict__ tv = P.tv + (int64_t)f0 * TR * E;  // [TR][FP][E]
+  const int HS = lds_row_stride(FP);
+  T* xs = reinterpret_cast<T*>(smem_raw);  // [TR][XS]: x rows of the tile (zero past N), later Z^O rows
+  T* hs = xs + TR * XS;                     // [TR][HS]: the tile's block
+  int32_t* fs = reinterpret_cast<int32_t*>(hs + TR * HS);  // [FP]: enrichment function of each tile column
+  const T* __restrict__ tv = P.tv + (int64_t)f0 * TR;  // [TR][FP]
   const T* __restrict__ zo = P.zo;                         // [n_enr][ncr]
   const T* __restrict__ x = P.x;
   const int64_t ldx = P.ldx;
+  const T* __restrict__ Yc = P.ycell;
+  const int64_t ldc = P.ldc;
+  const T alpha = P.alpha, c = P.c, beta = P.beta;
+  const T* prev = P.prev;  // may be the same array as out (each element is read before it is written)
+  T* out = P.out;
+  const int64_t ldo = P.ldo;
+  const int S = nc * P1;
   // Global loads below are unconditional, from clamped in-bounds addresses, with
   // unwanted values replaced by selects, so that each batch is issued at once.
   int colc[NB];
@@ -787,47 +1100,6 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
     colc[nb] = colok[nb] ? col : ncr - 1;
   }
 
-  // ---- stage the x tile and the H tile in LDS (one batch of coalesced loads each)
-  {
-    constexpr int XPT = TR * CBW / 256;
-    T xv[XPT];
-#pragma unroll
-    for (int i = 0; i < XPT; ++i) {
-      const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
-      const int g = min(g0 + r, N - 1), col = min(cb0 + cl, ncr - 1);
-      xv[i] = x[(int64_t)g * ldx + col];
-    }
-#pragma unroll
-    for (int i = 0; i < XPT; ++i) {
-      const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
-      xs[r * XS + cl] = g0 + r < N ? xv[i] : T(0);
-    }
-    const int nh = TR * FP * E;
-    for (int q0 = 0; q0 < nh; q0 += 256 * 8) {
-      T hv[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) hv[i] = tv[min(q0 + (int)threadIdx.x + 256 * i, nh - 1)];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int q = q0 + threadIdx.x + 256 * i;
-        if (q < nh) {
-          const int r = q / (FP * E);
-          hs[r * HS + (q - r * FP * E)] = hv[i];
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- node-slot gather + recurrence epilogue on the en layout
-  const T* __restrict__ Yc = P.ycell;
-  const int64_t ldc = P.ldc;
-  const Phase3<T> ph = P.ph;
-  const T alpha = P.alpha, c = P.c, beta = P.beta;
-  const T* __restrict__ prev = P.prev;
-  T* __restrict__ out = P.out;
-  const int64_t ldo = P.ldo;
-  const int S = nc * P1;
   // slots of node i per dimension: a shared node (i mod p == 0) has two, the one from
   // the lower cell first; slot 0 holds the periodic image of the last cell
   int bx[4], by[4], bz[4], gc[4];
@@ -849,27 +1121,76 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
     z2[v] = rz == 0;
     msc[v] = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
   }
-  // real float32 blocks: the first slot pair's loads are issued now and land during the MFMA
-  // phases (float64 has no registers to spare for them)
-  constexpr bool kEarly = !CPLX && sizeof(T) == 4;
+
+  // ---- one batch of loads: the x tile, the first part of the H tile, the function list
+  // and (real columns) the first slot pair of the gather, which lands during the
+  // matrix-core phase below
+  constexpr bool kEarly = sizeof(T) == 4;
+  constexpr int HPT = 8;
+  const int nh = TR * FP;
   T gA[4][NB], gB[4][NB];
-  if constexpr (kEarly) {
+  {
+    T xv[XPT], hv[HPT];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t row = bx[v] + (int64_t)S * (by[v] + (int64_t)S * bz[v]);
-      const int64_t row2 = x2[v] ? row + 1 : row;
+    for (int i = 0; i < XPT; ++i) {
+      const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
+      const int g = min(g0 + r, N - 1), col = min(cb0 + cl, ncr - 1);
+      xv[i] = x[(int64_t)g * ldx + col];
+    }
+    if (FP > 0) {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        gA[v][nb] = Yc[row * ldc + colc[nb]];
-        gB[v][nb] = Yc[row2 * ldc + colc[nb]];
+      for (int i = 0; i < HPT; ++i) hv[i] = tv[min((int)threadIdx.x + 256 * i, nh - 1)];
+    }
+    const int32_t fv = (int)threadIdx.x < FP ? tile_fns[f0 + threadIdx.x] : 0;
+    if constexpr (kEarly) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = bx[v] + (int64_t)S * (by[v] + (int64_t)S * bz[v]);
+        const int64_t row2 = x2[v] ? row + 1 : row;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          gA[v][nb] = Yc[row * ldc + colc[nb]];
+          gB[v][nb] = Yc[row2 * ldc + colc[nb]];
+        }
+      }
+    }
+    if ((int)threadIdx.x < FP) fs[threadIdx.x] = fv;
+    for (int f = threadIdx.x + 256; f < FP; f += 256) fs[f] = tile_fns[f0 + f];
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
+      xs[r * XS + cl] = g0 + r < N ? xv[i] : T(0);
+    }
+    if (FP > 0) {
+#pragma unroll
+      for (int i = 0; i < HPT; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        if (q < nh) {
+          const int r = q / FP;
+          hs[r * HS + (q - r * FP)] = hv[i];
+        }
       }
     }
   }
+  // the rest of the H tile
+  for (int q0 = 256 * HPT; q0 < nh; q0 += 256 * HPT) {
+    T hv[HPT];
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) hv[i] = tv[min(q0 + (int)threadIdx.x + 256 * i, nh - 1)];
+#pragma unroll
+    for (int i = 0; i < HPT; ++i) {
+      const int q = q0 + threadIdx.x + 256 * i;
+      if (q < nh) {
+        const int r = q / FP;
+        hs[r * HS + (q - r * FP)] = hv[i];
+      }
+    }
+  }
+  __syncthreads();
 
   // ---- part = Ht_t^* X_t from LDS: (function block mb, column block nb) pairs over the 4 waves
   if (FP > 0) {
     const int MB = (FP + 15) / 16;
-    const T sgn_pt = (li & 1) ? T(-1) : T(1);
     // two (mb, nb) blocks per wave at a time: independent accumulator chains
     for (int q0 = w; q0 < MB * NB; q0 += 8) {
       const bool two = q0 + 4 < MB * NB;
@@ -889,14 +1210,10 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
       for (int ks = 0; ks < TR / 4; ++ks) {
         const int r = ks * 4 + lk;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const T av = hs[r * HS + fcs[h] * E + e];
-            const T a = foks[h] ? av : T(0);
-            const T b = (!CPLX || e == 0) ? xs[r * XS + cls[h]] : sgn_pt * xs[r * XS + (cls[h] ^ 1)];
-            pc[h] = M::op(a, b, pc[h]);
-          }
+        for (int h = 0; h < 2; ++h) {
+          const T av = hs[r * HS + fcs[h]];
+          const T a = foks[h] ? av : T(0);
+          pc[h] = M::op(a, xs[r * XS + cls[h]], pc[h]);
         }
       }
 #pragma unroll
@@ -916,6 +1233,7 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
     }
   }
 
+  // ---- node-slot gather: sum over the (up to 8) cell results stored for the node
   T sum[4][NB];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
@@ -930,48 +1248,6 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
         sum[v][nb] += ok[v] ? add : T(0);
       }
   }
-
-  // ---- en = Ht_t Z^O: rows w*16 .. w*16+15 of the tile (A from LDS, B from Z^O)
-  // complex: the second real pass pairs Im(H) with the partner column, signed
-  const T sgn_en = (li & 1) ? T(1) : T(-1);
-  V4 acc[NB];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = V4{0, 0, 0, 0};
-  {
-    constexpr int KCE = CPLX ? 2 : 4;  // k-steps per load batch
-    const int rA = w * 16 + li;
-    for (int k0 = 0; k0 < FP; k0 += 4 * KCE) {
-      int fn[KCE];
-#pragma unroll
-      for (int ks = 0; ks < KCE; ++ks) fn[ks] = tile_fns[f0 + min(k0 + ks * 4 + lk, FP - 1)];
-      T a[KCE][E], b[KCE][E][NB];
-#pragma unroll
-      for (int ks = 0; ks < KCE; ++ks) {
-        const int f = k0 + ks * 4 + lk;
-        const bool on = f < FP && fn[ks] >= 0;
-        const int fc = min(f, FP - 1);
-        const T* zr = zo + (int64_t)max(fn[ks], 0) * ncr;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const T av = hs[rA * HS + fc * E + e];
-          a[ks][e] = on ? av : T(0);
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            if (!CPLX || e == 0) b[ks][e][nb] = zr[colc[nb]];
-            else b[ks][e][nb] = sgn_en * zr[colc[nb] ^ 1];
-          }
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int ks = 0; ks < KCE; ++ks)
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a[ks][e], b[ks][e][nb], acc[nb]);
-    }
-  }
-
   // (ky, kz) slot pairs in a fixed order; a pair is visited when some lane of the
   // wave needs it, lanes that do not need it reload their first slot (in bounds,
   // cached) and discard it
@@ -994,48 +1270,69 @@ __global__ __launch_bounds__(256, CPLX ? 1 : 2) void fe_node_mfma_kernel(KBatch<
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int j = colc[nb];
-        if constexpr (!CPLX) {
-          const T v0 = Yc[row * ldc + j];
-          const T v1 = Yc[row2 * ldc + j];
-          const T add = v0 + (x2[v] ? v1 : T(0));
-          sum[v][nb] += need[v] ? add : T(0);
-        } else {
-          const int jr = j & ~1;
-          C2<T> z0{Yc[row * ldc + jr], Yc[row * ldc + jr + 1]};
-          C2<T> z1{Yc[row2 * ldc + jr], Yc[row2 * ldc + jr + 1]};
-          // periodic images: slot 0 of a dimension came from the last cell
-          if (bx[v] == 0) z0 = cjmul(C2<T>{ph.re[0], ph.im[0]}, z0);
-          if (sy == 0) {
-            z0 = cjmul(C2<T>{ph.re[1], ph.im[1]}, z0);
-            z1 = cjmul(C2<T>{ph.re[1], ph.im[1]}, z1);
-          }
-          if (sz == 0) {
-            z0 = cjmul(C2<T>{ph.re[2], ph.im[2]}, z0);
-            z1 = cjmul(C2<T>{ph.re[2], ph.im[2]}, z1);
-          }
-          const T add = (j & 1) ? (z0.i + (x2[v] ? z1.i : T(0))) : (z0.r + (x2[v] ? z1.r : T(0)));
-          sum[v][nb] += need[v] ? add : T(0);
-        }
+        const T v0 = Yc[row * ldc + j];
+        const T v1 = Yc[row2 * ldc + j];
+        const T add = v0 + (x2[v] ? v1 : T(0));
+        sum[v][nb] += need[v] ? add : T(0);
       }
     }
   }
+
+  // ---- acc = m^-1/2 sum - c x on the MFMA result layout, then acc += Ht_t Z^O
+  V4 acc[NB];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    T xv[NB], pv[NB];
     const int rl = w * 16 + M::row(lane, v);
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) xv[nb] = xs[rl * XS + nb * 16 + li];
-    if (beta != T(0)) {  // prev may be null when beta is zero
+    for (int nb = 0; nb < NB; ++nb) acc[nb][v] = msc[v] * sum[v][nb] - c * xs[rl * XS + nb * 16 + li];
+  }
+  // the previous iterate is read here, before any element of out is written
+  T pv[4][NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) pv[nb] = prev[(int64_t)gc[v] * ldo + colc[nb]];
-    } else {
+  for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) pv[nb] = 0;
+    for (int nb = 0; nb < NB; ++nb) pv[v][nb] = beta != T(0) ? prev[(int64_t)gc[v] * ldo + colc[nb]] : T(0);
+
+  // Z^O rows of the tile's functions, in chunks of TR rows staged over the x tile
+  const int rA = w * 16 + li;
+  for (int fc0 = 0; fc0 < FP; fc0 += TR) {
+    const int FC = min(TR, FP - fc0);  // a multiple of 4, as FP is
+    __syncthreads();                   // the x tile (or the previous chunk) is no longer read
+    {
+      T zv[XPT];
+#pragma unroll
+      for (int i = 0; i < XPT; ++i) {
+        const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
+        const int fn = r < FC ? fs[fc0 + r] : -1;
+        zv[i] = zo[(int64_t)max(fn, 0) * ncr + min(cb0 + cl, ncr - 1)];
+      }
+#pragma unroll
+      for (int i = 0; i < XPT; ++i) {
+        const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
+        const int fn = r < FC ? fs[fc0 + r] : -1;
+        xs[r * XS + cl] = fn >= 0 ? zv[i] : T(0);
+      }
     }
+    __syncthreads();
+#pragma unroll 2
+    for (int k0 = 0; k0 < FC; k0 += 4) {
+      const int f = k0 + lk;
+      const T a = hs[rA * HS + fc0 + f];
+      T b[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b[nb] = xs[f * XS + nb * 16 + li];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a, b[nb], acc[nb]);
+    }
+  }
+
+  // ---- out = alpha acc - beta prev
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      T r = alpha * (msc[v] * sum[v][nb] + acc[nb][v] - c * xv[nb]);
-      if (beta != T(0)) r -= beta * pv[nb];
+      T r = alpha * acc[nb][v];
+      if (beta != T(0)) r -= beta * pv[v][nb];
       if (ok[v] && colok[nb]) out[(int64_t)gc[v] * ldo + colc[nb]] = r;
     }
   }
@@ -1390,26 +1687,50 @@ void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, 
   }
 }
 
-template <typename T, int NB, bool CPLX>
-void launch_node_nb(const oefe_op_s* op, const KBatch<T>& kb, int ncb, hipStream_t s) {
-  const size_t lds = node_lds_bytes<T, NB, CPLX>(op->n_enr > 0 ? op->tile_fpmax : 0);
-  if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_node_mfma_kernel<T, NB, CPLX>), lds) != hipSuccess) return;
-  hipLaunchKernelGGL((fe_node_mfma_kernel<T, NB, CPLX>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb,
+template <typename T, int NBW, bool CPLX>
+void launch_coupling_w(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, hipStream_t s) {
+  const int ngrp = (int)cdiv(cdiv(max_ncr, 16), NBW);
+  const int64_t items = op->n_tiles * (int64_t)ngrp;
+  hipLaunchKernelGGL((fe_coupling_kernel<T, NBW, CPLX>), dim3((unsigned)cdiv(items, 4), 1, (unsigned)kb.nk), dim3(256),
+                     0, s, kb, op->d.tile_fptr, op->d.tile_fns, (int)op->n_tiles, ngrp, (int)op->N);
+}
+
+// nbw: 16-column blocks per coupling wave (1, 2 or 4)
+template <typename T, bool CPLX>
+void launch_coupling(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int nbw, hipStream_t s) {
+  switch (nbw) {
+    case 4: launch_coupling_w<T, 4, CPLX>(op, kb, max_ncr, s); break;
+    case 2: launch_coupling_w<T, 2, CPLX>(op, kb, max_ncr, s); break;
+    default: launch_coupling_w<T, 1, CPLX>(op, kb, max_ncr, s); break;
+  }
+}
+
+template <typename T, bool CPLX>
+void launch_assemble(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, bool base_in_out, hipStream_t s) {
+  const int64_t nel = CPLX ? max_ncr / 2 : max_ncr;
+  const int64_t blocks = std::min<int64_t>(cdiv(op->N * nel, 256), int64_t(1) << 22);
+  hipLaunchKernelGGL((fe_assemble_kernel<T, CPLX>), dim3((unsigned)blocks, 1, (unsigned)kb.nk),
+                     dim3(256), 0, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op), (int)op->N,
+                     base_in_out ? 1 : 0);
+}
+
+template <typename T, int NB>
+void launch_node_fused_nb(const oefe_op_s* op, const KBatch<T>& kb, int ncb, hipStream_t s) {
+  const size_t lds = node_lds_bytes<T, NB>(op->n_enr > 0 ? op->tile_fpmax : 0);
+  if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_node_fused_kernel<T, NB>), lds) != hipSuccess) return;
+  hipLaunchKernelGGL((fe_node_fused_kernel<T, NB>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb,
                      (unsigned)kb.nk), dim3(256), lds, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op),
                      op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N);
 }
 
-template <typename T, bool CPLX>
-void launch_node(const oefe_op_s* op, const KBatch<T>& kb, int NB, int ncb, hipStream_t s) {
+template <typename T>
+void launch_node_fused(const oefe_op_s* op, const KBatch<T>& kb, int NB, int ncb, hipStream_t s) {
   switch (NB) {
-    case 1: launch_node_nb<T, 1, CPLX>(op, kb, ncb, s); break;
-    case 2: launch_node_nb<T, 2, CPLX>(op, kb, ncb, s); break;
-    case 3: launch_node_nb<T, 3, CPLX>(op, kb, ncb, s); break;
-    case 4: launch_node_nb<T, 4, CPLX>(op, kb, ncb, s); break;
-    case 5: launch_node_nb<T, 5, CPLX>(op, kb, ncb, s); break;
-    case 6: launch_node_nb<T, 6, CPLX>(op, kb, ncb, s); break;
-    case 7: launch_node_nb<T, 7, CPLX>(op, kb, ncb, s); break;
-    default: launch_node_nb<T, 8, CPLX>(op, kb, ncb, s); break;
+    case 1: launch_node_fused_nb<T, 1>(op, kb, ncb, s); break;
+    case 2: launch_node_fused_nb<T, 2>(op, kb, ncb, s); break;
+    case 3: launch_node_fused_nb<T, 3>(op, kb, ncb, s); break;
+    case 4: launch_node_fused_nb<T, 4>(op, kb, ncb, s); break;
+    default: launch_node_fused_nb<T, 5>(op, kb, ncb, s); break;
   }
 }
 
@@ -1438,46 +1759,33 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
   const unsigned nk = (unsigned)kb.nk;
   const int nO = op->n_enr;
   const bool ovl = ov != nullptr && nO > 0;
-  if (nO > 0 && (!ovl || ov->first))
-    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk),
-                       dim3(256), 0, s, kb, 0, op->N, nO);
-  // optional HIP events around one stage (oefe_kernel_timer)
-  auto timed = [&](int kind, auto&& launch) {
+  // optional HIP events around one stage (oefe_kernel_timer), on the stream it runs on
+  auto timed = [&](int kind, hipStream_t st, auto&& launch) {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     const bool on = op->timer_kind == kind && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
-    if (on) (void)hipEventRecord(ev0, s);
+    if (on) (void)hipEventRecord(ev0, st);
     launch();
     if (on) {
-      (void)hipEventRecord(ev1, s);
+      (void)hipEventRecord(ev1, st);
       op->timer_events.emplace_back(ev0, ev1);
     }
   };
-  timed(OEFE_TIMER_CELL, [&] {
-    if constexpr (std::is_same<T, float>::value && !CPLX) {
-      if (bf16) {
-        launch_cell_bf16(op, kb, s);
-        return;
+  auto cell_stage = [&] {
+    timed(OEFE_TIMER_CELL, s, [&] {
+      if constexpr (std::is_same<T, float>::value && !CPLX) {
+        if (bf16) {
+          launch_cell_bf16(op, kb, s);
+          return;
+        }
       }
-    }
-    launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw, s);
-  });
-  // node workgroup width: 16-column blocks, all real columns up to the cap, else near-equal
-  const int nbcap = std::max(1, std::min(kNodeNBMax, op->tune_cb > 0 ? op->tune_cb / 16 : kNodeNBMax));
-  const int nb_all = (int)cdiv(max_ncr, 16);
-  const int ncb = (int)cdiv(nb_all, nbcap);
-  const int NB = (int)cdiv(nb_all, ncb);
-  // the node stage needs this step's Z^O, computed by the previous step's side chain
-  if (ovl && !ov->first) (void)hipStreamWaitEvent(s, ov->ev_zo, 0);
-  timed(OEFE_TIMER_NODE, [&] { launch_node<T, CPLX>(op, kb, NB, ncb, s); });
-  if (nO > 0) {
-    hipStream_t se = s;
-    if (ovl) {
-      (void)hipEventRecord(ov->ev_node, s);
-      (void)hipStreamWaitEvent(ov->side, ov->ev_node, 0);
-      se = ov->side;
-    }
+      launch_cell<T, CPLX>(op, kb, max_ncr, op->tune_cw, s);
+    });
+  };
+  const dim3 gg((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk);
+  // the chain that folds the tile partials into W' and writes the enrichment rows of out
+  // (and, in an overlapped recurrence, Z^O of the next step), on stream se
+  auto side_chain = [&](hipStream_t se) {
     const int nch = reduce_chunks(op);
-    const dim3 gg((unsigned)cdiv(max_nv, 16), (unsigned)cdiv(nO, 16), nk);
     hipLaunchKernelGGL((enr_reduce1_kernel<T>), dim3((unsigned)(nO * nch), (unsigned)cdiv(max_ncr, 64), nk),
                        dim3(256), 0, se, kb, nch, op->d.fn_pptr, op->d.fn_poff);
     hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 1, op->N, nO);
@@ -1485,6 +1793,53 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
     if (ovl) {
       if (!ov->last) hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 3, op->N, nO);
       (void)hipEventRecord(ov->ev_zo, se);
+    }
+  };
+  if constexpr (!CPLX) {
+    // Real operators: fused node kernel after the cell stage; the chain of step k runs on
+    // the side stream beside the cell stage of step k+1, whose node stage waits for it.
+    if (nO > 0 && (!ovl || ov->first)) hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, s, kb, 0, op->N, nO);
+    cell_stage();
+    // node workgroup width: 16-column blocks, all real columns up to the cap, else near-equal
+    const int nbcap = std::max(1, std::min(kNodeNBMax, op->tune_cb > 0 ? op->tune_cb / 16 : kNodeNBMax));
+    const int nb_all = (int)cdiv(max_ncr, 16);
+    const int ncb = (int)cdiv(nb_all, nbcap);
+    const int NB = (int)cdiv(nb_all, ncb);
+    if (ovl && !ov->first) (void)hipStreamWaitEvent(s, ov->ev_zo, 0);  // this step's Z^O
+    timed(OEFE_TIMER_NODE, s, [&] { launch_node_fused<T>(op, kb, NB, ncb, s); });
+    if (nO > 0) {
+      hipStream_t se = s;
+      if (ovl) {
+        (void)hipEventRecord(ov->ev_node, s);
+        (void)hipStreamWaitEvent(ov->side, ov->ev_node, 0);
+        se = ov->side;
+      }
+      side_chain(se);
+      if (ovl && ov->last) (void)hipStreamWaitEvent(s, ov->ev_zo, 0);
+    }
+  } else {
+    // Bloch operators: the coupling kernel (and then the chain) on the side stream, after
+    // the previous step's node assembly and beside this step's cell stage; the assembly
+    // adds onto the coupling kernel's result in out.
+    if (nO > 0) {
+      hipStream_t se = s;
+      if (ovl) {
+        if (ov->first) (void)hipEventRecord(ov->ev_node, s);
+        (void)hipStreamWaitEvent(ov->side, ov->ev_node, 0);
+        se = ov->side;
+      }
+      if (!ovl || ov->first) hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 0, op->N, nO);
+      const int cb = op->tune_cb;
+      const int nbw = cb >= 64 ? 4 : (cb >= 32 ? 2 : 1);
+      timed(OEFE_TIMER_COUPLING, se, [&] { launch_coupling<T, CPLX>(op, kb, max_ncr, nbw, se); });
+      if (ovl) (void)hipEventRecord(ov->ev_k1, se);
+      side_chain(se);
+    }
+    cell_stage();
+    if (ovl) (void)hipStreamWaitEvent(s, ov->ev_k1, 0);
+    timed(OEFE_TIMER_NODE, s, [&] { launch_assemble<T, CPLX>(op, kb, max_ncr, nO > 0, s); });
+    if (ovl) {
+      (void)hipEventRecord(ov->ev_node, s);
       if (ov->last) (void)hipStreamWaitEvent(s, ov->ev_zo, 0);
     }
   }

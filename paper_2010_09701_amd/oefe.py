@@ -200,10 +200,10 @@ class Operator:
             self._work["buf"] = w
         return w
 
-    TIMER_KINDS = {"off": 0, "cell": 1, "node": 2}
+    TIMER_KINDS = {"off": 0, "cell": 1, "node": 2, "coupling": 3}
 
     def kernel_timer(self, which="cell"):
-        """Bracket the launches of one stage ("cell", "node"; "off"/None/False stops) with HIP events."""
+        """Bracket the launches of one stage ("cell", "node", "coupling"; "off"/None/False stops) with HIP events."""
         if which is True:
             which = "cell"
         if which in (None, False):
