@@ -453,44 +453,85 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, in
   jacobi_body<CPLX>(A, n, lam, U, V, rot, status, red);
 }
 
-// Same method with the matrix, the rotations and the accumulated vectors in LDS
-// (small n).  One round of the round-robin ordering rotates n/2 disjoint pairs at
-// once, so A <- G^* A G factors into independent 2x2 blocks: block (k1, k2) of
-// rows (p1, q1) and columns (p2, q2) becomes G_k1^* B G_k2.  A round is therefore
-// two barrier-separated phases: (a) the rotations, (b) the block updates of A and
-// the column updates of V.  Same rotations, same order of operations per entry
-// as the global-memory version (columns, then rows).
+// Same method for small n, in two kernels.
+// jacobi_rot_kernel (one workgroup): the matrix in LDS, upper triangle only (the lower
+// one is its conjugate transpose and is never read).  One round of the round-robin
+// ordering rotates n/2 disjoint pairs at once, so A <- G^* A G factors into independent
+// 2x2 blocks: block (k1, k2) of rows (p1, q1) and columns (p2, q2) becomes
+// G_k1^* B G_k2, and block (k2, k1) is its conjugate transpose, so only the blocks
+// k1 <= k2 are computed.  A round is two barrier-separated phases: (a) the rotations,
+// which are also written to a record, (b) the block updates.  The eigenvalues are the
+// diagonal, ranked ascending.
+// jacobi_vec_kernel (n/4 workgroups, one wave per row of V): applies the recorded
+// rotations of every round in order to its row of V = I, then writes the row to U with
+// the columns in rank order.  Rows of V evolve independently, so the accumulation of
+// the eigenvectors leaves the single-workgroup kernel.
+constexpr int kJacobiRecSweeps = 40;  // sweeps the rotation record holds
+
+__device__ __forceinline__ void jacobi_pair(int st, int k, int m, int& p, int& q) {
+  if (k == 0) {
+    p = 0;
+    q = 1 + st % m;
+  } else {
+    p = 1 + (st + k) % m;
+    q = 1 + (st - k + m) % m;
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+}
+
+size_t jacobi_rot_lds_bytes(bool cplx, int n) {
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2;
+  const size_t nblk = (size_t)npair * (npair + 1) / 2;
+  return ((size_t)n * n * (cplx ? 2 : 1) + 4 * (size_t)npair + 32) * sizeof(double) + npair * sizeof(int) +
+         nblk * sizeof(uint16_t);
+}
+
 template <bool CPLX>
-__global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restrict__ A, int n,
-                                                         double* __restrict__ lam, double* __restrict__ U,
-                                                         int32_t* __restrict__ status) {
+__global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restrict__ A, int n,
+                                                          double* __restrict__ lam, int32_t* __restrict__ rank_out,
+                                                          double* __restrict__ rec, int32_t* __restrict__ status) {
   constexpr int E = CPLX ? 2 : 1;
   extern __shared__ double sm[];
   const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
   const int npair = NN / 2, m = NN - 1;
-  double* As = sm;                       // n*n*E
-  double* Vs = As + (size_t)n * n * E;   // n*n*E
-  double* rot = Vs + (size_t)n * n * E;  // 6 * npair: c, s, er, ei, p, q
-  double* red = rot + 6 * npair;         // 2 per wave (<= 32)
-  __shared__ int nrot;                   // rotations applied in the current sweep
+  const int nblk = npair * (npair + 1) / 2;
+  double* As = sm;                       // n*n*E, upper triangle used
+  double* rc = As + (size_t)n * n * E;   // per pair: c
+  double* rs = rc + npair;               // s (0: no rotation)
+  double* rer = rs + npair;              // er + i ei = e^{i phi} of a_pq (real: er = sign)
+  double* rei = rer + npair;
+  double* red = rei + npair;             // 2 per wave (<= 32)
+  int* rpq = reinterpret_cast<int*>(red + 32);                 // p | q << 16
+  uint16_t* blk = reinterpret_cast<uint16_t*>(rpq + npair);    // k1 | k2 << 8, k1 <= k2
+  __shared__ int anyrot;  // a rotation was applied in the current sweep
   const int tid = threadIdx.x, nth = blockDim.x;
-  auto a_ = [&](int i, int j) -> double* { return As + ((int64_t)i * n + j) * E; };
   for (int t = tid; t < n * n * E; t += nth) As[t] = A[t];
-  for (int t = tid; t < n * n; t += nth) {
-    Vs[(int64_t)t * E] = (t / n == t % n) ? 1.0 : 0.0;
-    if (CPLX) Vs[(int64_t)t * E + 1] = 0.0;
+  for (int b = tid; b < nblk; b += nth) {
+    int k1 = 0, bb = b;
+    while (bb >= npair - k1) {
+      bb -= npair - k1;
+      ++k1;
+    }
+    blk[b] = (uint16_t)(k1 | ((k1 + bb) << 8));
   }
   __syncthreads();
-  int sweep = 0;
-  for (; sweep < 60; ++sweep) {
+  auto up = [&](int i, int j) -> double* { return As + ((int64_t)i * n + j) * E; };  // i <= j
+  int sweep = 0, nrec = 0;
+  bool conv = false;
+  for (; sweep < kJacobiRecSweeps; ++sweep) {
     // convergence test: squared Frobenius norms of the off-diagonal and diagonal parts
     double off = 0, dia = 0;
     for (int t = tid; t < n * n; t += nth) {
       const int i = t / n, j = t - i * n;
+      if (i > j) continue;
       const double* a = As + (int64_t)t * E;
       const double v = a[0] * a[0] + (CPLX ? a[1] * a[1] : 0.0);
       if (i == j) dia += v;
-      else off += v;
+      else off += 2.0 * v;
     }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_xor(off, o);
@@ -507,31 +548,28 @@ __global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restri
       dias += red[2 * w + 1];
     }
     const double nrm_n = sqrt(offs + dias) / n;  // Frobenius norm / n
-    if (tid == 0) nrot = 0;
+    if (tid == 0) anyrot = 0;
     __syncthreads();
-    if (offs <= 1e-30 * dias || offs == 0.0) break;
+    if (offs <= 1e-30 * dias || offs == 0.0) {
+      conv = true;
+      break;
+    }
+    double* rrec = rec + (size_t)nrec * m * npair * 4;
     for (int st = 0; st < m; ++st) {
-      // (a) rotation per pair (er + i ei = e^{i phi} of a_pq; real: er = sign)
+      // (a) rotation per pair
       for (int k = tid; k < npair; k += nth) {
         int p, q;
-        if (k == 0) {
-          p = 0;
-          q = 1 + st % m;
-        } else {
-          p = 1 + (st + k) % m;
-          q = 1 + (st - k + m) % m;
-        }
-        if (p > q) { int t = p; p = q; q = t; }
+        jacobi_pair(st, k, m, p, q);
         double c = 1, sn = 0, er = 1, ei = 0;
         if (q < n) {
-          const double* apq = a_(p, q);
+          const double* apq = up(p, q);
           const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
           const double r = sqrt(br * br + bi * bi);
-          const double al = a_(p, p)[0], ga = a_(q, q)[0];
+          const double al = up(p, p)[0], ga = up(q, q)[0];
           // rotate only when the pair is coupled above float64 rounding, measured on its
           // diagonal entries or on the matrix norm (whichever is larger)
           if (r > 1e-300 && r > 2.220446049250313e-16 * fmax(sqrt(fabs(al * ga)), nrm_n)) {
-            atomicAdd(&nrot, 1);
+            anyrot = 1;
             er = br / r;
             ei = bi / r;
             const double tau = (ga - al) / (2.0 * r);
@@ -540,47 +578,61 @@ __global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restri
             sn = t * c;
           }
         }
-        double* R = rot + 6 * k;
-        R[0] = c; R[1] = sn; R[2] = er; R[3] = ei; R[4] = p; R[5] = q;
+        rc[k] = c;
+        rs[k] = sn;
+        rer[k] = er;
+        rei[k] = ei;
+        rpq[k] = p | (q << 16);
+        double* R = rrec + ((size_t)st * npair + k) * 4;
+        R[0] = c; R[1] = sn; R[2] = er; R[3] = ei;
       }
       __syncthreads();
-      // (b) 2x2 blocks of A: columns by G_k2, then rows by G_k1^*
-      for (int t = tid; t < npair * npair; t += nth) {
-        const int k1 = t / npair, k2 = t - k1 * npair;
-        const double* R1 = rot + 6 * k1;
-        const double* R2 = rot + 6 * k2;
-        const bool on1 = R1[1] != 0.0, on2 = R2[1] != 0.0;
+      // (b) 2x2 blocks k1 <= k2 of the upper triangle: columns by G_k2, then rows by G_k1^*
+      for (int b = tid; b < nblk; b += nth) {
+        const int kk = blk[b], k1 = kk & 255, k2 = kk >> 8;
+        const bool on1 = rs[k1] != 0.0, on2 = rs[k2] != 0.0;
         if (!on1 && !on2) continue;
-        const int p1 = (int)R1[4], q1 = (int)R1[5], p2 = (int)R2[4], q2 = (int)R2[5];
+        const int pq1 = rpq[k1], pq2 = rpq[k2];
+        const int p1 = pq1 & 0xffff, q1 = pq1 >> 16, p2 = pq2 & 0xffff, q2 = pq2 >> 16;
         const bool r2 = q1 < n, c2 = q2 < n;  // second row / column exists
         if constexpr (!CPLX) {
-          double b00 = *a_(p1, p2), b01 = c2 ? *a_(p1, q2) : 0.0;
-          double b10 = r2 ? *a_(q1, p2) : 0.0, b11 = (r2 && c2) ? *a_(q1, q2) : 0.0;
+          auto ld = [&](int i, int j) { return i <= j ? *up(i, j) : *up(j, i); };
+          auto st1 = [&](int i, int j, double v) { *(i <= j ? up(i, j) : up(j, i)) = v; };
+          double b00 = ld(p1, p2), b01 = c2 ? ld(p1, q2) : 0.0;
+          double b10 = r2 ? ld(q1, p2) : 0.0, b11 = (r2 && c2) ? ld(q1, q2) : 0.0;
           if (on2) {
-            const double c = R2[0], sn = R2[1], sg = R2[2];
+            const double c = rc[k2], sn = rs[k2], sg = rer[k2];
             double x = b00, y = b01 * sg;
             b00 = x * c - y * sn; b01 = x * sn + y * c;
             x = b10; y = b11 * sg;
             b10 = x * c - y * sn; b11 = x * sn + y * c;
           }
           if (on1) {
-            const double c = R1[0], sn = R1[1], sg = R1[2];
+            const double c = rc[k1], sn = rs[k1], sg = rer[k1];
             double x = b00, y = sg * b10;
             b00 = c * x - sn * y; b10 = sn * x + c * y;
             x = b01; y = sg * b11;
             b01 = c * x - sn * y; b11 = sn * x + c * y;
           }
           if (k1 == k2) b01 = b10 = 0.0;  // the rotated pair
-          *a_(p1, p2) = b00;
-          if (c2) *a_(p1, q2) = b01;
-          if (r2) *a_(q1, p2) = b10;
-          if (r2 && c2) *a_(q1, q2) = b11;
+          st1(p1, p2, b00);
+          if (c2) st1(p1, q2, b01);
+          if (r2 && k1 != k2) st1(q1, p2, b10);
+          if (r2 && c2) st1(q1, q2, b11);
         } else {
-          auto ld = [&](bool ok, int i, int j) { return ok ? Z{a_(i, j)[0], a_(i, j)[1]} : Z{0.0, 0.0}; };
-          Z b00 = ld(true, p1, p2), b01 = ld(c2, p1, q2), b10 = ld(r2, q1, p2), b11 = ld(r2 && c2, q1, q2);
+          auto ld = [&](int i, int j) {
+            return i <= j ? Z{up(i, j)[0], up(i, j)[1]} : Z{up(j, i)[0], -up(j, i)[1]};
+          };
+          auto st2 = [&](int i, int j, Z v) {
+            if (i <= j) { up(i, j)[0] = v.r; up(i, j)[1] = v.i; }
+            else { up(j, i)[0] = v.r; up(j, i)[1] = -v.i; }
+          };
+          const Z z0{0.0, 0.0};
+          Z b00 = ld(p1, p2), b01 = c2 ? ld(p1, q2) : z0, b10 = r2 ? ld(q1, p2) : z0;
+          Z b11 = (r2 && c2) ? ld(q1, q2) : z0;
           if (on2) {
-            const double c = R2[0], sn = R2[1];
-            const Z emi{R2[2], -R2[3]};
+            const double c = rc[k2], sn = rs[k2];
+            const Z emi{rer[k2], -rei[k2]};
             Z x = b00, ye = zmul(b01, emi);
             b00 = {x.r * c - ye.r * sn, x.i * c - ye.i * sn};
             b01 = {x.r * sn + ye.r * c, x.i * sn + ye.i * c};
@@ -589,8 +641,8 @@ __global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restri
             b11 = {x.r * sn + ye.r * c, x.i * sn + ye.i * c};
           }
           if (on1) {
-            const double c = R1[0], sn = R1[1];
-            const Z eph{R1[2], R1[3]};
+            const double c = rc[k1], sn = rs[k1];
+            const Z eph{rer[k1], rei[k1]};
             Z x = b00, ye = zmul(eph, b10);
             b00 = {c * x.r - sn * ye.r, c * x.i - sn * ye.i};
             b10 = {sn * x.r + c * ye.r, sn * x.i + c * ye.i};
@@ -599,58 +651,116 @@ __global__ __launch_bounds__(1024) void jacobi_lds_kernel(const double* __restri
             b11 = {sn * x.r + c * ye.r, sn * x.i + c * ye.i};
           }
           if (k1 == k2) {  // the rotated pair; the diagonal stays real
-            b01 = b10 = Z{0.0, 0.0};
+            b01 = b10 = z0;
             b00.i = 0.0;
             b11.i = 0.0;
           }
-          auto st2 = [&](bool ok, int i, int j, Z v) {
-            if (ok) { a_(i, j)[0] = v.r; a_(i, j)[1] = v.i; }
-          };
-          st2(true, p1, p2, b00); st2(c2, p1, q2, b01); st2(r2, q1, p2, b10); st2(r2 && c2, q1, q2, b11);
-        }
-      }
-      // (b') V <- V G
-      for (int t = tid; t < n * npair; t += nth) {
-        const int r = t / npair, k = t - r * npair;
-        const double* R = rot + 6 * k;
-        const int p = (int)R[4], q = (int)R[5];
-        if (q >= n || R[1] == 0.0) continue;
-        const double c = R[0], sn = R[1];
-        double* vp = Vs + ((int64_t)r * n + p) * E;
-        double* vq = Vs + ((int64_t)r * n + q) * E;
-        if constexpr (!CPLX) {
-          const double x = vp[0], y = vq[0] * R[2];
-          vp[0] = x * c - y * sn;
-          vq[0] = x * sn + y * c;
-        } else {
-          const Z emi{R[2], -R[3]};
-          const Z x{vp[0], vp[1]}, y{vq[0], vq[1]};
-          const Z ye = zmul(y, emi);
-          vp[0] = x.r * c - ye.r * sn; vp[1] = x.i * c - ye.i * sn;
-          vq[0] = x.r * sn + ye.r * c; vq[1] = x.i * sn + ye.i * c;
+          st2(p1, p2, b00);
+          if (c2) st2(p1, q2, b01);
+          if (r2 && k1 != k2) st2(q1, p2, b10);
+          if (r2 && c2) st2(q1, q2, b11);
         }
       }
       __syncthreads();
     }
-    // a sweep that found no pair coupled above rounding: converged
-    if (nrot == 0) {
+    // a sweep that found no pair coupled above rounding: converged (its record is the identity)
+    if (anyrot == 0) {
       ++sweep;
+      conv = true;
       break;
     }
+    ++nrec;
   }
-  if (tid == 0) { status[0] = sweep < 60 ? 0 : OEFE_ENOCONV; status[1] = sweep; }
+  if (tid == 0) {
+    status[0] = conv ? 0 : OEFE_ENOCONV;
+    status[1] = sweep;
+    rank_out[n] = nrec;
+  }
   // ascending order by rank
   for (int i = tid; i < n; i += nth) {
-    const double li = a_(i, i)[0];
+    const double li = up(i, i)[0];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double lj = a_(j, j)[0];
+      const double lj = up(j, j)[0];
       if (lj < li || (lj == li && j < i)) ++rank;
     }
     lam[rank] = li;
-    for (int r = 0; r < n; ++r) {
-      U[((int64_t)r * n + rank) * E] = Vs[((int64_t)r * n + i) * E];
-      if (CPLX) U[((int64_t)r * n + rank) * E + 1] = Vs[((int64_t)r * n + i) * E + 1];
+    rank_out[i] = rank;
+  }
+}
+
+constexpr int kJacobiVecChunk = 8192;  // doubles of the rotation record staged in LDS at a time
+
+size_t jacobi_vec_lds_bytes(bool cplx, int n) {
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, m = NN - 1;
+  return ((size_t)kJacobiVecChunk + 4 * (size_t)n * (cplx ? 2 : 1)) * sizeof(double) +
+         (size_t)m * npair * sizeof(int);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void jacobi_vec_kernel(const double* __restrict__ rec,
+                                                         const int32_t* __restrict__ rank, int n,
+                                                         double* __restrict__ U) {
+  constexpr int E = CPLX ? 2 : 1;
+  extern __shared__ double sm[];
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, m = NN - 1;
+  double* chunk = sm;                                      // kJacobiVecChunk
+  double* vall = chunk + kJacobiVecChunk;                  // [4][n][E]
+  int* sched = reinterpret_cast<int*>(vall + 4 * n * E);   // [m][npair]: p | q << 16
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r = blockIdx.x * 4 + w;  // row of V (waves past n idle along)
+  double* v = vall + (size_t)w * n * E;
+  const int nround = rank[n] * m;
+  const int cr = max(1, kJacobiVecChunk / (4 * npair));  // rounds per chunk
+  for (int t = tid; t < m * npair; t += 256) {
+    int p, q;
+    jacobi_pair(t / npair, t - (t / npair) * npair, m, p, q);
+    sched[t] = p | (q << 16);
+  }
+  for (int i = lane; i < n; i += 64) {
+    v[(size_t)i * E] = i == r ? 1.0 : 0.0;
+    if (CPLX) v[(size_t)i * E + 1] = 0.0;
+  }
+  for (int s0 = 0; s0 < nround; s0 += cr) {
+    const int ns = min(cr, nround - s0);
+    __syncthreads();  // the previous chunk is no longer read
+    const double* src = rec + (size_t)s0 * npair * 4;
+    for (int t = tid; t < ns * npair * 4; t += 256) chunk[t] = src[t];
+    __syncthreads();
+    if (r < n) {
+      for (int j = 0; j < ns; ++j) {
+        const int* sp = sched + (size_t)((s0 + j) % m) * npair;
+        for (int k = lane; k < npair; k += 64) {
+          const double* R = chunk + ((size_t)j * npair + k) * 4;
+          const double c = R[0], sn = R[1];
+          const int pq = sp[k], p = pq & 0xffff, q = pq >> 16;
+          if (q >= n || sn == 0.0) continue;
+          double* vp = v + (size_t)p * E;
+          double* vq = v + (size_t)q * E;
+          if constexpr (!CPLX) {
+            const double x = vp[0], y = vq[0] * R[2];
+            vp[0] = x * c - y * sn;
+            vq[0] = x * sn + y * c;
+          } else {
+            const Z emi{R[2], -R[3]};
+            const Z x{vp[0], vp[1]}, y{vq[0], vq[1]};
+            const Z ye = zmul(y, emi);
+            vp[0] = x.r * c - ye.r * sn; vp[1] = x.i * c - ye.i * sn;
+            vq[0] = x.r * sn + ye.r * c; vq[1] = x.i * sn + ye.i * c;
+          }
+        }
+        // the next round reads entries this round's other lanes wrote
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+    }
+  }
+  if (r < n) {
+    for (int i = lane; i < n; i += 64) {
+      const int c = rank[i];
+      U[((int64_t)r * n + c) * E] = v[(size_t)i * E];
+      if (CPLX) U[((int64_t)r * n + c) * E + 1] = v[(size_t)i * E + 1];
     }
   }
 }
@@ -963,20 +1073,37 @@ int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int3
   return check();
 }
 
+// LDS version: the rotation record (kJacobiRecSweeps sweeps of m rounds x n/2 pairs x 4
+// doubles) and the ranks (+ the recorded sweep count); global version: V and the rotations.
+static bool jacobi_in_lds(bool cplx, int n) { return jacobi_rot_lds_bytes(cplx, n) <= 150 * 1024; }
+
 size_t jacobi_scratch_bytes(bool cplx, int n) {
-  const int NN = n + 1;
-  return ((size_t)n * n * (cplx ? 2 : 1) + 6 * (size_t)(NN / 2 + 1)) * sizeof(double);
+  const int NN = (n % 2) ? n + 1 : n;
+  const size_t glob = ((size_t)n * n * (cplx ? 2 : 1) + 6 * (size_t)(NN / 2 + 1)) * sizeof(double);
+  if (!jacobi_in_lds(cplx, n)) return glob;
+  const size_t recb = (size_t)kJacobiRecSweeps * (NN - 1) * (NN / 2) * 4 * sizeof(double) +
+                      ((size_t)n + 1) * sizeof(int32_t) + 256;
+  return std::max(glob, recb);
 }
 
 int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s) {
-  const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + 6 * (n / 2 + 1) + 32) * sizeof(double);
-  if (lds <= 150 * 1024) {
-    const void* fn = cplx ? (const void*)jacobi_lds_kernel<true> : (const void*)jacobi_lds_kernel<false>;
-    if (allow_dynamic_lds(fn, lds) != hipSuccess) return OEFE_EDEVICE;
-    if (cplx)
-      hipLaunchKernelGGL(jacobi_lds_kernel<true>, dim3(1), dim3(1024), lds, s, A, n, lam, U, status);
-    else
-      hipLaunchKernelGGL(jacobi_lds_kernel<false>, dim3(1), dim3(1024), lds, s, A, n, lam, U, status);
+  if (jacobi_in_lds(cplx, n)) {
+    const int NN = (n % 2) ? n + 1 : n;
+    double* rec = scratch;
+    int32_t* rank = reinterpret_cast<int32_t*>(rec + (size_t)kJacobiRecSweeps * (NN - 1) * (NN / 2) * 4);
+    const size_t lds = jacobi_rot_lds_bytes(cplx, n);
+    const size_t lds2 = jacobi_vec_lds_bytes(cplx, n);
+    const void* fn = cplx ? (const void*)jacobi_rot_kernel<true> : (const void*)jacobi_rot_kernel<false>;
+    const void* fn2 = cplx ? (const void*)jacobi_vec_kernel<true> : (const void*)jacobi_vec_kernel<false>;
+    if (allow_dynamic_lds(fn, lds) != hipSuccess || allow_dynamic_lds(fn2, lds2) != hipSuccess) return OEFE_EDEVICE;
+    const dim3 g2((unsigned)cdiv(n, 4));
+    if (cplx) {
+      hipLaunchKernelGGL(jacobi_rot_kernel<true>, dim3(1), dim3(1024), lds, s, A, n, lam, rank, rec, status);
+      hipLaunchKernelGGL(jacobi_vec_kernel<true>, g2, dim3(256), lds2, s, rec, rank, n, U);
+    } else {
+      hipLaunchKernelGGL(jacobi_rot_kernel<false>, dim3(1), dim3(1024), lds, s, A, n, lam, rank, rec, status);
+      hipLaunchKernelGGL(jacobi_vec_kernel<false>, g2, dim3(256), lds2, s, rec, rank, n, U);
+    }
     return check();
   }
   double* V = scratch;

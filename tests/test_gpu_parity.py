@@ -168,7 +168,7 @@ def _multiplet_angles(th, Xa, Xb, tol=1e-6):
     worst = 0.0
     for g in groups[:-1]:  # the last group may straddle the block edge
         A, B = Xa[:, g], Xb[:, g]
-        s = np.linalg.norm(B - A @ (A.T @ B), 2)
+        s = np.linalg.norm(B - A @ (np.conj(A.T) @ B), 2)
         worst = max(worst, s)
     return worst
 
@@ -181,6 +181,28 @@ def test_rayleigh_ritz_matches_oracle(lib):
     lam, U = np.linalg.eigh(H)
     rng = np.random.default_rng(7)
     Q, _ = och.cholgs(U[:, :10] + 1e-3 * rng.standard_normal((op.n_tot, 10)))
+    th, Xr = och.rayleigh_ritz(op.apply, Q)
+    Qd = _dev(Q)
+    thg = lib.rayleigh_ritz(gop, Qd).cpu().numpy()
+    assert np.abs(thg - th).max() < 1e-10 * max(1, np.abs(th).max())
+    assert _multiplet_angles(th, Xr, Qd.cpu().numpy()) < 1e-8
+
+
+@pytest.mark.parametrize("name,kvec,nv", [("single_atom", None, 11), ("p3", None, 40),
+                                          ("single_atom", (0.3, -0.2, 0.1), 21), ("p3", (-0.4, 0.25, 0.1), 33)])
+def test_rayleigh_ritz_odd_sizes_and_bloch(lib, name, kvec, nv):
+    """Odd block widths (a padded round-robin schedule) and Hermitian (Bloch) projected
+    matrices: Ritz values and multiplet subspaces against the oracle's eigh."""
+    base = SYSTEMS[name]()
+    sysm = base if kvec is None else base.with_k(np.array(kvec))
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    lam, U = np.linalg.eigh(op.dense())
+    rng = np.random.default_rng(11)
+    noise = rng.standard_normal((op.n_tot, nv))
+    if kvec is not None:
+        noise = noise + 1j * rng.standard_normal((op.n_tot, nv))
+    Q, _ = och.cholgs(U[:, :nv] + 1e-3 * noise)
     th, Xr = och.rayleigh_ritz(op.apply, Q)
     Qd = _dev(Q)
     thg = lib.rayleigh_ritz(gop, Qd).cpu().numpy()
