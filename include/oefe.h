@@ -94,7 +94,8 @@ typedef struct oefe_op_s* oefe_op;
 /* Build the operator on the current HIP device: quadrature rules, lumped GLL
  * mass (eqnMcc), potential, orthogonalized enrichment (eqnorthC, eqnorthCGLL),
  * blocks M^oo (eqnMoo), H^co, H^oo, S = (M^oo)^-1/2; uploads device data.
- * Errors: EINVAL (bad description), EUNSUPPORTED (p), ENOMEM, EDEVICE. */
+ * Errors: EINVAL (bad description, or more than 144 enrichment functions coupling
+ * to one tile of 64 consecutive FE rows), EUNSUPPORTED (p), ENOMEM, EDEVICE. */
 int oefe_op_create(const oefe_system_desc* desc, oefe_op* out);
 
 /* Test operator Ht = diag(lambda) (n real entries, host memory), no mesh. */
@@ -165,9 +166,9 @@ size_t oefe_batched_work_size(int32_t nk, const oefe_op* ops, oefe_prec prec, co
  * unit of the node stage: the workgroup of the fused node kernel of a real
  * operator (at most 80 columns are used: built-in, all columns up to 80, else
  * near-equal blocks), or one
- * wave of the coupling kernel (the H^co products) of a Bloch operator, where 16,
- * 32 and 64 are used (larger values act as 64; built-in 16).  Results do not
- * depend on the shape. */
+ * wave of the coupling kernel (the H^co products) of a Bloch operator, where 16
+ * and 32 are used (larger values act as 32; built-in 16).  Results do not depend
+ * on the shape. */
 int oefe_set_launch_shape(oefe_op op, int32_t cw, int32_t cb);
 
 /* Autotuner of the launch shape for a batch of operators (nk >= 1, same rules

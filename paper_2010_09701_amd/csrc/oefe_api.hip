@@ -355,6 +355,13 @@ int upload_operator(oefe_op_s* op, std::string& err) {
       }
       op->tile_slots = tfptr[op->n_tiles];
       op->tile_fpmax = fpmax;
+      // the node-stage kernels hold one tile's dense block in LDS
+      if (fpmax > kTileFunctionsMax) {
+        err = "enrichment too dense for the node stage: a tile of " + std::to_string(kTileRows) +
+              " FE rows couples to " + std::to_string(fpmax) + " functions (at most " +
+              std::to_string(kTileFunctionsMax) + ")";
+        return OEFE_EINVAL;
+      }
       // per function: its (tile, slot) partial positions, in tile order
       std::vector<int32_t> fpp(op->n_enr + 1, 0);
       for (int32_t f : tfns)

@@ -15,6 +15,9 @@ namespace oefe {
 
 constexpr int kMaxP1 = 5;  // supported GLL nodes per edge: 3, 4, 5 (degree 2..4)
 constexpr int kTileRows = 64;  // FE rows per enrichment tile
+// enrichment functions one tile may couple to: the node-stage kernels stage a tile's dense
+// block (complex: two planes of kTileRows x (F + 1) float64) in 150 KB of LDS
+constexpr int kTileFunctionsMax = 144;
 
 using cplx = std::complex<double>;
 

@@ -747,15 +747,25 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-constexpr int kCoupleNBWMax = 4;  // 16-column blocks per coupling wave
+constexpr int kCoupleNBWMax = 2;  // 16-column blocks per coupling wave
+
+// LDS of the coupling kernel: the tile's block, one plane per real / imaginary part, rows
+// of FP + 1 (odd) elements so that 16 lanes reading 16 consecutive functions of a row, or
+// one function of 16 consecutive rows, touch 16 distinct bank pairs; then the function list.
+__host__ __device__ constexpr int coupling_row_stride(int fp) { return fp + 1; }
+
+template <typename T, bool CPLX>
+constexpr size_t coupling_lds_bytes(int fpmax) {
+  return (size_t)(CPLX ? 2 : 1) * kTileRows * coupling_row_stride(fpmax) * sizeof(T) + (size_t)fpmax * sizeof(int32_t);
+}
 
 // part columns of NQ blocks of 16 functions (from function m0) over the tile's TR rows:
-// pc[q][nb] += Ht_t[r][m0 + 16 q + .]^* x[r][cols of block nb], k-steps of 4 rows issued
-// in batches of 4 (loads first, then the MFMAs)
+// pc[q][nb] += Ht_t[r][m0 + 16 q + .]^* x[r][cols of block nb], k-steps of 4 rows with the
+// x loads of 4 k-steps issued ahead of their MFMAs; Ht_t from LDS (planes hs[e])
 template <typename T, int NQ, int NBW, bool CPLX>
-__device__ __forceinline__ void coupling_part(const T* __restrict__ tv, const T* __restrict__ x, int64_t ldx,
-                                              int g0, int N, int FP, int m0, const int (&colc)[NBW], int li,
-                                              int lk, typename Mfma<T>::V4 (&pc)[4][NBW]) {
+__device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __restrict__ x, int64_t ldx, int g0,
+                                              int N, int FP, int m0, const int (&colc)[NBW], int li, int lk,
+                                              typename Mfma<T>::V4 (&pc)[4][NBW]) {
   using M = Mfma<T>;
   constexpr int TR = kTileRows, E = CPLX ? 2 : 1, KB = 4;
   const T sgn = (li & 1) ? T(-1) : T(1);
@@ -768,7 +778,7 @@ __device__ __forceinline__ void coupling_part(const T* __restrict__ tv, const T*
     fcl[q] = fok[q] ? f : FP - 1;
   }
   for (int ks0 = 0; ks0 < TR / 4; ks0 += KB) {
-    T b[KB][E][NBW], a[KB][NQ][E];
+    T b[KB][E][NBW];
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       const int r = (ks0 + j) * 4 + lk;
@@ -779,16 +789,10 @@ __device__ __forceinline__ void coupling_part(const T* __restrict__ tv, const T*
         const T xv = x[g * ldx + colc[nb]];
         b[j][0][nb] = rok ? xv : T(0);
       }
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const T av = tv[((int64_t)r * FP + fcl[q]) * E + e];
-          a[j][q][e] = fok[q] ? av : T(0);
-        }
     }
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
+      const int r = (ks0 + j) * 4 + lk;
       if constexpr (CPLX) {
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb) b[j][1][nb] = sgn * __shfl_xor(b[j][0][nb], 1);
@@ -796,109 +800,126 @@ __device__ __forceinline__ void coupling_part(const T* __restrict__ tv, const T*
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
 #pragma unroll
-        for (int e = 0; e < E; ++e)
+        for (int e = 0; e < E; ++e) {
+          const T av = hs[(e * TR + r) * HS + fcl[q]];
+          const T a = fok[q] ? av : T(0);
 #pragma unroll
-          for (int nb = 0; nb < NBW; ++nb) pc[q][nb] = M::op(a[j][q][e], b[j][e][nb], pc[q][nb]);
+          for (int nb = 0; nb < NBW; ++nb) pc[q][nb] = M::op(a, b[j][e][nb], pc[q][nb]);
+        }
     }
   }
 }
 
 template <typename T, int NBW, bool CPLX>
 __global__ __launch_bounds__(256) void fe_coupling_kernel(KBatch<T> kb, const int32_t* __restrict__ tile_fptr,
-                                                          const int32_t* __restrict__ tile_fns, int n_tiles,
-                                                          int ngrp, int N) {
+                                                          const int32_t* __restrict__ tile_fns, int N) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
-  constexpr int TR = kTileRows, E = CPLX ? 2 : 1, RB = TR / 16;
+  constexpr int TR = kTileRows, E = CPLX ? 2 : 1, RB = TR / 16, HPT = 8;
+  extern __shared__ unsigned char smem_raw[];
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= n_tiles * ngrp) return;
-  const int t = item / ngrp, grp = item - t * ngrp;
-  const int cb0 = grp * 16 * NBW;
-  if (cb0 >= ncr) return;  // column group beyond this operator's width
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int t = blockIdx.x;
   const int g0 = t * TR;
   const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;  // FP: a multiple of 4
+  const int HS = coupling_row_stride(FP);
+  T* hs = reinterpret_cast<T*>(smem_raw);                   // [E][TR][HS]
+  int32_t* fs = reinterpret_cast<int32_t*>(hs + E * TR * HS);  // [FP]
   const T* __restrict__ tv = P.tv + (int64_t)f0 * TR * E;   // [TR][FP][E], zero rows past N
   const T* __restrict__ x = P.x;
   const T* __restrict__ zo = P.zo;  // [n_enr][ncr]
   const int64_t ldx = P.ldx, ldo = P.ldo;
-  // Loads are unconditional, from clamped in-bounds addresses, with unwanted values
-  // replaced by selects, so that each batch is issued at once.
-  int colc[NBW];
-  bool colok[NBW];
-#pragma unroll
-  for (int nb = 0; nb < NBW; ++nb) {
-    const int col = cb0 + nb * 16 + li;
-    colok[nb] = col < ncr;
-    colc[nb] = colok[nb] ? col : ncr - 1;
-  }
+  const int ngrp = (ncr + 16 * NBW - 1) / (16 * NBW);
 
-  // ---- part = Ht_t^* X_t, up to 4 blocks of 16 functions at a time
-  // (complex: e = 1 pairs Im(H) with the partner column, signed)
-  for (int m0 = 0; m0 < FP; m0 += 64) {
-    V4 pc[4][NBW];
+  // ---- stage the tile's block (batches of HPT coalesced loads per thread) and its function list
+  const int nh = TR * FP * E;
+  for (int q0 = 0; q0 < nh; q0 += 256 * HPT) {
+    T hv[HPT];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int i = 0; i < HPT; ++i) hv[i] = tv[min(q0 + (int)threadIdx.x + 256 * i, nh - 1)];
 #pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) pc[q][nb] = V4{0, 0, 0, 0};
-    const int nq = min(4, (FP - m0 + 15) / 16);
-    switch (nq) {
-      case 4: coupling_part<T, 4, NBW, CPLX>(tv, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
-      case 3: coupling_part<T, 3, NBW, CPLX>(tv, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
-      case 2: coupling_part<T, 2, NBW, CPLX>(tv, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
-      default: coupling_part<T, 1, NBW, CPLX>(tv, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q >= nq) break;
-#pragma unroll
-      for (int nb = 0; nb < NBW; ++nb) {
-        if (!colok[nb]) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int fi = m0 + q * 16 + M::row(lane, v);
-          if (fi < FP) P.part[(int64_t)(f0 + fi) * ncr + colc[nb]] = pc[q][nb][v];
-        }
+    for (int i = 0; i < HPT; ++i) {
+      const int q = q0 + threadIdx.x + 256 * i;
+      if (q < nh) {
+        const int r = q / (FP * E), rem = q - r * FP * E, f = rem / E, e = rem - f * E;
+        hs[(e * TR + r) * HS + f] = hv[i];
       }
     }
   }
+  for (int f = threadIdx.x; f < FP; f += 256) fs[f] = tile_fns[f0 + f];
+  __syncthreads();
 
-  // ---- en = Ht_t Z^O for the RB 16-row blocks of the tile, k-steps of 4 functions in
-  // batches of KB (a k-step past the list multiplies zero columns of Z^O); the function
-  // list is held one entry per lane and broadcast
-  V4 acc[RB][NBW];
+  // ---- each wave: column groups w, w + 4, ...
+  for (int grp = w; grp < ngrp; grp += 4) {
+    const int cb0 = grp * 16 * NBW;
+    // Loads are unconditional, from clamped in-bounds addresses, with unwanted values
+    // replaced by selects, so that each batch is issued at once.
+    int colc[NBW];
+    bool colok[NBW];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+    for (int nb = 0; nb < NBW; ++nb) {
+      const int col = cb0 + nb * 16 + li;
+      colok[nb] = col < ncr;
+      colc[nb] = colok[nb] ? col : ncr - 1;
+    }
+
+    // part = Ht_t^* X_t, up to 4 blocks of 16 functions at a time
+    // (complex: e = 1 pairs Im(H) with the partner column, signed)
+    for (int m0 = 0; m0 < FP; m0 += 64) {
+      V4 pc[4][NBW];
 #pragma unroll
-    for (int nb = 0; nb < NBW; ++nb) acc[rb][nb] = V4{0, 0, 0, 0};
-  {
-    constexpr int KB = 2;
-    const T sgn = (li & 1) ? T(1) : T(-1);
-    for (int c0 = 0; c0 < FP; c0 += 64) {
-      const int fnl = c0 + lane < FP ? tile_fns[f0 + c0 + lane] : -1;
-      const int kc = min(64, FP - c0);
-      for (int k0 = 0; k0 < kc; k0 += 4 * KB) {
-        T b[KB][E][NBW], a[KB][RB][E];
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) pc[q][nb] = V4{0, 0, 0, 0};
+      const int nq = min(4, (FP - m0 + 15) / 16);
+      switch (nq) {
+        case 4: coupling_part<T, 4, NBW, CPLX>(hs, HS, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+        case 3: coupling_part<T, 3, NBW, CPLX>(hs, HS, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+        case 2: coupling_part<T, 2, NBW, CPLX>(hs, HS, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+        default: coupling_part<T, 1, NBW, CPLX>(hs, HS, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q >= nq) break;
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) {
+          if (!colok[nb]) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int fi = m0 + q * 16 + M::row(lane, v);
+            if (fi < FP) P.part[(int64_t)(f0 + fi) * ncr + colc[nb]] = pc[q][nb][v];
+          }
+        }
+      }
+    }
+
+    // en = Ht_t Z^O for the RB 16-row blocks of the tile, k-steps of 4 functions with the
+    // Z^O loads of KB k-steps issued ahead (a k-step past the list multiplies zero columns)
+    V4 acc[RB][NBW];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int nb = 0; nb < NBW; ++nb) acc[rb][nb] = V4{0, 0, 0, 0};
+    {
+      constexpr int KB = 4;
+      const T sgn = (li & 1) ? T(1) : T(-1);
+      for (int k0 = 0; k0 < FP; k0 += 4 * KB) {
+        T b[KB][E][NBW];
 #pragma unroll
         for (int j = 0; j < KB; ++j) {
-          const int kl = min(k0 + 4 * j + lk, 63);
-          const int fn = __shfl(fnl, kl);  // -1 past the list
-          const int f = min(c0 + kl, FP - 1);
+          const int f = k0 + 4 * j + lk;
+          const int fn = f < FP ? fs[f] : -1;
           const T* __restrict__ zr = zo + (int64_t)max(fn, 0) * ncr;
 #pragma unroll
           for (int nb = 0; nb < NBW; ++nb) {
             const T zv = zr[colc[nb]];
             b[j][0][nb] = fn >= 0 ? zv : T(0);
           }
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int e = 0; e < E; ++e) a[j][rb][e] = tv[((int64_t)(rb * 16 + li) * FP + f) * E + e];
         }
 #pragma unroll
         for (int j = 0; j < KB; ++j) {
+          const int f = min(k0 + 4 * j + lk, FP - 1);
           if constexpr (CPLX) {
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) b[j][1][nb] = sgn * __shfl_xor(b[j][0][nb], 1);
@@ -906,45 +927,47 @@ __global__ __launch_bounds__(256) void fe_coupling_kernel(KBatch<T> kb, const in
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int e = 0; e < E; ++e)
+            for (int e = 0; e < E; ++e) {
+              const T a = hs[(e * TR + rb * 16 + li) * HS + f];
 #pragma unroll
-              for (int nb = 0; nb < NBW; ++nb) acc[rb][nb] = M::op(a[j][rb][e], b[j][e][nb], acc[rb][nb]);
+              for (int nb = 0; nb < NBW; ++nb) acc[rb][nb] = M::op(a, b[j][e][nb], acc[rb][nb]);
+            }
         }
       }
     }
-  }
 
-  // ---- out = alpha en - beta prev (prev may be the same array as out: all of this
-  // lane's elements are read before any is written)
-  const T alpha = P.alpha, beta = P.beta;
-  T pv[RB][4][NBW];
-  if (beta != T(0)) {
+    // out = alpha en - beta prev (prev may be the same array as out: all of this lane's
+    // elements are read before any is written)
+    const T alpha = P.alpha, beta = P.beta;
+    T pv[RB][4][NBW];
+    if (beta != T(0)) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t g = min(g0 + rb * 16 + M::row(lane, v), N - 1);
+#pragma unroll
+          for (int nb = 0; nb < NBW; ++nb) pv[rb][v][nb] = beta * P.prev[g * ldo + colc[nb]];
+        }
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int nb = 0; nb < NBW; ++nb) pv[rb][v][nb] = T(0);
+    }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t g = min(g0 + rb * 16 + M::row(lane, v), N - 1);
+        const int gv = g0 + rb * 16 + M::row(lane, v);
+        if (gv >= N) continue;
 #pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) pv[rb][v][nb] = beta * P.prev[g * ldo + colc[nb]];
+        for (int nb = 0; nb < NBW; ++nb)
+          if (colok[nb]) P.out[(int64_t)gv * ldo + colc[nb]] = alpha * acc[rb][nb][v] - pv[rb][v][nb];
       }
-  } else {
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) pv[rb][v][nb] = T(0);
   }
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gv = g0 + rb * 16 + M::row(lane, v);
-      if (gv >= N) continue;
-#pragma unroll
-      for (int nb = 0; nb < NBW; ++nb)
-        if (colok[nb]) P.out[(int64_t)gv * ldo + colc[nb]] = alpha * acc[rb][nb][v] - pv[rb][v][nb];
-    }
 }
 
 // Flat element index -> (row, column) for rows of nel elements, without a 64-bit
@@ -1688,20 +1711,19 @@ void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, 
 }
 
 template <typename T, int NBW, bool CPLX>
-void launch_coupling_w(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, hipStream_t s) {
-  const int ngrp = (int)cdiv(cdiv(max_ncr, 16), NBW);
-  const int64_t items = op->n_tiles * (int64_t)ngrp;
-  hipLaunchKernelGGL((fe_coupling_kernel<T, NBW, CPLX>), dim3((unsigned)cdiv(items, 4), 1, (unsigned)kb.nk), dim3(256),
-                     0, s, kb, op->d.tile_fptr, op->d.tile_fns, (int)op->n_tiles, ngrp, (int)op->N);
+void launch_coupling_w(const oefe_op_s* op, const KBatch<T>& kb, hipStream_t s) {
+  const size_t lds = coupling_lds_bytes<T, CPLX>(op->tile_fpmax);
+  if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_coupling_kernel<T, NBW, CPLX>), lds) != hipSuccess) return;
+  hipLaunchKernelGGL((fe_coupling_kernel<T, NBW, CPLX>), dim3((unsigned)op->n_tiles, 1, (unsigned)kb.nk), dim3(256),
+                     lds, s, kb, op->d.tile_fptr, op->d.tile_fns, (int)op->N);
 }
 
-// nbw: 16-column blocks per coupling wave (1, 2 or 4)
+// nbw: 16-column blocks per coupling wave (1 or 2)
 template <typename T, bool CPLX>
-void launch_coupling(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int nbw, hipStream_t s) {
+void launch_coupling(const oefe_op_s* op, const KBatch<T>& kb, int nbw, hipStream_t s) {
   switch (nbw) {
-    case 4: launch_coupling_w<T, 4, CPLX>(op, kb, max_ncr, s); break;
-    case 2: launch_coupling_w<T, 2, CPLX>(op, kb, max_ncr, s); break;
-    default: launch_coupling_w<T, 1, CPLX>(op, kb, max_ncr, s); break;
+    case 2: launch_coupling_w<T, 2, CPLX>(op, kb, s); break;
+    default: launch_coupling_w<T, 1, CPLX>(op, kb, s); break;
   }
 }
 
@@ -1830,8 +1852,8 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
       }
       if (!ovl || ov->first) hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 0, op->N, nO);
       const int cb = op->tune_cb;
-      const int nbw = cb >= 64 ? 4 : (cb >= 32 ? 2 : 1);
-      timed(OEFE_TIMER_COUPLING, se, [&] { launch_coupling<T, CPLX>(op, kb, max_ncr, nbw, se); });
+      const int nbw = cb >= 32 ? kCoupleNBWMax : 1;
+      timed(OEFE_TIMER_COUPLING, se, [&] { launch_coupling<T, CPLX>(op, kb, nbw, se); });
       if (ovl) (void)hipEventRecord(ov->ev_k1, se);
       side_chain(se);
     }
