@@ -318,13 +318,19 @@ constexpr int lanes_cw() { return (64 / P1) & ~1; }
 
 template <typename T, int P1, bool CPLX>
 __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const T* __restrict__ WV, CellCoef<T> cf,
-                                                            int nc, int p, int n, int64_t n_cells) {
+                                                            int nc, int p, int n, int64_t n_cells, int nch) {
   constexpr int NP = P1 * P1;
   constexpr int CWc = lanes_cw<P1>();
+  // launch order: the column chunks of a group of 4 cells are consecutive in L, and each
+  // XCD (workgroups bk = x mod 8) takes a contiguous range of L, so that the chunks reading
+  // the same node rows, and neighbouring cells, share one L2
+  const int nbk = gridDim.x, bk = blockIdx.x, nb8 = nbk & ~7;
+  const int L = bk < nb8 ? (bk & 7) * (nb8 >> 3) + (bk >> 3) : bk;
+  const int chunk = L % nch, cgrp = L / nch;
   __shared__ T lds_all[4][NP * P1 * CWc];
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
-  if ((int)blockIdx.y * CWc >= ncr) return;  // column block beyond this operator's width
+  if (chunk * CWc >= ncr) return;  // column block beyond this operator's width
   const T* __restrict__ X = P.x;
   const int64_t ldx = P.ldx;
   T* __restrict__ Yc = P.ycell;
@@ -336,8 +342,8 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
   const int w = min(lane / CWc, P1 - 1);  // plane of this lane
   const int g = active ? lane % CWc : lane - P1 * CWc;  // spare lanes repeat a last-plane lane
   T* lds = lds_all[wid];
-  const int64_t e = (int64_t)blockIdx.x * 4 + wid;
-  const int j = blockIdx.y * CWc + g;
+  const int64_t e = (int64_t)cgrp * 4 + wid;
+  const int j = chunk * CWc + g;
   const bool valid = (e < n_cells) && (j < ncr);
   const int64_t ee = valid ? e : 0;
   const int cx = (int)(ee % nc), cy = (int)((ee / nc) % nc), cz = (int)(ee / ((int64_t)nc * nc));
@@ -603,7 +609,11 @@ __global__ __launch_bounds__(768) void fe_cell_bf16_kernel(KBatch<float> kb, con
   float* __restrict__ Yc = P.ycell;
   const int64_t ldc = P.ldc;
   const int S = nc * P1;
-  for (int64_t task = (int64_t)blockIdx.x * nw + w; task < ntask; task += (int64_t)gridDim.x * nw) {
+  // workgroups of one XCD (blockIdx.x = x mod 8) take a contiguous range of task groups,
+  // so that the column blocks of a cell and neighbouring cells share one L2
+  const int nbk = gridDim.x, bk = blockIdx.x, nb8 = nbk & ~7;
+  const int wg = bk < nb8 ? (bk & 7) * (nb8 >> 3) + (bk >> 3) : bk;
+  for (int64_t task = (int64_t)wg * nw + w; task < ntask; task += (int64_t)gridDim.x * nw) {
     const int64_t e = task / ncb;
     const int col = (int)(task - e * ncb) * 16 + c;
     const bool cok = col < ncr;
@@ -1687,9 +1697,10 @@ void launch_cell_p(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw
 template <typename T, int P1, bool CPLX>
 void launch_cell_lanes(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, hipStream_t s) {
   constexpr int CWc = lanes_cw<P1>();
-  dim3 grid((unsigned)cdiv(op->n_cells, 4), (unsigned)cdiv(max_ncr, CWc), (unsigned)kb.nk);
+  const int nch = (int)cdiv(max_ncr, CWc);
+  dim3 grid((unsigned)(cdiv(op->n_cells, 4) * nch), 1, (unsigned)kb.nk);
   hipLaunchKernelGGL((fe_cell_lanes_kernel<T, P1, CPLX>), grid, dim3(256), 0, s, kb, devptrs<T>(op).WV, coef<T>(op),
-                     op->nc, op->p, op->n, op->n_cells);
+                     op->nc, op->p, op->n, op->n_cells, nch);
 }
 
 // cw = 0: planes-in-lanes kernel; 8, 16, 32, 64: plane-per-wave kernel with cw columns per cell
