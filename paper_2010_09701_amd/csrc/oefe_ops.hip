@@ -796,8 +796,8 @@ __device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __re
       const int64_t g = rok ? g0 + r : N - 1;
 #pragma unroll
       for (int nb = 0; nb < NBW; ++nb) {
-        const T xv = x[g * ldx + colc[nb]];
-        b[j][0][nb] = rok ? xv : T(0);
+        // multiply by 1 or 0 rather than select: keeps the load unconditional and batched
+        b[j][0][nb] = x[g * ldx + colc[nb]] * (rok ? T(1) : T(0));
       }
     }
 #pragma unroll
@@ -922,10 +922,7 @@ __global__ __launch_bounds__(256) void fe_coupling_kernel(KBatch<T> kb, const in
           const int fn = f < FP ? fs[f] : -1;
           const T* __restrict__ zr = zo + (int64_t)max(fn, 0) * ncr;
 #pragma unroll
-          for (int nb = 0; nb < NBW; ++nb) {
-            const T zv = zr[colc[nb]];
-            b[j][0][nb] = fn >= 0 ? zv : T(0);
-          }
+          for (int nb = 0; nb < NBW; ++nb) b[j][0][nb] = zr[colc[nb]] * (fn >= 0 ? T(1) : T(0));
         }
 #pragma unroll
         for (int j = 0; j < KB; ++j) {
@@ -1389,14 +1386,30 @@ __global__ __launch_bounds__(256) void enr_reduce1_kernel(KBatch<T> kb, int nch,
   const int j = blockIdx.y * 64 + lane;
   const int e1 = fn_pptr[nu + 1];
   const int es = fn_pptr[nu] + ch * kReduceChunk, ee = min(e1, es + kReduceChunk);
-  T s0 = 0, s1 = 0;
-  if (j < ncr) {
-    int e = es + grp;
-    for (; e + 4 < ee; e += 8) {
-      s0 += part[(int64_t)fn_poff[e] * ncr + j];
-      s1 += part[(int64_t)fn_poff[e + 4] * ncr + j];
+  // this wave's entries es + grp + 4 i, all loads issued at once; summed as two
+  // interleaved chains (even i, odd i) in list order
+  constexpr int EPG = kReduceChunk / 4;
+  const int eg = __builtin_amdgcn_readfirstlane(es + grp);
+  T v[EPG];
+  if (ee > es) {
+    const int jc = min(j, ncr - 1);
+#pragma unroll
+    for (int i = 0; i < EPG; ++i) {
+      const int e = eg + 4 * i;
+      const T pv = part[(int64_t)fn_poff[min(e, ee - 1)] * ncr + jc];  // clamped in-bounds entry
+      // a multiply by 1 or 0 (not a select, which the compiler would turn into a branch
+      // around the load) keeps all loads of the batch in flight together
+      v[i] = pv * ((e < ee && j < ncr) ? T(1) : T(0));
     }
-    if (e < ee) s0 += part[(int64_t)fn_poff[e] * ncr + j];
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPG; ++i) v[i] = T(0);
+  }
+  T s0 = 0, s1 = 0;
+#pragma unroll
+  for (int i = 0; i < EPG; i += 2) {
+    s0 += v[i];
+    s1 += v[i + 1];
   }
   red[grp][lane] = s0 + s1;
   __syncthreads();
