@@ -328,6 +328,7 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
   const int L = bk < nb8 ? (bk & 7) * (nb8 >> 3) + (bk >> 3) : bk;
   const int chunk = L % nch, cgrp = L / nch;
   __shared__ T lds_all[4][NP * P1 * CWc];
+  __shared__ T wv_all[4][128];  // W V of the wave's cell at its quadrature points
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
   if (chunk * CWc >= ncr) return;  // column block beyond this operator's width
@@ -347,8 +348,15 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
   const bool valid = (e < n_cells) && (j < ncr);
   const int64_t ee = valid ? e : 0;
   const int cx = (int)(ee % nc), cy = (int)((ee / nc) % nc), cz = (int)(ee / ((int64_t)nc * nc));
+  // W V of the wave's cell (e is wave-uniform, ee is not: lanes past the block use cell 0):
+  // loaded now, parked in LDS after the first passes, read in step 5
+  constexpr int NQ3 = NP * P1;
+  const T* __restrict__ wvg = WV + (e < n_cells ? e : n_cells - 1) * NQ3;
+  const T wv0 = wvg[min(lane, NQ3 - 1)], wv1 = wvg[min(lane + 64, NQ3 - 1)];
 
   // 1. gather plane az = w with the m^-1/2 pre-scale (and Bloch phase)
+  const int jc = min(j, ncr - 1);
+  const T vmask = valid ? T(1) : T(0);
   T v[NP];
   {
     const int az = w;
@@ -367,20 +375,20 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
         if (wx) ix -= n;
         const int64_t g = ix + (int64_t)n * (iy + (int64_t)n * iz);
         const T sc = cf.mscale * cf.om[ax] * cf.om[ay] * cf.om[az];
-        T val = 0;
-        if (valid) {
-          if constexpr (!CPLX) {
-            val = X[g * ldx + j];
-          } else {
-            const T* px = X + g * ldx + (j & ~1);
-            C2<T> z{px[0], px[1]};
-            if (wx) z = cmul(z, C2<T>{ph.re[0], ph.im[0]});
-            if (wy) z = cmul(z, C2<T>{ph.re[1], ph.im[1]});
-            if (wz) z = cmul(z, C2<T>{ph.re[2], ph.im[2]});
-            val = (j & 1) ? z.i : z.r;
-          }
+        // unconditional in-bounds loads (column clamped), zeroed by a multiply for lanes
+        // outside the block: no branch around the load
+        T val;
+        if constexpr (!CPLX) {
+          val = X[g * ldx + jc];
+        } else {
+          const T* px = X + g * ldx + (jc & ~1);
+          C2<T> z{px[0], px[1]};
+          if (wx) z = cmul(z, C2<T>{ph.re[0], ph.im[0]});
+          if (wy) z = cmul(z, C2<T>{ph.re[1], ph.im[1]});
+          if (wz) z = cmul(z, C2<T>{ph.re[2], ph.im[2]});
+          val = (jc & 1) ? z.i : z.r;
         }
-        v[ay * P1 + ax] = sc * val;
+        v[ay * P1 + ax] = sc * (val * vmask);
       }
     }
   }
@@ -405,6 +413,9 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
       v[qy * P1 + qx] = s;
     }
   // 3. transpose z-planes -> x-planes: lds[(az*P1 + qy)*P1 + qx]
+  T* wvs = wv_all[wid];
+  if (lane < NQ3) wvs[lane] = wv0;
+  if (lane + 64 < NQ3) wvs[lane + 64] = wv1;
 #pragma unroll
   for (int qy = 0; qy < P1; ++qy)
 #pragma unroll
@@ -429,7 +440,6 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
   // 5. quadrature-point terms: potential + y/z kinetic
   const int qx = w;
   const T kx = cf.kappa * cf.w[qx];
-  const T* wv = WV + ee * (NP * P1);
 #pragma unroll
   for (int qz = 0; qz < P1; ++qz)
 #pragma unroll
@@ -440,7 +450,7 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
         ly += cf.L1[qy][k] * u[qz * P1 + k];
         lz += cf.L1[qz][k] * u[k * P1 + qy];
       }
-      t[qz * P1 + qy] = wv[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
+      t[qz * P1 + qy] = wvs[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
     }
   // 6. t' = (B^T)_y (B^T)_z t  -> indexed [az][ay]
   T tp[NP];
