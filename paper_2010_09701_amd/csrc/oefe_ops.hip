@@ -1166,7 +1166,9 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   // and (real columns) the first slot pair of the gather, which lands during the
   // matrix-core phase below
   constexpr bool kEarly = sizeof(T) == 4;
-  constexpr int HPT = 8;
+  // the whole H tile in the first batch for up to 48 (float64) / 32 (float32: its registers
+  // also hold the first gather loads) functions
+  constexpr int HPT = sizeof(T) == 8 ? 12 : 8;
   const int nh = TR * FP;
   T gA[4][NB], gB[4][NB];
   {
