@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 / bf16 filter measurements")
     ap.add_argument("--no-kpoints", action="store_true", help="skip the batched k-point filter measurement")
+    ap.add_argument("--no-d64", action="store_true", help="skip the diamond64 filter measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DIR")
@@ -93,7 +94,7 @@ def node_kernel_bytes(gop, ncr: int, m: int) -> float:
     """
     slots = (gop.nc * (gop.p + 1)) ** 3
     nb_all = -(-ncr // 16)
-    ncb = -(-nb_all // 8)
+    ncb = -(-nb_all // 5)  # column blocks of at most 5 x 16 real columns per workgroup
     rows = slots + 2 * gop.n_fe + gop.n_fe * (m - 1) / m + gop.tile_slots
     return 8.0 * (rows * ncr + gop.tile_slots * gop.tile_rows * ncb)
 
@@ -183,6 +184,53 @@ def kpoint_bench(oefe, wl, torch, base, m, reps):
         log(f"k-points {name}: batched filter {ms:.3f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s, shape {tune}, "
             + ", ".join(f"{k} {v:.1f}" for k, v in stages.items()))
     res["unit"] = "DoF*vec*deg/s (complex vectors)"
+    return res
+
+
+def d64_bench(oefe, wl, torch):
+    """diamond64 (885,056 DoF x 320 vectors, degree 60): one float64 and one float32 filter,
+    and the per-launch node / cell kernel durations, at a shape whose working set (several
+    GB) is far above the 256 MB Infinity Cache."""
+    cfg = wl.config("diamond64")
+    t = time.time()
+    gop = oefe.Operator(cfg.system)
+    setup_s = time.time() - t
+    X0 = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
+    v0 = torch.from_numpy(wl.lanczos_start(gop.n_tot, cfg.v0_seed)).cuda()
+    a0L, b = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k)
+    a = 0.5 * (a0L + b)
+    work = gop.n_tot * cfg.nv * cfg.m
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    res = {"workload": "diamond64: 24^3 cells p=4, 884736 FE + 320 enrichment DoF, 320 vectors, degree 60",
+           "setup_s": setup_s}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        X = X0.to(dt)
+        oefe.chebyshev_filter(gop, X, 2, a, b, a0L)  # warm-up
+        X.copy_(X0)
+        torch.cuda.synchronize()
+        e0.record()
+        oefe.chebyshev_filter(gop, X, cfg.m, a, b, a0L)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        r = {"filter_ms": ms, "rate": work / (ms / 1e3)}
+        for which in ("node", "cell"):
+            X.copy_(X0)
+            gop.kernel_timer(which)
+            oefe.chebyshev_filter(gop, X, 10, a, b, a0L)
+            n_launch, tot_ms = gop.kernel_timer_read()
+            gop.kernel_timer("off")
+            r[which + "_avg_us"] = tot_ms / max(n_launch, 1) * 1e3
+        if name == "f64":
+            nbytes = node_kernel_bytes(gop, cfg.nv, 10)
+            r["node_gbs"] = nbytes / (r["node_avg_us"] / 1e6) / 1e9
+            r["node_frac_of_8TBs"] = r["node_gbs"] / PEAK_HBM_GBS
+        res[name] = r
+        log(f"diamond64 {name}: filter {ms:.1f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s; node {r['node_avg_us']:.0f} us, "
+            f"cell {r['cell_avg_us']:.0f} us" + (f", node {r['node_gbs']:.0f} GB/s" if name == "f64" else ""))
+        del X
+    res["unit"] = "DoF*vec*deg/s"
     return res
 
 
@@ -374,6 +422,8 @@ def main():
 
     if not args.no_kpoints and sysm.name == "diamond8":
         extra["kpoints"] = kpoint_bench(oefe, wl, torch, sysm, cfg.m, reps)
+    if not args.no_d64 and sysm.name == "diamond8":
+        extra["diamond64"] = d64_bench(oefe, wl, torch)
 
     out = {
         "metric": "ChFSI filter DoF*vec*deg/s (one float64 ChFSI pass: filter + CholGS + Rayleigh-Ritz)",
