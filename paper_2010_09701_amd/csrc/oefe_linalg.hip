@@ -86,6 +86,134 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks,
   if (CPLX) G[((int64_t)i * ldg + j) * E + 1] = si;
 }
 
+// ---- Gram on the matrix cores (16x16x4 float64 MFMA), real, for 16 <= na, nb <= 16 kGramNBMax:
+// partial[chunk][i][j] = sum over the chunk's rows g of A[g][i] B[g][j].  One
+// workgroup per row chunk (two per CU, so that one loads while the other computes) walks it
+// in slabs of kGramSlab rows, each loaded coalesced into LDS and consumed by the MFMAs.  The 16x16 output blocks are dealt round-robin to the 4
+// waves (block b = w + 4 t); fragment lanes: row 4 k + lane / 16, column 16 ib + lane % 16.
+typedef double dv4 __attribute__((ext_vector_type(4)));
+constexpr int kGramNBMax = 5;   // 16-column blocks per operand
+constexpr int kGramChunks = 512;
+constexpr int kGramSlab = 32;   // rows per LDS slab
+
+__host__ __device__ constexpr int gram_lds_stride(int cols) { return cols + 1; }
+
+template <int BPW>
+__global__ __launch_bounds__(256) void gram_mfma_kernel(const double* __restrict__ A, int64_t lda, int na,
+                                                        const double* __restrict__ B, int64_t ldb, int nb,
+                                                        int64_t n, int64_t rows_per_chunk, double* __restrict__ part) {
+  constexpr int SR = kGramSlab;
+  extern __shared__ double gsm[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int NBj = (nb + 15) / 16, nblk = ((na + 15) / 16) * NBj;
+  const int SA = gram_lds_stride(na), SB = gram_lds_stride(nb);
+  double* As[1] = {gsm};
+  double* Bs[1] = {gsm + SR * SA};
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk, g1 = min(n, g0 + rows_per_chunk);
+  const int nslab = (int)((g1 - g0 + SR - 1) / SR);
+  int ca[BPW], cb[BPW];
+  bool oka[BPW], okb[BPW];
+#pragma unroll
+  for (int t = 0; t < BPW; ++t) {
+    const int b = min(w + 4 * t, nblk - 1), ib = b / NBj, jb = b - ib * NBj;
+    const int i = ib * 16 + li, j = jb * 16 + li;
+    oka[t] = i < na && w + 4 * t < nblk;
+    okb[t] = j < nb;
+    ca[t] = i < na ? i : na - 1;
+    cb[t] = j < nb ? j : nb - 1;
+  }
+  // slab loads: wave w takes rows w, w + 4, ... of the slab, lane l columns l and l + 64;
+  // unconditional loads from clamped in-bounds addresses, zeroed by a multiply past the
+  // chunk or the last column
+  constexpr int RPW = SR / 4;
+  double ra[2 * RPW], rb[2 * RPW];
+  const int la0 = min(lane, na - 1), la1 = min(lane + 64, na - 1);
+  const int lb0 = min(lane, nb - 1), lb1 = min(lane + 64, nb - 1);
+  const double ma0 = lane < na ? 1.0 : 0.0, ma1 = lane + 64 < na ? 1.0 : 0.0;
+  const double mb0 = lane < nb ? 1.0 : 0.0, mb1 = lane + 64 < nb ? 1.0 : 0.0;
+  auto load = [&](int sl) {
+    const int64_t gb = g0 + (int64_t)sl * SR;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int64_t g = gb + w + 4 * i;
+      const double m = g < g1 ? 1.0 : 0.0;
+      const int64_t gc = g < g1 ? g : g1 - 1;
+      ra[2 * i] = A[gc * lda + la0] * (m * ma0);
+      ra[2 * i + 1] = A[gc * lda + la1] * (m * ma1);
+      rb[2 * i] = B[gc * ldb + lb0] * (m * mb0);
+      rb[2 * i + 1] = B[gc * ldb + lb1] * (m * mb1);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = w + 4 * i;
+      if (lane < na) As[buf][r * SA + lane] = ra[2 * i];
+      if (lane + 64 < na) As[buf][r * SA + lane + 64] = ra[2 * i + 1];
+      if (lane < nb) Bs[buf][r * SB + lane] = rb[2 * i];
+      if (lane + 64 < nb) Bs[buf][r * SB + lane + 64] = rb[2 * i + 1];
+    }
+  };
+  dv4 acc[BPW];
+#pragma unroll
+  for (int t = 0; t < BPW; ++t) acc[t] = dv4{0, 0, 0, 0};
+  for (int sl = 0; sl < nslab; ++sl) {
+    load(sl);
+    __syncthreads();  // the previous slab is no longer read
+    store(0);
+    __syncthreads();
+#pragma unroll 2
+    for (int k = 0; k < SR / 4; ++k) {
+      const int r = 4 * k + lk;
+#pragma unroll
+      for (int t = 0; t < BPW; ++t) {
+        const double a = As[0][r * SA + ca[t]] * (oka[t] ? 1.0 : 0.0);
+        const double bv = Bs[0][r * SB + cb[t]] * (okb[t] ? 1.0 : 0.0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  double* out = part + (int64_t)blockIdx.x * na * nb;
+#pragma unroll
+  for (int t = 0; t < BPW; ++t) {
+    const int b = w + 4 * t;
+    if (b >= nblk) break;
+    const int ib = b / NBj, jb = b - ib * NBj, j = jb * 16 + li;
+    if (j >= nb) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ib * 16 + lk + 4 * v;
+      if (i < na) out[(int64_t)i * nb + j] = acc[t][v];
+    }
+  }
+}
+
+// G[i][j] = sum over the chunks, one wave per entry: lane l adds chunks l, l + 64, ... in
+// order, then a fixed butterfly over the 64 lanes
+template <bool CPLX>
+__global__ __launch_bounds__(256) void gram_reduce_wave_kernel(const double* __restrict__ part, int nchunks, int na,
+                                                               int nb, double* __restrict__ G, int ldg) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= na * nb) return;
+  double s[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) s[e] = 0.0;
+  for (int c = lane; c < nchunks; c += 64)
+#pragma unroll
+    for (int e = 0; e < E; ++e) s[e] += part[((int64_t)c * na * nb + idx) * E + e];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int e = 0; e < E; ++e) s[e] += __shfl_xor(s[e], o);
+  if (lane == 0) {
+    const int i = idx / nb, j = idx - i * nb;
+#pragma unroll
+    for (int e = 0; e < E; ++e) G[((int64_t)i * ldg + j) * E + e] = s[e];
+  }
+}
+
 // ---- C = A * B : A [n x k], B [k x m] (small); 64x64 output tile, 4x4 per thread
 template <bool CPLX>
 __global__ __launch_bounds__(256) void gemm_nn_kernel(const double* __restrict__ A, int64_t lda,
@@ -520,6 +648,14 @@ __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restri
   }
   __syncthreads();
   auto up = [&](int i, int j) -> double* { return As + ((int64_t)i * n + j) * E; };  // i <= j
+  // this thread's blocks (the assignment does not change between rounds)
+  constexpr int kBlkPerThread = 3;  // npair <= 69 (n <= 137): nblk <= 2415 <= 3 * 1024
+  int myblk[kBlkPerThread];
+#pragma unroll
+  for (int i = 0; i < kBlkPerThread; ++i) {
+    const int bb = tid + i * nth;
+    myblk[i] = bb < nblk ? (int)blk[bb] : -1;
+  }
   int sweep = 0, nrec = 0;
   bool conv = false;
   for (; sweep < kJacobiRecSweeps; ++sweep) {
@@ -564,17 +700,21 @@ __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restri
         if (q < n) {
           const double* apq = up(p, q);
           const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
-          const double r = sqrt(br * br + bi * bi);
+          const double r = CPLX ? sqrt(br * br + bi * bi) : fabs(br);
           const double al = up(p, p)[0], ga = up(q, q)[0];
           // rotate only when the pair is coupled above float64 rounding, measured on its
           // diagonal entries or on the matrix norm (whichever is larger)
           if (r > 1e-300 && r > 2.220446049250313e-16 * fmax(sqrt(fabs(al * ga)), nrm_n)) {
             anyrot = 1;
-            er = br / r;
-            ei = bi / r;
+            if constexpr (CPLX) {
+              er = br / r;
+              ei = bi / r;
+            } else {
+              er = br >= 0 ? 1.0 : -1.0;
+            }
             const double tau = (ga - al) / (2.0 * r);
             const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
+            c = rsqrt(1.0 + t * t);
             sn = t * c;
           }
         }
@@ -588,8 +728,11 @@ __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restri
       }
       __syncthreads();
       // (b) 2x2 blocks k1 <= k2 of the upper triangle: columns by G_k2, then rows by G_k1^*
-      for (int b = tid; b < nblk; b += nth) {
-        const int kk = blk[b], k1 = kk & 255, k2 = kk >> 8;
+#pragma unroll
+      for (int i = 0; i < kBlkPerThread; ++i) {
+        const int kk = myblk[i];
+        if (kk < 0) break;
+        const int k1 = kk & 255, k2 = kk >> 8;
         const bool on1 = rs[k1] != 0.0, on2 = rs[k2] != 0.0;
         if (!on1 && !on2) continue;
         const int pq1 = rpq[k1], pq2 = rpq[k2];
@@ -727,7 +870,44 @@ __global__ __launch_bounds__(256) void jacobi_vec_kernel(const double* __restric
     const double* src = rec + (size_t)s0 * npair * 4;
     for (int t = tid; t < ns * npair * 4; t += 256) chunk[t] = src[t];
     __syncthreads();
-    if (r < n) {
+    if (r < n && npair <= 64) {
+      // one pair per lane: the next round's rotation and pair are read while this round's
+      // entries are updated
+      const int k = min(lane, npair - 1);
+      const bool act = lane < npair;
+      int rr = s0 % m;
+      double c = chunk[k * 4], sn = chunk[k * 4 + 1], e2 = chunk[k * 4 + 2], e3 = chunk[k * 4 + 3];
+      int pq = sched[rr * npair + k];
+      for (int j = 0; j < ns; ++j) {
+        const double cc = c, ss = sn, f2 = e2, f3 = e3;
+        const int pqc = pq;
+        if (j + 1 < ns) {
+          rr = rr + 1 == m ? 0 : rr + 1;
+          const double* R = chunk + ((size_t)(j + 1) * npair + k) * 4;
+          c = R[0]; sn = R[1]; e2 = R[2]; e3 = R[3];
+          pq = sched[rr * npair + k];
+        }
+        const int p = pqc & 0xffff, q = pqc >> 16;
+        if (act && q < n && ss != 0.0) {
+          double* vp = v + (size_t)p * E;
+          double* vq = v + (size_t)q * E;
+          if constexpr (!CPLX) {
+            const double x = vp[0], y = vq[0] * f2;
+            vp[0] = x * cc - y * ss;
+            vq[0] = x * ss + y * cc;
+          } else {
+            const Z emi{f2, -f3};
+            const Z x{vp[0], vp[1]}, y{vq[0], vq[1]};
+            const Z ye = zmul(y, emi);
+            vp[0] = x.r * cc - ye.r * ss; vp[1] = x.i * cc - ye.i * ss;
+            vq[0] = x.r * ss + ye.r * cc; vq[1] = x.i * ss + ye.i * cc;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+    } else if (r < n) {
       for (int j = 0; j < ns; ++j) {
         const int* sp = sched + (size_t)((s0 + j) % m) * npair;
         for (int k = lane; k < npair; k += 64) {
@@ -1021,14 +1201,42 @@ int gram_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(
 
 }  // namespace
 
+static bool gram_on_mfma(bool cplx, int na, int nb) {
+  return !cplx && na >= 16 && nb >= 16 && na <= 16 * kGramNBMax && nb <= 16 * kGramNBMax;
+}
+static int gram_mfma_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kGramChunks, cdiv(n, 256))); }
+
 size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n) {
-  return (size_t)gram_chunks(n) * na * nb * (cplx ? 2 : 1) * sizeof(double);
+  const int nch = gram_on_mfma(cplx, na, nb) ? gram_mfma_chunks(n) : gram_chunks(n);
+  return (size_t)nch * na * nb * (cplx ? 2 : 1) * sizeof(double);
+}
+
+static void launch_gram_mfma(const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, int64_t n,
+                             double* G, int ldg, double* scratch, hipStream_t s) {
+  const int nch = gram_mfma_chunks(n);
+  const int64_t rpc = cdiv(cdiv(n, nch), 4) * 4;
+  const int bpw = (int)cdiv(cdiv(na, 16) * cdiv(nb, 16), 4);
+  const size_t lds = (size_t)kGramSlab * (gram_lds_stride(na) + gram_lds_stride(nb)) * sizeof(double);
+  const dim3 grid((unsigned)nch);
+  auto go = [&](auto kern) {
+    if (allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds) != hipSuccess) return;
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, A, lda, na, B, ldb, nb, n, rpc, scratch);
+  };
+  if (bpw <= 2) go(gram_mfma_kernel<2>);
+  else if (bpw <= 4) go(gram_mfma_kernel<4>);
+  else go(gram_mfma_kernel<7>);
+  hipLaunchKernelGGL((gram_reduce_wave_kernel<false>), dim3((unsigned)cdiv((int64_t)na * nb, 4)), dim3(256), 0, s,
+                     scratch, nch, na, nb, G, ldg);
 }
 
 int gram(bool cplx, const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, int64_t n, double* G,
          int ldg, double* scratch, size_t scratch_bytes, hipStream_t s) {
-  const int nch = gram_chunks(n);
   if (gram_scratch_bytes(cplx, na, nb, n) > scratch_bytes) return OEFE_EINVAL;
+  if (gram_on_mfma(cplx, na, nb)) {
+    launch_gram_mfma(A, lda, na, B, ldb, nb, n, G, ldg, scratch, s);
+    return check();
+  }
+  const int nch = gram_chunks(n);
   const int64_t rpc = cdiv(n, nch);
   dim3 grid(nch, (unsigned)cdiv(na, 16), (unsigned)cdiv(nb, 16));
   if (cplx) {
@@ -1075,7 +1283,10 @@ int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int3
 
 // LDS version: the rotation record (kJacobiRecSweeps sweeps of m rounds x n/2 pairs x 4
 // doubles) and the ranks (+ the recorded sweep count); global version: V and the rotations.
-static bool jacobi_in_lds(bool cplx, int n) { return jacobi_rot_lds_bytes(cplx, n) <= 150 * 1024; }
+static bool jacobi_in_lds(bool cplx, int n) {
+  const int npair = (n + 1) / 2;
+  return jacobi_rot_lds_bytes(cplx, n) <= 150 * 1024 && npair * (npair + 1) / 2 <= 3 * 1024;
+}
 
 size_t jacobi_scratch_bytes(bool cplx, int n) {
   const int NN = (n % 2) ? n + 1 : n;
