@@ -96,7 +96,9 @@ constexpr int kGramNBMax = 5;   // 16-column blocks per operand
 constexpr int kGramChunks = 512;
 constexpr int kGramSlab = 32;   // rows per LDS slab
 
-__host__ __device__ constexpr int gram_lds_stride(int cols) { return cols + 1; }
+// row stride padded to 16 mod 32 doubles: the two rows read by a 32-lane half of a
+// fragment load (16 consecutive columns each) fall into disjoint LDS banks
+__host__ __device__ constexpr int gram_lds_stride(int cols) { return cols + (((16 - cols % 32) % 32) + 32) % 32; }
 
 template <int BPW>
 __global__ __launch_bounds__(256) void gram_mfma_kernel(const double* __restrict__ A, int64_t lda, int na,

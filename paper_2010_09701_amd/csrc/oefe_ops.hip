@@ -1139,6 +1139,11 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     colok[nb] = col < ncr;
     colc[nb] = colok[nb] ? col : ncr - 1;
   }
+  // node-slot grid columns, not clamped: a row of the grid (ldc >= ncr, a multiple of 8) is
+  // followed by the next row or by the grid's padding row, so columns up to ldc + 7 stay in
+  // the allocation; their values only reach lanes whose output is not stored.  The loads of a
+  // row then differ by constant offsets.
+  const T* __restrict__ Ycl = P.ycell + cb0 + li;
 
   // slots of node i per dimension: a shared node (i mod p == 0) has two, the one from
   // the lower cell first; slot 0 holds the periodic image of the last cell
@@ -1191,8 +1196,8 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
         const int64_t row2 = x2[v] ? row + 1 : row;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          gA[v][nb] = Yc[row * ldc + colc[nb]];
-          gB[v][nb] = Yc[row2 * ldc + colc[nb]];
+          gA[v][nb] = Ycl[row * ldc + nb * 16];
+          gB[v][nb] = Ycl[row2 * ldc + nb * 16];
         }
       }
     }
@@ -1311,9 +1316,8 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
       const int64_t row2 = x2[v] ? row + 1 : row;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int j = colc[nb];
-        const T v0 = Yc[row * ldc + j];
-        const T v1 = Yc[row2 * ldc + j];
+        const T v0 = Ycl[row * ldc + nb * 16];
+        const T v1 = Ycl[row2 * ldc + nb * 16];
         const T add = v0 + (x2[v] ? v1 : T(0));
         sum[v][nb] += need[v] ? add : T(0);
       }
@@ -1959,7 +1963,8 @@ size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, i
   if (ldc_out) *ldc_out = ldc;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t bytes = 0;
-  if (!op->diagonal) bytes += al((size_t)op->n_cells * op->nd * ldc * elem_bytes);
+  // node-slot grid plus one row: the fused node kernel reads up to 8 columns past a row's end
+  if (!op->diagonal) bytes += al(((size_t)op->n_cells * op->nd + 1) * ldc * elem_bytes);
   bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                 // zo
   bytes += al((size_t)std::max<int64_t>(op->tile_slots, 1) * ncr * elem_bytes);  // part
   bytes += al((size_t)std::max(op->n_enr, 1) * reduce_chunks(op) * ncr * elem_bytes);  // part2
@@ -1977,7 +1982,7 @@ StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv,
   char* p = (char*)work;
   if (!op->diagonal) {
     w.ycell = p;
-    p += al((size_t)op->n_cells * op->nd * ldc * elem_bytes);
+    p += al(((size_t)op->n_cells * op->nd + 1) * ldc * elem_bytes);
   }
   w.zo = p;
   p += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);
