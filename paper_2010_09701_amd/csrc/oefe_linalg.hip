@@ -87,106 +87,93 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks,
 }
 
 // ---- Gram on the matrix cores (16x16x4 float64 MFMA), real, for 16 <= na, nb <= 16 kGramNBMax:
-// partial[chunk][i][j] = sum over the chunk's rows g of A[g][i] B[g][j].  One
-// workgroup per row chunk (two per CU, so that one loads while the other computes) walks it
-// in slabs of kGramSlab rows, each loaded coalesced into LDS and consumed by the MFMAs.  The 16x16 output blocks are dealt round-robin to the 4
-// waves (block b = w + 4 t); fragment lanes: row 4 k + lane / 16, column 16 ib + lane % 16.
+// partial[chunk][i][j] = sum over the chunk's rows g of A[g][i] B[g][j].  One workgroup
+// (one wave per SIMD) per (row chunk, group of NBI 16-row blocks of G); each wave takes
+// every fourth k-step of 4 rows and accumulates the NBI x NBJ output blocks of 16x16, with the fragments of the next k-step
+// loaded while the MFMAs of the current one run (lane: row 4 k + lane / 16, column
+// 16 ib + lane % 16).  The four waves' sums are then added through one LDS buffer in a
+// fixed order and the workgroup's partial is written.
 typedef double dv4 __attribute__((ext_vector_type(4)));
 constexpr int kGramNBMax = 5;   // 16-column blocks per operand
-constexpr int kGramChunks = 512;
-constexpr int kGramSlab = 32;   // rows per LDS slab
+constexpr int kGramChunks = 256;
 
-// row stride padded to 16 mod 32 doubles: the two rows read by a 32-lane half of a
-// fragment load (16 consecutive columns each) fall into disjoint LDS banks
-__host__ __device__ constexpr int gram_lds_stride(int cols) { return cols + (((16 - cols % 32) % 32) + 32) % 32; }
-
-template <int BPW>
-__global__ __launch_bounds__(256) void gram_mfma_kernel(const double* __restrict__ A, int64_t lda, int na,
-                                                        const double* __restrict__ B, int64_t ldb, int nb,
-                                                        int64_t n, int64_t rows_per_chunk, double* __restrict__ part) {
-  constexpr int SR = kGramSlab;
-  extern __shared__ double gsm[];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
-  const int NBj = (nb + 15) / 16, nblk = ((na + 15) / 16) * NBj;
-  const int SA = gram_lds_stride(na), SB = gram_lds_stride(nb);
-  double* As[1] = {gsm};
-  double* Bs[1] = {gsm + SR * SA};
+template <int NBI, int NBJ>
+__global__ __launch_bounds__(256, NBI == 1 ? 4 : 1) void gram_mfma_kernel(const double* __restrict__ A, int64_t lda, int na,
+                                                           const double* __restrict__ B, int64_t ldb, int nb,
+                                                           int64_t n, int64_t rows_per_chunk,
+                                                           double* __restrict__ part) {
+  extern __shared__ double gsm[];  // [NBI * NBJ * 4][64]
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk, g1 = min(n, g0 + rows_per_chunk);
-  const int nslab = (int)((g1 - g0 + SR - 1) / SR);
-  int ca[BPW], cb[BPW];
-  bool oka[BPW], okb[BPW];
+  const int ib0 = blockIdx.y * NBI;  // this workgroup's first 16-row block of G
+  int ca[NBI], cb[NBJ];
+  double ma[NBI], mb[NBJ];
 #pragma unroll
-  for (int t = 0; t < BPW; ++t) {
-    const int b = min(w + 4 * t, nblk - 1), ib = b / NBj, jb = b - ib * NBj;
-    const int i = ib * 16 + li, j = jb * 16 + li;
-    oka[t] = i < na && w + 4 * t < nblk;
-    okb[t] = j < nb;
-    ca[t] = i < na ? i : na - 1;
-    cb[t] = j < nb ? j : nb - 1;
+  for (int i = 0; i < NBI; ++i) {
+    const int c = (ib0 + i) * 16 + li;
+    ma[i] = c < na ? 1.0 : 0.0;
+    ca[i] = min(c, na - 1);
   }
-  // slab loads: wave w takes rows w, w + 4, ... of the slab, lane l columns l and l + 64;
-  // unconditional loads from clamped in-bounds addresses, zeroed by a multiply past the
-  // chunk or the last column
-  constexpr int RPW = SR / 4;
-  double ra[2 * RPW], rb[2 * RPW];
-  const int la0 = min(lane, na - 1), la1 = min(lane + 64, na - 1);
-  const int lb0 = min(lane, nb - 1), lb1 = min(lane + 64, nb - 1);
-  const double ma0 = lane < na ? 1.0 : 0.0, ma1 = lane + 64 < na ? 1.0 : 0.0;
-  const double mb0 = lane < nb ? 1.0 : 0.0, mb1 = lane + 64 < nb ? 1.0 : 0.0;
-  auto load = [&](int sl) {
-    const int64_t gb = g0 + (int64_t)sl * SR;
 #pragma unroll
-    for (int i = 0; i < RPW; ++i) {
-      const int64_t g = gb + w + 4 * i;
-      const double m = g < g1 ? 1.0 : 0.0;
-      const int64_t gc = g < g1 ? g : g1 - 1;
-      ra[2 * i] = A[gc * lda + la0] * (m * ma0);
-      ra[2 * i + 1] = A[gc * lda + la1] * (m * ma1);
-      rb[2 * i] = B[gc * ldb + lb0] * (m * mb0);
-      rb[2 * i + 1] = B[gc * ldb + lb1] * (m * mb1);
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < RPW; ++i) {
-      const int r = w + 4 * i;
-      if (lane < na) As[buf][r * SA + lane] = ra[2 * i];
-      if (lane + 64 < na) As[buf][r * SA + lane + 64] = ra[2 * i + 1];
-      if (lane < nb) Bs[buf][r * SB + lane] = rb[2 * i];
-      if (lane + 64 < nb) Bs[buf][r * SB + lane + 64] = rb[2 * i + 1];
-    }
-  };
-  dv4 acc[BPW];
-#pragma unroll
-  for (int t = 0; t < BPW; ++t) acc[t] = dv4{0, 0, 0, 0};
-  for (int sl = 0; sl < nslab; ++sl) {
-    load(sl);
-    __syncthreads();  // the previous slab is no longer read
-    store(0);
-    __syncthreads();
-#pragma unroll 2
-    for (int k = 0; k < SR / 4; ++k) {
-      const int r = 4 * k + lk;
-#pragma unroll
-      for (int t = 0; t < BPW; ++t) {
-        const double a = As[0][r * SA + ca[t]] * (oka[t] ? 1.0 : 0.0);
-        const double bv = Bs[0][r * SB + cb[t]] * (okb[t] ? 1.0 : 0.0);
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
-      }
-    }
+  for (int j = 0; j < NBJ; ++j) {
+    const int c = j * 16 + li;
+    mb[j] = c < nb ? 1.0 : 0.0;
+    cb[j] = min(c, nb - 1);
   }
-  double* out = part + (int64_t)blockIdx.x * na * nb;
+  dv4 acc[NBI][NBJ];
 #pragma unroll
-  for (int t = 0; t < BPW; ++t) {
-    const int b = w + 4 * t;
-    if (b >= nblk) break;
-    const int ib = b / NBj, jb = b - ib * NBj, j = jb * 16 + li;
-    if (j >= nb) continue;
+  for (int i = 0; i < NBI; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = ib * 16 + lk + 4 * v;
-      if (i < na) out[(int64_t)i * nb + j] = acc[t][v];
+    for (int j = 0; j < NBJ; ++j) acc[i][j] = dv4{0, 0, 0, 0};
+  // fragments of the k-step at rows gk .. gk + 3 (rows past the chunk: clamped, zeroed)
+  auto load = [&](int64_t gk, double (&a)[NBI], double (&b)[NBJ]) {
+    const int64_t r = gk + lk;
+    const double m = r < g1 ? 1.0 : 0.0;
+    const int64_t rc = r < g1 ? r : g1 - 1;
+    const double* Ar = A + rc * lda;
+    const double* Br = B + rc * ldb;
+#pragma unroll
+    for (int i = 0; i < NBI; ++i) a[i] = Ar[ca[i]] * (m * ma[i]);
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) b[j] = Br[cb[j]] * mb[j];
+  };
+  auto mma = [&](const double (&a)[NBI], const double (&b)[NBJ]) {
+#pragma unroll
+    for (int i = 0; i < NBI; ++i)
+#pragma unroll
+      for (int j = 0; j < NBJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+  };
+  double a0[NBI], b0[NBJ], a1[NBI], b1[NBJ];
+  int64_t gk = g0 + 4 * w;
+  if (gk < g1) load(gk, a0, b0);
+  for (; gk < g1; gk += 32) {
+    load(gk + 16, a1, b1);
+    mma(a0, b0);
+    if (gk + 16 >= g1) break;
+    load(gk + 32, a0, b0);
+    mma(a1, b1);
+  }
+  // combine the four waves in a fixed order through one LDS buffer: ((w3 + w2) + w1) + w0
+  auto slot = [&](int i, int j, int v) -> double& { return gsm[((size_t)(i * NBJ + j) * 4 + v) * 64 + lane]; };
+  for (int step = 3; step >= 0; --step) {
+    if (w == step) {
+#pragma unroll
+      for (int i = 0; i < NBI; ++i)
+#pragma unroll
+        for (int j = 0; j < NBJ; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double t = step == 3 ? acc[i][j][v] : slot(i, j, v) + acc[i][j][v];
+            if (step > 0) {
+              slot(i, j, v) = t;
+            } else {
+              const int row = (ib0 + i) * 16 + lk + 4 * v, col = j * 16 + li;
+              if (row < na && col < nb) part[(int64_t)blockIdx.x * na * nb + (int64_t)row * nb + col] = t;
+            }
+          }
     }
+    if (step > 0) __syncthreads();
   }
 }
 
@@ -1206,7 +1193,7 @@ int gram_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(
 static bool gram_on_mfma(bool cplx, int na, int nb) {
   return !cplx && na >= 16 && nb >= 16 && na <= 16 * kGramNBMax && nb <= 16 * kGramNBMax;
 }
-static int gram_mfma_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kGramChunks, cdiv(n, 256))); }
+static int gram_mfma_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kGramChunks, cdiv(n, 64))); }
 
 size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n) {
   const int nch = gram_on_mfma(cplx, na, nb) ? gram_mfma_chunks(n) : gram_chunks(n);
@@ -1217,16 +1204,19 @@ static void launch_gram_mfma(const double* A, int64_t lda, int na, const double*
                              double* G, int ldg, double* scratch, hipStream_t s) {
   const int nch = gram_mfma_chunks(n);
   const int64_t rpc = cdiv(cdiv(n, nch), 4) * 4;
-  const int bpw = (int)cdiv(cdiv(na, 16) * cdiv(nb, 16), 4);
-  const size_t lds = (size_t)kGramSlab * (gram_lds_stride(na) + gram_lds_stride(nb)) * sizeof(double);
-  const dim3 grid((unsigned)nch);
-  auto go = [&](auto kern) {
+  const int nbi = (int)cdiv(na, 16), nbj = (int)cdiv(nb, 16);
+  // one row block per workgroup (up to four workgroups per CU), column blocks rounded up to {2, 3, 5}:
+  // fragments past na / nb are zero
+  const int bi = 1, bj = nbj <= 2 ? 2 : (nbj <= 3 ? 3 : 5);
+  const dim3 g2((unsigned)nch, (unsigned)cdiv(nbi, bi));
+  auto go2 = [&](auto kern) {
+    const size_t lds = (size_t)bi * bj * 4 * 64 * sizeof(double);
     if (allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds) != hipSuccess) return;
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, A, lda, na, B, ldb, nb, n, rpc, scratch);
+    hipLaunchKernelGGL(kern, g2, dim3(256), lds, s, A, lda, na, B, ldb, nb, n, rpc, scratch);
   };
-  if (bpw <= 2) go(gram_mfma_kernel<2>);
-  else if (bpw <= 4) go(gram_mfma_kernel<4>);
-  else go(gram_mfma_kernel<7>);
+  if (bi == 1) { if (bj == 2) go2(gram_mfma_kernel<1, 2>); else if (bj == 3) go2(gram_mfma_kernel<1, 3>); else go2(gram_mfma_kernel<1, 5>); }
+  else if (bi == 2) { if (bj == 2) go2(gram_mfma_kernel<2, 2>); else if (bj == 3) go2(gram_mfma_kernel<2, 3>); else go2(gram_mfma_kernel<2, 5>); }
+  else { if (bj == 2) go2(gram_mfma_kernel<3, 2>); else if (bj == 3) go2(gram_mfma_kernel<3, 3>); else go2(gram_mfma_kernel<3, 5>); }
   hipLaunchKernelGGL((gram_reduce_wave_kernel<false>), dim3((unsigned)cdiv((int64_t)na * nb, 4)), dim3(256), 0, s,
                      scratch, nch, na, nb, G, ldg);
 }
