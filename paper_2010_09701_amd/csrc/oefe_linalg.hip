@@ -390,14 +390,12 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
   const int tid = threadIdx.x, nth = blockDim.x;
   const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
   const int npair = NN / 2, m = NN - 1;
-  __shared__ int done;
   __shared__ int nrot;  // rotations applied in the current sweep
   auto A_ = [&](int i, int j) -> double* { return A + ((int64_t)i * n + j) * E; };
   for (int t = tid; t < n * n; t += nth) {
     V[(int64_t)t * E] = (t / n == t % n) ? 1.0 : 0.0;
     if (CPLX) V[(int64_t)t * E + 1] = 0.0;
   }
-  if (tid == 0) done = 0;
   __syncthreads();
   int sweep = 0;
   for (; sweep < 60; ++sweep) {
@@ -1058,8 +1056,8 @@ __global__ void max_dev_identity_kernel(const double* __restrict__ G, int n, dou
   }
   red[threadIdx.x] = mx;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+  for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
   if (threadIdx.x == 0) *err = red[0];
@@ -1122,8 +1120,8 @@ __global__ void dot_final_kernel(const double* __restrict__ part, int nchunks, i
   }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+  for (int st = (int)blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];

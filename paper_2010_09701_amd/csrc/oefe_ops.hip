@@ -1122,7 +1122,6 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   const T* __restrict__ zo = P.zo;                         // [n_enr][ncr]
   const T* __restrict__ x = P.x;
   const int64_t ldx = P.ldx;
-  const T* __restrict__ Yc = P.ycell;
   const int64_t ldc = P.ldc;
   const T alpha = P.alpha, c = P.c, beta = P.beta;
   const T* prev = P.prev;  // may be the same array as out (each element is read before it is written)
@@ -1674,14 +1673,6 @@ __global__ void density_final_kernel2(const double* __restrict__ dens, int nblk,
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-int pick_cw(int ncr) {
-  if (ncr >= 64 && ncr % 64 == 0) return 64;
-  if (ncr >= 48) return (ncr % 32 == 0) ? 32 : (ncr % 16 == 0 ? 16 : (ncr >= 128 ? 64 : 8));
-  if (ncr >= 32 && ncr % 32 == 0) return 32;
-  if (ncr >= 16 && ncr % 16 == 0) return 16;
-  return 8;
-}
 
 template <typename T>
 const CellCoef<T>& coef(const oefe_op_s* op);
