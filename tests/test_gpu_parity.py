@@ -135,17 +135,20 @@ def test_lanczos_bounds(lib):
     assert abs(ga0 - a0) < 1e-9 * abs(b) and abs(gb - b) < 1e-9 * abs(b)
 
 
-def test_cholgs_matches_oracle(lib):
+@pytest.mark.parametrize("nv", [1, 2, 15, 16, 37, 80, 81])
+def test_cholgs_matches_oracle(lib, nv):
+    """Block widths on both sides of the matrix-core Gram path (16..80 columns) and of its
+    3-row-block groups; 1 and 2 columns for the degenerate schedules."""
     sysm = SYSTEMS["diamond_nc4"]()
     gop = lib.Operator(sysm)
     rng = np.random.default_rng(5)
-    Y = rng.standard_normal((gop.n_tot, 37)) @ np.diag(np.logspace(0, 4, 37))
+    Y = rng.standard_normal((gop.n_tot, nv)) @ np.diag(np.logspace(0, 4, nv))
     Q, _ = och.cholgs(Y)
     Yd = _dev(Y)
     lib.cholgs(gop, Yd)
     Qg = Yd.cpu().numpy()
     np.testing.assert_allclose(Qg, Q, atol=1e-10)
-    np.testing.assert_allclose(Qg.T @ Qg, np.eye(37), atol=1e-12)
+    np.testing.assert_allclose(Qg.T @ Qg, np.eye(nv), atol=1e-12)
 
 
 def test_cholgs_breakdown_is_reported(lib):
@@ -188,7 +191,8 @@ def test_rayleigh_ritz_matches_oracle(lib):
     assert _multiplet_angles(th, Xr, Qd.cpu().numpy()) < 1e-8
 
 
-@pytest.mark.parametrize("name,kvec,nv", [("single_atom", None, 11), ("p3", None, 40),
+@pytest.mark.parametrize("name,kvec,nv", [("single_atom", None, 1), ("single_atom", None, 2), ("single_atom", None, 11),
+                                          ("p3", None, 40), ("p3", None, 80),
                                           ("single_atom", (0.3, -0.2, 0.1), 21), ("p3", (-0.4, 0.25, 0.1), 33)])
 def test_rayleigh_ritz_odd_sizes_and_bloch(lib, name, kvec, nv):
     """Odd block widths (a padded round-robin schedule) and Hermitian (Bloch) projected
