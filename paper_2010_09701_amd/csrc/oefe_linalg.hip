@@ -598,14 +598,138 @@ __device__ __forceinline__ void jacobi_pair(int st, int k, int m, int& p, int& q
   }
 }
 
-size_t jacobi_rot_lds_bytes(bool cplx, int n) {
-  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2;
-  const size_t nblk = (size_t)npair * (npair + 1) / 2;
-  return ((size_t)n * n * (cplx ? 2 : 1) + 4 * (size_t)npair + 32) * sizeof(double) + npair * sizeof(int) +
-         nblk * sizeof(uint16_t);
+// ---- Parallel cyclic Jacobi in one workgroup, the matrix moved along the pairing ring.
+// The round-robin pairing of jacobi_pair is realised physically: the matrix sits in LDS in
+// full storage over NN = n + (n odd) positions, positions 2k and 2k + 1 hold pair k of the
+// current round, and after every round each index moves to the next position of a fixed
+// ring, which makes the next round's pairs adjacent again.  Index 0 stays at position 0; the
+// other NN - 1 positions form one cycle, so after NN - 1 rounds (one sweep) every index is
+// back where it started.  Every thread therefore updates 2x2 blocks at fixed positions.  The
+// padding index of odd n has a zero row and column and is never rotated.
+
+// position that the index at position j moves to after a round
+__device__ __forceinline__ int jacobi_ring_next(int j, int npair) {
+  const int k = j >> 1;
+  if ((j & 1) == 0) return k == 0 ? 0 : (k == 1 ? 1 : 2 * (k - 1));
+  return k == npair - 1 ? (npair == 1 ? 1 : 2 * (npair - 1)) : 2 * (k + 1) + 1;
+}
+// index at position j at the start of a sweep (round 0 of jacobi_pair)
+__device__ __forceinline__ int jacobi_ring_index(int j, int m) {
+  const int k = j >> 1;
+  if ((j & 1) == 0) return k == 0 ? 0 : 1 + k;
+  return k == 0 ? 1 : 1 + m - k;
+}
+// position of index i at the start of a sweep
+__device__ __forceinline__ int jacobi_ring_pos(int i, int npair, int m) {
+  return i <= 1 ? i : (i <= npair ? 2 * (i - 1) : 2 * (1 + m - i) + 1);
+}
+// position that the index at position j held in the previous round (inverse of jacobi_ring_next)
+__device__ __forceinline__ int jacobi_ring_prev(int j, int npair) {
+  const int k = j >> 1;
+  if (j <= 1) return j == 0 ? 0 : (npair >= 2 ? 2 : 1);
+  if ((j & 1) == 0) return k <= npair - 2 ? 2 * (k + 1) : 2 * (npair - 1) + 1;
+  return 2 * (k - 1) + 1;
+}
+
+// 1/x and 1/sqrt(x) for x in [1/4, 4]: the hardware estimate refined by two Newton steps
+// (each step squares the relative error of the estimate).
+__device__ __forceinline__ double rcp_refined(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// One plane rotation of a Jacobi round: c, s and the phase er + i ei of a_pq (real: er = sign
+// of a_pq); the identity (c = 1, s = 0, er = 1, ei = 0) when the pair is not rotated.
+struct JacobiRot {
+  double c, s, er, ei;
+  bool on;
+};
+
+// The rotation that annihilates a_pq = b of the Hermitian 2x2 pivot [al, b; conj(b), ga]:
+// t = tan(phi) = sgn(d) 2|b| / (|d| + sqrt(d^2 + 4|b|^2)) with d = ga - al (the smaller root
+// of t^2 + (d/|b|) t - 1 = 0), c = 1/sqrt(1 + t^2), s = t c.  d and 2|b| are first scaled
+// by a power of two that brings the larger into [1/2, 1), so t needs no unscaling and every
+// reciprocal and square root sees an argument in [1/4, 4].  The pair is rotated only when
+// |b| lies above float64 rounding, measured on its diagonal entries or on the matrix norm
+// (whichever is larger).  No branches: the identity is selected when the pair is not rotated.
+template <bool CPLX>
+__device__ __forceinline__ JacobiRot jacobi_rotation(double al, double ga, double br, double bi, double nrm_n) {
+  const double r = CPLX ? sqrt(br * br + bi * bi) : fabs(br);
+  const bool on = r > 1e-300 && r > 2.220446049250313e-16 * fmax(sqrt(fabs(al * ga)), nrm_n);
+  const double d = ga - al;
+  const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(d), 2.0 * r));
+  const double ds = ldexp(d, -ex), rs2 = ldexp(2.0 * r, -ex);  // max(|ds|, rs2) in [1/2, 1)
+  const double x = fma(ds, ds, rs2 * rs2);                     // [1/4, 2]
+  const double w = x * rsq_refined(x);                         // sqrt(x)
+  const double t = (d >= 0 ? rs2 : -rs2) * rcp_refined(fabs(ds) + w);
+  const double c = rsq_refined(fma(t, t, 1.0));
+  JacobiRot R;
+  R.on = on;
+  R.c = on ? c : 1.0;
+  R.s = on ? t * c : 0.0;
+  if constexpr (CPLX) {
+    const double ir = 1.0 / r;
+    R.er = on ? br * ir : 1.0;
+    R.ei = on ? bi * ir : 0.0;
+  } else {
+    R.er = on ? (br >= 0 ? 1.0 : -1.0) : 1.0;
+    R.ei = 0.0;
+  }
+  return R;
 }
 
 template <bool CPLX>
+__device__ __forceinline__ Z jz_load(const double* a) {
+  if constexpr (CPLX) return Z{a[0], a[1]};
+  else return Z{a[0], 0.0};
+}
+template <bool CPLX>
+__device__ __forceinline__ void jz_store(double* a, Z v) {
+  a[0] = v.r;
+  if constexpr (CPLX) a[1] = v.i;
+}
+template <bool CPLX>
+__device__ __forceinline__ Z jz_mul(Z a, Z b) {
+  if constexpr (CPLX) return zmul(a, b);
+  else return Z{a.r * b.r, 0.0};
+}
+template <bool CPLX>
+__device__ __forceinline__ Z jz_fma(Z a, Z b, Z c) {  // a b + c
+  if constexpr (CPLX) return Z{fma(a.r, b.r, fma(-a.i, b.i, c.r)), fma(a.r, b.i, fma(a.i, b.r, c.i))};
+  else return Z{fma(a.r, b.r, c.r), 0.0};
+}
+__device__ __forceinline__ Z jz_conj(Z a) { return Z{a.r, -a.i}; }
+// entry (a, b) of G1^* B G2 for 2x2 matrices stored row-major
+template <bool CPLX>
+__device__ __forceinline__ Z jz_entry(const Z* G1, const Z* B, const Z* G2, int a, int b) {
+  // columns a of G1 and b of G2 by selects (a, b may vary per lane)
+  const Z g1a0 = a ? G1[1] : G1[0], g1a1 = a ? G1[3] : G1[2];
+  const Z g2b0 = b ? G2[1] : G2[0], g2b1 = b ? G2[3] : G2[2];
+  const Z c0 = jz_fma<CPLX>(B[1], g2b1, jz_mul<CPLX>(B[0], g2b0));  // (B G2)[0][b]
+  const Z c1 = jz_fma<CPLX>(B[3], g2b1, jz_mul<CPLX>(B[2], g2b0));  // (B G2)[1][b]
+  return jz_fma<CPLX>(jz_conj(g1a1), c1, jz_mul<CPLX>(jz_conj(g1a0), c0));
+}
+
+size_t jacobi_rot_lds_bytes(bool cplx, int n) {
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, E = cplx ? 2 : 1;
+  const size_t nblk = (size_t)npair * (npair + 1) / 2;
+  return ((size_t)NN * (NN + 1) * E + 4 * (size_t)E * npair + 32) * sizeof(double) + nblk * sizeof(uint16_t);
+}
+
+// Rotations of all sweeps are recorded (c, s, er, ei per pair and round, in the orientation
+// p < q of jacobi_pair) for jacobi_vec_kernel; eigenvalues come out in ascending order with
+// the rank of every index.
+template <bool CPLX, int KB>
 __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restrict__ A, int n,
                                                           double* __restrict__ lam, int32_t* __restrict__ rank_out,
                                                           double* __restrict__ rec, int32_t* __restrict__ status) {
@@ -614,17 +738,31 @@ __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restri
   const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
   const int npair = NN / 2, m = NN - 1;
   const int nblk = npair * (npair + 1) / 2;
-  double* As = sm;                       // n*n*E, upper triangle used
-  double* rc = As + (size_t)n * n * E;   // per pair: c
-  double* rs = rc + npair;               // s (0: no rotation)
-  double* rer = rs + npair;              // er + i ei = e^{i phi} of a_pq (real: er = sign)
-  double* rei = rer + npair;
-  double* red = rei + npair;             // 2 per wave (<= 32)
-  int* rpq = reinterpret_cast<int*>(red + 32);                 // p | q << 16
-  uint16_t* blk = reinterpret_cast<uint16_t*>(rpq + npair);    // k1 | k2 << 8, k1 <= k2
+  // storage as in jacobi_ring1_kernel: slot-major rows / columns with an odd row stride, the
+  // rotation table as four arrays
+  const int ld = NN + 1;
+  double* As = sm;
+  double* gph = As + (size_t)NN * ld * E;       // [4][npair]: the 2x2 transforms by position
+  double* red = gph + 4 * (size_t)E * npair;    // 2 per wave (<= 32)
+  uint16_t* blk = reinterpret_cast<uint16_t*>(red + 32);  // k1 | k2 << 8, k1 <= k2
   __shared__ int anyrot;  // a rotation was applied in the current sweep
   const int tid = threadIdx.x, nth = blockDim.x;
-  for (int t = tid; t < n * n * E; t += nth) As[t] = A[t];
+  auto slot = [npair](int j) { return (j & 1) * npair + (j >> 1); };
+  auto at = [&](int pi, int pj) { return slot(pi) * ld + slot(pj); };
+  auto gtab = [&](int e) { return gph + (size_t)e * npair * E; };
+  // A (Hermitian; its upper triangle is read) at the ring positions of a sweep's start
+  for (int t = tid; t < NN * NN; t += nth) {
+    const int pi = t / NN, pj = t - pi * NN;
+    const int i = jacobi_ring_index(pi, m), j = jacobi_ring_index(pj, m);
+    double vr = 0.0, vi = 0.0;
+    if (i < n && j < n) {
+      const double* a = A + ((size_t)min(i, j) * n + max(i, j)) * E;
+      vr = a[0];
+      if (CPLX) vi = i == j ? 0.0 : (i < j ? a[E - 1] : -a[E - 1]);
+    }
+    As[(size_t)at(pi, pj) * E] = vr;
+    if (CPLX) As[(size_t)at(pi, pj) * E + 1] = vi;
+  }
   for (int b = tid; b < nblk; b += nth) {
     int k1 = 0, bb = b;
     while (bb >= npair - k1) {
@@ -634,27 +772,38 @@ __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restri
     blk[b] = (uint16_t)(k1 | ((k1 + bb) << 8));
   }
   __syncthreads();
-  auto up = [&](int i, int j) -> double* { return As + ((int64_t)i * n + j) * E; };  // i <= j
-  // this thread's blocks (the assignment does not change between rounds)
-  constexpr int kBlkPerThread = 3;  // npair <= 69 (n <= 137): nblk <= 2415 <= 3 * 1024
-  int myblk[kBlkPerThread];
+  // this thread's blocks (k1, k2), k1 <= k2: where their four entries are, and where the
+  // entries and their mirror images move to
+  int myblk[KB], src[KB][4], dst[KB][4], mir[KB][4];
 #pragma unroll
-  for (int i = 0; i < kBlkPerThread; ++i) {
+  for (int i = 0; i < KB; ++i) {
     const int bb = tid + i * nth;
     myblk[i] = bb < nblk ? (int)blk[bb] : -1;
+    const int kk = myblk[i] < 0 ? 0 : myblk[i];
+    const int k1 = kk & 255, k2 = kk >> 8;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int r = jacobi_ring_next(2 * k1 + a, npair), q = jacobi_ring_next(2 * k2 + c, npair);
+        src[i][2 * a + c] = at(2 * k1 + a, 2 * k2 + c);
+        dst[i][2 * a + c] = at(r, q);
+        mir[i][2 * a + c] = at(q, r);
+      }
   }
+  const int kp = tid < npair ? tid : 0;
+  const int opiv = at(2 * kp, 2 * kp), opiv1 = at(2 * kp + 1, 2 * kp + 1), opq = at(2 * kp, 2 * kp + 1);
   int sweep = 0, nrec = 0;
   bool conv = false;
   for (; sweep < kJacobiRecSweeps; ++sweep) {
     // convergence test: squared Frobenius norms of the off-diagonal and diagonal parts
     double off = 0, dia = 0;
-    for (int t = tid; t < n * n; t += nth) {
-      const int i = t / n, j = t - i * n;
-      if (i > j) continue;
-      const double* a = As + (int64_t)t * E;
+    for (int t = tid; t < NN * NN; t += nth) {
+      const int i = t / NN, j = t - i * NN;
+      const double* a = As + ((size_t)i * ld + j) * E;
       const double v = a[0] * a[0] + (CPLX ? a[1] * a[1] : 0.0);
       if (i == j) dia += v;
-      else off += 2.0 * v;
+      else off += v;
     }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_xor(off, o);
@@ -678,117 +827,65 @@ __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restri
       break;
     }
     double* rrec = rec + (size_t)nrec * m * npair * 4;
+    // schedule positions (st + k) mod m and (st - k) mod m of pair k = tid
+    int sa = kp % m, sb = (m - kp % m) % m;
     for (int st = 0; st < m; ++st) {
-      // (a) rotation per pair
-      for (int k = tid; k < npair; k += nth) {
-        int p, q;
-        jacobi_pair(st, k, m, p, q);
-        double c = 1, sn = 0, er = 1, ei = 0;
-        if (q < n) {
-          const double* apq = up(p, q);
-          const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
-          const double r = CPLX ? sqrt(br * br + bi * bi) : fabs(br);
-          const double al = up(p, p)[0], ga = up(q, q)[0];
-          // rotate only when the pair is coupled above float64 rounding, measured on its
-          // diagonal entries or on the matrix norm (whichever is larger)
-          if (r > 1e-300 && r > 2.220446049250313e-16 * fmax(sqrt(fabs(al * ga)), nrm_n)) {
-            anyrot = 1;
-            if constexpr (CPLX) {
-              er = br / r;
-              ei = bi / r;
-            } else {
-              er = br >= 0 ? 1.0 : -1.0;
-            }
-            const double tau = (ga - al) / (2.0 * r);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = rsqrt(1.0 + t * t);
-            sn = t * c;
-          }
-        }
-        rc[k] = c;
-        rs[k] = sn;
-        rer[k] = er;
-        rei[k] = ei;
-        rpq[k] = p | (q << 16);
+      // (a) one thread per pair forms the rotation of the pair at positions (2k, 2k+1); every
+      // thread reads its blocks (the previous round has finished moving them)
+      if (tid < npair) {
+        const int k = tid;
+        const double a00 = As[(size_t)opiv * E], a11 = As[(size_t)opiv1 * E];
+        const Z b = jz_load<CPLX>(As + (size_t)opq * E);
+        const bool sw = k >= 1 && sa > sb;  // position 2k holds q
+        const JacobiRot g = jacobi_rotation<CPLX>(sw ? a11 : a00, sw ? a00 : a11, b.r, sw ? -b.i : b.i, nrm_n);
         double* R = rrec + ((size_t)st * npair + k) * 4;
-        R[0] = c; R[1] = sn; R[2] = er; R[3] = ei;
+        R[0] = g.c; R[1] = g.s; R[2] = g.er; R[3] = g.ei;
+        // columns (p, q) <- (p, q) G with G = [c, s; -s conj(e), c conj(e)], e = er + i ei;
+        // by position the rows and columns of G are swapped when position 2k holds q
+        const Z g00{g.c, 0.0}, g01{g.s, 0.0}, g10{-g.s * g.er, g.s * g.ei}, g11{g.c * g.er, -g.c * g.ei};
+        jz_store<CPLX>(gtab(0) + (size_t)k * E, sw ? g11 : g00);
+        jz_store<CPLX>(gtab(1) + (size_t)k * E, sw ? g10 : g01);
+        jz_store<CPLX>(gtab(2) + (size_t)k * E, sw ? g01 : g10);
+        jz_store<CPLX>(gtab(3) + (size_t)k * E, sw ? g00 : g11);
+        if (g.on) anyrot = 1;
+        sa = sa + 1 == m ? 0 : sa + 1;
+        sb = sb + 1 == m ? 0 : sb + 1;
+      }
+      Z bl[KB][4];
+#pragma unroll
+      for (int i = 0; i < KB; ++i) {
+        if (myblk[i] < 0) break;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bl[i][e] = jz_load<CPLX>(As + (size_t)src[i][e] * E);
       }
       __syncthreads();
-      // (b) 2x2 blocks k1 <= k2 of the upper triangle: columns by G_k2, then rows by G_k1^*
+      // (b) B <- G_k1^* B G_k2, written to the positions of the next round
 #pragma unroll
-      for (int i = 0; i < kBlkPerThread; ++i) {
-        const int kk = myblk[i];
-        if (kk < 0) break;
-        const int k1 = kk & 255, k2 = kk >> 8;
-        const bool on1 = rs[k1] != 0.0, on2 = rs[k2] != 0.0;
-        if (!on1 && !on2) continue;
-        const int pq1 = rpq[k1], pq2 = rpq[k2];
-        const int p1 = pq1 & 0xffff, q1 = pq1 >> 16, p2 = pq2 & 0xffff, q2 = pq2 >> 16;
-        const bool r2 = q1 < n, c2 = q2 < n;  // second row / column exists
-        if constexpr (!CPLX) {
-          auto ld = [&](int i, int j) { return i <= j ? *up(i, j) : *up(j, i); };
-          auto st1 = [&](int i, int j, double v) { *(i <= j ? up(i, j) : up(j, i)) = v; };
-          double b00 = ld(p1, p2), b01 = c2 ? ld(p1, q2) : 0.0;
-          double b10 = r2 ? ld(q1, p2) : 0.0, b11 = (r2 && c2) ? ld(q1, q2) : 0.0;
-          if (on2) {
-            const double c = rc[k2], sn = rs[k2], sg = rer[k2];
-            double x = b00, y = b01 * sg;
-            b00 = x * c - y * sn; b01 = x * sn + y * c;
-            x = b10; y = b11 * sg;
-            b10 = x * c - y * sn; b11 = x * sn + y * c;
+      for (int i = 0; i < KB; ++i) {
+        if (myblk[i] < 0) break;
+        const int k1 = myblk[i] & 255, k2 = myblk[i] >> 8;
+        Z u[4], v[4], d[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          u[e] = jz_load<CPLX>(gtab(e) + (size_t)k1 * E);
+          v[e] = jz_load<CPLX>(gtab(e) + (size_t)k2 * E);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[e] = jz_entry<CPLX>(u, bl[i], v, e >> 1, e & 1);
+        if (k1 == k2) {
+          if (u[1].r != 0.0 || u[1].i != 0.0) {  // the rotated pair; its diagonal stays real
+            d[1] = d[2] = Z{0.0, 0.0};
+            d[0].i = 0.0;
+            d[3].i = 0.0;
           }
-          if (on1) {
-            const double c = rc[k1], sn = rs[k1], sg = rer[k1];
-            double x = b00, y = sg * b10;
-            b00 = c * x - sn * y; b10 = sn * x + c * y;
-            x = b01; y = sg * b11;
-            b01 = c * x - sn * y; b11 = sn * x + c * y;
-          }
-          if (k1 == k2) b01 = b10 = 0.0;  // the rotated pair
-          st1(p1, p2, b00);
-          if (c2) st1(p1, q2, b01);
-          if (r2 && k1 != k2) st1(q1, p2, b10);
-          if (r2 && c2) st1(q1, q2, b11);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) jz_store<CPLX>(As + (size_t)dst[i][e] * E, d[e]);
         } else {
-          auto ld = [&](int i, int j) {
-            return i <= j ? Z{up(i, j)[0], up(i, j)[1]} : Z{up(j, i)[0], -up(j, i)[1]};
-          };
-          auto st2 = [&](int i, int j, Z v) {
-            if (i <= j) { up(i, j)[0] = v.r; up(i, j)[1] = v.i; }
-            else { up(j, i)[0] = v.r; up(j, i)[1] = -v.i; }
-          };
-          const Z z0{0.0, 0.0};
-          Z b00 = ld(p1, p2), b01 = c2 ? ld(p1, q2) : z0, b10 = r2 ? ld(q1, p2) : z0;
-          Z b11 = (r2 && c2) ? ld(q1, q2) : z0;
-          if (on2) {
-            const double c = rc[k2], sn = rs[k2];
-            const Z emi{rer[k2], -rei[k2]};
-            Z x = b00, ye = zmul(b01, emi);
-            b00 = {x.r * c - ye.r * sn, x.i * c - ye.i * sn};
-            b01 = {x.r * sn + ye.r * c, x.i * sn + ye.i * c};
-            x = b10; ye = zmul(b11, emi);
-            b10 = {x.r * c - ye.r * sn, x.i * c - ye.i * sn};
-            b11 = {x.r * sn + ye.r * c, x.i * sn + ye.i * c};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            jz_store<CPLX>(As + (size_t)dst[i][e] * E, d[e]);
+            jz_store<CPLX>(As + (size_t)mir[i][e] * E, jz_conj(d[e]));
           }
-          if (on1) {
-            const double c = rc[k1], sn = rs[k1];
-            const Z eph{rer[k1], rei[k1]};
-            Z x = b00, ye = zmul(eph, b10);
-            b00 = {c * x.r - sn * ye.r, c * x.i - sn * ye.i};
-            b10 = {sn * x.r + c * ye.r, sn * x.i + c * ye.i};
-            x = b01; ye = zmul(eph, b11);
-            b01 = {c * x.r - sn * ye.r, c * x.i - sn * ye.i};
-            b11 = {sn * x.r + c * ye.r, sn * x.i + c * ye.i};
-          }
-          if (k1 == k2) {  // the rotated pair; the diagonal stays real
-            b01 = b10 = z0;
-            b00.i = 0.0;
-            b11.i = 0.0;
-          }
-          st2(p1, p2, b00);
-          if (c2) st2(p1, q2, b01);
-          if (r2 && k1 != k2) st2(q1, p2, b10);
-          if (r2 && c2) st2(q1, q2, b11);
         }
       }
       __syncthreads();
@@ -806,12 +903,252 @@ __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restri
     status[1] = sweep;
     rank_out[n] = nrec;
   }
+  // the layout is that of a sweep's start: eigenvalue of index i at position jacobi_ring_pos(i)
+  double* dg = gph;  // NN <= 4 E npair doubles
+  for (int i = tid; i < n; i += nth) {
+    const int q = jacobi_ring_pos(i, npair, m);
+    dg[i] = As[(size_t)at(q, q) * E];
+  }
+  __syncthreads();
   // ascending order by rank
   for (int i = tid; i < n; i += nth) {
-    const double li = up(i, i)[0];
+    const double li = dg[i];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double lj = up(j, j)[0];
+      const double lj = dg[j];
+      if (lj < li || (lj == li && j < i)) ++rank;
+    }
+    lam[rank] = li;
+    rank_out[i] = rank;
+  }
+}
+
+// The same Jacobi with one barrier per round (real or small n: the matrix is double
+// buffered in LDS and every block fits one thread).  Within a round every block thread reads
+// the current matrix and rotation table and writes the moved blocks to the other buffer,
+// while one thread per pair, in waves of their own, forms the rotation of the NEXT round: the
+// two indices that pair k meets at positions (2k, 2k+1) next round sit at positions
+// u = jacobi_ring_prev(2k) and v = jacobi_ring_prev(2k+1) now, in different pairs, so the
+// next pivot entries are entries of G_u^* B G_v for blocks B of the current matrix.
+// Storage is slot-major: position j is kept at row / column (j odd) * npair + j / 2, so a
+// ring step moves an entry by one column, and the blocks of neighbouring lanes (neighbouring
+// k2) are read and written at neighbouring addresses; the odd row stride spreads the mirror
+// images, written along a column, over the LDS banks.  The rotation table is kept as four
+// arrays (one per entry of the 2x2 transform).
+size_t jacobi_ring1_lds_bytes(bool cplx, int n) {
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, E = cplx ? 2 : 1;
+  const size_t nblk = (size_t)npair * (npair + 1) / 2;
+  return (2 * (size_t)NN * (NN + 1) * E + 8 * (size_t)E * npair + 32) * sizeof(double) + nblk * sizeof(uint16_t);
+}
+// block threads (one block each) and the waves of rotation threads fit 1024 threads
+bool jacobi_ring1_fits(int n) {
+  const int npair = (n + 1) / 2;
+  return npair * (npair + 1) / 2 <= 1024 - 64 * ((npair + 63) / 64);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void jacobi_ring1_kernel(const double* __restrict__ A, int n,
+                                                            double* __restrict__ lam, int32_t* __restrict__ rank_out,
+                                                            double* __restrict__ rec, int32_t* __restrict__ status) {
+  constexpr int E = CPLX ? 2 : 1;
+  extern __shared__ double sm[];
+  const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
+  const int npair = NN / 2, m = NN - 1;
+  const int nblk = npair * (npair + 1) / 2;
+  const int ld = NN + 1;
+  const size_t msz = (size_t)NN * ld * E;
+  double* Gt0 = sm + 2 * msz;                    // two rotation tables [4][npair]
+  double* red = Gt0 + 8 * (size_t)E * npair;     // 2 per wave (<= 32)
+  uint16_t* blk = reinterpret_cast<uint16_t*>(red + 32);  // k1 | k2 << 8, k1 <= k2
+  __shared__ int anyrot;  // a rotation was applied in the current sweep
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int rbase = nth - 64 * ((npair + 63) / 64);  // rotation threads: pair kr = tid - rbase
+  const int kr = tid - rbase;
+  const bool is_rot = kr >= 0 && kr < npair;
+  auto slot = [npair](int j) { return (j & 1) * npair + (j >> 1); };  // storage row / column of position j
+  auto at = [&](int pi, int pj) { return slot(pi) * ld + slot(pj); };  // entry offset of (pi, pj)
+  for (int t = tid; t < NN * NN; t += nth) {
+    const int pi = t / NN, pj = t - pi * NN;
+    const int i = jacobi_ring_index(pi, m), j = jacobi_ring_index(pj, m);
+    double vr = 0.0, vi = 0.0;
+    if (i < n && j < n) {
+      const double* a = A + ((size_t)min(i, j) * n + max(i, j)) * E;
+      vr = a[0];
+      if (CPLX) vi = i == j ? 0.0 : (i < j ? a[E - 1] : -a[E - 1]);
+    }
+    sm[(size_t)at(pi, pj) * E] = vr;
+    if (CPLX) sm[(size_t)at(pi, pj) * E + 1] = vi;
+  }
+  for (int b = tid; b < nblk; b += nth) {
+    int k1 = 0, bb = b;
+    while (bb >= npair - k1) {
+      bb -= npair - k1;
+      ++k1;
+    }
+    blk[b] = (uint16_t)(k1 | ((k1 + bb) << 8));
+  }
+  __syncthreads();
+  const int myb = tid < nblk ? (int)blk[tid] : -1;
+  const int k1 = myb < 0 ? 0 : (myb & 255), k2 = myb < 0 ? 0 : (myb >> 8);
+  int src[4], dst[4], mir[4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int r = jacobi_ring_next(2 * k1 + a, npair), q = jacobi_ring_next(2 * k2 + c, npair);
+      src[2 * a + c] = at(2 * k1 + a, 2 * k2 + c);
+      dst[2 * a + c] = at(r, q);
+      mir[2 * a + c] = at(q, r);
+    }
+  const int krc = is_rot ? kr : 0;
+  const int pu = jacobi_ring_prev(2 * krc, npair), pv = jacobi_ring_prev(2 * krc + 1, npair);
+  const int ku = pu >> 1, ul = pu & 1, kv = pv >> 1, vl = pv & 1;
+  int ouu[4], ovv[4], ouv[4];  // blocks (ku, ku), (kv, kv), (ku, kv)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      ouu[2 * a + c] = at(2 * ku + a, 2 * ku + c);
+      ovv[2 * a + c] = at(2 * kv + a, 2 * kv + c);
+      ouv[2 * a + c] = at(2 * ku + a, 2 * kv + c);
+    }
+  const int opiv = at(2 * krc, 2 * krc), opiv1 = at(2 * krc + 1, 2 * krc + 1), opq = at(2 * krc, 2 * krc + 1);
+  int cb = 0, gb = 0;  // current matrix buffer and rotation table
+  int sweep = 0, nrec = 0;
+  bool conv = false;
+  auto gtab = [&](int g, int e) { return Gt0 + ((size_t)(g * 4 + e) * npair) * E; };
+  // pair kr's rotation from its pivot entries as stored at positions (2kr, 2kr+1): record it and
+  // put its transform by position into table g
+  auto form = [&](double a00, double a11, Z b, int sa, int sb, double nrm_n, int g, double* R) {
+    const bool sw = kr >= 1 && sa > sb;  // position 2kr holds q
+    const JacobiRot q = jacobi_rotation<CPLX>(sw ? a11 : a00, sw ? a00 : a11, b.r, sw ? -b.i : b.i, nrm_n);
+    R[0] = q.c; R[1] = q.s; R[2] = q.er; R[3] = q.ei;
+    const Z g00{q.c, 0.0}, g01{q.s, 0.0}, g10{-q.s * q.er, q.s * q.ei}, g11{q.c * q.er, -q.c * q.ei};
+    jz_store<CPLX>(gtab(g, 0) + (size_t)kr * E, sw ? g11 : g00);
+    jz_store<CPLX>(gtab(g, 1) + (size_t)kr * E, sw ? g10 : g01);
+    jz_store<CPLX>(gtab(g, 2) + (size_t)kr * E, sw ? g01 : g10);
+    jz_store<CPLX>(gtab(g, 3) + (size_t)kr * E, sw ? g00 : g11);
+    if (q.on) anyrot = 1;
+  };
+  auto ldblk = [&](const double* Ab, const int* o, Z* B) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) B[e] = jz_load<CPLX>(Ab + (size_t)o[e] * E);
+  };
+  auto ldrot = [&](int g, int k, Z* G) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) G[e] = jz_load<CPLX>(gtab(g, e) + (size_t)k * E);
+  };
+  for (; sweep < kJacobiRecSweeps; ++sweep) {
+    const double* Ac = sm + cb * msz;
+    double off = 0, dia = 0;
+    for (int t = tid; t < NN * NN; t += nth) {
+      const int i = t / NN, j = t - i * NN;
+      const double* a = Ac + ((size_t)i * ld + j) * E;
+      const double v = a[0] * a[0] + (CPLX ? a[1] * a[1] : 0.0);
+      if (i == j) dia += v;
+      else off += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      dia += __shfl_xor(dia, o);
+    }
+    if ((tid & 63) == 0) {
+      red[2 * (tid >> 6)] = off;
+      red[2 * (tid >> 6) + 1] = dia;
+    }
+    __syncthreads();
+    double offs = 0, dias = 0;
+    for (int w = 0; w < nth / 64; ++w) {
+      offs += red[2 * w];
+      dias += red[2 * w + 1];
+    }
+    const double nrm_n = sqrt(offs + dias) / n;  // Frobenius norm / n
+    if (tid == 0) anyrot = 0;
+    __syncthreads();
+    if (offs <= 1e-30 * dias || offs == 0.0) {
+      conv = true;
+      break;
+    }
+    double* rrec = rec + (size_t)nrec * m * npair * 4;
+    int sa = krc % m, sb = (m - krc % m) % m;  // (round + kr) mod m, (round - kr) mod m
+    if (is_rot) {  // rotations of round 0 from the pivots
+      form(Ac[(size_t)opiv * E], Ac[(size_t)opiv1 * E], jz_load<CPLX>(Ac + (size_t)opq * E), sa, sb, nrm_n, gb,
+           rrec + (size_t)kr * 4);
+      sa = sa + 1 == m ? 0 : sa + 1;
+      sb = sb + 1 == m ? 0 : sb + 1;
+    }
+    __syncthreads();
+    for (int st = 0; st < m; ++st) {
+      const double* Acur = sm + cb * msz;
+      double* Anext = sm + (cb ^ 1) * msz;
+      if (myb >= 0) {  // B <- G_k1^* B G_k2, written to the positions of the next round
+        Z u[4], v[4], B[4];
+        ldrot(gb, k1, u);
+        ldrot(gb, k2, v);
+        ldblk(Acur, src, B);
+        Z d[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[e] = jz_entry<CPLX>(u, B, v, e >> 1, e & 1);
+        if (k1 == k2) {
+          if (u[1].r != 0.0 || u[1].i != 0.0) {  // the rotated pair; its diagonal stays real
+            d[1] = d[2] = Z{0.0, 0.0};
+            d[0].i = 0.0;
+            d[3].i = 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) jz_store<CPLX>(Anext + (size_t)dst[e] * E, d[e]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            jz_store<CPLX>(Anext + (size_t)dst[e] * E, d[e]);
+            jz_store<CPLX>(Anext + (size_t)mir[e] * E, jz_conj(d[e]));
+          }
+        }
+      }
+      if (is_rot && st + 1 < m) {  // rotation of pair kr in the next round
+        Z gu[4], gv[4], Buu[4], Bvv[4], Buv[4];
+        ldrot(gb, ku, gu);
+        ldrot(gb, kv, gv);
+        ldblk(Acur, ouu, Buu);
+        ldblk(Acur, ovv, Bvv);
+        ldblk(Acur, ouv, Buv);
+        const double xuu = jz_entry<CPLX>(gu, Buu, gu, ul, ul).r;
+        const double xvv = jz_entry<CPLX>(gv, Bvv, gv, vl, vl).r;
+        const Z xuv = jz_entry<CPLX>(gu, Buv, gv, ul, vl);
+        form(xuu, xvv, xuv, sa, sb, nrm_n, gb ^ 1, rrec + ((size_t)(st + 1) * npair + kr) * 4);
+        sa = sa + 1 == m ? 0 : sa + 1;
+        sb = sb + 1 == m ? 0 : sb + 1;
+      }
+      __syncthreads();
+      cb ^= 1;
+      gb ^= 1;
+    }
+    // a sweep that found no pair coupled above rounding: converged (its record is the identity)
+    if (anyrot == 0) {
+      ++sweep;
+      conv = true;
+      break;
+    }
+    ++nrec;
+  }
+  if (tid == 0) {
+    status[0] = conv ? 0 : OEFE_ENOCONV;
+    status[1] = sweep;
+    rank_out[n] = nrec;
+  }
+  // the layout is that of a sweep's start: eigenvalue of index i at position jacobi_ring_pos(i)
+  const double* Af = sm + cb * msz;
+  double* dg = Gt0;  // NN <= 8 E npair doubles
+  for (int i = tid; i < n; i += nth) {
+    const int q = jacobi_ring_pos(i, npair, m);
+    dg[i] = Af[(size_t)at(q, q) * E];
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nth) {
+    const double li = dg[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = dg[j];
       if (lj < li || (lj == li && j < i)) ++rank;
     }
     lam[rank] = li;
@@ -1275,7 +1612,7 @@ int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int3
 // doubles) and the ranks (+ the recorded sweep count); global version: V and the rotations.
 static bool jacobi_in_lds(bool cplx, int n) {
   const int npair = (n + 1) / 2;
-  return jacobi_rot_lds_bytes(cplx, n) <= 150 * 1024 && npair * (npair + 1) / 2 <= 3 * 1024;
+  return jacobi_rot_lds_bytes(cplx, n) <= 158 * 1024 && npair * (npair + 1) / 2 <= 3 * 1024;  // 160 KB of LDS per workgroup
 }
 
 size_t jacobi_scratch_bytes(bool cplx, int n) {
@@ -1292,19 +1629,25 @@ int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scra
     const int NN = (n % 2) ? n + 1 : n;
     double* rec = scratch;
     int32_t* rank = reinterpret_cast<int32_t*>(rec + (size_t)kJacobiRecSweeps * (NN - 1) * (NN / 2) * 4);
-    const size_t lds = jacobi_rot_lds_bytes(cplx, n);
     const size_t lds2 = jacobi_vec_lds_bytes(cplx, n);
-    const void* fn = cplx ? (const void*)jacobi_rot_kernel<true> : (const void*)jacobi_rot_kernel<false>;
+    // one barrier per round where the double-buffered matrix fits, else blocks of the upper
+    // triangle per thread of the two-barrier kernel
+    const int npair = NN / 2, kb = cdiv(npair * (npair + 1) / 2, 1024);
+    using RotFn = void (*)(const double*, int, double*, int32_t*, double*, int32_t*);
+    const bool one = jacobi_ring1_fits(n) && jacobi_ring1_lds_bytes(cplx, n) <= 158 * 1024;
+    size_t lds = one ? jacobi_ring1_lds_bytes(cplx, n) : jacobi_rot_lds_bytes(cplx, n);
+    RotFn rot = one ? (cplx ? jacobi_ring1_kernel<true> : jacobi_ring1_kernel<false>)
+              : cplx ? (kb == 1 ? jacobi_rot_kernel<true, 1> : kb == 2 ? jacobi_rot_kernel<true, 2> : jacobi_rot_kernel<true, 3>)
+                     : (kb == 1 ? jacobi_rot_kernel<false, 1> : kb == 2 ? jacobi_rot_kernel<false, 2> : jacobi_rot_kernel<false, 3>);
     const void* fn2 = cplx ? (const void*)jacobi_vec_kernel<true> : (const void*)jacobi_vec_kernel<false>;
-    if (allow_dynamic_lds(fn, lds) != hipSuccess || allow_dynamic_lds(fn2, lds2) != hipSuccess) return OEFE_EDEVICE;
+    if (allow_dynamic_lds((const void*)rot, lds) != hipSuccess || allow_dynamic_lds(fn2, lds2) != hipSuccess)
+      return OEFE_EDEVICE;
     const dim3 g2((unsigned)cdiv(n, 4));
-    if (cplx) {
-      hipLaunchKernelGGL(jacobi_rot_kernel<true>, dim3(1), dim3(1024), lds, s, A, n, lam, rank, rec, status);
+    hipLaunchKernelGGL(rot, dim3(1), dim3(1024), lds, s, A, n, lam, rank, rec, status);
+    if (cplx)
       hipLaunchKernelGGL(jacobi_vec_kernel<true>, g2, dim3(256), lds2, s, rec, rank, n, U);
-    } else {
-      hipLaunchKernelGGL(jacobi_rot_kernel<false>, dim3(1), dim3(1024), lds, s, A, n, lam, rank, rec, status);
+    else
       hipLaunchKernelGGL(jacobi_vec_kernel<false>, g2, dim3(256), lds2, s, rec, rank, n, U);
-    }
     return check();
   }
   double* V = scratch;
