@@ -1009,8 +1009,12 @@ int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* wo
       (void)hipStreamSynchronize(s);
       return fail(OEFE_ENOTSPD, "cholgs: Gram matrix not positive definite at column " + std::to_string(st[1]));
     }
-    rc = gemm_nn(cplx, Xd, ld, L.Rinv, nv, tmp, nv, op->n_tot, nv, nv, s);
-    if (!rc) rc = copy_block(tmp, (int64_t)nv * E, Xd, ld * E, op->n_tot, nv * E, s);
+    if (rowmul_on_mfma(cplx, nv)) {
+      rc = rowmul_inplace(Xd, ld, op->n_tot, nv, L.Rinv, s);
+    } else {
+      rc = gemm_nn(cplx, Xd, ld, L.Rinv, nv, tmp, nv, op->n_tot, nv, nv, s);
+      if (!rc) rc = copy_block(tmp, (int64_t)nv * E, Xd, ld * E, op->n_tot, nv * E, s);
+    }
     if (rc) return fail(rc, "cholgs: kernel launch failed");
     if (it == 1) break;  // repeated once at most
     // orthogonality check on Q^* Q
@@ -1048,9 +1052,13 @@ int rayleigh_ritz(oefe_op op, oefe_prec prec, void* Q, int64_t ld, int32_t nv, d
   rc = gram(cplx, Qd, ld, nv, W, nv, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
   if (!rc) rc = hermitian_part(cplx, L.G, nv, s);
   if (!rc) rc = jacobi_eig(cplx, L.G, nv, eigvals, L.U, L.jscr, L.status, s);
-  // Q <- Q U  (through the packed buffer)
-  if (!rc) rc = gemm_nn(cplx, Qd, ld, L.U, nv, W, nv, op->n_tot, nv, nv, s);
-  if (!rc) rc = copy_block(W, (int64_t)nv * (cplx ? 2 : 1), Qd, ld * (cplx ? 2 : 1), op->n_tot, nv * (cplx ? 2 : 1), s);
+  // Q <- Q U  (in place on the matrix cores, else through the packed buffer)
+  if (!rc && rowmul_on_mfma(cplx, nv)) {
+    rc = rowmul_inplace(Qd, ld, op->n_tot, nv, L.U, s);
+  } else if (!rc) {
+    rc = gemm_nn(cplx, Qd, ld, L.U, nv, W, nv, op->n_tot, nv, nv, s);
+    if (!rc) rc = copy_block(W, (int64_t)nv * (cplx ? 2 : 1), Qd, ld * (cplx ? 2 : 1), op->n_tot, nv * (cplx ? 2 : 1), s);
+  }
   if (rc) return fail(rc, "rayleigh_ritz: kernel launch failed");
   return OEFE_OK;
 }

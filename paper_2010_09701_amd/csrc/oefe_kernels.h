@@ -69,6 +69,9 @@ size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n);
 // C = A * B, A [n x k] (lda), B [k x m] (ldb, small), C [n x m] (ldc)
 int gemm_nn(bool cplx, const double* A, int64_t lda, const double* B, int ldb, double* C, int64_t ldc, int64_t n,
             int k, int m, hipStream_t s);
+// X <- X R in place on the matrix cores, X [n x nv] (ldx), R [nv x nv] row-major; real, nv <= 80
+bool rowmul_on_mfma(bool cplx, int nv);
+int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, hipStream_t s);
 // in-place Cholesky of Jacobi-scaled Hermitian G (n x n): writes Rinv = (D^-1 L)^-* ... see linalg source
 int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s);
 // Hermitian eigensolver (cyclic Jacobi, one workgroup): A overwritten; lam ascending, U columns.

@@ -269,6 +269,83 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const double* __restrict__
     }
 }
 
+// ---- X <- X R in place on the matrix cores (real, X [n x nv] with nv <= 80, R [nv x nv]).
+// Row-local: each wave owns 16 * RB rows and accumulates all nv output columns (NBJ blocks
+// of 16) over the k-steps of 4; every k-step of its rows is read before the wave stores, so
+// the result overwrites X.  R, zero-padded to a multiple of 4 rows and 16 NBJ columns, is
+// staged in LDS once per workgroup (row stride 16 NBJ + 1).  MFMA f64 16x16x4 layouts: the
+// A fragment of lane (li, lk) = (lane % 16, lane / 16) is X[row li][k lk], the B fragment
+// R[k lk][col li], and element v of the result is (row lane / 16 + 4 v, col lane % 16).
+constexpr int kRowMulRB = 2;  // 16-row blocks per wave
+
+template <int NBJ>
+__global__ __launch_bounds__(256) void rowmul_mfma_kernel(double* __restrict__ X, int64_t ldx, int64_t n, int nv,
+                                                          const double* __restrict__ R) {
+  extern __shared__ double rsm[];  // [nks * 4][16 NBJ + 1]
+  constexpr int RS = 16 * NBJ + 1;
+  const int nks = (nv + 3) / 4;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int t = threadIdx.x; t < nks * 4 * 16 * NBJ; t += 256) {
+    const int k = t / (16 * NBJ), c = t - k * (16 * NBJ);
+    rsm[k * RS + c] = (k < nv && c < nv) ? R[(int64_t)k * nv + c] : 0.0;
+  }
+  __syncthreads();
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 16 * kRowMulRB;
+  if (r0 >= n) return;
+  const double* xr[kRowMulRB];
+  double mrow[kRowMulRB];
+#pragma unroll
+  for (int b = 0; b < kRowMulRB; ++b) {
+    const int64_t r = r0 + 16 * b + li;
+    mrow[b] = r < n ? 1.0 : 0.0;
+    xr[b] = X + (r < n ? r : n - 1) * ldx;
+  }
+  dv4 acc[kRowMulRB][NBJ];
+#pragma unroll
+  for (int b = 0; b < kRowMulRB; ++b)
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) acc[b][j] = dv4{0, 0, 0, 0};
+  // A fragments of k-step s (columns past nv: clamped, zeroed)
+  auto load = [&](int s, double (&a)[kRowMulRB]) {
+    const int c = 4 * s + lk;
+    const double m = c < nv ? 1.0 : 0.0;
+    const int cc = c < nv ? c : nv - 1;
+#pragma unroll
+    for (int b = 0; b < kRowMulRB; ++b) a[b] = xr[b][cc] * (m * mrow[b]);
+  };
+  auto mma = [&](int s, const double (&a)[kRowMulRB]) {
+    const double* rk = rsm + (4 * s + lk) * RS + li;
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) {
+      const double bj = rk[16 * j];
+#pragma unroll
+      for (int b = 0; b < kRowMulRB; ++b) acc[b][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b], bj, acc[b][j], 0, 0, 0);
+    }
+  };
+  double a0[kRowMulRB], a1[kRowMulRB];
+  load(0, a0);
+  int s = 0;
+  for (; s + 1 < nks; s += 2) {
+    load(s + 1, a1);
+    mma(s, a0);
+    if (s + 2 < nks) load(s + 2, a0);
+    mma(s + 1, a1);
+  }
+  if (s < nks) mma(s, a0);
+  // every k-step of these rows has been read: store the result over them
+#pragma unroll
+  for (int b = 0; b < kRowMulRB; ++b)
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + 16 * b + lk + 4 * v;
+        const int c = 16 * j + li;
+        if (r < n && c < nv) X[r * ldx + c] = acc[b][j][v];
+      }
+}
+
 // ---- Cholesky of the Jacobi-scaled matrix and R^-1 = diag(d) L^-*  (one workgroup)
 template <bool CPLX>
 __global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int ldg, int n, double* __restrict__ Rinv,
@@ -1585,6 +1662,27 @@ int gemm_nn(bool cplx, const double* A, int64_t lda, const double* B, int ldb, d
     hipLaunchKernelGGL(gemm_nn_kernel<true>, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, n, k, m);
   else
     hipLaunchKernelGGL(gemm_nn_kernel<false>, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, n, k, m);
+  return check();
+}
+
+bool rowmul_on_mfma(bool cplx, int nv) { return !cplx && nv >= 1 && nv <= 80; }
+
+int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, hipStream_t s) {
+  if (n <= 0) return 0;
+  const int nbj = cdiv(nv, 16), nks = cdiv(nv, 4);
+  const size_t lds = (size_t)nks * 4 * (16 * nbj + 1) * sizeof(double);
+  const dim3 grid((unsigned)cdiv(n, 64 * kRowMulRB));
+  auto go = [&](auto kern) {
+    if (allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds) != hipSuccess) return;
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, ldx, n, nv, R);
+  };
+  switch (nbj) {
+    case 1: go(rowmul_mfma_kernel<1>); break;
+    case 2: go(rowmul_mfma_kernel<2>); break;
+    case 3: go(rowmul_mfma_kernel<3>); break;
+    case 4: go(rowmul_mfma_kernel<4>); break;
+    default: go(rowmul_mfma_kernel<5>); break;
+  }
   return check();
 }
 
