@@ -1346,6 +1346,110 @@ __global__ __launch_bounds__(256) void jacobi_vec_kernel(const double* __restric
   }
 }
 
+// Eigenvectors from the rotation record by the pairing ring (npair <= 64): one wave holds
+// RPW rows of V in registers by position, lane k the entries at positions 2k and 2k + 1 (the
+// pair k of the round).  A round applies the pair's 2x2 transform by position and then moves
+// the entries along the ring with two lane shifts: slot 0 of lane k comes from slot 0 of lane
+// k + 1 and slot 1 from slot 1 of lane k - 1, except slot 0 of lane 0 (stays), slot 1 of
+// lane 0 (from slot 0 of lane 1) and slot 0 of the last pair (from its own slot 1).  The
+// rotations of the next kJacobiVecAhead rounds are loaded ahead from the record.
+constexpr int kJacobiVecAhead = 4;
+constexpr int kJacobiVecRows = 1;  // rows of V per wave
+
+template <bool CPLX>
+__global__ __launch_bounds__(64) void jacobi_vec_ring_kernel(const double* __restrict__ rec,
+                                                             const int32_t* __restrict__ rank, int n,
+                                                             double* __restrict__ U) {
+  constexpr int E = CPLX ? 2 : 1, RPW = kJacobiVecRows, D = kJacobiVecAhead;
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, m = NN - 1;
+  const int k = threadIdx.x;
+  const int kc = k < npair ? k : npair - 1;
+  const int r0 = blockIdx.x * RPW;
+  const int i0 = jacobi_ring_index(2 * kc, m), i1 = jacobi_ring_index(2 * kc + 1, m);
+  // positions 2k, 2k + 1 of rows r0 .. r0 + RPW - 1, real and imaginary parts (V starts as I)
+  double v0r[RPW], v0i[RPW], v1r[RPW], v1i[RPW];
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) {
+    v0r[q] = i0 == r0 + q ? 1.0 : 0.0;
+    v1r[q] = i1 == r0 + q ? 1.0 : 0.0;
+    v0i[q] = v1i[q] = 0.0;
+  }
+  const int nround = rank[n] * m;
+  int sa = kc % m, sb = (m - kc % m) % m;  // (round + k) mod m, (round - k) mod m
+  const double* rk = rec + (size_t)kc * 4;
+  const size_t rstride = (size_t)npair * 4;
+  double bufa[D][4], bufb[D][4];
+  auto fetch = [&](int t0, double (&bf)[D][4]) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int t = min(t0 + d, max(nround - 1, 0));
+      const double* R = rk + (size_t)t * rstride;
+      // real rotations have ei = 0: no load is issued for it (a loaded, unused register
+      // would be reused while its load is in flight)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bf[d][e] = (CPLX || e < 3) ? R[e] : 0.0;
+    }
+  };
+  // rounds tb .. tb + D - 1 (those below nround) with the rotations in bf
+  auto run = [&](int tb, const double (&bf)[D][4]) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (tb + d < nround) {
+        const double c = bf[d][0], sn = bf[d][1], er = bf[d][2], ei = bf[d][3];
+        const bool sw = kc >= 1 && sa > sb;  // position 2k holds q
+        // (p, q) columns <- (p, q) G, G = [c, s; -s conj(e), c conj(e)]; by position the rows
+        // and columns of G are swapped when position 2k holds q
+        const Z g00{c, 0.0}, g01{sn, 0.0}, g10{-sn * er, sn * ei}, g11{c * er, -c * ei};
+        const Z h00 = sw ? g11 : g00, h01 = sw ? g10 : g01, h10 = sw ? g01 : g10, h11 = sw ? g00 : g11;
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+          const Z a{v0r[q], v0i[q]}, b{v1r[q], v1i[q]};
+          const Z n0 = jz_fma<CPLX>(b, h10, jz_mul<CPLX>(a, h00));
+          const Z n1 = jz_fma<CPLX>(b, h11, jz_mul<CPLX>(a, h01));
+          v0r[q] = n0.r; v1r[q] = n1.r;
+          if constexpr (CPLX) { v0i[q] = n0.i; v1i[q] = n1.i; }
+        }
+        if (npair > 1) {
+          const int ka = k + 1, kb = k - 1 < 0 ? 0 : k - 1;
+          const bool first = k == 0, last = k == npair - 1;
+#pragma unroll
+          for (int q = 0; q < RPW; ++q) {
+            const double ar = __shfl(v0r[q], ka), br = __shfl(v1r[q], kb);
+            const double n0r = first ? v0r[q] : (last ? v1r[q] : ar), n1r = first ? ar : br;
+            v0r[q] = n0r;
+            v1r[q] = n1r;
+            if constexpr (CPLX) {
+              const double ai = __shfl(v0i[q], ka), bi = __shfl(v1i[q], kb);
+              const double n0i = first ? v0i[q] : (last ? v1i[q] : ai), n1i = first ? ai : bi;
+              v0i[q] = n0i;
+              v1i[q] = n1i;
+            }
+          }
+        }
+        sa = sa + 1 == m ? 0 : sa + 1;
+        sb = sb + 1 == m ? 0 : sb + 1;
+      }
+    }
+  };
+  if (nround > 0) fetch(0, bufa);
+  for (int t0 = 0; t0 < nround; t0 += 2 * D) {
+    fetch(t0 + D, bufb);
+    run(t0, bufa);
+    fetch(t0 + 2 * D, bufa);
+    run(t0 + D, bufb);
+  }
+  // back at the sweep-start layout: position 2k + h holds index jacobi_ring_index(2k + h)
+  if (k < npair) {
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+      const int r = r0 + q;
+      if (r >= n) break;
+      if (i0 < n) jz_store<CPLX>(U + ((int64_t)r * n + rank[i0]) * E, Z{v0r[q], v0i[q]});
+      if (i1 < n) jz_store<CPLX>(U + ((int64_t)r * n + rank[i1]) * E, Z{v1r[q], v1i[q]});
+    }
+  }
+}
+
 // ---- Cholesky of the Jacobi-scaled Gram matrix and triangular inverse in LDS (small n).
 // Same scaling, pivots and breakdown rule as chol_kernel; G is only read.
 template <bool CPLX>
@@ -1742,10 +1846,17 @@ int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scra
       return OEFE_EDEVICE;
     const dim3 g2((unsigned)cdiv(n, 4));
     hipLaunchKernelGGL(rot, dim3(1), dim3(1024), lds, s, A, n, lam, rank, rec, status);
-    if (cplx)
+    if (npair <= 64) {  // eigenvectors in registers, moved along the ring by lane shifts
+      const dim3 g3((unsigned)cdiv(n, kJacobiVecRows));
+      if (cplx)
+        hipLaunchKernelGGL(jacobi_vec_ring_kernel<true>, g3, dim3(64), 0, s, rec, rank, n, U);
+      else
+        hipLaunchKernelGGL(jacobi_vec_ring_kernel<false>, g3, dim3(64), 0, s, rec, rank, n, U);
+    } else if (cplx) {
       hipLaunchKernelGGL(jacobi_vec_kernel<true>, g2, dim3(256), lds2, s, rec, rank, n, U);
-    else
+    } else {
       hipLaunchKernelGGL(jacobi_vec_kernel<false>, g2, dim3(256), lds2, s, rec, rank, n, U);
+    }
     return check();
   }
   double* V = scratch;
