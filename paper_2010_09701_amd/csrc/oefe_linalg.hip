@@ -1450,6 +1450,106 @@ __global__ __launch_bounds__(64) void jacobi_vec_ring_kernel(const double* __res
   }
 }
 
+// ---- Inverse Cholesky factor by elimination (one workgroup, small n).  Gaussian elimination
+// without pivoting of C = [A | I], A the Jacobi-scaled Gram matrix in full storage: step k
+// subtracts (c_ik / c_kk) times row k from every row i > k over the columns k < j <= n + k
+// (the rest of row k is zero).  That leaves the pivots D = diag(c_kk) of A = L_1 D L_1^*
+// (L_1 unit lower) and L_1^-1 in the right half; the Cholesky factor is L = L_1 D^1/2, so
+// L^-1 = D^-1/2 L_1^-1.  Step k reads only column k and row k, both final after step k - 1,
+// and writes neither, so one barrier per step suffices.  Thread t keeps column k + 1 + t % n
+// of the window and the rows k + 1 + t / n + r nth / n.  Same scaling, pivots and breakdown
+// rule as chol_kernel; G is only read.
+size_t chol_elim_lds_bytes(bool cplx, int n) { return ((size_t)n * (2 * n + 1) * (cplx ? 2 : 1) + n) * sizeof(double); }
+bool chol_elim_fits(bool cplx, int n) { return n <= 512 && chol_elim_lds_bytes(cplx, n) <= 158 * 1024; }
+
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void chol_elim_kernel(const double* __restrict__ G, int ldg, int n,
+                                                         double* __restrict__ Rinv, double* __restrict__ dsc,
+                                                         int32_t* __restrict__ status) {
+  constexpr int E = CPLX ? 2 : 1;
+  extern __shared__ double sm[];
+  const int ld = 2 * n + 1;             // odd row stride
+  double* C = sm;                       // [n][ld]: [A | I]
+  double* d = C + (size_t)n * ld * E;   // [n]: Jacobi scaling
+  __shared__ int bad;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (tid == 0) bad = -1;
+  __syncthreads();
+  for (int i = tid; i < n; i += nth) {
+    const double gii = G[((int64_t)i * ldg + i) * E];
+    if (!(gii > 0.0)) atomicMax(&bad, i);
+    d[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+    dsc[i] = d[i];
+  }
+  __syncthreads();
+  if (bad >= 0) {
+    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
+    return;
+  }
+  for (int t = tid; t < n * n; t += nth) {
+    const int i = t / n, j = t - i * n;
+    const double sc = d[i] * d[j];
+    const double* g = G + ((int64_t)i * ldg + j) * E;
+    double* a = C + ((size_t)i * ld + j) * E;
+    double* mm = C + ((size_t)i * ld + n + j) * E;
+    a[0] = g[0] * sc;
+    mm[0] = i == j ? 1.0 : 0.0;
+    if (CPLX) {
+      a[1] = g[E - 1] * sc;
+      mm[1] = 0.0;
+    }
+  }
+  const int cc = tid % n, ro = tid / n, rstep = nth / n;  // threads past rstep * n idle
+  __syncthreads();
+  auto at = [&](int i, int j) { return C + ((size_t)i * ld + j) * E; };
+  for (int k = 0; k < n; ++k) {
+    // breakdown: a pivot of the unit-diagonal (Jacobi-scaled) Gram matrix at or below
+    // n * 2^-52, i.e. numerically rank deficient in float64 (every thread sees the same value)
+    const double dk = at(k, k)[0];
+    if (!(dk > n * 2.220446049250313e-16) || !isfinite(dk)) {
+      if (tid == 0) bad = k;
+      break;
+    }
+    if (ro < rstep) {
+      const double rk = 1.0 / dk;
+      const int j = k + 1 + cc;
+      const double* sk = at(k, j);
+      const Z src{sk[0], CPLX ? sk[E - 1] : 0.0};
+      for (int i = k + 1 + ro; i < n; i += rstep) {
+        const double* ci = at(i, k);
+        const Z f{ci[0] * rk, CPLX ? ci[E - 1] * rk : 0.0};
+        double* c0 = at(i, j);
+        if constexpr (!CPLX) {
+          c0[0] = fma(-f.r, src.r, c0[0]);
+        } else {
+          const Z pr = zmul(f, src);
+          c0[0] -= pr.r;
+          c0[1] -= pr.i;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (bad >= 0) {
+    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
+    return;
+  }
+  // Rinv = diag(d) L^-*, L^-1 = D^-1/2 L_1^-1: Rinv[i][j] = d_i conj(m_ji) / sqrt(c_jj), j >= i
+  for (int t = tid; t < n * n; t += nth) {
+    const int i = t / n, j = t - i * n;
+    double vr = 0.0, vi = 0.0;
+    if (j >= i) {
+      const double sc = d[i] / sqrt(at(j, j)[0]);
+      const double* mm = at(j, n + i);
+      vr = sc * mm[0];
+      if (CPLX) vi = -sc * mm[E - 1];
+    }
+    Rinv[(int64_t)t * E] = vr;
+    if (CPLX) Rinv[(int64_t)t * E + 1] = vi;
+  }
+  if (tid == 0) { status[0] = 0; status[1] = -1; }
+}
+
 // ---- Cholesky of the Jacobi-scaled Gram matrix and triangular inverse in LDS (small n).
 // Same scaling, pivots and breakdown rule as chol_kernel; G is only read.
 template <bool CPLX>
@@ -1793,6 +1893,16 @@ int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, h
 int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s) {
   // dsc stored after Rinv (caller reserves n extra doubles)
   double* dsc = Rinv + (size_t)n * n * (cplx ? 2 : 1);
+  if (chol_elim_fits(cplx, n)) {
+    const size_t lds = chol_elim_lds_bytes(cplx, n);
+    const void* fn = cplx ? (const void*)chol_elim_kernel<true> : (const void*)chol_elim_kernel<false>;
+    if (allow_dynamic_lds(fn, lds) != hipSuccess) return OEFE_EDEVICE;
+    if (cplx)
+      hipLaunchKernelGGL(chol_elim_kernel<true>, dim3(1), dim3(1024), lds, s, G, ldg, n, Rinv, dsc, status);
+    else
+      hipLaunchKernelGGL(chol_elim_kernel<false>, dim3(1), dim3(1024), lds, s, G, ldg, n, Rinv, dsc, status);
+    return check();
+  }
   const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + n) * sizeof(double);
   if (lds <= 150 * 1024) {
     const void* fn = cplx ? (const void*)chol_lds_kernel<true> : (const void*)chol_lds_kernel<false>;
