@@ -996,6 +996,28 @@ int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* wo
   // exactly the Gram matrix the (at most one) repeated pass factors.
   int rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
   if (rc) return fail(rc, "cholgs: kernel launch failed");
+  if (cholgs_device_gated(cplx, nv)) {
+    // the same two passes with one host round trip at the end: device flags decide
+    // (status[2]: pass 1 factored, status[3]: repeat wanted, status[4]: pass 2 factored)
+    int32_t* st = L.status;
+    rc = hermitian_part(cplx, L.G, nv, s);
+    if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, st, s, nullptr, st + 2);
+    if (!rc) rc = rowmul_inplace(Xd, ld, op->n_tot, nv, L.Rinv, s, st + 2);
+    if (!rc) rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
+    if (!rc) rc = max_offdiag_identity(cplx, L.G, nv, L.misc, s, st, st + 3, 1e-12);
+    if (!rc) rc = hermitian_part(cplx, L.G, nv, s, st + 3);
+    if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, st, s, st + 3, st + 4);
+    if (!rc) rc = rowmul_inplace(Xd, ld, op->n_tot, nv, L.Rinv, s, st + 4);
+    if (rc) return fail(rc, "cholgs: kernel launch failed");
+    if (dev_status) (void)hipMemcpyAsync(dev_status, st, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    int32_t h[2];
+    hipError_t he = hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return hip_fail(he, "cholgs");
+    if (h[0] != 0)
+      return fail(OEFE_ENOTSPD, "cholgs: Gram matrix not positive definite at column " + std::to_string(h[1]));
+    return OEFE_OK;
+  }
   for (int it = 0; it < 2; ++it) {
     rc = hermitian_part(cplx, L.G, nv, s);
     if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, L.status, s);

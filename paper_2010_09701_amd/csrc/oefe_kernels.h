@@ -71,17 +71,27 @@ int gemm_nn(bool cplx, const double* A, int64_t lda, const double* B, int ldb, d
             int k, int m, hipStream_t s);
 // X <- X R in place on the matrix cores, X [n x nv] (ldx), R [nv x nv] row-major; real, nv <= 80
 bool rowmul_on_mfma(bool cplx, int nv);
-int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, hipStream_t s);
+// (gate: device int; the product is skipped when it holds 0)
+int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, hipStream_t s,
+                   const int32_t* gate = nullptr);
 // in-place Cholesky of Jacobi-scaled Hermitian G (n x n): writes Rinv = (D^-1 L)^-* ... see linalg source
-int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s);
+// gate (device int, optional): skipped when it holds 0; go (device int, optional): 1 after a
+// successful factorization, else 0.  Gates need cholgs_device_gated(cplx, n).
+int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s,
+                        const int32_t* gate = nullptr, int32_t* go = nullptr);
+// CholGS of nv columns can run without host round trips: the factor inverse takes gates and
+// X R^-1 runs in place on the matrix cores
+bool cholgs_device_gated(bool cplx, int nv);
 // Hermitian eigensolver (cyclic Jacobi, one workgroup): A overwritten; lam ascending, U columns.
 int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status,
                hipStream_t s);
 size_t jacobi_scratch_bytes(bool cplx, int n);
 // max |G - I| into *err (device double)
-int max_offdiag_identity(bool cplx, const double* G, int n, double* err, hipStream_t s);
+// with repeat (device int): repeat = (status[0] == 0 && max |G - I| > tol)
+int max_offdiag_identity(bool cplx, const double* G, int n, double* err, hipStream_t s,
+                         const int32_t* status = nullptr, int32_t* repeat = nullptr, double tol = 0.0);
 // symmetrize (Hermitian part) in place
-int hermitian_part(bool cplx, double* G, int n, hipStream_t s);
+int hermitian_part(bool cplx, double* G, int n, hipStream_t s, const int32_t* gate = nullptr);
 // copies / casts between blocks [n_rows x ld] (only the first ncols real columns)
 int copy_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n_rows, int ncols, hipStream_t s);
 // out = sum_j f_j Re sum_g conj(A[g][j]) B[g][j]  (f may be null: all ones), accumulated in float64

@@ -280,7 +280,9 @@ constexpr int kRowMulRB = 2;  // 16-row blocks per wave
 
 template <int NBJ>
 __global__ __launch_bounds__(256) void rowmul_mfma_kernel(double* __restrict__ X, int64_t ldx, int64_t n, int nv,
-                                                          const double* __restrict__ R) {
+                                                          const double* __restrict__ R,
+                                                          const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;  // the device-side gate (set by an earlier kernel) says skip
   extern __shared__ double rsm[];  // [nks * 4][16 NBJ + 1]
   constexpr int RS = 16 * NBJ + 1;
   const int nks = (nv + 3) / 4;
@@ -1462,11 +1464,18 @@ __global__ __launch_bounds__(64) void jacobi_vec_ring_kernel(const double* __res
 size_t chol_elim_lds_bytes(bool cplx, int n) { return ((size_t)n * (2 * n + 1) * (cplx ? 2 : 1) + n) * sizeof(double); }
 bool chol_elim_fits(bool cplx, int n) { return n <= 512 && chol_elim_lds_bytes(cplx, n) <= 158 * 1024; }
 
+// With a gate, the kernel runs only when *gate != 0; go (optional) receives 1 after a
+// successful factorization and 0 otherwise (also when the gate skipped it).
 template <bool CPLX>
 __global__ __launch_bounds__(1024) void chol_elim_kernel(const double* __restrict__ G, int ldg, int n,
                                                          double* __restrict__ Rinv, double* __restrict__ dsc,
-                                                         int32_t* __restrict__ status) {
+                                                         int32_t* __restrict__ status, const int32_t* __restrict__ gate,
+                                                         int32_t* __restrict__ go) {
   constexpr int E = CPLX ? 2 : 1;
+  if (gate && *gate == 0) {
+    if (go && threadIdx.x == 0) *go = 0;
+    return;
+  }
   extern __shared__ double sm[];
   const int ld = 2 * n + 1;             // odd row stride
   double* C = sm;                       // [n][ld]: [A | I]
@@ -1483,7 +1492,11 @@ __global__ __launch_bounds__(1024) void chol_elim_kernel(const double* __restric
   }
   __syncthreads();
   if (bad >= 0) {
-    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
+    if (tid == 0) {
+      status[0] = OEFE_ENOTSPD;
+      status[1] = bad;
+      if (go) *go = 0;
+    }
     return;
   }
   for (int t = tid; t < n * n; t += nth) {
@@ -1531,7 +1544,11 @@ __global__ __launch_bounds__(1024) void chol_elim_kernel(const double* __restric
     __syncthreads();
   }
   if (bad >= 0) {
-    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
+    if (tid == 0) {
+      status[0] = OEFE_ENOTSPD;
+      status[1] = bad;
+      if (go) *go = 0;
+    }
     return;
   }
   // Rinv = diag(d) L^-*, L^-1 = D^-1/2 L_1^-1: Rinv[i][j] = d_i conj(m_ji) / sqrt(c_jj), j >= i
@@ -1547,7 +1564,11 @@ __global__ __launch_bounds__(1024) void chol_elim_kernel(const double* __restric
     Rinv[(int64_t)t * E] = vr;
     if (CPLX) Rinv[(int64_t)t * E + 1] = vi;
   }
-  if (tid == 0) { status[0] = 0; status[1] = -1; }
+  if (tid == 0) {
+    status[0] = 0;
+    status[1] = -1;
+    if (go) *go = 1;
+  }
 }
 
 // ---- Cholesky of the Jacobi-scaled Gram matrix and triangular inverse in LDS (small n).
@@ -1662,7 +1683,8 @@ __global__ __launch_bounds__(512) void chol_lds_kernel(const double* __restrict_
 }
 
 template <bool CPLX>
-__global__ void max_dev_identity_kernel(const double* __restrict__ G, int n, double* __restrict__ err) {
+__global__ void max_dev_identity_kernel(const double* __restrict__ G, int n, double* __restrict__ err,
+                                        const int32_t* __restrict__ status, int32_t* __restrict__ repeat, double tol) {
   constexpr int E = CPLX ? 2 : 1;
   __shared__ double red[256];
   double mx = 0;
@@ -1678,12 +1700,17 @@ __global__ void max_dev_identity_kernel(const double* __restrict__ G, int n, dou
     if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *err = red[0];
+  if (threadIdx.x == 0) {
+    *err = red[0];
+    // repeat the factorization when the last one succeeded and left |Q^* Q - I| above tol
+    if (repeat) *repeat = (status[0] == 0 && red[0] > tol) ? 1 : 0;
+  }
 }
 
 template <bool CPLX>
-__global__ void hermitian_part_kernel(double* __restrict__ G, int n) {
+__global__ void hermitian_part_kernel(double* __restrict__ G, int n, const int32_t* __restrict__ gate) {
   constexpr int E = CPLX ? 2 : 1;
+  if (gate && *gate == 0) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * n) return;
   const int i = t / n, j = t % n;
@@ -1871,14 +1898,16 @@ int gemm_nn(bool cplx, const double* A, int64_t lda, const double* B, int ldb, d
 
 bool rowmul_on_mfma(bool cplx, int nv) { return !cplx && nv >= 1 && nv <= 80; }
 
-int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, hipStream_t s) {
+bool cholgs_device_gated(bool cplx, int nv) { return rowmul_on_mfma(cplx, nv) && chol_elim_fits(cplx, nv); }
+
+int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, hipStream_t s, const int32_t* gate) {
   if (n <= 0) return 0;
   const int nbj = cdiv(nv, 16), nks = cdiv(nv, 4);
   const size_t lds = (size_t)nks * 4 * (16 * nbj + 1) * sizeof(double);
   const dim3 grid((unsigned)cdiv(n, 64 * kRowMulRB));
   auto go = [&](auto kern) {
     if (allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds) != hipSuccess) return;
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, ldx, n, nv, R);
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, ldx, n, nv, R, gate);
   };
   switch (nbj) {
     case 1: go(rowmul_mfma_kernel<1>); break;
@@ -1890,7 +1919,9 @@ int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, h
   return check();
 }
 
-int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s) {
+int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s,
+                        const int32_t* gate, int32_t* go) {
+  if ((gate || go) && !chol_elim_fits(cplx, n)) return OEFE_EUNSUPPORTED;
   // dsc stored after Rinv (caller reserves n extra doubles)
   double* dsc = Rinv + (size_t)n * n * (cplx ? 2 : 1);
   if (chol_elim_fits(cplx, n)) {
@@ -1898,9 +1929,9 @@ int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int3
     const void* fn = cplx ? (const void*)chol_elim_kernel<true> : (const void*)chol_elim_kernel<false>;
     if (allow_dynamic_lds(fn, lds) != hipSuccess) return OEFE_EDEVICE;
     if (cplx)
-      hipLaunchKernelGGL(chol_elim_kernel<true>, dim3(1), dim3(1024), lds, s, G, ldg, n, Rinv, dsc, status);
+      hipLaunchKernelGGL(chol_elim_kernel<true>, dim3(1), dim3(1024), lds, s, G, ldg, n, Rinv, dsc, status, gate, go);
     else
-      hipLaunchKernelGGL(chol_elim_kernel<false>, dim3(1), dim3(1024), lds, s, G, ldg, n, Rinv, dsc, status);
+      hipLaunchKernelGGL(chol_elim_kernel<false>, dim3(1), dim3(1024), lds, s, G, ldg, n, Rinv, dsc, status, gate, go);
     return check();
   }
   const size_t lds = ((size_t)2 * n * n * (cplx ? 2 : 1) + n) * sizeof(double);
@@ -1978,20 +2009,21 @@ int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scra
   return check();
 }
 
-int max_offdiag_identity(bool cplx, const double* G, int n, double* err, hipStream_t s) {
+int max_offdiag_identity(bool cplx, const double* G, int n, double* err, hipStream_t s, const int32_t* status,
+                         int32_t* repeat, double tol) {
   if (cplx)
-    hipLaunchKernelGGL(max_dev_identity_kernel<true>, dim3(1), dim3(256), 0, s, G, n, err);
+    hipLaunchKernelGGL(max_dev_identity_kernel<true>, dim3(1), dim3(256), 0, s, G, n, err, status, repeat, tol);
   else
-    hipLaunchKernelGGL(max_dev_identity_kernel<false>, dim3(1), dim3(256), 0, s, G, n, err);
+    hipLaunchKernelGGL(max_dev_identity_kernel<false>, dim3(1), dim3(256), 0, s, G, n, err, status, repeat, tol);
   return check();
 }
 
-int hermitian_part(bool cplx, double* G, int n, hipStream_t s) {
+int hermitian_part(bool cplx, double* G, int n, hipStream_t s, const int32_t* gate) {
   dim3 grid((unsigned)cdiv((int64_t)n * n, 256));
   if (cplx)
-    hipLaunchKernelGGL(hermitian_part_kernel<true>, grid, dim3(256), 0, s, G, n);
+    hipLaunchKernelGGL(hermitian_part_kernel<true>, grid, dim3(256), 0, s, G, n, gate);
   else
-    hipLaunchKernelGGL(hermitian_part_kernel<false>, grid, dim3(256), 0, s, G, n);
+    hipLaunchKernelGGL(hermitian_part_kernel<false>, grid, dim3(256), 0, s, G, n, gate);
   return check();
 }
 

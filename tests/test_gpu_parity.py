@@ -159,10 +159,13 @@ def test_cholgs_breakdown_is_reported(lib):
     Y = rng.standard_normal((gop.n_tot, 6))
     Y[:, 4] = Y[:, 1] + Y[:, 2]
     st = torch.zeros(2, dtype=torch.int32, device="cuda")
+    Yd = _dev(Y)
     with pytest.raises(lib.OefeError) as ei:
-        lib.cholgs(gop, _dev(Y), st)
+        lib.cholgs(gop, Yd, st)
     assert ei.value.code == -4
     assert int(st[1]) == 4
+    # the failed factorization leaves the block as it was
+    assert np.array_equal(Yd.cpu().numpy(), Y)
 
 
 def _multiplet_angles(th, Xa, Xb, tol=1e-6):
