@@ -449,13 +449,16 @@ using namespace oefe;
 
 namespace {
 
-// Side stream and events of the overlapped recurrence (created once per operator).
+// Side stream and events of the overlapped recurrence (created once per operator).  The
+// events only order kernels of the two streams on this device, so they skip the
+// system-scope cache write-back and invalidation (no host or peer reads what they guard).
 int overlap_setup(const oefe_op_s* op, Overlap* ov) {
   if (!op->side_stream) {
+    const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
     hipError_t e = hipStreamCreateWithFlags(&op->side_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_node, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_k1, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_zo, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_node, fl);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_k1, fl);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&op->ev_zo, fl);
     if (e != hipSuccess) return hip_fail(e, "overlap stream setup");
   }
   ov->side = op->side_stream;
