@@ -346,8 +346,8 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
   const int64_t e = (int64_t)cgrp * 4 + wid;
   const int j = chunk * CWc + g;
   const bool valid = (e < n_cells) && (j < ncr);
-  const int64_t ee = valid ? e : 0;
-  const int cx = (int)(ee % nc), cy = (int)((ee / nc) % nc), cz = (int)(ee / ((int64_t)nc * nc));
+  const int ee = valid ? (int)e : 0;  // n_cells < 2^31
+  const int cx = ee % nc, cy = (ee / nc) % nc, cz = ee / (nc * nc);
   // W V of the wave's cell (e is wave-uniform, ee is not: lanes past the block use cell 0):
   // loaded now, parked in LDS after the first passes, read in step 5
   constexpr int NQ3 = NP * P1;
@@ -363,25 +363,30 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
     int iz = cz * p + az;
     bool wz = iz >= n;
     if (wz) iz -= n;
+    // addresses: one 64-bit base per lane for its z-plane, then 32-bit row offsets from
+    // full-rate 24-bit products (iy n ldx + ix ldx < n^2 ldx < 2^31, checked at launch)
+    const T* __restrict__ Xz = X + (int64_t)iz * n * n * ldx + (CPLX ? (jc & ~1) : jc);
+    const unsigned ldx32 = (unsigned)ldx, ldxn = (unsigned)ldx * (unsigned)n;
 #pragma unroll
     for (int ay = 0; ay < P1; ++ay) {
       int iy = cy * p + ay;
       bool wy = iy >= n;
       if (wy) iy -= n;
+      const unsigned oy = __umul24((unsigned)iy, ldxn);
 #pragma unroll
       for (int ax = 0; ax < P1; ++ax) {
         int ix = cx * p + ax;
         bool wx = ix >= n;
         if (wx) ix -= n;
-        const int64_t g = ix + (int64_t)n * (iy + (int64_t)n * iz);
+        const unsigned off = oy + __umul24((unsigned)ix, ldx32);
         const T sc = cf.mscale * cf.om[ax] * cf.om[ay] * cf.om[az];
         // unconditional in-bounds loads (column clamped), zeroed by a multiply for lanes
         // outside the block: no branch around the load
         T val;
         if constexpr (!CPLX) {
-          val = X[g * ldx + jc];
+          val = Xz[off];
         } else {
-          const T* px = X + g * ldx + (jc & ~1);
+          const T* px = Xz + off;
           C2<T> z{px[0], px[1]};
           if (wx) z = cmul(z, C2<T>{ph.re[0], ph.im[0]});
           if (wy) z = cmul(z, C2<T>{ph.re[1], ph.im[1]});
@@ -538,16 +543,19 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
     const int S = nc * P1;
     int sz = cz * P1 + w + 1;
     if (sz >= S) sz -= S;
+    // one 64-bit base per lane for its slot plane, 32-bit offsets below S^2 ldc < 2^31
+    T* __restrict__ Ycz = Yc + (int64_t)sz * S * S * ldc + j;
+    const unsigned ldc32 = (unsigned)ldc, ldcs = (unsigned)ldc * (unsigned)S;
 #pragma unroll
     for (int ay = 0; ay < P1; ++ay) {
       int sy = cy * P1 + ay + 1;
       if (sy >= S) sy -= S;
-      const int64_t rowyz = (int64_t)S * (sy + (int64_t)S * sz);
+      const unsigned oy = __umul24((unsigned)sy, ldcs);
 #pragma unroll
       for (int ax = 0; ax < P1; ++ax) {
         int sx = cx * P1 + ax + 1;
         if (sx >= S) sx -= S;
-        Yc[(rowyz + sx) * ldc + j] = y[ay * P1 + ax];
+        Ycz[oy + __umul24((unsigned)sx, ldc32)] = y[ay * P1 + ax];
       }
     }
   }
@@ -1501,6 +1509,126 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(KBatch<T> kb, int mode,
   }
 }
 
+// The three products of small_gemm modes 1, 2 and 3 in one launch: every product is
+// (n x n) times (n x columns), so one workgroup per block of kChainCols columns computes
+//   W' = (sum of the folded tile partials) + H^oo Z^O,
+//   out^O = alpha (S W' - c x^O) - beta prev^O,
+//   Z^O of the next step = S out^O (when next),
+// with S, H^oo and the block's Z^O, W' and out^O in LDS (1024 threads: one output of a phase
+// per thread for n kChainCols <= 1024).  Sums run in the same order as in
+// small_gemm (chunk partials first, then the products in k order); the chunk partials are
+// loaded in batches of 8.
+constexpr int kChainCols = 16;
+
+template <typename T, bool CPLX>
+constexpr size_t enr_chain_lds_bytes(int n) {
+  return (2 * (size_t)n * n + 3 * (size_t)n * kChainCols) * (CPLX ? 2 : 1) * sizeof(T);
+}
+
+template <typename T, bool CPLX>
+__global__ __launch_bounds__(1024) void enr_chain_kernel(KBatch<T> kb, int64_t N, int n, int next) {
+  constexpr int E = CPLX ? 2 : 1, TC = kChainCols;
+  extern __shared__ unsigned char chain_raw[];
+  T* Ss = reinterpret_cast<T*>(chain_raw);  // [n][n] S
+  T* Hs = Ss + (size_t)n * n * E;           // [n][n] H^oo
+  T* Zs = Hs + (size_t)n * n * E;           // [n][TC] Z^O of this step
+  T* Ws = Zs + (size_t)n * TC * E;          // [n][TC] W'
+  T* Os = Ws + (size_t)n * TC * E;          // [n][TC] out^O
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int m = P.nv, ncr = P.ncr;
+  const int j0 = blockIdx.x * TC;
+  if (j0 >= m) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int t = tid; t < n * n * E; t += nth) {
+    Ss[t] = P.S[t];
+    Hs[t] = P.Hoo[t];
+  }
+  for (int t = tid; t < n * TC; t += nth) {
+    const int i = t / TC, jl = t - i * TC, j = min(j0 + jl, m - 1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) Zs[(size_t)t * E + e] = P.zo[(int64_t)i * ncr + (int64_t)j * E + e];
+  }
+  __syncthreads();
+  // sum_k A[i][k] B[k][jl] over LDS tiles, in k order
+  auto dot = [&](const T* A, const T* B, int i, int jl, T& sr, T& si) {
+    sr = 0;
+    si = 0;
+#pragma unroll 8
+    for (int k = 0; k < n; ++k) {
+      const T* a = A + ((size_t)i * n + k) * E;
+      const T* b = B + ((size_t)k * TC + jl) * E;
+      if constexpr (!CPLX) {
+        sr += a[0] * b[0];
+      } else {
+        const C2<T> q = cmul(C2<T>{a[0], a[1]}, C2<T>{b[0], b[1]});
+        sr += q.r;
+        si += q.i;
+      }
+    }
+  };
+  // W'
+  for (int t = tid; t < n * TC; t += nth) {
+    const int i = t / TC, jl = t - i * TC, j = min(j0 + jl, m - 1);
+    const T* p2 = P.part2 + (int64_t)i * P.nch * ncr + (int64_t)j * E;
+    T wr = 0, wi = 0;
+    int ch = 0;
+    for (; ch + 8 <= P.nch; ch += 8) {
+      T vr[8], vi[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        vr[q] = p2[(int64_t)(ch + q) * ncr];
+        vi[q] = CPLX ? p2[(int64_t)(ch + q) * ncr + 1] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        wr += vr[q];
+        if (CPLX) wi += vi[q];
+      }
+    }
+    for (; ch < P.nch; ++ch) {
+      wr += p2[(int64_t)ch * ncr];
+      if (CPLX) wi += p2[(int64_t)ch * ncr + 1];
+    }
+    T sr, si;
+    dot(Hs, Zs, i, jl, sr, si);
+    Ws[(size_t)t * E] = wr + sr;
+    if (CPLX) Ws[(size_t)t * E + 1] = wi + si;
+  }
+  __syncthreads();
+  // out^O
+  for (int t = tid; t < n * TC; t += nth) {
+    const int i = t / TC, jl = t - i * TC, j = j0 + jl;
+    T sr, si;
+    dot(Ss, Ws, i, jl, sr, si);
+    const int64_t ox = (N + i) * P.ldx + (int64_t)min(j, m - 1) * E, oo = (N + i) * P.ldo + (int64_t)min(j, m - 1) * E;
+    T r = P.alpha * (sr - P.c * P.x[ox]);
+    if (P.beta != T(0)) r -= P.beta * P.prev[oo];
+    T r2 = 0;
+    if (CPLX) {
+      r2 = P.alpha * (si - P.c * P.x[ox + 1]);
+      if (P.beta != T(0)) r2 -= P.beta * P.prev[oo + 1];
+    }
+    Os[(size_t)t * E] = r;
+    if (CPLX) Os[(size_t)t * E + 1] = r2;
+    if (j < m) {
+      P.out[oo] = r;
+      if (CPLX) P.out[oo + 1] = r2;
+    }
+  }
+  if (!next) return;
+  __syncthreads();
+  // Z^O of the next step
+  for (int t = tid; t < n * TC; t += nth) {
+    const int i = t / TC, jl = t - i * TC, j = j0 + jl;
+    T sr, si;
+    dot(Ss, Os, i, jl, sr, si);
+    if (j < m) {
+      P.zo[(int64_t)i * ncr + (int64_t)j * E] = sr;
+      if (CPLX) P.zo[(int64_t)i * ncr + (int64_t)j * E + 1] = si;
+    }
+  }
+}
+
 // diagonal test operator: out = alpha (lambda x - c x) - beta prev
 template <typename T>
 __global__ void diag_step_kernel(const T* __restrict__ lam, const T* __restrict__ x, const T* __restrict__ prev,
@@ -1723,9 +1851,22 @@ void launch_cell_lanes(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, hi
                      op->nc, op->p, op->n, op->n_cells, nch);
 }
 
+// The planes-in-lanes kernel forms row offsets within a z-plane of X and of the node-slot
+// grid in 32 bits from 24-bit products: n^2 ldx and S^2 ldc below 2^31 (S = nc (p+1)).
+template <typename T>
+bool lanes_offsets_fit(const oefe_op_s* op, const KBatch<T>& kb) {
+  const int64_t S = (int64_t)op->nc * op->P1, n = op->n;
+  for (int q = 0; q < kb.nk; ++q) {
+    const int64_t ldx = kb.k[q].ldx, ldc = kb.k[q].ldc;
+    if (ldx * n * n >= (int64_t(1) << 31) || ldc * S * S >= (int64_t(1) << 31)) return false;
+  }
+  return true;
+}
+
 // cw = 0: planes-in-lanes kernel; 8, 16, 32, 64: plane-per-wave kernel with cw columns per cell
 template <typename T, bool CPLX>
 void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, hipStream_t s) {
+  if (cw == 0 && !lanes_offsets_fit(op, kb)) cw = 16;
   if (cw == 0) {
     switch (op->P1) {
       case 3: launch_cell_lanes<T, 3, CPLX>(op, kb, max_ncr, s); break;
@@ -1841,12 +1982,17 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
     const int nch = reduce_chunks(op);
     hipLaunchKernelGGL((enr_reduce1_kernel<T>), dim3((unsigned)(nO * nch), (unsigned)cdiv(max_ncr, 64), nk),
                        dim3(256), 0, se, kb, nch, op->d.fn_pptr, op->d.fn_poff);
-    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 1, op->N, nO);
-    hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 2, op->N, nO);
-    if (ovl) {
-      if (!ov->last) hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 3, op->N, nO);
-      (void)hipEventRecord(ov->ev_zo, se);
+    const size_t clds = enr_chain_lds_bytes<T, CPLX>(nO);
+    if (clds <= 96 * 1024 &&
+        allow_dynamic_lds(reinterpret_cast<const void*>(&enr_chain_kernel<T, CPLX>), clds) == hipSuccess) {
+      hipLaunchKernelGGL((enr_chain_kernel<T, CPLX>), dim3((unsigned)cdiv(max_nv, kChainCols), 1, nk), dim3(1024), clds,
+                         se, kb, op->N, nO, (ovl && !ov->last) ? 1 : 0);
+    } else {
+      hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 1, op->N, nO);
+      hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 2, op->N, nO);
+      if (ovl && !ov->last) hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, se, kb, 3, op->N, nO);
     }
+    if (ovl) (void)hipEventRecord(ov->ev_zo, se);
   };
   if constexpr (!CPLX) {
     // Real operators: fused node kernel after the cell stage; the chain of step k runs on
