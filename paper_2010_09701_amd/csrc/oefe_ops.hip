@@ -1125,7 +1125,7 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   const int HS = lds_row_stride(FP);
   T* xs = reinterpret_cast<T*>(smem_raw);  // [TR][XS]: x rows of the tile (zero past N), later Z^O rows
   T* hs = xs + TR * XS;                     // [TR][HS]: the tile's block
-  int32_t* fs = reinterpret_cast<int32_t*>(hs + TR * HS);  // [FP]: enrichment function of each tile column
+  int32_t* fs = reinterpret_cast<int32_t*>(hs + __umul24(TR, HS));  // [FP]: enrichment function of each tile column
   const T* __restrict__ tv = P.tv + (int64_t)f0 * TR;  // [TR][FP]
   const T* __restrict__ zo = P.zo;                         // [n_enr][ncr]
   const T* __restrict__ x = P.x;
@@ -1173,6 +1173,12 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     z2[v] = rz == 0;
     msc[v] = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
   }
+  // element offset of each row's first slot in the node-slot grid (one 64-bit product per
+  // row); the other slots of a node lie S ldc (y) and S^2 ldc (z) further (and ldc in x)
+  const int64_t Sl = (int64_t)S * ldc, S2l = Sl * S;
+  int64_t yoff[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) yoff[v] = (bx[v] + (int64_t)S * (by[v] + (int64_t)S * bz[v])) * ldc;
 
   // ---- one batch of loads: the x tile, the first part of the H tile, the function list
   // and (real columns) the first slot pair of the gather, which lands during the
@@ -1182,14 +1188,30 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   // also hold the first gather loads) functions
   constexpr int HPT = sizeof(T) == 8 ? 12 : 8;
   const int nh = TR * FP;
+  const int hd = FP > 0 ? 256 / FP : 0, hm = FP > 0 ? 256 - hd * FP : 0;  // 256 = hd FP + hm
   T gA[4][NB], gB[4][NB];
+  // element q = threadIdx.x + 256 i of a [TR][CBW] block sits at row r_i, column c_i: advanced
+  // from (r_0, c_0) by 256 = (256 / CBW) rows + (256 % CBW) columns per step (no division)
+  constexpr int kRowStep = 256 / CBW, kColStep = 256 % CBW;
+  const int r00 = (int)threadIdx.x / CBW, c00 = (int)threadIdx.x - r00 * CBW;
+  // tile rows and columns past N / ncr are clamped for the loads (their values are not used)
+  const int rmax = N - 1 - g0, cmax = ncr - 1 - cb0;
+  const T* __restrict__ xt = x + (int64_t)g0 * ldx + cb0;  // 32-bit offsets below: r ldx + c
+  const unsigned ldx32 = (unsigned)ldx;
   {
     T xv[XPT], hv[HPT];
+    {
+      int r = r00, cl = c00;
 #pragma unroll
-    for (int i = 0; i < XPT; ++i) {
-      const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
-      const int g = min(g0 + r, N - 1), col = min(cb0 + cl, ncr - 1);
-      xv[i] = x[(int64_t)g * ldx + col];
+      for (int i = 0; i < XPT; ++i) {
+        xv[i] = xt[__umul24((unsigned)min(r, rmax), ldx32) + (unsigned)min(cl, cmax)];
+        cl += kColStep;
+        r += kRowStep;
+        if (cl >= CBW) {
+          cl -= CBW;
+          ++r;
+        }
+      }
     }
     if (FP > 0) {
 #pragma unroll
@@ -1199,29 +1221,41 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     if constexpr (kEarly) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = bx[v] + (int64_t)S * (by[v] + (int64_t)S * bz[v]);
-        const int64_t row2 = x2[v] ? row + 1 : row;
+        const T* ya = Ycl + yoff[v];
+        const T* yb = x2[v] ? ya + ldc : ya;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          gA[v][nb] = Ycl[row * ldc + nb * 16];
-          gB[v][nb] = Ycl[row2 * ldc + nb * 16];
+          gA[v][nb] = ya[nb * 16];
+          gB[v][nb] = yb[nb * 16];
         }
       }
     }
     if ((int)threadIdx.x < FP) fs[threadIdx.x] = fv;
     for (int f = threadIdx.x + 256; f < FP; f += 256) fs[f] = tile_fns[f0 + f];
+    {
+      int r = r00, cl = c00;
 #pragma unroll
-    for (int i = 0; i < XPT; ++i) {
-      const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
-      xs[r * XS + cl] = g0 + r < N ? xv[i] : T(0);
+      for (int i = 0; i < XPT; ++i) {
+        xs[__umul24(r, XS) + cl] = r <= rmax ? xv[i] : T(0);
+        cl += kColStep;
+        r += kRowStep;
+        if (cl >= CBW) {
+          cl -= CBW;
+          ++r;
+        }
+      }
     }
     if (FP > 0) {
+      // [TR][FP] positions of q = threadIdx.x + 256 i, advanced by (hd rows, hm columns)
+      int r = (int)threadIdx.x / FP, cl = (int)threadIdx.x - r * FP;
 #pragma unroll
       for (int i = 0; i < HPT; ++i) {
-        const int q = threadIdx.x + 256 * i;
-        if (q < nh) {
-          const int r = q / FP;
-          hs[r * HS + (q - r * FP)] = hv[i];
+        if (r < TR) hs[__umul24(r, HS) + cl] = hv[i];
+        cl += hm;
+        r += hd;
+        if (cl >= FP) {
+          cl -= FP;
+          ++r;
         }
       }
     }
@@ -1231,12 +1265,16 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     T hv[HPT];
 #pragma unroll
     for (int i = 0; i < HPT; ++i) hv[i] = tv[min(q0 + (int)threadIdx.x + 256 * i, nh - 1)];
+    const int qq = q0 + (int)threadIdx.x;
+    int r = qq / FP, cl = qq - r * FP;
 #pragma unroll
     for (int i = 0; i < HPT; ++i) {
-      const int q = q0 + threadIdx.x + 256 * i;
-      if (q < nh) {
-        const int r = q / FP;
-        hs[r * HS + (q - r * FP)] = hv[i];
+      if (r < TR) hs[__umul24(r, HS) + cl] = hv[i];
+      cl += hm;
+      r += hd;
+      if (cl >= FP) {
+        cl -= FP;
+        ++r;
       }
     }
   }
@@ -1265,9 +1303,9 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
         const int r = ks * 4 + lk;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const T av = hs[r * HS + fcs[h]];
+          const T av = hs[__umul24(r, HS) + fcs[h]];
           const T a = foks[h] ? av : T(0);
-          pc[h] = M::op(a, xs[r * XS + cls[h]], pc[h]);
+          pc[h] = M::op(a, xs[__umul24(r, XS) + cls[h]], pc[h]);
         }
       }
 #pragma unroll
@@ -1316,15 +1354,15 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
       anyv |= need[v];
     }
     if (kk > 0 && !__any(anyv)) continue;
+    const int64_t kofs = ky * Sl + kz * S2l;  // slot offset of the pair (uniform)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int sy = by[v] + (need[v] ? ky : 0), sz = bz[v] + (need[v] ? kz : 0);
-      const int64_t row = bx[v] + (int64_t)S * (sy + (int64_t)S * sz);
-      const int64_t row2 = x2[v] ? row + 1 : row;
+      const T* ya = Ycl + yoff[v] + (need[v] ? kofs : 0);
+      const T* yb = x2[v] ? ya + ldc : ya;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const T v0 = Ycl[row * ldc + nb * 16];
-        const T v1 = Ycl[row2 * ldc + nb * 16];
+        const T v0 = ya[nb * 16];
+        const T v1 = yb[nb * 16];
         const T add = v0 + (x2[v] ? v1 : T(0));
         sum[v][nb] += need[v] ? add : T(0);
       }
@@ -1337,14 +1375,16 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   for (int v = 0; v < 4; ++v) {
     const int rl = w * 16 + M::row(lane, v);
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb][v] = msc[v] * sum[v][nb] - c * xs[rl * XS + nb * 16 + li];
+    for (int nb = 0; nb < NB; ++nb) acc[nb][v] = msc[v] * sum[v][nb] - c * xs[__umul24(rl, XS) + nb * 16 + li];
   }
   // the previous iterate is read here, before any element of out is written
   T pv[4][NB];
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+  for (int v = 0; v < 4; ++v) {
+    const T* pr = prev + (int64_t)gc[v] * ldo;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) pv[v][nb] = beta != T(0) ? prev[(int64_t)gc[v] * ldo + colc[nb]] : T(0);
+    for (int nb = 0; nb < NB; ++nb) pv[v][nb] = beta != T(0) ? pr[colc[nb]] : T(0);
+  }
 
   // Z^O rows of the tile's functions, in chunks of TR rows staged over the x tile
   const int rA = w * 16 + li;
@@ -1353,27 +1393,43 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     __syncthreads();                   // the x tile (or the previous chunk) is no longer read
     {
       T zv[XPT];
+      int fnv[XPT];
+      {
+        int r = r00, cl = c00;
 #pragma unroll
-      for (int i = 0; i < XPT; ++i) {
-        const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
-        const int fn = r < FC ? fs[fc0 + r] : -1;
-        zv[i] = zo[(int64_t)max(fn, 0) * ncr + min(cb0 + cl, ncr - 1)];
+        for (int i = 0; i < XPT; ++i) {
+          fnv[i] = r < FC ? fs[fc0 + r] : -1;
+          zv[i] = zo[__umul24((unsigned)max(fnv[i], 0), (unsigned)ncr) + (unsigned)min(cl, cmax) + (unsigned)cb0];
+          cl += kColStep;
+          r += kRowStep;
+          if (cl >= CBW) {
+            cl -= CBW;
+            ++r;
+          }
+        }
       }
+      {
+        int r = r00, cl = c00;
 #pragma unroll
-      for (int i = 0; i < XPT; ++i) {
-        const int q = threadIdx.x + 256 * i, r = q / CBW, cl = q - r * CBW;
-        const int fn = r < FC ? fs[fc0 + r] : -1;
-        xs[r * XS + cl] = fn >= 0 ? zv[i] : T(0);
+        for (int i = 0; i < XPT; ++i) {
+          xs[__umul24(r, XS) + cl] = fnv[i] >= 0 ? zv[i] : T(0);
+          cl += kColStep;
+          r += kRowStep;
+          if (cl >= CBW) {
+            cl -= CBW;
+            ++r;
+          }
+        }
       }
     }
     __syncthreads();
 #pragma unroll 2
     for (int k0 = 0; k0 < FC; k0 += 4) {
       const int f = k0 + lk;
-      const T a = hs[rA * HS + fc0 + f];
+      const T a = hs[__umul24(rA, HS) + fc0 + f];
       T b[NB];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) b[nb] = xs[f * XS + nb * 16 + li];
+      for (int nb = 0; nb < NB; ++nb) b[nb] = xs[__umul24(f, XS) + nb * 16 + li];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a, b[nb], acc[nb]);
     }
@@ -1382,11 +1438,12 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   // ---- out = alpha acc - beta prev
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
+    T* orow = out + (int64_t)gc[v] * ldo;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       T r = alpha * acc[nb][v];
       if (beta != T(0)) r -= beta * pv[v][nb];
-      if (ok[v] && colok[nb]) out[(int64_t)gc[v] * ldo + colc[nb]] = r;
+      if (ok[v] && colok[nb]) orow[colc[nb]] = r;
     }
   }
 }
