@@ -1331,14 +1331,18 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) sum[v][nb] = 0;
+  // masks as factors (the gathered values are finite): fma(v, 1, s) = v + s and fma(v, 0, s) = s
+  // exactly, so the sums equal those of the selects, without the selects
+  T m2[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) m2[v] = x2[v] ? T(1) : T(0);
   if constexpr (kEarly) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 4; ++v) {
+      const T mo = ok[v] ? T(1) : T(0);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const T add = gA[v][nb] + (x2[v] ? gB[v][nb] : T(0));
-        sum[v][nb] += ok[v] ? add : T(0);
-      }
+      for (int nb = 0; nb < NB; ++nb) sum[v][nb] = fma(fma(gB[v][nb], m2[v], gA[v][nb]), mo, sum[v][nb]);
+    }
   }
   // (ky, kz) slot pairs in a fixed order; a pair is visited when some lane of the
   // wave needs it, lanes that do not need it reload their first slot (in bounds,
@@ -1359,12 +1363,12 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     for (int v = 0; v < 4; ++v) {
       const T* ya = Ycl + yoff[v] + (need[v] ? kofs : 0);
       const T* yb = x2[v] ? ya + ldc : ya;
+      const T mn = need[v] ? T(1) : T(0);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const T v0 = ya[nb * 16];
         const T v1 = yb[nb * 16];
-        const T add = v0 + (x2[v] ? v1 : T(0));
-        sum[v][nb] += need[v] ? add : T(0);
+        sum[v][nb] = fma(fma(v1, m2[v], v0), mn, sum[v][nb]);
       }
     }
   }
