@@ -196,13 +196,16 @@ def test_rayleigh_ritz_matches_oracle(lib):
 
 @pytest.mark.parametrize("name,kvec,nv", [("single_atom", None, 1), ("single_atom", None, 2), ("single_atom", None, 11),
                                           ("p3", None, 40), ("p3", None, 80), ("p3", None, 91), ("p3", None, 100),
+                                          ("p3", None, 130),
                                           ("single_atom", (0.3, -0.2, 0.1), 21), ("p3", (-0.4, 0.25, 0.1), 33),
                                           ("p3", (-0.4, 0.25, 0.1), 80)])
 def test_rayleigh_ritz_odd_sizes_and_bloch(lib, name, kvec, nv):
     """Odd block widths (a padded round-robin schedule) and Hermitian (Bloch) projected
     matrices: Ritz values and multiplet subspaces against the oracle's eigh.  Real widths up
     to 86 and complex widths up to 68 take the one-barrier Jacobi (double-buffered matrix);
-    91 and 100 (two blocks per thread) and complex 80 take the two-barrier kernel."""
+    91 and 100 (two blocks per thread), 130 (three) and complex 80 take the two-barrier
+    kernel; 130 also takes the LDS eigenvector kernel (more than 64 pairs) and the vector-ALU
+    Gram and Ritz products (more than 80 columns)."""
     base = SYSTEMS[name]()
     sysm = base if kvec is None else base.with_k(np.array(kvec))
     op = OEFEOperator(sysm)
