@@ -1190,28 +1190,21 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   const int nh = TR * FP;
   const int hd = FP > 0 ? 256 / FP : 0, hm = FP > 0 ? 256 - hd * FP : 0;  // 256 = hd FP + hm
   T gA[4][NB], gB[4][NB];
-  // element q = threadIdx.x + 256 i of a [TR][CBW] block sits at row r_i, column c_i: advanced
-  // from (r_0, c_0) by 256 = (256 / CBW) rows + (256 % CBW) columns per step (no division)
-  constexpr int kRowStep = 256 / CBW, kColStep = 256 % CBW;
-  const int r00 = (int)threadIdx.x / CBW, c00 = (int)threadIdx.x - r00 * CBW;
+  // staging of a [TR][CBW] block: thread (tr, tc) = (threadIdx.x / 16, threadIdx.x % 16) takes
+  // rows tr + 16 i (i < TR / 16) and columns tc + 16 j (j < NB), element i NB + j
+  static_assert(TR == 64 && XPT == 4 * NB, "staging layout assumes 64-row tiles");
+  const int tr = (int)threadIdx.x >> 4, tc = (int)threadIdx.x & 15;
   // tile rows and columns past N / ncr are clamped for the loads (their values are not used)
   const int rmax = N - 1 - g0, cmax = ncr - 1 - cb0;
   const T* __restrict__ xt = x + (int64_t)g0 * ldx + cb0;  // 32-bit offsets below: r ldx + c
   const unsigned ldx32 = (unsigned)ldx;
   {
     T xv[XPT], hv[HPT];
-    {
-      int r = r00, cl = c00;
 #pragma unroll
-      for (int i = 0; i < XPT; ++i) {
-        xv[i] = xt[__umul24((unsigned)min(r, rmax), ldx32) + (unsigned)min(cl, cmax)];
-        cl += kColStep;
-        r += kRowStep;
-        if (cl >= CBW) {
-          cl -= CBW;
-          ++r;
-        }
-      }
+    for (int i = 0; i < 4; ++i) {
+      const unsigned ro = __umul24((unsigned)min(tr + 16 * i, rmax), ldx32);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) xv[i * NB + j] = xt[ro + (unsigned)min(tc + 16 * j, cmax)];
     }
     if (FP > 0) {
 #pragma unroll
@@ -1232,19 +1225,10 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     }
     if ((int)threadIdx.x < FP) fs[threadIdx.x] = fv;
     for (int f = threadIdx.x + 256; f < FP; f += 256) fs[f] = tile_fns[f0 + f];
-    {
-      int r = r00, cl = c00;
 #pragma unroll
-      for (int i = 0; i < XPT; ++i) {
-        xs[__umul24(r, XS) + cl] = r <= rmax ? xv[i] : T(0);
-        cl += kColStep;
-        r += kRowStep;
-        if (cl >= CBW) {
-          cl -= CBW;
-          ++r;
-        }
-      }
-    }
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) xs[(tr + 16 * i) * XS + tc + 16 * j] = tr + 16 * i <= rmax ? xv[i * NB + j] : T(0);
     if (FP > 0) {
       // [TR][FP] positions of q = threadIdx.x + 256 i, advanced by (hd rows, hm columns)
       int r = (int)threadIdx.x / FP, cl = (int)threadIdx.x - r * FP;
@@ -1397,34 +1381,19 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     __syncthreads();                   // the x tile (or the previous chunk) is no longer read
     {
       T zv[XPT];
-      int fnv[XPT];
-      {
-        int r = r00, cl = c00;
+      int fnv[4];
 #pragma unroll
-        for (int i = 0; i < XPT; ++i) {
-          fnv[i] = r < FC ? fs[fc0 + r] : -1;
-          zv[i] = zo[__umul24((unsigned)max(fnv[i], 0), (unsigned)ncr) + (unsigned)min(cl, cmax) + (unsigned)cb0];
-          cl += kColStep;
-          r += kRowStep;
-          if (cl >= CBW) {
-            cl -= CBW;
-            ++r;
-          }
-        }
-      }
-      {
-        int r = r00, cl = c00;
+      for (int i = 0; i < 4; ++i) {
+        const int r = tr + 16 * i;
+        fnv[i] = r < FC ? fs[fc0 + r] : -1;
+        const unsigned ro = __umul24((unsigned)max(fnv[i], 0), (unsigned)ncr) + (unsigned)cb0;
 #pragma unroll
-        for (int i = 0; i < XPT; ++i) {
-          xs[__umul24(r, XS) + cl] = fnv[i] >= 0 ? zv[i] : T(0);
-          cl += kColStep;
-          r += kRowStep;
-          if (cl >= CBW) {
-            cl -= CBW;
-            ++r;
-          }
-        }
+        for (int j = 0; j < NB; ++j) zv[i * NB + j] = zo[ro + (unsigned)min(tc + 16 * j, cmax)];
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) xs[(tr + 16 * i) * XS + tc + 16 * j] = fnv[i] >= 0 ? zv[i * NB + j] : T(0);
     }
     __syncthreads();
 #pragma unroll 2
