@@ -1188,7 +1188,6 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   // also hold the first gather loads) functions
   constexpr int HPT = sizeof(T) == 8 ? 12 : 8;
   const int nh = TR * FP;
-  const int hd = FP > 0 ? 256 / FP : 0, hm = FP > 0 ? 256 - hd * FP : 0;  // 256 = hd FP + hm
   T gA[4][NB], gB[4][NB];
   // staging of a [TR][CBW] block: thread (tr, tc) = (threadIdx.x / 16, threadIdx.x % 16) takes
   // rows tr + 16 i (i < TR / 16) and columns tc + 16 j (j < NB), element i NB + j
@@ -1198,6 +1197,28 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   const int rmax = N - 1 - g0, cmax = ncr - 1 - cb0;
   const T* __restrict__ xt = x + (int64_t)g0 * ldx + cb0;  // 32-bit offsets below: r ldx + c
   const unsigned ldx32 = (unsigned)ldx;
+  // the H tile [TR][FP] on the same map, HJ 16-column groups per batch: rows tr + 16 i,
+  // columns jc0 + tc + 16 j (past FP: clamped loads, no store)
+  constexpr int HJ = HPT / 4;
+  auto hload = [&](int jc0, T (&hv)[HPT]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ro = (int)__umul24((unsigned)(tr + 16 * i), (unsigned)FP);
+#pragma unroll
+      for (int j = 0; j < HJ; ++j) hv[i * HJ + j] = tv[min(ro + jc0 + tc + 16 * j, nh - 1)];
+    }
+  };
+  auto hstore = [&](int jc0, const T (&hv)[HPT]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ro = (int)__umul24((unsigned)(tr + 16 * i), (unsigned)HS);
+#pragma unroll
+      for (int j = 0; j < HJ; ++j) {
+        const int col = jc0 + tc + 16 * j;
+        if (col < FP) hs[ro + col] = hv[i * HJ + j];
+      }
+    }
+  };
   {
     T xv[XPT], hv[HPT];
 #pragma unroll
@@ -1206,10 +1227,7 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
 #pragma unroll
       for (int j = 0; j < NB; ++j) xv[i * NB + j] = xt[ro + (unsigned)min(tc + 16 * j, cmax)];
     }
-    if (FP > 0) {
-#pragma unroll
-      for (int i = 0; i < HPT; ++i) hv[i] = tv[min((int)threadIdx.x + 256 * i, nh - 1)];
-    }
+    if (FP > 0) hload(0, hv);
     const int32_t fv = (int)threadIdx.x < FP ? tile_fns[f0 + threadIdx.x] : 0;
     if constexpr (kEarly) {
 #pragma unroll
@@ -1229,38 +1247,13 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < NB; ++j) xs[(tr + 16 * i) * XS + tc + 16 * j] = tr + 16 * i <= rmax ? xv[i * NB + j] : T(0);
-    if (FP > 0) {
-      // [TR][FP] positions of q = threadIdx.x + 256 i, advanced by (hd rows, hm columns)
-      int r = (int)threadIdx.x / FP, cl = (int)threadIdx.x - r * FP;
-#pragma unroll
-      for (int i = 0; i < HPT; ++i) {
-        if (r < TR) hs[__umul24(r, HS) + cl] = hv[i];
-        cl += hm;
-        r += hd;
-        if (cl >= FP) {
-          cl -= FP;
-          ++r;
-        }
-      }
-    }
+    if (FP > 0) hstore(0, hv);
   }
   // the rest of the H tile
-  for (int q0 = 256 * HPT; q0 < nh; q0 += 256 * HPT) {
+  for (int jc0 = 16 * HJ; jc0 < FP; jc0 += 16 * HJ) {
     T hv[HPT];
-#pragma unroll
-    for (int i = 0; i < HPT; ++i) hv[i] = tv[min(q0 + (int)threadIdx.x + 256 * i, nh - 1)];
-    const int qq = q0 + (int)threadIdx.x;
-    int r = qq / FP, cl = qq - r * FP;
-#pragma unroll
-    for (int i = 0; i < HPT; ++i) {
-      if (r < TR) hs[__umul24(r, HS) + cl] = hv[i];
-      cl += hm;
-      r += hd;
-      if (cl >= FP) {
-        cl -= FP;
-        ++r;
-      }
-    }
+    hload(jc0, hv);
+    hstore(jc0, hv);
   }
   __syncthreads();
 
