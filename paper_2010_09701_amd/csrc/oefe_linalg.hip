@@ -293,8 +293,11 @@ __global__ __launch_bounds__(256) void rowmul_mfma_kernel(double* __restrict__ X
     rsm[k * RS + c] = (k < nv && c < nv) ? R[(int64_t)k * nv + c] : 0.0;
   }
   __syncthreads();
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * 16 * kRowMulRB;
-  if (r0 >= n) return;
+  // persistent: the workgroup keeps R in LDS and takes tasks of 64 RB rows in turn
+  const int64_t ntask = (n + 64 * kRowMulRB - 1) / (64 * kRowMulRB);
+  for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
+  const int64_t r0 = (task * 4 + w) * 16 * kRowMulRB;
+  if (r0 >= n) continue;
   const double* xr[kRowMulRB];
   double mrow[kRowMulRB];
 #pragma unroll
@@ -346,6 +349,7 @@ __global__ __launch_bounds__(256) void rowmul_mfma_kernel(double* __restrict__ X
         const int c = 16 * j + li;
         if (r < n && c < nv) X[r * ldx + c] = acc[b][j][v];
       }
+  }
 }
 
 // ---- Cholesky of the Jacobi-scaled matrix and R^-1 = diag(d) L^-*  (one workgroup)
@@ -1904,9 +1908,14 @@ int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, h
   if (n <= 0) return 0;
   const int nbj = cdiv(nv, 16), nks = cdiv(nv, 4);
   const size_t lds = (size_t)nks * 4 * (16 * nbj + 1) * sizeof(double);
-  const dim3 grid((unsigned)cdiv(n, 64 * kRowMulRB));
+  // persistent grid: as many workgroups as are resident at once
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   auto go = [&](auto kern) {
     if (allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds) != hipSuccess) return;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    const dim3 grid((unsigned)std::min<int64_t>(cdiv(n, 64 * kRowMulRB), (int64_t)per_cu * cus));
     hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, X, ldx, n, nv, R, gate);
   };
   switch (nbj) {
