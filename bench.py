@@ -331,11 +331,17 @@ def main():
     state = {"a0": a0L, "a": 0.5 * (a0L + b)}
     X = X0.clone()
 
+    st_dev = torch.zeros(2, dtype=torch.int32, device=X.device)
+    st_host = torch.zeros(2, dtype=torch.int32).pin_memory()
+
     def step():
         oefe.chebyshev_filter(gop, X, cfg.m, state["a"], b, state["a0"])
-        oefe.cholgs(gop, X)
+        oefe.cholgs_async(gop, X, st_dev)  # its status is read with the Ritz values
         th = oefe.rayleigh_ritz(gop, X)
+        st_host.copy_(st_dev, non_blocking=True)
         th_h = th.cpu().numpy()
+        if int(st_host[0]) != 0:
+            raise RuntimeError(f"cholgs failed: status {st_host.tolist()}")
         state["a0"], state["a"] = float(th_h[0]), float(th_h[-1])
         return th_h
 

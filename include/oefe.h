@@ -196,6 +196,17 @@ int lanczos_bounds(oefe_op op, int32_t k, const double* v0, double* out, void* w
 int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
            oefe_stream stream);
 
+/* The same CholGS without waiting on the stream, for pipelines that queue the
+ * next step (Rayleigh-Ritz) at once: dev_status (device int32[2], required)
+ * receives {0, -1} or {OEFE_ENOTSPD, column} in stream order, and the caller
+ * reads it after a later synchronization.  A failed factorization leaves X
+ * unchanged, as does the repeated pass when its factorization fails.  Argument
+ * errors return at once.  Blocks whose CholGS needs host decisions (complex,
+ * more than 80 columns, or a Gram matrix too large for one workgroup's LDS)
+ * take the synchronous path of cholgs, which also fills dev_status. */
+int cholgs_async(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
+                 oefe_stream stream);
+
 /* Rayleigh-Ritz (eqnProjKS in symmetric form, Q^* Q = I): W = Ht Q,
  * Hq = Q^* W (Hermitian part), Hq = U diag(theta) U^*, Q <- Q U.
  * eigvals: device float64 [nv], ascending.  prec F64 or C128. */

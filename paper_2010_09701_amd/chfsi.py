@@ -32,6 +32,9 @@ def chfsi_run(op: "oefe.Operator", X0: torch.Tensor, v0: torch.Tensor, m: int, p
     a0, a = a0L, 0.5 * (a0L + b)
     X = X0.clone()
     hist = []
+    # CholGS is queued without waiting; its status is read with the Ritz values
+    st_dev = torch.zeros(2, dtype=torch.int32, device=X.device)
+    st_host = torch.zeros(2, dtype=torch.int32).pin_memory()
     for it in range(passes):
         fp = sched[it]
         if fp == "f64":
@@ -42,8 +45,13 @@ def chfsi_run(op: "oefe.Operator", X0: torch.Tensor, v0: torch.Tensor, m: int, p
             oefe.chebyshev_filter_mixed(op, X, m, a, b, a0, bf16=True)
         else:
             raise ValueError(fp)
-        oefe.cholgs(op, X)
-        th = oefe.rayleigh_ritz(op, X).cpu().numpy()
+        oefe.cholgs_async(op, X, st_dev)
+        ev = oefe.rayleigh_ritz(op, X)
+        st_host.copy_(st_dev, non_blocking=True)
+        th = ev.cpu().numpy()
+        if int(st_host[0]) != 0:
+            raise oefe.OefeError(int(st_host[0]), "cholgs",
+                                 f"Gram matrix not positive definite at column {int(st_host[1])}")
         hist.append(dict(a=a, b=b, a0=a0, theta=th))
         if callback is not None:
             callback(it, X, th)

@@ -984,6 +984,25 @@ int oefe_autotune(int32_t nk, const oefe_op* ops, oefe_prec prec, void* const* X
   return OEFE_OK;
 }
 
+// CholGS on the matrix-core path without host round trips (the Gram matrix of X is in L.G):
+// device flags decide (status[2]: pass 1 factored, status[3]: repeat wanted, status[4]: pass 2
+// factored); {code, column} ends in L.status[0..1] and, when given, in dev_status.
+static int cholgs_gated_enqueue(oefe_op op, const Layout& L, bool cplx, double* Xd, int64_t ld, int32_t nv,
+                                int32_t* dev_status, hipStream_t s) {
+  int32_t* st = L.status;
+  int rc = hermitian_part(cplx, L.G, nv, s);
+  if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, st, s, nullptr, st + 2);
+  if (!rc) rc = rowmul_inplace(Xd, ld, op->n_tot, nv, L.Rinv, s, st + 2);
+  if (!rc) rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
+  if (!rc) rc = max_offdiag_identity(cplx, L.G, nv, L.misc, s, st, st + 3, 1e-12);
+  if (!rc) rc = hermitian_part(cplx, L.G, nv, s, st + 3);
+  if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, st, s, st + 3, st + 4);
+  if (!rc) rc = rowmul_inplace(Xd, ld, op->n_tot, nv, L.Rinv, s, st + 4);
+  if (!rc && dev_status && hipMemcpyAsync(dev_status, st, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    rc = OEFE_EDEVICE;
+  return rc;
+}
+
 int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
            oefe_stream stream) {
   if (!op || !X || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
@@ -1000,19 +1019,9 @@ int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* wo
   int rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
   if (rc) return fail(rc, "cholgs: kernel launch failed");
   if (cholgs_device_gated(cplx, nv)) {
-    // the same two passes with one host round trip at the end: device flags decide
-    // (status[2]: pass 1 factored, status[3]: repeat wanted, status[4]: pass 2 factored)
-    int32_t* st = L.status;
-    rc = hermitian_part(cplx, L.G, nv, s);
-    if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, st, s, nullptr, st + 2);
-    if (!rc) rc = rowmul_inplace(Xd, ld, op->n_tot, nv, L.Rinv, s, st + 2);
-    if (!rc) rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
-    if (!rc) rc = max_offdiag_identity(cplx, L.G, nv, L.misc, s, st, st + 3, 1e-12);
-    if (!rc) rc = hermitian_part(cplx, L.G, nv, s, st + 3);
-    if (!rc) rc = chol_factor_inverse(cplx, L.G, nv, nv, L.Rinv, st, s, st + 3, st + 4);
-    if (!rc) rc = rowmul_inplace(Xd, ld, op->n_tot, nv, L.Rinv, s, st + 4);
+    rc = cholgs_gated_enqueue(op, L, cplx, Xd, ld, nv, dev_status, s);
     if (rc) return fail(rc, "cholgs: kernel launch failed");
-    if (dev_status) (void)hipMemcpyAsync(dev_status, st, 2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    int32_t* st = L.status;
     int32_t h[2];
     hipError_t he = hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
@@ -1057,6 +1066,22 @@ int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* wo
     (void)hipMemcpyAsync(dev_status, ok, sizeof(ok), hipMemcpyHostToDevice, s);
     (void)hipStreamSynchronize(s);
   }
+  return OEFE_OK;
+}
+
+int cholgs_async(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
+                 oefe_stream stream) {
+  if (!op || !X || !work || !dev_status || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
+  if (prec != OEFE_F64 && prec != OEFE_C128) return fail(OEFE_EINVAL, "cholgs runs in float64 (F64 or C128)");
+  if (int rc = check_prec(op, prec)) return rc;
+  const bool cplx = op->cplx;
+  if (!cholgs_device_gated(cplx, nv)) return cholgs(op, prec, X, ld, nv, work, dev_status, stream);
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  double* Xd = (double*)X;
+  int rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
+  if (!rc) rc = cholgs_gated_enqueue(op, L, cplx, Xd, ld, nv, dev_status, s);
+  if (rc) return fail(rc, "cholgs_async: kernel launch failed");
   return OEFE_OK;
 }
 

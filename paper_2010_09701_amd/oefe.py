@@ -73,6 +73,7 @@ def _load():
         "oefe_autotune": ([i32, vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp], i32),
         "lanczos_bounds": ([vp, i32, vp, vp, vp, vp], i32),
         "cholgs": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
+        "cholgs_async": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "band_energy_grad": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "oefe_kernel_timer": ([vp, i32], i32),
@@ -94,7 +95,7 @@ EXPORTED = [
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
     "chebyshev_filter_mixed", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
-    "lanczos_bounds", "cholgs", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
+    "lanczos_bounds", "cholgs", "cholgs_async", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_strerror", "oefe_last_error",
 ]
 
@@ -390,6 +391,17 @@ def cholgs(op: Operator, X: torch.Tensor, status: Optional[torch.Tensor] = None)
     prec = _prec(X)
     w = op.work(prec, nv)
     _check(_lib.cholgs(op.handle, prec, _ptr(X), ld, nv, _ptr(w), _ptr(status), _stream()), "cholgs")
+    return X
+
+
+def cholgs_async(op: Operator, X: torch.Tensor, status: torch.Tensor) -> torch.Tensor:
+    """CholGS queued without waiting; status (device int32[2]) receives {code, column}."""
+    ld, nv = _block(X, op.n_tot)
+    prec = _prec(X)
+    w = op.work(prec, nv)
+    if status is None or status.device != X.device or status.dtype != torch.int32 or status.numel() < 2:
+        raise ValueError("cholgs_async needs a device int32 status tensor of 2 elements")
+    _check(_lib.cholgs_async(op.handle, prec, _ptr(X), ld, nv, _ptr(w), _ptr(status), _stream()), "cholgs_async")
     return X
 
 

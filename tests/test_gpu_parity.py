@@ -168,6 +168,39 @@ def test_cholgs_breakdown_is_reported(lib):
     assert np.array_equal(Yd.cpu().numpy(), Y)
 
 
+@pytest.mark.parametrize("nv", [6, 72, 81])
+def test_cholgs_async_matches_cholgs(lib, nv):
+    """The queued CholGS gives the synchronous one's block bit for bit (6 and 72 columns on the
+    device-gated path, 81 through the synchronous fallback) and status {0, -1}."""
+    import torch
+    sysm = SYSTEMS["diamond_nc4"]()
+    gop = lib.Operator(sysm)
+    rng = np.random.default_rng(8)
+    Y = rng.standard_normal((gop.n_tot, nv)) @ np.diag(np.logspace(0, 4, nv))
+    A, B = _dev(Y), _dev(Y)
+    lib.cholgs(gop, A)
+    st = torch.full((2,), 7, dtype=torch.int32, device="cuda")
+    lib.cholgs_async(gop, B, st)
+    torch.cuda.synchronize()
+    assert st.tolist() == [0, -1]
+    assert torch.equal(A, B)
+
+
+def test_cholgs_async_breakdown_in_status(lib):
+    import torch
+    sysm = SYSTEMS["single_atom"]()
+    gop = lib.Operator(sysm)
+    rng = np.random.default_rng(6)
+    Y = rng.standard_normal((gop.n_tot, 6))
+    Y[:, 4] = Y[:, 1] + Y[:, 2]
+    st = torch.zeros(2, dtype=torch.int32, device="cuda")
+    Yd = _dev(Y)
+    lib.cholgs_async(gop, Yd, st)  # no exception: the status carries the breakdown
+    torch.cuda.synchronize()
+    assert st.tolist() == [-4, 4]
+    assert np.array_equal(Yd.cpu().numpy(), Y)
+
+
 def _multiplet_angles(th, Xa, Xb, tol=1e-6):
     """Largest sine of principal angles between Xa and Xb restricted to each gap-separated multiplet."""
     groups = np.split(np.arange(len(th)), np.nonzero(np.diff(th) > tol * max(1, np.abs(th).max()))[0] + 1)
