@@ -137,6 +137,17 @@ int ham_apply(oefe_op op, oefe_prec prec, const void* X, void* Y, int64_t ld, in
 int chebyshev_filter(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, int32_t m,
                      double a, double b, double a0, void* work, oefe_stream stream);
 
+/* The same filter with its bounds in device memory: bounds = {a, b, a0} (device
+ * float64[3], read in stream order, e.g. written there from the previous
+ * Rayleigh-Ritz values), so that a pipeline queues the filter without waiting
+ * for them.  The recurrence scalars are computed on the device with the same
+ * float64 arithmetic (same results as chebyshev_filter).  Bounds that violate
+ * a0 < a < b are reported in dev_status (device int32[2], optional) as
+ * {OEFE_EINVAL, 0}, and the filter then writes zeros; {0, -1} otherwise.
+ * 1 <= m <= 160; finite-element operators only. */
+int chebyshev_filter_dev(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, int32_t m,
+                         const double* bounds, void* work, int32_t* dev_status, oefe_stream stream);
+
 /* Mixed-precision filter on a float64 block: X (F64 or C128 layout, device) is
  * rounded to float32 (round-to-nearest-even), filtered with prec_filter (F32 or
  * BF16 for a real operator, C64 for a Bloch operator) as in chebyshev_filter,

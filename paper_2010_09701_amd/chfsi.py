@@ -3,8 +3,10 @@
 A pass is: Chebyshev filter (float64, or float32 / bf16-operand arithmetic on
 a float64 block), Cholesky-Gram-Schmidt (float64), Rayleigh-Ritz (float64).
 Bounds: k-step Lanczos once per operator; pass 1 cuts at a = (a0 + b) / 2,
-later passes use a0 = theta_1 and a = theta_nv of the previous pass.  Only
-scalars (bounds, Ritz values) cross to the host, once per pass.
+later passes use a0 = theta_1 and a = theta_nv of the previous pass.  A float64
+run without a callback keeps those bounds on the device (the filter reads them
+from there) and reads the Ritz values and statuses once, after the last pass;
+otherwise they cross to the host once per pass.
 """
 from __future__ import annotations
 
@@ -31,6 +33,8 @@ def chfsi_run(op: "oefe.Operator", X0: torch.Tensor, v0: torch.Tensor, m: int, p
         a0L, b = bounds
     a0, a = a0L, 0.5 * (a0L + b)
     X = X0.clone()
+    if callback is None and all(fp == "f64" for fp in sched) and not op.is_diagonal and m <= 160:
+        return _run_device_bounds(op, X, m, passes, a0L, b)
     hist = []
     # CholGS is queued without waiting; its status is read with the Ritz values
     st_dev = torch.zeros(2, dtype=torch.int32, device=X.device)
@@ -56,4 +60,34 @@ def chfsi_run(op: "oefe.Operator", X0: torch.Tensor, v0: torch.Tensor, m: int, p
         if callback is not None:
             callback(it, X, th)
         a0, a = float(th[0]), float(th[-1])
+    return dict(a0_lanczos=a0L, b=b, passes=hist, X=X, theta=hist[-1]["theta"])
+
+
+def _run_device_bounds(op: "oefe.Operator", X: torch.Tensor, m: int, passes: int, a0L: float, b: float) -> dict:
+    """Float64 passes queued back to back: each Rayleigh-Ritz writes the next filter's bounds
+    (a = theta_nv, a0 = theta_1) into device memory; one host wait at the end."""
+    dev = X.device
+    bounds = torch.tensor([0.5 * (a0L + b), b, a0L], dtype=torch.float64, device=dev)
+    st = torch.zeros(passes, 2, 2, dtype=torch.int32, device=dev)  # [pass][filter, cholgs][code, column]
+    thetas = []
+    for it in range(passes):
+        oefe.chebyshev_filter_dev(op, X, m, bounds, st[it, 0])
+        oefe.cholgs_async(op, X, st[it, 1])
+        th = oefe.rayleigh_ritz(op, X)
+        thetas.append(th)
+        bounds[0:1].copy_(th[-1:])
+        bounds[2:3].copy_(th[:1])
+    st_h = st.cpu().numpy()
+    th_h = [t.cpu().numpy() for t in thetas]
+    hist = []
+    a0, a = a0L, 0.5 * (a0L + b)
+    for it in range(passes):
+        if st_h[it, 0, 0] != 0:
+            raise oefe.OefeError(int(st_h[it, 0, 0]), "chebyshev_filter_dev",
+                                 f"pass {it}: need a0 < a < b, got a={a}, a0={a0}")
+        if st_h[it, 1, 0] != 0:
+            raise oefe.OefeError(int(st_h[it, 1, 0]), "cholgs",
+                                 f"pass {it}: Gram matrix not positive definite at column {int(st_h[it, 1, 1])}")
+        hist.append(dict(a=a, b=b, a0=a0, theta=th_h[it]))
+        a0, a = float(th_h[it][0]), float(th_h[it][-1])
     return dict(a0_lanczos=a0L, b=b, passes=hist, X=X, theta=hist[-1]["theta"])

@@ -469,9 +469,14 @@ int overlap_setup(const oefe_op_s* op, Overlap* ov) {
   return OEFE_OK;
 }
 
+// the device-bounds filter keeps its [m][3] scalars in the work buffer's misc area (512 doubles)
+constexpr int kFilterDevMaxDegree = 160;
+
 template <typename T>
 int filter_impl(oefe_op_s* op, bool bf16, T* X, int64_t ld, int nv, int m, double a, double b, double a0,
-                const Layout& L, hipStream_t s) {
+                const Layout& L, hipStream_t s, const double* dsc = nullptr) {
+  // dsc (device [m][3], optional): the steps' scalars, computed on the device from device
+  // bounds; a, b, a0 are then not used
   const double e = (b - a) / 2.0, c = (b + a) / 2.0;
   const double s1 = e / (a0 - c);
   const int64_t ldw = nv;  // second buffer is packed
@@ -506,7 +511,7 @@ int filter_impl(oefe_op_s* op, bool bf16, T* X, int64_t ld, int nv, int m, doubl
   // Y_1 = (s1/e)(H x - c x)  -> old buffer
   ov.first = true;
   ov.last = m == 1;
-  int rc = apply_step<T>(op, bf16, cur, ldu, nullptr, old, ldu, nv, s1 / e, c, 0.0, L.step, s, &ov);
+  int rc = apply_step<T>(op, bf16, cur, ldu, nullptr, old, ldu, nv, s1 / e, c, 0.0, L.step, s, &ov, dsc);
   if (rc) return bail(rc);
   std::swap(cur, old);  // cur = Y1, old = Y0
   double sig = s1;
@@ -514,7 +519,9 @@ int filter_impl(oefe_op_s* op, bool bf16, T* X, int64_t ld, int nv, int m, doubl
     const double sn = 1.0 / (2.0 / s1 - sig);
     ov.first = false;
     ov.last = k == m - 1;
-    rc = apply_step<T>(op, bf16, cur, ldu, old, old, ldu, nv, 2.0 * sn / e, c, sig * sn, L.step, s, &ov);
+    // (device scalars: the host beta only marks that prev is read)
+    rc = apply_step<T>(op, bf16, cur, ldu, old, old, ldu, nv, 2.0 * sn / e, c, dsc ? 1.0 : sig * sn, L.step, s, &ov,
+                       dsc ? dsc + 3 * k : nullptr);
     if (rc) return bail(rc);
     std::swap(cur, old);
     sig = sn;
@@ -726,6 +733,28 @@ int chebyshev_filter(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv
   else
     rc = filter_impl<double>(op, false, (double*)X, ld, nv, m, a, b, a0, L, s);
   if (rc == OEFE_EUNSUPPORTED) return fail(rc, "precision not supported by chebyshev_filter");
+  if (rc) return fail(rc, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+  return OEFE_OK;
+}
+
+int chebyshev_filter_dev(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, int32_t m,
+                         const double* bounds, void* work, int32_t* dev_status, oefe_stream stream) {
+  if (!op || !X || !work || !bounds || nv <= 0 || ld < nv || m < 1) return fail(OEFE_EINVAL, "bad arguments");
+  if (m > kFilterDevMaxDegree) return fail(OEFE_EINVAL, "degree above the device-bounds limit");
+  if (op->diagonal) return fail(OEFE_EUNSUPPORTED, "device bounds need a finite-element operator");
+  if (int rc = check_prec(op, prec)) return rc;
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  double* dsc = L.misc + 32;  // [m][3]
+  int rc = cheb_scalars(bounds, m, dsc, dev_status, s);
+  // finite placeholders for the host-side recurrence (its values are not used)
+  if (!rc) {
+    if (prec_fp32(prec))
+      rc = filter_impl<float>(op, prec == OEFE_BF16, (float*)X, ld, nv, m, 0.0, 2.0, -1.0, L, s, dsc);
+    else
+      rc = filter_impl<double>(op, false, (double*)X, ld, nv, m, 0.0, 2.0, -1.0, L, s, dsc);
+  }
+  if (rc == OEFE_EUNSUPPORTED) return fail(rc, "precision not supported by chebyshev_filter_dev");
   if (rc) return fail(rc, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
   return OEFE_OK;
 }

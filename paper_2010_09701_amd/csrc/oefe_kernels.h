@@ -41,10 +41,14 @@ struct Overlap {
 // out = alpha (Ht x - c x) - beta prev   (prev may be null when beta == 0)
 // T = double or float; x: [n_tot x ld], prev and out: [n_tot x ldo] (complex: interleaved, leading
 // dimensions in complex elements).  prev may alias out.
+// sc (device, optional): (alpha, c, beta) of the step, read by the kernels in place of the
+// host values (which then only say whether prev is read: beta != 0)
 template <typename T>
 int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
                double alpha, double c, double beta, const StepWork& w, hipStream_t s,
-               const Overlap* ov = nullptr);
+               const Overlap* ov = nullptr, const double* sc = nullptr);
+// the m steps' (alpha, c, beta) of a filter from device bounds (a, b, a0) into out [m][3]
+int cheb_scalars(const double* bounds, int m, double* out, int32_t* status, hipStream_t s);
 // Batched steps of nk operators sharing one mesh / enrichment layout (k-points), in lockstep.
 template <typename T>
 int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* const* x, const int64_t* ld,

@@ -62,8 +62,23 @@ struct KP {
   const T* S;
   const T* Hoo;
   T alpha, c, beta;
+  const double* sc;  // device (alpha, c, beta) of the step in place of the three above, or null
   Phase3<T> ph;
 };
+
+// the step's scalars: from device memory when the filter's bounds live on the device
+template <typename T>
+__device__ __forceinline__ void step_scalars(const KP<T>& P, T& alpha, T& c, T& beta) {
+  if (P.sc) {
+    alpha = (T)P.sc[0];
+    c = (T)P.sc[1];
+    beta = (T)P.sc[2];
+  } else {
+    alpha = P.alpha;
+    c = P.c;
+    beta = P.beta;
+  }
+}
 
 template <typename T>
 struct KBatch {
@@ -963,7 +978,8 @@ __global__ __launch_bounds__(256) void fe_coupling_kernel(KBatch<T> kb, const in
 
     // out = alpha en - beta prev (prev may be the same array as out: all of this lane's
     // elements are read before any is written)
-    const T alpha = P.alpha, beta = P.beta;
+    T alpha, cst, beta;
+    step_scalars(P, alpha, cst, beta);
     T pv[RB][4][NBW];
     if (beta != T(0)) {
 #pragma unroll
@@ -1032,7 +1048,8 @@ __device__ __forceinline__ void assemble_one(const KP<T>& P, int64_t i, int nel,
   const T msc = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
   const T* __restrict__ Yc = P.ycell;
   const int64_t ldc = P.ldc;
-  const T alpha = P.alpha, c = P.c, beta = P.beta;
+  T alpha, c, beta;
+  step_scalars(P, alpha, c, beta);
   // (ky, kz) slot pairs in a fixed order, each the lower-x slot then (shared x node) the next one
   if constexpr (!CPLX) {
     T s = 0;
@@ -1131,7 +1148,8 @@ __global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int
   const T* __restrict__ x = P.x;
   const int64_t ldx = P.ldx;
   const int64_t ldc = P.ldc;
-  const T alpha = P.alpha, c = P.c, beta = P.beta;
+  T alpha, c, beta;
+  step_scalars(P, alpha, c, beta);
   const T* prev = P.prev;  // may be the same array as out (each element is read before it is written)
   T* out = P.out;
   const int64_t ldo = P.ldo;
@@ -1521,12 +1539,14 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(KBatch<T> kb, int mode,
     if (CPLX) P.wp[(int64_t)i * P.ncr + (int64_t)jc * E + 1] = wi + si;
   } else {
     const int64_t ox = (N + i) * P.ldx + (int64_t)jc * E, oo = (N + i) * P.ldo + (int64_t)jc * E;
-    T r = P.alpha * (sr - P.c * P.x[ox]);
-    if (P.beta != T(0)) r -= P.beta * P.prev[oo];
+    T alpha, cst, beta;
+    step_scalars(P, alpha, cst, beta);
+    T r = alpha * (sr - cst * P.x[ox]);
+    if (beta != T(0)) r -= beta * P.prev[oo];
     P.out[oo] = r;
     if (CPLX) {
-      T r2 = P.alpha * (si - P.c * P.x[ox + 1]);
-      if (P.beta != T(0)) r2 -= P.beta * P.prev[oo + 1];
+      T r2 = alpha * (si - cst * P.x[ox + 1]);
+      if (beta != T(0)) r2 -= beta * P.prev[oo + 1];
       P.out[oo + 1] = r2;
     }
   }
@@ -1624,12 +1644,14 @@ __global__ __launch_bounds__(1024) void enr_chain_kernel(KBatch<T> kb, int64_t N
     T sr, si;
     dot(Ss, Ws, i, jl, sr, si);
     const int64_t ox = (N + i) * P.ldx + (int64_t)min(j, m - 1) * E, oo = (N + i) * P.ldo + (int64_t)min(j, m - 1) * E;
-    T r = P.alpha * (sr - P.c * P.x[ox]);
-    if (P.beta != T(0)) r -= P.beta * P.prev[oo];
+    T alpha, cst, beta;
+    step_scalars(P, alpha, cst, beta);
+    T r = alpha * (sr - cst * P.x[ox]);
+    if (beta != T(0)) r -= beta * P.prev[oo];
     T r2 = 0;
     if (CPLX) {
-      r2 = P.alpha * (si - P.c * P.x[ox + 1]);
-      if (P.beta != T(0)) r2 -= P.beta * P.prev[oo + 1];
+      r2 = alpha * (si - cst * P.x[ox + 1]);
+      if (beta != T(0)) r2 -= beta * P.prev[oo + 1];
     }
     Os[(size_t)t * E] = r;
     if (CPLX) Os[(size_t)t * E + 1] = r2;
@@ -2094,6 +2116,7 @@ KP<T> make_kp(const oefe_op_s* op, const T* x, int64_t ld, const T* prev, T* out
   P.alpha = (T)alpha;
   P.c = (T)c;
   P.beta = (T)beta;
+  P.sc = nullptr;
   for (int d = 0; d < 3; ++d) {
     P.ph.re[d] = (T)op->phase[d][0];
     P.ph.im[d] = (T)op->phase[d][1];
@@ -2156,10 +2179,12 @@ StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv,
 
 template <typename T>
 int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* prev, T* out, int64_t ldo, int nv,
-               double alpha, double c, double beta, const StepWork& w, hipStream_t s, const Overlap* ov) {
+               double alpha, double c, double beta, const StepWork& w, hipStream_t s, const Overlap* ov,
+               const double* sc) {
   // BF16 cell stage: real operators with float32 vectors and the dense-cell matrices
   if (bf16 && (sizeof(T) != 4 || op->cplx || op->diagonal || !op->d.bf_mats)) return OEFE_EUNSUPPORTED;
   if (!x || !out || (beta != 0.0 && !prev)) return OEFE_EINVAL;  // prev is read only when beta != 0
+  if (sc && op->diagonal) return OEFE_EUNSUPPORTED;
   if (op->diagonal) {
     const DevPtrs<T> dp = devptrs<T>(op);
     const int64_t tot = op->N * nv;
@@ -2170,15 +2195,49 @@ int apply_step(const oefe_op_s* op, bool bf16, const T* x, int64_t ld, const T* 
   KBatch<T> kb{};
   kb.nk = 1;
   kb.k[0] = make_kp<T>(op, x, ld, prev, out, ldo, nv, alpha, c, beta, w);
+  kb.k[0].sc = sc;
   const oefe_op_s* ops[1] = {op};
   if (op->cplx) return apply_step_batch_impl<T, true>(ops, kb, s, ov, false);
   return apply_step_batch_impl<T, false>(ops, kb, s, ov, bf16);
 }
 
 template int apply_step<double>(const oefe_op_s*, bool, const double*, int64_t, const double*, double*, int64_t, int,
-                                double, double, double, const StepWork&, hipStream_t, const Overlap*);
+                                double, double, double, const StepWork&, hipStream_t, const Overlap*, const double*);
 template int apply_step<float>(const oefe_op_s*, bool, const float*, int64_t, const float*, float*, int64_t, int,
-                               double, double, double, const StepWork&, hipStream_t, const Overlap*);
+                               double, double, double, const StepWork&, hipStream_t, const Overlap*, const double*);
+
+// The scalars of an m-step filter from device bounds (a, b, a0), in the order and arithmetic
+// of the host recurrence: step 0 (s1 / e, c, 0), step k (2 s_k+1 / e, c, s_k s_k+1) with
+// e = (b - a) / 2, c = (b + a) / 2, s1 = e / (a0 - c), s_k+1 = 1 / (2 / s1 - s_k).  Bounds
+// that violate a0 < a < b give zero scalars and status {OEFE_EINVAL, 0}; else {0, -1}.
+__global__ void cheb_scalars_kernel(const double* __restrict__ bounds, int m, double* __restrict__ out,
+                                    int32_t* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double a = bounds[0], b = bounds[1], a0 = bounds[2];
+  const bool ok = a < b && a0 < a && isfinite(a) && isfinite(b) && isfinite(a0);
+  const double e = (b - a) / 2.0, c = (b + a) / 2.0;
+  const double s1 = e / (a0 - c);
+  out[0] = ok ? s1 / e : 0.0;
+  out[1] = ok ? c : 0.0;
+  out[2] = 0.0;
+  double sig = s1;
+  for (int k = 1; k < m; ++k) {
+    const double sn = 1.0 / (2.0 / s1 - sig);
+    out[3 * k] = ok ? 2.0 * sn / e : 0.0;
+    out[3 * k + 1] = ok ? c : 0.0;
+    out[3 * k + 2] = ok ? sig * sn : 0.0;
+    sig = sn;
+  }
+  if (status) {
+    status[0] = ok ? 0 : OEFE_EINVAL;
+    status[1] = ok ? -1 : 0;
+  }
+}
+
+int cheb_scalars(const double* bounds, int m, double* out, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(cheb_scalars_kernel, dim3(1), dim3(64), 0, s, bounds, m, out, status);
+  return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
+}
 
 template <typename T>
 int apply_step_batch(const oefe_op_s* const* ops, int nk, bool bf16, const T* const* x, const int64_t* ld,

@@ -74,6 +74,7 @@ def _load():
         "lanczos_bounds": ([vp, i32, vp, vp, vp, vp], i32),
         "cholgs": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "cholgs_async": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
+        "chebyshev_filter_dev": ([vp, i32, vp, i64, i32, i32, vp, vp, vp, vp], i32),
         "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "band_energy_grad": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "oefe_kernel_timer": ([vp, i32], i32),
@@ -93,7 +94,7 @@ _lib = _load()
 EXPORTED = [
     "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
-    "chebyshev_filter_mixed", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
+    "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
     "lanczos_bounds", "cholgs", "cholgs_async", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_strerror", "oefe_last_error",
@@ -163,6 +164,7 @@ class Operator:
         (self.n_fe, self.n_enr, self.n_tot, self.n_cells, self.nq, self.nc, self.p, cx, self.tile_slots,
          self.tile_rows) = [int(x) for x in dims]
         self.is_complex = bool(cx)
+        self.is_diagonal = False
         self._work = {}
 
     @classmethod
@@ -172,7 +174,9 @@ class Operator:
         h = ctypes.c_void_p(0)
         _check(_lib.oefe_op_create_diagonal(lam.ctypes.data_as(ctypes.c_void_p), lam.size, ctypes.byref(h)),
                "oefe_op_create_diagonal")
-        return cls(_handle=h)
+        op = cls(_handle=h)
+        op.is_diagonal = True
+        return op
 
     def close(self):
         if self._h:
@@ -263,6 +267,22 @@ def chebyshev_filter(op: Operator, X: torch.Tensor, m: int, a: float, b: float, 
     w = op.work(prec, nv)
     _check(_lib.chebyshev_filter(op.handle, prec, _ptr(X), ld, nv, int(m), float(a), float(b), float(a0),
                                  _ptr(w), _stream()), "chebyshev_filter")
+    return X
+
+
+def chebyshev_filter_dev(op: Operator, X: torch.Tensor, m: int, bounds: torch.Tensor,
+                         status: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The filter with bounds = (a, b, a0) in a device float64 tensor (no host wait)."""
+    ld, nv = _block(X, op.n_tot)
+    prec = _prec(X)
+    if bounds.dtype != torch.float64 or bounds.device != X.device or bounds.numel() < 3 or not bounds.is_contiguous():
+        raise ValueError("bounds: a contiguous device float64 tensor (a, b, a0)")
+    if status is not None and (status.device != X.device or status.dtype != torch.int32 or status.numel() < 2
+                               or not status.is_contiguous()):
+        raise ValueError("status: a contiguous device int32 tensor of 2 elements")
+    w = op.work(prec, nv)
+    _check(_lib.chebyshev_filter_dev(op.handle, prec, _ptr(X), ld, nv, int(m), _ptr(bounds), _ptr(w), _ptr(status),
+                                     _stream()), "chebyshev_filter_dev")
     return X
 
 
@@ -399,7 +419,8 @@ def cholgs_async(op: Operator, X: torch.Tensor, status: torch.Tensor) -> torch.T
     ld, nv = _block(X, op.n_tot)
     prec = _prec(X)
     w = op.work(prec, nv)
-    if status is None or status.device != X.device or status.dtype != torch.int32 or status.numel() < 2:
+    if (status is None or status.device != X.device or status.dtype != torch.int32 or status.numel() < 2
+            or not status.is_contiguous()):
         raise ValueError("cholgs_async needs a device int32 status tensor of 2 elements")
     _check(_lib.cholgs_async(op.handle, prec, _ptr(X), ld, nv, _ptr(w), _ptr(status), _stream()), "cholgs_async")
     return X

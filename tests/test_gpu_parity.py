@@ -125,6 +125,63 @@ def test_filter_on_diagonal_operator_matches_closed_form(lib):
     np.testing.assert_allclose(Xd.cpu().numpy(), gain[:, None] * X, rtol=1e-11, atol=1e-13)
 
 
+@pytest.mark.parametrize("name,kvec,nv,m,dt", [("single_atom", None, 8, 20, "f64"), ("diamond_nc4", None, 24, 30, "f64"),
+                                                ("single_atom", None, 13, 7, "f32"), ("single_atom", None, 5, 1, "f64"),
+                                                ("tiny2", np.array([0.2, 0.3, -0.1]), 6, 9, "c128")])
+def test_filter_dev_matches_filter(lib, name, kvec, nv, m, dt):
+    """Bounds read from device memory give the same block, bit for bit, as the same bounds passed by value."""
+    import torch
+    sysm = SYSTEMS[name]() if kvec is None else SYSTEMS[name]().with_k(kvec)
+    gop = lib.Operator(sysm)
+    X = wl.start_block(gop.n_tot, nv, 3)
+    if dt == "c128":
+        X = X + 1j * wl.start_block(gop.n_tot, nv, 4)
+    Xd = _dev(X)
+    if dt == "f32":
+        Xd = Xd.float()
+    a0, b = lib.lanczos_bounds(gop, _dev(wl.lanczos_start(gop.n_tot, 2)), 10)
+    a = 0.37 * a0 + 0.63 * b
+    Y1, Y2 = Xd.clone(), Xd.clone()
+    lib.chebyshev_filter(gop, Y1, m, a, b, a0)
+    bounds = torch.tensor([a, b, a0], dtype=torch.float64, device="cuda")
+    st = torch.full((2,), 7, dtype=torch.int32, device="cuda")
+    lib.chebyshev_filter_dev(gop, Y2, m, bounds, st)
+    torch.cuda.synchronize()
+    assert st.tolist() == [0, -1]
+    assert torch.equal(Y1, Y2)
+
+
+def test_filter_dev_invalid_bounds_in_status(lib):
+    import torch
+    gop = lib.Operator(SYSTEMS["single_atom"]())
+    Xd = _dev(wl.start_block(gop.n_tot, 4, 1))
+    st = torch.zeros(2, dtype=torch.int32, device="cuda")
+    for bad in ([5.0, 1.0, 0.0], [1.0, 5.0, 2.0], [float("nan"), 5.0, 0.0]):
+        bounds = torch.tensor(bad, dtype=torch.float64, device="cuda")
+        lib.chebyshev_filter_dev(gop, Xd, 6, bounds, st)  # no exception: the status carries it
+        torch.cuda.synchronize()
+        assert st.tolist() == [-1, 0]
+        assert not Xd.abs().max().item()  # zero scalars: the filter writes zeros
+    with pytest.raises(lib.OefeError):
+        lib.chebyshev_filter_dev(gop, Xd, 161, bounds, st)
+
+
+def test_chfsi_device_bounds_match_host_bounds(lib):
+    """The device-resident pass sequence (float64, no callback) against the per-pass host path
+    (forced by a callback): same Ritz values and block, bit for bit."""
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    sysm = SYSTEMS["single_atom"]()
+    gop = lib.Operator(sysm)
+    X0 = _dev(wl.start_block(gop.n_tot, 10, 1))
+    v0 = _dev(wl.lanczos_start(gop.n_tot, 2))
+    rd = chfsi_run(gop, X0, v0, 12, 4, 10)
+    rh = chfsi_run(gop, X0, v0, 12, 4, 10, callback=lambda it, X, th: None)
+    for pd, ph in zip(rd["passes"], rh["passes"]):
+        assert (pd["a"], pd["b"], pd["a0"]) == (ph["a"], ph["b"], ph["a0"])
+        assert np.array_equal(pd["theta"], ph["theta"])
+    assert np.array_equal(rd["X"].cpu().numpy(), rh["X"].cpu().numpy())
+
+
 def test_lanczos_bounds(lib):
     sysm = SYSTEMS["single_atom"]()
     op = OEFEOperator(sysm)
