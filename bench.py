@@ -17,8 +17,9 @@ value = N_tot * nv * m / (seconds per step), in DoF*vec*deg/s.
 Also reported: the filter-only rate, the float32-arithmetic filter's speedup
 and its Ritz-value error against the float64 path after 5 passes, the node
 kernel's memory roofline and the cell kernel's arithmetic roofline (HIP events
-bracketing each launch on the stream it runs on), and the CPU oracle on a
-bounded sample.
+bracketing each launch on the stream it runs on), the rate of the library's
+stream-copy kernel over 4 GiB (the node kernel's rate is also given as a
+fraction of it), and the CPU oracle on a bounded sample.
 
 Helpers for the committed profile summaries (they read rocprofv3 output):
     python bench.py --summarize-trace DIR           kernel-trace statistics table
@@ -58,6 +59,7 @@ CELL_FLOPS_P4 = 14500.0
 OPS_SOURCE = os.path.join(ROOT, "paper_2010_09701_amd", "csrc", "oefe_ops.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fe_node_fused_kernel_diamond8_traffic.md")
 CALIB_BYTES = 512 * 2**20
+COPY_BW_BYTES = 4 * 2**30
 
 
 def parse():
@@ -72,6 +74,7 @@ def parse():
     ap.add_argument("--no-d64", action="store_true", help="skip the diamond64 filter measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one 512 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--no-copy-bw", action="store_true", help="skip the 4 GiB copy-bandwidth measurement (also skipped with --calib-copy)")
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     return ap.parse_args()
@@ -116,6 +119,17 @@ def load_traffic():
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def copy_bandwidth(oefe, torch, reps=5):
+    """Achievable HBM rate: the library's hand-written stream-copy kernel over 4 GiB (read + write
+    bytes per second, median of `reps` copies after one warm-up, HIP events on the stream)."""
+    a = torch.empty(COPY_BW_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    gbs = oefe.copy_rate(a, c, reps)
+    del a, c
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def cpu_baseline(cfg):
@@ -442,6 +456,12 @@ def main():
         extra["kpoints"] = kpoint_bench(oefe, wl, torch, sysm, cfg.m, reps)
     if not args.no_d64 and sysm.name == "diamond8":
         extra["diamond64"] = d64_bench(oefe, wl, torch)
+    copy_gbs = None
+    if not args.no_copy_bw and not args.calib_copy:  # (the counter calibration takes the largest copy)
+        copy_gbs = copy_bandwidth(oefe, torch)
+        extra["hbm_copy_gbs"] = copy_gbs
+        log(f"stream copy of {COPY_BW_BYTES >> 30} GiB: {copy_gbs:.0f} GB/s (read + write); node kernel "
+            f"{node_gbs / copy_gbs:.2f} of it")
 
     out = {
         "metric": "ChFSI filter DoF*vec*deg/s (one float64 ChFSI pass: filter + CholGS + Rayleigh-Ritz)",
@@ -461,7 +481,8 @@ def main():
                    "global_batch": cfg.nv, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "fe_node_fused_kernel<double>", "achieved": node_gbs,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": node_gbs / PEAK_HBM_GBS,
-                     "traffic": traffic, "avg_launch_us": node_ms * 1e3, "bytes_per_launch": node_bytes},
+                     "traffic": traffic, "avg_launch_us": node_ms * 1e3, "bytes_per_launch": node_bytes,
+                     "frac_of_copy": (node_gbs / copy_gbs) if copy_gbs else None},
         "extra": extra,
     }
     if not args.no_cpu_baseline:

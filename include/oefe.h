@@ -252,6 +252,14 @@ typedef enum {
 int oefe_kernel_timer(oefe_op op, int which);
 int oefe_kernel_timer_read(oefe_op op, int64_t* launches, double* total_ms);
 
+/* Measurement aid (not part of the method): the achievable device-memory rate of
+ * this GPU, from a hand-written grid-stride copy of `bytes` bytes from src to dst
+ * (device, 16-byte aligned, non-overlapping, caller-owned; bytes a positive
+ * multiple of 16).  One untimed copy, then `reps` >= 1 copies each bracketed by
+ * HIP events on `stream`; *gbs = 2 bytes / median time (read + write, GB/s).
+ * Synchronizes the stream; allocates no device memory.  Errors: EINVAL. */
+int oefe_copy_rate(const void* src, void* dst, size_t bytes, int32_t reps, double* gbs, oefe_stream stream);
+
 const char* oefe_strerror(int code);
 const char* oefe_last_error(void);
 

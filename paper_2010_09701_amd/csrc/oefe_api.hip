@@ -449,6 +449,22 @@ using namespace oefe;
 
 namespace {
 
+// Achievable HBM rate: a grid-stride copy of 16-byte elements, four loads in flight per
+// thread before their stores, one workgroup per free slot of the device.
+__global__ __launch_bounds__(256) void stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                          int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
 // Side stream and events of the overlapped recurrence (created once per operator).  The
 // events only order kernels of the two streams on this device, so they skip the
 // system-scope cache write-back and invalidation (no host or peer reads what they guard).
@@ -584,6 +600,47 @@ int oefe_kernel_timer_read(oefe_op op, int64_t* launches, double* total_ms) {
   *launches = n;
   *total_ms = tot;
   return rc;
+}
+
+int oefe_copy_rate(const void* src, void* dst, size_t bytes, int32_t reps, double* gbs, oefe_stream stream) {
+  if (!src || !dst || !gbs || bytes == 0 || reps < 1 || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+    return fail(OEFE_EINVAL, "oefe_copy_rate: bytes and both addresses must be positive multiples of 16");
+  const uintptr_t s0 = (uintptr_t)src, d0 = (uintptr_t)dst;
+  if (s0 < d0 + bytes && d0 < s0 + bytes) return fail(OEFE_EINVAL, "oefe_copy_rate: buffers overlap");
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&stream_copy_kernel), 256, 0);
+  if (e != hipSuccess) return hip_fail(e, "oefe_copy_rate");
+  const int64_t n = (int64_t)(bytes / 16);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::max(per_cu, 1), (n + 255) / 256));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::vector<float> ms;
+  auto launch = [&] {
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(grid), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n);
+    return hipGetLastError();
+  };
+  if (e == hipSuccess) e = launch();  // warm-up
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    float t = 0.f;
+    e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    ms.push_back(t);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "oefe_copy_rate");
+  std::sort(ms.begin(), ms.end());
+  const double med = ms[ms.size() / 2];
+  *gbs = med > 0 ? 2.0 * (double)bytes / (med * 1e-3) / 1e9 : 0.0;
+  return OEFE_OK;
 }
 
 int oefe_op_create(const oefe_system_desc* desc, oefe_op* out) {

@@ -79,6 +79,7 @@ def _load():
         "band_energy_grad": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "oefe_kernel_timer": ([vp, i32], i32),
         "oefe_kernel_timer_read": ([vp, vp, vp], i32),
+        "oefe_copy_rate": ([vp, vp, ctypes.c_size_t, i32, vp, vp], i32),
         "oefe_strerror": ([i32], ctypes.c_char_p),
         "oefe_last_error": ([], ctypes.c_char_p),
     }
@@ -97,7 +98,7 @@ EXPORTED = [
     "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
     "lanczos_bounds", "cholgs", "cholgs_async", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
-    "oefe_kernel_timer_read", "oefe_strerror", "oefe_last_error",
+    "oefe_kernel_timer_read", "oefe_copy_rate", "oefe_strerror", "oefe_last_error",
 ]
 
 
@@ -284,6 +285,18 @@ def chebyshev_filter_dev(op: Operator, X: torch.Tensor, m: int, bounds: torch.Te
     _check(_lib.chebyshev_filter_dev(op.handle, prec, _ptr(X), ld, nv, int(m), _ptr(bounds), _ptr(w), _ptr(status),
                                      _stream()), "chebyshev_filter_dev")
     return X
+
+
+def copy_rate(src: torch.Tensor, dst: torch.Tensor, reps: int = 5) -> float:
+    """Device-memory rate (GB/s, read + write) of the library's stream-copy kernel from src to dst."""
+    if src.device.type != "cuda" or dst.device != src.device or not src.is_contiguous() or not dst.is_contiguous():
+        raise ValueError("copy_rate takes two contiguous tensors on one device")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    g = ctypes.c_double(0.0)
+    _check(_lib.oefe_copy_rate(_ptr(src), _ptr(dst), nbytes, int(reps), ctypes.byref(g), _stream()), "oefe_copy_rate")
+    return float(g.value)
 
 
 def chebyshev_filter_mixed(op: Operator, X: torch.Tensor, m: int, a: float, b: float, a0: float,

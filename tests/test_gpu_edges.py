@@ -108,3 +108,16 @@ def test_argument_errors(lib):
     # the device is still healthy afterwards
     Y = lib.ham_apply(gop, X + 1.0)
     assert torch.isfinite(Y).all()
+
+
+def test_copy_rate_copies_exactly(lib):
+    """The stream-copy kernel behind the bench's achievable-bandwidth figure: an exact copy
+    (ragged element count, not a multiple of the grid), a positive rate, and argument checks."""
+    import torch
+    src = torch.arange(1_000_003 * 2, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    g = lib.copy_rate(src, dst, 2)
+    torch.cuda.synchronize()
+    assert g > 0 and torch.equal(src, dst)
+    with pytest.raises(lib.OefeError):
+        lib.copy_rate(src[1:], dst[1:], 1)  # 8-byte aligned, odd size
