@@ -1841,6 +1841,20 @@ static bool gram_on_mfma(bool cplx, int na, int nb) {
   return !cplx && na >= 16 && nb >= 16 && na <= 16 * kGramNBMax && nb <= 16 * kGramNBMax;
 }
 static int gram_mfma_chunks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kGramChunks, cdiv(n, 64))); }
+// chunks of one launch: at most gram_mfma_chunks(n) (the scratch bound), and few enough that the
+// chunks x row blocks workgroups fit the device's resident slots (four per CU) in one round, so
+// no partial second round of full-length workgroups follows
+static int gram_mfma_chunks_launch(int64_t n, int nbi) {
+  static int slots[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (!slots[dev]) {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+    slots[dev] = 4 * ncu;
+  }
+  return std::max(1, std::min(gram_mfma_chunks(n), slots[dev] / std::max(1, nbi)));
+}
 
 size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n) {
   const int nch = gram_on_mfma(cplx, na, nb) ? gram_mfma_chunks(n) : gram_chunks(n);
@@ -1849,9 +1863,9 @@ size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n) {
 
 static void launch_gram_mfma(const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, int64_t n,
                              double* G, int ldg, double* scratch, hipStream_t s) {
-  const int nch = gram_mfma_chunks(n);
-  const int64_t rpc = cdiv(cdiv(n, nch), 4) * 4;
   const int nbi = (int)cdiv(na, 16), nbj = (int)cdiv(nb, 16);
+  const int nch = gram_mfma_chunks_launch(n, nbi);
+  const int64_t rpc = cdiv(cdiv(n, nch), 4) * 4;
   // one row block per workgroup (up to four workgroups per CU), column blocks rounded up to {2, 3, 5}:
   // fragments past na / nb are zero
   const int bi = 1, bj = nbj <= 2 ? 2 : (nbj <= 3 ? 3 : 5);
