@@ -854,7 +854,7 @@ __device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __re
 }
 
 template <typename T, int NBW, bool CPLX>
-__global__ __launch_bounds__(256) void fe_coupling_kernel(KBatch<T> kb, const int32_t* __restrict__ tile_fptr,
+__global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBatch<T> kb, const int32_t* __restrict__ tile_fptr,
                                                           const int32_t* __restrict__ tile_fns, int N) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
