@@ -1122,7 +1122,7 @@ constexpr size_t node_lds_bytes(int fpmax) {
 }
 
 template <typename T, int NB>
-__global__ __launch_bounds__(256, 2) void fe_node_fused_kernel(KBatch<T> kb, int nc, int p, int n, int P1,
+__global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBatch<T> kb, int nc, int p, int n, int P1,
                                                                CellCoef<T> cf, const int32_t* __restrict__ tile_fptr,
                                                                const int32_t* __restrict__ tile_fns, int N) {
   using M = Mfma<T>;
