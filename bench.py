@@ -344,7 +344,7 @@ def main():
     log(f"operator setup {time.time() - t:.1f} s, n_tot={gop.n_tot}, nv={cfg.nv}, m={cfg.m}")
     X0 = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
     v0 = torch.from_numpy(wl.lanczos_start(gop.n_tot, cfg.v0_seed)).cuda()
-    a0L, b = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k)
+    a0L, b, a1 = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k, with_cut=True)
     log(f"bounds a0={a0L:.6f} b={b:.6f}")
     X = X0.clone()
 
@@ -427,7 +427,7 @@ def main():
 
     if not args.no_fp32:
         from paper_2010_09701_amd.chfsi import chfsi_run
-        r64 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f64", bounds=(a0L, b))
+        r64 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f64", bounds=(a0L, b, a1))
         n_occ = cfg.nv - 16
         Q64 = r64["X"][:, :n_occ]
         for name, bf in (("fp32", False), ("bf16", True)):
@@ -440,7 +440,7 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             mixed_ms = e0.elapsed_time(e1) / reps
-            rm = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "bf16" if bf else "f32", bounds=(a0L, b))
+            rm = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "bf16" if bf else "f32", bounds=(a0L, b, a1))
             err = [float(np.abs(pm["theta"][:n_occ] - p64["theta"][:n_occ]).max())
                    for pm, p64 in zip(rm["passes"], r64["passes"])]
             Q = rm["X"][:, :n_occ]

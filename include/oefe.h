@@ -125,8 +125,13 @@ int oefe_op_get_enrichment(oefe_op op, double* S_host, double* Moo_eigs_host);
 /* Bytes of `work` needed by the compute calls below for a block of nv vectors. */
 size_t oefe_work_size(oefe_op op, oefe_prec prec, int32_t nv);
 
-/* Y = Ht X (X, Y device [n_tot x ld], must not overlap).  prec: F64/F32/BF16 for a
- * real operator, C128/C64 for a Bloch operator. */
+/* Y = Ht X: one application of the symmetrized operator M^-1/2 H M^-1/2 of the
+ * generalized problem H u = eps M u (eqnKSEigGenDiscrete, eqnHOEFEelelements), with
+ * the block-diagonal overlap inverse (eqnMOEFEInv: diagonal GLL mass on the FE rows,
+ * dense (M^oo)^-1/2 on the enrichment rows) applied as a scaling on both sides; same
+ * eigenvalues as the standard form of eqnKSEignStandDiscrete.  X, Y device
+ * [n_tot x ld], must not overlap.  prec: F64/F32/BF16 for a real operator, C128/C64
+ * for a Bloch operator. */
 int ham_apply(oefe_op op, oefe_prec prec, const void* X, void* Y, int64_t ld, int32_t nv,
               void* work, oefe_stream stream);
 
@@ -193,16 +198,27 @@ int oefe_autotune(int32_t nk, const oefe_op* ops, oefe_prec prec, void* const* X
                   const int32_t* nv, int32_t reps, void* work, int32_t* cw_out, int32_t* cb_out,
                   double* ms_per_step, oefe_stream stream);
 
-/* k-step Lanczos with full reorthogonalization from v0 (device, n_tot real, or
- * complex interleaved for a Bloch operator) in float64; out[0] = smallest Ritz
- * value of T_k, out[1] = largest + beta_k (an upper bound of the spectrum).
- * out is host memory; synchronizes `stream`.  1 <= k <= 64. */
-int lanczos_bounds(oefe_op op, int32_t k, const double* v0, double* out, void* work, oefe_stream stream);
+/* Spectrum bounds of the filter (Sec. IV: the filter maps the unwanted part of the
+ * spectrum, [a, b], linearly onto [-1, 1], so it needs an upper bound b of the
+ * spectrum and an estimate a0 of its lower end): k-step Lanczos with full
+ * reorthogonalization (twice) from v0 (device, n_tot real, or complex interleaved for
+ * a Bloch operator) in float64.  out (host double[3]): out[0] = a0 = smallest Ritz
+ * value of T_k, out[1] = b = largest + beta_k, out[2] = the first pass's cut
+ * a = (a0 + b) / 2 (later passes take a0 = theta_1 and a = theta_nv of the previous
+ * Rayleigh-Ritz, see rayleigh_ritz).  dev_bounds (device double[3], optional)
+ * receives {a, b, a0} in the order chebyshev_filter_dev reads.  Synchronizes
+ * `stream`.  1 <= k <= 64.  Errors: EINVAL; ENOCONV if the eigensolver of T_k hit
+ * its sweep limit. */
+int lanczos_bounds(oefe_op op, int32_t k, const double* v0, double* out, void* work, double* dev_bounds,
+                   oefe_stream stream);
 
-/* Cholesky-Gram-Schmidt (float64): G = X^* X, G = L L^* (from the Jacobi-scaled
- * G), X <- X L^-* (the Q of a QR factorization with positive diagonal R),
- * repeated once when max|Q^* Q - I| > 1e-12.  prec F64 or C128.  On breakdown
- * returns OEFE_ENOTSPD and, if dev_status (device int32[2]) is given, writes
+/* Orthonormalization of the filtered block (Sec. IV: the filtered vectors are
+ * orthonormalized before the Rayleigh-Ritz step; the paper uses a QR factorization)
+ * by Cholesky-Gram-Schmidt in float64: G = X^* X, G = L L^* (from the Jacobi-scaled
+ * G), X <- X L^-* (the Q of a QR factorization with positive diagonal R), repeated
+ * once when max|Q^* Q - I| > 1e-12.  prec F64 or C128.  On breakdown (a squared pivot
+ * of the unit-diagonal scaled Gram matrix at or below nv 2^-52) returns
+ * OEFE_ENOTSPD and, if dev_status (device int32[2]) is given, writes
  * {OEFE_ENOTSPD, column}.  Synchronizes `stream`. */
 int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
            oefe_stream stream);
@@ -219,10 +235,23 @@ int cholgs_async(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, vo
                  oefe_stream stream);
 
 /* Rayleigh-Ritz (eqnProjKS in symmetric form, Q^* Q = I): W = Ht Q,
- * Hq = Q^* W (Hermitian part), Hq = U diag(theta) U^*, Q <- Q U.
- * eigvals: device float64 [nv], ascending.  prec F64 or C128. */
+ * Hq = Q^* W (Hermitian part), Hq = U diag(theta) U^* (float64 cyclic Jacobi),
+ * Q <- Q U.  eigvals: device float64 [nv], ascending.  prec F64 or C128.
+ * Queued on `stream` without a host wait.  dev_status (device int32[2], optional)
+ * receives {0, sweeps} or {OEFE_ENOCONV, sweeps} when the eigensolver reached its
+ * sweep limit before the off-diagonal part fell to rounding (the values and vectors
+ * are then those of the last sweep).  next_bounds (device double[3], optional)
+ * receives the next pass's filter bounds in chebyshev_filter_dev's order:
+ * next_bounds[0] = a = theta_nv, next_bounds[2] = a0 = theta_1 (next_bounds[1] = b
+ * is left as it is). */
 int rayleigh_ritz(oefe_op op, oefe_prec prec, void* Q, int64_t ld, int32_t nv, double* eigvals, void* work,
-                  oefe_stream stream);
+                  int32_t* dev_status, double* next_bounds, oefe_stream stream);
+
+/* Sweep limit of the dense Hermitian eigensolver used by rayleigh_ritz and
+ * lanczos_bounds on this operator (0 restores the built-in limit of 40 sweeps for
+ * matrices held in LDS, 60 otherwise).  Lets a caller bound the eigensolver's time;
+ * reaching the limit is reported as OEFE_ENOCONV. */
+int oefe_set_eig_sweep_limit(oefe_op op, int32_t sweeps);
 
 /* Band energy E = sum_i f_i x_i^* Ht x_i (device scalar, float64) and its
  * gradients: dE_dV[e,q] = W_{e,q} sum_i f_i |psi_i(x_{e,q})|^2 (device float64

@@ -490,6 +490,21 @@ int overlap_setup(const oefe_op_s* op, Overlap* ov) {
 // the device-bounds filter keeps its [m][3] scalars in the work buffer's misc area (512 doubles)
 constexpr int kFilterDevMaxDegree = 160;
 
+// Rayleigh-Ritz epilogue: the eigensolver status {code, sweeps} and the next pass's filter
+// bounds (a = theta_nv, a0 = theta_1; b unchanged) from the ascending Ritz values.
+__global__ void rr_finish_kernel(const double* __restrict__ lam, int nv, const int32_t* __restrict__ jst,
+                                 int32_t* __restrict__ dev_status, double* __restrict__ next_bounds) {
+  if (threadIdx.x != 0) return;
+  if (dev_status) {
+    dev_status[0] = jst[0];
+    dev_status[1] = jst[1];
+  }
+  if (next_bounds) {
+    next_bounds[0] = lam[nv - 1];
+    next_bounds[2] = lam[0];
+  }
+}
+
 template <typename T>
 int filter_impl(oefe_op_s* op, bool bf16, T* X, int64_t ld, int nv, int m, double a, double b, double a0,
                 const Layout& L, hipStream_t s, const double* dsc = nullptr) {
@@ -1175,7 +1190,7 @@ int cholgs_async(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, vo
 }
 
 int rayleigh_ritz(oefe_op op, oefe_prec prec, void* Q, int64_t ld, int32_t nv, double* eigvals, void* work,
-                  oefe_stream stream) {
+                  int32_t* dev_status, double* next_bounds, oefe_stream stream) {
   if (!op || !Q || !eigvals || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
   if (prec != OEFE_F64 && prec != OEFE_C128) return fail(OEFE_EINVAL, "rayleigh_ritz runs in float64 (F64 or C128)");
   if (int rc = check_prec(op, prec)) return rc;
@@ -1190,7 +1205,7 @@ int rayleigh_ritz(oefe_op op, oefe_prec prec, void* Q, int64_t ld, int32_t nv, d
   // Hq = Q^* W (Hermitian part), Hq = U diag(theta) U^*
   rc = gram(cplx, Qd, ld, nv, W, nv, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
   if (!rc) rc = hermitian_part(cplx, L.G, nv, s);
-  if (!rc) rc = jacobi_eig(cplx, L.G, nv, eigvals, L.U, L.jscr, L.status, s);
+  if (!rc) rc = jacobi_eig(cplx, L.G, nv, eigvals, L.U, L.jscr, L.status, s, op->eig_sweeps);
   // Q <- Q U  (in place on the matrix cores, else through the packed buffer)
   if (!rc && rowmul_on_mfma(cplx, nv)) {
     rc = rowmul_inplace(Qd, ld, op->n_tot, nv, L.U, s);
@@ -1198,11 +1213,23 @@ int rayleigh_ritz(oefe_op op, oefe_prec prec, void* Q, int64_t ld, int32_t nv, d
     rc = gemm_nn(cplx, Qd, ld, L.U, nv, W, nv, op->n_tot, nv, nv, s);
     if (!rc) rc = copy_block(W, (int64_t)nv * (cplx ? 2 : 1), Qd, ld * (cplx ? 2 : 1), op->n_tot, nv * (cplx ? 2 : 1), s);
   }
+  // the eigensolver's status and the next pass's filter bounds, in stream order
+  if (!rc && (dev_status || next_bounds)) {
+    hipLaunchKernelGGL(rr_finish_kernel, dim3(1), dim3(64), 0, s, eigvals, nv, L.status, dev_status, next_bounds);
+    if (hipGetLastError() != hipSuccess) rc = OEFE_EDEVICE;
+  }
   if (rc) return fail(rc, "rayleigh_ritz: kernel launch failed");
   return OEFE_OK;
 }
 
-int lanczos_bounds(oefe_op op, int32_t k, const double* v0, double* out, void* work, oefe_stream stream) {
+int oefe_set_eig_sweep_limit(oefe_op op, int32_t sweeps) {
+  if (!op || sweeps < 0) return fail(OEFE_EINVAL, "bad arguments");
+  op->eig_sweeps = sweeps;
+  return OEFE_OK;
+}
+
+int lanczos_bounds(oefe_op op, int32_t k, const double* v0, double* out, void* work, double* dev_bounds,
+                   oefe_stream stream) {
   if (!op || !v0 || !out || !work || k < 1 || k > 64) return fail(OEFE_EINVAL, "bad arguments");
   const bool cplx = op->cplx;
   const int E = cplx ? 2 : 1;
@@ -1269,14 +1296,27 @@ int lanczos_bounds(oefe_op op, int32_t k, const double* v0, double* out, void* w
   }
   hipError_t he = hipMemcpyAsync(L.Rinv, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, s);
   if (he != hipSuccess) return hip_fail(he, "lanczos");
-  rc = jacobi_eig(cplx, L.Rinv, m, L.lam, L.U, L.jscr, L.status, s);
+  rc = jacobi_eig(cplx, L.Rinv, m, L.lam, L.U, L.jscr, L.status, s, op->eig_sweeps);
   if (rc) return fail(rc, "lanczos: eigensolver launch failed");
   std::vector<double> th(m);
+  int32_t jst[2] = {0, 0};
   he = hipMemcpyAsync(th.data(), L.lam, m * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(jst, L.status, sizeof(jst), hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return hip_fail(he, "lanczos");
+  if (jst[0] != 0)
+    return fail(OEFE_ENOCONV, "lanczos: eigensolver of T_k stopped after " + std::to_string(jst[1]) + " sweeps");
+  // a0 = smallest Ritz value of T_k, b = largest + beta_k; the first pass cuts the spectrum
+  // at the midpoint of [a0, b]
   out[0] = th[0];
   out[1] = th[m - 1] + beta[m - 1];
+  out[2] = 0.5 * (out[0] + out[1]);
+  if (dev_bounds) {
+    const double abc[3] = {out[2], out[1], out[0]};
+    he = hipMemcpyAsync(dev_bounds, abc, sizeof(abc), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return hip_fail(he, "lanczos");
+  }
   return OEFE_OK;
 }
 

@@ -142,6 +142,8 @@ struct oefe_op_s {
   oefe::DeviceArrays d;
   // launch shape overrides (autotuner): cell-kernel column width, node/partial column block
   int tune_cw = 0, tune_cb = 0;
+  // sweep limit of the dense Hermitian eigensolver (0: built-in); oefe_set_eig_sweep_limit
+  int eig_sweeps = 0;
   // instrumentation (oefe_kernel_timer)
   int timer_kind = 0;  // oefe_timer_kind
   // side stream and events of the overlapped recurrence (created on first use)

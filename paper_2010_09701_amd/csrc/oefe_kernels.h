@@ -87,8 +87,10 @@ int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int3
 // X R^-1 runs in place on the matrix cores
 bool cholgs_device_gated(bool cplx, int nv);
 // Hermitian eigensolver (cyclic Jacobi, one workgroup): A overwritten; lam ascending, U columns.
+// status: {0, sweeps} or {OEFE_ENOCONV, sweeps} when max_sweeps (0: built-in limit) ended the
+// iteration before the off-diagonal part vanished to rounding
 int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status,
-               hipStream_t s);
+               hipStream_t s, int max_sweeps = 0);
 size_t jacobi_scratch_bytes(bool cplx, int n);
 // max |G - I| into *err (device double)
 // with repeat (device int): repeat = (status[0] == 0 && max |G - I| > tol)

@@ -468,7 +468,7 @@ __global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int 
 // ---- cyclic Jacobi (round-robin parallel ordering), one workgroup
 template <bool CPLX>
 __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* __restrict__ U, double* V,
-                            double* rot, int32_t* __restrict__ status, double* red) {
+                            double* rot, int32_t* __restrict__ status, double* red, int max_sweeps) {
   constexpr int E = CPLX ? 2 : 1;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
@@ -481,7 +481,8 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
   }
   __syncthreads();
   int sweep = 0;
-  for (; sweep < 60; ++sweep) {
+  bool conv = false;
+  for (; sweep < max_sweeps; ++sweep) {
     // convergence test: off-diagonal vs diagonal (squared Frobenius)
     double off = 0, dia = 0;
     for (int t = tid; t < n * n; t += nth) {
@@ -508,7 +509,10 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
     const double dias = red[0];
     const double nrm_n = sqrt(offs + dias) / n;  // Frobenius norm / n
     __syncthreads();
-    if (offs <= 1e-30 * dias || offs == 0.0) break;
+    if (offs <= 1e-30 * dias || offs == 0.0) {
+      conv = true;
+      break;
+    }
     if (tid == 0) nrot = 0;
     __syncthreads();
     for (int st = 0; st < m; ++st) {
@@ -623,10 +627,11 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
     // a sweep that found no pair coupled above rounding: converged
     if (nrot == 0) {
       ++sweep;
+      conv = true;
       break;
     }
   }
-  if (tid == 0) { status[0] = sweep < 60 ? 0 : OEFE_ENOCONV; status[1] = sweep; }
+  if (tid == 0) { status[0] = conv ? 0 : OEFE_ENOCONV; status[1] = sweep; }
   // sort ascending by rank
   for (int i = tid; i < n; i += nth) {
     const double li = A_(i, i)[0];
@@ -646,9 +651,10 @@ __device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* 
 template <bool CPLX>
 __global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, int n, double* __restrict__ lam,
                                                       double* __restrict__ U, double* __restrict__ V,
-                                                      double* __restrict__ rot, int32_t* __restrict__ status) {
+                                                      double* __restrict__ rot, int32_t* __restrict__ status,
+                                                      int max_sweeps) {
   __shared__ double red[1024];
-  jacobi_body<CPLX>(A, n, lam, U, V, rot, status, red);
+  jacobi_body<CPLX>(A, n, lam, U, V, rot, status, red, max_sweeps);
 }
 
 // Same method for small n, in two kernels.
@@ -665,6 +671,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, in
 // the columns in rank order.  Rows of V evolve independently, so the accumulation of
 // the eigenvectors leaves the single-workgroup kernel.
 constexpr int kJacobiRecSweeps = 40;  // sweeps the rotation record holds
+constexpr int kJacobiGlobalSweeps = 60;  // sweep limit of the global-memory version
 
 __device__ __forceinline__ void jacobi_pair(int st, int k, int m, int& p, int& q) {
   if (k == 0) {
@@ -815,7 +822,7 @@ size_t jacobi_rot_lds_bytes(bool cplx, int n) {
 template <bool CPLX, int KB>
 __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restrict__ A, int n,
                                                           double* __restrict__ lam, int32_t* __restrict__ rank_out,
-                                                          double* __restrict__ rec, int32_t* __restrict__ status) {
+                                                          double* __restrict__ rec, int32_t* __restrict__ status, int max_sweeps) {
   constexpr int E = CPLX ? 2 : 1;
   extern __shared__ double sm[];
   const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
@@ -878,7 +885,7 @@ __global__ __launch_bounds__(1024) void jacobi_rot_kernel(const double* __restri
   const int opiv = at(2 * kp, 2 * kp), opiv1 = at(2 * kp + 1, 2 * kp + 1), opq = at(2 * kp, 2 * kp + 1);
   int sweep = 0, nrec = 0;
   bool conv = false;
-  for (; sweep < kJacobiRecSweeps; ++sweep) {
+  for (; sweep < min(kJacobiRecSweeps, max_sweeps); ++sweep) {
     // convergence test: squared Frobenius norms of the off-diagonal and diagonal parts
     double off = 0, dia = 0;
     for (int t = tid; t < NN * NN; t += nth) {
@@ -1032,7 +1039,7 @@ bool jacobi_ring1_fits(int n) {
 template <bool CPLX>
 __global__ __launch_bounds__(1024) void jacobi_ring1_kernel(const double* __restrict__ A, int n,
                                                             double* __restrict__ lam, int32_t* __restrict__ rank_out,
-                                                            double* __restrict__ rec, int32_t* __restrict__ status) {
+                                                            double* __restrict__ rec, int32_t* __restrict__ status, int max_sweeps) {
   constexpr int E = CPLX ? 2 : 1;
   extern __shared__ double sm[];
   const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
@@ -1121,7 +1128,7 @@ __global__ __launch_bounds__(1024) void jacobi_ring1_kernel(const double* __rest
 #pragma unroll
     for (int e = 0; e < 4; ++e) G[e] = jz_load<CPLX>(gtab(g, e) + (size_t)k * E);
   };
-  for (; sweep < kJacobiRecSweeps; ++sweep) {
+  for (; sweep < min(kJacobiRecSweeps, max_sweeps); ++sweep) {
     const double* Ac = sm + cb * msz;
     double off = 0, dia = 0;
     for (int t = tid; t < NN * NN; t += nth) {
@@ -1990,7 +1997,8 @@ size_t jacobi_scratch_bytes(bool cplx, int n) {
   return std::max(glob, recb);
 }
 
-int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s) {
+int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s,
+               int max_sweeps) {
   if (jacobi_in_lds(cplx, n)) {
     const int NN = (n % 2) ? n + 1 : n;
     double* rec = scratch;
@@ -1999,7 +2007,7 @@ int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scra
     // one barrier per round where the double-buffered matrix fits, else blocks of the upper
     // triangle per thread of the two-barrier kernel
     const int npair = NN / 2, kb = cdiv(npair * (npair + 1) / 2, 1024);
-    using RotFn = void (*)(const double*, int, double*, int32_t*, double*, int32_t*);
+    using RotFn = void (*)(const double*, int, double*, int32_t*, double*, int32_t*, int);
     const bool one = jacobi_ring1_fits(n) && jacobi_ring1_lds_bytes(cplx, n) <= 158 * 1024;
     size_t lds = one ? jacobi_ring1_lds_bytes(cplx, n) : jacobi_rot_lds_bytes(cplx, n);
     RotFn rot = one ? (cplx ? jacobi_ring1_kernel<true> : jacobi_ring1_kernel<false>)
@@ -2009,7 +2017,8 @@ int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scra
     if (allow_dynamic_lds((const void*)rot, lds) != hipSuccess || allow_dynamic_lds(fn2, lds2) != hipSuccess)
       return OEFE_EDEVICE;
     const dim3 g2((unsigned)cdiv(n, 4));
-    hipLaunchKernelGGL(rot, dim3(1), dim3(1024), lds, s, A, n, lam, rank, rec, status);
+    hipLaunchKernelGGL(rot, dim3(1), dim3(1024), lds, s, A, n, lam, rank, rec, status,
+                       max_sweeps > 0 ? max_sweeps : kJacobiRecSweeps);
     if (npair <= 64) {  // eigenvectors in registers, moved along the ring by lane shifts
       const dim3 g3((unsigned)cdiv(n, kJacobiVecRows));
       if (cplx)
@@ -2026,9 +2035,11 @@ int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scra
   double* V = scratch;
   double* rot = scratch + (size_t)n * n * (cplx ? 2 : 1);
   if (cplx)
-    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(1024), 0, s, A, n, lam, U, V, rot, status);
+    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(1024), 0, s, A, n, lam, U, V, rot, status,
+                       max_sweeps > 0 ? max_sweeps : kJacobiGlobalSweeps);
   else
-    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(1024), 0, s, A, n, lam, U, V, rot, status);
+    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(1024), 0, s, A, n, lam, U, V, rot, status,
+                       max_sweeps > 0 ? max_sweeps : kJacobiGlobalSweeps);
   return check();
 }
 

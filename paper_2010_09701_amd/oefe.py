@@ -71,11 +71,12 @@ def _load():
         "oefe_batched_work_size": ([i32, vp, i32, vp], ctypes.c_size_t),
         "oefe_set_launch_shape": ([vp, i32, i32], i32),
         "oefe_autotune": ([i32, vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp], i32),
-        "lanczos_bounds": ([vp, i32, vp, vp, vp, vp], i32),
+        "lanczos_bounds": ([vp, i32, vp, vp, vp, vp, vp], i32),
         "cholgs": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "cholgs_async": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "chebyshev_filter_dev": ([vp, i32, vp, i64, i32, i32, vp, vp, vp, vp], i32),
-        "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
+        "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp], i32),
+        "oefe_set_eig_sweep_limit": ([vp, i32], i32),
         "band_energy_grad": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "oefe_kernel_timer": ([vp, i32], i32),
         "oefe_kernel_timer_read": ([vp, vp, vp], i32),
@@ -97,7 +98,7 @@ EXPORTED = [
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
     "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
-    "lanczos_bounds", "cholgs", "cholgs_async", "rayleigh_ritz", "band_energy_grad", "oefe_kernel_timer",
+    "lanczos_bounds", "cholgs", "cholgs_async", "rayleigh_ritz", "oefe_set_eig_sweep_limit", "band_energy_grad", "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_copy_rate", "oefe_strerror", "oefe_last_error",
 ]
 
@@ -407,16 +408,29 @@ def autotune(ops, Xs, reps: int = 3, cache: Optional[str] = None, bf16: bool = F
     return dict(r, cached=False)
 
 
-def lanczos_bounds(op: Operator, v0: torch.Tensor, k: int = 10) -> Tuple[float, float]:
+def lanczos_bounds(op: Operator, v0: torch.Tensor, k: int = 10, dev_bounds: Optional[torch.Tensor] = None,
+                   with_cut: bool = False):
+    """(a0, b), or (a0, b, a) with the first pass's cut a when with_cut; dev_bounds (device float64[3],
+    optional) receives (a, b, a0) for chebyshev_filter_dev."""
     if v0.dim() != 1 or v0.shape[0] != op.n_tot:
         raise ValueError("v0 must be a vector of length n_tot")
+    if dev_bounds is not None and (dev_bounds.dtype != torch.float64 or not dev_bounds.is_cuda
+                                   or dev_bounds.numel() < 3 or not dev_bounds.is_contiguous()):
+        raise ValueError("dev_bounds: a contiguous device float64 tensor of 3 elements")
     dt = torch.complex128 if op.is_complex else torch.float64
     v0 = v0.to(dtype=dt).contiguous()
     prec = C128 if op.is_complex else F64
     w = op.work(prec, k + 2)
-    out = (ctypes.c_double * 2)()
-    _check(_lib.lanczos_bounds(op.handle, int(k), _ptr(v0), out, _ptr(w), _stream()), "lanczos_bounds")
+    out = (ctypes.c_double * 3)()
+    _check(_lib.lanczos_bounds(op.handle, int(k), _ptr(v0), out, _ptr(w), _ptr(dev_bounds), _stream()),
+           "lanczos_bounds")
+    if with_cut:
+        return float(out[0]), float(out[1]), float(out[2])
     return float(out[0]), float(out[1])
+
+
+def set_eig_sweep_limit(op: Operator, sweeps: int = 0):
+    _check(_lib.oefe_set_eig_sweep_limit(op.handle, int(sweeps)), "oefe_set_eig_sweep_limit")
 
 
 def cholgs(op: Operator, X: torch.Tensor, status: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -439,12 +453,22 @@ def cholgs_async(op: Operator, X: torch.Tensor, status: torch.Tensor) -> torch.T
     return X
 
 
-def rayleigh_ritz(op: Operator, Q: torch.Tensor) -> torch.Tensor:
+def rayleigh_ritz(op: Operator, Q: torch.Tensor, status: Optional[torch.Tensor] = None,
+                  next_bounds: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Ritz values (device float64, ascending); Q becomes the Ritz vectors.
+
+    status (device int32[2], optional) receives {code, sweeps} of the eigensolver; next_bounds
+    (device float64[3], optional) receives a = theta_nv at [0] and a0 = theta_1 at [2].
+    """
     ld, nv = _block(Q, op.n_tot)
     prec = _prec(Q)
+    for t, dt, n in ((status, torch.int32, 2), (next_bounds, torch.float64, 3)):
+        if t is not None and (t.device != Q.device or t.dtype != dt or t.numel() < n or not t.is_contiguous()):
+            raise ValueError("status / next_bounds: contiguous device tensors (int32[2], float64[3])")
     w = op.work(prec, nv)
     ev = torch.empty(nv, dtype=torch.float64, device=Q.device)
-    _check(_lib.rayleigh_ritz(op.handle, prec, _ptr(Q), ld, nv, _ptr(ev), _ptr(w), _stream()), "rayleigh_ritz")
+    _check(_lib.rayleigh_ritz(op.handle, prec, _ptr(Q), ld, nv, _ptr(ev), _ptr(w), _ptr(status), _ptr(next_bounds),
+                              _stream()), "rayleigh_ritz")
     return ev
 
 

@@ -85,7 +85,8 @@ def test_diamond8_mixed_precision_passes(lib):
     gop = lib.Operator(cfg.system)
     X0 = _dev(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed))
     v0 = _dev(wl.lanczos_start(gop.n_tot, cfg.v0_seed))
-    bounds = (float(g["a0L"]), float(g["b"]))
+    a0L, b = float(g["a0L"]), float(g["b"])
+    bounds = (a0L, b, 0.5 * (a0L + b))  # the oracle's bounds and its first-pass cut
     n_occ = cfg.nv - 16
     runs = {}
     for name, sched in (("f64", "f64"), ("f32", "f32"), ("bf16", "bf16"),

@@ -183,13 +183,66 @@ def test_chfsi_device_bounds_match_host_bounds(lib):
 
 
 def test_lanczos_bounds(lib):
+    """Both bounds to 1e-10 relative each, the first pass's cut (a0 + b) / 2 from the library, and
+    the device copy {a, b, a0} the device-bounds filter reads."""
+    import torch
     sysm = SYSTEMS["single_atom"]()
     op = OEFEOperator(sysm)
     gop = lib.Operator(sysm)
     v0 = wl.lanczos_start(op.n_tot, 2)
     a0, b, _, _ = och.lanczos_bounds(op.apply, v0, 10)
-    ga0, gb = lib.lanczos_bounds(gop, _dev(v0), 10)
-    assert abs(ga0 - a0) < 1e-9 * abs(b) and abs(gb - b) < 1e-9 * abs(b)
+    dev = torch.zeros(3, dtype=torch.float64, device="cuda")
+    ga0, gb, ga = lib.lanczos_bounds(gop, _dev(v0), 10, dev_bounds=dev, with_cut=True)
+    assert abs(ga0 - a0) <= 1e-10 * abs(a0) and abs(gb - b) <= 1e-10 * abs(b)
+    assert ga == 0.5 * (ga0 + gb)
+    assert dev.cpu().tolist() == [ga, gb, ga0]
+
+
+def test_rayleigh_ritz_status_and_next_bounds(lib):
+    """The eigensolver status {0, sweeps} and the next pass's bounds a = theta_nv, a0 = theta_1
+    written into device memory (b left as it was)."""
+    import torch
+    sysm = SYSTEMS["single_atom"]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    lam, U = np.linalg.eigh(op.dense())
+    rng = np.random.default_rng(3)
+    Q, _ = och.cholgs(U[:, :12] + 1e-3 * rng.standard_normal((op.n_tot, 12)))
+    st = torch.full((2,), 7, dtype=torch.int32, device="cuda")
+    nb = torch.tensor([0.0, 123.5, 0.0], dtype=torch.float64, device="cuda")
+    th = lib.rayleigh_ritz(gop, _dev(Q), st, nb)
+    sth, nbh, thh = st.cpu().tolist(), nb.cpu().tolist(), th.cpu().numpy()
+    assert sth[0] == 0 and 1 <= sth[1] <= 40
+    assert nbh == [thh[-1], 123.5, thh[0]]
+
+
+def test_rayleigh_ritz_sweep_limit_reports_enoconv(lib):
+    """A sweep limit below what the projected matrix needs: the eigensolver stops there, the call
+    returns normally and the status carries OEFE_ENOCONV with the sweep count; chfsi_run raises.
+    The limit also reaches the Lanczos bounds' eigensolver.  Restored afterwards."""
+    import torch
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    sysm = SYSTEMS["p3"]()
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    rng = np.random.default_rng(5)
+    Q, _ = och.cholgs(rng.standard_normal((op.n_tot, 40)))
+    st = torch.zeros(2, dtype=torch.int32, device="cuda")
+    try:
+        lib.set_eig_sweep_limit(gop, 1)
+        lib.rayleigh_ritz(gop, _dev(Q), st)
+        assert st.cpu().tolist() == [-5, 1]
+        with pytest.raises(lib.OefeError) as ei:
+            lib.lanczos_bounds(gop, _dev(wl.lanczos_start(op.n_tot, 2)), 10)
+        assert ei.value.code == -5
+        with pytest.raises(lib.OefeError) as ei:
+            chfsi_run(gop, _dev(Q), _dev(wl.lanczos_start(op.n_tot, 2)), 4, 1, 10,
+                      bounds=(-1.0, 50.0, 10.0))
+        assert ei.value.code == -5
+    finally:
+        lib.set_eig_sweep_limit(gop, 0)
+    lib.rayleigh_ritz(gop, _dev(Q), st)
+    assert st.cpu().tolist()[0] == 0
 
 
 @pytest.mark.parametrize("nv", [1, 2, 15, 16, 37, 80, 81])
@@ -394,7 +447,7 @@ def test_diamond8_full_size(lib):
     scale = g["hx_colnorm"][None, :] / np.sqrt(gop.n_tot)
     assert np.abs(Y[rows] - g["hx_rows"]).max() / np.abs(g["hx_rows"]).max() < 1e-10
     a0, b = lib.lanczos_bounds(gop, _dev(wl.lanczos_start(gop.n_tot, 2)), 10)
-    assert abs(a0 - float(g["a0L"])) < 1e-9 * abs(b) and abs(b - float(g["b"])) < 1e-9 * abs(b)
+    assert abs(a0 - float(g["a0L"])) <= 1e-10 * abs(a0) and abs(b - float(g["b"])) <= 1e-10 * abs(b)
     Xd = _dev(X0)
     a0o, bo = float(g["a0L"]), float(g["b"])
     lib.chebyshev_filter(gop, Xd, cfg.m, 0.5 * (a0o + bo), bo, a0o)

@@ -30,7 +30,7 @@ def d64():
     gop = oefe.Operator(cfg.system)
     X0 = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
     v0 = torch.from_numpy(wl.lanczos_start(gop.n_tot, cfg.v0_seed)).cuda()
-    bounds = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k)
+    bounds = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k, with_cut=True)
     r32 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f32", bounds=bounds)
     del X0
     return oefe, cfg, gop, v0, bounds, r32
