@@ -234,6 +234,18 @@ int cholgs(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* wo
 int cholgs_async(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, void* work, int32_t* dev_status,
                  oefe_stream stream);
 
+/* cholgs_async without a `work` buffer, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Its scratch (Gram matrix, factor inverse, Gram chunk partials,
+ * flags; at most 14 MiB) lives in a device array of the library, one per GPU, held
+ * until the process ends; the call itself allocates nothing.  Real float64 blocks
+ * (F64) of 1..80 columns of a finite-element operator; otherwise EUNSUPPORTED, and
+ * EINVAL for a block whose scratch would exceed 14 MiB.  Same results, status and
+ * stream ordering as cholgs_async.  Every call on one GPU shares that scratch:
+ * calls that overlap on one GPU (several streams or host threads) race. */
+int cholgs_noalloc(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, int32_t* dev_status,
+                   oefe_stream stream);
+
 /* Rayleigh-Ritz (eqnProjKS in symmetric form, Q^* Q = I): W = Ht Q,
  * Hq = Q^* W (Hermitian part), Hq = U diag(theta) U^* (float64 cyclic Jacobi),
  * Q <- Q U.  eigvals: device float64 [nv], ascending.  prec F64 or C128.

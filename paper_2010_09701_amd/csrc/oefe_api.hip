@@ -5,11 +5,16 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "oefe_kernels.h"
+
+// Scratch of the allocation-free entry point (cholgs_noalloc), 14 MiB per device.
+constexpr size_t kScratchBytes = (size_t)14 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace oefe {
 
@@ -490,6 +495,34 @@ int overlap_setup(const oefe_op_s* op, Overlap* ov) {
 // the device-bounds filter keeps its [m][3] scalars in the work buffer's misc area (512 doubles)
 constexpr int kFilterDevMaxDegree = 160;
 
+// ---- allocation-free CholGS: its Gram, factor and flag scratch in the file-scope device
+// array `scratch` (each device holds its own copy until the process ends).  Host code never
+// passes the array's name to a kernel or a copy: its device address is taken once per device
+// with hipGetSymbolAddress and kept in scratch_ptr.
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kScratchDevices] = {};
+
+// device address of `scratch` on the current device (nullptr and a message on failure)
+void* scratch_address(std::string& err) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) {
+    err = "no usable HIP device";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    scratch_ptr[dev] = ptr;
+  }
+  return scratch_ptr[dev];
+}
+
 // Rayleigh-Ritz epilogue: the eigensolver status {code, sweeps} and the next pass's filter
 // bounds (a = theta_nv, a0 = theta_1; b unchanged) from the ascending Ritz values.
 __global__ void rr_finish_kernel(const double* __restrict__ lam, int nv, const int32_t* __restrict__ jst,
@@ -681,6 +714,8 @@ int oefe_op_create(const oefe_system_desc* desc, oefe_op* out) {
     }
   }
   if (rc == OEFE_OK) rc = upload_operator(op, err);
+  // the allocation-free calls' scratch address on this device, taken at set-up
+  if (rc == OEFE_OK && !scratch_address(err)) rc = OEFE_EDEVICE;
   if (rc != OEFE_OK) {
     free_device(op);
     delete op;
@@ -1186,6 +1221,38 @@ int cholgs_async(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, vo
   int rc = gram(cplx, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, (size_t)1 << 62, s);
   if (!rc) rc = cholgs_gated_enqueue(op, L, cplx, Xd, ld, nv, dev_status, s);
   if (rc) return fail(rc, "cholgs_async: kernel launch failed");
+  return OEFE_OK;
+}
+
+int cholgs_noalloc(oefe_op op, oefe_prec prec, void* X, int64_t ld, int32_t nv, int32_t* dev_status,
+                   oefe_stream stream) {
+  if (!op || !X || !dev_status || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
+  if (prec != OEFE_F64) return fail(OEFE_EUNSUPPORTED, "cholgs_noalloc takes real float64 blocks (F64)");
+  if (int rc = check_prec(op, prec)) return rc;
+  if (op->diagonal || !cholgs_device_gated(false, nv))
+    return fail(OEFE_EUNSUPPORTED, "cholgs_noalloc takes 1..80 columns of a finite-element operator");
+  // scratch layout: G [nv^2], factor inverse [nv^2 + nv], Gram chunk partials, 512 doubles, flags
+  const size_t sq = al256((size_t)nv * nv * sizeof(double));
+  const size_t gs = al256(gram_scratch_bytes(false, nv, nv, op->n_tot));
+  const size_t need = sq + sq + al256((size_t)nv * sizeof(double)) + gs + 512 * sizeof(double) + 256;
+  if (need > kScratchBytes)
+    return fail(OEFE_EINVAL, "cholgs_noalloc: the block needs " + std::to_string(need) +
+                                 " bytes of scratch, more than the " + std::to_string(kScratchBytes) + " available");
+  std::string err;
+  char* base = (char*)scratch_address(err);
+  if (!base) return fail(OEFE_EDEVICE, err);
+  Layout L{};
+  char* p = base;
+  L.G = (double*)p; p += sq;
+  L.Rinv = (double*)p; p += sq + al256((size_t)nv * sizeof(double));
+  L.gscr = (double*)p; p += gs;
+  L.misc = (double*)p; p += 512 * sizeof(double);
+  L.status = (int32_t*)p;
+  hipStream_t s = (hipStream_t)stream;
+  double* Xd = (double*)X;
+  int rc = gram(false, Xd, ld, nv, Xd, ld, nv, op->n_tot, L.G, nv, L.gscr, gs, s);
+  if (!rc) rc = cholgs_gated_enqueue(op, L, false, Xd, ld, nv, dev_status, s);
+  if (rc) return fail(rc, "cholgs_noalloc: kernel launch failed");
   return OEFE_OK;
 }
 

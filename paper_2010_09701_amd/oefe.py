@@ -74,6 +74,7 @@ def _load():
         "lanczos_bounds": ([vp, i32, vp, vp, vp, vp, vp], i32),
         "cholgs": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
         "cholgs_async": ([vp, i32, vp, i64, i32, vp, vp, vp], i32),
+        "cholgs_noalloc": ([vp, i32, vp, i64, i32, vp, vp], i32),
         "chebyshev_filter_dev": ([vp, i32, vp, i64, i32, i32, vp, vp, vp, vp], i32),
         "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp], i32),
         "oefe_set_eig_sweep_limit": ([vp, i32], i32),
@@ -98,7 +99,7 @@ EXPORTED = [
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
     "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
-    "lanczos_bounds", "cholgs", "cholgs_async", "rayleigh_ritz", "oefe_set_eig_sweep_limit", "band_energy_grad", "oefe_kernel_timer",
+    "lanczos_bounds", "cholgs", "cholgs_async", "cholgs_noalloc", "rayleigh_ritz", "oefe_set_eig_sweep_limit", "band_energy_grad", "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_copy_rate", "oefe_strerror", "oefe_last_error",
 ]
 
@@ -450,6 +451,17 @@ def cholgs_async(op: Operator, X: torch.Tensor, status: torch.Tensor) -> torch.T
             or not status.is_contiguous()):
         raise ValueError("cholgs_async needs a device int32 status tensor of 2 elements")
     _check(_lib.cholgs_async(op.handle, prec, _ptr(X), ld, nv, _ptr(w), _ptr(status), _stream()), "cholgs_async")
+    return X
+
+
+def cholgs_noalloc(op: Operator, X: torch.Tensor, status: torch.Tensor) -> torch.Tensor:
+    """cholgs_async with the library's own device scratch (no work buffer); float64 blocks of <= 80 columns."""
+    ld, nv = _block(X, op.n_tot)
+    prec = _prec(X)
+    if (status is None or status.device != X.device or status.dtype != torch.int32 or status.numel() < 2
+            or not status.is_contiguous()):
+        raise ValueError("cholgs_noalloc needs a device int32 status tensor of 2 elements")
+    _check(_lib.cholgs_noalloc(op.handle, prec, _ptr(X), ld, nv, _ptr(status), _stream()), "cholgs_noalloc")
     return X
 
 
