@@ -1,32 +1,44 @@
 """Throughput of the ChFSI hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload diamond8] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload diamond64] [--no-cpu-baseline]
 
-Workload "diamond8": 8-atom diamond cell (Z = 14, L = 10.26 bohr, jittered),
-12^3 degree-4 spectral cells (110,592 FE DoF) + 40 orthogonalized enrichment
-functions, 72 vectors, Chebyshev degree 50.  Synthetic, seeded inputs.
+Headline workload "diamond64": 2x2x2 supercell of the 8-atom diamond cell (64
+atoms, Z = 14, L = 20.52 bohr, jittered), 24^3 degree-4 spectral cells
+(884,736 FE DoF) + 320 orthogonalized enrichment functions, 320 vectors,
+Chebyshev degree 60, float64.  Synthetic, seeded inputs (the largest
+configuration; its working set, several GB, is far above the 256 MB Infinity
+Cache).
 
-A step is one ChFSI pass in float64: Chebyshev filter (50 applications of
+A step is one ChFSI pass in float64: Chebyshev filter (60 applications of
 M^-1/2 H M^-1/2), Cholesky-Gram-Schmidt, Rayleigh-Ritz.  The spectrum bounds
 (Lanczos, once per operator) and the operator setup are outside the timed
 region; inputs are resident in device memory.  Each pass's filter bounds come
-from the previous pass's Ritz values through device memory (no host wait
-between passes); statuses and Ritz values are checked after the timed passes.
+from the previous pass's Rayleigh-Ritz through device memory; statuses and
+Ritz values are checked after the timed passes.
 value = N_tot * nv * m / (seconds per step), in DoF*vec*deg/s.
 
-Also reported: the filter-only rate, the float32-arithmetic filter's speedup
-and its Ritz-value error against the float64 path after 5 passes, the node
-kernel's memory roofline and the cell kernel's arithmetic roofline (HIP events
-bracketing each launch on the stream it runs on), the rate of the library's
-stream-copy kernel over 4 GiB (the node kernel's rate is also given as a
-fraction of it), and the CPU oracle on a bounded sample.
+Roofline: the algorithmic HBM bytes of one filter degree are those of the
+method's minimum traffic (read X_k and X_{k-1}, write X_{k+1}; the potential at
+the quadrature points, the lumped mass, the nonzeros of H^co and the dense
+enrichment blocks once): s (3 N_tot nv + n_cells nq + N + nnz(H^co) + n_O^2)
+with s the element size.  `roofline` divides them by the dominant kernel's
+average launch duration (HIP events around each launch, on its stream), and
+`extra.degree_roofline` by the time of a whole degree.
+
+Also reported (`extra`): the filter alone (median of >= 10 calls), the float32
+filter on diamond64; on diamond8 (12^3 cells, 110,632 DoF, 72 vectors, degree
+50) the float64 pass and filter, the float32 / bf16-operand filters with their
+per-pass Ritz-value error against the float64 oracle; the 8 k-point batched
+filter in complex128 / complex64; the library's stream-copy rate; and the CPU
+oracle on a bounded sample of the headline workload (`cpu_baseline`).
 
 Helpers for the committed profile summaries (they read rocprofv3 output):
     python bench.py --summarize-trace DIR           kernel-trace statistics table
-    python bench.py --summarize-traffic FETCH_DIR WRITE_DIR
-                                                    HBM bytes per node-kernel launch from
-                                                    FETCH_SIZE / WRITE_SIZE, calibrated on
-                                                    the device-to-device copy of --calib-copy
+    python bench.py --summarize-traffic FETCH_DIR WRITE_DIR KERNEL_PREFIX
+                                                    HBM bytes per launch of the most frequent
+                                                    kernel matching the prefix, from FETCH_SIZE /
+                                                    WRITE_SIZE, calibrated on the device-to-device
+                                                    copy of --calib-copy
 """
 from __future__ import annotations
 
@@ -57,7 +69,8 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 CELL_FLOPS_P4 = 14500.0
 
 OPS_SOURCE = os.path.join(ROOT, "paper_2010_09701_amd", "csrc", "oefe_ops.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fe_node_fused_kernel_diamond8_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fe_node_fused_kernel_diamond64_traffic.md")
+GOLD = os.path.join(ROOT, "tests", "golden")
 CALIB_BYTES = 512 * 2**20
 COPY_BW_BYTES = 4 * 2**30
 
@@ -67,16 +80,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="diamond8")
+    ap.add_argument("--workload", default="diamond64")
+    ap.add_argument("--filter-reps", type=int, default=10, help="filter-only calls for the median")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the float32 / bf16 filter measurements")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only (no diamond8 / k-point extras)")
     ap.add_argument("--no-kpoints", action="store_true", help="skip the batched k-point filter measurement")
-    ap.add_argument("--no-d64", action="store_true", help="skip the diamond64 filter measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one 512 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--no-copy-bw", action="store_true", help="skip the 4 GiB copy-bandwidth measurement (also skipped with --calib-copy)")
+    ap.add_argument("--no-copy-bw", action="store_true",
+                    help="skip the 4 GiB copy-bandwidth measurement (also skipped with --calib-copy)")
     ap.add_argument("--summarize-trace", metavar="DIR")
-    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL_PREFIX"))
     return ap.parse_args()
 
 
@@ -89,23 +103,15 @@ def ops_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def node_kernel_bytes(gop, ncr: int, m: int) -> float:
-    """Algorithmic HBM bytes of one node-kernel launch inside the filter, averaged over its m steps.
-
-    Per launch: the cell results of every node slot ((nc (p+1))^3 rows), X and the
-    output (N rows each), the previous iterate (N rows, read in m-1 of the m steps),
-    the dense coupling blocks (tile_slots x tile_rows, once per column block) and
-    the tile partials written (tile_slots rows), all x ncr real columns of 8 bytes.
-    """
-    slots = (gop.nc * (gop.p + 1)) ** 3
-    nb_all = -(-ncr // 16)
-    ncb = -(-nb_all // 5)  # column blocks of at most 5 x 16 real columns per workgroup
-    rows = slots + 2 * gop.n_fe + gop.n_fe * (m - 1) / m + gop.tile_slots
-    return 8.0 * (rows * ncr + gop.tile_slots * gop.tile_rows * ncb)
+def degree_bytes(gop, nv: int, elem: int) -> float:
+    """Algorithmic HBM bytes of one filter degree (the method's minimum traffic, see the module doc)."""
+    ops = gop.n_cells * gop.nq + gop.n_fe + gop.hco_nnz + gop.n_enr ** 2
+    return float(elem) * (3.0 * gop.n_tot * nv + ops)
 
 
 def load_traffic():
-    """HBM bytes per node-kernel launch from the committed counter summary, if the kernel source is unchanged."""
+    """Calibrated HBM bytes per launch of the dominant kernel from the committed counter summary,
+    while the kernel source is the one the counters were taken on."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     vals = {}
@@ -133,8 +139,9 @@ def copy_bandwidth(oefe, torch, reps=5):
 
 
 def cpu_baseline(cfg):
-    """One whole float64 pass of the oracle on the same workload (filter of degree m on all
-    vectors, CholGS, Rayleigh-Ritz), timed on the host; the same unit as the GPU value."""
+    """The oracle (numpy/scipy float64) on a bounded sample of the same workload: one filter degree
+    (Ht applied to a block, the recurrence update) on 160 of the vectors, median of 3 after a
+    warm-up, scaled to DoF*vec*deg/s.  The oracle's operator set-up is outside the timing."""
     from oracle import chfsi as och
     from oracle.operator import OEFEOperator
     from paper_2010_09701_amd import workloads as wl
@@ -143,22 +150,94 @@ def cpu_baseline(cfg):
         blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         blas_threads = 1
+    t = time.perf_counter()
     op = OEFEOperator(cfg.system)
-    X0 = wl.start_block(op.n_tot, cfg.nv, cfg.x0_seed)
+    setup_s = time.perf_counter() - t
+    nvs = min(160, cfg.nv)
+    X0 = wl.start_block(op.n_tot, nvs, cfg.x0_seed)
     a0, b, _, _ = och.lanczos_bounds(op.apply, wl.lanczos_start(op.n_tot, cfg.v0_seed), cfg.lanczos_k)
     a = 0.5 * (a0 + b)
-    och.chebyshev_filter(op.apply, X0[:, :4], 1, a, b, a0)  # warm-up
-    t = time.perf_counter()
-    Y = och.chebyshev_filter(op.apply, X0, cfg.m, a, b, a0)
-    Q, _ = och.cholgs(Y)
-    och.rayleigh_ritz(op.apply, Q)
-    dt = time.perf_counter() - t
-    rate = op.n_tot * cfg.nv * cfg.m / dt
+    och.chebyshev_filter(op.apply, X0[:, :8], 1, a, b, a0)  # warm-up
+    times = []
+    for _ in range(3):
+        t = time.perf_counter()
+        och.chebyshev_filter(op.apply, X0, 1, a, b, a0)
+        times.append(time.perf_counter() - t)
+    dt = float(np.median(times))
+    rate = op.n_tot * nvs / dt
     cores = len(os.sched_getaffinity(0))
     return {"value": rate, "unit": "DoF*vec*deg/s", "cores": int(min(cores, max(blas_threads, 1))), "kind": "oracle",
-            "sample": f"{cfg.system.name}: one float64 oracle pass (degree-{cfg.m} filter on all {cfg.nv} vectors, "
-                      f"CholGS, Rayleigh-Ritz; {dt:.1f} s; numpy/scipy with {blas_threads} BLAS threads, "
-                      f"{cores} host cores available)"}
+            "sample": f"{cfg.system.name}: one float64 filter degree of the oracle on {nvs} of the {cfg.nv} vectors "
+                      f"({op.n_tot} DoF), median of 3 ({dt:.1f} s each) after a warm-up; oracle set-up "
+                      f"{setup_s:.0f} s untimed; numpy/scipy with {blas_threads} BLAS threads, {cores} host cores"}
+
+
+def median_filter_ms(oefe, torch, gop, X0, m, abc, reps, mixed=None):
+    """Median over `reps` calls of one filter (HIP events on the current stream around each call)."""
+    a, b, a0 = abc
+    X = X0.clone()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        if mixed is None:
+            oefe.chebyshev_filter(gop, X, m, a, b, a0)
+        else:
+            oefe.chebyshev_filter_mixed(gop, X, m, a, b, a0, bf16=(mixed == "bf16"))
+        e1.record(stream)
+        X.copy_(X0)
+    torch.cuda.synchronize()
+    del X
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+
+def stage_us(oefe, gop, X0, m, abc, which):
+    """Average duration (us) of one stage's launches inside a filter (library HIP events around each
+    launch, on the stream it runs on)."""
+    a, b, a0 = abc
+    X = X0.clone()
+    gop.kernel_timer(which)
+    oefe.chebyshev_filter(gop, X, m, a, b, a0)
+    n_launch, tot_ms = gop.kernel_timer_read()
+    gop.kernel_timer("off")
+    del X
+    return tot_ms / max(n_launch, 1) * 1e3, n_launch
+
+
+def run_passes(oefe, torch, gop, X, m, dev_bounds, n_warm, n_steps):
+    """n_warm + n_steps float64 passes queued back to back; returns (ms per step (mean), per-step ms,
+    Ritz values per pass)."""
+    n_pass = n_warm + n_steps
+    st = torch.zeros(n_pass, 3, 2, dtype=torch.int32, device=X.device)  # [pass][filter, cholgs, rr][code, .]
+    thetas = []
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_steps)]
+
+    def step(i):
+        oefe.chebyshev_filter_dev(gop, X, m, dev_bounds, st[i, 0])
+        oefe.cholgs_async(gop, X, st[i, 1])
+        thetas.append(oefe.rayleigh_ritz(gop, X, st[i, 2], dev_bounds))
+
+    for i in range(n_warm):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for i in range(n_steps):
+        ev[i][0].record(stream)
+        step(n_warm + i)
+        ev[i][1].record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    st_h = st.cpu().numpy()
+    if (st_h[:, :, 0] != 0).any():
+        raise RuntimeError(f"pass failed: statuses [pass][filter, cholgs, rr][code, .] {st_h.tolist()}")
+    th_all = np.stack([t.cpu().numpy() for t in thetas])
+    if not np.isfinite(th_all).all() or (np.diff(th_all, axis=1) < 0).any():
+        raise RuntimeError("Ritz values not finite and ascending")
+    return t0.elapsed_time(t1) / n_steps, [a.elapsed_time(b) for a, b in ev], th_all
 
 
 def kpoint_bench(oefe, wl, torch, base, m, reps):
@@ -171,8 +250,8 @@ def kpoint_bench(oefe, wl, torch, base, m, reps):
     abc = []
     for op in ops:
         v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, 2)).cuda()
-        a0, bb = oefe.lanczos_bounds(op, v0, 10)
-        abc.append((0.5 * (a0 + bb), bb, a0))
+        a0, bb, a = oefe.lanczos_bounds(op, v0, 10, with_cut=True)
+        abc.append((a, bb, a0))
     work = sum(op.n_tot * nv for op, nv in zip(ops, wl.KPOINT_NV)) * m
     res = {"k_points": len(ops), "nv": wl.KPOINT_NV, "m": m}
     e0 = torch.cuda.Event(enable_timing=True)
@@ -188,8 +267,6 @@ def kpoint_bench(oefe, wl, torch, base, m, reps):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        # per-launch stage durations (HIP events on the stream each stage runs on; the
-        # coupling kernel runs on the side stream beside the cell stage)
         stages = {}
         for which in ("cell", "node", "coupling"):
             ops[0].kernel_timer(which)
@@ -201,55 +278,77 @@ def kpoint_bench(oefe, wl, torch, base, m, reps):
                      "stage_avg_us": stages}
         log(f"k-points {name}: batched filter {ms:.3f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s, shape {tune}, "
             + ", ".join(f"{k} {v:.1f}" for k, v in stages.items()))
+    # complex64 filter passes against the complex128 oracle at the k-points with the fewest and the
+    # most vectors (stored oracle values)
+    gpath = os.path.join(GOLD, "kpoint_passes_oracle.npz")
+    if os.path.exists(gpath):
+        from paper_2010_09701_amd.chfsi import chfsi_run
+        g = np.load(gpath)
+        for q in (0, 7):
+            bounds = (float(g[f"a0L{q}"]), float(g[f"b{q}"]), 0.5 * (float(g[f"a0L{q}"]) + float(g[f"b{q}"])))
+            v0 = torch.from_numpy(wl.lanczos_start(ops[q].n_tot, 2)).cuda()
+            th_o = g[f"thetas{q}"]
+            n_occ = wl.KPOINT_NV[q] - 16
+            for name in ("c128", "c64"):
+                r = chfsi_run(ops[q], blocks[q], v0, m, th_o.shape[0], 10, name if name == "c64" else "f64",
+                              bounds=bounds)
+                err = [float(np.abs(p["theta"][:n_occ] - t[:n_occ]).max()) for p, t in zip(r["passes"], th_o)]
+                res.setdefault("ritz_err_vs_oracle_per_pass_Ha", {})[f"k{q}_{name}"] = err
+                log(f"k-point {q} {name}: Ritz error vs oracle per pass {['%.1e' % x for x in err]}")
     res["unit"] = "DoF*vec*deg/s (complex vectors)"
     return res
 
 
-def d64_bench(oefe, wl, torch):
-    """diamond64 (885,056 DoF x 320 vectors, degree 60): one float64 and one float32 filter,
-    and the per-launch node / cell kernel durations, at a shape whose working set (several
-    GB) is far above the 256 MB Infinity Cache."""
-    cfg = wl.config("diamond64")
-    t = time.time()
+def diamond8_extra(oefe, wl, torch, reps):
+    """diamond8: float64 pass and filter, float32 / bf16-operand filters with their per-pass Ritz
+    error against the float64 oracle (stored values) and against the float64 GPU run."""
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    cfg = wl.config("diamond8")
     gop = oefe.Operator(cfg.system)
-    setup_s = time.time() - t
     X0 = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
     v0 = torch.from_numpy(wl.lanczos_start(gop.n_tot, cfg.v0_seed)).cuda()
-    a0L, b = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k)
-    a = 0.5 * (a0L + b)
+    dev_bounds = torch.zeros(3, dtype=torch.float64, device="cuda")
+    a0L, b, a1 = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k, dev_bounds=dev_bounds, with_cut=True)
+    X = X0.clone()
+    pass_ms, _, _ = run_passes(oefe, torch, gop, X, cfg.m, dev_bounds, 1, max(5, reps))
+    abc = (a1, b, a0L)
+    filt_ms = median_filter_ms(oefe, torch, gop, X0, cfg.m, abc, reps)
+    node_us, _ = stage_us(oefe, gop, X0, cfg.m, abc, "node")
+    cell_us, _ = stage_us(oefe, gop, X0, cfg.m, abc, "cell")
     work = gop.n_tot * cfg.nv * cfg.m
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    res = {"workload": "diamond64: 24^3 cells p=4, 884736 FE + 320 enrichment DoF, 320 vectors, degree 60",
-           "setup_s": setup_s}
-    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
-        X = X0.to(dt)
-        oefe.chebyshev_filter(gop, X, 2, a, b, a0L)  # warm-up
-        X.copy_(X0)
-        torch.cuda.synchronize()
-        e0.record()
-        oefe.chebyshev_filter(gop, X, cfg.m, a, b, a0L)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        r = {"filter_ms": ms, "rate": work / (ms / 1e3)}
-        for which in ("node", "cell"):
-            X.copy_(X0)
-            gop.kernel_timer(which)
-            oefe.chebyshev_filter(gop, X, 10, a, b, a0L)
-            n_launch, tot_ms = gop.kernel_timer_read()
-            gop.kernel_timer("off")
-            r[which + "_avg_us"] = tot_ms / max(n_launch, 1) * 1e3
-        if name == "f64":
-            nbytes = node_kernel_bytes(gop, cfg.nv, 10)
-            r["node_gbs"] = nbytes / (r["node_avg_us"] / 1e6) / 1e9
-            r["node_frac_of_8TBs"] = r["node_gbs"] / PEAK_HBM_GBS
-        res[name] = r
-        log(f"diamond64 {name}: filter {ms:.1f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s; node {r['node_avg_us']:.0f} us, "
-            f"cell {r['cell_avg_us']:.0f} us" + (f", node {r['node_gbs']:.0f} GB/s" if name == "f64" else ""))
-        del X
-    res["unit"] = "DoF*vec*deg/s"
-    return res
+    dbytes = degree_bytes(gop, cfg.nv, 8)
+    out = {"workload": f"diamond8: 12^3 cells p=4, {gop.n_fe} FE + {gop.n_enr} enrichment DoF, {cfg.nv} vectors, "
+                       f"degree {cfg.m}",
+           "pass_ms": pass_ms, "pass_rate": work / (pass_ms / 1e3), "filter_ms": filt_ms,
+           "filter_rate": work / (filt_ms / 1e3), "node_avg_us": node_us, "cell_avg_us": cell_us,
+           "degree_bytes": dbytes, "degree_frac_of_8TBs": dbytes / (filt_ms / cfg.m / 1e3) / 1e9 / PEAK_HBM_GBS}
+    log(f"diamond8 f64: pass {pass_ms:.3f} ms, filter {filt_ms:.3f} ms ({work / (filt_ms / 1e3):.3e}); node "
+        f"{node_us:.1f} us, cell {cell_us:.1f} us")
+    gpath = os.path.join(GOLD, "diamond8_oracle.npz")
+    th_oracle = np.load(gpath)["thetas"] if os.path.exists(gpath) else None
+    r64 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f64", bounds=(a0L, b, a1))
+    n_occ = cfg.nv - 16
+    Q64 = r64["X"][:, :n_occ]
+    for name in ("fp32", "bf16"):
+        mode = "bf16" if name == "bf16" else "f32"
+        mixed_ms = median_filter_ms(oefe, torch, gop, X0, cfg.m, abc, reps, mixed=mode)
+        rm = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, mode, bounds=(a0L, b, a1))
+        err64 = [float(np.abs(pm["theta"][:n_occ] - p64["theta"][:n_occ]).max())
+                 for pm, p64 in zip(rm["passes"], r64["passes"])]
+        Q = rm["X"][:, :n_occ]
+        sin_angle = float(torch.linalg.matrix_norm(Q - Q64 @ (Q64.T @ Q), ord=2))
+        rec = {"filter_ms": mixed_ms, "speedup_vs_f64": filt_ms / mixed_ms,
+               "ritz_err_vs_gpu_f64_per_pass_Ha": err64, "subspace_sin_angle_vs_f64": sin_angle}
+        if th_oracle is not None:
+            err_o = [float(np.abs(pm["theta"][:n_occ] - t[:n_occ]).max()) for pm, t in zip(rm["passes"], th_oracle)]
+            rec["ritz_err_vs_oracle_per_pass_Ha"] = err_o
+            rec["meets_1e-6_Ha"] = bool(err_o[-1] <= 1e-6)
+        out[name] = rec
+        log(f"diamond8 {name} filter {mixed_ms:.3f} ms (x{filt_ms / mixed_ms:.2f}); Ritz err per pass "
+            f"{['%.1e' % x for x in rec.get('ritz_err_vs_oracle_per_pass_Ha', err64)]}; sin(max angle) "
+            f"{sin_angle:.1e}")
+    out["mixed_occupied_states"] = n_occ
+    return out, gop
 
 
 def summarize_trace(d):
@@ -295,15 +394,14 @@ def _per_kernel(rows, counter):
     return out
 
 
-def summarize_traffic(fetch_dir, write_dir):
+def summarize_traffic(fetch_dir, write_dir, prefix):
     fe = _per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
     wr = _per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
-    # the filter's node-kernel instance is the float64 one launched most often
-    node = sorted((k for k in fe if k.startswith("fe_node_fused_kernel<double")), key=lambda k: -len(fe[k]))
+    cand = sorted((k for k in fe if k.startswith(prefix)), key=lambda k: -len(fe[k]))
     copy = [k for k in fe if "copyBuffer" in k or "copy_kernel" in k]
-    if not node or not copy:
+    if not cand or not copy:
         sys.exit(f"kernels not found: {sorted(fe)}")
-    k, c = node[0], copy[0]
+    k, c = cand[0], copy[0]
     cf = max(fe[c]) * 1024.0 / CALIB_BYTES  # the largest dispatch is the 512 MiB calibration copy
     cw = max(wr[c]) * 1024.0 / CALIB_BYTES
     f_kib, w_kib = float(np.median(fe[k])), float(np.median(wr[k]))
@@ -344,124 +442,63 @@ def main():
     log(f"operator setup {time.time() - t:.1f} s, n_tot={gop.n_tot}, nv={cfg.nv}, m={cfg.m}")
     X0 = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
     v0 = torch.from_numpy(wl.lanczos_start(gop.n_tot, cfg.v0_seed)).cuda()
-    a0L, b, a1 = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k, with_cut=True)
+    dev_bounds = torch.zeros(3, dtype=torch.float64, device="cuda")
+    a0L, b, a1 = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k, dev_bounds=dev_bounds, with_cut=True)
+    abc = (a1, b, a0L)
     log(f"bounds a0={a0L:.6f} b={b:.6f}")
+
+    # the timed passes: filter bounds through device memory, statuses checked afterwards
     X = X0.clone()
-
-    # The bounds of each pass's filter stay on the device: (a, b, a0), pass 1 cut at
-    # (a0 + b) / 2, later passes a = theta_nv and a0 = theta_1 written there by the previous
-    # Rayleigh-Ritz.  Filter and CholGS statuses and the Ritz values are checked after the
-    # timed passes, so the host never waits inside a pass.
-    n_pass = args.warmup + args.steps
-    bounds = torch.tensor([0.5 * (a0L + b), b, a0L], dtype=torch.float64, device=X.device)
-    st_dev = torch.zeros(n_pass, 2, 2, dtype=torch.int32, device=X.device)  # [pass][filter, cholgs][code, col]
-    thetas = []
-
-    def step(i):
-        oefe.chebyshev_filter_dev(gop, X, cfg.m, bounds, st_dev[i, 0])
-        oefe.cholgs_async(gop, X, st_dev[i, 1])
-        th = oefe.rayleigh_ritz(gop, X)
-        bounds[0:1].copy_(th[-1:])
-        bounds[2:3].copy_(th[:1])
-        thetas.append(th)
-
-    for i in range(args.warmup):
-        step(i)
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for i in range(args.steps):
-        step(args.warmup + i)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    st_h = st_dev.cpu().numpy()
-    if (st_h[:, :, 0] != 0).any():
-        raise RuntimeError(f"pass failed: statuses [pass][filter, cholgs][code, column] {st_h.tolist()}")
-    th_all = np.stack([t.cpu().numpy() for t in thetas])
-    if not np.isfinite(th_all).all() or (np.diff(th_all, axis=1) < 0).any():
-        raise RuntimeError("Ritz values not finite and ascending")
-    ms = e0.elapsed_time(e1) / args.steps
+    ms, step_ms, _ = run_passes(oefe, torch, gop, X, cfg.m, dev_bounds, args.warmup, args.steps)
+    del X
     work = gop.n_tot * cfg.nv * cfg.m
     value = work / (ms / 1e3)
-    log(f"pass: {ms:.3f} ms, {value:.3e} DoF*vec*deg/s")
+    log(f"pass: {ms:.3f} ms (median {np.median(step_ms):.3f}), {value:.3e} DoF*vec*deg/s")
 
-    # filter-only rate
-    Xf = X0.clone()
-    reps = max(2, args.steps)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(reps):
-        oefe.chebyshev_filter(gop, Xf, cfg.m, 0.5 * (a0L + b), b, a0L)
-        Xf.copy_(X0)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    filt_ms = e0.elapsed_time(e1) / reps
-
-    # per-launch durations of the node and cell kernels: HIP events recorded by the
-    # library around each launch, on the stream the kernel runs on
-    def stage_ms(which):
-        gop.kernel_timer(which)
-        oefe.chebyshev_filter(gop, Xf, cfg.m, 0.5 * (a0L + b), b, a0L)
-        n_launch, tot_ms = gop.kernel_timer_read()
-        gop.kernel_timer("off")
-        Xf.copy_(X0)
-        return tot_ms / max(n_launch, 1), n_launch
-
-    node_ms, node_n = stage_ms("node")
-    cell_ms, cell_n = stage_ms("cell")
-    node_bytes = node_kernel_bytes(gop, cfg.nv, cfg.m)
-    node_gbs = node_bytes / (node_ms / 1e3) / 1e9
+    # the filter alone: median of >= 10 calls; stage durations; roofline
+    reps = max(10, args.filter_reps)
+    filt_ms = median_filter_ms(oefe, torch, gop, X0, cfg.m, abc, reps)
+    node_us, node_n = stage_us(oefe, gop, X0, cfg.m, abc, "node")
+    cell_us, cell_n = stage_us(oefe, gop, X0, cfg.m, abc, "cell")
+    dbytes = degree_bytes(gop, cfg.nv, 8)
+    node_gbs = dbytes / (node_us / 1e6) / 1e9
+    degree_gbs = dbytes / (filt_ms / cfg.m / 1e3) / 1e9
     cell_flops = CELL_FLOPS_P4 * (sysm.p + 1) ** 3 / 125.0 * gop.n_cells * cfg.nv
-    cell_tfs = cell_flops / (cell_ms / 1e3) / 1e12
+    cell_tfs = cell_flops / (cell_us / 1e6) / 1e12
     traffic = load_traffic()
-    log(f"filter: {filt_ms:.3f} ms; node kernel avg {node_ms * 1e3:.1f} us ({node_n} launches), "
-        f"{node_gbs:.0f} GB/s algorithmic; cell kernel avg {cell_ms * 1e3:.1f} us, {cell_tfs:.2f} TFLOP/s")
+    log(f"filter: median {filt_ms:.2f} ms ({work / (filt_ms / 1e3):.3e} DoF*vec*deg/s); node kernel avg "
+        f"{node_us:.1f} us ({node_n} launches); cell kernel avg {cell_us:.1f} us ({cell_tfs:.2f} TFLOP/s); degree "
+        f"{dbytes / 1e9:.3f} GB algorithmic -> {degree_gbs:.0f} GB/s per degree")
 
-    extra = {"filter_ms": filt_ms, "filter_rate": work / (filt_ms / 1e3), "pass_ms": ms,
-             "lanczos_bounds": [a0L, b], "n_tot": gop.n_tot, "n_fe": gop.n_fe, "n_enr": gop.n_enr,
-             "cell_kernel": {"bound": "alu", "kernel": "fe_cell_kernel<double,5>", "achieved": cell_tfs,
+    extra = {"filter_ms_median": filt_ms, "filter_reps": reps, "filter_rate": work / (filt_ms / 1e3),
+             "pass_ms_median": float(np.median(step_ms)), "lanczos_bounds": [a0L, b], "first_cut": a1,
+             "n_tot": gop.n_tot, "n_fe": gop.n_fe, "n_enr": gop.n_enr, "hco_nnz": gop.hco_nnz,
+             "degree_bytes": dbytes,
+             "degree_roofline": {"bound": "hbm", "achieved": degree_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": degree_gbs / PEAK_HBM_GBS, "degree_us": filt_ms / cfg.m * 1e3},
+             "cell_kernel": {"bound": "alu", "kernel": "fe_cell_lanes_kernel<double,5,false>", "achieved": cell_tfs,
                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": cell_tfs / PEAK_FP64_TFLOPS,
-                             "avg_launch_us": cell_ms * 1e3, "flops_per_launch": cell_flops}}
+                             "avg_launch_us": cell_us, "flops_per_launch": cell_flops}}
 
-    if not args.no_fp32:
-        from paper_2010_09701_amd.chfsi import chfsi_run
-        r64 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f64", bounds=(a0L, b, a1))
-        n_occ = cfg.nv - 16
-        Q64 = r64["X"][:, :n_occ]
-        for name, bf in (("fp32", False), ("bf16", True)):
-            Xm = X0.clone()
-            torch.cuda.synchronize()
-            e0.record(stream)
-            for i in range(reps):
-                oefe.chebyshev_filter_mixed(gop, Xm, cfg.m, 0.5 * (a0L + b), b, a0L, bf16=bf)
-                Xm.copy_(X0)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            mixed_ms = e0.elapsed_time(e1) / reps
-            rm = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "bf16" if bf else "f32", bounds=(a0L, b, a1))
-            err = [float(np.abs(pm["theta"][:n_occ] - p64["theta"][:n_occ]).max())
-                   for pm, p64 in zip(rm["passes"], r64["passes"])]
-            Q = rm["X"][:, :n_occ]
-            sin_angle = float(torch.linalg.matrix_norm(Q - Q64 @ (Q64.T @ Q), ord=2))
-            extra.update({f"{name}_filter_ms": mixed_ms, f"{name}_filter_speedup": filt_ms / mixed_ms,
-                          f"{name}_ritz_err_vs_fp64_per_pass_Ha": err,
-                          f"{name}_subspace_sin_angle_vs_fp64": sin_angle})
-            log(f"{name} filter {mixed_ms:.3f} ms (x{filt_ms / mixed_ms:.2f}); Ritz err per pass "
-                f"{['%.1e' % x for x in err]}; sin(max angle) {sin_angle:.1e}")
-        extra["mixed_occupied_states"] = n_occ
+    # float32 filter on the headline workload
+    f32_ms = median_filter_ms(oefe, torch, gop, X0.float(), cfg.m, abc, max(3, reps // 3))
+    extra["f32_filter_ms_median"] = f32_ms
+    extra["f32_filter_speedup"] = filt_ms / f32_ms
+    log(f"float32 filter: median {f32_ms:.2f} ms (x{filt_ms / f32_ms:.2f})")
+    del X0
+    torch.cuda.empty_cache()
 
-    if not args.no_kpoints and sysm.name == "diamond8":
-        extra["kpoints"] = kpoint_bench(oefe, wl, torch, sysm, cfg.m, reps)
-    if not args.no_d64 and sysm.name == "diamond8":
-        extra["diamond64"] = d64_bench(oefe, wl, torch)
+    if not args.no_extra:
+        extra["diamond8"], op8 = diamond8_extra(oefe, wl, torch, reps)
+        del op8
+        if not args.no_kpoints:
+            cfg8 = wl.config("diamond8")
+            extra["kpoints"] = kpoint_bench(oefe, wl, torch, cfg8.system, cfg8.m, 3)
     copy_gbs = None
     if not args.no_copy_bw and not args.calib_copy:  # (the counter calibration takes the largest copy)
         copy_gbs = copy_bandwidth(oefe, torch)
         extra["hbm_copy_gbs"] = copy_gbs
-        log(f"stream copy of {COPY_BW_BYTES >> 30} GiB: {copy_gbs:.0f} GB/s (read + write); node kernel "
-            f"{node_gbs / copy_gbs:.2f} of it")
+        log(f"stream copy of {COPY_BW_BYTES >> 30} GiB: {copy_gbs:.0f} GB/s (read + write)")
 
     out = {
         "metric": "ChFSI filter DoF*vec*deg/s (one float64 ChFSI pass: filter + CholGS + Rayleigh-Ritz)",
@@ -481,7 +518,7 @@ def main():
                    "global_batch": cfg.nv, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "fe_node_fused_kernel<double>", "achieved": node_gbs,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": node_gbs / PEAK_HBM_GBS,
-                     "traffic": traffic, "avg_launch_us": node_ms * 1e3, "bytes_per_launch": node_bytes,
+                     "traffic": traffic, "avg_launch_us": node_us, "bytes_per_launch": dbytes,
                      "frac_of_copy": (node_gbs / copy_gbs) if copy_gbs else None},
         "extra": extra,
     }

@@ -103,10 +103,11 @@ int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out);
 
 int oefe_op_destroy(oefe_op op);
 
-/* dims[0..9] = n_fe, n_enr, n_tot, n_cells, nq, nc, p, is_complex,
+/* dims[0..10] = n_fe, n_enr, n_tot, n_cells, nq, nc, p, is_complex,
  * coupling-tile slots (sum over the tiles of tile_rows consecutive FE rows of
- * the number of enrichment functions each couples to, padded to 4), tile_rows.
- * dims must hold 10 entries. */
+ * the number of enrichment functions each couples to, padded to 4), tile_rows,
+ * nonzeros of H^co (FE row, enrichment function pairs whose supports overlap).
+ * dims must hold 11 entries. */
 int oefe_op_dims(oefe_op op, int64_t* dims);
 
 /* Replace the potential at the quadrature points: V[n_cells * nq] (cell-major,

@@ -772,6 +772,7 @@ int oefe_op_dims(oefe_op op, int64_t* dims) {
   dims[7] = op->cplx ? 1 : 0;
   dims[8] = op->n_enr > 0 ? op->tile_slots : 0;
   dims[9] = kTileRows;
+  dims[10] = op->n_enr > 0 ? op->fr_nnz : 0;
   return OEFE_OK;
 }
 

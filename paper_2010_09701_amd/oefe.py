@@ -162,10 +162,10 @@ class Operator:
                 raise RuntimeError("no HIP device")
             torch.cuda.current_device()
             _check(_lib.oefe_op_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create")
-        dims = (ctypes.c_int64 * 10)()
+        dims = (ctypes.c_int64 * 11)()
         _check(_lib.oefe_op_dims(self._h, dims), "oefe_op_dims")
         (self.n_fe, self.n_enr, self.n_tot, self.n_cells, self.nq, self.nc, self.p, cx, self.tile_slots,
-         self.tile_rows) = [int(x) for x in dims]
+         self.tile_rows, self.hco_nnz) = [int(x) for x in dims]
         self.is_complex = bool(cx)
         self.is_diagonal = False
         self._work = {}

@@ -7,6 +7,8 @@ library.  The paper prints no values that apply to these synthetic operators.
     python tests/golden/make_golden.py diamond8     (about 10 min on 8 cores)
     python tests/golden/make_golden.py diamond64    (about 20 min)
     python tests/golden/make_golden.py kpoints      (about 5 min)
+    python tests/golden/make_golden.py kpoint_passes   (about 20 min)
+    python tests/golden/make_golden.py diamond64_pass1 (about 40 min, ~20 GB of host memory)
 """
 import os
 import sys
@@ -89,7 +91,78 @@ def kpoints():
     np.savez_compressed(os.path.join(HERE, "kpoints_oracle.npz"), **out)
 
 
+def _passes(op, X0, v0, m, passes, k, rows):
+    """The oracle's ChFSI step by step: bounds, pass-1 filtered rows / column norms, Ritz values per pass."""
+    a0L, b, _, _ = ch.lanczos_bounds(op.apply, v0, k)
+    a0, a = a0L, 0.5 * (a0L + b)
+    X = X0
+    thetas = []
+    out = dict(a0L=a0L, b=b)
+    for it in range(passes):
+        Y = ch.chebyshev_filter(op.apply, X, m, a, b, a0)
+        if it == 0:
+            out["filt1_rows"] = Y[rows]
+            out["filt1_colnorm"] = np.linalg.norm(Y, axis=0)
+        Q, _ = ch.cholgs(Y)
+        th, X = ch.rayleigh_ritz(op.apply, Q)
+        thetas.append(th)
+        a0, a = float(th[0]), float(th[-1])
+    out["thetas"] = np.stack(thetas)
+    return out
+
+
+def kpoint_passes():
+    """Five float64 (complex128) ChFSI passes at the k-points with the fewest (48) and the most (96)
+    vectors of the 2x2x2 Monkhorst-Pack grid on diamond8."""
+    base = wl.config("diamond8").system
+    cfg = wl.config("diamond8")
+    ks = wl.monkhorst_pack_2(base.L)
+    out = {}
+    t = time.time()
+    for q in (0, 7):
+        op = OEFEOperator(base.with_k(ks[q]))
+        nv = wl.KPOINT_NV[q]
+        X0 = wl.start_block(op.n_tot, nv, 10 + q, complex_=True)
+        v0 = wl.lanczos_start(op.n_tot, cfg.v0_seed)
+        rows = sample_rows(op.N, op.n_enr, 200, 50 + q)
+        r = _passes(op, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, rows)
+        out[f"rows{q}"] = rows
+        for key, val in r.items():
+            out[f"{key}{q}"] = val
+        print("k-point", q, nv, r["thetas"][:, :3], time.time() - t, flush=True)
+    np.savez_compressed(os.path.join(HERE, "kpoint_passes_oracle.npz"), **out)
+
+
+def diamond64_pass1():
+    """diamond64: bounds and the first float64 ChFSI pass (degree-60 filter on all 320 vectors in
+    column chunks, which the filter treats independently; CholGS and Rayleigh-Ritz on the block)."""
+    cfg = wl.config("diamond64")
+    t = time.time()
+    op = OEFEOperator(cfg.system)
+    print("operator", time.time() - t, flush=True)
+    X0 = wl.start_block(op.n_tot, cfg.nv, cfg.x0_seed)
+    v0 = wl.lanczos_start(op.n_tot, cfg.v0_seed)
+    a0L, b, _, _ = ch.lanczos_bounds(op.apply, v0, cfg.lanczos_k)
+    print("bounds", a0L, b, time.time() - t, flush=True)
+    a = 0.5 * (a0L + b)
+    Y = np.empty_like(X0)
+    for j0 in range(0, cfg.nv, 64):
+        Y[:, j0:j0 + 64] = ch.chebyshev_filter(op.apply, X0[:, j0:j0 + 64], cfg.m, a, b, a0L)
+        print("filtered columns", j0 + 64, time.time() - t, flush=True)
+    del X0
+    rows = sample_rows(op.N, op.n_enr, 400, 23)
+    filt1_rows = Y[rows]
+    filt1_colnorm = np.linalg.norm(Y, axis=0)
+    Q, _ = ch.cholgs(Y)
+    del Y
+    th, _ = ch.rayleigh_ritz(op.apply, Q)
+    print("pass 1 Ritz values", th[:4], th[-2:], time.time() - t, flush=True)
+    np.savez_compressed(os.path.join(HERE, "diamond64_pass1_oracle.npz"), a0L=a0L, b=b, rows=rows,
+                        filt1_rows=filt1_rows, filt1_colnorm=filt1_colnorm, theta1=th)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["diamond8"]
     for w in which:
-        {"diamond8": diamond8, "diamond64": diamond64, "kpoints": kpoints}[w]()
+        {"diamond8": diamond8, "diamond64": diamond64, "kpoints": kpoints, "kpoint_passes": kpoint_passes,
+         "diamond64_pass1": diamond64_pass1}[w]()

@@ -4,9 +4,11 @@
   filter against the oracle's filter of each k-point;
 * diamond8 at the 8 k-points of the 2x2x2 Monkhorst-Pack grid with 48..96 vectors:
   the operator on sampled rows against stored oracle values, and the batched filter
-  against one filter per operator (the same arithmetic, so equal to rounding);
+  against one filter per operator (the same arithmetic in the same order: equal to
+  the bit);
 * the autotuner: the chosen shape is one of the candidates, results do not depend on
-  the shape, and a JSON cache entry is reused.
+  the shape (equal to the bit: every launch shape sums in the same fixed order), and a
+  JSON cache entry is reused.
 """
 import os
 
@@ -92,8 +94,8 @@ def _bounds(lib, ops):
     out = []
     for op in ops:
         v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, 2)).cuda()
-        a0, b = lib.lanczos_bounds(op, v0, 10)
-        out.append((0.5 * (a0 + b), b, a0))
+        a0, b, a = lib.lanczos_bounds(op, v0, 10, with_cut=True)
+        out.append((a, b, a0))
     return out
 
 
@@ -109,8 +111,7 @@ def test_mp_grid_batched_equals_per_operator(lib, mp_ops, prec):
     for q, op in enumerate(mp_ops):
         Xs = _dev(blocks[q], dt)
         lib.chebyshev_filter(op, Xs, m, *abc[q])
-        a, b = Xb[q].cpu().numpy(), Xs.cpu().numpy()
-        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max(), q
+        assert torch.equal(Xb[q], Xs), q
 
 
 def test_autotune_shape_and_cache(lib, mp_ops, tmp_path):
@@ -127,8 +128,20 @@ def test_autotune_shape_and_cache(lib, mp_ops, tmp_path):
     Xt = [_dev(X, torch.complex128) for X in blocks]
     lib.chebyshev_filter_batched(mp_ops, Xt, m, abc)  # tuned shape
     for a, b in zip(Xa, Xt):
-        a, b = a.cpu().numpy(), b.cpu().numpy()
-        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+        assert torch.equal(a, b)
+    # every candidate shape, complex64 as well
+    for dt in (torch.complex128, torch.complex64):
+        Xr = [_dev(X, dt) for X in blocks]
+        lib.chebyshev_filter_batched(mp_ops, Xr, m, abc)
+        for cw, cb in ((8, 32), (16, 64), (32, 128), (64, 16)):
+            for op in mp_ops:
+                lib.set_launch_shape(op, cw, cb)
+            Xs = [_dev(X, dt) for X in blocks]
+            lib.chebyshev_filter_batched(mp_ops, Xs, m, abc)
+            for a, b in zip(Xr, Xs):
+                assert torch.equal(a, b), (dt, cw, cb)
+        for op in mp_ops:
+            lib.set_launch_shape(op, 0, 0)
     r2 = lib.autotune(mp_ops, [_dev(X, torch.complex128) for X in blocks], cache=cache)
     assert r2["cached"] and (r2["cw"], r2["cb"]) == (r["cw"], r["cb"])
     for op in mp_ops:

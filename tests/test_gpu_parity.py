@@ -480,3 +480,28 @@ def test_diamond64_full_size_rows(lib):
     Y = lib.ham_apply(gop, _dev(X0)).cpu().numpy()
     rows = g["rows"]
     assert np.abs(Y[rows] - g["hx_rows"]).max() / np.abs(g["hx_rows"]).max() < 1e-10
+
+
+@pytest.mark.parametrize("dt", ["float64", "float32"])
+def test_filter_bitwise_across_launch_shapes_and_runs(lib, dt):
+    """Fixed-order sums everywhere (no atomics): the same filter on a real operator gives the same
+    bits from run to run and for every launch shape of the cell and node stages."""
+    import torch
+    dtype = getattr(torch, dt)
+    sysm = SYSTEMS["diamond_nc4"]()
+    gop = lib.Operator(sysm)
+    X0 = _dev(wl.start_block(gop.n_tot, 72, 0), dtype)
+    a0, b, a = lib.lanczos_bounds(gop, _dev(wl.lanczos_start(gop.n_tot, 2)), 10, with_cut=True)
+    ref = X0.clone()
+    lib.chebyshev_filter(gop, ref, 7, a, b, a0)
+    again = X0.clone()
+    lib.chebyshev_filter(gop, again, 7, a, b, a0)
+    assert torch.equal(ref, again)
+    try:
+        for cw, cb in ((8, 32), (16, 64), (32, 128), (64, 16)):
+            lib.set_launch_shape(gop, cw, cb)
+            X = X0.clone()
+            lib.chebyshev_filter(gop, X, 7, a, b, a0)
+            assert torch.equal(ref, X), (cw, cb)
+    finally:
+        lib.set_launch_shape(gop, 0, 0)
