@@ -352,311 +352,6 @@ __global__ __launch_bounds__(256) void rowmul_mfma_kernel(double* __restrict__ X
   }
 }
 
-// ---- Cholesky of the Jacobi-scaled matrix and R^-1 = diag(d) L^-*  (one workgroup)
-template <bool CPLX>
-__global__ __launch_bounds__(1024) void chol_kernel(double* __restrict__ G, int ldg, int n, double* __restrict__ Rinv,
-                                                    double* __restrict__ dsc, int32_t* __restrict__ status) {
-  constexpr int E = CPLX ? 2 : 1;
-  __shared__ int bad;
-  __shared__ double piv;
-  const int tid = threadIdx.x;
-  auto re = [&](int i, int j) -> double& { return G[((int64_t)i * ldg + j) * E]; };
-  auto im = [&](int i, int j) -> double& { return G[((int64_t)i * ldg + j) * E + (E - 1)]; };
-  if (tid == 0) bad = -1;
-  __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) {
-    const double gii = re(i, i);
-    if (!(gii > 0.0)) atomicMax(&bad, i);
-    dsc[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
-  }
-  __syncthreads();
-  if (bad >= 0) {
-    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
-    return;
-  }
-  for (int t = tid; t < n * n; t += blockDim.x) {
-    const int i = t / n, j = t % n;
-    re(i, j) *= dsc[i] * dsc[j];
-    if (CPLX) im(i, j) *= dsc[i] * dsc[j];
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      // breakdown: a pivot of the unit-diagonal (Jacobi-scaled) Gram matrix at or below
-      // n * 2^-52, i.e. numerically rank deficient in float64
-      const double d = re(k, k);
-      if (!(d > n * 2.220446049250313e-16) || !isfinite(d)) {
-        bad = k;
-        piv = 1.0;
-      } else {
-        piv = sqrt(d);
-      }
-    }
-    __syncthreads();
-    if (bad >= 0) break;
-    const double l = piv;
-    for (int i = k + 1 + tid; i < n; i += blockDim.x) {
-      re(i, k) /= l;
-      if (CPLX) im(i, k) /= l;
-    }
-    if (tid == 0) {
-      re(k, k) = l;
-      if (CPLX) im(k, k) = 0.0;
-    }
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int t = tid; t < m * m; t += blockDim.x) {
-      const int i = k + 1 + t / m, j = k + 1 + t % m;
-      if (j > i) continue;
-      if constexpr (!CPLX) {
-        re(i, j) -= re(i, k) * re(j, k);
-      } else {
-        // G[i][j] -= L[i][k] conj(L[j][k])
-        const double ar = re(i, k), ai = im(i, k), br = re(j, k), bi = im(j, k);
-        re(i, j) -= ar * br + ai * bi;
-        im(i, j) -= ai * br - ar * bi;
-      }
-    }
-    __syncthreads();
-  }
-  if (bad >= 0) {
-    if (tid == 0) { status[0] = OEFE_ENOTSPD; status[1] = bad; }
-    return;
-  }
-  // Linv (lower) by forward substitution, one column per thread; stored in the upper
-  // part of Rinv temporarily as Rinv[i][j] = d_i conj(Linv[j][i]).
-  for (int j = tid; j < n; j += blockDim.x) {
-    // solve L y = e_j for y (entries i >= j)
-    for (int i = 0; i < j; ++i) {
-      Rinv[((int64_t)i * n + j) * E] = 0.0;  // placeholder, overwritten below
-      if (CPLX) Rinv[((int64_t)i * n + j) * E + 1] = 0.0;
-    }
-    for (int i = j; i < n; ++i) {
-      double sr = (i == j) ? 1.0 : 0.0, si = 0.0;
-      for (int kk = j; kk < i; ++kk) {
-        // y_kk stored as Rinv[j][kk] = d_j conj(Linv[kk][j]) ... keep a raw copy instead:
-        const double yr = Rinv[((int64_t)kk * n + j) * E];
-        const double yi = CPLX ? Rinv[((int64_t)kk * n + j) * E + 1] : 0.0;
-        const double lr = re(i, kk), li = CPLX ? im(i, kk) : 0.0;
-        sr -= lr * yr - li * yi;
-        si -= lr * yi + li * yr;
-      }
-      const double lii = re(i, i);
-      Rinv[((int64_t)i * n + j) * E] = sr / lii;
-      if (CPLX) Rinv[((int64_t)i * n + j) * E + 1] = si / lii;
-    }
-  }
-  __syncthreads();
-  // Rinv currently holds Linv (lower, row-major).  Transform in place to diag(d) Linv^*:
-  // out[i][j] = d_i conj(Linv[j][i]).  Swap pairs (i < j) once.
-  for (int t = tid; t < n * n; t += blockDim.x) {
-    const int i = t / n, j = t % n;
-    if (i > j) continue;
-    const double lij_r = Rinv[((int64_t)i * n + j) * E], lij_i = CPLX ? Rinv[((int64_t)i * n + j) * E + 1] : 0.0;
-    const double lji_r = Rinv[((int64_t)j * n + i) * E], lji_i = CPLX ? Rinv[((int64_t)j * n + i) * E + 1] : 0.0;
-    // new[i][j] = d_i conj(L[j][i]);  new[j][i] = d_j conj(L[i][j])
-    Rinv[((int64_t)i * n + j) * E] = dsc[i] * lji_r;
-    if (CPLX) Rinv[((int64_t)i * n + j) * E + 1] = -dsc[i] * lji_i;
-    if (i != j) {
-      Rinv[((int64_t)j * n + i) * E] = dsc[j] * lij_r;
-      if (CPLX) Rinv[((int64_t)j * n + i) * E + 1] = -dsc[j] * lij_i;
-    }
-  }
-  if (tid == 0) { status[0] = 0; status[1] = -1; }
-}
-
-// ---- cyclic Jacobi (round-robin parallel ordering), one workgroup
-template <bool CPLX>
-__device__ void jacobi_body(double* A, int n, double* __restrict__ lam, double* __restrict__ U, double* V,
-                            double* rot, int32_t* __restrict__ status, double* red, int max_sweeps) {
-  constexpr int E = CPLX ? 2 : 1;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int NN = (n % 2) ? n + 1 : n;  // padded size for the schedule
-  const int npair = NN / 2, m = NN - 1;
-  __shared__ int nrot;  // rotations applied in the current sweep
-  auto A_ = [&](int i, int j) -> double* { return A + ((int64_t)i * n + j) * E; };
-  for (int t = tid; t < n * n; t += nth) {
-    V[(int64_t)t * E] = (t / n == t % n) ? 1.0 : 0.0;
-    if (CPLX) V[(int64_t)t * E + 1] = 0.0;
-  }
-  __syncthreads();
-  int sweep = 0;
-  bool conv = false;
-  for (; sweep < max_sweeps; ++sweep) {
-    // convergence test: off-diagonal vs diagonal (squared Frobenius)
-    double off = 0, dia = 0;
-    for (int t = tid; t < n * n; t += nth) {
-      const int i = t / n, j = t % n;
-      const double* a = A_(i, j);
-      const double v = a[0] * a[0] + (CPLX ? a[E - 1] * a[E - 1] : 0.0);
-      if (i == j) dia += v;
-      else off += v;
-    }
-    red[tid] = off;
-    __syncthreads();
-    for (int s = nth / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    const double offs = red[0];
-    __syncthreads();
-    red[tid] = dia;
-    __syncthreads();
-    for (int s = nth / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    const double dias = red[0];
-    const double nrm_n = sqrt(offs + dias) / n;  // Frobenius norm / n
-    __syncthreads();
-    if (offs <= 1e-30 * dias || offs == 0.0) {
-      conv = true;
-      break;
-    }
-    if (tid == 0) nrot = 0;
-    __syncthreads();
-    for (int st = 0; st < m; ++st) {
-      // (a) rotation per pair: rot[k] = {c, s, er, ei, p, q} (er+i ei = e^{i phi})
-      for (int k = tid; k < npair; k += nth) {
-        int p, q;
-        if (k == 0) {
-          p = 0;
-          q = 1 + st % m;
-        } else {
-          p = 1 + (st + k) % m;
-          q = 1 + (st - k + m) % m;
-        }
-        if (p > q) { int t = p; p = q; q = t; }
-        double c = 1, s = 0, er = 1, ei = 0;
-        if (q < n) {
-          const double* apq = A_(p, q);
-          const double br = apq[0], bi = CPLX ? apq[E - 1] : 0.0;
-          const double r = sqrt(br * br + bi * bi);
-          const double al = A_(p, p)[0], ga = A_(q, q)[0];
-          // rotate only when the pair is coupled above float64 rounding, measured on its
-          // diagonal entries or on the matrix norm (whichever is larger)
-          if (r > 1e-300 && r > 2.220446049250313e-16 * fmax(sqrt(fabs(al * ga)), nrm_n)) {
-            atomicAdd(&nrot, 1);
-            er = br / r;
-            ei = bi / r;
-            const double tau = (ga - al) / (2.0 * r);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
-        }
-        double* R = rot + 6 * k;
-        R[0] = c; R[1] = s; R[2] = er; R[3] = ei; R[4] = p; R[5] = q;
-      }
-      __syncthreads();
-      // (b) columns: A <- A G,  G = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
-      for (int t = tid; t < n * npair; t += nth) {
-        const int r = t / npair, k = t % npair;
-        const double* R = rot + 6 * k;
-        const int p = (int)R[4], q = (int)R[5];
-        if (q >= n || R[1] == 0.0) continue;
-        const double c = R[0], s = R[1];
-        double* ap = A_(r, p);
-        double* aq = A_(r, q);
-        if constexpr (!CPLX) {
-          const double x = ap[0], y = aq[0] * R[2];  // R[2] = sign(a_pq)
-          ap[0] = x * c - y * s;
-          aq[0] = x * s + y * c;
-        } else {
-          const Z emi{R[2], -R[3]};
-          const Z x{ap[0], ap[1]}, y{aq[0], aq[1]};
-          const Z ye = zmul(y, emi);
-          ap[0] = x.r * c - ye.r * s; ap[1] = x.i * c - ye.i * s;
-          aq[0] = x.r * s + ye.r * c; aq[1] = x.i * s + ye.i * c;
-        }
-      }
-      __syncthreads();
-      // (c) rows: A <- G^* A
-      for (int t = tid; t < n * npair; t += nth) {
-        const int r = t / npair, k = t % npair;
-        const double* R = rot + 6 * k;
-        const int p = (int)R[4], q = (int)R[5];
-        if (q >= n || R[1] == 0.0) continue;
-        const double c = R[0], s = R[1];
-        double* ap = A_(p, r);
-        double* aq = A_(q, r);
-        if constexpr (!CPLX) {
-          const double x = ap[0], y = R[2] * aq[0];
-          ap[0] = c * x - s * y;
-          aq[0] = s * x + c * y;
-        } else {
-          const Z eph{R[2], R[3]};
-          const Z x{ap[0], ap[1]}, y{aq[0], aq[1]};
-          const Z ye = zmul(eph, y);
-          ap[0] = c * x.r - s * ye.r; ap[1] = c * x.i - s * ye.i;
-          aq[0] = s * x.r + c * ye.r; aq[1] = s * x.i + c * ye.i;
-        }
-      }
-      __syncthreads();
-      // (d) V <- V G ; zero the rotated pair
-      for (int t = tid; t < n * npair; t += nth) {
-        const int r = t / npair, k = t % npair;
-        const double* R = rot + 6 * k;
-        const int p = (int)R[4], q = (int)R[5];
-        if (q >= n || R[1] == 0.0) continue;
-        const double c = R[0], s = R[1];
-        double* vp = V + ((int64_t)r * n + p) * E;
-        double* vq = V + ((int64_t)r * n + q) * E;
-        if constexpr (!CPLX) {
-          const double x = vp[0], y = vq[0] * R[2];
-          vp[0] = x * c - y * s;
-          vq[0] = x * s + y * c;
-        } else {
-          const Z emi{R[2], -R[3]};
-          const Z x{vp[0], vp[1]}, y{vq[0], vq[1]};
-          const Z ye = zmul(y, emi);
-          vp[0] = x.r * c - ye.r * s; vp[1] = x.i * c - ye.i * s;
-          vq[0] = x.r * s + ye.r * c; vq[1] = x.i * s + ye.i * c;
-        }
-        if (r == 0) {
-          double* apq = A_(p, q);
-          double* aqp = A_(q, p);
-          apq[0] = 0; aqp[0] = 0;
-          if (CPLX) { apq[1] = 0; aqp[1] = 0; }
-          A_(p, p)[E - 1] = CPLX ? 0.0 : A_(p, p)[0];
-          A_(q, q)[E - 1] = CPLX ? 0.0 : A_(q, q)[0];
-        }
-      }
-      __syncthreads();
-    }
-    // a sweep that found no pair coupled above rounding: converged
-    if (nrot == 0) {
-      ++sweep;
-      conv = true;
-      break;
-    }
-  }
-  if (tid == 0) { status[0] = conv ? 0 : OEFE_ENOCONV; status[1] = sweep; }
-  // sort ascending by rank
-  for (int i = tid; i < n; i += nth) {
-    const double li = A_(i, i)[0];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double lj = A_(j, j)[0];
-      if (lj < li || (lj == li && j < i)) ++rank;
-    }
-    lam[rank] = li;
-    for (int r = 0; r < n; ++r) {
-      U[((int64_t)r * n + rank) * E] = V[((int64_t)r * n + i) * E];
-      if (CPLX) U[((int64_t)r * n + rank) * E + 1] = V[((int64_t)r * n + i) * E + 1];
-    }
-  }
-}
-
-template <bool CPLX>
-__global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, int n, double* __restrict__ lam,
-                                                      double* __restrict__ U, double* __restrict__ V,
-                                                      double* __restrict__ rot, int32_t* __restrict__ status,
-                                                      int max_sweeps) {
-  __shared__ double red[1024];
-  jacobi_body<CPLX>(A, n, lam, U, V, rot, status, red, max_sweeps);
-}
-
 // Same method for small n, in two kernels.
 // jacobi_rot_kernel (one workgroup): the matrix in LDS, upper triangle only (the lower
 // one is its conjugate transpose and is never read).  One round of the round-robin
@@ -671,7 +366,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(double* __restrict__ A, in
 // the columns in rank order.  Rows of V evolve independently, so the accumulation of
 // the eigenvectors leaves the single-workgroup kernel.
 constexpr int kJacobiRecSweeps = 40;  // sweeps the rotation record holds
-constexpr int kJacobiGlobalSweeps = 60;  // sweep limit of the global-memory version
+constexpr int kJacobiGlobalSweeps = 60;  // sweep limit of the global-memory version (jbig_eig)
 
 __device__ __forceinline__ void jacobi_pair(int st, int k, int m, int& p, int& q) {
   if (k == 0) {
@@ -1471,7 +1166,7 @@ __global__ __launch_bounds__(64) void jacobi_vec_ring_kernel(const double* __res
 // L^-1 = D^-1/2 L_1^-1.  Step k reads only column k and row k, both final after step k - 1,
 // and writes neither, so one barrier per step suffices.  Thread t keeps column k + 1 + t % n
 // of the window and the rows k + 1 + t / n + r nth / n.  Same scaling, pivots and breakdown
-// rule as chol_kernel; G is only read.
+// rule as chol_lds_kernel; G is only read.
 size_t chol_elim_lds_bytes(bool cplx, int n) { return ((size_t)n * (2 * n + 1) * (cplx ? 2 : 1) + n) * sizeof(double); }
 bool chol_elim_fits(bool cplx, int n) { return n <= 512 && chol_elim_lds_bytes(cplx, n) <= 158 * 1024; }
 
@@ -1583,7 +1278,8 @@ __global__ __launch_bounds__(1024) void chol_elim_kernel(const double* __restric
 }
 
 // ---- Cholesky of the Jacobi-scaled Gram matrix and triangular inverse in LDS (small n).
-// Same scaling, pivots and breakdown rule as chol_kernel; G is only read.
+// Jacobi scaling of the Gram matrix, pivots, and breakdown when a pivot of the scaled
+// (unit-diagonal) matrix is at or below n 2^-52; G is only read.
 template <bool CPLX>
 __global__ __launch_bounds__(512) void chol_lds_kernel(const double* __restrict__ G, int ldg, int n,
                                                        double* __restrict__ Rinv, double* __restrict__ dsc,
@@ -1863,7 +1559,16 @@ static int gram_mfma_chunks_launch(int64_t n, int nbi) {
   return std::max(1, std::min(gram_mfma_chunks(n), slots[dev] / std::max(1, nbi)));
 }
 
+// real blocks wider than one matrix-core Gram launch takes: tiled over column groups
+static bool gram_mfma_tiled(bool cplx, int na, int nb) {
+  return !cplx && na >= 16 && nb >= 16 && (na > 16 * kGramNBMax || nb > 16 * kGramNBMax);
+}
+
 size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n) {
+  if (gram_mfma_tiled(cplx, na, nb)) {
+    const int bi = (int)cdiv(na, cdiv(na, 16 * kGramNBMax)), bj = (int)cdiv(nb, cdiv(nb, 16 * kGramNBMax));
+    return (size_t)gram_mfma_chunks(n) * bi * bj * sizeof(double);
+  }
   const int nch = gram_on_mfma(cplx, na, nb) ? gram_mfma_chunks(n) : gram_chunks(n);
   return (size_t)nch * na * nb * (cplx ? 2 : 1) * sizeof(double);
 }
@@ -1894,6 +1599,19 @@ int gram(bool cplx, const double* A, int64_t lda, int na, const double* B, int64
   if (gram_scratch_bytes(cplx, na, nb, n) > scratch_bytes) return OEFE_EINVAL;
   if (gram_on_mfma(cplx, na, nb)) {
     launch_gram_mfma(A, lda, na, B, ldb, nb, n, G, ldg, scratch, s);
+    return check();
+  }
+  if (gram_mfma_tiled(cplx, na, nb)) {
+    // wide real blocks: the matrix-core Gram on every pair of column groups of at most
+    // 16 kGramNBMax columns (near-equal groups, each of at least 16 columns)
+    const int gi = (int)cdiv(na, 16 * kGramNBMax), gj = (int)cdiv(nb, 16 * kGramNBMax);
+    for (int I = 0; I < gi; ++I) {
+      const int i0 = (int)((int64_t)na * I / gi), i1 = (int)((int64_t)na * (I + 1) / gi);
+      for (int J = 0; J < gj; ++J) {
+        const int j0 = (int)((int64_t)nb * J / gj), j1 = (int)((int64_t)nb * (J + 1) / gj);
+        launch_gram_mfma(A + i0, lda, i1 - i0, B + j0, ldb, j1 - j0, n, G + (size_t)i0 * ldg + j0, ldg, scratch, s);
+      }
+    }
     return check();
   }
   const int nch = gram_chunks(n);
@@ -1949,6 +1667,122 @@ int rowmul_inplace(double* X, int64_t ldx, int64_t n, int nv, const double* R, h
   return check();
 }
 
+// ---- Cholesky factor inverse for matrices above the LDS size: the elimination of [A | I]
+// (A the Jacobi-scaled Gram matrix) with one launch per step.  Step k subtracts multiples of
+// row k from the rows below: columns k+1 .. n-1 of the left part (kept in G) and columns
+// 0 .. k of the right part (kept in Rinv, where the unit lower-triangular L_1^-1 builds up);
+// column k itself is not rewritten, so every thread reads the multiplier A_ik and row k
+// unchanged by the other threads of the launch.  The pivots D_k are A = L_1 D L_1^*'s, so
+// L^-1 = D^-1/2 L_1^-1 and R^-1 = diag(d) L^-*.  Breakdown rule as in the other Cholesky
+// kernels (a pivot of the unit-diagonal matrix at or below n 2^-52, or a non-positive
+// diagonal before scaling); flag[0] holds the first failing index (INT32_MAX: none).
+template <bool CPLX>
+__global__ __launch_bounds__(256) void cholbig_scale_kernel(double* __restrict__ G, int ldg, int n,
+                                                            double* __restrict__ Rinv, double* __restrict__ dsc,
+                                                            int32_t* __restrict__ flag) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t - (int64_t)i * n);
+  const double gii = G[((int64_t)i * ldg + i) * E], gjj = G[((int64_t)j * ldg + j) * E];
+  if (j == 0) {
+    if (!(gii > 0.0)) atomicMin(flag, i);
+    dsc[i] = gii > 0.0 ? 1.0 / sqrt(gii) : 0.0;
+  }
+  const double f = (gii > 0.0 && gjj > 0.0) ? 1.0 / (sqrt(gii) * sqrt(gjj)) : 0.0;
+  double* g = G + ((int64_t)i * ldg + j) * E;
+  g[0] = i == j ? (gii > 0.0 ? 1.0 : 0.0) : g[0] * f;
+  if (CPLX) g[1] = i == j ? 0.0 : g[1] * f;
+  double* r = Rinv + ((int64_t)i * n + j) * E;
+  r[0] = i == j ? 1.0 : 0.0;
+  if (CPLX) r[1] = 0.0;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void cholbig_step_kernel(double* __restrict__ G, int ldg, int n,
+                                                           double* __restrict__ Rinv, int k, int32_t* __restrict__ flag) {
+  constexpr int E = CPLX ? 2 : 1;
+  if (*flag != INT32_MAX) return;
+  const double d = G[((int64_t)k * ldg + k) * E];
+  if (!(d > n * 2.220446049250313e-16) || !isfinite(d)) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) atomicMin(flag, k);
+    return;
+  }
+  const int i = k + 1 + (int)blockIdx.y;  // row
+  const int c = (int)(blockIdx.x * blockDim.x + threadIdx.x);  // 0 .. n-1: left columns k+1.., then right 0..k
+  if (i >= n || c >= n) return;
+  const double* gik = G + ((int64_t)i * ldg + k) * E;
+  const double fr = gik[0] / d, fi = CPLX ? gik[1] / d : 0.0;  // multiplier A_ik / D_k
+  double* dst;
+  const double* src;
+  if (c < n - 1 - k) {
+    const int col = k + 1 + c;
+    dst = G + ((int64_t)i * ldg + col) * E;
+    src = G + ((int64_t)k * ldg + col) * E;
+  } else {
+    const int col = c - (n - 1 - k);  // 0 .. k
+    dst = Rinv + ((int64_t)i * n + col) * E;
+    src = Rinv + ((int64_t)k * n + col) * E;
+  }
+  if constexpr (!CPLX) {
+    dst[0] -= fr * src[0];
+  } else {
+    dst[0] -= fr * src[0] - fi * src[1];
+    dst[1] -= fr * src[1] + fi * src[0];
+  }
+}
+
+// R^-1[i][j] = d_i conj(L^-1[j][i]) = d_i conj(L_1^-1[j][i]) / sqrt(D_j) (i <= j), 0 below
+template <bool CPLX>
+__global__ __launch_bounds__(256) void cholbig_final_kernel(const double* __restrict__ G, int ldg, int n,
+                                                            double* __restrict__ Rinv, const double* __restrict__ dsc,
+                                                            const int32_t* __restrict__ flag, int32_t* __restrict__ status) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int bad = *flag;
+  if (t == 0) {
+    status[0] = bad != INT32_MAX ? OEFE_ENOTSPD : 0;
+    status[1] = bad != INT32_MAX ? bad : -1;
+  }
+  if (bad != INT32_MAX || t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t - (int64_t)i * n);
+  if (i > j) return;
+  double* a = Rinv + ((int64_t)i * n + j) * E;
+  double* b = Rinv + ((int64_t)j * n + i) * E;
+  const double sj = 1.0 / sqrt(G[((int64_t)j * ldg + j) * E]);
+  const double lr = b[0], li = CPLX ? b[1] : 0.0;  // L_1^-1[j][i]
+  a[0] = dsc[i] * lr * sj;
+  if (CPLX) a[1] = -dsc[i] * li * sj;
+  if (i != j) {
+    b[0] = 0.0;
+    if (CPLX) b[1] = 0.0;
+  }
+}
+
+__global__ void cholbig_init_kernel(int32_t* flag) { *flag = INT32_MAX; }
+
+static int chol_big(bool cplx, double* G, int ldg, int n, double* Rinv, double* dsc, int32_t* status, hipStream_t s) {
+  int32_t* flag = status + 2;  // the status block has room beyond {code, column}
+  hipLaunchKernelGGL(cholbig_init_kernel, dim3(1), dim3(1), 0, s, flag);
+  const unsigned g1 = (unsigned)cdiv((int64_t)n * n, 256);
+  if (cplx)
+    hipLaunchKernelGGL(cholbig_scale_kernel<true>, dim3(g1), dim3(256), 0, s, G, ldg, n, Rinv, dsc, flag);
+  else
+    hipLaunchKernelGGL(cholbig_scale_kernel<false>, dim3(g1), dim3(256), 0, s, G, ldg, n, Rinv, dsc, flag);
+  for (int k = 0; k < n; ++k) {
+    const dim3 g((unsigned)cdiv(n, 256), (unsigned)std::max(n - 1 - k, 1));
+    if (cplx)
+      hipLaunchKernelGGL(cholbig_step_kernel<true>, g, dim3(256), 0, s, G, ldg, n, Rinv, k, flag);
+    else
+      hipLaunchKernelGGL(cholbig_step_kernel<false>, g, dim3(256), 0, s, G, ldg, n, Rinv, k, flag);
+  }
+  if (cplx)
+    hipLaunchKernelGGL(cholbig_final_kernel<true>, dim3(g1), dim3(256), 0, s, G, ldg, n, Rinv, dsc, flag, status);
+  else
+    hipLaunchKernelGGL(cholbig_final_kernel<false>, dim3(g1), dim3(256), 0, s, G, ldg, n, Rinv, dsc, flag, status);
+  return check();
+}
+
 int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int32_t* status, hipStream_t s,
                         const int32_t* gate, int32_t* go) {
   if ((gate || go) && !chol_elim_fits(cplx, n)) return OEFE_EUNSUPPORTED;
@@ -1974,15 +1808,299 @@ int chol_factor_inverse(bool cplx, double* G, int ldg, int n, double* Rinv, int3
       hipLaunchKernelGGL(chol_lds_kernel<false>, dim3(1), dim3(512), lds, s, G, ldg, n, Rinv, dsc, status);
     return check();
   }
-  if (cplx)
-    hipLaunchKernelGGL(chol_kernel<true>, dim3(1), dim3(1024), 0, s, G, ldg, n, Rinv, dsc, status);
-  else
-    hipLaunchKernelGGL(chol_kernel<false>, dim3(1), dim3(1024), 0, s, G, ldg, n, Rinv, dsc, status);
-  return check();
+  return chol_big(cplx, G, ldg, n, Rinv, dsc, status, s);
 }
 
 // LDS version: the rotation record (kJacobiRecSweeps sweeps of m rounds x n/2 pairs x 4
 // doubles) and the ranks (+ the recorded sweep count); global version: V and the rotations.
+// ---- The same cyclic Jacobi for matrices above the LDS size, one launch per round.
+// The matrix and the eigenvector matrix live in global memory, each double buffered, in the
+// ring-position storage of the LDS kernels (position j holds index jacobi_ring_index(j) at a
+// sweep's start; pair k of every round sits at positions 2k, 2k + 1).  A round launch reads
+// the current buffers and writes the next ones: every thread of the matrix part takes one
+// 2x2 block (k1 <= k2), forms the rotations of its two pairs itself from the current pivot
+// entries (the same branch-free formula as the LDS kernels), and writes G_k1^* B G_k2 (and
+// its mirror) to the positions of the next round; every thread of the vector part rotates
+// the entries (2k, 2k + 1) of one row of V and moves them along the ring.  A control block
+// carries the sweep state: a norm kernel at every sweep start sets the rotation threshold,
+// and declares convergence when the off-diagonal part fell to rounding or the previous sweep
+// rotated nothing; later launches then return at once.
+struct JacobiCtl {
+  double nrm_n;     // Frobenius norm / n at the current sweep's start
+  int32_t done;     // no more rounds
+  int32_t conv;     // converged (else the sweep limit ended it)
+  int32_t buf;      // buffer that holds the matrix and V when done was set
+  int32_t sweeps;   // sweeps started
+  int32_t anyrot;   // a pair was rotated in the current sweep
+  int32_t pad;
+};
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void jbig_init_kernel(const double* __restrict__ A, int n, double* __restrict__ A0,
+                                                        double* __restrict__ V0, JacobiCtl* __restrict__ ctl) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int NN = (n % 2) ? n + 1 : n, m = NN - 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    ctl->nrm_n = 0.0;
+    ctl->done = 0;
+    ctl->conv = 0;
+    ctl->buf = 0;
+    ctl->sweeps = 0;
+    ctl->anyrot = 1;
+  }
+  if (t < (int64_t)NN * NN) {
+    const int pi = (int)(t / NN), pj = (int)(t - (int64_t)pi * NN);
+    const int i = jacobi_ring_index(pi, m), j = jacobi_ring_index(pj, m);
+    double vr = 0.0, vi = 0.0;
+    if (i < n && j < n) {
+      const double* a = A + ((size_t)min(i, j) * n + max(i, j)) * E;
+      vr = a[0];
+      if (CPLX) vi = i == j ? 0.0 : (i < j ? a[E - 1] : -a[E - 1]);
+    }
+    A0[t * E] = vr;
+    if (CPLX) A0[t * E + 1] = vi;
+  }
+  if (t < (int64_t)n * NN) {  // V = I by ring position: V[r][pos] = (index at pos == r)
+    const int r = (int)(t / NN), pj = (int)(t - (int64_t)r * NN);
+    V0[t * E] = jacobi_ring_index(pj, m) == r ? 1.0 : 0.0;
+    if (CPLX) V0[t * E + 1] = 0.0;
+  }
+}
+
+// sweep start: convergence test and the rotation threshold; one workgroup
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void jbig_norm_kernel(const double* __restrict__ A0, const double* __restrict__ A1,
+                                                         int n, int cur, int max_sweeps, JacobiCtl* __restrict__ ctl) {
+  constexpr int E = CPLX ? 2 : 1;
+  __shared__ double red[32];
+  if (ctl->done) return;
+  const int NN = (n % 2) ? n + 1 : n;
+  const double* Ac = cur ? A1 : A0;
+  const int tid = threadIdx.x;
+  double off = 0, dia = 0;
+  for (int t = tid; t < NN * NN; t += blockDim.x) {
+    const int i = t / NN, j = t - i * NN;
+    const double* a = Ac + (size_t)t * E;
+    const double v = a[0] * a[0] + (CPLX ? a[1] * a[1] : 0.0);
+    if (i == j) dia += v;
+    else off += v;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    off += __shfl_xor(off, o);
+    dia += __shfl_xor(dia, o);
+  }
+  if ((tid & 63) == 0) {
+    red[2 * (tid >> 6)] = off;
+    red[2 * (tid >> 6) + 1] = dia;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double offs = 0, dias = 0;
+  for (int w = 0; w < (int)blockDim.x / 64; ++w) {
+    offs += red[2 * w];
+    dias += red[2 * w + 1];
+  }
+  // a sweep that found no pair coupled above rounding, or an off-diagonal part at rounding:
+  // converged; the sweep limit: stopped
+  const bool conv = (ctl->sweeps > 0 && ctl->anyrot == 0) || offs <= 1e-30 * dias || offs == 0.0;
+  if (conv || ctl->sweeps >= max_sweeps) {
+    ctl->done = 1;
+    ctl->conv = conv ? 1 : 0;
+    ctl->buf = cur;
+    return;
+  }
+  ctl->nrm_n = sqrt(offs + dias) / n;
+  ctl->anyrot = 0;
+  ctl->sweeps += 1;
+}
+
+template <bool CPLX>
+__device__ __forceinline__ void jbig_table(const double* __restrict__ Ac, int NN, int npair, int m, int st, int k,
+                                           double nrm_n, Z* g, bool& on) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int p0 = 2 * k, p1 = 2 * k + 1;
+  const double a00 = Ac[((size_t)p0 * NN + p0) * E], a11 = Ac[((size_t)p1 * NN + p1) * E];
+  const Z b = jz_load<CPLX>(Ac + ((size_t)p0 * NN + p1) * E);
+  // position 2k holds the larger index q of the pair at this round (as in the LDS kernels)
+  const int sa = (k + st) % m, sb = (m - k + st) % m;
+  const bool sw = k >= 1 && sa > sb;
+  const JacobiRot R = jacobi_rotation<CPLX>(sw ? a11 : a00, sw ? a00 : a11, b.r, sw ? -b.i : b.i, nrm_n);
+  const Z g00{R.c, 0.0}, g01{R.s, 0.0}, g10{-R.s * R.er, R.s * R.ei}, g11{R.c * R.er, -R.c * R.ei};
+  g[0] = sw ? g11 : g00;
+  g[1] = sw ? g10 : g01;
+  g[2] = sw ? g01 : g10;
+  g[3] = sw ? g00 : g11;
+  on = R.on;
+  (void)npair;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void jbig_round_kernel(const double* __restrict__ Ac, double* __restrict__ An,
+                                                         const double* __restrict__ Vc, double* __restrict__ Vn,
+                                                         int n, int st, JacobiCtl* __restrict__ ctl) {
+  constexpr int E = CPLX ? 2 : 1;
+  if (ctl->done) return;
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, m = NN - 1;
+  const int nblk = npair * (npair + 1) / 2;
+  const double nrm_n = ctl->nrm_n;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nblk) {
+    // block b -> (k1, k2), k1 <= k2, row-major over the upper triangle of pairs
+    int k1 = (int)((2.0 * npair + 1.0 - sqrt((2.0 * npair + 1.0) * (2.0 * npair + 1.0) - 8.0 * (double)t)) * 0.5);
+    k1 = max(0, min(k1, npair - 1));
+    auto first = [npair](int k) { return k * npair - k * (k - 1) / 2; };
+    while (k1 > 0 && first(k1) > t) --k1;
+    while (k1 + 1 < npair && first(k1 + 1) <= t) ++k1;
+    const int k2 = k1 + (int)(t - first(k1));
+    Z u[4], v[4], bl[4], d[4];
+    bool on1, on2;
+    jbig_table<CPLX>(Ac, NN, npair, m, st, k1, nrm_n, u, on1);
+    jbig_table<CPLX>(Ac, NN, npair, m, st, k2, nrm_n, v, on2);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      bl[e] = jz_load<CPLX>(Ac + ((size_t)(2 * k1 + (e >> 1)) * NN + 2 * k2 + (e & 1)) * E);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) d[e] = jz_entry<CPLX>(u, bl, v, e >> 1, e & 1);
+    if (k1 == k2) {
+      if (on1) {  // the rotated pair; its diagonal stays real
+        d[1] = d[2] = Z{0.0, 0.0};
+        d[0].i = 0.0;
+        d[3].i = 0.0;
+        ctl->anyrot = 1;  // benign race: every writer stores 1
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = jacobi_ring_next(2 * k1 + (e >> 1), npair), q = jacobi_ring_next(2 * k2 + (e & 1), npair);
+      jz_store<CPLX>(An + ((size_t)r * NN + q) * E, d[e]);
+      if (k1 != k2) jz_store<CPLX>(An + ((size_t)q * NN + r) * E, jz_conj(d[e]));
+    }
+    return;
+  }
+  const int64_t tv = t - nblk;
+  if (tv >= (int64_t)n * npair) return;
+  // row r of V, pair k: (v_2k, v_2k+1) <- (v_2k, v_2k+1) G_k, moved along the ring
+  const int r = (int)(tv / npair), k = (int)(tv - (int64_t)r * npair);
+  Z g[4];
+  bool on;
+  jbig_table<CPLX>(Ac, NN, npair, m, st, k, nrm_n, g, on);
+  const double* vr = Vc + (size_t)r * NN * E;
+  const Z v0 = jz_load<CPLX>(vr + (size_t)(2 * k) * E), v1 = jz_load<CPLX>(vr + (size_t)(2 * k + 1) * E);
+  const Z w0 = jz_fma<CPLX>(v1, g[2], jz_mul<CPLX>(v0, g[0]));
+  const Z w1 = jz_fma<CPLX>(v1, g[3], jz_mul<CPLX>(v0, g[1]));
+  double* vn = Vn + (size_t)r * NN * E;
+  jz_store<CPLX>(vn + (size_t)jacobi_ring_next(2 * k, npair) * E, w0);
+  jz_store<CPLX>(vn + (size_t)jacobi_ring_next(2 * k + 1, npair) * E, w1);
+}
+
+// eigenvalues (ascending), U[r][rank(i)] = V[r][pos(i)], status; one workgroup
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void jbig_final_kernel(const double* __restrict__ A0, const double* __restrict__ A1,
+                                                          const double* __restrict__ V0, const double* __restrict__ V1,
+                                                          int n, double* __restrict__ lam, double* __restrict__ U,
+                                                          int32_t* __restrict__ rankbuf, const JacobiCtl* __restrict__ ctl,
+                                                          int32_t* __restrict__ status) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, m = NN - 1;
+  const int buf = ctl->buf;
+  const double* Af = buf ? A1 : A0;
+  const double* Vf = buf ? V1 : V0;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) {
+    const int q = jacobi_ring_pos(i, npair, m);
+    const double li = Af[((size_t)q * NN + q) * E];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const int qj = jacobi_ring_pos(j, npair, m);
+      const double lj = Af[((size_t)qj * NN + qj) * E];
+      if (lj < li || (lj == li && j < i)) ++rank;
+    }
+    lam[rank] = li;
+    rankbuf[i] = rank;
+  }
+  __syncthreads();
+  for (int t = tid; t < n * n; t += blockDim.x) {
+    const int r = t / n, i = t - r * n;
+    const int q = jacobi_ring_pos(i, npair, m);
+    const double* src = Vf + ((size_t)r * NN + q) * E;
+    double* dst = U + ((size_t)r * n + rankbuf[i]) * E;
+    dst[0] = src[0];
+    if (CPLX) dst[1] = src[1];
+  }
+  if (tid == 0) {
+    status[0] = ctl->conv ? 0 : OEFE_ENOCONV;
+    status[1] = ctl->sweeps;
+  }
+}
+
+size_t jbig_scratch_bytes(bool cplx, int n) {
+  const int NN = (n % 2) ? n + 1 : n, E = cplx ? 2 : 1;
+  const size_t a = (size_t)NN * NN * E * sizeof(double), v = (size_t)n * NN * E * sizeof(double);
+  return 2 * ((a + 255) / 256 * 256) + 2 * ((v + 255) / 256 * 256) + 256 + ((size_t)n * sizeof(int32_t) + 255) / 256 * 256;
+}
+
+int jbig_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s,
+             int max_sweeps) {
+  const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, m = NN - 1, E = cplx ? 2 : 1;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  char* p = (char*)scratch;
+  double* Ab[2];
+  double* Vb[2];
+  Ab[0] = (double*)p; p += al((size_t)NN * NN * E * sizeof(double));
+  Ab[1] = (double*)p; p += al((size_t)NN * NN * E * sizeof(double));
+  Vb[0] = (double*)p; p += al((size_t)n * NN * E * sizeof(double));
+  Vb[1] = (double*)p; p += al((size_t)n * NN * E * sizeof(double));
+  JacobiCtl* ctl = (JacobiCtl*)p; p += 256;
+  int32_t* rankbuf = (int32_t*)p;
+  const int64_t ninit = std::max<int64_t>((int64_t)NN * NN, (int64_t)n * NN);
+  if (cplx)
+    hipLaunchKernelGGL(jbig_init_kernel<true>, dim3((unsigned)cdiv(ninit, 256)), dim3(256), 0, s, A, n, Ab[0], Vb[0], ctl);
+  else
+    hipLaunchKernelGGL(jbig_init_kernel<false>, dim3((unsigned)cdiv(ninit, 256)), dim3(256), 0, s, A, n, Ab[0], Vb[0], ctl);
+  const int nblk = npair * (npair + 1) / 2;
+  const unsigned grid = (unsigned)cdiv((int64_t)nblk + (int64_t)n * npair, 256);
+  // a pinned host word per host thread for the convergence flag (allocated once, kept)
+  static thread_local int32_t* done_h = nullptr;
+  if (!done_h && hipHostMalloc((void**)&done_h, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) done_h = nullptr;
+  int cur = 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    if (cplx)
+      hipLaunchKernelGGL(jbig_norm_kernel<true>, dim3(1), dim3(1024), 0, s, Ab[0], Ab[1], n, cur, max_sweeps, ctl);
+    else
+      hipLaunchKernelGGL(jbig_norm_kernel<false>, dim3(1), dim3(1024), 0, s, Ab[0], Ab[1], n, cur, max_sweeps, ctl);
+    // after the first sweeps, look whether the sweep start found convergence before queueing
+    // its rounds (later launches would return at once, but each costs a launch)
+    if (sw >= 2 && done_h) {
+      if (hipMemcpyAsync(done_h, &ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        break;
+      if (*done_h) break;
+    }
+    for (int st = 0; st < m; ++st) {
+      if (cplx)
+        hipLaunchKernelGGL(jbig_round_kernel<true>, dim3(grid), dim3(256), 0, s, Ab[cur], Ab[cur ^ 1], Vb[cur],
+                           Vb[cur ^ 1], n, st, ctl);
+      else
+        hipLaunchKernelGGL(jbig_round_kernel<false>, dim3(grid), dim3(256), 0, s, Ab[cur], Ab[cur ^ 1], Vb[cur],
+                           Vb[cur ^ 1], n, st, ctl);
+      cur ^= 1;
+    }
+  }
+  // the state after the last sweep (the limit, or a convergence not yet declared)
+  if (cplx)
+    hipLaunchKernelGGL(jbig_norm_kernel<true>, dim3(1), dim3(1024), 0, s, Ab[0], Ab[1], n, cur, 0, ctl);
+  else
+    hipLaunchKernelGGL(jbig_norm_kernel<false>, dim3(1), dim3(1024), 0, s, Ab[0], Ab[1], n, cur, 0, ctl);
+  if (cplx)
+    hipLaunchKernelGGL(jbig_final_kernel<true>, dim3(1), dim3(1024), 0, s, Ab[0], Ab[1], Vb[0], Vb[1], n, lam, U,
+                       rankbuf, ctl, status);
+  else
+    hipLaunchKernelGGL(jbig_final_kernel<false>, dim3(1), dim3(1024), 0, s, Ab[0], Ab[1], Vb[0], Vb[1], n, lam, U,
+                       rankbuf, ctl, status);
+  return check();
+}
+
 static bool jacobi_in_lds(bool cplx, int n) {
   const int npair = (n + 1) / 2;
   return jacobi_rot_lds_bytes(cplx, n) <= 158 * 1024 && npair * (npair + 1) / 2 <= 3 * 1024;  // 160 KB of LDS per workgroup
@@ -1990,11 +2108,10 @@ static bool jacobi_in_lds(bool cplx, int n) {
 
 size_t jacobi_scratch_bytes(bool cplx, int n) {
   const int NN = (n % 2) ? n + 1 : n;
-  const size_t glob = ((size_t)n * n * (cplx ? 2 : 1) + 6 * (size_t)(NN / 2 + 1)) * sizeof(double);
-  if (!jacobi_in_lds(cplx, n)) return glob;
+  if (!jacobi_in_lds(cplx, n)) return jbig_scratch_bytes(cplx, n);
   const size_t recb = (size_t)kJacobiRecSweeps * (NN - 1) * (NN / 2) * 4 * sizeof(double) +
                       ((size_t)n + 1) * sizeof(int32_t) + 256;
-  return std::max(glob, recb);
+  return recb;
 }
 
 int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratch, int32_t* status, hipStream_t s,
@@ -2032,15 +2149,7 @@ int jacobi_eig(bool cplx, double* A, int n, double* lam, double* U, double* scra
     }
     return check();
   }
-  double* V = scratch;
-  double* rot = scratch + (size_t)n * n * (cplx ? 2 : 1);
-  if (cplx)
-    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(1024), 0, s, A, n, lam, U, V, rot, status,
-                       max_sweeps > 0 ? max_sweeps : kJacobiGlobalSweeps);
-  else
-    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(1024), 0, s, A, n, lam, U, V, rot, status,
-                       max_sweeps > 0 ? max_sweeps : kJacobiGlobalSweeps);
-  return check();
+  return jbig_eig(cplx, A, n, lam, U, scratch, status, s, max_sweeps > 0 ? max_sweeps : kJacobiGlobalSweeps);
 }
 
 int max_offdiag_identity(bool cplx, const double* G, int n, double* err, hipStream_t s, const int32_t* status,

@@ -505,3 +505,61 @@ def test_filter_bitwise_across_launch_shapes_and_runs(lib, dt):
             assert torch.equal(ref, X), (cw, cb)
     finally:
         lib.set_launch_shape(gop, 0, 0)
+
+
+@pytest.mark.parametrize("name,kvec,nv", [("diamond_nc4", None, 150), ("diamond_nc4", None, 161),
+                                          ("diamond_nc4", None, 320), ("p3", (-0.4, 0.25, 0.1), 110)])
+def test_rayleigh_ritz_large_blocks(lib, name, kvec, nv):
+    """Projected matrices above the LDS size (real from 141 columns, complex from 100): the Jacobi
+    with one launch per round in global memory, the column-group-tiled matrix-core Gram and the
+    eliminated Cholesky of CholGS; Ritz values and multiplet subspaces against the oracle."""
+    import torch
+    base = SYSTEMS[name]()
+    sysm = base if kvec is None else base.with_k(np.array(kvec))
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    rng = np.random.default_rng(nv)
+    X = rng.uniform(-1, 1, (op.n_tot, nv))
+    if kvec is not None:
+        X = X + 1j * rng.uniform(-1, 1, (op.n_tot, nv))
+    # two filter degrees so that the projected matrix has a spread spectrum, as in a pass
+    lam = och.lanczos_bounds(op.apply, wl.lanczos_start(op.n_tot, 2), 10)
+    Y = och.chebyshev_filter(op.apply, X, 2, 0.5 * (lam[0] + lam[1]), lam[1], lam[0])
+    Q, _ = och.cholgs(Y)
+    th, Xr = och.rayleigh_ritz(op.apply, Q)
+    Qd = _dev(Q)
+    st = torch.zeros(2, dtype=torch.int32, device="cuda")
+    thg = lib.rayleigh_ritz(gop, Qd, st).cpu().numpy()
+    sth = st.cpu().tolist()
+    assert sth[0] == 0 and 1 <= sth[1] <= 60, sth
+    assert np.abs(thg - th).max() < 1e-10 * max(1, np.abs(th).max())
+    assert _multiplet_angles(th, Xr, Qd.cpu().numpy()) < 1e-8
+    # CholGS of the filtered block on the same path: orthonormal, same span as the oracle's Q
+    Yd = _dev(Y)
+    lib.cholgs(gop, Yd)
+    Qg = Yd.cpu().numpy()
+    assert np.abs(np.conj(Qg.T) @ Qg - np.eye(nv)).max() < 1e-12
+    assert np.abs(Qg - Q @ (np.conj(Q.T) @ Qg)).max() < 1e-9
+    # the eigensolver's sweep limit on this path
+    try:
+        lib.set_eig_sweep_limit(gop, 1)
+        lib.rayleigh_ritz(gop, _dev(Q), st)
+        assert st.cpu().tolist() == [-5, 1]
+    finally:
+        lib.set_eig_sweep_limit(gop, 0)
+
+
+def test_cholgs_large_block_breakdown(lib):
+    """A repeated column in a 150-column block: the eliminated Cholesky reports its index."""
+    sysm = SYSTEMS["diamond_nc4"]()
+    gop = lib.Operator(sysm)
+    rng = np.random.default_rng(9)
+    X = rng.uniform(-1, 1, (gop.n_tot, 150))
+    X[:, 97] = X[:, 12]
+    with pytest.raises(lib.OefeError) as ei:
+        lib.cholgs(gop, _dev(X))
+    assert ei.value.code == -4
+    Xo = X.copy()
+    with pytest.raises(och.CholeskyBreakdown) as eo:
+        och.cholgs(Xo)
+    assert f"column {eo.value.column}" in str(ei.value)
