@@ -1124,7 +1124,7 @@ constexpr size_t node_lds_bytes(int fpmax) {
 template <typename T, int NB>
 __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBatch<T> kb, int nc, int p, int n, int P1,
                                                                CellCoef<T> cf, const int32_t* __restrict__ tile_fptr,
-                                                               const int32_t* __restrict__ tile_fns, int N) {
+                                                               const int32_t* __restrict__ tile_fns, int N, int ncb) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
   constexpr int TR = kTileRows, CBW = NB * 16, XS = lds_row_stride(CBW);
@@ -1132,11 +1132,16 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   extern __shared__ unsigned char smem_raw[];
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
-  const int cb0 = blockIdx.y * CBW;
+  // launch order: the column blocks of a tile are consecutive in L, and each XCD (workgroups
+  // bk = x mod 8) takes a contiguous range of L, so the column blocks that read the same
+  // coupling block and x rows share one L2
+  const int nbk = gridDim.x, bk = blockIdx.x, nb8 = nbk & ~7;
+  const int L = bk < nb8 ? (bk & 7) * (nb8 >> 3) + (bk >> 3) : bk;
+  const int t = L / ncb;
+  const int cb0 = (L - t * ncb) * CBW;
   if (cb0 >= ncr) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int t = blockIdx.x;
   const int g0 = t * TR;
   const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
   const int HS = lds_row_stride(FP);
@@ -1957,9 +1962,9 @@ template <typename T, int NB>
 void launch_node_fused_nb(const oefe_op_s* op, const KBatch<T>& kb, int ncb, hipStream_t s) {
   const size_t lds = node_lds_bytes<T, NB>(op->n_enr > 0 ? op->tile_fpmax : 0);
   if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_node_fused_kernel<T, NB>), lds) != hipSuccess) return;
-  hipLaunchKernelGGL((fe_node_fused_kernel<T, NB>), dim3((unsigned)cdiv(op->N, kTileRows), (unsigned)ncb,
+  hipLaunchKernelGGL((fe_node_fused_kernel<T, NB>), dim3((unsigned)(cdiv(op->N, kTileRows) * ncb), 1u,
                      (unsigned)kb.nk), dim3(256), lds, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op),
-                     op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N);
+                     op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N, ncb);
 }
 
 template <typename T>
