@@ -331,28 +331,33 @@ int upload_operator(oefe_op_s* op, std::string& err) {
         for (int f = 0; f < B.nf; ++f) fr_fn[k + f] = B.fn0 + f;
       }
     }
-    // enrichment tiles: union of functions over kTileRows consecutive rows
+    // enrichment tiles (blocks of 16 x 2 x 2 FE nodes, tile_node): union of functions over the rows
     {
-      op->n_tiles = (op->N + kTileRows - 1) / kTileRows;
+      op->n_tiles = tile_count(op->n);
       std::vector<int32_t> tfptr(op->n_tiles + 1, 0), tfns;
       std::vector<int32_t> slot(op->n_enr, -1);
       op->csr_to_tile.assign(op->fr_nnz, 0);
       int fpmax = 0;
       for (int64_t t = 0; t < op->n_tiles; ++t) {
-        const int64_t g0 = t * kTileRows, g1 = std::min<int64_t>(op->N, g0 + kTileRows);
         std::vector<int32_t> fl;
-        for (int64_t g = g0; g < g1; ++g)
+        for (int r = 0; r < kTileRows; ++r) {
+          const int g = tile_node((int)t, r, op->n);
+          if (g < 0) continue;
           for (int64_t k = fr_ptr[g]; k < fr_ptr[g + 1]; ++k)
             if (slot[fr_fn[k]] < 0) {
               slot[fr_fn[k]] = 0;
               fl.push_back(fr_fn[k]);
             }
+        }
         std::sort(fl.begin(), fl.end());
         const int F = (int)fl.size(), FP = (F + 3) / 4 * 4;
         for (int j = 0; j < F; ++j) slot[fl[j]] = j;
-        for (int64_t g = g0; g < g1; ++g)
+        for (int r = 0; r < kTileRows; ++r) {
+          const int g = tile_node((int)t, r, op->n);
+          if (g < 0) continue;
           for (int64_t k = fr_ptr[g]; k < fr_ptr[g + 1]; ++k)
-            op->csr_to_tile[k] = (int64_t)tfptr[t] * kTileRows + (g - g0) * FP + slot[fr_fn[k]];
+            op->csr_to_tile[k] = (int64_t)tfptr[t] * kTileRows + (int64_t)r * FP + slot[fr_fn[k]];
+        }
         for (int j = 0; j < FP; ++j) tfns.push_back(j < F ? fl[j] : -1);
         for (int32_t f : fl) slot[f] = -1;
         tfptr[t + 1] = tfptr[t] + FP;
@@ -363,7 +368,7 @@ int upload_operator(oefe_op_s* op, std::string& err) {
       // the node-stage kernels hold one tile's dense block in LDS
       if (fpmax > kTileFunctionsMax) {
         err = "enrichment too dense for the node stage: a tile of " + std::to_string(kTileRows) +
-              " FE rows couples to " + std::to_string(fpmax) + " functions (at most " +
+              " FE nodes (a 16 x 2 x 2 block) couples to " + std::to_string(fpmax) + " functions (at most " +
               std::to_string(kTileFunctionsMax) + ")";
         return OEFE_EINVAL;
       }

@@ -15,6 +15,23 @@ namespace oefe {
 
 constexpr int kMaxP1 = 5;  // supported GLL nodes per edge: 3, 4, 5 (degree 2..4)
 constexpr int kTileRows = 64;  // FE rows per enrichment tile
+
+// Enrichment coupling tiles: tile t is the block of 16 x 2 x 2 FE nodes starting at node
+// (16 bx, 2 by, 2 bz), t = bx + nbx (by + nby bz), nbx = ceil(n / 16), nby = ceil(n / 2)
+// (n nodes per edge); its row r is the node (16 bx + r % 16, 2 by + (r / 16) % 2,
+// 2 bz + r / 32), or none (-1) past the mesh.  Such a block couples to fewer enrichment
+// functions than 64 consecutive nodes of one x-line, and each 16-row group (one wave of the
+// node stage) still lies on one x-line, where every node has the same slots in y and z.
+__host__ __device__ inline int tile_count(int n) {
+  const int nbx = (n + 15) >> 4, nby = (n + 1) >> 1;
+  return nbx * nby * nby;
+}
+__host__ __device__ inline int tile_node(int t, int r, int n) {
+  const int nbx = (n + 15) >> 4, nby = (n + 1) >> 1;
+  const int bx = t % nbx, rest = t / nbx, by = rest % nby, bz = rest / nby;
+  const int ix = 16 * bx + (r & 15), iy = 2 * by + ((r >> 4) & 1), iz = 2 * bz + (r >> 5);
+  return (ix < n && iy < n && iz < n) ? ix + n * (iy + n * iz) : -1;
+}
 // enrichment functions one tile may couple to: the node-stage kernels stage a tile's dense
 // block (complex: two planes of kTileRows x (F + 1) float64) in 150 KB of LDS
 constexpr int kTileFunctionsMax = 144;

@@ -754,7 +754,7 @@ __global__ __launch_bounds__(768) void fe_cell_bf16_kernel(KBatch<float> kb, con
 // critical path:
 //
 // fe_coupling_kernel (side stream, beside the cell stage; needs only X and Z^O):
-//   for each tile t of kTileRows consecutive FE rows and each group of 16 NBW real columns
+//   for each tile t of kTileRows FE rows (a 16 x 2 x 2 node block) and each group of 16 NBW real columns
 //     part_t = Ht_t^* X_t              -> per-tile partial of W' (reduced later)
 //     out_t  = alpha Ht_t Z^O - beta prev_t
 //   (Ht_t: the tile's dense block of m^-1/2 H^co) on the matrix cores (16x16x4 MFMA,
@@ -806,8 +806,8 @@ constexpr size_t coupling_lds_bytes(int fpmax) {
 // pc[q][nb] += Ht_t[r][m0 + 16 q + .]^* x[r][cols of block nb], k-steps of 4 rows with the
 // x loads of 4 k-steps issued ahead of their MFMAs; Ht_t from LDS (planes hs[e])
 template <typename T, int NQ, int NBW, bool CPLX>
-__device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __restrict__ x, int64_t ldx, int g0,
-                                              int N, int FP, int m0, const int (&colc)[NBW], int li, int lk,
+__device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __restrict__ x, int64_t ldx, int t,
+                                              int n, int FP, int m0, const int (&colc)[NBW], int li, int lk,
                                               typename Mfma<T>::V4 (&pc)[4][NBW]) {
   using M = Mfma<T>;
   constexpr int TR = kTileRows, E = CPLX ? 2 : 1, KB = 4;
@@ -825,8 +825,9 @@ __device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __re
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       const int r = (ks0 + j) * 4 + lk;
-      const bool rok = g0 + r < N;
-      const int64_t g = rok ? g0 + r : N - 1;
+      const int gt = tile_node(t, r, n);
+      const bool rok = gt >= 0;
+      const int64_t g = rok ? gt : 0;
 #pragma unroll
       for (int nb = 0; nb < NBW; ++nb) {
         // multiply by 1 or 0 rather than select: keeps the load unconditional and batched
@@ -855,7 +856,7 @@ __device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __re
 
 template <typename T, int NBW, bool CPLX>
 __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBatch<T> kb, const int32_t* __restrict__ tile_fptr,
-                                                          const int32_t* __restrict__ tile_fns, int N) {
+                                                          const int32_t* __restrict__ tile_fns, int n) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
   constexpr int TR = kTileRows, E = CPLX ? 2 : 1, RB = TR / 16, HPT = 8;
@@ -864,12 +865,11 @@ __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBat
   const int ncr = P.ncr;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   const int t = blockIdx.x;
-  const int g0 = t * TR;
   const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;  // FP: a multiple of 4
   const int HS = coupling_row_stride(FP);
   T* hs = reinterpret_cast<T*>(smem_raw);                   // [E][TR][HS]
   int32_t* fs = reinterpret_cast<int32_t*>(hs + E * TR * HS);  // [FP]
-  const T* __restrict__ tv = P.tv + (int64_t)f0 * TR * E;   // [TR][FP][E], zero rows past N
+  const T* __restrict__ tv = P.tv + (int64_t)f0 * TR * E;   // [TR][FP][E], zero rows past the mesh
   const T* __restrict__ x = P.x;
   const T* __restrict__ zo = P.zo;  // [n_enr][ncr]
   const int64_t ldx = P.ldx, ldo = P.ldo;
@@ -917,10 +917,10 @@ __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBat
         for (int nb = 0; nb < NBW; ++nb) pc[q][nb] = V4{0, 0, 0, 0};
       const int nq = min(4, (FP - m0 + 15) / 16);
       switch (nq) {
-        case 4: coupling_part<T, 4, NBW, CPLX>(hs, HS, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
-        case 3: coupling_part<T, 3, NBW, CPLX>(hs, HS, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
-        case 2: coupling_part<T, 2, NBW, CPLX>(hs, HS, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
-        default: coupling_part<T, 1, NBW, CPLX>(hs, HS, x, ldx, g0, N, FP, m0, colc, li, lk, pc); break;
+        case 4: coupling_part<T, 4, NBW, CPLX>(hs, HS, x, ldx, t, n, FP, m0, colc, li, lk, pc); break;
+        case 3: coupling_part<T, 3, NBW, CPLX>(hs, HS, x, ldx, t, n, FP, m0, colc, li, lk, pc); break;
+        case 2: coupling_part<T, 2, NBW, CPLX>(hs, HS, x, ldx, t, n, FP, m0, colc, li, lk, pc); break;
+        default: coupling_part<T, 1, NBW, CPLX>(hs, HS, x, ldx, t, n, FP, m0, colc, li, lk, pc); break;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -986,7 +986,7 @@ __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBat
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t g = min(g0 + rb * 16 + M::row(lane, v), N - 1);
+          const int64_t g = max(tile_node(t, rb * 16 + M::row(lane, v), n), 0);
 #pragma unroll
           for (int nb = 0; nb < NBW; ++nb) pv[rb][v][nb] = beta * P.prev[g * ldo + colc[nb]];
         }
@@ -1002,8 +1002,8 @@ __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBat
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gv = g0 + rb * 16 + M::row(lane, v);
-        if (gv >= N) continue;
+        const int gv = tile_node(t, rb * 16 + M::row(lane, v), n);
+        if (gv < 0) continue;
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb)
           if (colok[nb]) P.out[(int64_t)gv * ldo + colc[nb]] = alpha * acc[rb][nb][v] - pv[rb][v][nb];
@@ -1100,7 +1100,7 @@ __device__ __forceinline__ void assemble_one(const KP<T>& P, int64_t i, int nel,
 }
 
 // Node stage of real operators in one kernel, fe_node_fused_kernel: one workgroup (4
-// waves) per tile of kTileRows FE rows x 16 NB real columns computes part, the slot
+// waves) per tile of kTileRows FE rows (a 16 x 2 x 2 node block) x 16 NB real columns computes part, the slot
 // gather and out = alpha (m^-1/2 sum_slots(Y) + Ht_t Z^O - c x) - beta prev.  Order within
 // the workgroup: one batch of loads (x tile, H tile, function list; float32 also the
 // first slot pair of the gather, which lands during the matrix-core phase), part on the
@@ -1115,16 +1115,30 @@ constexpr int lds_row_stride(int w) { return w + (((16 - w % 32) % 32) + 32) % 3
 
 constexpr int kNodeNBMax = 5;  // 16-column blocks per fused node workgroup (80 real columns: no spills)
 
+// Row stride of the coupling block in LDS for a tile of FP functions: padded to 16 mod 32
+// (lds_row_stride) unless that would keep two workgroups from sharing a CU's 160 KB of LDS;
+// then the largest odd stride that fits (hs_cap, at least FP).
+template <typename T, int NB>
+constexpr int node_hs_cap(int fpmax) {
+  const int budget = (80 * 1024 - 512) / (int)sizeof(T);  // elements per workgroup
+  const int cap = (budget - kTileRows * lds_row_stride(NB * 16) - fpmax * (int)sizeof(int32_t) / (int)sizeof(T)) /
+                  kTileRows;
+  return (cap & 1) ? cap : cap - 1;
+}
+__host__ __device__ constexpr int node_hs(int fp, int hs_cap) {
+  return lds_row_stride(fp) <= hs_cap || hs_cap < fp ? lds_row_stride(fp) : hs_cap;
+}
 template <typename T, int NB>
 constexpr size_t node_lds_bytes(int fpmax) {
-  return (size_t)kTileRows * (lds_row_stride(NB * 16) + lds_row_stride(fpmax)) * sizeof(T) +
+  return (size_t)kTileRows * (lds_row_stride(NB * 16) + node_hs(fpmax, node_hs_cap<T, NB>(fpmax))) * sizeof(T) +
          (size_t)fpmax * sizeof(int32_t);
 }
 
 template <typename T, int NB>
 __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBatch<T> kb, int nc, int p, int n, int P1,
                                                                CellCoef<T> cf, const int32_t* __restrict__ tile_fptr,
-                                                               const int32_t* __restrict__ tile_fns, int N, int ncb) {
+                                                               const int32_t* __restrict__ tile_fns, int N, int ncb,
+                                                               int hs_cap) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
   constexpr int TR = kTileRows, CBW = NB * 16, XS = lds_row_stride(CBW);
@@ -1142,10 +1156,9 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   if (cb0 >= ncr) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int g0 = t * TR;
   const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
-  const int HS = lds_row_stride(FP);
-  T* xs = reinterpret_cast<T*>(smem_raw);  // [TR][XS]: x rows of the tile (zero past N), later Z^O rows
+  const int HS = node_hs(FP, hs_cap);
+  T* xs = reinterpret_cast<T*>(smem_raw);  // [TR][XS]: x rows of the tile (zero past the mesh), later Z^O rows
   T* hs = xs + TR * XS;                     // [TR][HS]: the tile's block
   int32_t* fs = reinterpret_cast<int32_t*>(hs + __umul24(TR, HS));  // [FP]: enrichment function of each tile column
   const T* __restrict__ tv = P.tv + (int64_t)f0 * TR;  // [TR][FP]
@@ -1182,9 +1195,9 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   T msc[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int gv = g0 + w * 16 + M::row(lane, v);
-    ok[v] = gv < N;
-    const int g = ok[v] ? gv : N - 1;
+    const int gv = tile_node(t, w * 16 + M::row(lane, v), n);
+    ok[v] = gv >= 0;
+    const int g = ok[v] ? gv : 0;
     gc[v] = g;
     const int iz = g / (n * n), rem = g - iz * n * n, iy = rem / n, ix = rem - iy * n;
     const int qx = ix / p, rx = ix - qx * p, qy = iy / p, ry = iy - qy * p, qz = iz / p, rz = iz - qz * p;
@@ -1216,10 +1229,17 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   // rows tr + 16 i (i < TR / 16) and columns tc + 16 j (j < NB), element i NB + j
   static_assert(TR == 64 && XPT == 4 * NB, "staging layout assumes 64-row tiles");
   const int tr = (int)threadIdx.x >> 4, tc = (int)threadIdx.x & 15;
-  // tile rows and columns past N / ncr are clamped for the loads (their values are not used)
-  const int rmax = N - 1 - g0, cmax = ncr - 1 - cb0;
-  const T* __restrict__ xt = x + (int64_t)g0 * ldx + cb0;  // 32-bit offsets below: r ldx + c
-  const unsigned ldx32 = (unsigned)ldx;
+  // tile rows past the mesh and columns past ncr are clamped for the loads (their values are
+  // not used); the staging rows of this thread: tr + 16 i
+  const int cmax = ncr - 1 - cb0;
+  const T* xrow[4];
+  bool rowok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gr = tile_node(t, tr + 16 * i, n);
+    rowok[i] = gr >= 0;
+    xrow[i] = x + (int64_t)(rowok[i] ? gr : 0) * ldx + cb0;
+  }
   // the H tile [TR][FP] on the same map, HJ 16-column groups per batch: rows tr + 16 i,
   // columns jc0 + tc + 16 j (past FP: clamped loads, no store)
   constexpr int HJ = HPT / 4;
@@ -1246,9 +1266,8 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
     T xv[XPT], hv[HPT];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const unsigned ro = __umul24((unsigned)min(tr + 16 * i, rmax), ldx32);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) xv[i * NB + j] = xt[ro + (unsigned)min(tc + 16 * j, cmax)];
+      for (int j = 0; j < NB; ++j) xv[i * NB + j] = xrow[i][min(tc + 16 * j, cmax)];
     }
     if (FP > 0) hload(0, hv);
     const int32_t fv = (int)threadIdx.x < FP ? tile_fns[f0 + threadIdx.x] : 0;
@@ -1269,7 +1288,7 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) xs[(tr + 16 * i) * XS + tc + 16 * j] = tr + 16 * i <= rmax ? xv[i * NB + j] : T(0);
+      for (int j = 0; j < NB; ++j) xs[(tr + 16 * i) * XS + tc + 16 * j] = rowok[i] ? xv[i * NB + j] : T(0);
     if (FP > 0) hstore(0, hv);
   }
   // the rest of the H tile
@@ -1937,7 +1956,7 @@ void launch_coupling_w(const oefe_op_s* op, const KBatch<T>& kb, hipStream_t s) 
   const size_t lds = coupling_lds_bytes<T, CPLX>(op->tile_fpmax);
   if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_coupling_kernel<T, NBW, CPLX>), lds) != hipSuccess) return;
   hipLaunchKernelGGL((fe_coupling_kernel<T, NBW, CPLX>), dim3((unsigned)op->n_tiles, 1, (unsigned)kb.nk), dim3(256),
-                     lds, s, kb, op->d.tile_fptr, op->d.tile_fns, (int)op->N);
+                     lds, s, kb, op->d.tile_fptr, op->d.tile_fns, op->n);
 }
 
 // nbw: 16-column blocks per coupling wave (1 or 2)
@@ -1962,9 +1981,10 @@ template <typename T, int NB>
 void launch_node_fused_nb(const oefe_op_s* op, const KBatch<T>& kb, int ncb, hipStream_t s) {
   const size_t lds = node_lds_bytes<T, NB>(op->n_enr > 0 ? op->tile_fpmax : 0);
   if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_node_fused_kernel<T, NB>), lds) != hipSuccess) return;
-  hipLaunchKernelGGL((fe_node_fused_kernel<T, NB>), dim3((unsigned)(cdiv(op->N, kTileRows) * ncb), 1u,
+  hipLaunchKernelGGL((fe_node_fused_kernel<T, NB>), dim3((unsigned)((int64_t)tile_count(op->n) * ncb), 1u,
                      (unsigned)kb.nk), dim3(256), lds, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op),
-                     op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N, ncb);
+                     op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N, ncb,
+                     node_hs_cap<T, NB>(op->n_enr > 0 ? op->tile_fpmax : 0));
 }
 
 template <typename T>
