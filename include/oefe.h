@@ -110,13 +110,20 @@ int oefe_op_destroy(oefe_op op);
  * dims must hold 11 entries. */
 int oefe_op_dims(oefe_op op, int64_t* dims);
 
-/* Replace the potential at the quadrature points: V[n_cells * nq] (cell-major,
- * point index qx + (p+1) qy + (p+1)^2 qz), host memory.  Rebuilds the potential
- * parts of H^cc, H^co, H^oo (the overlap and S do not depend on V).  Synchronous. */
-int oefe_op_set_potential(oefe_op op, const double* V_host);
+/* Replace the potential at the quadrature points: V device float64 [n_cells * nq]
+ * (cell-major, point index qx + (p+1) qy + (p+1)^2 qz), read in stream order.
+ * Rebuilds on the device, queued on `stream` without a host wait, the potential
+ * parts of the operator (eqnHOEFEelelements): W V at the quadrature points for the
+ * H^cc cell stage, H^co = kinetic part + sum over the cells of a row's node of
+ * B^T diag(W V) N^O (pre-scaled by m^-1/2, in every layout the kernels read) and
+ * H^oo = kinetic part + sum W V conj(N^O) N^O; the overlap and S do not depend on
+ * V.  Compute calls on other streams must be ordered after it by the caller.
+ * Errors: EINVAL (null V, diagonal operator), EDEVICE. */
+int oefe_op_set_potential(oefe_op op, const double* V, oefe_stream stream);
 
 /* Copy the current potential and the quadrature weights W_{e,q} to host
- * arrays of n_cells * nq doubles (either pointer may be NULL). */
+ * arrays of n_cells * nq doubles (either pointer may be NULL).  Waits for the
+ * device (so a queued oefe_op_set_potential is included). */
 int oefe_op_get_potential(oefe_op op, double* V_host, double* W_host);
 
 /* Copy S = (M^oo)^-1/2 (n_enr^2, row-major; complex interleaved) and the

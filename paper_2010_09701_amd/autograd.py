@@ -6,11 +6,11 @@ Backward (one library call, band_energy_grad):
   dE/dX       = 2 Ht X diag(f)                          (PyTorch's convention for complex X)
 
 V is the potential at the quadrature points ([n_cells, nq], float64, host or
-device); the forward pass loads it into the operator (oefe_op_set_potential).
+device); the forward pass loads it into the operator (oefe_op_set_potential,
+which rebuilds the potential-dependent operator data on the device).
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from . import oefe
@@ -19,7 +19,7 @@ from . import oefe
 class BandEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, X: torch.Tensor, V: torch.Tensor, f: torch.Tensor, op: "oefe.Operator"):
-        op.set_potential(V.detach().to("cpu", torch.float64).numpy())
+        op.set_potential(V.detach())
         need_dV = ctx.needs_input_grad[1]
         need_dX = ctx.needs_input_grad[0]
         E, dV, dX = oefe.band_energy_grad(op, X.detach(), f.detach(), want_dV=need_dV, want_dX=need_dX)

@@ -416,6 +416,98 @@ int upload_operator(oefe_op_s* op, std::string& err) {
       }
       off += (int64_t)B.cells.size();
     }
+    // ---- structure of the device potential rebuild (oefe_op_set_potential)
+    {
+      const int P1 = op->P1, p = op->p, n = op->n, nc = op->nc;
+      std::vector<int64_t> boff(nb + 1, 0);
+      for (int b = 0; b < nb; ++b) boff[b + 1] = boff[b] + (int64_t)op->blocks[b].cells.size();
+      std::vector<int32_t> cf_cell(boff[nb]);
+      for (int b = 0; b < nb; ++b)
+        for (size_t ci = 0; ci < op->blocks[b].cells.size(); ++ci) cf_cell[boff[b] + ci] = (int32_t)op->blocks[b].cells[ci];
+      // block row -> (flattened support cell, local node) pairs, ordered by cell then node
+      std::vector<int32_t> row_blk(op->n_hrows);
+      std::vector<int64_t> rpos(op->n_hrows), rr_ptr(op->n_hrows + 1, 0);
+      std::vector<int32_t> local(op->N, -1);
+      for (int b = 0; b < nb; ++b) {
+        auto& B = op->blocks[b];
+        for (size_t r = 0; r < B.rows.size(); ++r) {
+          row_blk[rptr[b] + r] = b;
+          rpos[rptr[b] + r] = op->fr_pos[b][r];
+        }
+      }
+      auto node_of = [&](int64_t e, int a) {
+        const int cx = (int)(e % nc), cy = (int)((e / nc) % nc), cz = (int)(e / ((int64_t)nc * nc));
+        const int ix = (cx * p + a % P1) % n, iy = (cy * p + (a / P1) % P1) % n, iz = (cz * p + a / (P1 * P1)) % n;
+        return (int64_t)ix + (int64_t)n * (iy + (int64_t)n * iz);
+      };
+      for (int b = 0; b < nb; ++b) {  // count
+        auto& B = op->blocks[b];
+        for (size_t r = 0; r < B.rows.size(); ++r) local[B.rows[r]] = (int32_t)r;
+        for (size_t ci = 0; ci < B.cells.size(); ++ci)
+          for (int a = 0; a < op->nd; ++a) rr_ptr[rptr[b] + local[node_of(B.cells[ci], a)] + 1]++;
+        for (size_t r = 0; r < B.rows.size(); ++r) local[B.rows[r]] = -1;
+      }
+      for (int64_t R = 0; R < op->n_hrows; ++R) rr_ptr[R + 1] += rr_ptr[R];
+      {
+        std::vector<int32_t> rr_ent(rr_ptr[op->n_hrows]);
+        std::vector<int64_t> fillp(rr_ptr.begin(), rr_ptr.end() - 1);
+        for (int b = 0; b < nb; ++b) {  // fill
+          auto& B = op->blocks[b];
+          for (size_t r = 0; r < B.rows.size(); ++r) local[B.rows[r]] = (int32_t)r;
+          for (size_t ci = 0; ci < B.cells.size(); ++ci)
+            for (int a = 0; a < op->nd; ++a) {
+              const int64_t R = rptr[b] + local[node_of(B.cells[ci], a)];
+              rr_ent[fillp[R]++] = (int32_t)((boff[b] + (int64_t)ci) * 128 + a);
+            }
+          for (size_t r = 0; r < B.rows.size(); ++r) local[B.rows[r]] = -1;
+        }
+        if ((rc = dput(&op->d.rr_ent, rr_ent, err))) return rc;
+      }
+      // kinetic part of H^co by block row
+      std::vector<double> hkin((size_t)op->n_hrows * op->FMAX * E, 0.0);
+      for (int b = 0; b < nb; ++b) {
+        auto& B = op->blocks[b];
+        for (size_t r = 0; r < B.rows.size(); ++r)
+          for (int f = 0; f < B.nf; ++f) {
+            const size_t o = ((size_t)(rptr[b] + r) * op->FMAX + f) * E;
+            hkin[o] = B.hkin[r * B.nf + f].real();
+            if (cplx) hkin[o + 1] = B.hkin[r * B.nf + f].imag();
+          }
+      }
+      // common support cells of every pair of atom blocks (ascending cell index)
+      std::vector<int64_t> hp_ptr((size_t)nb * nb + 1, 0);
+      std::vector<int32_t> hp_i, hp_j;
+      for (int bi = 0; bi < nb; ++bi)
+        for (int bj = 0; bj < nb; ++bj) {
+          auto& ci = op->blocks[bi].cells;
+          auto& cj = op->blocks[bj].cells;
+          size_t i = 0, j = 0;
+          while (i < ci.size() && j < cj.size()) {
+            if (ci[i] < cj[j]) { ++i; continue; }
+            if (ci[i] > cj[j]) { ++j; continue; }
+            hp_i.push_back((int32_t)(boff[bi] + (int64_t)i));
+            hp_j.push_back((int32_t)(boff[bj] + (int64_t)j));
+            ++i;
+            ++j;
+          }
+          hp_ptr[(size_t)bi * nb + bj + 1] = (int64_t)hp_i.size();
+        }
+      if (hp_i.empty()) hp_i.push_back(0), hp_j.push_back(0);
+      std::vector<double> msq(op->N);
+      for (int64_t g = 0; g < op->N; ++g) msq[g] = 1.0 / std::sqrt(op->mdiag[g]);
+      if ((rc = dput(&op->d.cf_cell, cf_cell, err))) return rc;
+      if ((rc = dput(&op->d.row_blk, row_blk, err))) return rc;
+      if ((rc = dput(&op->d.rpos, rpos, err))) return rc;
+      if ((rc = dput(&op->d.rr_ptr, rr_ptr, err))) return rc;
+      if ((rc = dput(&op->d.hkin, hkin, err))) return rc;
+      if ((rc = dput(&op->d.hp_ptr, hp_ptr, err))) return rc;
+      if ((rc = dput(&op->d.hp_i, hp_i, err))) return rc;
+      if ((rc = dput(&op->d.hp_j, hp_j, err))) return rc;
+      if ((rc = dput(&op->d.msq, msq, err))) return rc;
+      std::vector<double> hook = flatten(op->Hoo_kin, cplx);
+      if ((rc = dput(&op->d.Hoo_kin, hook, err))) return rc;
+      if ((rc = dput(&op->d.csr2tile, op->csr_to_tile, err))) return rc;
+    }
     if ((rc = dput(&op->d.blk_fn0, fn0, err))) return rc;
     if ((rc = dput(&op->d.blk_nf, nf, err))) return rc;
     if ((rc = dput(&op->d.fn_blk, fn_blk, err))) return rc;
@@ -440,6 +532,8 @@ int upload_operator(oefe_op_s* op, std::string& err) {
     std::vector<int64_t> fr_ptr(op->N + 1, 0);
     if ((rc = dput(&op->d.fr_ptr, fr_ptr, err))) return rc;
   }
+  if ((rc = dput(&op->d.W, op->W, err))) return rc;
+  if ((rc = dput(&op->d.V, op->V, err))) return rc;
   return upload_potential_parts(op, err);
 }
 
@@ -451,6 +545,9 @@ void free_device(oefe_op_s* op) {
   dfree(d.chunk_r0); dfree(d.chunk_r1); dfree(d.blk_chunk0); dfree(d.fn_blk); dfree(d.S); dfree(d.Hoo);
   dfree(d.Sf); dfree(d.Hoof); dfree(d.cph_ptr); dfree(d.cph_blk); dfree(d.cph_off); dfree(d.phi);
   dfree(d.lambda); dfree(d.lambdaf); dfree(d.bf_mats);
+  dfree(d.W); dfree(d.V); dfree(d.msq); dfree(d.hkin); dfree(d.Hoo_kin); dfree(d.row_blk); dfree(d.rpos);
+  dfree(d.rr_ptr); dfree(d.rr_ent); dfree(d.cf_cell); dfree(d.csr2tile); dfree(d.hp_ptr); dfree(d.hp_i);
+  dfree(d.hp_j);
 }
 
 }  // namespace oefe
@@ -499,6 +596,134 @@ int overlap_setup(const oefe_op_s* op, Overlap* ov) {
 
 // the device-bounds filter keeps its [m][3] scalars in the work buffer's misc area (512 doubles)
 constexpr int kFilterDevMaxDegree = 160;
+
+// ---- Potential-dependent operator data rebuilt on the device (oefe_op_set_potential).
+// W V at the quadrature points (float64 and float32 copies)
+__global__ void wv_kernel(const double* __restrict__ W, const double* __restrict__ V, double* __restrict__ WV,
+                          float* __restrict__ WVf, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = W[i] * V[i];
+  WV[i] = v;
+  WVf[i] = (float)v;
+}
+
+// H^co (eqnHOEFEelelements, FE row g, enrichment function nu) = kinetic part (fixed) +
+// sum over the (cell e, local node a) pairs of row g of conj(theta_ea) sum_q B[q, a] W_eq V_eq
+// N^O_nu(x_eq), pre-scaled by m_g^-1/2 as the node stage uses it; one thread per (block row,
+// function), pairs in ascending cell order, written to the block-row, CSR and tile layouts.
+struct HcoRebuild {
+  const double *W, *V, *phi, *msq, *hkin;
+  const int64_t *rr_ptr, *rpos, *csr2tile;
+  const int32_t *rr_ent, *cf_cell, *row_blk, *blk_nf, *blk_rows;
+  double *hv, *fr_val, *tile_val;
+  float *hvf, *fr_valf, *tile_valf;
+  int64_t n_hrows;
+  int FMAX, nq, P1, p, nc, n;
+  double ph[3][2];
+};
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void hco_rebuild_kernel(HcoRebuild a, CellCoef<double> cd) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_hrows * a.FMAX) return;
+  const int64_t R = t / a.FMAX;
+  const int f = (int)(t - R * a.FMAX);
+  if (f >= a.blk_nf[a.row_blk[R]]) return;
+  const int P1 = a.P1, nq = a.nq;
+  double sr = 0.0, si = 0.0;
+  for (int64_t k = a.rr_ptr[R]; k < a.rr_ptr[R + 1]; ++k) {
+    const int cf = a.rr_ent[k] >> 7, an = a.rr_ent[k] & 127;
+    const int e = a.cf_cell[cf];
+    const int ax = an % P1, ay = (an / P1) % P1, az = an / (P1 * P1);
+    const double* Wc = a.W + (int64_t)e * nq;
+    const double* Vc = a.V + (int64_t)e * nq;
+    const double* pc = a.phi + ((int64_t)cf * nq * a.FMAX + f) * E;
+    double vr = 0.0, vi = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      const int qx = q % P1, qy = (q / P1) % P1, qz = q / (P1 * P1);
+      const double w = cd.B1[qx][ax] * cd.B1[qy][ay] * cd.B1[qz][az] * (Wc[q] * Vc[q]);
+      vr += w * pc[(int64_t)q * a.FMAX * E];
+      if (CPLX) vi += w * pc[(int64_t)q * a.FMAX * E + 1];
+    }
+    if constexpr (CPLX) {
+      // conj(theta) of the periodic image the node is reached through
+      const int cx = e % a.nc, cy = (e / a.nc) % a.nc, cz = e / (a.nc * a.nc);
+      double tr = 1.0, ti = 0.0;
+      const bool wr[3] = {cx * a.p + ax >= a.n, cy * a.p + ay >= a.n, cz * a.p + az >= a.n};
+      for (int d = 0; d < 3; ++d)
+        if (wr[d]) {
+          const double nr = tr * a.ph[d][0] - ti * a.ph[d][1], ni = tr * a.ph[d][1] + ti * a.ph[d][0];
+          tr = nr;
+          ti = ni;
+        }
+      sr += tr * vr + ti * vi;
+      si += tr * vi - ti * vr;
+    } else {
+      sr += vr;
+    }
+  }
+  const int g = a.blk_rows[R];
+  const double ms = a.msq[g];
+  const double* hk = a.hkin + (R * a.FMAX + f) * E;
+  const double hr = ms * (hk[0] + sr), hi = CPLX ? ms * (hk[1] + si) : 0.0;
+  const int64_t ob = (R * a.FMAX + f) * E, k = a.rpos[R] + f, tp = a.csr2tile[k] * E;
+  a.hv[ob] = hr;
+  a.hvf[ob] = (float)hr;
+  a.fr_val[k * E] = hr;
+  a.fr_valf[k * E] = (float)hr;
+  a.tile_val[tp] = hr;
+  a.tile_valf[tp] = (float)hr;
+  if (CPLX) {
+    a.hv[ob + 1] = hi;
+    a.hvf[ob + 1] = (float)hi;
+    a.fr_val[k * E + 1] = hi;
+    a.fr_valf[k * E + 1] = (float)hi;
+    a.tile_val[tp + 1] = hi;
+    a.tile_valf[tp + 1] = (float)hi;
+  }
+}
+
+// H^oo = kinetic part + sum over the common support cells (ascending) and quadrature points of
+// W V conj(N^O_i) N^O_j; one thread per entry (i, j)
+template <bool CPLX>
+__global__ __launch_bounds__(256) void hoo_rebuild_kernel(const double* __restrict__ W, const double* __restrict__ V,
+                                                          const double* __restrict__ phi, const double* __restrict__ Hoo_kin,
+                                                          const int64_t* __restrict__ hp_ptr, const int32_t* __restrict__ hp_i,
+                                                          const int32_t* __restrict__ hp_j, const int32_t* __restrict__ cf_cell,
+                                                          const int32_t* __restrict__ fn_blk, const int32_t* __restrict__ blk_fn0,
+                                                          int nO, int nb, int FMAX, int nq, double* __restrict__ Hoo,
+                                                          float* __restrict__ Hoof) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nO * nO) return;
+  const int i = t / nO, j = t - i * nO;
+  const int bi = fn_blk[i], bj = fn_blk[j];
+  const int f = i - blk_fn0[bi], g = j - blk_fn0[bj];
+  double sr = Hoo_kin[(int64_t)t * E], si = CPLX ? Hoo_kin[(int64_t)t * E + 1] : 0.0;
+  const int64_t pr = (int64_t)bi * nb + bj;
+  for (int64_t k = hp_ptr[pr]; k < hp_ptr[pr + 1]; ++k) {
+    const int ci = hp_i[k], cj = hp_j[k];
+    const int e = cf_cell[ci];
+    const double* pa = phi + ((int64_t)ci * nq * FMAX + f) * E;
+    const double* pb = phi + ((int64_t)cj * nq * FMAX + g) * E;
+    for (int q = 0; q < nq; ++q) {
+      const double wv = W[(int64_t)e * nq + q] * V[(int64_t)e * nq + q];
+      const double ar = pa[(int64_t)q * FMAX * E], ai = CPLX ? -pa[(int64_t)q * FMAX * E + 1] : 0.0;
+      const double br = pb[(int64_t)q * FMAX * E], bim = CPLX ? pb[(int64_t)q * FMAX * E + 1] : 0.0;
+      const double xr = wv * ar, xi = wv * ai;
+      sr += xr * br - xi * bim;
+      if (CPLX) si += xr * bim + xi * br;
+    }
+  }
+  Hoo[(int64_t)t * E] = sr;
+  Hoof[(int64_t)t * E] = (float)sr;
+  if (CPLX) {
+    Hoo[(int64_t)t * E + 1] = si;
+    Hoof[(int64_t)t * E + 1] = (float)si;
+  }
+}
 
 // ---- allocation-free CholGS: its Gram, factor and flag scratch in the file-scope device
 // array `scratch` (each device holds its own copy until the process ends).  Host code never
@@ -781,19 +1006,56 @@ int oefe_op_dims(oefe_op op, int64_t* dims) {
   return OEFE_OK;
 }
 
-int oefe_op_set_potential(oefe_op op, const double* V_host) {
-  if (!op || !V_host || op->diagonal) return fail(OEFE_EINVAL, "bad arguments");
-  std::copy(V_host, V_host + op->V.size(), op->V.begin());
-  std::string err;
-  int rc = rebuild_potential_parts(op, err);
-  if (!rc) rc = upload_potential_parts(op, err);
-  return rc ? fail(rc, err) : OEFE_OK;
+int oefe_op_set_potential(oefe_op op, const double* V, oefe_stream stream) {
+  if (!op || !V || op->diagonal) return fail(OEFE_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nqt = op->n_cells * op->nq;
+  if (hipMemcpyAsync(op->d.V, V, (size_t)nqt * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(OEFE_EDEVICE, "oefe_op_set_potential: copy of V failed");
+  hipLaunchKernelGGL(wv_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s, op->d.W, op->d.V, op->d.WV,
+                     op->d.WVf, nqt);
+  if (op->n_enr > 0) {
+    HcoRebuild a{};
+    a.W = op->d.W; a.V = op->d.V; a.phi = op->d.phi; a.msq = op->d.msq; a.hkin = op->d.hkin;
+    a.rr_ptr = op->d.rr_ptr; a.rpos = op->d.rpos; a.csr2tile = op->d.csr2tile;
+    a.rr_ent = op->d.rr_ent; a.cf_cell = op->d.cf_cell; a.row_blk = op->d.row_blk; a.blk_nf = op->d.blk_nf;
+    a.blk_rows = op->d.blk_rows;
+    a.hv = op->d.hv; a.fr_val = op->d.fr_val; a.tile_val = op->d.tile_val;
+    a.hvf = op->d.hvf; a.fr_valf = op->d.fr_valf; a.tile_valf = op->d.tile_valf;
+    a.n_hrows = op->n_hrows;
+    a.FMAX = op->FMAX; a.nq = op->nq; a.P1 = op->P1; a.p = op->p; a.nc = op->nc; a.n = op->n;
+    for (int d = 0; d < 3; ++d) {
+      a.ph[d][0] = op->phase[d][0];
+      a.ph[d][1] = op->phase[d][1];
+    }
+    const unsigned g1 = (unsigned)((op->n_hrows * op->FMAX + 255) / 256);
+    if (op->cplx)
+      hipLaunchKernelGGL(hco_rebuild_kernel<true>, dim3(g1), dim3(256), 0, s, a, op->cd);
+    else
+      hipLaunchKernelGGL(hco_rebuild_kernel<false>, dim3(g1), dim3(256), 0, s, a, op->cd);
+    const int nO = op->n_enr, nb = (int)op->blocks.size();
+    const unsigned g2 = (unsigned)(((int64_t)nO * nO + 255) / 256);
+    if (op->cplx)
+      hipLaunchKernelGGL(hoo_rebuild_kernel<true>, dim3(g2), dim3(256), 0, s, op->d.W, op->d.V, op->d.phi,
+                         op->d.Hoo_kin, op->d.hp_ptr, op->d.hp_i, op->d.hp_j, op->d.cf_cell, op->d.fn_blk,
+                         op->d.blk_fn0, nO, nb, op->FMAX, op->nq, op->d.Hoo, op->d.Hoof);
+    else
+      hipLaunchKernelGGL(hoo_rebuild_kernel<false>, dim3(g2), dim3(256), 0, s, op->d.W, op->d.V, op->d.phi,
+                         op->d.Hoo_kin, op->d.hp_ptr, op->d.hp_i, op->d.hp_j, op->d.cf_cell, op->d.fn_blk,
+                         op->d.blk_fn0, nO, nb, op->FMAX, op->nq, op->d.Hoo, op->d.Hoof);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "oefe_op_set_potential");
+  return OEFE_OK;
 }
 
 int oefe_op_get_potential(oefe_op op, double* V_host, double* W_host) {
   if (!op || op->diagonal) return fail(OEFE_EINVAL, "bad arguments");
-  if (V_host) std::copy(op->V.begin(), op->V.end(), V_host);
-  if (W_host) std::copy(op->W.begin(), op->W.end(), W_host);
+  const size_t bytes = (size_t)op->n_cells * op->nq * sizeof(double);
+  hipError_t e = hipDeviceSynchronize();  // after the set_potential calls queued on any stream
+  if (e == hipSuccess && V_host) e = hipMemcpy(V_host, op->d.V, bytes, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && W_host) e = hipMemcpy(W_host, op->d.W, bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "oefe_op_get_potential");
   return OEFE_OK;
 }
 

@@ -110,6 +110,21 @@ struct DeviceArrays {
   // diagonal test operator
   double* lambda = nullptr;
   float* lambdaf = nullptr;
+  // potential rebuild on the device (oefe_op_set_potential)
+  double* W = nullptr;          // quadrature weights [n_cells * nq]
+  double* V = nullptr;          // current potential [n_cells * nq]
+  double* msq = nullptr;        // m_g^-1/2 [N]
+  double* hkin = nullptr;       // kinetic part of H^co by block row [n_hrows][FMAX] (complex: x2), unscaled
+  double* Hoo_kin = nullptr;    // kinetic part of H^oo [n_enr^2] (complex: x2)
+  int32_t* row_blk = nullptr;   // block of each block row [n_hrows]
+  int64_t* rpos = nullptr;      // CSR position of each block row's first function [n_hrows]
+  int64_t* rr_ptr = nullptr;    // block row -> its (support cell, local node) pairs [n_hrows + 1]
+  int32_t* rr_ent = nullptr;    // pair: 128 * (flattened support cell) + local node
+  int32_t* cf_cell = nullptr;   // cell of each flattened support cell (index into phi)
+  int64_t* csr2tile = nullptr;  // CSR entry -> tile_val position [fr_nnz]
+  int64_t* hp_ptr = nullptr;    // atom-block pair (bi nb + bj) -> common support cells [nb^2 + 1]
+  int32_t* hp_i = nullptr;      // flattened support cell of bi for each common cell
+  int32_t* hp_j = nullptr;      // flattened support cell of bj
 };
 
 struct AtomBlock {

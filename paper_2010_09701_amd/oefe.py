@@ -60,7 +60,7 @@ def _load():
         "oefe_op_create_diagonal": ([vp, i64, ctypes.POINTER(vp)], i32),
         "oefe_op_destroy": ([vp], i32),
         "oefe_op_dims": ([vp, vp], i32),
-        "oefe_op_set_potential": ([vp, vp], i32),
+        "oefe_op_set_potential": ([vp, vp, vp], i32),
         "oefe_op_get_potential": ([vp, vp, vp], i32),
         "oefe_op_get_enrichment": ([vp, vp, vp], i32),
         "oefe_work_size": ([vp, i32, i32], ctypes.c_size_t),
@@ -225,11 +225,17 @@ class Operator:
         _check(_lib.oefe_kernel_timer_read(self._h, ctypes.byref(n), ctypes.byref(ms)), "oefe_kernel_timer_read")
         return int(n.value), float(ms.value)
 
-    def set_potential(self, V: np.ndarray):
-        V = np.ascontiguousarray(V, dtype=np.float64).ravel()
-        if V.size != self.n_cells * self.nq:
+    def set_potential(self, V):
+        """Replace V at the quadrature points ([n_cells, nq] numpy array or torch tensor); the operator
+        data that depend on V are rebuilt on the device, on torch's current stream."""
+        if isinstance(V, torch.Tensor):
+            Vd = V.detach().to(device="cuda", dtype=torch.float64).contiguous().reshape(-1)
+        else:
+            Vd = torch.from_numpy(np.ascontiguousarray(V, dtype=np.float64).ravel()).cuda()
+        if Vd.numel() != self.n_cells * self.nq:
             raise ValueError("V must have n_cells * nq entries")
-        _check(_lib.oefe_op_set_potential(self._h, V.ctypes.data_as(ctypes.c_void_p)), "oefe_op_set_potential")
+        _check(_lib.oefe_op_set_potential(self._h, _ptr(Vd), _stream()), "oefe_op_set_potential")
+        self._keep_V = Vd  # held until the queued rebuild has read it (the next call replaces it)
 
     def get_potential(self):
         V = np.empty(self.n_cells * self.nq)

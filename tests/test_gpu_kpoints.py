@@ -162,3 +162,39 @@ def test_stage_timers_batched(lib, mp_ops):
         n, ms = mp_ops[0].kernel_timer_read()
         mp_ops[0].kernel_timer("off")
         assert n == m and ms > 0, (which, n, ms)
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "kpoint_passes_oracle.npz")), reason="golden file missing")
+@pytest.mark.parametrize("q", [0, 7])
+def test_mp_kpoint_passes_vs_oracle(lib, mp_ops, q):
+    """diamond8 at the k-points with the fewest (48) and the most (96) vectors: complex128 bounds,
+    pass-1 filter rows and the Ritz values of five passes against the oracle's complex128 run
+    (1e-10); complex64-filter passes against the same oracle values, per pass, over the lowest
+    nv - 16 states."""
+    import torch
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    g = np.load(os.path.join(GOLD, "kpoint_passes_oracle.npz"))
+    cfg = wl.config("diamond8")
+    op = mp_ops[q]
+    nv = wl.KPOINT_NV[q]
+    X0 = _mp_blocks(mp_ops)[q]
+    v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, cfg.v0_seed)).cuda()
+    a0o, bo = float(g[f"a0L{q}"]), float(g[f"b{q}"])
+    a0, b, a = lib.lanczos_bounds(op, v0, cfg.lanczos_k, with_cut=True)
+    assert abs(a0 - a0o) <= 1e-10 * abs(a0o) and abs(b - bo) <= 1e-10 * abs(bo)
+    X = _dev(X0, torch.complex128)
+    lib.chebyshev_filter(op, X, cfg.m, 0.5 * (a0o + bo), bo, a0o)
+    Y = X.cpu().numpy()
+    rows, ref = g[f"rows{q}"], g[f"filt1_rows{q}"]
+    assert _colrel(Y[rows], ref) < 1e-9
+    np.testing.assert_allclose(np.linalg.norm(Y, axis=0), g[f"filt1_colnorm{q}"], rtol=1e-10)
+    th_o = g[f"thetas{q}"]
+    bounds = (a0o, bo, 0.5 * (a0o + bo))
+    r = chfsi_run(op, _dev(X0, torch.complex128), v0, cfg.m, th_o.shape[0], cfg.lanczos_k, "f64", bounds=bounds)
+    th = np.stack([p["theta"] for p in r["passes"]])
+    assert np.abs(th - th_o).max() <= 1e-10 * np.abs(th_o).max()
+    r64 = chfsi_run(op, _dev(X0, torch.complex128), v0, cfg.m, th_o.shape[0], cfg.lanczos_k, "c64", bounds=bounds)
+    n_occ = nv - 16
+    err = [float(np.abs(p["theta"][:n_occ] - t[:n_occ]).max()) for p, t in zip(r64["passes"], th_o)]
+    print(f"k-point {q} complex64 filter: Ritz error vs oracle per pass (Ha)", ["%.1e" % e for e in err])
+    assert err[-1] <= 1e-6

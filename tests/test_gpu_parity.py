@@ -411,18 +411,36 @@ def test_band_energy_grad_p4(lib):
     assert abs(float(E) - adj.band_energy(op, X, f)) < 1e-10 * abs(float(E))
 
 
-def test_set_potential(lib):
-    sysm = SYSTEMS["tiny2"]()
+@pytest.mark.parametrize("name,kvec", [("tiny2", None), ("diamond_nc4", None), ("p3", (-0.4, 0.25, 0.1)),
+                                       ("single_atom", (0.3, -0.2, 0.1))])
+def test_set_potential(lib, name, kvec):
+    """The potential-dependent operator data rebuilt on the device (W V, H^co in every layout, H^oo):
+    re-setting the creation potential reproduces the operator built on the host, and a perturbed
+    potential gives the oracle's operator for that potential, in float64 and float32."""
+    import torch
+    base = SYSTEMS[name]()
+    sysm = base if kvec is None else base.with_k(np.array(kvec))
     gop = lib.Operator(sysm)
     V0, W = gop.get_potential()
     op0 = OEFEOperator(sysm)
     np.testing.assert_allclose(V0, op0.V, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(W, np.broadcast_to(op0.mesh.Wcell, W.shape), rtol=1e-13)
+    X = wl.start_block(op0.n_tot, 7, 2, complex_=kvec is not None)
+    Y0 = lib.ham_apply(gop, _dev(X)).cpu().numpy()
+    gop.set_potential(V0)
+    Y1 = lib.ham_apply(gop, _dev(X)).cpu().numpy()
+    assert _colrel(Y1, Y0) < 1e-13
     dV = wl.potential_perturbation(op0.mesh.n_cells, op0.mesh.nq, 101)
-    gop.set_potential(V0 + 0.3 * dV)
+    gop.set_potential(torch.from_numpy(V0 + 0.3 * dV).cuda())
+    Vg, _ = gop.get_potential()
+    assert np.array_equal(Vg, V0 + 0.3 * dV)
     op = OEFEOperator(sysm, V=op0.V + 0.3 * dV)
-    X = wl.start_block(op.n_tot, 7, 2)
     Y = lib.ham_apply(gop, _dev(X)).cpu().numpy()
-    assert _colrel(Y, op.apply(X)) < 1e-10
+    ref = op.apply(X)
+    assert _colrel(Y, ref) < 1e-10
+    dt = torch.complex64 if kvec is not None else torch.float32
+    Yf = lib.ham_apply(gop, _dev(X, dt)).cpu().numpy().astype(ref.dtype)
+    assert _colrel(Yf, ref) < 1e-5
 
 
 def test_enrichment_overlap_and_S(lib):

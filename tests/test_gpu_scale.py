@@ -1,9 +1,10 @@
 """Differentiation at scale: diamond64 (2x2x2 supercell of diamond8: 64 atoms, 24^3 cells
 p = 4, 884,736 FE DoF + 320 enrichment functions), 320 vectors, float32 filter of degree 60.
 
-* 5 ChFSI passes with the float32 filter (float64 CholGS / Rayleigh-Ritz) against the same
-  passes with the float64 filter, whose operator is pinned to the oracle on sampled rows
-  (stored oracle values) at this size;
+* the bounds, the pass-1 filtered block (sampled rows, column norms) and the pass-1 Ritz
+  values of the float64 path against the oracle's float64 pass (stored values);
+* 5 ChFSI passes with the float32 filter (float64 CholGS / Rayleigh-Ritz) against the oracle
+  at pass 1 and against the float64 passes, per pass;
 * the band-energy adjoint at the float32-filtered Ritz vectors against central finite
   differences (h = 1e-5, float64 energies) on 16 random potential perturbations
   (seeds 100..115) and 4 random vector perturbations.  E is linear in V and quadratic in X,
@@ -34,6 +35,32 @@ def d64():
     r32 = chfsi_run(gop, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f32", bounds=bounds)
     del X0
     return oefe, cfg, gop, v0, bounds, r32
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "diamond64_pass1_oracle.npz")), reason="golden file missing")
+def test_diamond64_pass1_vs_oracle(d64):
+    import torch
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    oefe, cfg, gop, v0, bounds, r32 = d64
+    g = np.load(os.path.join(GOLD, "diamond64_pass1_oracle.npz"))
+    a0o, bo = float(g["a0L"]), float(g["b"])
+    assert abs(bounds[0] - a0o) <= 1e-10 * abs(a0o) and abs(bounds[1] - bo) <= 1e-10 * abs(bo)
+    X = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
+    oefe.chebyshev_filter(gop, X, cfg.m, 0.5 * (a0o + bo), bo, a0o)
+    rows = g["rows"]
+    Yr = X[torch.from_numpy(rows).cuda()].cpu().numpy()
+    num = np.linalg.norm(Yr - g["filt1_rows"], axis=0)
+    den = np.linalg.norm(g["filt1_rows"], axis=0)
+    assert (num / den).max() < 1e-9
+    np.testing.assert_allclose(torch.linalg.vector_norm(X, dim=0).cpu().numpy(), g["filt1_colnorm"], rtol=1e-10)
+    del X
+    X0 = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
+    r = chfsi_run(gop, X0, v0, cfg.m, 1, cfg.lanczos_k, "f64", bounds=(a0o, bo, 0.5 * (a0o + bo)))
+    th = r["passes"][0]["theta"]
+    assert np.abs(th - g["theta1"]).max() <= 1e-10 * np.abs(g["theta1"]).max()
+    n_occ = 256
+    e32 = float(np.abs(r32["passes"][0]["theta"][:n_occ] - g["theta1"][:n_occ]).max())
+    print(f"diamond64 float32 filter, pass 1: Ritz error vs oracle {e32:.1e} Ha")
 
 
 def test_diamond64_float32_passes_vs_float64(d64):
