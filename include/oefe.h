@@ -281,6 +281,29 @@ int oefe_set_eig_sweep_limit(oefe_op op, int32_t sweeps);
 int band_energy_grad(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* f,
                      double* E, double* dE_dV, void* dE_dX, void* work, oefe_stream stream);
 
+/* Occupations from Ritz values (Sec. II): Fermi-Dirac f = 1 / (1 + exp((theta - mu)
+ * / kT)) (eqnfd) with the Fermi level mu fixed by the electron count
+ * 2 sum_k w_k sum_alpha f = n_elec (eqnne), found by bisection in float64 (the paper
+ * does not say how; see the oracle), and the band energy 2 sum_k w_k sum_alpha f theta.
+ * nk k-points (1..64): nv[k] values each (host), weights wk[k] (host); theta: device
+ * float64, the nk blocks of Ritz values concatenated.  Outputs (device): f [sum nv]
+ * (occupations in [0, 1], same layout), out[3] = {mu, E_band, electron count at mu};
+ * dev_status int32[2] = {0, halvings} or {OEFE_EINVAL, 0} when n_elec is not between 0
+ * and twice the weighted number of states.  kT > 0 (Hartree).  One workgroup, queued on
+ * `stream`. */
+int oefe_fermi_occupations(int32_t nk, const int32_t* nv, const double* wk, const double* theta, double n_elec,
+                           double kT, double* f, double* out, int32_t* dev_status, oefe_stream stream);
+
+/* Electron density at the quadrature points from a block of Ritz vectors (eqnrho):
+ * rho[e * nq + q] (+)= sum_i weights[i] |psi_i(x_{e,q})|^2, psi_i the field of
+ * M^-1/2 x_i (|u| = |psi| for the Bloch functions of a phase-twisted basis); with
+ * weights = 2 w_k f this is one k-point's term of eqnrho, and accumulate != 0 adds it
+ * to rho (k-points summed in call order).  weights: device float64 [nv]; rho: device
+ * float64 [n_cells * nq].  prec as for band_energy_grad; work: oefe_work_size(op,
+ * prec, nv) bytes. */
+int oefe_density(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* weights, double* rho,
+                 int32_t accumulate, void* work, oefe_stream stream);
+
 /* Instrumentation.  While a kernel is selected, each of its launches inside
  * ham_apply / chebyshev_filter* is bracketed by HIP events on the stream it is
  * launched on.  which: OEFE_TIMER_OFF, OEFE_TIMER_CELL (the sum-factorized

@@ -21,6 +21,8 @@ operator     the symmetrized operator M^-1/2 H M^-1/2 (eqnKSEigGenDiscrete,
 chfsi        Lanczos bounds, scaled Chebyshev filter, Cholesky-Gram-Schmidt,
              Rayleigh-Ritz and the pass driver (Sec. IV, eqnProjKS).
 adjoint      band energy and its gradients w.r.t. V and X (eqnrho, E_band).
+occupations  Fermi-Dirac occupations, Fermi level from the electron count, band
+             energy and density from Ritz pairs (eqnfd, eqnne, eqnrho, E_band).
 
 Functions whose only check is agreement with the HIP path say "parity
 unpinned" in their docstring.

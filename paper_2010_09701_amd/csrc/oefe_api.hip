@@ -725,6 +725,98 @@ __global__ __launch_bounds__(256) void hoo_rebuild_kernel(const double* __restri
   }
 }
 
+// ---- Occupations and Fermi level (eqnfd, eqnne) for the Ritz values of nk k-points, one
+// workgroup: bisection on mu for 2 sum_k w_k sum f(theta, mu) = N_e (the count increases with
+// mu), every count summed in a fixed order (each thread a fixed strided share, then a fixed
+// tree), so the result is reproducible; then f and E_band = 2 sum_k w_k sum f theta.
+constexpr int kOccMaxK = 64;
+struct OccArgs {
+  int nk;
+  int off[kOccMaxK + 1];  // value offsets of the k-points in theta
+  double w2[kOccMaxK];    // 2 w_k
+};
+
+__device__ double occ_block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+__device__ double occ_count(const double* __restrict__ th, const OccArgs& a, double mu, double kT, double* red) {
+  double s = 0.0;
+  for (int k = 0; k < a.nk; ++k)
+    for (int i = a.off[k] + (int)threadIdx.x; i < a.off[k + 1]; i += blockDim.x)
+      s += a.w2[k] / (1.0 + exp((th[i] - mu) / kT));
+  return occ_block_sum(s, red);
+}
+
+__global__ __launch_bounds__(1024) void occupations_kernel(const double* __restrict__ th, OccArgs a, double n_elec,
+                                                           double kT, double* __restrict__ f, double* __restrict__ out,
+                                                           int32_t* __restrict__ status) {
+  __shared__ double red[16];
+  const int ntot = a.off[a.nk];
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
+    lo = fmin(lo, th[i]);
+    hi = fmax(hi, th[i]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+  }
+  __shared__ double mm[2][16];
+  if ((threadIdx.x & 63) == 0) {
+    mm[0][threadIdx.x >> 6] = lo;
+    mm[1][threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  lo = INFINITY;
+  hi = -INFINITY;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+    lo = fmin(lo, mm[0][i]);
+    hi = fmax(hi, mm[1][i]);
+  }
+  lo -= 50.0 * kT;
+  hi += 50.0 * kT;
+  const double cmax = occ_count(th, a, hi, kT, red);
+  if (!(n_elec > 0.0 && n_elec < cmax)) {
+    if (threadIdx.x == 0) {
+      status[0] = OEFE_EINVAL;
+      status[1] = 0;
+    }
+    return;
+  }
+  int it = 0;
+  for (; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(1.0, fabs(mid))) break;
+    if (occ_count(th, a, mid, kT, red) < n_elec) lo = mid;
+    else hi = mid;
+  }
+  const double mu = 0.5 * (lo + hi);
+  double eb = 0.0;
+  for (int k = 0; k < a.nk; ++k)
+    for (int i = a.off[k] + (int)threadIdx.x; i < a.off[k + 1]; i += blockDim.x) {
+      const double fi = 1.0 / (1.0 + exp((th[i] - mu) / kT));
+      f[i] = fi;
+      eb += a.w2[k] * fi * th[i];
+    }
+  eb = occ_block_sum(eb, red);
+  const double cnt = occ_count(th, a, mu, kT, red);
+  if (threadIdx.x == 0) {
+    out[0] = mu;
+    out[1] = eb;
+    out[2] = cnt;
+    status[0] = 0;
+    status[1] = it;
+  }
+}
+
 // ---- allocation-free CholGS: its Gram, factor and flag scratch in the file-scope device
 // array `scratch` (each device holds its own copy until the process ends).  Host code never
 // passes the array's name to a kernel or a copy: its device address is taken once per device
@@ -1696,6 +1788,47 @@ int band_energy_grad(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int3
     rc = scale_grad(cplx, dE_dX, ld, op->n_tot, nv, f, f32, s);
     if (rc) return fail(rc, "band_energy_grad: scaling failed");
   }
+  return OEFE_OK;
+}
+
+int oefe_fermi_occupations(int32_t nk, const int32_t* nv, const double* wk, const double* theta, double n_elec,
+                           double kT, double* f, double* out, int32_t* dev_status, oefe_stream stream) {
+  if (nk < 1 || nk > kOccMaxK || !nv || !wk || !theta || !f || !out || !dev_status || !(kT > 0.0))
+    return fail(OEFE_EINVAL, "bad arguments (1 <= nk <= 64, kT > 0, non-null pointers)");
+  OccArgs a{};
+  a.nk = nk;
+  a.off[0] = 0;
+  for (int k = 0; k < nk; ++k) {
+    if (nv[k] < 1 || !(wk[k] >= 0.0)) return fail(OEFE_EINVAL, "bad block width or weight");
+    a.off[k + 1] = a.off[k] + nv[k];
+    a.w2[k] = 2.0 * wk[k];
+  }
+  hipLaunchKernelGGL(occupations_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, theta, a, n_elec, kT, f, out,
+                     dev_status);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "oefe_fermi_occupations");
+  return OEFE_OK;
+}
+
+int oefe_density(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* weights, double* rho,
+                 int32_t accumulate, void* work, oefe_stream stream) {
+  if (!op || !X || !weights || !rho || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
+  if (int rc = check_prec(op, prec)) return rc;
+  if (op->diagonal) return fail(OEFE_EINVAL, "diagonal operator has no density");
+  const bool cplx = op->cplx;
+  Layout L = layout(op, prec, nv, work);
+  hipStream_t s = (hipStream_t)stream;
+  const int ncr = cplx ? 2 * nv : nv;
+  int rc;
+  if (prec_fp32(prec)) {
+    rc = zo_only<float>(op, (const float*)X, ld, nv, (float*)L.step.zo, ncr, s);
+    if (!rc) rc = density_partial<float>(op, (const float*)X, ld, nv, weights, (const float*)L.step.zo, ncr, L.dens, s);
+  } else {
+    rc = zo_only<double>(op, (const double*)X, ld, nv, (double*)L.step.zo, ncr, s);
+    if (!rc) rc = density_partial<double>(op, (const double*)X, ld, nv, weights, (const double*)L.step.zo, ncr, L.dens, s);
+  }
+  if (!rc) rc = density_final(op, L.dens, ncols_blocks(ncr), rho, s, accumulate ? 2 : 1);
+  if (rc) return fail(rc, "oefe_density: kernel launch failed");
   return OEFE_OK;
 }
 

@@ -63,7 +63,7 @@ template <typename T>
 int density_partial(const oefe_op_s* op, const T* x, int64_t ld, int nv, const double* f, const T* zo, int ncr,
                     double* dens, hipStream_t s);
 // dEdV[e][q] = W_eq sum_blk dens[blk][e][q]
-int density_final(const oefe_op_s* op, const double* dens, int nblk, double* dEdV, hipStream_t s);
+int density_final(const oefe_op_s* op, const double* dens, int nblk, double* dEdV, hipStream_t s, int mode = 0);
 
 // ---- dense linear algebra (float64, real or complex-interleaved), oefe_linalg.hip
 // G[i][j] = sum_g conj(A[g][i]) B[g][j]  (na x nb, row-major ldg), rows 0..n-1.

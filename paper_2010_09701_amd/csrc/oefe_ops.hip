@@ -1857,16 +1857,23 @@ __global__ __launch_bounds__(64 * P1) void density_kernel(
 struct GW {
   double w[8];
 };
+// mode 0: out = W s (the potential gradient); 1: out = s (the density); 2: out += s
 __global__ void density_final_kernel2(const double* __restrict__ dens, int nblk, int64_t total, int P1, GW gw,
-                                      double h3, double* __restrict__ out) {
+                                      double h3, double* __restrict__ out, int mode) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const int nq = P1 * P1 * P1;
   const int q = (int)(t % nq);
   double s = 0;
   for (int b = 0; b < nblk; ++b) s += dens[(int64_t)b * total + t];
-  const double W = h3 * gw.w[q % P1] * gw.w[(q / P1) % P1] * gw.w[q / (P1 * P1)];
-  out[t] = W * s;
+  if (mode == 0) {
+    const double W = h3 * gw.w[q % P1] * gw.w[(q / P1) % P1] * gw.w[q / (P1 * P1)];
+    out[t] = W * s;
+  } else if (mode == 1) {
+    out[t] = s;
+  } else {
+    out[t] += s;
+  }
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -2329,13 +2336,13 @@ int density_partial(const oefe_op_s* op, const T* x, int64_t ld, int nv, const d
   return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
 }
 
-int density_final(const oefe_op_s* op, const double* dens, int nblk, double* dEdV, hipStream_t s) {
+int density_final(const oefe_op_s* op, const double* dens, int nblk, double* dEdV, hipStream_t s, int mode) {
   const int64_t total = op->n_cells * op->nq;
   GW gw;
   for (int i = 0; i < 8; ++i) gw.w[i] = i < op->P1 ? op->gauss_w[i] : 0.0;
   const double h3 = (op->h / 2) * (op->h / 2) * (op->h / 2);
   hipLaunchKernelGGL(density_final_kernel2, dim3((unsigned)cdiv(total, 256)), dim3(256), 0, s, dens, nblk, total,
-                     op->P1, gw, h3, dEdV);
+                     op->P1, gw, h3, dEdV, mode);
   return hipGetLastError() == hipSuccess ? OEFE_OK : OEFE_EDEVICE;
 }
 

@@ -79,6 +79,8 @@ def _load():
         "rayleigh_ritz": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp], i32),
         "oefe_set_eig_sweep_limit": ([vp, i32], i32),
         "band_energy_grad": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
+        "oefe_fermi_occupations": ([i32, vp, vp, vp, dbl, dbl, vp, vp, vp, vp], i32),
+        "oefe_density": ([vp, i32, vp, i64, i32, vp, vp, i32, vp, vp], i32),
         "oefe_kernel_timer": ([vp, i32], i32),
         "oefe_kernel_timer_read": ([vp, vp, vp], i32),
         "oefe_copy_rate": ([vp, vp, ctypes.c_size_t, i32, vp, vp], i32),
@@ -99,7 +101,8 @@ EXPORTED = [
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
     "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
-    "lanczos_bounds", "cholgs", "cholgs_async", "cholgs_noalloc", "rayleigh_ritz", "oefe_set_eig_sweep_limit", "band_energy_grad", "oefe_kernel_timer",
+    "lanczos_bounds", "cholgs", "cholgs_async", "cholgs_noalloc", "rayleigh_ritz", "oefe_set_eig_sweep_limit", "band_energy_grad",
+    "oefe_fermi_occupations", "oefe_density", "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_copy_rate", "oefe_strerror", "oefe_last_error",
 ]
 
@@ -503,3 +506,46 @@ def band_energy_grad(op: Operator, X: torch.Tensor, f: torch.Tensor, want_dV: bo
     _check(_lib.band_energy_grad(op.handle, prec, _ptr(X), ld, nv, _ptr(f), _ptr(E), _ptr(dV), _ptr(dX), _ptr(w),
                                  _stream()), "band_energy_grad")
     return E, dV, dX
+
+
+def fermi_occupations(thetas, wk, n_elec: float, kT: float):
+    """Occupations of the Ritz values of nk k-points (list of device float64 tensors), weights wk:
+    (list of occupation tensors, mu, E_band, electron count at mu).  Raises when n_elec cannot
+    be reached with these states."""
+    nk = len(thetas)
+    if nk == 0 or nk != len(wk):
+        raise ValueError("one weight per k-point")
+    th = torch.cat([t.to(torch.float64).reshape(-1) for t in thetas]).contiguous()
+    if not th.is_cuda:
+        raise ValueError("Ritz values must be device tensors")
+    NV = (ctypes.c_int32 * nk)(*[int(t.numel()) for t in thetas])
+    WK = (ctypes.c_double * nk)(*[float(w) for w in wk])
+    f = torch.empty_like(th)
+    out = torch.empty(3, dtype=torch.float64, device=th.device)
+    st = torch.zeros(2, dtype=torch.int32, device=th.device)
+    _check(_lib.oefe_fermi_occupations(nk, NV, WK, _ptr(th), float(n_elec), float(kT), _ptr(f), _ptr(out), _ptr(st),
+                                       _stream()), "oefe_fermi_occupations")
+    sth = st.cpu().tolist()
+    if sth[0] != 0:
+        raise OefeError(sth[0], "oefe_fermi_occupations", "the electron count cannot be reached with these states")
+    o = out.cpu().tolist()
+    return list(torch.split(f, [int(t.numel()) for t in thetas])), o[0], o[1], o[2]
+
+
+def density(op: Operator, X: torch.Tensor, weights: torch.Tensor, rho: Optional[torch.Tensor] = None,
+            accumulate: bool = False) -> torch.Tensor:
+    """sum_i weights_i |psi_i|^2 at the quadrature points ([n_cells, nq], float64), added to rho when
+    accumulate (k-point sums)."""
+    ld, nv = _block(X, op.n_tot)
+    prec = _prec(X)
+    weights = weights.to(device=X.device, dtype=torch.float64).contiguous()
+    if weights.numel() != nv:
+        raise ValueError("one weight per vector")
+    if rho is None:
+        rho = torch.zeros(op.n_cells, op.nq, dtype=torch.float64, device=X.device)
+    elif rho.dtype != torch.float64 or rho.numel() != op.n_cells * op.nq or not rho.is_contiguous():
+        raise ValueError("rho: contiguous float64 [n_cells, nq]")
+    w = op.work(prec, nv)
+    _check(_lib.oefe_density(op.handle, prec, _ptr(X), ld, nv, _ptr(weights), _ptr(rho), 1 if accumulate else 0,
+                             _ptr(w), _stream()), "oefe_density")
+    return rho

@@ -1,0 +1,109 @@
+"""Occupations, Fermi level, band energy and density from Ritz pairs on the GPU (oefe_fermi_occupations,
+oefe_density) against the oracle (oracle/occupations.py).
+
+Tolerances: mu and E_band to 1e-12 relative (both sides bisect in float64 to rounding, summing in
+different orders), occupations to 1e-12, the density to 1e-10 relative (float64 fields).  Where the
+Fermi level falls in a gap, mu is not unique: any mu meeting the electron count is correct, and the
+occupations and band energy (unique) are compared.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import occupations as occ
+from oracle.operator import OEFEOperator
+from paper_2010_09701_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+KT = 500.0 * occ.K_BOLTZMANN_HA_PER_K  # the paper's smearing temperature
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2010_09701_amd import oefe
+    return oefe
+
+
+def _check(lib, thetas, wk, n_elec, kT=KT):
+    import torch
+    f, mu, eb, cnt = lib.fermi_occupations([torch.from_numpy(t).cuda() for t in thetas], wk, n_elec, kT)
+    mu_o, _ = occ.fermi_level(thetas, wk, n_elec, kT)
+    f_o = [occ.fermi_dirac(t, mu_o, kT) for t in thetas]
+    eb_o = occ.band_energy(thetas, wk, f_o)
+    # mu is unique only where the count grows with it; inside a gap (no state within many kT)
+    # every mu of the gap is a solution, so there the GPU's mu is checked by the oracle's count
+    slope = sum(2.0 * w * np.sum(fo * (1.0 - fo)) / kT for fo, w in zip(f_o, wk))
+    if slope > 1e-3:
+        assert abs(mu - mu_o) <= 1e-12 * max(1.0, abs(mu_o))
+    assert abs(occ.electron_count(thetas, wk, mu, kT) - n_elec) <= 1e-12 * n_elec
+    assert abs(cnt - n_elec) <= 1e-12 * n_elec
+    for a, b in zip(f, f_o):
+        assert np.abs(a.cpu().numpy() - b).max() <= 1e-12
+    assert abs(eb - eb_o) <= 1e-12 * abs(eb_o)
+    return f, mu, eb
+
+
+@pytest.mark.parametrize("nk", [1, 3, 8])
+def test_occupations_random_spectra(lib, nk):
+    rng = np.random.default_rng(20 + nk)
+    thetas = [np.sort(rng.uniform(-40.0, 2.0, size=30 + 7 * k)) for k in range(nk)]
+    wk = rng.uniform(0.5, 1.0, size=nk)
+    wk = wk / wk.sum()
+    for n_elec in (10.0, 33.3, 47.0):
+        _check(lib, thetas, list(wk), n_elec)
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "diamond8_oracle.npz")), reason="golden file missing")
+def test_occupations_diamond8_ritz_values(lib):
+    """diamond8's pass-5 Ritz values (oracle), 8 Si atoms = 112 electrons at 500 K: the 56 lowest
+    states are occupied (the core and valence states lie far below the rest of the block)."""
+    th = np.load(os.path.join(GOLD, "diamond8_oracle.npz"))["thetas"][-1]
+    f, mu, eb = _check(lib, [th], [1.0], 112.0)
+    fh = f[0].cpu().numpy()
+    assert fh[:50].min() > 1.0 - 1e-9 and fh[60:].max() < 1e-9
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "kpoint_passes_oracle.npz")), reason="golden file missing")
+def test_occupations_two_kpoints(lib):
+    g = np.load(os.path.join(GOLD, "kpoint_passes_oracle.npz"))
+    thetas = [g["thetas0"][-1], g["thetas7"][-1]]
+    _check(lib, thetas, [0.5, 0.5], 80.0)
+
+
+def test_occupations_reject_unreachable_count(lib):
+    import torch
+    th = torch.linspace(-3.0, 3.0, 10, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.OefeError) as ei:
+        lib.fermi_occupations([th], [1.0], 25.0, KT)
+    assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("kvec", [None, (0.3, -0.2, 0.1)])
+def test_density_and_band_energy_from_ritz_pairs(lib, kvec):
+    """single_atom after five ChFSI passes on the GPU: occupations of its Ritz values, the density
+    of its Ritz vectors against the oracle's, accumulated over two calls, and the band energy of the
+    Ritz values against the Rayleigh quotients (band_energy_grad) with the same weights."""
+    import torch
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    cfg = wl.config("single_atom")
+    sysm = cfg.system if kvec is None else cfg.system.with_k(np.array(kvec))
+    op = OEFEOperator(sysm)
+    gop = lib.Operator(sysm)
+    X0 = wl.start_block(op.n_tot, cfg.nv, 0, complex_=kvec is not None)
+    v0 = wl.lanczos_start(op.n_tot, 2)
+    r = chfsi_run(gop, torch.from_numpy(X0).cuda(), torch.from_numpy(v0).cuda(), cfg.m, cfg.passes, cfg.lanczos_k)
+    th = r["theta"]
+    f, mu, eb = _check(lib, [th], [1.0], 6.0)
+    wts = 2.0 * f[0]
+    rho = lib.density(gop, r["X"], wts)
+    Xh = r["X"].cpu().numpy()
+    rho_o = occ.density(op, Xh, wts.cpu().numpy())
+    assert np.abs(rho.cpu().numpy() - rho_o).max() <= 1e-10 * np.abs(rho_o).max()
+    lib.density(gop, r["X"], wts, rho=rho, accumulate=True)
+    assert np.abs(rho.cpu().numpy() - 2.0 * rho_o).max() <= 1e-10 * np.abs(rho_o).max()
+    E, _, _ = lib.band_energy_grad(gop, r["X"], wts, want_dV=False, want_dX=False)
+    assert abs(float(E) - eb) <= 1e-9 * abs(eb)
