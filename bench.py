@@ -89,8 +89,14 @@ def parse():
                     help="end with one 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-copy-bw", action="store_true",
                     help="skip the 4 GiB copy-bandwidth measurement (also skipped with --calib-copy)")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for counter collection: one float64 filter of the workload; with "
+                         "--profile-extra also one float64 pass and one bf16-operand filter on diamond8")
+    ap.add_argument("--profile-extra", action="store_true")
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL_PREFIX"))
+    ap.add_argument("--summarize-mfma", metavar="DIR",
+                    help="matrix-core use per kernel and grid from an SQ_*MFMA* / GRBM_GUI_ACTIVE counter run")
     return ap.parse_args()
 
 
@@ -257,7 +263,7 @@ def kpoint_bench(oefe, wl, torch, base, m, reps):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
-        Xs = [X.to(dt) for X in blocks]
+        Xs = [X.to(dt, copy=True) for X in blocks]  # the batched filter works in place
         tune = oefe.autotune(ops, Xs, reps=3)
         oefe.chebyshev_filter_batched(ops, Xs, m, abc)  # warm-up (the filter is scaled: values stay bounded)
         torch.cuda.synchronize()
@@ -351,6 +357,34 @@ def diamond8_extra(oefe, wl, torch, reps):
     return out, gop
 
 
+def profile_run(oefe, wl, torch, cfg, args):
+    """Counter-collection run: one float64 filter (and the diamond8 extras) without timing."""
+    gop = oefe.Operator(cfg.system)
+    X = torch.from_numpy(wl.start_block(gop.n_tot, cfg.nv, cfg.x0_seed)).cuda()
+    v0 = torch.from_numpy(wl.lanczos_start(gop.n_tot, cfg.v0_seed)).cuda()
+    a0, b, a = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k, with_cut=True)
+    oefe.chebyshev_filter(gop, X, cfg.m, a, b, a0)
+    torch.cuda.synchronize()
+    log(f"profile: {cfg.system.name} float64 filter done")
+    del X, gop
+    if args.profile_extra:
+        from paper_2010_09701_amd.chfsi import chfsi_run
+        c8 = wl.config("diamond8")
+        g8 = oefe.Operator(c8.system)
+        X8 = torch.from_numpy(wl.start_block(g8.n_tot, c8.nv, c8.x0_seed)).cuda()
+        v8 = torch.from_numpy(wl.lanczos_start(g8.n_tot, c8.v0_seed)).cuda()
+        chfsi_run(g8, X8, v8, c8.m, 1, c8.lanczos_k, "f64")
+        chfsi_run(g8, X8, v8, c8.m, 1, c8.lanczos_k, "bf16")
+        torch.cuda.synchronize()
+        log("profile: diamond8 float64 pass and bf16 pass done")
+    if args.calib_copy:
+        a_ = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        c_ = torch.empty_like(a_)
+        torch.cuda.synchronize()
+        c_.copy_(a_)
+        torch.cuda.synchronize()
+
+
 def summarize_trace(d):
     f = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
     if not f:
@@ -394,6 +428,38 @@ def _per_kernel(rows, counter):
     return out
 
 
+MFMA_PEAK_TFLOPS = {"F64": 78.6, "F32": 157.3, "BF16": 2500.0}
+
+
+def summarize_mfma(d):
+    """Per (kernel, grid size): median per dispatch of the matrix-core counters.  GRBM_GUI_ACTIVE is
+    summed over the 8 XCDs (so the kernel's cycles are a eighth of it); utilisation =
+    SQ_VALU_MFMA_BUSY_CYCLES / (cycles x 1024 SIMDs); flops = SQ_INSTS_VALU_MFMA_MOPS_<type> x 512."""
+    acc = {}
+    meta = {}
+    for r in _counter_rows(d):
+        key = (_short(r["Kernel_Name"]), r["Grid_Size"], r["Dispatch_Id"])
+        acc.setdefault(key, {})[r["Counter_Name"]] = acc.get(key, {}).get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        meta[key] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-3
+    groups = {}
+    for (k, g, di), c in acc.items():
+        if c.get("SQ_INSTS_MFMA", 0.0) <= 0:
+            continue
+        groups.setdefault((k, g), []).append((c, meta[(k, g, di)]))
+    print("| kernel | grid | dispatches | us (cycles / 2.4 GHz) | MFMA busy % | MFMA type | TFLOP/s | of peak |")
+    print("|---|---:|---:|---:|---:|---|---:|---:|")
+    for (k, g), lst in sorted(groups.items(), key=lambda t: -len(t[1])):
+        lst.sort(key=lambda t: t[0]["GRBM_GUI_ACTIVE"])
+        c, _ = lst[len(lst) // 2]
+        cyc = c["GRBM_GUI_ACTIVE"] / 8.0
+        us = cyc / 2.4e3
+        util = 100.0 * c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (cyc * 1024.0)
+        typ = max(("F64", "F32", "BF16"), key=lambda t: c.get("SQ_INSTS_VALU_MFMA_MOPS_" + t, 0.0))
+        fl = c.get("SQ_INSTS_VALU_MFMA_MOPS_" + typ, 0.0) * 512.0
+        tfs = fl / (us * 1e-6) / 1e12
+        print(f"| `{k}` | {g} | {len(lst)} | {us:.1f} | {util:.1f} | {typ} | {tfs:.2f} | {tfs / MFMA_PEAK_TFLOPS[typ]:.3f} |")
+
+
 def summarize_traffic(fetch_dir, write_dir, prefix):
     fe = _per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
     wr = _per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
@@ -425,6 +491,9 @@ def main():
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
         return
+    if args.summarize_mfma:
+        summarize_mfma(args.summarize_mfma)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
@@ -437,6 +506,9 @@ def main():
     cfg = wl.config(args.workload)
     sysm = cfg.system
     torch.cuda.set_device(0)
+    if args.profile:
+        profile_run(oefe, wl, torch, cfg, args)
+        return
     t = time.time()
     gop = oefe.Operator(sysm)
     log(f"operator setup {time.time() - t:.1f} s, n_tot={gop.n_tot}, nv={cfg.nv}, m={cfg.m}")

@@ -94,8 +94,11 @@ typedef struct oefe_op_s* oefe_op;
 /* Build the operator on the current HIP device: quadrature rules, lumped GLL
  * mass (eqnMcc), potential, orthogonalized enrichment (eqnorthC, eqnorthCGLL),
  * blocks M^oo (eqnMoo), H^co, H^oo, S = (M^oo)^-1/2; uploads device data.
+ * The FE rows are grouped into coupling tiles of 64 rows: 64 consecutive rows, or blocks
+ * of 16 x 2 x 2 FE nodes where those couple to clearly fewer enrichment functions in all
+ * (the operator's choice, made here).
  * Errors: EINVAL (bad description, or more than 144 enrichment functions coupling
- * to one block of 16 x 2 x 2 FE nodes), EUNSUPPORTED (p), ENOMEM, EDEVICE. */
+ * to one coupling tile), EUNSUPPORTED (p), ENOMEM, EDEVICE. */
 int oefe_op_create(const oefe_system_desc* desc, oefe_op* out);
 
 /* Test operator Ht = diag(lambda) (n real entries, host memory), no mesh. */
@@ -104,8 +107,8 @@ int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out);
 int oefe_op_destroy(oefe_op op);
 
 /* dims[0..10] = n_fe, n_enr, n_tot, n_cells, nq, nc, p, is_complex,
- * coupling-tile slots (sum over the tiles, blocks of 16 x 2 x 2 FE nodes, of the
- * number of enrichment functions each couples to, padded to 4), tile_rows (64),
+ * coupling-tile slots (sum over the coupling tiles of the number of enrichment
+ * functions each couples to, padded to 4), tile_rows (64),
  * nonzeros of H^co (FE row, enrichment function pairs whose supports overlap).
  * dims must hold 11 entries. */
 int oefe_op_dims(oefe_op op, int64_t* dims);

@@ -331,44 +331,64 @@ int upload_operator(oefe_op_s* op, std::string& err) {
         for (int f = 0; f < B.nf; ++f) fr_fn[k + f] = B.fn0 + f;
       }
     }
-    // enrichment tiles (blocks of 16 x 2 x 2 FE nodes, tile_node): union of functions over the rows
+    // enrichment tiles: union of functions over the rows of each tile (tile_node).  The block
+    // shape (mode 1) is taken when it needs clearly fewer (tile, function) slots than runs of
+    // consecutive rows (mode 0): where atoms are dense relative to the mesh.
     {
-      op->n_tiles = tile_count(op->n);
-      std::vector<int32_t> tfptr(op->n_tiles + 1, 0), tfns;
-      std::vector<int32_t> slot(op->n_enr, -1);
-      op->csr_to_tile.assign(op->fr_nnz, 0);
-      int fpmax = 0;
-      for (int64_t t = 0; t < op->n_tiles; ++t) {
-        std::vector<int32_t> fl;
-        for (int r = 0; r < kTileRows; ++r) {
-          const int g = tile_node((int)t, r, op->n);
-          if (g < 0) continue;
-          for (int64_t k = fr_ptr[g]; k < fr_ptr[g + 1]; ++k)
-            if (slot[fr_fn[k]] < 0) {
-              slot[fr_fn[k]] = 0;
-              fl.push_back(fr_fn[k]);
-            }
+      struct Tiling {
+        std::vector<int32_t> tfptr, tfns;
+        std::vector<int64_t> csr_to_tile;
+        int fpmax = 0;
+      };
+      auto build_tiles = [&](int mode, Tiling& T) {
+        const int nt = tile_count(op->n, mode);
+        T.tfptr.assign(nt + 1, 0);
+        T.tfns.clear();
+        T.csr_to_tile.assign(op->fr_nnz, 0);
+        T.fpmax = 0;
+        std::vector<int32_t> slot(op->n_enr, -1);
+        for (int t = 0; t < nt; ++t) {
+          std::vector<int32_t> fl;
+          for (int r = 0; r < kTileRows; ++r) {
+            const int g = tile_node(t, r, op->n, mode);
+            if (g < 0) continue;
+            for (int64_t k = fr_ptr[g]; k < fr_ptr[g + 1]; ++k)
+              if (slot[fr_fn[k]] < 0) {
+                slot[fr_fn[k]] = 0;
+                fl.push_back(fr_fn[k]);
+              }
+          }
+          std::sort(fl.begin(), fl.end());
+          const int F = (int)fl.size(), FP = (F + 3) / 4 * 4;
+          for (int j = 0; j < F; ++j) slot[fl[j]] = j;
+          for (int r = 0; r < kTileRows; ++r) {
+            const int g = tile_node(t, r, op->n, mode);
+            if (g < 0) continue;
+            for (int64_t k = fr_ptr[g]; k < fr_ptr[g + 1]; ++k)
+              T.csr_to_tile[k] = (int64_t)T.tfptr[t] * kTileRows + (int64_t)r * FP + slot[fr_fn[k]];
+          }
+          for (int j = 0; j < FP; ++j) T.tfns.push_back(j < F ? fl[j] : -1);
+          for (int32_t f : fl) slot[f] = -1;
+          T.tfptr[t + 1] = T.tfptr[t] + FP;
+          T.fpmax = std::max(T.fpmax, FP);
         }
-        std::sort(fl.begin(), fl.end());
-        const int F = (int)fl.size(), FP = (F + 3) / 4 * 4;
-        for (int j = 0; j < F; ++j) slot[fl[j]] = j;
-        for (int r = 0; r < kTileRows; ++r) {
-          const int g = tile_node((int)t, r, op->n);
-          if (g < 0) continue;
-          for (int64_t k = fr_ptr[g]; k < fr_ptr[g + 1]; ++k)
-            op->csr_to_tile[k] = (int64_t)tfptr[t] * kTileRows + (int64_t)r * FP + slot[fr_fn[k]];
-        }
-        for (int j = 0; j < FP; ++j) tfns.push_back(j < F ? fl[j] : -1);
-        for (int32_t f : fl) slot[f] = -1;
-        tfptr[t + 1] = tfptr[t] + FP;
-        fpmax = std::max(fpmax, FP);
-      }
+      };
+      Tiling T0, T1;
+      build_tiles(0, T0);
+      build_tiles(1, T1);
+      const bool blocks_win = (double)T1.tfptr.back() <= 0.85 * (double)T0.tfptr.back();
+      Tiling& T = blocks_win ? T1 : T0;
+      op->tile_mode = blocks_win ? 1 : 0;
+      op->n_tiles = tile_count(op->n, op->tile_mode);
+      std::vector<int32_t> tfptr = std::move(T.tfptr), tfns = std::move(T.tfns);
+      op->csr_to_tile = std::move(T.csr_to_tile);
+      const int fpmax = T.fpmax;
       op->tile_slots = tfptr[op->n_tiles];
       op->tile_fpmax = fpmax;
       // the node-stage kernels hold one tile's dense block in LDS
       if (fpmax > kTileFunctionsMax) {
         err = "enrichment too dense for the node stage: a tile of " + std::to_string(kTileRows) +
-              " FE nodes (a 16 x 2 x 2 block) couples to " + std::to_string(fpmax) + " functions (at most " +
+              " FE nodes couples to " + std::to_string(fpmax) + " functions (at most " +
               std::to_string(kTileFunctionsMax) + ")";
         return OEFE_EINVAL;
       }
@@ -1443,7 +1463,8 @@ int chebyshev_filter_batched(int32_t nk, const oefe_op* ops, oefe_prec prec, voi
     const oefe_op_s* a = ops[0];
     const oefe_op_s* b = ops[q];
     if (b->diagonal || a->diagonal || b->nc != a->nc || b->p != a->p || b->L != a->L || b->n_enr != a->n_enr ||
-        b->n_tiles != a->n_tiles || b->tile_slots != a->tile_slots || b->tile_fpmax != a->tile_fpmax)
+        b->n_tiles != a->n_tiles || b->tile_mode != a->tile_mode || b->tile_slots != a->tile_slots ||
+        b->tile_fpmax != a->tile_fpmax)
       return fail(OEFE_EINVAL, "batched operators must share the mesh and the enrichment layout");
     const double aa = abc[3 * q], bb = abc[3 * q + 1], a0 = abc[3 * q + 2];
     if (!(aa < bb) || !(a0 < aa)) return fail(OEFE_EINVAL, "need a0 < a < b for every operator");
@@ -1469,7 +1490,8 @@ int oefe_autotune(int32_t nk, const oefe_op* ops, oefe_prec prec, void* const* X
     const oefe_op_s* a = ops[0];
     const oefe_op_s* b = ops[q];
     if (b->nc != a->nc || b->p != a->p || b->L != a->L || b->n_enr != a->n_enr || b->cplx != a->cplx ||
-        b->n_tiles != a->n_tiles || b->tile_slots != a->tile_slots || b->tile_fpmax != a->tile_fpmax)
+        b->n_tiles != a->n_tiles || b->tile_mode != a->tile_mode || b->tile_slots != a->tile_slots ||
+        b->tile_fpmax != a->tile_fpmax)
       return fail(OEFE_EINVAL, "operators must share mesh and enrichment layout");
   }
   hipStream_t s = (hipStream_t)stream;

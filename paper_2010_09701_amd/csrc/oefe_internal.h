@@ -16,21 +16,68 @@ namespace oefe {
 constexpr int kMaxP1 = 5;  // supported GLL nodes per edge: 3, 4, 5 (degree 2..4)
 constexpr int kTileRows = 64;  // FE rows per enrichment tile
 
-// Enrichment coupling tiles: tile t is the block of 16 x 2 x 2 FE nodes starting at node
-// (16 bx, 2 by, 2 bz), t = bx + nbx (by + nby bz), nbx = ceil(n / 16), nby = ceil(n / 2)
-// (n nodes per edge); its row r is the node (16 bx + r % 16, 2 by + (r / 16) % 2,
-// 2 bz + r / 32), or none (-1) past the mesh.  Such a block couples to fewer enrichment
-// functions than 64 consecutive nodes of one x-line, and each 16-row group (one wave of the
-// node stage) still lies on one x-line, where every node has the same slots in y and z.
-__host__ __device__ inline int tile_count(int n) {
+// Enrichment coupling tiles of kTileRows FE rows, in one of two shapes chosen per operator:
+//  mode 0: 64 consecutive FE rows, g = 64 t + r;
+//  mode 1: the block of 16 x 2 x 2 FE nodes starting at node (16 bx, 2 by, 2 bz),
+//          t = bx + nbx (by + nby bz), nbx = ceil(n / 16), nby = ceil(n / 2) (n nodes per edge),
+//          row r = the node (16 bx + r % 16, 2 by + (r / 16) % 2, 2 bz + r / 32).
+// A block couples to fewer enrichment functions than 64 nodes of one x-line where atoms are
+// dense relative to the mesh, and each 16-row group (one wave of the node stage) still lies on
+// one x-line, where every node has the same slots in y and z.  Rows past the mesh: none (-1).
+__host__ __device__ inline int tile_count(int n, int mode) {
+  if (mode == 0) return (int)(((int64_t)n * n * n + 63) / 64);
   const int nbx = (n + 15) >> 4, nby = (n + 1) >> 1;
   return nbx * nby * nby;
 }
-__host__ __device__ inline int tile_node(int t, int r, int n) {
+// first node of tile t: (x0, y0, z0) in mode 1; in mode 0 x0 = 64 t (the first row)
+__host__ __device__ inline void tile_origin(int t, int n, int mode, int& x0, int& y0, int& z0) {
+  if (mode == 0) {
+    x0 = 64 * t;
+    y0 = z0 = 0;
+    return;
+  }
   const int nbx = (n + 15) >> 4, nby = (n + 1) >> 1;
-  const int bx = t % nbx, rest = t / nbx, by = rest % nby, bz = rest / nby;
-  const int ix = 16 * bx + (r & 15), iy = 2 * by + ((r >> 4) & 1), iz = 2 * bz + (r >> 5);
+  const int rest = t / nbx;
+  x0 = 16 * (t - rest * nbx);
+  y0 = 2 * (rest % nby);
+  z0 = 2 * (rest / nby);
+}
+// FE row of row r of the tile with origin (x0, y0, z0) and its node (ix, iy, iz), or -1 past the
+// mesh (then ix = iy = iz = 0)
+__host__ __device__ inline int tile_row_coords(int x0, int y0, int z0, int r, int n, int mode, int& ix, int& iy,
+                                               int& iz) {
+  if (mode == 0) {
+    const int g = x0 + r, nn = n * n;
+    if (g >= nn * n) {
+      ix = iy = iz = 0;
+      return -1;
+    }
+    iz = g / nn;
+    const int rem = g - iz * nn;
+    iy = rem / n;
+    ix = rem - iy * n;
+    return g;
+  }
+  ix = x0 + (r & 15);
+  iy = y0 + ((r >> 4) & 1);
+  iz = z0 + (r >> 5);
+  if (ix < n && iy < n && iz < n) return ix + n * (iy + n * iz);
+  ix = iy = iz = 0;
+  return -1;
+}
+// FE row of row r of the tile with origin (x0, y0, z0), or -1 past the mesh
+__host__ __device__ inline int tile_row_node(int x0, int y0, int z0, int r, int n, int mode) {
+  if (mode == 0) {
+    const int g = x0 + r;
+    return g < n * n * n ? g : -1;
+  }
+  const int ix = x0 + (r & 15), iy = y0 + ((r >> 4) & 1), iz = z0 + (r >> 5);
   return (ix < n && iy < n && iz < n) ? ix + n * (iy + n * iz) : -1;
+}
+__host__ __device__ inline int tile_node(int t, int r, int n, int mode) {
+  int x0, y0, z0;
+  tile_origin(t, n, mode, x0, y0, z0);
+  return tile_row_node(x0, y0, z0, r, n, mode);
 }
 // enrichment functions one tile may couple to: the node-stage kernels stage a tile's dense
 // block (complex: two planes of kTileRows x (F + 1) float64) in 150 KB of LDS
@@ -169,6 +216,7 @@ struct oefe_op_s {
   std::vector<std::vector<int64_t>> fr_pos;  // per block, per row: CSR position of its first function
   std::vector<int64_t> csr_to_tile;           // CSR entry -> index into tile_val
   int64_t n_tiles = 0, tile_slots = 0;        // tiles, total padded (tile, function) slots
+  int tile_mode = 0;                           // coupling-tile shape (tile_count)
   int tile_fpmax = 0;
   int fn_smax = 0;  // most tile partials of one enrichment function
   oefe::DeviceArrays d;

@@ -754,7 +754,7 @@ __global__ __launch_bounds__(768) void fe_cell_bf16_kernel(KBatch<float> kb, con
 // critical path:
 //
 // fe_coupling_kernel (side stream, beside the cell stage; needs only X and Z^O):
-//   for each tile t of kTileRows FE rows (a 16 x 2 x 2 node block) and each group of 16 NBW real columns
+//   for each coupling tile t of kTileRows FE rows (tile_node) and each group of 16 NBW real columns
 //     part_t = Ht_t^* X_t              -> per-tile partial of W' (reduced later)
 //     out_t  = alpha Ht_t Z^O - beta prev_t
 //   (Ht_t: the tile's dense block of m^-1/2 H^co) on the matrix cores (16x16x4 MFMA,
@@ -806,8 +806,9 @@ constexpr size_t coupling_lds_bytes(int fpmax) {
 // pc[q][nb] += Ht_t[r][m0 + 16 q + .]^* x[r][cols of block nb], k-steps of 4 rows with the
 // x loads of 4 k-steps issued ahead of their MFMAs; Ht_t from LDS (planes hs[e])
 template <typename T, int NQ, int NBW, bool CPLX>
-__device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __restrict__ x, int64_t ldx, int t,
-                                              int n, int FP, int m0, const int (&colc)[NBW], int li, int lk,
+__device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __restrict__ x, int64_t ldx, int tx0,
+                                              int ty0, int tz0, int n, int tm, int FP, int m0, const int (&colc)[NBW], int li,
+                                              int lk,
                                               typename Mfma<T>::V4 (&pc)[4][NBW]) {
   using M = Mfma<T>;
   constexpr int TR = kTileRows, E = CPLX ? 2 : 1, KB = 4;
@@ -825,7 +826,7 @@ __device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __re
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       const int r = (ks0 + j) * 4 + lk;
-      const int gt = tile_node(t, r, n);
+      const int gt = tile_row_node(tx0, ty0, tz0, r, n, tm);
       const bool rok = gt >= 0;
       const int64_t g = rok ? gt : 0;
 #pragma unroll
@@ -856,7 +857,7 @@ __device__ __forceinline__ void coupling_part(const T* hs, int HS, const T* __re
 
 template <typename T, int NBW, bool CPLX>
 __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBatch<T> kb, const int32_t* __restrict__ tile_fptr,
-                                                          const int32_t* __restrict__ tile_fns, int n) {
+                                                          const int32_t* __restrict__ tile_fns, int n, int tm) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
   constexpr int TR = kTileRows, E = CPLX ? 2 : 1, RB = TR / 16, HPT = 8;
@@ -865,6 +866,8 @@ __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBat
   const int ncr = P.ncr;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   const int t = blockIdx.x;
+  int tx0, ty0, tz0;
+  tile_origin(t, n, tm, tx0, ty0, tz0);
   const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;  // FP: a multiple of 4
   const int HS = coupling_row_stride(FP);
   T* hs = reinterpret_cast<T*>(smem_raw);                   // [E][TR][HS]
@@ -917,10 +920,10 @@ __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBat
         for (int nb = 0; nb < NBW; ++nb) pc[q][nb] = V4{0, 0, 0, 0};
       const int nq = min(4, (FP - m0 + 15) / 16);
       switch (nq) {
-        case 4: coupling_part<T, 4, NBW, CPLX>(hs, HS, x, ldx, t, n, FP, m0, colc, li, lk, pc); break;
-        case 3: coupling_part<T, 3, NBW, CPLX>(hs, HS, x, ldx, t, n, FP, m0, colc, li, lk, pc); break;
-        case 2: coupling_part<T, 2, NBW, CPLX>(hs, HS, x, ldx, t, n, FP, m0, colc, li, lk, pc); break;
-        default: coupling_part<T, 1, NBW, CPLX>(hs, HS, x, ldx, t, n, FP, m0, colc, li, lk, pc); break;
+        case 4: coupling_part<T, 4, NBW, CPLX>(hs, HS, x, ldx, tx0, ty0, tz0, n, tm, FP, m0, colc, li, lk, pc); break;
+        case 3: coupling_part<T, 3, NBW, CPLX>(hs, HS, x, ldx, tx0, ty0, tz0, n, tm, FP, m0, colc, li, lk, pc); break;
+        case 2: coupling_part<T, 2, NBW, CPLX>(hs, HS, x, ldx, tx0, ty0, tz0, n, tm, FP, m0, colc, li, lk, pc); break;
+        default: coupling_part<T, 1, NBW, CPLX>(hs, HS, x, ldx, tx0, ty0, tz0, n, tm, FP, m0, colc, li, lk, pc); break;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -986,7 +989,7 @@ __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBat
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t g = max(tile_node(t, rb * 16 + M::row(lane, v), n), 0);
+          const int64_t g = max(tile_row_node(tx0, ty0, tz0, rb * 16 + M::row(lane, v), n, tm), 0);
 #pragma unroll
           for (int nb = 0; nb < NBW; ++nb) pv[rb][v][nb] = beta * P.prev[g * ldo + colc[nb]];
         }
@@ -1002,7 +1005,7 @@ __global__ __launch_bounds__(256, NBW == 1 ? 2 : 1) void fe_coupling_kernel(KBat
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gv = tile_node(t, rb * 16 + M::row(lane, v), n);
+        const int gv = tile_row_node(tx0, ty0, tz0, rb * 16 + M::row(lane, v), n, tm);
         if (gv < 0) continue;
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb)
@@ -1100,7 +1103,7 @@ __device__ __forceinline__ void assemble_one(const KP<T>& P, int64_t i, int nel,
 }
 
 // Node stage of real operators in one kernel, fe_node_fused_kernel: one workgroup (4
-// waves) per tile of kTileRows FE rows (a 16 x 2 x 2 node block) x 16 NB real columns computes part, the slot
+// waves) per coupling tile of kTileRows FE rows (tile_node) x 16 NB real columns computes part, the slot
 // gather and out = alpha (m^-1/2 sum_slots(Y) + Ht_t Z^O - c x) - beta prev.  Order within
 // the workgroup: one batch of loads (x tile, H tile, function list; float32 also the
 // first slot pair of the gather, which lands during the matrix-core phase), part on the
@@ -1138,7 +1141,7 @@ template <typename T, int NB>
 __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBatch<T> kb, int nc, int p, int n, int P1,
                                                                CellCoef<T> cf, const int32_t* __restrict__ tile_fptr,
                                                                const int32_t* __restrict__ tile_fns, int N, int ncb,
-                                                               int hs_cap) {
+                                                               int hs_cap, int tm) {
   using M = Mfma<T>;
   using V4 = typename M::V4;
   constexpr int TR = kTileRows, CBW = NB * 16, XS = lds_row_stride(CBW);
@@ -1183,8 +1186,9 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
     colc[nb] = colok[nb] ? col : ncr - 1;
   }
   // node-slot grid columns, not clamped: a row of the grid (ldc >= ncr, a multiple of 8) is
-  // followed by the next row or by the grid's padding row, so columns up to ldc + 7 stay in
-  // the allocation; their values only reach lanes whose output is not stored.  The loads of a
+  // followed by the next row or by the grid's padding (one row plus 16 kNodeNBMax elements,
+  // slot_grid_elems), so every column this block reads, below ncr + 16 NB, stays in the
+  // allocation; values past ncr only reach lanes whose output is not stored.  The loads of a
   // row then differ by constant offsets.
   const T* __restrict__ Ycl = P.ycell + cb0 + li;
 
@@ -1193,13 +1197,14 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   int bx[4], by[4], bz[4], gc[4];
   bool x2[4], y2[4], z2[4], ok[4];
   T msc[4];
+  int tx0, ty0, tz0;  // the tile's first node (uniform)
+  tile_origin(t, n, tm, tx0, ty0, tz0);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int gv = tile_node(t, w * 16 + M::row(lane, v), n);
+    int ix, iy, iz;
+    const int gv = tile_row_coords(tx0, ty0, tz0, w * 16 + M::row(lane, v), n, tm, ix, iy, iz);
     ok[v] = gv >= 0;
-    const int g = ok[v] ? gv : 0;
-    gc[v] = g;
-    const int iz = g / (n * n), rem = g - iz * n * n, iy = rem / n, ix = rem - iy * n;
+    gc[v] = ok[v] ? gv : 0;
     const int qx = ix / p, rx = ix - qx * p, qy = iy / p, ry = iy - qy * p, qz = iz / p, rz = iz - qz * p;
     bx[v] = qx * P1 + (rx ? rx + 1 : 0);
     by[v] = qy * P1 + (ry ? ry + 1 : 0);
@@ -1236,7 +1241,7 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   bool rowok[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int gr = tile_node(t, tr + 16 * i, n);
+    const int gr = tile_row_node(tx0, ty0, tz0, tr + 16 * i, n, tm);
     rowok[i] = gr >= 0;
     xrow[i] = x + (int64_t)(rowok[i] ? gr : 0) * ldx + cb0;
   }
@@ -1963,7 +1968,7 @@ void launch_coupling_w(const oefe_op_s* op, const KBatch<T>& kb, hipStream_t s) 
   const size_t lds = coupling_lds_bytes<T, CPLX>(op->tile_fpmax);
   if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_coupling_kernel<T, NBW, CPLX>), lds) != hipSuccess) return;
   hipLaunchKernelGGL((fe_coupling_kernel<T, NBW, CPLX>), dim3((unsigned)op->n_tiles, 1, (unsigned)kb.nk), dim3(256),
-                     lds, s, kb, op->d.tile_fptr, op->d.tile_fns, op->n);
+                     lds, s, kb, op->d.tile_fptr, op->d.tile_fns, op->n, op->tile_mode);
 }
 
 // nbw: 16-column blocks per coupling wave (1 or 2)
@@ -1988,10 +1993,10 @@ template <typename T, int NB>
 void launch_node_fused_nb(const oefe_op_s* op, const KBatch<T>& kb, int ncb, hipStream_t s) {
   const size_t lds = node_lds_bytes<T, NB>(op->n_enr > 0 ? op->tile_fpmax : 0);
   if (allow_dynamic_lds(reinterpret_cast<const void*>(&fe_node_fused_kernel<T, NB>), lds) != hipSuccess) return;
-  hipLaunchKernelGGL((fe_node_fused_kernel<T, NB>), dim3((unsigned)((int64_t)tile_count(op->n) * ncb), 1u,
+  hipLaunchKernelGGL((fe_node_fused_kernel<T, NB>), dim3((unsigned)((int64_t)tile_count(op->n, op->tile_mode) * ncb), 1u,
                      (unsigned)kb.nk), dim3(256), lds, s, kb, op->nc, op->p, op->n, op->P1, coef<T>(op),
                      op->n_enr > 0 ? op->d.tile_fptr : nullptr, op->d.tile_fns, (int)op->N, ncb,
-                     node_hs_cap<T, NB>(op->n_enr > 0 ? op->tile_fpmax : 0));
+                     node_hs_cap<T, NB>(op->n_enr > 0 ? op->tile_fpmax : 0), op->tile_mode);
 }
 
 template <typename T>
@@ -2172,14 +2177,21 @@ void launch_density(const oefe_op_s* op, const T* x, int64_t ldx, int ncr, const
 
 }  // namespace
 
+// Node-slot grid elements: n_cells nd rows of ldc, then a padding of one row plus 16 kNodeNBMax
+// elements.  The fused node kernel reads the columns of a row without clamping them to ncr:
+// at most cb0 + 16 NB - 1 < ncr + 16 kNodeNBMax - 1 for a column block that starts below ncr,
+// so the reads past the last row's end stay inside the padding (ncr <= ldc).
+static size_t slot_grid_elems(const oefe_op_s* op, int ldc) {
+  return (size_t)op->n_cells * op->nd * ldc + (size_t)ldc + 16 * kNodeNBMax;
+}
+
 size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, int* ldc_out) {
   const int ncr = cplx ? 2 * nv : nv;
   const int ldc = (int)cdiv(ncr, 8) * 8;
   if (ldc_out) *ldc_out = ldc;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t bytes = 0;
-  // node-slot grid plus one row: the fused node kernel reads up to 8 columns past a row's end
-  if (!op->diagonal) bytes += al(((size_t)op->n_cells * op->nd + 1) * ldc * elem_bytes);
+  if (!op->diagonal) bytes += al(slot_grid_elems(op, ldc) * elem_bytes);
   bytes += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);                 // zo
   bytes += al((size_t)std::max<int64_t>(op->tile_slots, 1) * ncr * elem_bytes);  // part
   bytes += al((size_t)std::max(op->n_enr, 1) * reduce_chunks(op) * ncr * elem_bytes);  // part2
@@ -2197,7 +2209,7 @@ StepWork carve_step_work(const oefe_op_s* op, int elem_bytes, bool cplx, int nv,
   char* p = (char*)work;
   if (!op->diagonal) {
     w.ycell = p;
-    p += al(((size_t)op->n_cells * op->nd + 1) * ldc * elem_bytes);
+    p += al(slot_grid_elems(op, ldc) * elem_bytes);
   }
   w.zo = p;
   p += al((size_t)std::max(op->n_enr, 1) * ncr * elem_bytes);
