@@ -34,6 +34,7 @@ oracle on a bounded sample of the headline workload (`cpu_baseline`).
 
 Helpers for the committed profile summaries (they read rocprofv3 output):
     python bench.py --summarize-trace DIR           kernel-trace statistics table
+    python bench.py --summarize-gaps DIR KERNEL     device idle time per filter degree
     python bench.py --summarize-traffic FETCH_DIR WRITE_DIR KERNEL_PREFIX
                                                     HBM bytes per launch of the most frequent
                                                     kernel matching the prefix, from FETCH_SIZE /
@@ -94,6 +95,9 @@ def parse():
                          "--profile-extra also one float64 pass and one bf16-operand filter on diamond8")
     ap.add_argument("--profile-extra", action="store_true")
     ap.add_argument("--summarize-trace", metavar="DIR")
+    ap.add_argument("--summarize-gaps", nargs=2, metavar=("DIR", "KERNEL"),
+                    help="per filter degree (between successive launches of KERNEL): period, time with a "
+                         "kernel running on any stream, idle remainder, launches")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL_PREFIX"))
     ap.add_argument("--summarize-mfma", metavar="DIR",
                     help="matrix-core use per kernel and grid from an SQ_*MFMA* / GRBM_GUI_ACTIVE counter run")
@@ -396,6 +400,45 @@ def summarize_trace(d):
               f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
 
 
+def summarize_gaps(d, key):
+    """Idle time of the device per filter degree from a kernel trace: the degree is the interval
+    between successive starts of the kernel named `key`; its busy time is the union of the
+    intervals of every kernel (any stream) inside it.  Grouped by the degree's period, so that
+    filters of different workloads in one trace fall into separate rows."""
+    f = sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True))
+    if not f:
+        sys.exit(f"no kernel_trace.csv under {d}")
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in csv.DictReader(open(f[0])))
+    starts = sorted(int(r["Start_Timestamp"]) for r in csv.DictReader(open(f[0])) if key in _short(r["Kernel_Name"]))
+    rows = []
+    for a, b in zip(starts[:-1], starts[1:]):
+        if b - a > 20_000_000:  # not consecutive degrees of one filter
+            continue
+        iv = sorted((max(s, a), min(e, b)) for s, e in ev if e > a and s < b)
+        busy, (cs, ce) = 0, iv[0]
+        for s, e in iv[1:]:
+            if s > ce:
+                busy, cs, ce = busy + ce - cs, s, e
+            else:
+                ce = max(ce, e)
+        busy += ce - cs
+        rows.append(((b - a) / 1e3, busy / 1e3, sum(1 for s, _ in ev if a <= s < b)))
+    rows.sort()
+    print(f"kernel `{key}`: {len(rows)} degrees")
+    print("| degrees | period us (median) | busy us | idle us | idle % | launches |")
+    print("|---:|---:|---:|---:|---:|---:|")
+    grp = []
+    for r in rows + [None]:
+        if grp and (r is None or r[0] > 1.5 * grp[0][0]):
+            g = np.array(grp)
+            i = len(g) // 2
+            print(f"| {len(g)} | {g[i, 0]:.1f} | {g[i, 1]:.1f} | {np.median(g[:, 0] - g[:, 1]):.1f} | "
+                  f"{100 * np.median((g[:, 0] - g[:, 1]) / g[:, 0]):.2f} | {int(np.median(g[:, 2]))} |")
+            grp = []
+        if r is not None:
+            grp.append(r)
+
+
 def _short(name):
     n = name.replace("void ", "").replace("oefe::(anonymous namespace)::", "").replace("oefe::", "")
     out, depth = "", 0
@@ -487,6 +530,9 @@ def main():
     args = parse()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_gaps:
+        summarize_gaps(*args.summarize_gaps)
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
