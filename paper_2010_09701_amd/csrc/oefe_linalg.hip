@@ -97,16 +97,14 @@ typedef double dv4 __attribute__((ext_vector_type(4)));
 constexpr int kGramNBMax = 5;   // 16-column blocks per operand
 constexpr int kGramChunks = 256;
 
+// One workgroup's share: 16-row blocks ib0 .. ib0 + NBI - 1 of G = A^T B over rows g0 .. g1 - 1,
+// written to out (row-major na x nb).  gsm: [NBI * NBJ * 4][64] doubles of LDS.
 template <int NBI, int NBJ>
-__global__ __launch_bounds__(256, NBI == 1 ? 4 : 1) void gram_mfma_kernel(const double* __restrict__ A, int64_t lda, int na,
-                                                           const double* __restrict__ B, int64_t ldb, int nb,
-                                                           int64_t n, int64_t rows_per_chunk,
-                                                           double* __restrict__ part) {
-  extern __shared__ double gsm[];  // [NBI * NBJ * 4][64]
+__device__ __forceinline__ void gram_mfma_body(const double* __restrict__ A, int64_t lda, int na,
+                                               const double* __restrict__ B, int64_t ldb, int nb, int64_t g0,
+                                               int64_t g1, int ib0, double* __restrict__ out, double* gsm) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk, g1 = min(n, g0 + rows_per_chunk);
-  const int ib0 = blockIdx.y * NBI;  // this workgroup's first 16-row block of G
   int ca[NBI], cb[NBJ];
   double ma[NBI], mb[NBJ];
 #pragma unroll
@@ -169,11 +167,74 @@ __global__ __launch_bounds__(256, NBI == 1 ? 4 : 1) void gram_mfma_kernel(const 
               slot(i, j, v) = t;
             } else {
               const int row = (ib0 + i) * 16 + lk + 4 * v, col = j * 16 + li;
-              if (row < na && col < nb) part[(int64_t)blockIdx.x * na * nb + (int64_t)row * nb + col] = t;
+              if (row < na && col < nb) out[(int64_t)row * nb + col] = t;
             }
           }
     }
     if (step > 0) __syncthreads();
+  }
+}
+
+template <int NBI, int NBJ>
+__global__ __launch_bounds__(256, NBI == 1 ? 4 : 1) void gram_mfma_kernel(const double* __restrict__ A, int64_t lda, int na,
+                                                           const double* __restrict__ B, int64_t ldb, int nb,
+                                                           int64_t n, int64_t rows_per_chunk,
+                                                           double* __restrict__ part) {
+  extern __shared__ double gsm[];
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk, g1 = min(n, g0 + rows_per_chunk);
+  gram_mfma_body<NBI, NBJ>(A, lda, na, B, ldb, nb, g0, g1, blockIdx.y * NBI, part + (int64_t)blockIdx.x * na * nb,
+                           gsm);
+}
+
+// Gram matrices of blocks wider than 16 kGramNBMax columns in one launch: G is cut into
+// column groups of at most 16 kGramNBMax (near-equal), and each (I, J) pair of groups is one
+// matrix-core Gram as above.  Pair p covers rows i0[p] .. i0[p] + ni[p] - 1 of G (columns of A)
+// and columns j0[p] .. of G (columns of B); with A = B only the pairs I <= J are computed and
+// the rest of G is their mirror image.
+constexpr int kGramPairsMax = 64;
+struct GramPairs {
+  int np, gs;  // pairs; partial-block stride (gs x gs doubles, gs = the largest group)
+  int i0[kGramPairsMax], ni[kGramPairsMax], j0[kGramPairsMax], nj[kGramPairsMax];
+};
+
+// workgroup L (after the XCD remap) = ((chunk np + pair) rbs + row block): the workgroups of one
+// row chunk are contiguous in L, so each XCD (workgroups bk = x mod 8, a contiguous range of L)
+// reads a chunk's rows of A and B from HBM once for all pairs and row blocks
+__global__ __launch_bounds__(256, 4) void gram_mfma_pairs_kernel(const double* __restrict__ A, int64_t lda,
+                                                                 const double* __restrict__ B, int64_t ldb, int64_t n,
+                                                                 int64_t rows_per_chunk, int nch, GramPairs gp,
+                                                                 double* __restrict__ part) {
+  extern __shared__ double gsm[];
+  const int nbk = gridDim.x, bk = blockIdx.x, nb8 = nbk & ~7;
+  const int L = bk < nb8 ? (bk & 7) * (nb8 >> 3) + (bk >> 3) : bk;
+  const int rbs = (gp.gs + 15) >> 4;
+  const int rb = L % rbs, rest = L / rbs;
+  const int p = rest % gp.np, chunk = rest / gp.np;
+  const int na = gp.ni[p], nb = gp.nj[p];
+  if (rb * 16 >= na) return;  // whole workgroup: no barrier is pending
+  const int64_t g0 = (int64_t)chunk * rows_per_chunk, g1 = min(n, g0 + rows_per_chunk);
+  gram_mfma_body<1, kGramNBMax>(A + gp.i0[p], lda, na, B + gp.j0[p], ldb, nb, g0, g1, rb,
+                                part + ((int64_t)p * nch + chunk) * gp.gs * gp.gs, gsm);
+}
+
+// G entries of pair blockIdx.y = sum over the chunks, one wave per entry (lane-strided chunks in
+// order, then a fixed butterfly); mirror != 0 also writes the transposed entry of an off-diagonal pair
+__global__ __launch_bounds__(256) void gram_reduce_pairs_kernel(const double* __restrict__ part, int nch, GramPairs gp,
+                                                                double* __restrict__ G, int ldg, int mirror) {
+  const int p = blockIdx.y;
+  const int na = gp.ni[p], nb = gp.nj[p];
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= na * nb) return;
+  const double* pp = part + (int64_t)p * nch * gp.gs * gp.gs;
+  double s = 0.0;
+  for (int c = lane; c < nch; c += 64) s += pp[(int64_t)c * gp.gs * gp.gs + idx];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) {
+    const int i = gp.i0[p] + idx / nb, j = gp.j0[p] + idx % nb;
+    G[(int64_t)i * ldg + j] = s;
+    if (mirror && gp.i0[p] != gp.j0[p]) G[(int64_t)j * ldg + i] = s;
   }
 }
 
@@ -1564,10 +1625,40 @@ static bool gram_mfma_tiled(bool cplx, int na, int nb) {
   return !cplx && na >= 16 && nb >= 16 && (na > 16 * kGramNBMax || nb > 16 * kGramNBMax);
 }
 
+// column groups of a tiled Gram and the chunks of its pairs launch: every workgroup of the launch
+// resident in one round of 1024 slots (four per CU on 256 CUs); fixed, so that the summation order
+// does not depend on the device
+static int gram_pairs_chunks(int64_t n, int np, int gs) {
+  return std::max(1, std::min(gram_mfma_chunks(n), 1024 / std::max(1, np * (int)cdiv(gs, 16))));
+}
+static bool gram_pairs(const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, GramPairs& gp,
+                       bool& sym) {
+  const int gi = (int)cdiv(na, 16 * kGramNBMax), gj = (int)cdiv(nb, 16 * kGramNBMax);
+  sym = A == B && lda == ldb && na == nb;
+  gp.np = 0;
+  gp.gs = 0;
+  for (int I = 0; I < gi; ++I)
+    for (int J = sym ? I : 0; J < gj; ++J) {
+      if (gp.np == kGramPairsMax) return false;
+      const int q = gp.np++;
+      gp.i0[q] = (int)((int64_t)na * I / gi);
+      gp.ni[q] = (int)((int64_t)na * (I + 1) / gi) - gp.i0[q];
+      gp.j0[q] = (int)((int64_t)nb * J / gj);
+      gp.nj[q] = (int)((int64_t)nb * (J + 1) / gj) - gp.j0[q];
+      gp.gs = std::max(gp.gs, std::max(gp.ni[q], gp.nj[q]));
+    }
+  return true;
+}
+
 size_t gram_scratch_bytes(bool cplx, int na, int nb, int64_t n) {
   if (gram_mfma_tiled(cplx, na, nb)) {
-    const int bi = (int)cdiv(na, cdiv(na, 16 * kGramNBMax)), bj = (int)cdiv(nb, cdiv(nb, 16 * kGramNBMax));
-    return (size_t)gram_mfma_chunks(n) * bi * bj * sizeof(double);
+    const int gi = (int)cdiv(na, 16 * kGramNBMax), gj = (int)cdiv(nb, 16 * kGramNBMax);
+    const int bi = (int)cdiv(na, gi), bj = (int)cdiv(nb, gj), gs = std::max(bi, bj);
+    size_t bytes = (size_t)gram_mfma_chunks(n) * bi * bj * sizeof(double);  // one pair per launch
+    // one launch for all pairs (the symmetric case has fewer pairs, possibly more chunks)
+    for (int np : {gi * gj, gi * (gi + 1) / 2})
+      if (np <= kGramPairsMax) bytes = std::max(bytes, (size_t)np * gram_pairs_chunks(n, np, gs) * gs * gs * sizeof(double));
+    return bytes;
   }
   const int nch = gram_on_mfma(cplx, na, nb) ? gram_mfma_chunks(n) : gram_chunks(n);
   return (size_t)nch * na * nb * (cplx ? 2 : 1) * sizeof(double);
@@ -1603,7 +1694,22 @@ int gram(bool cplx, const double* A, int64_t lda, int na, const double* B, int64
   }
   if (gram_mfma_tiled(cplx, na, nb)) {
     // wide real blocks: the matrix-core Gram on every pair of column groups of at most
-    // 16 kGramNBMax columns (near-equal groups, each of at least 16 columns)
+    // 16 kGramNBMax columns (near-equal groups, each of at least 16 columns), all pairs in one
+    // launch where the pair table holds them
+    GramPairs gp;
+    bool sym = false;
+    if (gram_pairs(A, lda, na, B, ldb, nb, gp, sym)) {
+      const int nch = gram_pairs_chunks(n, gp.np, gp.gs);
+      const int64_t rpc = cdiv(cdiv(n, nch), 4) * 4;
+      const int rbs = (int)cdiv(gp.gs, 16);
+      const size_t lds = (size_t)kGramNBMax * 4 * 64 * sizeof(double);
+      if (allow_dynamic_lds(reinterpret_cast<const void*>(&gram_mfma_pairs_kernel), lds) != hipSuccess) return OEFE_EDEVICE;
+      hipLaunchKernelGGL(gram_mfma_pairs_kernel, dim3((unsigned)((int64_t)nch * gp.np * rbs)), dim3(256), lds, s, A, lda,
+                         B, ldb, n, rpc, nch, gp, scratch);
+      hipLaunchKernelGGL(gram_reduce_pairs_kernel, dim3((unsigned)cdiv((int64_t)gp.gs * gp.gs, 4), (unsigned)gp.np),
+                         dim3(256), 0, s, scratch, nch, gp, G, ldg, sym ? 1 : 0);
+      return check();
+    }
     const int gi = (int)cdiv(na, 16 * kGramNBMax), gj = (int)cdiv(nb, 16 * kGramNBMax);
     for (int I = 0; I < gi; ++I) {
       const int i0 = (int)((int64_t)na * I / gi), i1 = (int)((int64_t)na * (I + 1) / gi);

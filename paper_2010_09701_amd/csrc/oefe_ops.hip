@@ -2082,7 +2082,10 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
     if (nO > 0 && (!ovl || ov->first)) hipLaunchKernelGGL((small_gemm_kernel<T, CPLX>), gg, dim3(256), 0, s, kb, 0, op->N, nO);
     cell_stage();
     // node workgroup width: 16-column blocks, all real columns up to the cap, else near-equal
-    const int nbcap = std::max(1, std::min(kNodeNBMax, op->tune_cb > 0 ? op->tune_cb / 16 : kNodeNBMax));
+    // parts.  Built-in cap: 4 blocks in float64 (diamond meshes of 110 k and 885 k nodes: node
+    // stage 112 / 3650 us against 127 / 4470 us with 5), 5 in float32.
+    const int nbdef = sizeof(T) == 8 ? 4 : kNodeNBMax;
+    const int nbcap = std::max(1, std::min(kNodeNBMax, op->tune_cb > 0 ? op->tune_cb / 16 : nbdef));
     const int nb_all = (int)cdiv(max_ncr, 16);
     const int ncb = (int)cdiv(nb_all, nbcap);
     const int NB = (int)cdiv(nb_all, ncb);
