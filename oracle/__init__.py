@@ -23,6 +23,9 @@ chfsi        Lanczos bounds, scaled Chebyshev filter, Cholesky-Gram-Schmidt,
 adjoint      band energy and its gradients w.r.t. V and X (eqnrho, E_band).
 occupations  Fermi-Dirac occupations, Fermi level from the electron count, band
              energy and density from Ritz pairs (eqnfd, eqnne, eqnrho, E_band).
+poisson      smeared nuclear charges and the auxiliary electrostatic potential in
+             the OEFE basis (eqnsmeared, eqngr, eqnvg, eqnpoissonaux, eqnPhiOEFE,
+             eqnpoissX, eqnDiscLaplace, eqnDiscForceVec).
 
 Functions whose only check is agreement with the HIP path say "parity
 unpinned" in their docstring.
