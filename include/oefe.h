@@ -49,7 +49,7 @@ typedef enum {
   OEFE_ENOMEM = -2,       /* device allocation failed in oefe_op_create */
   OEFE_EDEVICE = -3,      /* HIP runtime error (message via oefe_last_error) */
   OEFE_ENOTSPD = -4,      /* Cholesky breakdown: Gram matrix not positive definite */
-  OEFE_ENOCONV = -5,      /* dense eigensolver did not converge */
+  OEFE_ENOCONV = -5,      /* dense eigensolver or Poisson CG did not converge */
   OEFE_EUNSUPPORTED = -6  /* precision / degree / operator kind not supported */
 } oefe_status;
 
@@ -306,6 +306,39 @@ int oefe_fermi_occupations(int32_t nk, const int32_t* nv, const double* wk, cons
  * prec, nv) bytes. */
 int oefe_density(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* weights, double* rho,
                  int32_t accumulate, void* work, oefe_stream stream);
+
+/* Operator of the discrete Poisson problem for the auxiliary electrostatic potential
+ * (Sec. II eqnpoissonaux; Sec. III.A eqnPhiOEFE, eqnpoissX, eqnDiscLaplace) on the mesh
+ * and atoms of desc: the FE functions plus one orthogonalized enrichment function per
+ * atom (eqnOrthoEnrichedPhiAux), whose atomic part is (V_H - Z v_g(r, rc)) h(r)
+ * (eqnPhiAuxAtomic, eqnEnrichedPhiAux, eqnnucsmear, eqnvg) with the cutoff h of
+ * desc (r0, r1), rc half the distance to the nearest other atom or periodic image, and
+ * V_H the Hartree potential of the model atom density Z alpha^3/(8 pi) exp(-alpha r),
+ * alpha = 2 Z^(1/3) (an atomic solver's radial Hartree potential stands there in the
+ * paper).  desc's enrichment list and sigma are not used.  The handle applies
+ * At = P^T A P, P = diag(m^-1/2, S), S = (A^oo)^-1/2, through ham_apply (F64) and
+ * solves with oefe_poisson_solve; dims (oefe_op_dims) count one enrichment function per
+ * atom.  Errors: EINVAL (no atoms, Z <= 0, kvec set, bad cutoff), EUNSUPPORTED (p),
+ * ENOMEM, EDEVICE. */
+int oefe_poisson_create(const oefe_system_desc* desc, oefe_op* out);
+
+/* Work bytes of oefe_poisson_solve (0 for other operators). */
+size_t oefe_poisson_work_size(oefe_op pop);
+
+/* phi with A phi = c (eqnpoissX): A_mn = 1/(4 pi) int grad N_m . grad N_n
+ * (eqnDiscLaplace), c_m = int (b + rho - background) N_m (eqnDiscForceVec) with b the
+ * smeared nuclear charge -sum_I Z_I g(|x - R_I|, rc_I) (eqnsmeared, eqngr, nearest
+ * image) and the background the quadrature mean of b + rho (so that the periodic
+ * problem is consistent).  rho: device float64 [n_cells * nq] (cell-major, as
+ * oefe_density writes it).  phi: device float64 [n_fe + n_atoms], the FE coefficients
+ * (GLL-mass-weighted mean zero) then the enrichment coefficients.  Conjugate gradients on
+ * At (the GLL mass and A^oo as preconditioner) from zero, stopping when the residual
+ * norm falls below tol times its starting value (tested every 8 iterations) or after
+ * max_iter iterations; info (host double[2]) = {iterations, relative residual}.  Queued
+ * on `stream`, with one host wait per 8 iterations.  Errors: EINVAL (bad arguments, not
+ * a Poisson operator), ENOCONV (tolerance not met: phi holds the last iterate), EDEVICE. */
+int oefe_poisson_solve(oefe_op pop, const double* rho, double* phi, double tol, int32_t max_iter, double* info,
+                       void* work, oefe_stream stream);
 
 /* Instrumentation.  While a kernel is selected, each of its launches inside
  * ham_apply / chebyshev_filter* is bracketed by HIP events on the stream it is

@@ -527,6 +527,7 @@ int upload_operator(oefe_op_s* op, std::string& err) {
       std::vector<double> hook = flatten(op->Hoo_kin, cplx);
       if ((rc = dput(&op->d.Hoo_kin, hook, err))) return rc;
       if ((rc = dput(&op->d.csr2tile, op->csr_to_tile, err))) return rc;
+      if (op->poisson && (rc = dput(&op->d.blk_cf0, boff, err))) return rc;
     }
     if ((rc = dput(&op->d.blk_fn0, fn0, err))) return rc;
     if ((rc = dput(&op->d.blk_nf, nf, err))) return rc;
@@ -554,6 +555,7 @@ int upload_operator(oefe_op_s* op, std::string& err) {
   }
   if ((rc = dput(&op->d.W, op->W, err))) return rc;
   if ((rc = dput(&op->d.V, op->V, err))) return rc;
+  if (op->poisson && (rc = dput(&op->d.bsmear, op->bsmear, err))) return rc;
   return upload_potential_parts(op, err);
 }
 
@@ -566,7 +568,7 @@ void free_device(oefe_op_s* op) {
   dfree(d.Sf); dfree(d.Hoof); dfree(d.cph_ptr); dfree(d.cph_blk); dfree(d.cph_off); dfree(d.phi);
   dfree(d.lambda); dfree(d.lambdaf); dfree(d.bf_mats);
   dfree(d.W); dfree(d.V); dfree(d.msq); dfree(d.hkin); dfree(d.Hoo_kin); dfree(d.row_blk); dfree(d.rpos);
-  dfree(d.rr_ptr); dfree(d.rr_ent); dfree(d.cf_cell); dfree(d.csr2tile); dfree(d.hp_ptr); dfree(d.hp_i);
+  dfree(d.bsmear); dfree(d.blk_cf0); dfree(d.rr_ptr); dfree(d.rr_ent); dfree(d.cf_cell); dfree(d.csr2tile); dfree(d.hp_ptr); dfree(d.hp_i);
   dfree(d.hp_j);
 }
 
@@ -1830,6 +1832,334 @@ int oefe_fermi_occupations(int32_t nk, const int32_t* nv, const double* wk, cons
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "oefe_fermi_occupations");
   return OEFE_OK;
+}
+
+}  // extern "C"
+
+// ---- The auxiliary-potential Poisson problem (eqnpoissonaux, eqnpoissX) on the device.
+// The operator of oefe_poisson_create applies At = P^T A P with P = diag(m^-1/2, S),
+// S = (A^oo)^-1/2 (the same kernels as Ht: no potential, the Laplacian 1/(4 pi) grad . grad,
+// the phi enrichment).  A phi = c becomes At y = P^T c, phi = P y, solved by conjugate gradients:
+// CG on At is CG on A preconditioned by the diagonal GLL mass on the FE rows and A^oo on the
+// enrichment rows.
+namespace {
+constexpr int kPoisPartials = 256;
+
+// per workgroup, in a fixed order: sum W (b + rho) and sum W over a contiguous range
+__global__ __launch_bounds__(256) void pois_charge_partial_kernel(const double* __restrict__ W,
+                                                                  const double* __restrict__ b,
+                                                                  const double* __restrict__ rho, int64_t n,
+                                                                  int64_t per, double* __restrict__ part) {
+  __shared__ double s0[256], s1[256];
+  const int t = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(n, i0 + per);
+  double a = 0.0, w = 0.0;
+  for (int64_t i = i0 + t; i < i1; i += 256) {
+    a += W[i] * (b[i] + rho[i]);
+    w += W[i];
+  }
+  s0[t] = a;
+  s1[t] = w;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s0[t] += s0[t + o];
+      s1[t] += s1[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * blockIdx.x] = s0[0];
+    part[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
+// sc[0] = (sum W (b + rho)) / (sum W): the uniform background removed from the charge
+__global__ void pois_mean_kernel(const double* __restrict__ part, int G, double* __restrict__ sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0, w = 0.0;
+  for (int g = 0; g < G; ++g) {
+    a += part[2 * g];
+    w += part[2 * g + 1];
+  }
+  sc[0] = a / w;
+}
+
+// f = b + rho - background (eqnDiscForceVec's charge, made neutral)
+__global__ void pois_neutral_kernel(const double* __restrict__ b, const double* __restrict__ rho,
+                                    const double* __restrict__ sc, double* __restrict__ f, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = b[i] + rho[i] - sc[0];
+}
+
+// right-hand side on the FE rows: yb[g] = m_g^-1/2 c_g, c_g = int f N_g = sum over the (up to 8)
+// cells of node g of sum_q W_q f_q B[q, a] (B the tensor-product values of the GLL basis at the
+// Gauss points), cells and points in a fixed order; z[g] = m_g^1/2 (the null vector of At)
+__global__ __launch_bounds__(256) void pois_rhs_fe_kernel(const double* __restrict__ f, const double* __restrict__ W,
+                                                          CellCoef<double> cf, const double* __restrict__ msq,
+                                                          int nc, int p, int n, int P1, int nq, int64_t N,
+                                                          double* __restrict__ yb, double* __restrict__ z) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int nn = n * n;
+  const int iz = (int)(g / nn), rem = (int)(g - (int64_t)iz * nn), iy = rem / n, ix = rem - iy * n;
+  const int id[3] = {ix, iy, iz};
+  int cc[3][2], aa[3][2], na[3];
+  for (int d = 0; d < 3; ++d) {
+    const int c = id[d] / p, a = id[d] - c * p;
+    na[d] = 1;
+    cc[d][0] = c;
+    aa[d][0] = a;
+    if (a == 0) {  // also the last local node of the previous cell (periodic)
+      na[d] = 2;
+      cc[d][1] = c == 0 ? nc - 1 : c - 1;
+      aa[d][1] = p;
+    }
+  }
+  double c = 0.0;
+  for (int kz = 0; kz < na[2]; ++kz)
+    for (int ky = 0; ky < na[1]; ++ky)
+      for (int kx = 0; kx < na[0]; ++kx) {
+        const int64_t e = cc[0][kx] + (int64_t)nc * (cc[1][ky] + (int64_t)nc * cc[2][kz]);
+        const int ax = aa[0][kx], ay = aa[1][ky], az = aa[2][kz];
+        const double* fe = f + e * nq;
+        const double* We = W + e * nq;
+        double se = 0.0;
+        for (int qz = 0; qz < P1; ++qz) {
+          double sy = 0.0;
+          for (int qy = 0; qy < P1; ++qy) {
+            double sx = 0.0;
+            for (int qx = 0; qx < P1; ++qx) {
+              const int q = qx + P1 * (qy + P1 * qz);
+              sx += cf.B1[qx][ax] * (We[q] * fe[q]);
+            }
+            sy += cf.B1[qy][ay] * sx;
+          }
+          se += cf.B1[qz][az] * sy;
+        }
+        c += se;
+      }
+  yb[g] = msq[g] * c;
+  z[g] = 1.0 / msq[g];
+}
+
+// enrichment rows of c: c_I = sum over the support cells of block I and their points of W f N^O_I
+// (one workgroup per block, one function per block, fixed order)
+__global__ __launch_bounds__(256) void pois_rhs_enr_kernel(const double* __restrict__ f, const double* __restrict__ W,
+                                                           const double* __restrict__ phi,
+                                                           const int32_t* __restrict__ cf_cell,
+                                                           const int64_t* __restrict__ blk_cf0, int nq,
+                                                           double* __restrict__ cO) {
+  __shared__ double red[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int64_t j0 = blk_cf0[b] * nq, j1 = blk_cf0[b + 1] * nq;
+  double a = 0.0;
+  for (int64_t j = j0 + t; j < j1; j += 256) {
+    const int64_t e = cf_cell[j / nq];
+    const int q = (int)(j % nq);
+    a += W[e * nq + q] * f[e * nq + q] * phi[j];
+  }
+  red[t] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t == 0) cO[b] = red[0];
+}
+
+// y[i] = sum_j S[i][j] x[j] (S symmetric, nO x nO), one thread per row
+__global__ void pois_small_mv_kernel(const double* __restrict__ S, const double* __restrict__ x, int nO,
+                                     double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nO) return;
+  double a = 0.0;
+  for (int j = 0; j < nO; ++j) a += S[(size_t)i * nO + j] * x[j];
+  y[i] = a;
+}
+
+// v[0..N) -= (num / den) z  (the component along the null vector z; num, den device scalars)
+__global__ void pois_project_kernel(double* __restrict__ v, const double* __restrict__ z, const double* __restrict__ num,
+                                    const double* __restrict__ den, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) v[i] -= (num[0] / den[0]) * z[i];
+}
+
+// x = 0, r = p = v
+__global__ void pois_start_kernel(const double* __restrict__ v, double* __restrict__ x, double* __restrict__ r,
+                                  double* __restrict__ pv, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] = 0.0;
+  r[i] = v[i];
+  pv[i] = v[i];
+}
+
+// x += alpha p, r -= alpha q with alpha = rr / pq (0 when pq <= 0)
+__global__ void pois_step_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ pv,
+                                 const double* __restrict__ q, const double* __restrict__ rr,
+                                 const double* __restrict__ pq, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double al = pq[0] > 0.0 ? rr[0] / pq[0] : 0.0;
+  x[i] += al * pv[i];
+  r[i] -= al * q[i];
+}
+
+// p = r + beta p with beta = rr_new / rr
+__global__ void pois_dir_kernel(double* __restrict__ pv, const double* __restrict__ r,
+                                const double* __restrict__ rr_new, const double* __restrict__ rr, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double be = rr[0] > 0.0 ? rr_new[0] / rr[0] : 0.0;
+  pv[i] = r[i] + be * pv[i];
+}
+
+// phi = P y with the FE part's GLL-mass-weighted mean removed: phi_g = m_g^-1/2 y_g - (z . y) / (z . z)
+__global__ void pois_finish_fe_kernel(const double* __restrict__ y, const double* __restrict__ msq,
+                                      const double* __restrict__ zy, const double* __restrict__ zz,
+                                      double* __restrict__ phi, int64_t N) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < N) phi[g] = msq[g] * y[g] - zy[0] / zz[0];
+}
+
+struct PoisLayout {
+  StepWork step;
+  double *x, *r, *p, *q, *v, *z, *f, *cO, *dscr, *sc, *part;
+  size_t total;
+};
+
+PoisLayout pois_layout(const oefe_op_s* op, void* work) {
+  PoisLayout L{};
+  char* p = (char*)work;
+  const size_t sb = al256(step_work_bytes(op, 8, false, 1, nullptr));
+  if (work) L.step = carve_step_work(op, 8, false, 1, work);
+  p += sb;
+  const size_t vb = al256((size_t)op->n_tot * sizeof(double));
+  auto take = [&](size_t bytes) {
+    double* r = (double*)p;
+    p += al256(bytes);
+    return r;
+  };
+  L.x = take(vb);
+  L.r = take(vb);
+  L.p = take(vb);
+  L.q = take(vb);
+  L.v = take(vb);
+  L.z = take((size_t)op->N * sizeof(double));
+  L.f = take((size_t)op->n_cells * op->nq * sizeof(double));
+  L.cO = take((size_t)std::max(op->n_enr, 1) * sizeof(double));
+  L.dscr = take(256 * sizeof(double));
+  L.sc = take(16 * sizeof(double));
+  L.part = take(2 * kPoisPartials * sizeof(double));
+  L.total = (size_t)(p - (char*)work);
+  return L;
+}
+}  // namespace
+
+extern "C" {
+
+int oefe_poisson_create(const oefe_system_desc* desc, oefe_op* out) {
+  if (!desc || !out) return fail(OEFE_EINVAL, "null argument");
+  *out = nullptr;
+  if (desc->n_atoms < 1 || !desc->pos || !desc->Z) return fail(OEFE_EINVAL, "the Poisson operator needs atoms");
+  if (desc->kvec) return fail(OEFE_EINVAL, "the Poisson operator is real (no Bloch wavevector)");
+  for (int I = 0; I < desc->n_atoms; ++I)
+    if (!(desc->Z[I] > 0)) return fail(OEFE_EINVAL, "atomic numbers must be positive");
+  oefe_op_s* op = new (std::nothrow) oefe_op_s();
+  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  op->poisson = true;
+  std::string err;
+  int rc = build_operator(op, desc, err);
+  if (rc == OEFE_OK && hipGetDevice(&op->device) != hipSuccess) {
+    rc = OEFE_EDEVICE;
+    err = "no HIP device";
+  }
+  if (rc == OEFE_OK) rc = upload_operator(op, err);
+  if (rc == OEFE_OK && !scratch_address(err)) rc = OEFE_EDEVICE;
+  if (rc != OEFE_OK) {
+    free_device(op);
+    delete op;
+    return fail(rc, err);
+  }
+  *out = op;
+  return OEFE_OK;
+}
+
+size_t oefe_poisson_work_size(oefe_op pop) {
+  if (!pop || !pop->poisson) return 0;
+  return pois_layout(pop, nullptr).total + 256;
+}
+
+int oefe_poisson_solve(oefe_op pop, const double* rho, double* phi, double tol, int32_t max_iter, double* info,
+                       void* work, oefe_stream stream) {
+  if (!pop || !rho || !phi || !work || !info || max_iter < 1 || !(tol > 0.0))
+    return fail(OEFE_EINVAL, "bad arguments");
+  if (!pop->poisson) return fail(OEFE_EINVAL, "not an operator of oefe_poisson_create");
+  const oefe_op_s* op = pop;
+  hipStream_t s = (hipStream_t)stream;
+  PoisLayout L = pois_layout(op, work);
+  const int64_t N = op->N, n = op->n_tot, nqt = op->n_cells * op->nq;
+  const int nO = op->n_enr;
+  auto blocks = [](int64_t m) { return dim3((unsigned)((m + 255) / 256)); };
+  // charge: f = b + rho - background
+  const int64_t per = (nqt + kPoisPartials - 1) / kPoisPartials;
+  hipLaunchKernelGGL(pois_charge_partial_kernel, dim3(kPoisPartials), dim3(256), 0, s, op->d.W, op->d.bsmear, rho, nqt,
+                     per, L.part);
+  hipLaunchKernelGGL(pois_mean_kernel, dim3(1), dim3(64), 0, s, L.part, kPoisPartials, L.sc + 8);
+  hipLaunchKernelGGL(pois_neutral_kernel, blocks(nqt), dim3(256), 0, s, op->d.bsmear, rho, L.sc + 8, L.f, nqt);
+  // v = P^T c, projected off the null vector z = (m^1/2, 0)
+  hipLaunchKernelGGL(pois_rhs_fe_kernel, blocks(N), dim3(256), 0, s, L.f, op->d.W, op->cd, op->d.msq, op->nc, op->p,
+                     op->n, op->P1, op->nq, N, L.v, L.z);
+  hipLaunchKernelGGL(pois_rhs_enr_kernel, dim3((unsigned)nO), dim3(256), 0, s, L.f, op->d.W, op->d.phi,
+                     op->d.cf_cell, op->d.blk_cf0, op->nq, L.cO);
+  hipLaunchKernelGGL(pois_small_mv_kernel, blocks(nO), dim3(256), 0, s, op->d.S, L.cO, nO, L.v + N);
+  int rc = dot_columns<double>(false, L.z, 1, L.v, 1, N, 1, nullptr, L.sc + 4, L.dscr, s);  // z . v
+  if (!rc) rc = dot_columns<double>(false, L.z, 1, L.z, 1, N, 1, nullptr, L.sc + 5, L.dscr, s);  // z . z
+  if (rc) return fail(rc, "oefe_poisson_solve: kernel launch failed");
+  hipLaunchKernelGGL(pois_project_kernel, blocks(N), dim3(256), 0, s, L.v, L.z, L.sc + 4, L.sc + 5, N);
+  // conjugate gradients on At y = v from y = 0; rr of iteration k in sc[k & 1], pq in sc[2],
+  // the starting residual in sc[3]
+  hipLaunchKernelGGL(pois_start_kernel, blocks(n), dim3(256), 0, s, L.v, L.x, L.r, L.p, n);
+  rc = dot_columns<double>(false, L.r, 1, L.r, 1, n, 1, nullptr, L.sc + 0, L.dscr, s);
+  if (!rc) rc = dot_columns<double>(false, L.r, 1, L.r, 1, n, 1, nullptr, L.sc + 3, L.dscr, s);
+  if (rc) return fail(rc, "oefe_poisson_solve: kernel launch failed");
+  thread_local double* hbuf = nullptr;
+  if (!hbuf && hipHostMalloc((void**)&hbuf, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    hbuf = nullptr;
+    return fail(OEFE_EDEVICE, "oefe_poisson_solve: pinned host buffer");
+  }
+  int it = 0;
+  double rel = 1.0;
+  bool done = false;
+  while (!done && it < max_iter) {
+    const int k = it & 1;
+    rc = apply_step<double>(op, false, L.p, 1, nullptr, L.q, 1, 1, 1.0, 0.0, 0.0, L.step, s);
+    if (!rc) rc = dot_columns<double>(false, L.p, 1, L.q, 1, n, 1, nullptr, L.sc + 2, L.dscr, s);
+    if (rc) return fail(rc, "oefe_poisson_solve: kernel launch failed");
+    hipLaunchKernelGGL(pois_step_kernel, blocks(n), dim3(256), 0, s, L.x, L.r, L.p, L.q, L.sc + k, L.sc + 2, n);
+    rc = dot_columns<double>(false, L.r, 1, L.r, 1, n, 1, nullptr, L.sc + (k ^ 1), L.dscr, s);
+    if (rc) return fail(rc, "oefe_poisson_solve: kernel launch failed");
+    hipLaunchKernelGGL(pois_dir_kernel, blocks(n), dim3(256), 0, s, L.p, L.r, L.sc + (k ^ 1), L.sc + k, n);
+    ++it;
+    if (it % 8 == 0 || it == max_iter) {  // convergence test: one host read every 8 iterations
+      hipError_t e = hipMemcpyAsync(hbuf, L.sc, 4 * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(e, "oefe_poisson_solve");
+      rel = hbuf[3] > 0.0 ? std::sqrt(std::max(hbuf[it & 1], 0.0) / hbuf[3]) : 0.0;
+      done = rel <= tol;
+    }
+  }
+  // phi = P y (FE part with zero mass-weighted mean)
+  rc = dot_columns<double>(false, L.z, 1, L.x, 1, N, 1, nullptr, L.sc + 6, L.dscr, s);
+  if (rc) return fail(rc, "oefe_poisson_solve: kernel launch failed");
+  hipLaunchKernelGGL(pois_finish_fe_kernel, blocks(N), dim3(256), 0, s, L.x, op->d.msq, L.sc + 6, L.sc + 5, phi, N);
+  hipLaunchKernelGGL(pois_small_mv_kernel, blocks(nO), dim3(256), 0, s, op->d.S, L.x + N, nO, phi + N);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "oefe_poisson_solve");
+  info[0] = it;
+  info[1] = rel;
+  return done ? OEFE_OK : fail(OEFE_ENOCONV, "oefe_poisson_solve: residual above the tolerance after max_iter");
 }
 
 int oefe_density(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* weights, double* rho,

@@ -172,6 +172,9 @@ struct DeviceArrays {
   int64_t* hp_ptr = nullptr;    // atom-block pair (bi nb + bj) -> common support cells [nb^2 + 1]
   int32_t* hp_i = nullptr;      // flattened support cell of bi for each common cell
   int32_t* hp_j = nullptr;      // flattened support cell of bj
+  // auxiliary-potential Poisson operator (oefe_poisson_create)
+  double* bsmear = nullptr;     // smeared nuclear charge at the quadrature points [n_cells * nq]
+  int64_t* blk_cf0 = nullptr;   // first flattened support cell of each block [nblk + 1]
 };
 
 struct AtomBlock {
@@ -189,6 +192,10 @@ struct AtomBlock {
 struct oefe_op_s {
   bool diagonal = false;
   bool cplx = false;
+  // operator of the auxiliary-potential Poisson problem: one phi-enrichment function per
+  // atom, no potential, the Laplacian 1/(4 pi) int grad . grad in place of the kinetic
+  // 1/2 int grad . grad, and S = (A^oo)^-1/2 (the enrichment block's Jacobi factor)
+  bool poisson = false;
   int device = 0;
   // geometry
   double L = 0, h = 0;
@@ -208,6 +215,7 @@ struct oefe_op_s {
   std::vector<oefe::AtomBlock> blocks;
   std::vector<oefe::cplx> Moo, Hoo_kin, Hoo, S;
   std::vector<double> Moo_eigs;
+  std::vector<double> bsmear, rc_smear;  // Poisson operator: smeared charge, smearing radii
   int FMAX = 1;
   int64_t n_hrows = 0;  // total rows over blocks
   int64_t n_chunks = 0;

@@ -361,10 +361,11 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
   const int64_t e = (int64_t)cgrp * 4 + wid;
   const int j = chunk * CWc + g;
   const bool valid = (e < n_cells) && (j < ncr);
-  const int ee = valid ? (int)e : 0;  // n_cells < 2^31
-  const int cx = ee % nc, cy = (ee / nc) % nc, cz = ee / (nc * nc);
-  // W V of the wave's cell (e is wave-uniform, ee is not: lanes past the block use cell 0):
-  // loaded now, parked in LDS after the first passes, read in step 5
+  // the wave's cell (uniform: scalar arithmetic); a wave past the last cell addresses the last
+  // cell's nodes and stores nothing
+  const int eu = (int)(e < n_cells ? e : n_cells - 1);  // n_cells < 2^31
+  const int cx = eu % nc, cy = (eu / nc) % nc, cz = eu / (nc * nc);
+  // W V of the wave's cell: loaded now, parked in LDS after the first passes, read in step 5
   constexpr int NQ3 = NP * P1;
   const T* __restrict__ wvg = WV + (e < n_cells ? e : n_cells - 1) * NQ3;
   const T wv0 = wvg[min(lane, NQ3 - 1)], wv1 = wvg[min(lane + 64, NQ3 - 1)];
@@ -1023,6 +1024,17 @@ __device__ __forceinline__ int64_t row_of(int64_t i, int nel, double rnel) {
   return g;
 }
 
+// floor(a / d) for 0 <= a < 2^31, 1 <= d, from rd = 1 / d in float64 (the product is within one
+// of the quotient; one correction step), instead of an integer division sequence
+__device__ __forceinline__ int div_rcp(int a, int d, double rd) {
+  int q = (int)((double)a * rd);
+  const int r = a - q * d;
+  q += r < 0 ? -1 : (r >= d ? 1 : 0);
+  return q;
+}
+// a / p for the supported element degrees p = 2, 3, 4 (a >= 0): constant divisors
+__device__ __forceinline__ int div_p(int a, int p) { return p == 4 ? a >> 2 : (p == 2 ? a >> 1 : a / 3); }
+
 template <typename T, bool CPLX>
 __device__ __forceinline__ void assemble_one(const KP<T>& P, int64_t i, int nel, double rnel, int nc, int p, int n,
                                              int P1, const CellCoef<T>& cf, int base_in_out);
@@ -1044,8 +1056,10 @@ __device__ __forceinline__ void assemble_one(const KP<T>& P, int64_t i, int nel,
   const int64_t g = row_of(i, nel, rnel);
   const int j = (int)(i - g * nel);
   const int gi = (int)g;
-  const int iz = gi / (n * n), rem = gi - iz * n * n, iy = rem / n, ix = rem - iy * n;
-  const int qx = ix / p, rx = ix - qx * p, qy = iy / p, ry = iy - qy * p, qz = iz / p, rz = iz - qz * p;
+  const int nn = n * n;
+  const int iz = div_rcp(gi, nn, 1.0 / nn), rem = gi - iz * nn, iy = div_rcp(rem, n, 1.0 / n), ix = rem - iy * n;
+  const int qx = div_p(ix, p), rx = ix - qx * p, qy = div_p(iy, p), ry = iy - qy * p, qz = div_p(iz, p),
+            rz = iz - qz * p;
   const int S = nc * P1;
   const int bx = qx * P1 + (rx ? rx + 1 : 0), by = qy * P1 + (ry ? ry + 1 : 0), bz = qz * P1 + (rz ? rz + 1 : 0);
   const T msc = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
@@ -1157,7 +1171,7 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   const int t = L / ncb;
   const int cb0 = (L - t * ncb) * CBW;
   if (cb0 >= ncr) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const int f0 = tile_fptr ? tile_fptr[t] : 0, FP = tile_fptr ? tile_fptr[t + 1] - f0 : 0;
   const int HS = node_hs(FP, hs_cap);
@@ -1199,13 +1213,39 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   T msc[4];
   int tx0, ty0, tz0;  // the tile's first node (uniform)
   tile_origin(t, n, tm, tx0, ty0, tz0);
+  // consecutive rows (mode 0): the node of the tile's first row (uniform), the others by stepping
+  // along x from it, without a division per row
+  int sx0 = 0, sy0 = 0, sz0 = 0;
+  if (tm == 0) {
+    sz0 = tx0 / (n * n);
+    const int rem = tx0 - sz0 * n * n;
+    sy0 = rem / n;
+    sx0 = rem - sy0 * n;
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    int ix, iy, iz;
-    const int gv = tile_row_coords(tx0, ty0, tz0, w * 16 + M::row(lane, v), n, tm, ix, iy, iz);
+    const int r = w * 16 + M::row(lane, v);
+    int ix, iy, iz, gv;
+    if (tm == 0) {
+      gv = tx0 + r;
+      ix = sx0 + r;
+      iy = sy0;
+      iz = sz0;
+      while (ix >= n) {
+        ix -= n;
+        if (++iy == n) {
+          iy = 0;
+          ++iz;
+        }
+      }
+      if (gv >= N) gv = -1, ix = iy = iz = 0;
+    } else {
+      gv = tile_row_coords(tx0, ty0, tz0, r, n, tm, ix, iy, iz);
+    }
     ok[v] = gv >= 0;
     gc[v] = ok[v] ? gv : 0;
-    const int qx = ix / p, rx = ix - qx * p, qy = iy / p, ry = iy - qy * p, qz = iz / p, rz = iz - qz * p;
+    const int qx = div_p(ix, p), rx = ix - qx * p, qy = div_p(iy, p), ry = iy - qy * p, qz = div_p(iz, p),
+              rz = iz - qz * p;
     bx[v] = qx * P1 + (rx ? rx + 1 : 0);
     by[v] = qy * P1 + (ry ? ry + 1 : 0);
     bz[v] = qz * P1 + (rz ? rz + 1 : 0);

@@ -174,6 +174,53 @@ void atomic_fn(const double d[3], int pw, double zeta, int axis, double r0, doub
   }
 }
 
+// Unit smeared charge g(r, rc) (eqngr) and its potential v_g(r, rc) with dv_g/dr (eqnvg).
+double smeared_g(double r, double rc) {
+  if (r > rc) return 0.0;
+  const double t = r - rc;
+  return -21.0 * t * t * t * (6.0 * r * r + 3.0 * r * rc + rc * rc) / (5.0 * kPi * std::pow(rc, 8));
+}
+void smeared_v(double r, double rc, double& v, double& dv) {
+  if (r > rc) {
+    v = 1.0 / r;
+    dv = -1.0 / (r * r);
+    return;
+  }
+  const double r2 = r * r, r4 = r2 * r2, c2 = rc * rc, c5 = c2 * c2 * rc, c8 = std::pow(rc, 8);
+  v = (9.0 * r4 * r2 * r - 30.0 * r4 * r2 * rc + 28.0 * r4 * r * c2 - 14.0 * r2 * c5 + 12.0 * c5 * c2) / (5.0 * c8);
+  dv = (63.0 * r4 * r2 - 180.0 * r4 * r * rc + 140.0 * r4 * c2 - 28.0 * r * c5) / (5.0 * c8);
+}
+
+// Hartree potential of the model atom density Z alpha^3 / (8 pi) exp(-alpha r) (the isolated-atom
+// Hartree potential of the auxiliary-potential enrichment, which an atomic solver would supply):
+// V = Z (1 - (1 + alpha r / 2) exp(-alpha r)) / r, with its series below alpha r = 1e-3.
+void model_hartree(double r, double Z, double alpha, double& v, double& dv) {
+  const double x = alpha * r;
+  if (x < 1e-3) {
+    v = Z * alpha * (0.5 - x * x / 12.0 + x * x * x / 24.0);
+    dv = Z * alpha * alpha * (-x / 6.0 + x * x / 8.0);
+    return;
+  }
+  const double e = std::exp(-x), u = 1.0 - (1.0 + 0.5 * x) * e;
+  v = Z * alpha * u / x;
+  dv = Z * alpha * alpha * ((0.5 + 0.5 * x) * e * x - u) / (x * x);
+}
+
+// Atomic part of the auxiliary-potential enrichment (eqnPhiAuxAtomic, eqnEnrichedPhiAux):
+// (V_H(r) - Z v_g(r, rc)) h(r) and its gradient at displacement d.
+void phi_aux_fn(const double d[3], double Z, double alpha, double rc, double r0, double r1, double& val,
+                double grad[3]) {
+  const double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double vh, dvh, vg, dvg, h, dh;
+  model_hartree(r, Z, alpha, vh, dvh);
+  smeared_v(r, rc, vg, dvg);
+  cutoff(r, r0, r1, h, dh);
+  const double f = vh - Z * vg, fp = dvh - Z * dvg;
+  val = f * h;
+  const double radial = fp * h + f * dh;
+  for (int k = 0; k < 3; ++k) grad[k] = r > 0.0 ? radial * d[k] / r : 0.0;
+}
+
 // Tensor-product transforms on one cell (P1 = q = p + 1 points per direction).
 // fwd: out[qz][qy][qx] = sum Mz[qz][az] My[qy][ay] Mx[qx][ax] in[az][ay][ax]
 template <typename S>
@@ -338,9 +385,20 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
   op->h = op->L / op->nc;
   op->N = (int64_t)op->n * op->n * op->n;
   op->n_cells = (int64_t)op->nc * op->nc * op->nc;
-  op->n_enr = desc->n_enr;
+  const bool pois = op->poisson;
+  op->n_enr = pois ? desc->n_atoms : desc->n_enr;
   op->n_tot = op->N + op->n_enr;
   op->cplx = desc->kvec != nullptr;
+  if (pois && (op->cplx || desc->n_atoms < 1)) {
+    err = "the auxiliary-potential operator needs atoms and no Bloch wavevector";
+    return OEFE_EINVAL;
+  }
+  if (pois && !(desc->r1 > desc->r0 && desc->r0 > 0 && desc->r1 < 0.5 * desc->L)) {
+    err = "need 0 < r0 < r1 < L/2";
+    return OEFE_EINVAL;
+  }
+  // Laplacian scale: 1/2 for the Kohn-Sham kinetic term, 1/(4 pi) for the Poisson problem
+  const double kin = pois ? 1.0 / (4.0 * kPi) : 0.5;
   if (op->cplx) {
     for (int d = 0; d < 3; ++d) {
       op->kvec[d] = desc->kvec[d];
@@ -387,7 +445,7 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
       op->cd.BtL[i][j] = s;
     }
   }
-  op->cd.kappa = h / 4.0;
+  op->cd.kappa = kin * h / 2.0;  // kin (2/h)^2 (h/2)^3
   op->cd.mscale = std::pow(h / 2.0, -1.5);
   {
     auto& f = op->cf;
@@ -428,7 +486,7 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
       double x[3];
       geo.quad_point(e, q, x);
       double v = 0.0;
-      for (int I = 0; I < desc->n_atoms; ++I) {
+      for (int I = 0; I < (pois ? 0 : desc->n_atoms); ++I) {
         double d2 = 0;
         for (int k = 0; k < 3; ++k) {
           double dd = x[k] - desc->pos[3 * I + k];
@@ -439,9 +497,61 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
       }
       op->V[e * nq + q] = v;
     }
-  // ---- enrichment blocks (one per atom with functions)
+  // ---- Poisson operator: smearing radii (half the distance to the nearest other atom or
+  // periodic image, the largest radii without overlap) and the smeared nuclear charge
+  // b = -sum_I Z_I g(|x - R_I|, rc_I) at the quadrature points (eqnsmeared, nearest image)
+  std::vector<double> alpha_m;
+  if (pois) {
+    const int na = desc->n_atoms;
+    op->rc_smear.assign(na, 0.0);
+    alpha_m.assign(na, 0.0);
+    for (int I = 0; I < na; ++I) {
+      double best = 1e300;
+      for (int J = 0; J < na; ++J)
+        for (int sz = -1; sz <= 1; ++sz)
+          for (int sy = -1; sy <= 1; ++sy)
+            for (int sx = -1; sx <= 1; ++sx) {
+              if (J == I && sx == 0 && sy == 0 && sz == 0) continue;
+              const int sh[3] = {sx, sy, sz};
+              double d2 = 0;
+              for (int k = 0; k < 3; ++k) {
+                const double dd = desc->pos[3 * J + k] + op->L * sh[k] - desc->pos[3 * I + k];
+                d2 += dd * dd;
+              }
+              best = std::min(best, std::sqrt(d2));
+            }
+      op->rc_smear[I] = 0.5 * best;
+      alpha_m[I] = 2.0 * std::cbrt(desc->Z[I]);
+    }
+    op->bsmear.assign(op->n_cells * nq, 0.0);
+    for (int64_t e = 0; e < op->n_cells; ++e)
+      for (int q = 0; q < nq; ++q) {
+        double x[3];
+        geo.quad_point(e, q, x);
+        double b = 0.0;
+        for (int I = 0; I < na; ++I) {
+          double d2 = 0;
+          for (int k = 0; k < 3; ++k) {
+            double dd = x[k] - desc->pos[3 * I + k];
+            dd -= op->L * std::nearbyint(dd / op->L);
+            d2 += dd * dd;
+          }
+          b -= desc->Z[I] * smeared_g(std::sqrt(d2), op->rc_smear[I]);
+        }
+        op->bsmear[e * nq + q] = b;
+      }
+  }
+  // ---- enrichment blocks (one per atom with functions; the Poisson operator: one per atom)
   op->blocks.clear();
-  if (op->n_enr > 0) {
+  if (pois) {
+    for (int I = 0; I < desc->n_atoms; ++I) {
+      AtomBlock b;
+      b.atom = I;
+      b.fn0 = I;
+      b.nf = 1;
+      op->blocks.push_back(std::move(b));
+    }
+  } else if (op->n_enr > 0) {
     for (int nu = 0; nu < op->n_enr; ++nu) {
       int I = desc->enr_atom[nu];
       if (I < 0 || I >= desc->n_atoms) { err = "enrichment atom index out of range"; return OEFE_EINVAL; }
@@ -520,7 +630,10 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
         for (int f = 0; f < nf; ++f) {
           int fn = b.fn0 + f;
           double val, gr[3];
-          atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
+          if (pois)
+            phi_aux_fn(d, desc->Z[b.atom], alpha_m[b.atom], op->rc_smear[b.atom], desc->r0, desc->r1, val, gr);
+          else
+            atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
           NA[(ci * nq + q) * nf + f] = ph * val;
           for (int k = 0; k < 3; ++k) gNA[((ci * nq + q) * nf + f) * 3 + k] = ph * gr[k];
         }
@@ -579,7 +692,7 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
     b.rows.clear();
     for (int64_t g = 0; g < op->N; ++g)
       if (touched[g]) b.rows.push_back((int32_t)g);
-    // kinetic part of H^co: sum_q W 1/2 (2/h) G_d[q,a] dPhi_d
+    // kinetic part of H^co: sum_q W kin (2/h) G_d[q,a] dPhi_d
     dacc.assign((size_t)op->N * nf, cplx(0, 0));
     for (size_t ci = 0; ci < ncb; ++ci) {
       int64_t e = b.cells[ci];
@@ -587,7 +700,7 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
         std::vector<cplx> acc(op->nd, cplx(0, 0));
         for (int dd = 0; dd < 3; ++dd) {
           for (int q = 0; q < nq; ++q)
-            tin[q] = 0.5 * s2h * op->W[e * nq + q] * b.gphi[((ci * nq + q) * nf + f) * 3 + dd];
+            tin[q] = kin * s2h * op->W[e * nq + q] * b.gphi[((ci * nq + q) * nf + f) * 3 + dd];
           const double* Mx = dd == 0 ? Dm : Bm;
           const double* My = dd == 1 ? Dm : Bm;
           const double* Mz = dd == 2 ? Dm : Bm;
@@ -628,7 +741,7 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
               size_t ix = (size_t)(bi.fn0 + f) * nO + (bj.fn0 + g2);
               op->Moo[ix] += Wq * a * bb;
               op->Hoo_kin[ix] +=
-                  0.5 * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
+                  kin * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
             }
           }
         }
@@ -636,7 +749,9 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
         ++j;
       }
     }
-  // ---- S = (M^oo)^-1/2
+  // ---- S = (M^oo)^-1/2; for the Poisson operator the block's own metric is A^oo, so that
+  // S A^oo S = I (the enrichment rows' Jacobi factor of the preconditioned Laplacian)
+  if (pois) op->Moo = op->Hoo_kin;
   if (nO > 0) {
     std::vector<cplx> A(op->Moo), U;
     for (int i = 0; i < nO; ++i)

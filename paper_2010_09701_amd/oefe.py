@@ -81,6 +81,9 @@ def _load():
         "band_energy_grad": ([vp, i32, vp, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "oefe_fermi_occupations": ([i32, vp, vp, vp, dbl, dbl, vp, vp, vp, vp], i32),
         "oefe_density": ([vp, i32, vp, i64, i32, vp, vp, i32, vp, vp], i32),
+        "oefe_poisson_create": ([vp, ctypes.POINTER(vp)], i32),
+        "oefe_poisson_work_size": ([vp], ctypes.c_size_t),
+        "oefe_poisson_solve": ([vp, vp, vp, dbl, i32, vp, vp, vp], i32),
         "oefe_kernel_timer": ([vp, i32], i32),
         "oefe_kernel_timer_read": ([vp, vp, vp], i32),
         "oefe_copy_rate": ([vp, vp, ctypes.c_size_t, i32, vp, vp], i32),
@@ -102,7 +105,8 @@ EXPORTED = [
     "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
     "lanczos_bounds", "cholgs", "cholgs_async", "cholgs_noalloc", "rayleigh_ritz", "oefe_set_eig_sweep_limit", "band_energy_grad",
-    "oefe_fermi_occupations", "oefe_density", "oefe_kernel_timer",
+    "oefe_fermi_occupations", "oefe_density", "oefe_poisson_create", "oefe_poisson_work_size", "oefe_poisson_solve",
+    "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_copy_rate", "oefe_strerror", "oefe_last_error",
 ]
 
@@ -145,8 +149,11 @@ def _block(X: torch.Tensor, n_tot: int) -> Tuple[int, int]:
 class Operator:
     """Device-resident OEFE operator (or a diagonal test operator)."""
 
-    def __init__(self, system: Optional[workloads.System] = None, _handle=None):
+    def __init__(self, system: Optional[workloads.System] = None, _handle=None, poisson: bool = False):
+        """poisson: the operator of the auxiliary-potential Poisson problem on the system's mesh and
+        atoms (oefe_poisson_create) instead of the Kohn-Sham operator."""
         self._h = ctypes.c_void_p(0)
+        self.is_poisson = poisson
         if _handle is not None:
             self._h = _handle
         else:
@@ -164,7 +171,10 @@ class Operator:
             if not torch.cuda.is_available():
                 raise RuntimeError("no HIP device")
             torch.cuda.current_device()
-            _check(_lib.oefe_op_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create")
+            if poisson:
+                _check(_lib.oefe_poisson_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_poisson_create")
+            else:
+                _check(_lib.oefe_op_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create")
         dims = (ctypes.c_int64 * 11)()
         _check(_lib.oefe_op_dims(self._h, dims), "oefe_op_dims")
         (self.n_fe, self.n_enr, self.n_tot, self.n_cells, self.nq, self.nc, self.p, cx, self.tile_slots,
@@ -549,3 +559,23 @@ def density(op: Operator, X: torch.Tensor, weights: torch.Tensor, rho: Optional[
     _check(_lib.oefe_density(op.handle, prec, _ptr(X), ld, nv, _ptr(weights), _ptr(rho), 1 if accumulate else 0,
                              _ptr(w), _stream()), "oefe_density")
     return rho
+
+
+def poisson_solve(pop: Operator, rho: torch.Tensor, tol: float = 1e-10, max_iter: int = 2000):
+    """phi_aux coefficients (device float64 [n_tot]: FE part with zero mass-weighted mean, then one
+    per atom) for the electron density rho at the quadrature points ([n_cells, nq] float64, device)
+    and the smeared nuclear charges; returns (phi, iterations, relative residual)."""
+    if not pop.is_poisson:
+        raise ValueError("not a Poisson operator (Operator(system, poisson=True))")
+    if not rho.is_cuda or rho.dtype != torch.float64 or rho.numel() != pop.n_cells * pop.nq:
+        raise ValueError("rho: device float64 [n_cells, nq]")
+    rho = rho.contiguous()
+    phi = torch.empty(pop.n_tot, dtype=torch.float64, device=rho.device)
+    w = pop._work.get("poisson")
+    if w is None:
+        w = torch.empty(int(_lib.oefe_poisson_work_size(pop.handle)), dtype=torch.uint8, device=rho.device)
+        pop._work["poisson"] = w
+    info = (ctypes.c_double * 2)()
+    _check(_lib.oefe_poisson_solve(pop.handle, _ptr(rho), _ptr(phi), float(tol), int(max_iter), info, _ptr(w),
+                                   _stream()), "oefe_poisson_solve")
+    return phi, int(info[0]), float(info[1])

@@ -9,6 +9,7 @@ library.  The paper prints no values that apply to these synthetic operators.
     python tests/golden/make_golden.py kpoints      (about 5 min)
     python tests/golden/make_golden.py kpoint_passes   (about 20 min)
     python tests/golden/make_golden.py diamond64_pass1 (about 40 min, ~20 GB of host memory)
+    python tests/golden/make_golden.py poisson_diamond8 (about 2 min)
 """
 import os
 import sys
@@ -161,8 +162,19 @@ def diamond64_pass1():
                         filt1_rows=filt1_rows, filt1_colnorm=filt1_colnorm, theta1=th)
 
 
+def poisson_diamond8():
+    """The auxiliary potential of diamond8 for the model atomic densities (oracle/poisson.py)."""
+    from oracle import poisson as po
+    t = time.time()
+    P = po.PoissonOEFE(wl.diamond8())
+    rho = P.model_electron_density()
+    phi = P.solve(P.neutral_charge(rho), rtol=1e-13)
+    print("poisson diamond8", P.n_tot, time.time() - t, flush=True)
+    np.savez_compressed(os.path.join(HERE, "poisson_diamond8_oracle.npz"), rho=rho, phi=phi)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["diamond8"]
     for w in which:
         {"diamond8": diamond8, "diamond64": diamond64, "kpoints": kpoints, "kpoint_passes": kpoint_passes,
-         "diamond64_pass1": diamond64_pass1}[w]()
+         "diamond64_pass1": diamond64_pass1, "poisson_diamond8": poisson_diamond8}[w]()

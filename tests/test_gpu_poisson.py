@@ -1,0 +1,106 @@
+"""The auxiliary-potential Poisson problem on the GPU (oefe_poisson_create, oefe_poisson_solve)
+against the oracle (oracle/poisson.py).
+
+* The operator: ham_apply on the Poisson handle applies At = P^T A P, P = diag(m^-1/2, S),
+  S = (A^oo)^-1/2; compared column by column with the oracle's A to 1e-10 relative (float64,
+  different summation orders).
+* The solve: phi (FE part with zero GLL-mass-weighted mean, then one coefficient per atom) against
+  the oracle's solution of the same discrete system.  CG stops at a relative residual of 1e-12 in
+  the preconditioned system; with condition numbers below ~1e4 here the coefficients agree to 1e-8
+  of their largest magnitude, the bound used.
+* diamond8 (12^3 cells p = 4, 8 atoms): the oracle's solution stored by tests/golden/make_golden.py.
+* Errors: a Kohn-Sham operator is refused; a tolerance not met reports ENOCONV.
+"""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+from oracle import poisson as po
+from paper_2010_09701_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2010_09701_amd import oefe
+    return oefe
+
+
+def _systems():
+    t2 = wl.tiny_system(nc=3, p=2, n_atoms=2, seed=5, L=6.0, r0=1.0, r1=2.0)
+    t3 = dataclasses.replace(wl.tiny_system(nc=3, p=3, n_atoms=3, seed=7, L=7.0, r0=1.0, r1=2.0), Z=np.array([2.0, 3.0, 6.0]))
+    t4 = wl.tiny_system(nc=4, p=4, n_atoms=2, seed=5, L=6.0, r0=1.0, r1=2.0)
+    return {"tiny_p2": t2, "tiny_p3": t3, "tiny_p4": t4, "single_atom": wl.single_atom()}
+
+
+def _precond(P):
+    lam, U = np.linalg.eigh(P.Aoo)
+    S = (U / np.sqrt(lam)[None, :]) @ U.T
+    return 1.0 / np.sqrt(P.m), S
+
+
+@pytest.mark.parametrize("name", list(_systems()))
+def test_poisson_operator_vs_oracle(lib, name):
+    import torch
+    sysm = _systems()[name]
+    P = po.PoissonOEFE(sysm)
+    pop = lib.Operator(sysm, poisson=True)
+    assert (pop.n_fe, pop.n_enr, pop.n_tot) == (P.N, P.n_enr, P.n_tot)
+    rng = np.random.default_rng(3)
+    X = rng.uniform(-1.0, 1.0, size=(P.n_tot, 5))
+    Y = lib.ham_apply(pop, torch.from_numpy(X).cuda()).cpu().numpy()
+    d, S = _precond(P)
+    A = P.matrix()
+    Z = np.concatenate([d[:, None] * X[:P.N], S @ X[P.N:]])
+    AZ = A @ Z
+    Yo = np.concatenate([d[:, None] * AZ[:P.N], S @ AZ[P.N:]])
+    err = np.abs(Y - Yo).max(axis=0) / np.abs(Yo).max(axis=0)
+    assert err.max() <= 1e-10, err
+
+
+@pytest.mark.parametrize("name", list(_systems()))
+def test_poisson_solve_vs_oracle(lib, name):
+    import torch
+    sysm = _systems()[name]
+    P = po.PoissonOEFE(sysm)
+    rho = P.model_electron_density()
+    phi_o = P.solve(P.neutral_charge(rho))
+    pop = lib.Operator(sysm, poisson=True)
+    phi, it, rel = lib.poisson_solve(pop, torch.from_numpy(np.ascontiguousarray(rho)).cuda(), tol=1e-12, max_iter=5000)
+    assert rel <= 1e-12 and 0 < it < 5000
+    ph = phi.cpu().numpy()
+    assert np.abs(ph - phi_o).max() <= 1e-8 * np.abs(phi_o).max()
+    # the FE part has zero mass-weighted mean on both sides
+    assert abs((P.m * ph[:P.N]).sum()) <= 1e-12 * P.m.sum() * np.abs(ph).max()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "poisson_diamond8_oracle.npz")), reason="golden file missing")
+def test_poisson_solve_diamond8(lib):
+    import torch
+    g = np.load(os.path.join(GOLD, "poisson_diamond8_oracle.npz"))
+    sysm = wl.diamond8()
+    pop = lib.Operator(sysm, poisson=True)
+    phi, it, rel = lib.poisson_solve(pop, torch.from_numpy(g["rho"]).cuda(), tol=1e-12, max_iter=5000)
+    assert rel <= 1e-12
+    ph = phi.cpu().numpy()
+    assert np.abs(ph - g["phi"]).max() <= 1e-8 * np.abs(g["phi"]).max()
+
+
+def test_poisson_errors(lib):
+    import torch
+    sysm = _systems()["tiny_p2"]
+    op = lib.Operator(sysm)
+    rho = torch.zeros(op.n_cells, op.nq, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        lib.poisson_solve(op, rho)
+    pop = lib.Operator(sysm, poisson=True)
+    with pytest.raises(lib.OefeError) as ei:
+        lib.poisson_solve(pop, rho + 1e-3 * torch.arange(rho.numel(), dtype=torch.float64, device="cuda").reshape(rho.shape),
+                          tol=1e-14, max_iter=2)
+    assert ei.value.code == -5  # OEFE_ENOCONV
