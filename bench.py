@@ -28,9 +28,11 @@ average launch duration (HIP events around each launch, on its stream), and
 Also reported (`extra`): the filter alone (median of >= 10 calls), the float32
 filter on diamond64; on diamond8 (12^3 cells, 110,632 DoF, 72 vectors, degree
 50) the float64 pass and filter, the float32 / bf16-operand filters with their
-per-pass Ritz-value error against the float64 oracle; the 8 k-point batched
-filter in complex128 / complex64; the library's stream-copy rate; and the CPU
-oracle on a bounded sample of the headline workload (`cpu_baseline`).
+per-pass Ritz-value error against the float64 oracle; on both workloads the rest
+of an SCF step from the last pass's Ritz pairs (occupations and Fermi level,
+density, auxiliary potential by conjugate gradients: `scf_tail`); the 8 k-point
+batched filter in complex128 / complex64; the library's stream-copy rate; and the
+CPU oracle on a bounded sample of the headline workload (`cpu_baseline`).
 
 Helpers for the committed profile summaries (they read rocprofv3 output):
     python bench.py --summarize-trace DIR           kernel-trace statistics table
@@ -94,6 +96,9 @@ def parse():
                     help="short run for counter collection: one float64 filter of the workload; with "
                          "--profile-extra also one float64 pass and one bf16-operand filter on diamond8")
     ap.add_argument("--profile-extra", action="store_true")
+    ap.add_argument("--profile-poisson", action="store_true",
+                    help="short run for a kernel trace: two auxiliary-potential solves of the workload (smeared "
+                         "nuclear charges with a uniform background, no electron density)")
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-gaps", nargs=2, metavar=("DIR", "KERNEL"),
                     help="per filter degree (between successive launches of KERNEL): period, time with a "
@@ -309,6 +314,45 @@ def kpoint_bench(oefe, wl, torch, base, m, reps):
     return res
 
 
+def scf_tail_bench(oefe, torch, gop, sysm, X, theta, n_elec, reps=3):
+    """The rest of an SCF step after a float64 pass, on the pass's Ritz pairs: Fermi-Dirac
+    occupations at 500 K with the Fermi level (oefe_fermi_occupations), the density at the
+    quadrature points (oefe_density) and the auxiliary potential of the smeared nuclear charges
+    plus that density (oefe_poisson_solve, CG to a relative residual of 1e-10).  Median of `reps`
+    timed calls each (HIP events on the current stream)."""
+    stream = torch.cuda.current_stream()
+    kT = 500.0 * 3.166811563e-6
+    th = torch.as_tensor(theta, dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        out, ts = None, []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return out, float(np.median(ts[1:]))
+
+    (f, mu, eb, cnt), occ_ms = timed(lambda: oefe.fermi_occupations([th], [1.0], n_elec, kT))
+    w = 2.0 * f[0]
+    rho, dens_ms = timed(lambda: oefe.density(gop, X, w))
+    pop = oefe.Operator(sysm, poisson=True)
+    (phi, iters, rel), pois_ms = timed(lambda: oefe.poisson_solve(pop, rho, tol=1e-10, max_iter=20000))
+    it_bytes = degree_bytes(pop, 1, 8) + 13.0 * 8.0 * pop.n_tot  # operator at one column + CG vector updates
+    gbs = it_bytes * iters / (pois_ms / 1e3) / 1e9
+    out = {"n_elec": n_elec, "kT_Ha": kT, "fermi_level_Ha": mu, "band_energy_Ha": eb, "electron_count": cnt,
+           "occupations_ms": occ_ms, "density_ms": dens_ms,
+           "poisson": {"ms": pois_ms, "cg_iterations": iters, "relative_residual": rel, "ms_per_iteration": pois_ms / iters,
+                       "bytes_per_iteration": it_bytes, "achieved_gbs": gbs, "frac_of_8TBs": gbs / PEAK_HBM_GBS,
+                       "unknowns": pop.n_tot}}
+    log(f"{sysm.name} scf tail: occupations {occ_ms:.3f} ms (mu {mu:.4f} Ha), density {dens_ms:.2f} ms, poisson "
+        f"{pois_ms:.2f} ms ({iters} CG iterations, {pois_ms / iters * 1e3:.1f} us each, {gbs:.0f} GB/s)")
+    del pop
+    return out
+
+
 def diamond8_extra(oefe, wl, torch, reps):
     """diamond8: float64 pass and filter, float32 / bf16-operand filters with their per-pass Ritz
     error against the float64 oracle (stored values) and against the float64 GPU run."""
@@ -320,7 +364,9 @@ def diamond8_extra(oefe, wl, torch, reps):
     dev_bounds = torch.zeros(3, dtype=torch.float64, device="cuda")
     a0L, b, a1 = oefe.lanczos_bounds(gop, v0, cfg.lanczos_k, dev_bounds=dev_bounds, with_cut=True)
     X = X0.clone()
-    pass_ms, _, _ = run_passes(oefe, torch, gop, X, cfg.m, dev_bounds, 1, max(5, reps))
+    pass_ms, _, th8 = run_passes(oefe, torch, gop, X, cfg.m, dev_bounds, 1, max(5, reps))
+    scf8 = scf_tail_bench(oefe, torch, gop, cfg.system, X, th8[-1], 8 * 14.0)
+    del X
     abc = (a1, b, a0L)
     filt_ms = median_filter_ms(oefe, torch, gop, X0, cfg.m, abc, reps)
     node_us, _ = stage_us(oefe, gop, X0, cfg.m, abc, "node")
@@ -358,6 +404,7 @@ def diamond8_extra(oefe, wl, torch, reps):
             f"{['%.1e' % x for x in rec.get('ritz_err_vs_oracle_per_pass_Ha', err64)]}; sin(max angle) "
             f"{sin_angle:.1e}")
     out["mixed_occupied_states"] = n_occ
+    out["scf_tail"] = scf8
     return out, gop
 
 
@@ -441,6 +488,7 @@ def summarize_gaps(d, key):
 
 def _short(name):
     n = name.replace("void ", "").replace("oefe::(anonymous namespace)::", "").replace("oefe::", "")
+    n = n.replace("(anonymous namespace)::", "")
     out, depth = "", 0
     for ch in n:
         if ch == "(" and depth == 0:
@@ -555,6 +603,14 @@ def main():
     if args.profile:
         profile_run(oefe, wl, torch, cfg, args)
         return
+    if args.profile_poisson:
+        pop = oefe.Operator(sysm, poisson=True)
+        rho = torch.zeros(pop.n_cells, pop.nq, dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            _, iters, rel = oefe.poisson_solve(pop, rho, tol=1e-10, max_iter=20000)
+        torch.cuda.synchronize()
+        log(f"profile: {sysm.name} auxiliary potential, {iters} CG iterations, relative residual {rel:.1e}")
+        return
     t = time.time()
     gop = oefe.Operator(sysm)
     log(f"operator setup {time.time() - t:.1f} s, n_tot={gop.n_tot}, nv={cfg.nv}, m={cfg.m}")
@@ -567,7 +623,10 @@ def main():
 
     # the timed passes: filter bounds through device memory, statuses checked afterwards
     X = X0.clone()
-    ms, step_ms, _ = run_passes(oefe, torch, gop, X, cfg.m, dev_bounds, args.warmup, args.steps)
+    ms, step_ms, th_passes = run_passes(oefe, torch, gop, X, cfg.m, dev_bounds, args.warmup, args.steps)
+    # occupations, density and auxiliary potential from the last pass's Ritz pairs; the block's 320
+    # states hold fewer than the 64 atoms' 896 electrons, so 2 (nv - 32) electrons are placed
+    scf_tail = None if args.no_extra else scf_tail_bench(oefe, torch, gop, sysm, X, th_passes[-1], 2.0 * (cfg.nv - 32))
     del X
     work = gop.n_tot * cfg.nv * cfg.m
     value = work / (ms / 1e3)
@@ -597,6 +656,8 @@ def main():
              "cell_kernel": {"bound": "alu", "kernel": "fe_cell_lanes_kernel<double,5,false>", "achieved": cell_tfs,
                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": cell_tfs / PEAK_FP64_TFLOPS,
                              "avg_launch_us": cell_us, "flops_per_launch": cell_flops}}
+    if scf_tail is not None:
+        extra["scf_tail"] = scf_tail
 
     # float32 filter on the headline workload
     f32_ms = median_filter_ms(oefe, torch, gop, X0.float(), cfg.m, abc, max(3, reps // 3))

@@ -1522,6 +1522,29 @@ __global__ void dot_partial_kernel(const T* __restrict__ A, int64_t lda, const T
   part[(int64_t)blockIdx.x * nv + j] = s;
 }
 
+// one column: workgroup b sums the rows of its contiguous chunk (thread-strided, then a fixed tree)
+template <typename T, bool CPLX>
+__global__ __launch_bounds__(256) void dot1_partial_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                                           int64_t ldb, int64_t n, int64_t rows_per_chunk,
+                                                           double* __restrict__ part) {
+  constexpr int E = CPLX ? 2 : 1;
+  __shared__ double red[256];
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk, g1 = min(n, g0 + rows_per_chunk);
+  double s = 0;
+  for (int64_t g = g0 + threadIdx.x; g < g1; g += 256) {
+    const T* a = A + g * lda * E;
+    const T* b = B + g * ldb * E;
+    s += (double)a[0] * (double)b[0] + (CPLX ? (double)a[E - 1] * (double)b[E - 1] : 0.0);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 __global__ void dot_final_kernel(const double* __restrict__ part, int nchunks, int nv, const double* __restrict__ f,
                                  double* __restrict__ out) {
   __shared__ double red[256];
@@ -2285,6 +2308,17 @@ int copy_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t
 template <typename T>
 int dot_columns(bool cplx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n, int nv, const double* f,
                 double* out, double* scratch, hipStream_t s) {
+  if (nv == 1) {
+    // a single column: 256 threads per chunk (the per-column kernel would use one lane of 64)
+    const int nch = gram_chunks(n);
+    const int64_t rpc = cdiv(n, nch);
+    if (cplx)
+      hipLaunchKernelGGL((dot1_partial_kernel<T, true>), dim3(nch), dim3(256), 0, s, A, lda, B, ldb, n, rpc, scratch);
+    else
+      hipLaunchKernelGGL((dot1_partial_kernel<T, false>), dim3(nch), dim3(256), 0, s, A, lda, B, ldb, n, rpc, scratch);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, scratch, nch, 1, f, out);
+    return check();
+  }
   const int nch = gram_chunks(n);
   const int64_t rpc = cdiv(n, nch);
   dim3 grid(nch, (unsigned)cdiv(nv, 64));
