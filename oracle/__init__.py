@@ -23,6 +23,8 @@ chfsi        Lanczos bounds, scaled Chebyshev filter, Cholesky-Gram-Schmidt,
 adjoint      band energy and its gradients w.r.t. V and X (eqnrho, E_band).
 occupations  Fermi-Dirac occupations, Fermi level from the electron count, band
              energy and density from Ritz pairs (eqnfd, eqnne, eqnrho, E_band).
+uform        the k-point Hamiltonian in the periodic-function form (eqnksdftu,
+             eqnUOEFEAtomic, eqnHOEFEelelements with its k terms).
 poisson      smeared nuclear charges and the auxiliary electrostatic potential in
              the OEFE basis (eqnsmeared, eqngr, eqnvg, eqnpoissonaux, eqnPhiOEFE,
              eqnpoissX, eqnDiscLaplace, eqnDiscForceVec).
