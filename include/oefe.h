@@ -101,6 +101,19 @@ typedef struct oefe_op_s* oefe_op;
  * to one coupling tile), EUNSUPPORTED (p), ENOMEM, EDEVICE. */
 int oefe_op_create(const oefe_system_desc* desc, oefe_op* out);
 
+/* The k-point operator in the periodic-function form (Sec. II eqnksdftu; Sec. III.A
+ * eqnUOEFEAtomic, eqnHOEFEelelements): u = exp(-i k.x) psi in periodic FE functions (no
+ * Bloch phase) plus orthogonalized enrichment functions with the atomic part
+ * exp(-i k.(x - R^x)) psi~(x - R^x), and H = 1/2 grad . grad - i k . grad + |k|^2/2 + V
+ * (the enrichment blocks' first-derivative term in its Hermitian form
+ * -i/2 k . int (N_m^* grad N_n - grad N_m^* N_n), equal to the written one where the Gauss
+ * rule integrates grad (N_m^* N_n) exactly).  desc->kvec is required.  The handle is used
+ * like one of oefe_op_create with a wavevector (complex blocks, C128 / C64; batches of
+ * this form only); oefe_op_set_potential and oefe_op_get_potential take and return V
+ * without the |k|^2/2.  Errors as oefe_op_create; EUNSUPPORTED from a step on a mesh whose
+ * n^2 ld or (nc (p+1))^2 ld reach 2^31 elements. */
+int oefe_op_create_uform(const oefe_system_desc* desc, oefe_op* out);
+
 /* Test operator Ht = diag(lambda) (n real entries, host memory), no mesh. */
 int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out);
 

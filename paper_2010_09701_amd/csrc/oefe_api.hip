@@ -621,6 +621,11 @@ constexpr int kFilterDevMaxDegree = 160;
 
 // ---- Potential-dependent operator data rebuilt on the device (oefe_op_set_potential).
 // W V at the quadrature points (float64 and float32 copies)
+__global__ void shift_kernel(double* __restrict__ v, double c, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] += c;
+}
+
 __global__ void wv_kernel(const double* __restrict__ W, const double* __restrict__ V, double* __restrict__ WV,
                           float* __restrict__ WVf, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1069,6 +1074,36 @@ int oefe_op_create(const oefe_system_desc* desc, oefe_op* out) {
   return OEFE_OK;
 }
 
+int oefe_op_create_uform(const oefe_system_desc* desc, oefe_op* out) {
+  if (!desc || !out) return fail(OEFE_EINVAL, "null argument");
+  *out = nullptr;
+  if (!desc->kvec) return fail(OEFE_EINVAL, "the periodic-function form needs a Bloch wavevector (kvec)");
+  if (desc->n_atoms < 0 || desc->n_enr < 0 || (desc->n_atoms > 0 && (!desc->pos || !desc->Z)) ||
+      (desc->n_enr > 0 && (!desc->enr_atom || !desc->enr_power || !desc->enr_zeta || !desc->enr_axis)))
+    return fail(OEFE_EINVAL, "inconsistent system description");
+  for (int nu = 0; nu < desc->n_enr; ++nu)
+    if (desc->enr_power[nu] < 0 || desc->enr_axis[nu] < -1 || desc->enr_axis[nu] > 2 || !(desc->enr_zeta[nu] > 0))
+      return fail(OEFE_EINVAL, "bad enrichment function parameters");
+  oefe_op_s* op = new (std::nothrow) oefe_op_s();
+  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  op->uform = true;
+  std::string err;
+  int rc = build_operator(op, desc, err);
+  if (rc == OEFE_OK && hipGetDevice(&op->device) != hipSuccess) {
+    rc = OEFE_EDEVICE;
+    err = "no HIP device";
+  }
+  if (rc == OEFE_OK) rc = upload_operator(op, err);
+  if (rc == OEFE_OK && !scratch_address(err)) rc = OEFE_EDEVICE;
+  if (rc != OEFE_OK) {
+    free_device(op);
+    delete op;
+    return fail(rc, err);
+  }
+  *out = op;
+  return OEFE_OK;
+}
+
 int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out) {
   if (!lambda || !out || n <= 0) return fail(OEFE_EINVAL, "bad diagonal operator arguments");
   oefe_op_s* op = new (std::nothrow) oefe_op_s();
@@ -1126,6 +1161,8 @@ int oefe_op_set_potential(oefe_op op, const double* V, oefe_stream stream) {
   const int64_t nqt = op->n_cells * op->nq;
   if (hipMemcpyAsync(op->d.V, V, (size_t)nqt * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail(OEFE_EDEVICE, "oefe_op_set_potential: copy of V failed");
+  if (op->vshift != 0.0)  // the periodic-function form's |k|^2/2 rides on V
+    hipLaunchKernelGGL(shift_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s, op->d.V, op->vshift, nqt);
   hipLaunchKernelGGL(wv_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s, op->d.W, op->d.V, op->d.WV,
                      op->d.WVf, nqt);
   if (op->n_enr > 0) {
@@ -1170,6 +1207,8 @@ int oefe_op_get_potential(oefe_op op, double* V_host, double* W_host) {
   if (e == hipSuccess && V_host) e = hipMemcpy(V_host, op->d.V, bytes, hipMemcpyDeviceToHost);
   if (e == hipSuccess && W_host) e = hipMemcpy(W_host, op->d.W, bytes, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "oefe_op_get_potential");
+  if (V_host && op->vshift != 0.0)  // report the caller's V (without the form's |k|^2/2)
+    for (size_t i = 0; i < bytes / sizeof(double); ++i) V_host[i] -= op->vshift;
   return OEFE_OK;
 }
 

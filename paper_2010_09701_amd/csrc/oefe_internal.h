@@ -102,6 +102,9 @@ struct CellCoef {
   T om[kMaxP1];
   T kappa;  // h / 4: scale of the reference kinetic form
   T mscale; // (h/2)^(-3/2): scale of m^-1/2
+  // the derivative at the Gauss points of the interpolant of values there (reference
+  // coordinates): the first-derivative term of the periodic-function k-point form
+  T Dh[kMaxP1][kMaxP1];
 };
 
 struct DeviceArrays {
@@ -196,6 +199,12 @@ struct oefe_op_s {
   // atom, no potential, the Laplacian 1/(4 pi) int grad . grad in place of the kinetic
   // 1/2 int grad . grad, and S = (A^oo)^-1/2 (the enrichment block's Jacobi factor)
   bool poisson = false;
+  // k-point operator in the periodic-function form (oefe_op_create_uform): periodic FE functions
+  // (no Bloch phase), the k terms of the Hamiltonian (-i k . grad in the cell stage, |k|^2/2
+  // added to the potential: vshift) and the k-dependent enrichment
+  bool uform = false;
+  double vshift = 0.0;
+  double uk[3] = {0, 0, 0};  // (h/2)^3 (2/h) k_d: the cell stage's first-derivative coefficients
   int device = 0;
   // geometry
   double L = 0, h = 0;

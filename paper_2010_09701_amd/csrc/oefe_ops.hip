@@ -58,12 +58,14 @@ struct KP {
   T* part2;
   int nch;  // chunks per function in part2
   T* wp;
+  const T* wv;  // W (V + the form's constant shift) of this operator at its quadrature points
   const T* tv;
   const T* S;
   const T* Hoo;
   T alpha, c, beta;
   const double* sc;  // device (alpha, c, beta) of the step in place of the three above, or null
   Phase3<T> ph;
+  T uk[3];  // periodic-function k-point form: (h/2)^3 (2/h) k_d (zero otherwise)
 };
 
 // the step's scalars: from device memory when the filter's bounds live on the device
@@ -100,8 +102,8 @@ struct KBatch {
 // equals K_e z + B^T diag(W V) B z with the exact (Gauss) cell stiffness.
 // ---------------------------------------------------------------------------
 template <typename T, int P1, int CW, bool CPLX>
-__global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, const T* __restrict__ WV, CellCoef<T> cf,
-                                                          int nc, int p, int n, int64_t n_cells) {
+__global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, CellCoef<T> cf, int nc, int p, int n,
+                                                          int64_t n_cells) {
   constexpr int NP = P1 * P1;
   constexpr int CPT = 64 / CW;
   __shared__ T lds[NP * P1][64];
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, const T*
   // 5. quadrature-point terms: potential + y/z kinetic
   const int qx = w;
   const T kx = cf.kappa * cf.w[qx];
-  const T* wv = WV + ee * (NP * P1);
+  const T* wv = P.wv + ee * (NP * P1);
 #pragma unroll
   for (int qz = 0; qz < P1; ++qz)
 #pragma unroll
@@ -331,9 +333,15 @@ __device__ __forceinline__ void wave_sync() {
 template <int P1>
 constexpr int lanes_cw() { return (64 / P1) & ~1; }
 
-template <typename T, int P1, bool CPLX>
-__global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const T* __restrict__ WV, CellCoef<T> cf,
-                                                            int nc, int p, int n, int64_t n_cells, int nch) {
+// UF: the periodic-function k-point form's first-derivative term -i k . int N grad N is added
+// (complex columns only): k . grad u at the Gauss points (derivatives of the interpolant of the
+// Gauss values, the x-derivative taken on the x-y plane before the transpose), weighted, from
+// the complex partner lane (real <-> imaginary part) with the sign of -i, into the values that
+// the backward passes project.
+template <typename T, int P1, bool CPLX, bool UF = false>
+__global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCoef<T> cf, int nc, int p, int n,
+                                                            int64_t n_cells, int nch) {
+  static_assert(!UF || CPLX, "the first-derivative term acts on complex columns");
   constexpr int NP = P1 * P1;
   constexpr int CWc = lanes_cw<P1>();
   // launch order: the column chunks of a group of 4 cells are consecutive in L, and each
@@ -367,7 +375,7 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
   const int cx = eu % nc, cy = (eu / nc) % nc, cz = eu / (nc * nc);
   // W V of the wave's cell: loaded now, parked in LDS after the first passes, read in step 5
   constexpr int NQ3 = NP * P1;
-  const T* __restrict__ wvg = WV + (e < n_cells ? e : n_cells - 1) * NQ3;
+  const T* __restrict__ wvg = P.wv + (e < n_cells ? e : n_cells - 1) * NQ3;
   const T wv0 = wvg[min(lane, NQ3 - 1)], wv1 = wvg[min(lane + 64, NQ3 - 1)];
 
   // 1. gather plane az = w with the m^-1/2 pre-scale (and Bloch phase)
@@ -433,6 +441,19 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
       for (int ay = 0; ay < P1; ++ay) s += cf.B1[qy][ay] * t[ay * P1 + qx];
       v[qy * P1 + qx] = s;
     }
+  // UF: x-derivative of the x-y plane (transposed and z-interpolated after step 4)
+  T dxv[UF ? NP : 1];
+  if constexpr (UF) {
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < P1; ++qx) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < P1; ++k) s += cf.Dh[qx][k] * v[qy * P1 + k];
+        dxv[qy * P1 + qx] = s;
+      }
+  }
   // 3. transpose z-planes -> x-planes: lds[(az*P1 + qy)*P1 + qx]
   T* wvs = wv_all[wid];
   if (lane < NQ3) wvs[lane] = wv0;
@@ -458,6 +479,39 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
       for (int az = 0; az < P1; ++az) s += cf.B1[qz][az] * t[az * P1 + qy];
       u[qz * P1 + qy] = s;
     }
+  // UF: tg = W' uk . grad u at this lane's Gauss points (W' the product of the 1D weights), then
+  // taken from the complex partner with the sign of -i: real part += (k.G) imag, imag -= (k.G) real
+  T tg[UF ? NP : 1];
+  if constexpr (UF) {
+    wave_sync();  // every lane has read the step-3 transpose
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < P1; ++qx) lds[((w * P1 + qy) * P1 + qx) * CWc + g] = dxv[qy * P1 + qx];
+    wave_sync();
+    T dt[NP];
+#pragma unroll
+    for (int az = 0; az < P1; ++az)
+#pragma unroll
+      for (int qy = 0; qy < P1; ++qy) dt[az * P1 + qy] = lds[((az * P1 + qy) * P1 + w) * CWc + g];
+    const T k0 = P.uk[0], k1 = P.uk[1], k2 = P.uk[2];
+#pragma unroll
+    for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+      for (int qy = 0; qy < P1; ++qy) {
+        T dx = 0, dy = 0, dz = 0;
+#pragma unroll
+        for (int k = 0; k < P1; ++k) {
+          dx += cf.B1[qz][k] * dt[k * P1 + qy];
+          dy += cf.Dh[qy][k] * u[qz * P1 + k];
+          dz += cf.Dh[qz][k] * u[k * P1 + qy];
+        }
+        tg[qz * P1 + qy] = cf.w[w] * cf.w[qy] * cf.w[qz] * (k0 * dx + k1 * dy + k2 * dz);
+      }
+    const T sg = (g & 1) ? T(-1) : T(1);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) tg[i] = sg * __shfl_xor(tg[i], 1);
+  }
   // 5. quadrature-point terms: potential + y/z kinetic
   const int qx = w;
   const T kx = cf.kappa * cf.w[qx];
@@ -472,6 +526,7 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, const 
         lz += cf.L1[qz][k] * u[k * P1 + qy];
       }
       t[qz * P1 + qy] = wvs[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
+      if constexpr (UF) t[qz * P1 + qy] += tg[qz * P1 + qy];
     }
   // 6. t' = (B^T)_y (B^T)_z t  -> indexed [az][ay]
   T tp[NP];
@@ -593,8 +648,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBf16MatElems = 8 * 4 * 64 * 8;  // one 128 x 128 matrix in fragment order
 
 __global__ __launch_bounds__(768) void fe_cell_bf16_kernel(KBatch<float> kb, const uint16_t* __restrict__ mats,
-                                                           const float* __restrict__ WV, CellCoef<float> cf, int nc,
-                                                           int p, int n, int P1, int64_t n_cells) {
+                                                           CellCoef<float> cf, int nc, int p, int n, int P1,
+                                                           int64_t n_cells) {
   extern __shared__ unsigned char smem_raw[];
   bf16x8* frag = reinterpret_cast<bf16x8*>(smem_raw);  // [3][8][4][64]
   // per local node a < 128: (ax, ay, az) packed in 8-bit fields, and the m^-1/2 factor
@@ -659,7 +714,7 @@ __global__ __launch_bounds__(768) void fe_cell_bf16_kernel(KBatch<float> kb, con
     const bool interior = cx < nc - 1 && cy < nc - 1 && cz < nc - 1;
     const int64_t gbase = bx + (int64_t)n * (by + (int64_t)n * bz);
     // W V of this lane's quadrature points, loaded with the gather (used after U = B Z)
-    const float* wv = WV + e * nd;
+    const float* wv = P.wv + e * nd;
     float wq[4][8];
 #pragma unroll
     for (int k4 = 0; k4 < 4; ++k4)
@@ -1949,8 +2004,8 @@ template <typename T, int P1, int CW, bool CPLX>
 void launch_cell_cw(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, hipStream_t s) {
   constexpr int CPT = 64 / CW;
   dim3 grid((unsigned)cdiv(op->n_cells, CPT), (unsigned)cdiv(max_ncr, CW), (unsigned)kb.nk);
-  hipLaunchKernelGGL((fe_cell_kernel<T, P1, CW, CPLX>), grid, dim3(64 * P1), 0, s, kb, devptrs<T>(op).WV,
-                     coef<T>(op), op->nc, op->p, op->n, op->n_cells);
+  hipLaunchKernelGGL((fe_cell_kernel<T, P1, CW, CPLX>), grid, dim3(64 * P1), 0, s, kb, coef<T>(op), op->nc, op->p,
+                     op->n, op->n_cells);
 }
 
 template <typename T, int P1, bool CPLX>
@@ -1968,8 +2023,15 @@ void launch_cell_lanes(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, hi
   constexpr int CWc = lanes_cw<P1>();
   const int nch = (int)cdiv(max_ncr, CWc);
   dim3 grid((unsigned)(cdiv(op->n_cells, 4) * nch), 1, (unsigned)kb.nk);
-  hipLaunchKernelGGL((fe_cell_lanes_kernel<T, P1, CPLX>), grid, dim3(256), 0, s, kb, devptrs<T>(op).WV, coef<T>(op),
-                     op->nc, op->p, op->n, op->n_cells, nch);
+  if constexpr (CPLX) {
+    if (op->uform) {  // the operators of a batch share the form (checked by the batched entry points)
+      hipLaunchKernelGGL((fe_cell_lanes_kernel<T, P1, true, true>), grid, dim3(256), 0, s, kb, coef<T>(op), op->nc,
+                         op->p, op->n, op->n_cells, nch);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((fe_cell_lanes_kernel<T, P1, CPLX>), grid, dim3(256), 0, s, kb, coef<T>(op), op->nc, op->p, op->n,
+                     op->n_cells, nch);
 }
 
 // The planes-in-lanes kernel forms row offsets within a z-plane of X and of the node-slot
@@ -1987,7 +2049,13 @@ bool lanes_offsets_fit(const oefe_op_s* op, const KBatch<T>& kb) {
 // cw = 0: planes-in-lanes kernel; 8, 16, 32, 64: plane-per-wave kernel with cw columns per cell
 template <typename T, bool CPLX>
 void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, hipStream_t s) {
-  if (cw == 0 && !lanes_offsets_fit(op, kb)) cw = 16;
+  if (op->uform) {
+    // only the planes-in-lanes kernel carries the periodic-function form's first-derivative
+    // term; oefe_op_create_uform checks that its 32-bit offsets fit the mesh
+    cw = 0;
+  } else if (cw == 0 && !lanes_offsets_fit(op, kb)) {
+    cw = 16;
+  }
   if (cw == 0) {
     switch (op->P1) {
       case 3: launch_cell_lanes<T, 3, CPLX>(op, kb, max_ncr, s); break;
@@ -2060,7 +2128,7 @@ void launch_cell_bf16(const oefe_op_s* op, const KBatch<float>& kb, hipStream_t 
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   hipLaunchKernelGGL(fe_cell_bf16_kernel, dim3((unsigned)std::max(1, cus / kb.nk), 1, (unsigned)kb.nk), dim3(768),
-                     lds, s, kb, op->d.bf_mats, op->d.WVf, op->cf, op->nc, op->p, op->n, op->P1, op->n_cells);
+                     lds, s, kb, op->d.bf_mats, op->cf, op->nc, op->p, op->n, op->P1, op->n_cells);
 }
 
 template <typename T, bool CPLX>
@@ -2071,7 +2139,10 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
   for (int q = 0; q < kb.nk; ++q) {
     max_ncr = std::max(max_ncr, kb.k[q].ncr);
     max_nv = std::max(max_nv, kb.k[q].nv);
+    if (ops[q]->uform != op->uform) return OEFE_EINVAL;  // one form per batch
   }
+  // the periodic-function form runs on the planes-in-lanes cell kernel only
+  if (op->uform && !lanes_offsets_fit(op, kb)) return OEFE_EUNSUPPORTED;
   const unsigned nk = (unsigned)kb.nk;
   const int nO = op->n_enr;
   const bool ovl = ov != nullptr && nO > 0;
@@ -2190,6 +2261,7 @@ KP<T> make_kp(const oefe_op_s* op, const T* x, int64_t ld, const T* prev, T* out
   P.part2 = (T*)w.part2;
   P.nch = reduce_chunks(op);
   P.wp = (T*)w.wp;
+  P.wv = dp.WV;
   P.tv = dp.tv;
   P.S = dp.S;
   P.Hoo = dp.Hoo;
@@ -2200,6 +2272,7 @@ KP<T> make_kp(const oefe_op_s* op, const T* x, int64_t ld, const T* prev, T* out
   for (int d = 0; d < 3; ++d) {
     P.ph.re[d] = (T)op->phase[d][0];
     P.ph.im[d] = (T)op->phase[d][1];
+    P.uk[d] = (T)op->uk[d];
   }
   return P;
 }

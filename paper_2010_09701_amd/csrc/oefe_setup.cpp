@@ -389,6 +389,11 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
   op->n_enr = pois ? desc->n_atoms : desc->n_enr;
   op->n_tot = op->N + op->n_enr;
   op->cplx = desc->kvec != nullptr;
+  const bool uf = op->uform;
+  if (uf && !op->cplx) {
+    err = "the periodic-function form needs a Bloch wavevector";
+    return OEFE_EINVAL;
+  }
   if (pois && (op->cplx || desc->n_atoms < 1)) {
     err = "the auxiliary-potential operator needs atoms and no Bloch wavevector";
     return OEFE_EINVAL;
@@ -402,10 +407,12 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
   if (op->cplx) {
     for (int d = 0; d < 3; ++d) {
       op->kvec[d] = desc->kvec[d];
-      op->phase[d][0] = std::cos(desc->kvec[d] * op->L);
-      op->phase[d][1] = std::sin(desc->kvec[d] * op->L);
+      // the periodic-function form's FE functions are periodic: no phase across the cell boundary
+      op->phase[d][0] = uf ? 1.0 : std::cos(desc->kvec[d] * op->L);
+      op->phase[d][1] = uf ? 0.0 : std::sin(desc->kvec[d] * op->L);
     }
   }
+  op->vshift = uf ? 0.5 * (op->kvec[0] * op->kvec[0] + op->kvec[1] * op->kvec[1] + op->kvec[2] * op->kvec[2]) : 0.0;
   const int P1 = op->P1;
   const double h = op->h;
   // ---- 1D data
@@ -447,6 +454,9 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
   }
   op->cd.kappa = kin * h / 2.0;  // kin (2/h)^2 (h/2)^3
   op->cd.mscale = std::pow(h / 2.0, -1.5);
+  for (int i = 0; i < P1; ++i)
+    for (int j = 0; j < P1; ++j) op->cd.Dh[i][j] = Dh[i * P1 + j];
+  for (int d = 0; d < 3; ++d) op->uk[d] = uf ? std::pow(h / 2.0, 3) * (2.0 / h) * op->kvec[d] : 0.0;
   {
     auto& f = op->cf;
     auto& c = op->cd;
@@ -462,6 +472,8 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
     }
     f.kappa = (float)c.kappa;
     f.mscale = (float)c.mscale;
+    for (int i = 0; i < kMaxP1; ++i)
+      for (int j = 0; j < kMaxP1; ++j) f.Dh[i][j] = (float)c.Dh[i][j];
   }
   // ---- lumped GLL mass m_g = (h/2)^3 prod_d w'(i_d mod p)
   const int n = op->n;
@@ -495,7 +507,7 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
         }
         v -= desc->Z[I] * erf_over_r(std::sqrt(d2), desc->sigma);
       }
-      op->V[e * nq + q] = v;
+      op->V[e * nq + q] = v + op->vshift;  // the periodic-function form's |k|^2/2 rides on V
     }
   // ---- Poisson operator: smearing radii (half the distance to the nearest other atom or
   // periodic image, the largest radii without overlap) and the smeared nuclear charge
@@ -623,7 +635,10 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
           d[k] = dr - op->L * t[k];
         }
         cplx ph(1.0, 0.0);
-        if (op->cplx) {
+        if (uf) {  // exp(-i k . (x - R^x)) (eqnUOEFEAtomic)
+          double arg = -(op->kvec[0] * d[0] + op->kvec[1] * d[1] + op->kvec[2] * d[2]);
+          ph = cplx(std::cos(arg), std::sin(arg));
+        } else if (op->cplx) {
           double arg = op->L * (op->kvec[0] * t[0] + op->kvec[1] * t[1] + op->kvec[2] * t[2]);
           ph = cplx(std::cos(arg), std::sin(arg));
         }
@@ -635,7 +650,8 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
           else
             atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
           NA[(ci * nq + q) * nf + f] = ph * val;
-          for (int k = 0; k < 3; ++k) gNA[((ci * nq + q) * nf + f) * 3 + k] = ph * gr[k];
+          for (int k = 0; k < 3; ++k)  // the periodic-function form: grad (e^{-ik.d} f) = e^{-ik.d} (grad f - i k f)
+            gNA[((ci * nq + q) * nf + f) * 3 + k] = ph * (uf ? cplx(gr[k], -op->kvec[k] * val) : cplx(gr[k], 0.0));
         }
       }
     }
@@ -706,6 +722,17 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
           const double* Mz = dd == 2 ? Dm : Bm;
           tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
           for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+          if (uf) {
+            // the first-derivative term in Hermitian form (the enrichment function is not a
+            // polynomial): -i/2 k_d int N^C d_d Phi + i/2 k_d int (d_d N^C) Phi
+            const cplx mi(0.0, -0.5 * op->kvec[dd]), pi(0.0, 0.5 * op->kvec[dd]);
+            for (int q = 0; q < nq; ++q) tin[q] = mi * op->W[e * nq + q] * b.gphi[((ci * nq + q) * nf + f) * 3 + dd];
+            tp_backward<cplx>(P1, Bm, Bm, Bm, tin.data(), tout.data());
+            for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+            for (int q = 0; q < nq; ++q) tin[q] = pi * s2h * op->W[e * nq + q] * b.phi[(ci * nq + q) * nf + f];
+            tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
+            for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+          }
         }
         for (int a = 0; a < op->nd; ++a) {
           int64_t g;
@@ -742,6 +769,11 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
               op->Moo[ix] += Wq * a * bb;
               op->Hoo_kin[ix] +=
                   kin * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
+              if (uf) {  // -i/2 k . int (Phi_i^* grad Phi_j - grad Phi_i^* Phi_j)
+                cplx t(0.0, 0.0);
+                for (int k = 0; k < 3; ++k) t += op->kvec[k] * (a * gb[k] - std::conj(ga[k]) * bb);
+                op->Hoo_kin[ix] += cplx(0.0, -0.5) * Wq * t;
+              }
             }
           }
         }

@@ -58,6 +58,7 @@ def _load():
     sig = {
         "oefe_op_create": ([ctypes.POINTER(_Desc), ctypes.POINTER(vp)], i32),
         "oefe_op_create_diagonal": ([vp, i64, ctypes.POINTER(vp)], i32),
+        "oefe_op_create_uform": ([vp, ctypes.POINTER(vp)], i32),
         "oefe_op_destroy": ([vp], i32),
         "oefe_op_dims": ([vp, vp], i32),
         "oefe_op_set_potential": ([vp, vp, vp], i32),
@@ -100,7 +101,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = [
-    "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
+    "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_create_uform", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
     "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
@@ -149,9 +150,11 @@ def _block(X: torch.Tensor, n_tot: int) -> Tuple[int, int]:
 class Operator:
     """Device-resident OEFE operator (or a diagonal test operator)."""
 
-    def __init__(self, system: Optional[workloads.System] = None, _handle=None, poisson: bool = False):
+    def __init__(self, system: Optional[workloads.System] = None, _handle=None, poisson: bool = False,
+                 uform: bool = False):
         """poisson: the operator of the auxiliary-potential Poisson problem on the system's mesh and
-        atoms (oefe_poisson_create) instead of the Kohn-Sham operator."""
+        atoms (oefe_poisson_create) instead of the Kohn-Sham operator; uform: the k-point operator
+        in the periodic-function form (oefe_op_create_uform; the system needs a wavevector)."""
         self._h = ctypes.c_void_p(0)
         self.is_poisson = poisson
         if _handle is not None:
@@ -173,6 +176,8 @@ class Operator:
             torch.cuda.current_device()
             if poisson:
                 _check(_lib.oefe_poisson_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_poisson_create")
+            elif uform:
+                _check(_lib.oefe_op_create_uform(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create_uform")
             else:
                 _check(_lib.oefe_op_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create")
         dims = (ctypes.c_int64 * 11)()
