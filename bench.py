@@ -255,20 +255,10 @@ def run_passes(oefe, torch, gop, X, m, dev_bounds, n_warm, n_steps):
     return t0.elapsed_time(t1) / n_steps, [a.elapsed_time(b) for a, b in ev], th_all
 
 
-def kpoint_bench(oefe, wl, torch, base, m, reps):
-    """The 8 k-points of the 2x2x2 Monkhorst-Pack grid, 48..96 vectors each, in one batched
-    filter per precision (complex128, complex64), after the launch-shape autotuner."""
-    ks = wl.monkhorst_pack_2(base.L)
-    ops = [oefe.Operator(base.with_k(k)) for k in ks]
-    blocks = [torch.from_numpy(wl.start_block(op.n_tot, wl.KPOINT_NV[q], 10 + q, complex_=True)).cuda()
-              for q, op in enumerate(ops)]
-    abc = []
-    for op in ops:
-        v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, 2)).cuda()
-        a0, bb, a = oefe.lanczos_bounds(op, v0, 10, with_cut=True)
-        abc.append((a, bb, a0))
-    work = sum(op.n_tot * nv for op, nv in zip(ops, wl.KPOINT_NV)) * m
-    res = {"k_points": len(ops), "nv": wl.KPOINT_NV, "m": m}
+def _batched_filter_timing(oefe, torch, ops, blocks, abc, m, reps, work, label):
+    """Mean time of `reps` batched filters per precision (complex128, complex64), after the
+    launch-shape autotuner, with the average cell / node / coupling stage times."""
+    res = {}
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     for name, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
@@ -291,8 +281,35 @@ def kpoint_bench(oefe, wl, torch, base, m, reps):
             stages[which + "_us"] = tot_ms / max(n_launch, 1) * 1e3
         res[name] = {"filter_ms": ms, "rate": work / (ms / 1e3), "shape": {"cw": tune["cw"], "cb": tune["cb"]},
                      "stage_avg_us": stages}
-        log(f"k-points {name}: batched filter {ms:.3f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s, shape {tune}, "
+        log(f"{label} {name}: batched filter {ms:.3f} ms, {work / (ms / 1e3):.3e} DoF*vec*deg/s, shape {tune}, "
             + ", ".join(f"{k} {v:.1f}" for k, v in stages.items()))
+    return res
+
+
+def kpoint_bench(oefe, wl, torch, base, m, reps):
+    """The 8 k-points of the 2x2x2 Monkhorst-Pack grid, 48..96 vectors each, in one batched
+    filter per precision (complex128, complex64), after the launch-shape autotuner."""
+    ks = wl.monkhorst_pack_2(base.L)
+    ops = [oefe.Operator(base.with_k(k)) for k in ks]
+    blocks = [torch.from_numpy(wl.start_block(op.n_tot, wl.KPOINT_NV[q], 10 + q, complex_=True)).cuda()
+              for q, op in enumerate(ops)]
+    abc = []
+    for op in ops:
+        v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, 2)).cuda()
+        a0, bb, a = oefe.lanczos_bounds(op, v0, 10, with_cut=True)
+        abc.append((a, bb, a0))
+    work = sum(op.n_tot * nv for op, nv in zip(ops, wl.KPOINT_NV)) * m
+    res = {"k_points": len(ops), "nv": wl.KPOINT_NV, "m": m}
+    res.update(_batched_filter_timing(oefe, torch, ops, blocks, abc, m, reps, work, "k-points"))
+    # the same k-points in the periodic-function form (eqnksdftu): periodic FE basis, the
+    # first-derivative term in the cell stage, |k|^2/2 with the potential
+    uops = [oefe.Operator(base.with_k(k), uform=True) for k in ks]
+    uabc = []
+    for op in uops:
+        v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, 2)).cuda()
+        a0, bb, a = oefe.lanczos_bounds(op, v0, 10, with_cut=True)
+        uabc.append((a, bb, a0))
+    res["uform"] = _batched_filter_timing(oefe, torch, uops, blocks, uabc, m, reps, work, "k-points u-form")
     # complex64 filter passes against the complex128 oracle at the k-points with the fewest and the
     # most vectors (stored oracle values)
     gpath = os.path.join(GOLD, "kpoint_passes_oracle.npz")
@@ -487,6 +504,8 @@ def summarize_gaps(d, key):
 
 
 def _short(name):
+    if name.replace("void ", "", 1).startswith("at::native::"):  # torch's own kernels: the operation only
+        return "at::native direct copy" if "direct_copy" in name else name.replace("void ", "", 1).split("<")[0]
     n = name.replace("void ", "").replace("oefe::(anonymous namespace)::", "").replace("oefe::", "")
     n = n.replace("(anonymous namespace)::", "")
     out, depth = "", 0
@@ -653,7 +672,7 @@ def main():
              "degree_bytes": dbytes,
              "degree_roofline": {"bound": "hbm", "achieved": degree_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                  "frac": degree_gbs / PEAK_HBM_GBS, "degree_us": filt_ms / cfg.m * 1e3},
-             "cell_kernel": {"bound": "alu", "kernel": "fe_cell_lanes_kernel<double,5,false>", "achieved": cell_tfs,
+             "cell_kernel": {"bound": "alu", "kernel": "fe_cell_lanes_kernel<double,5,false,false>", "achieved": cell_tfs,
                              "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": cell_tfs / PEAK_FP64_TFLOPS,
                              "avg_launch_us": cell_us, "flops_per_launch": cell_flops}}
     if scf_tail is not None:

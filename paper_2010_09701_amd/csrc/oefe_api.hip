@@ -1375,7 +1375,9 @@ int autotune_impl(int nk, const oefe_op* ops, bool bf16, void* const* X, const i
   ov.first = ov.last = true;  // each timed step is a whole overlapped step
   double best = 1e300;
   int bcw = 0, bcb = 0, rc = OEFE_OK;
-  for (int a = 0; a < 5 && !rc; ++a)
+  // the periodic-function form runs on the planes-in-lanes cell kernel (cw = 0) only
+  const int n_cw = opp[0]->uform ? 1 : 5;
+  for (int a = 0; a < n_cw && !rc; ++a)
     for (int b = 0; b < 4 && !rc; ++b) {
       for (int q = 0; q < nk; ++q) {
         ops[q]->tune_cw = cws[a];

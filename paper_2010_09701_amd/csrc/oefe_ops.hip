@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCo
       for (int ay = 0; ay < P1; ++ay) s += cf.B1[qy][ay] * t[ay * P1 + qx];
       v[qy * P1 + qx] = s;
     }
-  // UF: x-derivative of the x-y plane (transposed and z-interpolated after step 4)
+  // UF: x-derivative of the x-y plane (transposed after step 3, z-interpolated after step 4)
   T dxv[UF ? NP : 1];
   if constexpr (UF) {
 #pragma unroll
@@ -468,6 +468,14 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCo
   for (int az = 0; az < P1; ++az)
 #pragma unroll
     for (int qy = 0; qy < P1; ++qy) t[az * P1 + qy] = lds[((az * P1 + qy) * P1 + w) * CWc + g];
+  if constexpr (UF) {
+    wave_sync();  // every lane has read the transpose
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < P1; ++qx) lds[((w * P1 + qy) * P1 + qx) * CWc + g] = dxv[qy * P1 + qx];
+    wave_sync();
+  }
   // 4. z-pass -> u[qz][qy]
   T u[NP];
 #pragma unroll
@@ -479,38 +487,30 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCo
       for (int az = 0; az < P1; ++az) s += cf.B1[qz][az] * t[az * P1 + qy];
       u[qz * P1 + qy] = s;
     }
-  // UF: tg = W' uk . grad u at this lane's Gauss points (W' the product of the 1D weights), then
-  // taken from the complex partner with the sign of -i: real part += (k.G) imag, imag -= (k.G) real
-  T tg[UF ? NP : 1];
+  // UF: t = W' uk . grad u at this lane's Gauss points (W' the product of the 1D weights; t is
+  // free after step 4), taken from the complex partner with the sign of -i: real part
+  // += (k.G) imag, imag -= (k.G) real; the x-derivative read from the transposed plane in LDS
   if constexpr (UF) {
-    wave_sync();  // every lane has read the step-3 transpose
-#pragma unroll
-    for (int qy = 0; qy < P1; ++qy)
-#pragma unroll
-      for (int qx = 0; qx < P1; ++qx) lds[((w * P1 + qy) * P1 + qx) * CWc + g] = dxv[qy * P1 + qx];
-    wave_sync();
-    T dt[NP];
-#pragma unroll
-    for (int az = 0; az < P1; ++az)
-#pragma unroll
-      for (int qy = 0; qy < P1; ++qy) dt[az * P1 + qy] = lds[((az * P1 + qy) * P1 + w) * CWc + g];
     const T k0 = P.uk[0], k1 = P.uk[1], k2 = P.uk[2];
+    const T sg = (g & 1) ? T(-1) : T(1);
 #pragma unroll
-    for (int qz = 0; qz < P1; ++qz)
+    for (int qy = 0; qy < P1; ++qy) {
+      T dt[P1];
 #pragma unroll
-      for (int qy = 0; qy < P1; ++qy) {
+      for (int k = 0; k < P1; ++k) dt[k] = lds[((k * P1 + qy) * P1 + w) * CWc + g];
+#pragma unroll
+      for (int qz = 0; qz < P1; ++qz) {
         T dx = 0, dy = 0, dz = 0;
 #pragma unroll
         for (int k = 0; k < P1; ++k) {
-          dx += cf.B1[qz][k] * dt[k * P1 + qy];
+          dx += cf.B1[qz][k] * dt[k];
           dy += cf.Dh[qy][k] * u[qz * P1 + k];
           dz += cf.Dh[qz][k] * u[k * P1 + qy];
         }
-        tg[qz * P1 + qy] = cf.w[w] * cf.w[qy] * cf.w[qz] * (k0 * dx + k1 * dy + k2 * dz);
+        const T tg = cf.w[w] * cf.w[qy] * cf.w[qz] * (k0 * dx + k1 * dy + k2 * dz);
+        t[qz * P1 + qy] = sg * __shfl_xor(tg, 1);
       }
-    const T sg = (g & 1) ? T(-1) : T(1);
-#pragma unroll
-    for (int i = 0; i < NP; ++i) tg[i] = sg * __shfl_xor(tg[i], 1);
+    }
   }
   // 5. quadrature-point terms: potential + y/z kinetic
   const int qx = w;
@@ -525,8 +525,12 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCo
         ly += cf.L1[qy][k] * u[qz * P1 + k];
         lz += cf.L1[qz][k] * u[k * P1 + qy];
       }
-      t[qz * P1 + qy] = wvs[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
-      if constexpr (UF) t[qz * P1 + qy] += tg[qz * P1 + qy];
+      const T tq = wvs[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
+      if constexpr (UF) {
+        t[qz * P1 + qy] = tq + t[qz * P1 + qy];
+      } else {
+        t[qz * P1 + qy] = tq;
+      }
     }
   // 6. t' = (B^T)_y (B^T)_z t  -> indexed [az][ay]
   T tp[NP];
