@@ -28,6 +28,8 @@ uform        the k-point Hamiltonian in the periodic-function form (eqnksdftu,
 poisson      smeared nuclear charges and the auxiliary electrostatic potential in
              the OEFE basis (eqnsmeared, eqngr, eqnvg, eqnpoissonaux, eqnPhiOEFE,
              eqnpoissX, eqnDiscLaplace, eqnDiscForceVec).
+adaptive     adaptive quadrature for the integrals of the enrichment functions
+             (Sec. III.B) and the Kohn-Sham operator whose enrichment blocks use it.
 
 Functions whose only check is agreement with the HIP path say "parity
 unpinned" in their docstring.

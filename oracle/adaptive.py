@@ -1,0 +1,340 @@
+"""Adaptive quadrature for the integrals of the enrichment functions (Sec. III.B), and the
+Kohn-Sham operator whose enrichment blocks use it.  Test infrastructure only.
+
+The enrichment functions vary sharply near the nuclei, so the paper integrates them with a
+quadrature built by dividing each finite element recursively until a set of trial integrals
+of the enrichment functions converges (divide and conquer; the details are in a cited work).
+Readings used here:
+
+* the rule of a box is the tensor Gauss rule with q = p + 1 points per direction mapped to
+  the box; a box is split into its 8 half-size children;
+* trial integrals of a box, for every atomic function nu (radial part times angular factor
+  times cutoff, without Bloch phase) whose atom's support contains the cell: int psi~^2 and
+  int |grad psi~|^2 (the enrichment blocks are quadratic in the functions), and for every local
+  node a of the cell int psi~ N_a and int grad psi~ . grad^ N_a (grad^ the gradient in the
+  cell's reference coordinates): the FE-enrichment integrals of the orthogonalization
+  numerator and of H^co;
+* a box is accepted when, for every trial integral, its own rule and the sum of its
+  children's rules differ by at most tol times the trial integral's scale: the whole-space
+  integrals A_nu = int psi~^2 and B_nu = int |grad psi~|^2 (radial integrals) for the quadratic
+  ones, and sqrt(A_nu v) and sqrt(B_nu v) for the ones with N_a (v = 4/3 pi r1^3, the volume
+  where psi~ is nonzero: Cauchy-Schwarz bounds of int |psi~| and int |grad psi~|); otherwise
+  each child is treated the same way, down to max_depth levels, where boxes are accepted;
+* a box that meets the ball of radius r1 around one of its atoms (nearest image) while none
+  of its Gauss points lies inside that ball is split without the test: its rule cannot see
+  the part of the functions it holds;
+* the accepted boxes (leaves) of a cell are ordered depth first, children in the order
+  cx + 2 cy + 4 cz; the points of a leaf in the order qx + q qy + q^2 qz; the rule covers the
+  union of the supports (core cells within r1 of an atom, plus one layer), cells ascending;
+* with the adaptive rule: the numerator of the orthogonalization coefficients
+  (eqnorthC; the denominator stays the GLL mass), M^oo, H^oo and H^co; H^cc keeps the
+  Gauss rule.  V at the adaptive points is an input (by default the nuclear potential
+  evaluated there).
+
+With max_depth = 0 every cell is one leaf and the blocks are those of enrichment.py.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .enrichment import atomic_function, atomic_part
+from .mesh import Mesh
+from .operator import OEFEOperator
+from .potential import min_image, nuclear_potential
+from .quadrature import gauss_rule
+
+CHILD_OFFSETS = np.array([[c & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], dtype=np.float64)
+
+
+def radial_scales(fn, r0: float, r1: float, panels: int = 64, order: int = 20):
+    """A = int psi~^2 and B = int |grad psi~|^2 over R^3 for one atomic function.
+
+    psi~ = g(r) (s-type) or d_axis g(r) (p-type), g = r^power exp(-zeta r) h(r).  Angular
+    integrals: 4 pi g^2 (s) or 4 pi r^2 g^2 / 3 (p) for the value;
+    4 pi g'^2 (s) or 4 pi (g^2 + 2/3 r g g' + r^2 g'^2 / 3) (p) for the gradient.
+    """
+    x, w = gauss_rule(order)
+    edges = np.linspace(0.0, r1, panels + 1)
+    a, b = edges[:-1, None], edges[1:, None]
+    r = (0.5 * (b - a) * (x[None, :] + 1.0) + a).ravel()
+    wr = (0.5 * (b - a) * w[None, :]).ravel()
+    d = np.zeros((r.size, 3))
+    d[:, 0] = r
+    g, gg = atomic_function(d, fn.power, fn.zeta, -1, r0, r1)
+    gp = gg[:, 0]
+    if fn.axis < 0:
+        A = np.sum(wr * 4.0 * np.pi * r * r * g * g)
+        B = np.sum(wr * 4.0 * np.pi * r * r * gp * gp)
+    else:
+        A = np.sum(wr * 4.0 * np.pi * r ** 4 * g * g / 3.0)
+        B = np.sum(wr * 4.0 * np.pi * r * r * (g * g + 2.0 / 3.0 * r * g * gp + r * r * gp * gp / 3.0))
+    return A, B
+
+
+def lagrange_at(nodes: np.ndarray, t: np.ndarray):
+    """ell_a(t) and ell_a'(t) of the Lagrange basis on `nodes` at points t (product formula;
+    the derivative as the sum over the dropped factor).  Returns [len(t), len(nodes)] each."""
+    n = nodes.size
+    V = np.ones((t.size, n))
+    D = np.zeros((t.size, n))
+    for a in range(n):
+        others = [j for j in range(n) if j != a]
+        den = np.prod([nodes[a] - nodes[j] for j in others])
+        V[:, a] = np.prod([t - nodes[j] for j in others], axis=0) / den
+        D[:, a] = sum(np.prod([t - nodes[j] for j in others if j != k], axis=0) for k in others) / den
+    return V, D
+
+
+def box_rule(lo: np.ndarray, size: float, q: int):
+    """Tensor Gauss points [q^3, 3] and weights [q^3] of the box [lo, lo + size]^3."""
+    eta, w = gauss_rule(q)
+    t = lo[None, :] + 0.5 * size * (eta[:, None] + 1.0)  # [q, 3] per direction
+    wt = 0.5 * size * w
+    iz, iy, ix = np.meshgrid(np.arange(q), np.arange(q), np.arange(q), indexing="ij")
+    ix, iy, iz = ix.ravel(), iy.ravel(), iz.ravel()  # qx fastest
+    pts = np.stack([t[ix, 0], t[iy, 1], t[iz, 2]], axis=-1)
+    return pts, wt[ix] * wt[iy] * wt[iz]
+
+
+class AdaptiveRule:
+    """The adaptive rule on the union of the enrichment supports of `system`."""
+
+    def __init__(self, mesh: Mesh, system, tol: float, max_depth: int):
+        self.mesh = mesh
+        self.tol = float(tol)
+        self.max_depth = int(max_depth)
+        q = mesh.q1
+        atom_of = np.array([f.atom for f in system.enr], dtype=np.int64)
+        self.support = {}  # atom -> support cells (ascending)
+        fns_of_cell = {}
+        for I in range(system.n_atoms):
+            idx = np.nonzero(atom_of == I)[0]
+            if idx.size == 0:
+                continue
+            cells = mesh.dilate_cells(mesh.cells_near(system.pos[I], system.r1))
+            self.support[I] = cells
+            for e in cells.tolist():
+                fns_of_cell.setdefault(e, []).extend((I, int(i)) for i in idx)
+        scales = {}
+        vol = 4.0 / 3.0 * np.pi * system.r1 ** 3
+        nd = mesh.nd
+        for i, fn in enumerate(system.enr):
+            A, B = radial_scales(fn, system.r0, system.r1)
+            scales[i] = np.concatenate([[A, B], np.full(nd, np.sqrt(A * vol)), np.full(nd, np.sqrt(B * vol))])
+        xi = mesh.ref.xi
+        p1 = mesh.p1
+        ia = np.arange(nd)
+        iax, iay, iaz = ia % p1, (ia // p1) % p1, ia // (p1 * p1)
+        self.cells = np.array(sorted(fns_of_cell), dtype=np.int64)
+        self.leaves = {}  # cell -> list of (lo [3], size)
+        h = mesh.h
+
+        def trial(lo, size, fl, org):
+            pts, wq = box_rule(lo, size, q)
+            ref = 2.0 * (pts - org[None, :]) / h - 1.0
+            Vx, Dx = lagrange_at(xi, ref[:, 0])
+            Vy, Dy = lagrange_at(xi, ref[:, 1])
+            Vz, Dz = lagrange_at(xi, ref[:, 2])
+            Na = Vx[:, iax] * Vy[:, iay] * Vz[:, iaz]  # [q^3, nd]
+            Ga = np.stack([Dx[:, iax] * Vy[:, iay] * Vz[:, iaz], Vx[:, iax] * Dy[:, iay] * Vz[:, iaz],
+                           Vx[:, iax] * Vy[:, iay] * Dz[:, iaz]], axis=-1)  # [q^3, nd, 3]
+            out = np.zeros((len(fl), 2 + 2 * nd))
+            for j, (I, i) in enumerate(fl):
+                fn = system.enr[i]
+                d = min_image(pts - system.pos[I][None, :], mesh.L)
+                v, g = atomic_function(d, fn.power, fn.zeta, fn.axis, system.r0, system.r1)
+                out[j, 0] = np.sum(wq * v * v)
+                out[j, 1] = np.sum(wq * (g * g).sum(-1))
+                out[j, 2:2 + nd] = (wq * v) @ Na
+                out[j, 2 + nd:] = np.einsum("q,qd,qad->a", wq, g, Ga)
+            return out
+
+        for e in self.cells.tolist():
+            fl = fns_of_cell[e]
+            bound = self.tol * np.array([scales[i] for (_, i) in fl])  # [nfn, 2 + 2 nd]
+            leaves = []
+            org = mesh.cell_origin[e].astype(np.float64)
+
+            atoms = sorted({I for (I, _) in fl})
+
+            def blind(lo, size):
+                # the box meets an atom's ball of radius r1 but none of its Gauss points is inside
+                pts, _ = box_rule(lo, size, q)
+                for I in atoms:
+                    c = min_image(lo + 0.5 * size - system.pos[I], mesh.L)
+                    ex = np.maximum(np.abs(c) - 0.5 * size, 0.0)
+                    if np.sqrt((ex * ex).sum()) < system.r1:
+                        d = min_image(pts - system.pos[I][None, :], mesh.L)
+                        if np.sqrt((d * d).sum(-1)).min() >= system.r1:
+                            return True
+                return False
+
+            def refine(lo, size, depth):
+                if depth == self.max_depth:
+                    leaves.append((lo, size))
+                    return
+                kids = [(lo + 0.5 * size * CHILD_OFFSETS[c], 0.5 * size) for c in range(8)]
+                if blind(lo, size):
+                    for (k_lo, k_s) in kids:
+                        refine(k_lo, k_s, depth + 1)
+                    return
+                own = trial(lo, size, fl, org)
+                ksum = sum(trial(k_lo, k_s, fl, org) for (k_lo, k_s) in kids)
+                if np.all(np.abs(own - ksum) <= bound):
+                    leaves.append((lo, size))
+                    return
+                for (k_lo, k_s) in kids:
+                    refine(k_lo, k_s, depth + 1)
+
+            refine(org, h, 0)
+            self.leaves[e] = leaves
+        # points, weights and the FE basis at them, per cell
+        xi = mesh.ref.xi
+        self.points, self.weights, self.B, self.G = {}, {}, {}, {}
+        for e in self.cells.tolist():
+            P, Wt = [], []
+            for (lo, size) in self.leaves[e]:
+                pts, wq = box_rule(lo, size, q)
+                P.append(pts)
+                Wt.append(wq)
+            P = np.concatenate(P)
+            self.points[e] = P
+            self.weights[e] = np.concatenate(Wt)
+            ref = 2.0 * (P - mesh.cell_origin[e][None, :]) / h - 1.0  # reference coordinates in [-1, 1]
+            Vx, Dx = lagrange_at(xi, ref[:, 0])
+            Vy, Dy = lagrange_at(xi, ref[:, 1])
+            Vz, Dz = lagrange_at(xi, ref[:, 2])
+            p1 = mesh.p1
+            a = np.arange(mesh.nd)
+            ax, ay, az = a % p1, (a // p1) % p1, a // (p1 * p1)
+            self.B[e] = Vx[:, ax] * Vy[:, ay] * Vz[:, az]  # [n_pts, nd]
+            self.G[e] = np.stack([Dx[:, ax] * Vy[:, ay] * Vz[:, az], Vx[:, ax] * Dy[:, ay] * Vz[:, az],
+                                  Vx[:, ax] * Vy[:, ay] * Dz[:, az]])  # [3, n_pts, nd], reference derivatives
+        self.offsets = np.concatenate([[0], np.cumsum([self.points[e].shape[0] for e in self.cells.tolist()])])
+        self.n_points = int(self.offsets[-1])
+
+    def all_points(self) -> np.ndarray:
+        """Every point of the rule [n_points, 3], cells ascending, leaves and points in rule order."""
+        return np.concatenate([self.points[e] for e in self.cells.tolist()])
+
+    def all_weights(self) -> np.ndarray:
+        return np.concatenate([self.weights[e] for e in self.cells.tolist()])
+
+    def cell_slice(self, e: int) -> slice:
+        k = int(np.searchsorted(self.cells, e))
+        return slice(int(self.offsets[k]), int(self.offsets[k + 1]))
+
+
+class AdaptiveEnrichment:
+    """Enrichment blocks (eqnorthC, eqnMoo, eqnHOEFEelelements in the Bloch-function form) with
+    the adaptive rule.  V_adapt: V at every point of the rule (rule order).  atom_fn holds N^O
+    at the Gauss points (for fields there, with the coefficients c of the adaptive numerator),
+    atom_fn_adapt at the rule's points."""
+
+    def __init__(self, mesh: Mesh, system, m: np.ndarray, kvec, rule: AdaptiveRule, V_adapt: np.ndarray):
+        self.mesh = mesh
+        self.rule = rule
+        self.n_enr = system.n_enr
+        dtype = np.float64 if kvec is None else np.complex128
+        theta = mesh.bloch_phase(kvec)
+        s = 2.0 / mesh.h
+        atom_of = np.array([f.atom for f in system.enr], dtype=np.int64)
+        self.atom_fn_adapt = []  # (atom, fn indices, cells, [Phi per cell], [gradPhi per cell])
+        self.atom_fn = []  # (atom, fn indices, cells, Phi [nc, nq, F], gradPhi [nc, nq, F, 3]) at the Gauss points
+        for I, cells in rule.support.items():
+            idx = np.nonzero(atom_of == I)[0]
+            F = idx.size
+            NA, gNA = [], []
+            for e in cells.tolist():
+                x = rule.points[e]
+                draw = x - system.pos[I][None, :]
+                t = np.round(draw / mesh.L)
+                d = draw - mesh.L * t
+                ph = np.ones(x.shape[0]) if kvec is None else np.exp(1j * mesh.L * (t @ np.asarray(kvec)))
+                v = np.zeros((x.shape[0], F), dtype=dtype)
+                g = np.zeros((x.shape[0], F, 3), dtype=dtype)
+                for j, i in enumerate(idx):
+                    fn = system.enr[i]
+                    vv, gg = atomic_function(d, fn.power, fn.zeta, fn.axis, system.r0, system.r1)
+                    v[:, j] = ph * vv
+                    g[:, j, :] = ph[:, None] * gg
+                NA.append(v)
+                gNA.append(g)
+            # d_g = sum over (e, a) -> g of conj(theta_ea) sum_points w B_a N^A ; c = d / m
+            dnum = np.zeros((mesh.N, F), dtype=dtype)
+            for ci, e in enumerate(cells.tolist()):
+                de = rule.B[e].T @ (rule.weights[e][:, None] * NA[ci])  # [nd, F]
+                np.add.at(dnum, mesh.cell_dofs[e], np.conj(theta[e])[:, None] * de)
+            c = dnum / m[:, None]
+            Phi, gPhi = [], []
+            for ci, e in enumerate(cells.tolist()):
+                ce = theta[e][:, None] * c[mesh.cell_dofs[e]]  # [nd, F]
+                Phi.append(NA[ci] - rule.B[e] @ ce)
+                gp = gNA[ci].copy()
+                for dd in range(3):
+                    gp[:, :, dd] -= s * (rule.G[e][dd] @ ce)
+                gPhi.append(gp)
+            self.atom_fn_adapt.append((I, idx, cells, Phi, gPhi))
+            # the same orthogonalized functions at the Gauss points of the support cells
+            NAg, gNAg = atomic_part(mesh, system.pos[I], [system.enr[i] for i in idx], cells, system.r0, system.r1,
+                                    kvec)
+            ceg = theta[cells][:, :, None] * c[mesh.cell_dofs[cells]]  # [nc, nd, F]
+            Phig = NAg - np.einsum("qa,eaf->eqf", mesh.B, ceg)
+            gPhig = gNAg.copy()
+            for dd in range(3):
+                gPhig[..., dd] -= s * np.einsum("qa,eaf->eqf", mesh.Gref[dd], ceg)
+            self.atom_fn.append((I, idx, cells, Phig, gPhig))
+        nO = self.n_enr
+        Moo = np.zeros((nO, nO), dtype=dtype)
+        Hoo = np.zeros((nO, nO), dtype=dtype)
+        for (I, iI, cI, PI, gI) in self.atom_fn_adapt:
+            for (J, iJ, cJ, PJ, gJ) in self.atom_fn_adapt:
+                common, aI, aJ = np.intersect1d(cI, cJ, return_indices=True)
+                for e, i, j in zip(common.tolist(), aI.tolist(), aJ.tolist()):
+                    w = rule.weights[e]
+                    Ve = V_adapt[rule.cell_slice(e)]
+                    a, b = PI[i], PJ[j]
+                    Moo[np.ix_(iI, iJ)] += np.conj(a).T @ (w[:, None] * b)
+                    Hoo[np.ix_(iI, iJ)] += 0.5 * np.einsum("pfd,pgd->fg", np.conj(gI[i]) * w[:, None, None], gJ[j])
+                    Hoo[np.ix_(iI, iJ)] += np.conj(a).T @ ((w * Ve)[:, None] * b)
+        self.Moo, self.Hoo = Moo, Hoo
+        rows, cols, vals = [], [], []
+        for (I, idx, cells, Phi, gPhi) in self.atom_fn_adapt:
+            for ci, e in enumerate(cells.tolist()):
+                w = rule.weights[e]
+                Ve = V_adapt[rule.cell_slice(e)]
+                he = rule.B[e].T @ ((w * Ve)[:, None] * Phi[ci])
+                for dd in range(3):
+                    he += 0.5 * s * rule.G[e][dd].T @ (w[:, None] * gPhi[ci][:, :, dd])
+                he = np.conj(theta[e])[:, None] * he
+                rows.append(np.repeat(mesh.cell_dofs[e], idx.size))
+                cols.append(np.tile(idx, mesh.nd))
+                vals.append(he.reshape(-1))
+        if rows:
+            self.Hco = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                     shape=(mesh.N, nO)).tocsr()
+            self.Hco.sum_duplicates()
+        else:
+            self.Hco = sp.csr_matrix((mesh.N, nO), dtype=dtype)
+        if nO:
+            lam, U = np.linalg.eigh(Moo)
+            self.Moo_eigs = lam
+            self.S = (U / np.sqrt(lam)[None, :]) @ np.conj(U.T)
+        else:
+            self.Moo_eigs = np.zeros(0)
+            self.S = np.zeros((0, 0), dtype=dtype)
+
+
+class AdaptiveOEFEOperator(OEFEOperator):
+    """The Kohn-Sham operator (Gamma or Bloch-function form) with the enrichment blocks on the
+    adaptive rule; H^cc and V at the Gauss points as in OEFEOperator."""
+
+    def __init__(self, system, tol: float, max_depth: int, V: np.ndarray | None = None,
+                 V_adapt: np.ndarray | None = None, kvec="system"):
+        super().__init__(system, V=V, kvec=kvec)
+        self.rule = AdaptiveRule(self.mesh, system, tol, max_depth)
+        if V_adapt is None:
+            V_adapt = nuclear_potential(self.rule.all_points(), system.pos, system.Z, system.sigma, system.L)
+        self.V_adapt = np.ascontiguousarray(V_adapt, dtype=np.float64)
+        self.enr = AdaptiveEnrichment(self.mesh, system, self.m, self.kvec, self.rule, self.V_adapt)
