@@ -114,6 +114,34 @@ int oefe_op_create(const oefe_system_desc* desc, oefe_op* out);
  * n^2 ld or (nc (p+1))^2 ld reach 2^31 elements. */
 int oefe_op_create_uform(const oefe_system_desc* desc, oefe_op* out);
 
+/* The operator of oefe_op_create (Gamma point, or the Bloch-function form with desc->kvec)
+ * with the integrals of the enrichment functions on an adaptive quadrature (Sec. III.B: each
+ * finite element of an enrichment support is divided recursively until trial integrals of the
+ * enrichment functions converge).  Rule: a box carries the tensor Gauss rule of p + 1 points
+ * per direction; the trial integrals of a box are int psi~^2 and int |grad psi~|^2 of every
+ * atomic function (no phase) whose atom's support holds the cell; a box is kept when its rule
+ * and the sum of its 8 half-size children's rules differ by at most tol times the function's
+ * whole-space integral (radial integrals), else its children are refined (order
+ * cx + 2 cy + 4 cz, depth first) down to max_depth levels.  The rule covers the union of the
+ * supports (cells ascending); the orthogonalization numerator (eqnorthC), M^oo, H^oo and H^co
+ * use it, H^cc keeps the Gauss rule.  V at the rule's points is the nuclear potential of desc
+ * at creation; oefe_op_set_potential_adaptive replaces it.  0 < tol < 1, 0 <= max_depth <= 5,
+ * desc->n_enr >= 1.  Errors as oefe_op_create. */
+int oefe_op_create_adaptive(const oefe_system_desc* desc, double tol, int32_t max_depth, oefe_op* out);
+
+/* The points of the adaptive rule of an operator from oefe_op_create_adaptive: *n_points, and
+ * (host, either may be NULL) xyz [n_points x 3] and weights [n_points], in rule order (cells
+ * ascending, leaves depth first, points qx + (p+1) qy + (p+1)^2 qz within a leaf).
+ * Errors: EINVAL (not an adaptive-rule operator). */
+int oefe_op_adaptive_points(oefe_op op, int64_t* n_points, double* xyz_host, double* w_host);
+
+/* oefe_op_set_potential for an operator with the adaptive rule: V at the Gauss points (device
+ * [n_cells * nq], for H^cc) and V_adapt at the rule's points (device [n_points], rule order,
+ * for the enrichment blocks), read in stream order; H^co and H^oo are rebuilt on the device
+ * (eqnHOEFEelelements with the adaptive rule), queued on `stream`.  oefe_op_set_potential
+ * refuses such an operator.  Errors: EINVAL, EDEVICE. */
+int oefe_op_set_potential_adaptive(oefe_op op, const double* V, const double* V_adapt, oefe_stream stream);
+
 /* Test operator Ht = diag(lambda) (n real entries, host memory), no mesh. */
 int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out);
 
@@ -134,7 +162,7 @@ int oefe_op_dims(oefe_op op, int64_t* dims);
  * B^T diag(W V) N^O (pre-scaled by m^-1/2, in every layout the kernels read) and
  * H^oo = kinetic part + sum W V conj(N^O) N^O; the overlap and S do not depend on
  * V.  Compute calls on other streams must be ordered after it by the caller.
- * Errors: EINVAL (null V, diagonal operator), EDEVICE. */
+ * Errors: EINVAL (null V, diagonal operator, an operator with the adaptive rule), EDEVICE. */
 int oefe_op_set_potential(oefe_op op, const double* V, oefe_stream stream);
 
 /* Copy the current potential and the quadrature weights W_{e,q} to host
@@ -293,7 +321,9 @@ int oefe_set_eig_sweep_limit(oefe_op op, int32_t sweeps);
  * gradients: dE_dV[e,q] = W_{e,q} sum_i f_i |psi_i(x_{e,q})|^2 (device float64
  * [n_cells * nq]; psi_i the field of M^-1/2 x_i, the density of eqnrho times W),
  * dE_dX = 2 Ht X diag(f) (device, layout of X).  f: device float64 [nv].
- * dE_dV / dE_dX may be NULL.  prec F64/F32 (real) or C128/C64 (Bloch). */
+ * dE_dV / dE_dX may be NULL.  prec F64/F32 (real) or C128/C64 (Bloch).  dE_dV of an
+ * operator with the adaptive rule (oefe_op_create_adaptive) is EUNSUPPORTED: V enters its
+ * enrichment blocks at the rule's points as well. */
 int band_energy_grad(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t nv, const double* f,
                      double* E, double* dE_dV, void* dE_dX, void* work, oefe_stream stream);
 

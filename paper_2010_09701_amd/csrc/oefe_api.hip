@@ -528,6 +528,43 @@ int upload_operator(oefe_op_s* op, std::string& err) {
       if ((rc = dput(&op->d.Hoo_kin, hook, err))) return rc;
       if ((rc = dput(&op->d.csr2tile, op->csr_to_tile, err))) return rc;
       if (op->poisson && (rc = dput(&op->d.blk_cf0, boff, err))) return rc;
+      // adaptive rule (oefe_op_create_adaptive): points, leaves, N^O at the points of every
+      // flattened support cell, and the partials of the potential part of H^co
+      if (op->adaptive) {
+        std::vector<int32_t> cf_acell(boff[nb]);
+        std::vector<int64_t> cf_aoff(boff[nb] + 1, 0);
+        for (int b = 0; b < nb; ++b) {
+          auto& B = op->blocks[b];
+          for (size_t ci = 0; ci < B.cells.size(); ++ci) {
+            const int64_t cf = boff[b] + (int64_t)ci;
+            cf_acell[cf] = op->ad_index[B.cells[ci]];
+            cf_aoff[cf + 1] = cf_aoff[cf] + (B.aoff[ci + 1] - B.aoff[ci]);
+          }
+        }
+        std::vector<double> phiA((size_t)cf_aoff[boff[nb]] * op->FMAX * E, 0.0);
+        for (int b = 0; b < nb; ++b) {
+          auto& B = op->blocks[b];
+          for (size_t ci = 0; ci < B.cells.size(); ++ci) {
+            const int64_t cf = boff[b] + (int64_t)ci;
+            for (int64_t r = 0; r < B.aoff[ci + 1] - B.aoff[ci]; ++r)
+              for (int f = 0; f < B.nf; ++f) {
+                const std::complex<double> v = B.phiA[(size_t)(B.aoff[ci] + r) * B.nf + f];
+                const size_t o = ((size_t)(cf_aoff[cf] + r) * op->FMAX + f) * E;
+                phiA[o] = v.real();
+                if (cplx) phiA[o + 1] = v.imag();
+              }
+          }
+        }
+        if ((rc = dput(&op->d.a_w, op->ad_w, err))) return rc;
+        if ((rc = dput(&op->d.a_V, op->ad_V, err))) return rc;
+        if ((rc = dput(&op->d.a_leafB, op->ad_B, err))) return rc;
+        if ((rc = dput(&op->d.a_off, op->ad_off, err))) return rc;
+        if ((rc = dput(&op->d.cf_acell, cf_acell, err))) return rc;
+        if ((rc = dput(&op->d.cf_aoff, cf_aoff, err))) return rc;
+        if ((rc = dput(&op->d.phiA, phiA, err))) return rc;
+        if ((rc = dalloc(&op->d.hpart, (size_t)boff[nb] * op->nd * op->FMAX * E, err))) return rc;
+        op->n_cf = boff[nb];
+      }
     }
     if ((rc = dput(&op->d.blk_fn0, fn0, err))) return rc;
     if ((rc = dput(&op->d.blk_nf, nf, err))) return rc;
@@ -568,6 +605,8 @@ void free_device(oefe_op_s* op) {
   dfree(d.Sf); dfree(d.Hoof); dfree(d.cph_ptr); dfree(d.cph_blk); dfree(d.cph_off); dfree(d.phi);
   dfree(d.lambda); dfree(d.lambdaf); dfree(d.bf_mats);
   dfree(d.W); dfree(d.V); dfree(d.msq); dfree(d.hkin); dfree(d.Hoo_kin); dfree(d.row_blk); dfree(d.rpos);
+  dfree(d.a_w); dfree(d.a_V); dfree(d.a_leafB); dfree(d.a_off); dfree(d.cf_acell); dfree(d.cf_aoff);
+  dfree(d.phiA); dfree(d.hpart);
   dfree(d.bsmear); dfree(d.blk_cf0); dfree(d.rr_ptr); dfree(d.rr_ent); dfree(d.cf_cell); dfree(d.csr2tile); dfree(d.hp_ptr); dfree(d.hp_i);
   dfree(d.hp_j);
 }
@@ -641,14 +680,59 @@ __global__ void wv_kernel(const double* __restrict__ W, const double* __restrict
 // function), pairs in ascending cell order, written to the block-row, CSR and tile layouts.
 struct HcoRebuild {
   const double *W, *V, *phi, *msq, *hkin;
+  const double* hpart;  // adaptive rule: the (support cell, local node, f) partials, else null
   const int64_t *rr_ptr, *rpos, *csr2tile;
   const int32_t *rr_ent, *cf_cell, *row_blk, *blk_nf, *blk_rows;
   double *hv, *fr_val, *tile_val;
   float *hvf, *fr_valf, *tile_valf;
   int64_t n_hrows;
-  int FMAX, nq, P1, p, nc, n;
+  int FMAX, nq, P1, p, nc, n, nd;
   double ph[3][2];
 };
+
+// Adaptive rule (Sec. III.B): the potential part of H^co per (flattened support cell cf, local
+// node a, function f), sum over the cell's rule points x of ell_a(x) w V(x) N^O_f(x), ell_a(x)
+// the product of the point's leaf's 1D Lagrange values; one workgroup per cf, each thread a
+// strided share of the (a, f) items, the points in rule order (fixed summation order).
+struct HcoAdapt {
+  const double *a_w, *a_V, *a_leafB, *phiA;
+  const int64_t *a_off, *cf_aoff;
+  const int32_t* cf_acell;
+  double* hpart;
+  int nd, P1, FMAX;
+};
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void hco_adapt_partial_kernel(HcoAdapt a) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int64_t cf = blockIdx.x;
+  const int k = a.cf_acell[cf];
+  const int P1 = a.P1, nq3 = P1 * P1 * P1;
+  const int64_t p0 = a.a_off[k], l0 = p0 / nq3, l1 = a.a_off[k + 1] / nq3, r0 = a.cf_aoff[cf];
+  for (int it = threadIdx.x; it < a.nd * a.FMAX; it += blockDim.x) {
+    const int an = it / a.FMAX, f = it - an * a.FMAX;
+    const int ax = an % P1, ay = (an / P1) % P1, az = an / (P1 * P1);
+    double sr = 0.0, si = 0.0;
+    for (int64_t l = l0; l < l1; ++l) {
+      const double* lb = a.a_leafB + l * 3 * P1 * P1;
+      const int64_t gl = l * nq3, rl = r0 + (gl - p0);
+      int qi = 0;
+      for (int qz = 0; qz < P1; ++qz)
+        for (int qy = 0; qy < P1; ++qy) {
+          const double byz = lb[(P1 + qy) * P1 + ay] * lb[(2 * P1 + qz) * P1 + az];
+          for (int qx = 0; qx < P1; ++qx, ++qi) {
+            const double wv = lb[qx * P1 + ax] * byz * (a.a_w[gl + qi] * a.a_V[gl + qi]);
+            const double* ph = a.phiA + ((rl + qi) * a.FMAX + f) * E;
+            sr += wv * ph[0];
+            if (CPLX) si += wv * ph[1];
+          }
+        }
+    }
+    double* o = a.hpart + ((cf * a.nd + an) * a.FMAX + f) * E;
+    o[0] = sr;
+    if (CPLX) o[1] = si;
+  }
+}
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void hco_rebuild_kernel(HcoRebuild a, CellCoef<double> cd) {
@@ -664,15 +748,21 @@ __global__ __launch_bounds__(256) void hco_rebuild_kernel(HcoRebuild a, CellCoef
     const int cf = a.rr_ent[k] >> 7, an = a.rr_ent[k] & 127;
     const int e = a.cf_cell[cf];
     const int ax = an % P1, ay = (an / P1) % P1, az = an / (P1 * P1);
-    const double* Wc = a.W + (int64_t)e * nq;
-    const double* Vc = a.V + (int64_t)e * nq;
-    const double* pc = a.phi + ((int64_t)cf * nq * a.FMAX + f) * E;
     double vr = 0.0, vi = 0.0;
-    for (int q = 0; q < nq; ++q) {
-      const int qx = q % P1, qy = (q / P1) % P1, qz = q / (P1 * P1);
-      const double w = cd.B1[qx][ax] * cd.B1[qy][ay] * cd.B1[qz][az] * (Wc[q] * Vc[q]);
-      vr += w * pc[(int64_t)q * a.FMAX * E];
-      if (CPLX) vi += w * pc[(int64_t)q * a.FMAX * E + 1];
+    if (a.hpart) {  // adaptive rule: the partial of this (support cell, node, function)
+      const double* hp = a.hpart + (((int64_t)cf * a.nd + an) * a.FMAX + f) * E;
+      vr = hp[0];
+      if (CPLX) vi = hp[1];
+    } else {
+      const double* Wc = a.W + (int64_t)e * nq;
+      const double* Vc = a.V + (int64_t)e * nq;
+      const double* pc = a.phi + ((int64_t)cf * nq * a.FMAX + f) * E;
+      for (int q = 0; q < nq; ++q) {
+        const int qx = q % P1, qy = (q / P1) % P1, qz = q / (P1 * P1);
+        const double w = cd.B1[qx][ax] * cd.B1[qy][ay] * cd.B1[qz][az] * (Wc[q] * Vc[q]);
+        vr += w * pc[(int64_t)q * a.FMAX * E];
+        if (CPLX) vi += w * pc[(int64_t)q * a.FMAX * E + 1];
+      }
     }
     if constexpr (CPLX) {
       // conj(theta) of the periodic image the node is reached through
@@ -749,6 +839,50 @@ __global__ __launch_bounds__(256) void hoo_rebuild_kernel(const double* __restri
   if (CPLX) {
     Hoo[(int64_t)t * E + 1] = si;
     Hoof[(int64_t)t * E + 1] = (float)si;
+  }
+}
+
+// Adaptive rule: H^oo = kinetic part + sum over the common support cells (ascending) and their
+// rule points of w V conj(N^O_i) N^O_j; one thread per entry (i, j)
+struct HooAdapt {
+  const double *a_w, *a_V, *phiA, *Hoo_kin;
+  const int64_t *a_off, *cf_aoff, *hp_ptr;
+  const int32_t *cf_acell, *hp_i, *hp_j, *fn_blk, *blk_fn0;
+  double* Hoo;
+  float* Hoof;
+  int nO, nb, FMAX;
+};
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void hoo_adapt_kernel(HooAdapt a) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nO * a.nO) return;
+  const int i = t / a.nO, j = t - i * a.nO;
+  const int bi = a.fn_blk[i], bj = a.fn_blk[j];
+  const int f = i - a.blk_fn0[bi], g = j - a.blk_fn0[bj];
+  double sr = a.Hoo_kin[(int64_t)t * E], si = CPLX ? a.Hoo_kin[(int64_t)t * E + 1] : 0.0;
+  const int64_t pr = (int64_t)bi * a.nb + bj;
+  for (int64_t k = a.hp_ptr[pr]; k < a.hp_ptr[pr + 1]; ++k) {
+    const int ci = a.hp_i[k], cj = a.hp_j[k];
+    const int kc = a.cf_acell[ci];
+    const int64_t p0 = a.a_off[kc], np = a.a_off[kc + 1] - p0;
+    const double* pa = a.phiA + (a.cf_aoff[ci] * a.FMAX + f) * E;
+    const double* pb = a.phiA + (a.cf_aoff[cj] * a.FMAX + g) * E;
+    for (int64_t q = 0; q < np; ++q) {
+      const double wv = a.a_w[p0 + q] * a.a_V[p0 + q];
+      const double ar = pa[q * a.FMAX * E], ai = CPLX ? -pa[q * a.FMAX * E + 1] : 0.0;
+      const double br = pb[q * a.FMAX * E], bim = CPLX ? pb[q * a.FMAX * E + 1] : 0.0;
+      const double xr = wv * ar, xi = wv * ai;
+      sr += xr * br - xi * bim;
+      if (CPLX) si += xr * bim + xi * br;
+    }
+  }
+  a.Hoo[(int64_t)t * E] = sr;
+  a.Hoof[(int64_t)t * E] = (float)sr;
+  if (CPLX) {
+    a.Hoo[(int64_t)t * E + 1] = si;
+    a.Hoof[(int64_t)t * E + 1] = (float)si;
   }
 }
 
@@ -1043,7 +1177,10 @@ int oefe_copy_rate(const void* src, void* dst, size_t bytes, int32_t reps, doubl
   return OEFE_OK;
 }
 
-int oefe_op_create(const oefe_system_desc* desc, oefe_op* out) {
+static int rebuild_potential_device(oefe_op op, hipStream_t s);
+
+// Arguments shared by the finite-element operators' create calls.
+static int check_desc(const oefe_system_desc* desc, oefe_op* out) {
   if (!desc || !out) return fail(OEFE_EINVAL, "null argument");
   *out = nullptr;
   if (desc->n_atoms < 0 || desc->n_enr < 0 || (desc->n_atoms > 0 && (!desc->pos || !desc->Z)) ||
@@ -1052,19 +1189,31 @@ int oefe_op_create(const oefe_system_desc* desc, oefe_op* out) {
   for (int nu = 0; nu < desc->n_enr; ++nu)
     if (desc->enr_power[nu] < 0 || desc->enr_axis[nu] < -1 || desc->enr_axis[nu] > 2 || !(desc->enr_zeta[nu] > 0))
       return fail(OEFE_EINVAL, "bad enrichment function parameters");
-  oefe_op_s* op = new (std::nothrow) oefe_op_s();
-  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  return OEFE_OK;
+}
+
+// Host construction, upload and (adaptive rule) the potential parts on the device; frees `op`
+// on failure.
+static int finish_create(oefe_op_s* op, const oefe_system_desc* desc, oefe_op* out) {
   std::string err;
   int rc = build_operator(op, desc, err);
-  if (rc == OEFE_OK) {
-    if (hipGetDevice(&op->device) != hipSuccess) {
-      rc = OEFE_EDEVICE;
-      err = "no HIP device";
-    }
+  if (rc == OEFE_OK && hipGetDevice(&op->device) != hipSuccess) {
+    rc = OEFE_EDEVICE;
+    err = "no HIP device";
   }
   if (rc == OEFE_OK) rc = upload_operator(op, err);
   // the allocation-free calls' scratch address on this device, taken at set-up
   if (rc == OEFE_OK && !scratch_address(err)) rc = OEFE_EDEVICE;
+  if (rc == OEFE_OK && op->adaptive && op->n_enr > 0) {
+    // the potential parts of the enrichment blocks under the adaptive rule
+    rc = rebuild_potential_device(op, nullptr);
+    if (rc == OEFE_OK && hipDeviceSynchronize() != hipSuccess) {
+      rc = OEFE_EDEVICE;
+      err = "potential rebuild failed";
+    } else if (rc != OEFE_OK) {
+      err = oefe_last_error();
+    }
+  }
   if (rc != OEFE_OK) {
     free_device(op);
     delete op;
@@ -1074,34 +1223,33 @@ int oefe_op_create(const oefe_system_desc* desc, oefe_op* out) {
   return OEFE_OK;
 }
 
+int oefe_op_create(const oefe_system_desc* desc, oefe_op* out) {
+  if (int rc = check_desc(desc, out)) return rc;
+  oefe_op_s* op = new (std::nothrow) oefe_op_s();
+  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  return finish_create(op, desc, out);
+}
+
 int oefe_op_create_uform(const oefe_system_desc* desc, oefe_op* out) {
-  if (!desc || !out) return fail(OEFE_EINVAL, "null argument");
-  *out = nullptr;
+  if (int rc = check_desc(desc, out)) return rc;
   if (!desc->kvec) return fail(OEFE_EINVAL, "the periodic-function form needs a Bloch wavevector (kvec)");
-  if (desc->n_atoms < 0 || desc->n_enr < 0 || (desc->n_atoms > 0 && (!desc->pos || !desc->Z)) ||
-      (desc->n_enr > 0 && (!desc->enr_atom || !desc->enr_power || !desc->enr_zeta || !desc->enr_axis)))
-    return fail(OEFE_EINVAL, "inconsistent system description");
-  for (int nu = 0; nu < desc->n_enr; ++nu)
-    if (desc->enr_power[nu] < 0 || desc->enr_axis[nu] < -1 || desc->enr_axis[nu] > 2 || !(desc->enr_zeta[nu] > 0))
-      return fail(OEFE_EINVAL, "bad enrichment function parameters");
   oefe_op_s* op = new (std::nothrow) oefe_op_s();
   if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
   op->uform = true;
-  std::string err;
-  int rc = build_operator(op, desc, err);
-  if (rc == OEFE_OK && hipGetDevice(&op->device) != hipSuccess) {
-    rc = OEFE_EDEVICE;
-    err = "no HIP device";
-  }
-  if (rc == OEFE_OK) rc = upload_operator(op, err);
-  if (rc == OEFE_OK && !scratch_address(err)) rc = OEFE_EDEVICE;
-  if (rc != OEFE_OK) {
-    free_device(op);
-    delete op;
-    return fail(rc, err);
-  }
-  *out = op;
-  return OEFE_OK;
+  return finish_create(op, desc, out);
+}
+
+int oefe_op_create_adaptive(const oefe_system_desc* desc, double tol, int32_t max_depth, oefe_op* out) {
+  if (int rc = check_desc(desc, out)) return rc;
+  if (!(tol > 0.0 && tol < 1.0) || max_depth < 0 || max_depth > kAdaptMaxDepth)
+    return fail(OEFE_EINVAL, "adaptive rule: need 0 < tol < 1 and 0 <= max_depth <= 5");
+  if (desc->n_enr < 1) return fail(OEFE_EINVAL, "adaptive rule: no enrichment functions");
+  oefe_op_s* op = new (std::nothrow) oefe_op_s();
+  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  op->adaptive = true;
+  op->ad_tol = tol;
+  op->ad_depth = max_depth;
+  return finish_create(op, desc, out);
 }
 
 int oefe_op_create_diagonal(const double* lambda, int64_t n, oefe_op* out) {
@@ -1155,26 +1303,33 @@ int oefe_op_dims(oefe_op op, int64_t* dims) {
   return OEFE_OK;
 }
 
-int oefe_op_set_potential(oefe_op op, const double* V, oefe_stream stream) {
-  if (!op || !V || op->diagonal) return fail(OEFE_EINVAL, "bad arguments");
-  hipStream_t s = (hipStream_t)stream;
+// The potential parts on the device from d.V (and, with the adaptive rule, d.a_V), queued on s:
+// W V for the cell stage, H^co in every layout the kernels read, and H^oo.
+static int rebuild_potential_device(oefe_op op, hipStream_t s) {
   const int64_t nqt = op->n_cells * op->nq;
-  if (hipMemcpyAsync(op->d.V, V, (size_t)nqt * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return fail(OEFE_EDEVICE, "oefe_op_set_potential: copy of V failed");
-  if (op->vshift != 0.0)  // the periodic-function form's |k|^2/2 rides on V
-    hipLaunchKernelGGL(shift_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s, op->d.V, op->vshift, nqt);
   hipLaunchKernelGGL(wv_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s, op->d.W, op->d.V, op->d.WV,
                      op->d.WVf, nqt);
   if (op->n_enr > 0) {
+    if (op->adaptive) {
+      HcoAdapt h{};
+      h.a_w = op->d.a_w; h.a_V = op->d.a_V; h.a_leafB = op->d.a_leafB; h.phiA = op->d.phiA;
+      h.a_off = op->d.a_off; h.cf_aoff = op->d.cf_aoff; h.cf_acell = op->d.cf_acell; h.hpart = op->d.hpart;
+      h.nd = op->nd; h.P1 = op->P1; h.FMAX = op->FMAX;
+      if (op->cplx)
+        hipLaunchKernelGGL(hco_adapt_partial_kernel<true>, dim3((unsigned)op->n_cf), dim3(256), 0, s, h);
+      else
+        hipLaunchKernelGGL(hco_adapt_partial_kernel<false>, dim3((unsigned)op->n_cf), dim3(256), 0, s, h);
+    }
     HcoRebuild a{};
     a.W = op->d.W; a.V = op->d.V; a.phi = op->d.phi; a.msq = op->d.msq; a.hkin = op->d.hkin;
+    a.hpart = op->adaptive ? op->d.hpart : nullptr;
     a.rr_ptr = op->d.rr_ptr; a.rpos = op->d.rpos; a.csr2tile = op->d.csr2tile;
     a.rr_ent = op->d.rr_ent; a.cf_cell = op->d.cf_cell; a.row_blk = op->d.row_blk; a.blk_nf = op->d.blk_nf;
     a.blk_rows = op->d.blk_rows;
     a.hv = op->d.hv; a.fr_val = op->d.fr_val; a.tile_val = op->d.tile_val;
     a.hvf = op->d.hvf; a.fr_valf = op->d.fr_valf; a.tile_valf = op->d.tile_valf;
     a.n_hrows = op->n_hrows;
-    a.FMAX = op->FMAX; a.nq = op->nq; a.P1 = op->P1; a.p = op->p; a.nc = op->nc; a.n = op->n;
+    a.FMAX = op->FMAX; a.nq = op->nq; a.P1 = op->P1; a.p = op->p; a.nc = op->nc; a.n = op->n; a.nd = op->nd;
     for (int d = 0; d < 3; ++d) {
       a.ph[d][0] = op->phase[d][0];
       a.ph[d][1] = op->phase[d][1];
@@ -1186,17 +1341,59 @@ int oefe_op_set_potential(oefe_op op, const double* V, oefe_stream stream) {
       hipLaunchKernelGGL(hco_rebuild_kernel<false>, dim3(g1), dim3(256), 0, s, a, op->cd);
     const int nO = op->n_enr, nb = (int)op->blocks.size();
     const unsigned g2 = (unsigned)(((int64_t)nO * nO + 255) / 256);
-    if (op->cplx)
+    if (op->adaptive) {
+      HooAdapt o{};
+      o.a_w = op->d.a_w; o.a_V = op->d.a_V; o.phiA = op->d.phiA; o.Hoo_kin = op->d.Hoo_kin;
+      o.a_off = op->d.a_off; o.cf_aoff = op->d.cf_aoff; o.hp_ptr = op->d.hp_ptr;
+      o.cf_acell = op->d.cf_acell; o.hp_i = op->d.hp_i; o.hp_j = op->d.hp_j; o.fn_blk = op->d.fn_blk;
+      o.blk_fn0 = op->d.blk_fn0; o.Hoo = op->d.Hoo; o.Hoof = op->d.Hoof;
+      o.nO = nO; o.nb = nb; o.FMAX = op->FMAX;
+      if (op->cplx)
+        hipLaunchKernelGGL(hoo_adapt_kernel<true>, dim3(g2), dim3(256), 0, s, o);
+      else
+        hipLaunchKernelGGL(hoo_adapt_kernel<false>, dim3(g2), dim3(256), 0, s, o);
+    } else if (op->cplx) {
       hipLaunchKernelGGL(hoo_rebuild_kernel<true>, dim3(g2), dim3(256), 0, s, op->d.W, op->d.V, op->d.phi,
                          op->d.Hoo_kin, op->d.hp_ptr, op->d.hp_i, op->d.hp_j, op->d.cf_cell, op->d.fn_blk,
                          op->d.blk_fn0, nO, nb, op->FMAX, op->nq, op->d.Hoo, op->d.Hoof);
-    else
+    } else {
       hipLaunchKernelGGL(hoo_rebuild_kernel<false>, dim3(g2), dim3(256), 0, s, op->d.W, op->d.V, op->d.phi,
                          op->d.Hoo_kin, op->d.hp_ptr, op->d.hp_i, op->d.hp_j, op->d.cf_cell, op->d.fn_blk,
                          op->d.blk_fn0, nO, nb, op->FMAX, op->nq, op->d.Hoo, op->d.Hoof);
+    }
   }
   const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "oefe_op_set_potential");
+  if (e != hipSuccess) return hip_fail(e, "potential rebuild");
+  return OEFE_OK;
+}
+
+int oefe_op_set_potential(oefe_op op, const double* V, oefe_stream stream) {
+  if (!op || !V || op->diagonal) return fail(OEFE_EINVAL, "bad arguments");
+  if (op->adaptive) return fail(OEFE_EINVAL, "an operator with the adaptive rule takes V at its points too (oefe_op_set_potential_adaptive)");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nqt = op->n_cells * op->nq;
+  if (hipMemcpyAsync(op->d.V, V, (size_t)nqt * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(OEFE_EDEVICE, "oefe_op_set_potential: copy of V failed");
+  if (op->vshift != 0.0)  // the periodic-function form's |k|^2/2 rides on V
+    hipLaunchKernelGGL(shift_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s, op->d.V, op->vshift, nqt);
+  return rebuild_potential_device(op, s);
+}
+
+int oefe_op_set_potential_adaptive(oefe_op op, const double* V, const double* V_adapt, oefe_stream stream) {
+  if (!op || !V || !V_adapt || op->diagonal || !op->adaptive) return fail(OEFE_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nqt = op->n_cells * op->nq, np = op->ad_off.back();
+  if (hipMemcpyAsync(op->d.V, V, (size_t)nqt * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(op->d.a_V, V_adapt, (size_t)np * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(OEFE_EDEVICE, "oefe_op_set_potential_adaptive: copy of V failed");
+  return rebuild_potential_device(op, s);
+}
+
+int oefe_op_adaptive_points(oefe_op op, int64_t* n_points, double* xyz_host, double* w_host) {
+  if (!op || !n_points || !op->adaptive) return fail(OEFE_EINVAL, "bad arguments");
+  *n_points = op->ad_off.back();
+  if (xyz_host) std::memcpy(xyz_host, op->ad_x.data(), op->ad_x.size() * sizeof(double));
+  if (w_host) std::memcpy(w_host, op->ad_w.data(), op->ad_w.size() * sizeof(double));
   return OEFE_OK;
 }
 
@@ -1817,6 +2014,8 @@ int band_energy_grad(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int3
   if (!op || !X || !f || !E || !work || nv <= 0 || ld < nv) return fail(OEFE_EINVAL, "bad arguments");
   if (int rc = check_prec(op, prec)) return rc;
   if (op->diagonal && dE_dV) return fail(OEFE_EINVAL, "diagonal operator has no potential");
+  if (op->adaptive && dE_dV)  // V also enters at the adaptive rule's points
+    return fail(OEFE_EUNSUPPORTED, "dE/dV at the Gauss points is not the whole derivative under the adaptive rule");
   const bool cplx = op->cplx;
   const bool f32 = prec_fp32(prec);
   Layout L = layout(op, prec, nv, work);

@@ -15,6 +15,7 @@ namespace oefe {
 
 constexpr int kMaxP1 = 5;  // supported GLL nodes per edge: 3, 4, 5 (degree 2..4)
 constexpr int kTileRows = 64;  // FE rows per enrichment tile
+constexpr int kAdaptMaxDepth = 5;  // deepest subdivision of the adaptive rule (8^5 leaves per cell at most)
 
 // Enrichment coupling tiles of kTileRows FE rows, in one of two shapes chosen per operator:
 //  mode 0: 64 consecutive FE rows, g = 64 t + r;
@@ -178,6 +179,17 @@ struct DeviceArrays {
   // auxiliary-potential Poisson operator (oefe_poisson_create)
   double* bsmear = nullptr;     // smeared nuclear charge at the quadrature points [n_cells * nq]
   int64_t* blk_cf0 = nullptr;   // first flattened support cell of each block [nblk + 1]
+  // adaptive quadrature of the enrichment integrals (oefe_op_create_adaptive): the rule's
+  // points by rule cell (whole leaves of P1^3 points each), the 1D basis of every leaf, and
+  // N^O at the points of every flattened support cell
+  double* a_w = nullptr;        // weights [n_points]
+  double* a_V = nullptr;        // potential at the points [n_points]
+  double* a_leafB = nullptr;    // leaf l, direction d: ell_a(t_q) at [(l * 3 + d) * P1 + q] * P1 + a
+  int64_t* a_off = nullptr;     // rule cell -> first point [n_rule_cells + 1]
+  int32_t* cf_acell = nullptr;  // flattened support cell -> rule cell
+  int64_t* cf_aoff = nullptr;   // flattened support cell -> first row of phiA
+  double* phiA = nullptr;       // N^O: phiA[(row * FMAX + f)] (complex: x2)
+  double* hpart = nullptr;      // potential part of H^co per (flattened support cell, local node, f)
 };
 
 struct AtomBlock {
@@ -188,6 +200,10 @@ struct AtomBlock {
   std::vector<cplx> gphi;          // [ncell][nq][nf][3]
   std::vector<int32_t> rows;       // sorted FE rows where H^co is nonzero
   std::vector<cplx> hkin;          // kinetic part of H^co on rows [rows][nf]
+  // adaptive quadrature: N^O and its gradient at the rule's points of each support cell
+  std::vector<int64_t> aoff;       // support cell -> first row (its points) [ncell + 1]
+  std::vector<cplx> phiA;          // [rows][nf]
+  std::vector<cplx> gphiA;         // [rows][nf][3] (set-up only)
 };
 
 }  // namespace oefe
@@ -225,6 +241,18 @@ struct oefe_op_s {
   std::vector<oefe::cplx> Moo, Hoo_kin, Hoo, S;
   std::vector<double> Moo_eigs;
   std::vector<double> bsmear, rc_smear;  // Poisson operator: smeared charge, smearing radii
+  // adaptive quadrature of the enrichment integrals (Sec. III.B; oefe_op_create_adaptive):
+  // rule cells ascending, their points (whole leaves of P1^3 tensor Gauss points), weights,
+  // the potential there, and per leaf the 1D Lagrange values and derivatives at its points
+  bool adaptive = false;
+  double ad_tol = 0.0;
+  int ad_depth = 0;
+  std::vector<int64_t> ad_cells;    // rule cell -> mesh cell
+  std::vector<int32_t> ad_index;    // mesh cell -> rule cell or -1 [n_cells]
+  std::vector<int64_t> ad_off;      // rule cell -> first point [n_rule_cells + 1]
+  std::vector<double> ad_x, ad_w, ad_V;
+  std::vector<double> ad_B, ad_D;   // leaf l, direction d: [(l * 3 + d) * P1 + q] * P1 + a
+  int64_t n_cf = 0;                 // flattened (block, support cell) pairs
   int FMAX = 1;
   int64_t n_hrows = 0;  // total rows over blocks
   int64_t n_chunks = 0;

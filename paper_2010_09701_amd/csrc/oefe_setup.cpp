@@ -10,6 +10,7 @@
 // the same rule and the denominator the GLL mass.  Cell-level transforms are
 // sum-factorized (tensor-product 1D passes).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -304,6 +305,265 @@ struct Geo {
     for (int d = 0; d < 3; ++d) x[d] = c[d] * op->h + (op->gauss_x[qq[d]] + 1.0) * op->h / 2.0;
   }
 };
+
+// ---- adaptive quadrature of the enrichment integrals (Sec. III.B)
+//
+// Whole-space integrals A = int psi~^2 and B = int |grad psi~|^2 of an atomic function
+// psi~ = g(r) (axis < 0) or d_axis g(r), g = r^pw exp(-zeta r) h(r), after the angular
+// integration: s-type 4 pi r^2 g^2 and 4 pi r^2 g'^2; p-type 4 pi r^4 g^2 / 3 and
+// 4 pi r^2 (g^2 + 2/3 r g g' + r^2 g'^2 / 3); radial integrals by 64 panels of 20-point
+// Gauss-Legendre on [0, r1] (g vanishes beyond r1).
+void radial_scales(int pw, double zeta, int axis, double r0, double r1, double& A, double& B) {
+  constexpr int kPanels = 64, kOrder = 20;
+  double x[kOrder], w[kOrder];
+  gauss_rule(kOrder, x, w);
+  A = 0.0;
+  B = 0.0;
+  for (int k = 0; k < kPanels; ++k) {
+    const double a = r1 * k / kPanels, b = r1 * (k + 1) / kPanels;
+    for (int j = 0; j < kOrder; ++j) {
+      const double r = 0.5 * (b - a) * (x[j] + 1.0) + a, wr = 0.5 * (b - a) * w[j];
+      const double d[3] = {r, 0.0, 0.0};
+      double g, gr[3];
+      atomic_fn(d, pw, zeta, -1, r0, r1, g, gr);
+      const double gp = gr[0];
+      if (axis < 0) {
+        A += wr * 4.0 * kPi * r * r * g * g;
+        B += wr * 4.0 * kPi * r * r * gp * gp;
+      } else {
+        A += wr * 4.0 * kPi * r * r * r * r * g * g / 3.0;
+        B += wr * 4.0 * kPi * r * r * (g * g + 2.0 / 3.0 * r * g * gp + r * r * gp * gp / 3.0);
+      }
+    }
+  }
+}
+
+// Trial integrals of one box [lo, lo + size]^3 of the cell with origin org under the box's
+// tensor Gauss rule (P1 points per direction), for each function fl[j] = (atom, enrichment
+// function), psi~ at the displacement from the atom's nearest image: out[j * nt + 0] =
+// int psi~^2, [1] = int |grad psi~|^2, [2 + a] = int psi~ N_a, [2 + nd + a] =
+// int grad psi~ . grad^ N_a (grad^: the gradient in the cell's reference coordinates), a over
+// the cell's nd local nodes; nt = 2 + 2 nd.
+void box_trials(const oefe_op_s* op, const oefe_system_desc* desc, const double* xi, const double org[3],
+                const double lo[3], double size, const std::vector<std::pair<int, int>>& fl, std::vector<double>& out) {
+  const int P1 = op->P1, nd = op->nd, nt = 2 + 2 * nd;
+  const double h = op->h;
+  double t[3][8], wt[3][8], Lv[3][8][8], Ld[3][8][8];
+  for (int d = 0; d < 3; ++d)
+    for (int q = 0; q < P1; ++q) {
+      t[d][q] = lo[d] + 0.5 * size * (op->gauss_x[q] + 1.0);
+      wt[d][q] = 0.5 * size * op->gauss_w[q];
+      const double ref = 2.0 * (t[d][q] - org[d]) / h - 1.0;
+      for (int a = 0; a < P1; ++a) lagrange(P1, xi, a, ref, Lv[d][q][a], Ld[d][q][a]);
+    }
+  out.assign(fl.size() * nt, 0.0);
+  for (int qz = 0; qz < P1; ++qz)
+    for (int qy = 0; qy < P1; ++qy)
+      for (int qx = 0; qx < P1; ++qx) {
+        const double x[3] = {t[0][qx], t[1][qy], t[2][qz]};
+        const double w = wt[0][qx] * wt[1][qy] * wt[2][qz];
+        for (size_t j = 0; j < fl.size(); ++j) {
+          const int I = fl[j].first, fn = fl[j].second;
+          double dd[3];
+          for (int k = 0; k < 3; ++k) {
+            const double dr = x[k] - desc->pos[3 * I + k];
+            dd[k] = dr - op->L * std::nearbyint(dr / op->L);
+          }
+          double v, g[3];
+          atomic_fn(dd, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, v, g);
+          double* o = &out[j * nt];
+          o[0] += w * v * v;
+          o[1] += w * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+          if (v == 0.0 && g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0) continue;
+          for (int az = 0; az < P1; ++az)
+            for (int ay = 0; ay < P1; ++ay)
+              for (int ax = 0; ax < P1; ++ax) {
+                const int a = ax + P1 * (ay + P1 * az);
+                const double na = Lv[0][qx][ax] * Lv[1][qy][ay] * Lv[2][qz][az];
+                const double gn = g[0] * Ld[0][qx][ax] * Lv[1][qy][ay] * Lv[2][qz][az] +
+                                  g[1] * Lv[0][qx][ax] * Ld[1][qy][ay] * Lv[2][qz][az] +
+                                  g[2] * Lv[0][qx][ax] * Lv[1][qy][ay] * Ld[2][qz][az];
+                o[2 + a] += w * v * na;
+                o[2 + nd + a] += w * gn;
+              }
+        }
+      }
+}
+
+// A box that meets the ball of radius r1 around one of the atoms of fl (nearest image) while
+// none of its Gauss points lies inside that ball: its rule cannot see the functions there.
+bool blind_box(const oefe_op_s* op, const oefe_system_desc* desc, const std::vector<std::pair<int, int>>& fl,
+               const double lo[3], double size) {
+  const int P1 = op->P1;
+  const double r1 = desc->r1;
+  int last = -1;
+  for (const auto& pr : fl) {
+    const int I = pr.first;
+    if (I == last) continue;
+    last = I;
+    const double* R = &desc->pos[3 * I];
+    double ex2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double c = lo[k] + 0.5 * size - R[k];
+      c -= op->L * std::nearbyint(c / op->L);
+      const double ex = std::max(std::fabs(c) - 0.5 * size, 0.0);
+      ex2 += ex * ex;
+    }
+    if (!(std::sqrt(ex2) < r1)) continue;
+    bool inside = false;
+    for (int qz = 0; qz < P1 && !inside; ++qz)
+      for (int qy = 0; qy < P1 && !inside; ++qy)
+        for (int qx = 0; qx < P1 && !inside; ++qx) {
+          const int qq[3] = {qx, qy, qz};
+          double d2 = 0.0;
+          for (int k = 0; k < 3; ++k) {
+            double dr = lo[k] + 0.5 * size * (op->gauss_x[qq[k]] + 1.0) - R[k];
+            dr -= op->L * std::nearbyint(dr / op->L);
+            d2 += dr * dr;
+          }
+          inside = std::sqrt(d2) < r1;
+        }
+    if (!inside) return true;
+  }
+  return false;
+}
+
+// Leaves of one cell: a box blind to an atom's support (blind_box) is split; otherwise it is
+// kept when, for every trial integral, its own rule and the sum of its 8 half-size children's
+// rules (children in the order cx + 2 cy + 4 cz) differ by at most bound[], else its children
+// are refined in that order; at max_depth levels boxes are kept.  Leaves are appended depth
+// first as {lo_x, lo_y, lo_z, size}.
+void refine_box(const oefe_op_s* op, const oefe_system_desc* desc, const double* xi, const double org[3],
+                const std::vector<std::pair<int, int>>& fl, const std::vector<double>& bound, const double lo[3],
+                double size, int depth, std::vector<std::array<double, 4>>& leaves) {
+  if (depth == op->ad_depth) {
+    leaves.push_back({lo[0], lo[1], lo[2], size});
+    return;
+  }
+  double clo[8][3];
+  for (int c = 0; c < 8; ++c) {
+    const int off[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+    for (int d = 0; d < 3; ++d) clo[c][d] = lo[d] + 0.5 * size * off[d];
+  }
+  bool split = blind_box(op, desc, fl, lo, size);
+  if (!split) {
+    std::vector<double> own, kid, ksum;
+    box_trials(op, desc, xi, org, lo, size, fl, own);
+    ksum.assign(own.size(), 0.0);
+    for (int c = 0; c < 8; ++c) {
+      box_trials(op, desc, xi, org, clo[c], 0.5 * size, fl, kid);
+      for (size_t j = 0; j < kid.size(); ++j) ksum[j] += kid[j];
+    }
+    for (size_t j = 0; j < own.size() && !split; ++j) split = !(std::fabs(own[j] - ksum[j]) <= bound[j]);
+  }
+  if (!split) {
+    leaves.push_back({lo[0], lo[1], lo[2], size});
+    return;
+  }
+  for (int c = 0; c < 8; ++c) refine_box(op, desc, xi, org, fl, bound, clo[c], 0.5 * size, depth + 1, leaves);
+}
+
+// The adaptive rule on the union of the blocks' support cells (cells ascending): leaves, their
+// points and weights, the 1D GLL Lagrange values and derivatives at each leaf's points (in the
+// cell's reference coordinates), and the potential at the points.
+int build_adaptive_rule(oefe_op_s* op, const oefe_system_desc* desc, const double* xi, std::string& err) {
+  const int P1 = op->P1, nq = op->nq;
+  const double h = op->h;
+  std::vector<double> scaleA(op->n_enr), scaleB(op->n_enr);
+  for (int fn = 0; fn < op->n_enr; ++fn)
+    radial_scales(desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, scaleA[fn],
+                  scaleB[fn]);
+  std::vector<std::vector<std::pair<int, int>>> fns_of(op->n_cells);
+  for (auto& b : op->blocks)
+    for (int64_t e : b.cells)
+      for (int f = 0; f < b.nf; ++f) fns_of[e].push_back({b.atom, b.fn0 + f});
+  op->ad_cells.clear();
+  op->ad_index.assign(op->n_cells, -1);
+  for (int64_t e = 0; e < op->n_cells; ++e)
+    if (!fns_of[e].empty()) {
+      op->ad_index[e] = (int32_t)op->ad_cells.size();
+      op->ad_cells.push_back(e);
+    }
+  op->ad_off.assign(1, 0);
+  op->ad_x.clear();
+  op->ad_w.clear();
+  op->ad_B.clear();
+  op->ad_D.clear();
+  const int nc = op->nc;
+  // scales of the trial integrals: A, B for the quadratic ones, their Cauchy-Schwarz bounds
+  // sqrt(A v), sqrt(B v) (v = 4/3 pi r1^3) for the ones with the FE functions
+  const int nd = op->nd, nt = 2 + 2 * nd;
+  const double vol = 4.0 / 3.0 * kPi * desc->r1 * desc->r1 * desc->r1;
+  for (int64_t e : op->ad_cells) {
+    const auto& fl = fns_of[e];
+    std::vector<double> bound(nt * fl.size());
+    for (size_t j = 0; j < fl.size(); ++j) {
+      const double A = scaleA[fl[j].second], B = scaleB[fl[j].second];
+      bound[j * nt] = op->ad_tol * A;
+      bound[j * nt + 1] = op->ad_tol * B;
+      for (int a = 0; a < nd; ++a) {
+        bound[j * nt + 2 + a] = op->ad_tol * std::sqrt(A * vol);
+        bound[j * nt + 2 + nd + a] = op->ad_tol * std::sqrt(B * vol);
+      }
+    }
+    const double org[3] = {(double)(e % nc) * h, (double)((e / nc) % nc) * h, (double)(e / ((int64_t)nc * nc)) * h};
+    std::vector<std::array<double, 4>> leaves;
+    refine_box(op, desc, xi, org, fl, bound, org, h, 0, leaves);
+    for (const auto& lf : leaves) {
+      double t[3][8], wt[3][8];
+      for (int d = 0; d < 3; ++d)
+        for (int q = 0; q < P1; ++q) {
+          t[d][q] = lf[d] + 0.5 * lf[3] * (op->gauss_x[q] + 1.0);
+          wt[d][q] = 0.5 * lf[3] * op->gauss_w[q];
+          const double ref = 2.0 * (t[d][q] - org[d]) / h - 1.0;
+          for (int a = 0; a < P1; ++a) {
+            double v, dv;
+            lagrange(P1, xi, a, ref, v, dv);
+            op->ad_B.push_back(v);
+            op->ad_D.push_back(dv);
+          }
+        }
+      for (int qz = 0; qz < P1; ++qz)
+        for (int qy = 0; qy < P1; ++qy)
+          for (int qx = 0; qx < P1; ++qx) {
+            op->ad_x.push_back(t[0][qx]);
+            op->ad_x.push_back(t[1][qy]);
+            op->ad_x.push_back(t[2][qz]);
+            op->ad_w.push_back(wt[0][qx] * wt[1][qy] * wt[2][qz]);
+          }
+    }
+    op->ad_off.push_back(op->ad_off.back() + (int64_t)leaves.size() * nq);
+  }
+  const int64_t np = op->ad_off.back();
+  if (np >= (int64_t(1) << 31)) {
+    err = "adaptive rule has 2^31 points or more";
+    return OEFE_EUNSUPPORTED;
+  }
+  op->ad_V.assign(np, 0.0);
+  for (int64_t i = 0; i < np; ++i) {
+    double v = 0.0;
+    for (int I = 0; I < desc->n_atoms; ++I) {
+      double d2 = 0;
+      for (int k = 0; k < 3; ++k) {
+        double dd = op->ad_x[3 * i + k] - desc->pos[3 * I + k];
+        dd -= op->L * std::nearbyint(dd / op->L);
+        d2 += dd * dd;
+      }
+      v -= desc->Z[I] * erf_over_r(std::sqrt(d2), desc->sigma);
+    }
+    op->ad_V[i] = v;
+  }
+  return OEFE_OK;
+}
+
+// 1D matrices of leaf l in the stride-8 layout of tp_forward / tp_backward (rows: the leaf's
+// points, columns: nodes), values (D = false) or derivatives (D = true) in direction d.
+void leaf_matrix(const oefe_op_s* op, int64_t l, int d, bool D, double* M) {
+  const int P1 = op->P1;
+  const double* src = (D ? op->ad_D.data() : op->ad_B.data()) + ((size_t)l * 3 + d) * P1 * P1;
+  for (int q = 0; q < P1; ++q)
+    for (int a = 0; a < P1; ++a) M[q * 8 + a] = src[q * P1 + a];
+}
 
 }  // namespace
 
@@ -620,6 +880,19 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
     }
     for (int64_t e = 0; e < op->n_cells; ++e)
       if (sup[e]) b.cells.push_back(e);
+  }
+  // ---- adaptive quadrature of the enrichment integrals: the rule on the union of the supports
+  const bool ad = op->adaptive;
+  if (ad) {
+    if (pois || uf) {
+      err = "adaptive quadrature is built for the Kohn-Sham operator in the Bloch-function form";
+      return OEFE_EUNSUPPORTED;
+    }
+    if (int rc = build_adaptive_rule(op, desc, xi, err)) return rc;
+  }
+  const int nq3 = nq;
+  for (auto& b : op->blocks) {
+    const double* R = &desc->pos[3 * b.atom];
     const int nf = b.nf;
     const size_t ncb = b.cells.size();
     // N^A and grad N^A at the quadrature points of the support cells
@@ -655,10 +928,69 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
         }
       }
     }
-    // d_g = sum_{(e,a)->g} conj(theta_ea) sum_q W B[q,a] N^A ; c_g = d_g / m_g
+    // adaptive rule: N^A and grad N^A at the rule's points of the support cells
+    std::vector<cplx> NAa, gNAa;
+    if (ad) {
+      b.aoff.assign(ncb + 1, 0);
+      for (size_t ci = 0; ci < ncb; ++ci) {
+        const int32_t k = op->ad_index[b.cells[ci]];
+        b.aoff[ci + 1] = b.aoff[ci] + (op->ad_off[k + 1] - op->ad_off[k]);
+      }
+      NAa.assign((size_t)b.aoff[ncb] * nf, cplx(0, 0));
+      gNAa.assign((size_t)b.aoff[ncb] * nf * 3, cplx(0, 0));
+      for (size_t ci = 0; ci < ncb; ++ci) {
+        const int32_t k = op->ad_index[b.cells[ci]];
+        for (int64_t i = op->ad_off[k]; i < op->ad_off[k + 1]; ++i) {
+          const int64_t row = b.aoff[ci] + (i - op->ad_off[k]);
+          double d[3], t[3];
+          for (int kk = 0; kk < 3; ++kk) {
+            const double dr = op->ad_x[3 * i + kk] - R[kk];
+            t[kk] = std::nearbyint(dr / op->L);
+            d[kk] = dr - op->L * t[kk];
+          }
+          cplx ph(1.0, 0.0);
+          if (op->cplx) {
+            const double arg = op->L * (op->kvec[0] * t[0] + op->kvec[1] * t[1] + op->kvec[2] * t[2]);
+            ph = cplx(std::cos(arg), std::sin(arg));
+          }
+          for (int f = 0; f < nf; ++f) {
+            const int fn = b.fn0 + f;
+            double val, gr[3];
+            atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
+            NAa[(size_t)row * nf + f] = ph * val;
+            for (int kk = 0; kk < 3; ++kk) gNAa[((size_t)row * nf + f) * 3 + kk] = ph * gr[kk];
+          }
+        }
+      }
+    }
+    // d_g = sum_{(e,a)->g} conj(theta_ea) sum_q W B[q,a] N^A ; c_g = d_g / m_g (the adaptive
+    // rule's points and weights in place of the cell's Gauss rule when it is in use)
     dacc.assign((size_t)op->N * nf, cplx(0, 0));
     std::vector<cplx> tin(nq), tout(nq);
-    for (size_t ci = 0; ci < ncb; ++ci) {
+    for (size_t ci = 0; ad && ci < ncb; ++ci) {
+      const int64_t e = b.cells[ci];
+      const int32_t k = op->ad_index[e];
+      for (int f = 0; f < nf; ++f) {
+        std::vector<cplx> acc(op->nd, cplx(0, 0));
+        for (int64_t l = op->ad_off[k] / nq3; l < op->ad_off[k + 1] / nq3; ++l) {
+          double Mx[64], My[64], Mz[64];
+          leaf_matrix(op, l, 0, false, Mx);
+          leaf_matrix(op, l, 1, false, My);
+          leaf_matrix(op, l, 2, false, Mz);
+          const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
+          for (int q = 0; q < nq; ++q) tin[q] = op->ad_w[l * nq3 + q] * NAa[(size_t)(row0 + q) * nf + f];
+          tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
+          for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+        }
+        for (int a = 0; a < op->nd; ++a) {
+          int64_t g;
+          cplx th;
+          geo.dof(e, a, g, th);
+          dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
+        }
+      }
+    }
+    for (size_t ci = 0; !ad && ci < ncb; ++ci) {
       int64_t e = b.cells[ci];
       for (int f = 0; f < nf; ++f) {
         for (int q = 0; q < nq; ++q) tin[q] = op->W[e * nq + q] * NA[(ci * nq + q) * nf + f];
@@ -696,6 +1028,40 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
         }
       }
     }
+    // adaptive rule: N^O and grad N^O at its points with the same coefficients
+    if (ad) {
+      b.phiA.assign((size_t)b.aoff[ncb] * nf, cplx(0, 0));
+      b.gphiA.assign((size_t)b.aoff[ncb] * nf * 3, cplx(0, 0));
+      for (size_t ci = 0; ci < ncb; ++ci) {
+        const int64_t e = b.cells[ci];
+        const int32_t k = op->ad_index[e];
+        for (int f = 0; f < nf; ++f) {
+          for (int a = 0; a < op->nd; ++a) {
+            int64_t g;
+            cplx th;
+            geo.dof(e, a, g, th);
+            ce[a] = th * (dacc[(size_t)g * nf + f] / op->mdiag[g]);
+          }
+          for (int64_t l = op->ad_off[k] / nq3; l < op->ad_off[k + 1] / nq3; ++l) {
+            double Bx[64], By[64], Bz[64], Dx[64], Dy[64], Dz[64];
+            leaf_matrix(op, l, 0, false, Bx);
+            leaf_matrix(op, l, 1, false, By);
+            leaf_matrix(op, l, 2, false, Bz);
+            leaf_matrix(op, l, 0, true, Dx);
+            leaf_matrix(op, l, 1, true, Dy);
+            leaf_matrix(op, l, 2, true, Dz);
+            const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
+            tp_forward<cplx>(P1, Bx, By, Bz, ce.data(), o.data());
+            for (int q = 0; q < nq; ++q) b.phiA[(size_t)(row0 + q) * nf + f] = NAa[(size_t)(row0 + q) * nf + f] - o[q];
+            for (int dd = 0; dd < 3; ++dd) {
+              tp_forward<cplx>(P1, dd == 0 ? Dx : Bx, dd == 1 ? Dy : By, dd == 2 ? Dz : Bz, ce.data(), o.data());
+              for (int q = 0; q < nq; ++q)
+                b.gphiA[((size_t)(row0 + q) * nf + f) * 3 + dd] = gNAa[((size_t)(row0 + q) * nf + f) * 3 + dd] - s2h * o[q];
+            }
+          }
+        }
+      }
+    }
     // rows of H^co: all FE nodes of the support cells
     touched.assign(op->N, 0);
     for (size_t ci = 0; ci < ncb; ++ci)
@@ -708,9 +1074,38 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
     b.rows.clear();
     for (int64_t g = 0; g < op->N; ++g)
       if (touched[g]) b.rows.push_back((int32_t)g);
-    // kinetic part of H^co: sum_q W kin (2/h) G_d[q,a] dPhi_d
+    // kinetic part of H^co: sum_q W kin (2/h) G_d[q,a] dPhi_d (the adaptive rule's points when in use)
     dacc.assign((size_t)op->N * nf, cplx(0, 0));
-    for (size_t ci = 0; ci < ncb; ++ci) {
+    for (size_t ci = 0; ad && ci < ncb; ++ci) {
+      const int64_t e = b.cells[ci];
+      const int32_t k = op->ad_index[e];
+      for (int f = 0; f < nf; ++f) {
+        std::vector<cplx> acc(op->nd, cplx(0, 0));
+        for (int64_t l = op->ad_off[k] / nq3; l < op->ad_off[k + 1] / nq3; ++l) {
+          double Bx[64], By[64], Bz[64], Dx[64], Dy[64], Dz[64];
+          leaf_matrix(op, l, 0, false, Bx);
+          leaf_matrix(op, l, 1, false, By);
+          leaf_matrix(op, l, 2, false, Bz);
+          leaf_matrix(op, l, 0, true, Dx);
+          leaf_matrix(op, l, 1, true, Dy);
+          leaf_matrix(op, l, 2, true, Dz);
+          const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
+          for (int dd = 0; dd < 3; ++dd) {
+            for (int q = 0; q < nq; ++q)
+              tin[q] = kin * s2h * op->ad_w[l * nq3 + q] * b.gphiA[((size_t)(row0 + q) * nf + f) * 3 + dd];
+            tp_backward<cplx>(P1, dd == 0 ? Dx : Bx, dd == 1 ? Dy : By, dd == 2 ? Dz : Bz, tin.data(), tout.data());
+            for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+          }
+        }
+        for (int a = 0; a < op->nd; ++a) {
+          int64_t g;
+          cplx th;
+          geo.dof(e, a, g, th);
+          dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
+        }
+      }
+    }
+    for (size_t ci = 0; !ad && ci < ncb; ++ci) {
       int64_t e = b.cells[ci];
       for (int f = 0; f < nf; ++f) {
         std::vector<cplx> acc(op->nd, cplx(0, 0));
@@ -757,6 +1152,29 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
         if (bi.cells[i] < bj.cells[j]) { ++i; continue; }
         if (bi.cells[i] > bj.cells[j]) { ++j; continue; }
         int64_t e = bi.cells[i];
+        if (ad) {  // the adaptive rule's points of cell e (the same rows for both blocks' functions)
+          const int32_t k = op->ad_index[e];
+          const int64_t npt = op->ad_off[k + 1] - op->ad_off[k];
+          for (int64_t pt = 0; pt < npt; ++pt) {
+            const double Wq = op->ad_w[op->ad_off[k] + pt];
+            const int64_t ri = bi.aoff[i] + pt, rj = bj.aoff[j] + pt;
+            for (int f = 0; f < bi.nf; ++f) {
+              const cplx a = std::conj(bi.phiA[(size_t)ri * bi.nf + f]);
+              const cplx* ga = &bi.gphiA[((size_t)ri * bi.nf + f) * 3];
+              for (int g2 = 0; g2 < bj.nf; ++g2) {
+                const cplx bb = bj.phiA[(size_t)rj * bj.nf + g2];
+                const cplx* gb = &bj.gphiA[((size_t)rj * bj.nf + g2) * 3];
+                const size_t ix = (size_t)(bi.fn0 + f) * nO + (bj.fn0 + g2);
+                op->Moo[ix] += Wq * a * bb;
+                op->Hoo_kin[ix] +=
+                    kin * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
+              }
+            }
+          }
+          ++i;
+          ++j;
+          continue;
+        }
         for (int q = 0; q < nq; ++q) {
           double Wq = op->W[e * nq + q];
           for (int f = 0; f < bi.nf; ++f) {
@@ -781,6 +1199,7 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
         ++j;
       }
     }
+  for (auto& b : op->blocks) std::vector<cplx>().swap(b.gphiA);  // set-up only
   // ---- S = (M^oo)^-1/2; for the Poisson operator the block's own metric is A^oo, so that
   // S A^oo S = I (the enrichment rows' Jacobi factor of the preconditioned Laplacian)
   if (pois) op->Moo = op->Hoo_kin;

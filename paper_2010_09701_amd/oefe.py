@@ -59,6 +59,9 @@ def _load():
         "oefe_op_create": ([ctypes.POINTER(_Desc), ctypes.POINTER(vp)], i32),
         "oefe_op_create_diagonal": ([vp, i64, ctypes.POINTER(vp)], i32),
         "oefe_op_create_uform": ([vp, ctypes.POINTER(vp)], i32),
+        "oefe_op_create_adaptive": ([vp, dbl, i32, ctypes.POINTER(vp)], i32),
+        "oefe_op_adaptive_points": ([vp, vp, vp, vp], i32),
+        "oefe_op_set_potential_adaptive": ([vp, vp, vp, vp], i32),
         "oefe_op_destroy": ([vp], i32),
         "oefe_op_dims": ([vp, vp], i32),
         "oefe_op_set_potential": ([vp, vp, vp], i32),
@@ -101,7 +104,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = [
-    "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_create_uform", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
+    "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_create_uform", "oefe_op_create_adaptive",
+    "oefe_op_adaptive_points", "oefe_op_set_potential_adaptive", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
     "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
     "oefe_autotune",
@@ -151,12 +155,15 @@ class Operator:
     """Device-resident OEFE operator (or a diagonal test operator)."""
 
     def __init__(self, system: Optional[workloads.System] = None, _handle=None, poisson: bool = False,
-                 uform: bool = False):
+                 uform: bool = False, adaptive=None):
         """poisson: the operator of the auxiliary-potential Poisson problem on the system's mesh and
         atoms (oefe_poisson_create) instead of the Kohn-Sham operator; uform: the k-point operator
-        in the periodic-function form (oefe_op_create_uform; the system needs a wavevector)."""
+        in the periodic-function form (oefe_op_create_uform; the system needs a wavevector);
+        adaptive = (tol, max_depth): the Kohn-Sham operator with the enrichment integrals on the
+        adaptive rule (oefe_op_create_adaptive)."""
         self._h = ctypes.c_void_p(0)
         self.is_poisson = poisson
+        self.is_adaptive = adaptive is not None
         if _handle is not None:
             self._h = _handle
         else:
@@ -178,6 +185,10 @@ class Operator:
                 _check(_lib.oefe_poisson_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_poisson_create")
             elif uform:
                 _check(_lib.oefe_op_create_uform(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create_uform")
+            elif adaptive is not None:
+                tol, depth = adaptive
+                _check(_lib.oefe_op_create_adaptive(ctypes.byref(d), float(tol), int(depth), ctypes.byref(self._h)),
+                       "oefe_op_create_adaptive")
             else:
                 _check(_lib.oefe_op_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create")
         dims = (ctypes.c_int64 * 11)()
@@ -243,17 +254,40 @@ class Operator:
         _check(_lib.oefe_kernel_timer_read(self._h, ctypes.byref(n), ctypes.byref(ms)), "oefe_kernel_timer_read")
         return int(n.value), float(ms.value)
 
-    def set_potential(self, V):
-        """Replace V at the quadrature points ([n_cells, nq] numpy array or torch tensor); the operator
+    def set_potential(self, V, V_adapt=None):
+        """Replace V at the quadrature points ([n_cells, nq] numpy array or torch tensor) and, for an
+        operator with the adaptive rule, V_adapt at the rule's points ([n_points]); the operator
         data that depend on V are rebuilt on the device, on torch's current stream."""
-        if isinstance(V, torch.Tensor):
-            Vd = V.detach().to(device="cuda", dtype=torch.float64).contiguous().reshape(-1)
-        else:
-            Vd = torch.from_numpy(np.ascontiguousarray(V, dtype=np.float64).ravel()).cuda()
+        def dev(a):
+            if isinstance(a, torch.Tensor):
+                return a.detach().to(device="cuda", dtype=torch.float64).contiguous().reshape(-1)
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+        Vd = dev(V)
         if Vd.numel() != self.n_cells * self.nq:
             raise ValueError("V must have n_cells * nq entries")
-        _check(_lib.oefe_op_set_potential(self._h, _ptr(Vd), _stream()), "oefe_op_set_potential")
-        self._keep_V = Vd  # held until the queued rebuild has read it (the next call replaces it)
+        if V_adapt is None:
+            _check(_lib.oefe_op_set_potential(self._h, _ptr(Vd), _stream()), "oefe_op_set_potential")
+            self._keep_V = Vd  # held until the queued rebuild has read it (the next call replaces it)
+            return
+        Va = dev(V_adapt)
+        n, _, _ = self.adaptive_points(coords=False)
+        if Va.numel() != n:
+            raise ValueError("V_adapt must have one entry per point of the adaptive rule")
+        _check(_lib.oefe_op_set_potential_adaptive(self._h, _ptr(Vd), _ptr(Va), _stream()),
+               "oefe_op_set_potential_adaptive")
+        self._keep_V = (Vd, Va)
+
+    def adaptive_points(self, coords: bool = True):
+        """(n_points, xyz [n, 3], weights [n]) of the adaptive rule (host arrays; None without coords)."""
+        n = ctypes.c_int64(0)
+        _check(_lib.oefe_op_adaptive_points(self._h, ctypes.byref(n), None, None), "oefe_op_adaptive_points")
+        if not coords:
+            return int(n.value), None, None
+        xyz = np.empty((n.value, 3))
+        w = np.empty(n.value)
+        _check(_lib.oefe_op_adaptive_points(self._h, ctypes.byref(n), xyz.ctypes.data_as(ctypes.c_void_p),
+                                            w.ctypes.data_as(ctypes.c_void_p)), "oefe_op_adaptive_points")
+        return int(n.value), xyz, w
 
     def get_potential(self):
         V = np.empty(self.n_cells * self.nq)
