@@ -425,6 +425,66 @@ def diamond8_extra(oefe, wl, torch, reps):
     return out, gop
 
 
+def adaptive_bench(oefe, wl, torch, reps):
+    """diamond8 with the enrichment integrals on the adaptive rule (Sec. III.B): set-up time and
+    rule size, the device rebuild of the potential parts (oefe_op_set_potential_adaptive) against
+    the Gauss-rule operator's (oefe_op_set_potential), the filter (the same kernels), and five
+    float64 passes' Ritz values of the Gauss rule and two adaptive rules (tol 1e-6 / depth 2 and
+    tol 1e-7 / depth 3) against each other."""
+    from paper_2010_09701_amd.chfsi import chfsi_run
+    cfg = wl.config("diamond8")
+    specs = (("gauss", None), ("tol1e-6_d2", (1e-6, 2)), ("tol1e-7_d3", (1e-7, 3)))
+    res = {"unit_ritz": "Ha", "rules": {}}
+    thetas = {}
+    n_occ = cfg.nv - 16
+    for name, spec in specs:
+        t = time.time()
+        op = oefe.Operator(cfg.system, adaptive=spec)
+        torch.cuda.synchronize()
+        setup_s = time.time() - t
+        rec = {"setup_s": setup_s}
+        if spec is not None:
+            n, _, _ = op.adaptive_points(coords=False)
+            rec.update({"tol": spec[0], "max_depth": spec[1], "points": n,
+                        "gauss_points_same_cells": op.n_cells * op.nq})
+        X0 = torch.from_numpy(wl.start_block(op.n_tot, cfg.nv, cfg.x0_seed)).cuda()
+        v0 = torch.from_numpy(wl.lanczos_start(op.n_tot, cfg.v0_seed)).cuda()
+        a0L, b, a1 = oefe.lanczos_bounds(op, v0, cfg.lanczos_k, with_cut=True)
+        r = chfsi_run(op, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k, "f64", bounds=(a0L, b, a1))
+        thetas[name] = r["passes"][-1]["theta"][:n_occ]
+        rec["filter_ms"] = median_filter_ms(oefe, torch, op, X0, cfg.m, (a1, b, a0L), max(3, reps // 3))
+        # the potential rebuild on the device (after the passes: it replaces V)
+        V, _ = op.get_potential()
+        Vd = torch.from_numpy(np.ascontiguousarray(V.ravel())).cuda()
+        Va = None
+        if spec is not None:
+            Va = torch.full((rec["points"],), -1.0, dtype=torch.float64, device="cuda")
+        op.set_potential(Vd, Va)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op.set_potential(Vd, Va)
+        e1.record()
+        torch.cuda.synchronize()
+        rec["set_potential_ms"] = e0.elapsed_time(e1) / reps
+        res["rules"][name] = rec
+        log(f"diamond8 {name}: set-up {setup_s:.1f} s, " + (f"{rec['points']} rule points, " if spec else "")
+            + f"filter {rec['filter_ms']:.2f} ms, potential rebuild {rec['set_potential_ms']:.2f} ms, "
+              f"lowest Ritz value {thetas[name][0]:.6f}")
+        del op
+        torch.cuda.empty_cache()
+    res["ritz_diff_pass5_Ha"] = {
+        "adaptive_d2_vs_gauss": float(np.abs(thetas["tol1e-6_d2"] - thetas["gauss"]).max()),
+        "adaptive_d3_vs_d2": float(np.abs(thetas["tol1e-7_d3"] - thetas["tol1e-6_d2"]).max()),
+        "lowest": {k: float(v[0]) for k, v in thetas.items()},
+        "states": n_occ}
+    log(f"diamond8 adaptive rule: occupied Ritz values d2 vs Gauss {res['ritz_diff_pass5_Ha']['adaptive_d2_vs_gauss']:.3e} Ha, "
+        f"d3 vs d2 {res['ritz_diff_pass5_Ha']['adaptive_d3_vs_d2']:.3e} Ha")
+    return res
+
+
 def profile_run(oefe, wl, torch, cfg, args):
     """Counter-collection run: one float64 filter (and the diamond8 extras) without timing."""
     gop = oefe.Operator(cfg.system)
@@ -692,6 +752,7 @@ def main():
         if not args.no_kpoints:
             cfg8 = wl.config("diamond8")
             extra["kpoints"] = kpoint_bench(oefe, wl, torch, cfg8.system, cfg8.m, 3)
+        extra["adaptive_quadrature"] = adaptive_bench(oefe, wl, torch, reps)
     copy_gbs = None
     if not args.no_copy_bw and not args.calib_copy:  # (the counter calibration takes the largest copy)
         copy_gbs = copy_bandwidth(oefe, torch)

@@ -562,9 +562,10 @@ int upload_operator(oefe_op_s* op, std::string& err) {
         if ((rc = dput(&op->d.cf_acell, cf_acell, err))) return rc;
         if ((rc = dput(&op->d.cf_aoff, cf_aoff, err))) return rc;
         if ((rc = dput(&op->d.phiA, phiA, err))) return rc;
-        if ((rc = dalloc(&op->d.hpart, (size_t)boff[nb] * op->nd * op->FMAX * E, err))) return rc;
-        op->n_cf = boff[nb];
       }
+      // partials of the potential part of H^co per (flattened support cell, local node, function)
+      if ((rc = dalloc(&op->d.hpart, (size_t)boff[nb] * op->nd * op->FMAX * E, err))) return rc;
+      op->n_cf = boff[nb];
     }
     if ((rc = dput(&op->d.blk_fn0, fn0, err))) return rc;
     if ((rc = dput(&op->d.blk_nf, nf, err))) return rc;
@@ -690,80 +691,140 @@ struct HcoRebuild {
   double ph[3][2];
 };
 
-// Adaptive rule (Sec. III.B): the potential part of H^co per (flattened support cell cf, local
-// node a, function f), sum over the cell's rule points x of ell_a(x) w V(x) N^O_f(x), ell_a(x)
-// the product of the point's leaf's 1D Lagrange values; one workgroup per cf, each thread a
-// strided share of the (a, f) items, the points in rule order (fixed summation order).
-struct HcoAdapt {
-  const double *a_w, *a_V, *a_leafB, *phiA;
+// The potential part of H^co per (flattened support cell cf, local node a, function f): the sum
+// over the cell's quadrature points x of ell_a(x) w V(x) N^O_f(x), over the cell's Gauss points or
+// the leaves of the adaptive rule (Sec. III.B).  Per leaf: w V N^O staged in LDS, then the
+// tensor contractions with the leaf's 1D Lagrange values, x, y, z in turn; one workgroup per cf
+// accumulating its (a, f) items over the leaves in rule order (a fixed summation order).
+struct HcoPart {
+  const double *W, *V, *phi;  // the Gauss rule: weights, potential, N^O [cf][nq][FMAX]
+  const int32_t* cf_cell;
+  const double *a_w, *a_V, *a_leafB, *phiA;  // the adaptive rule (a_off null: the Gauss rule)
   const int64_t *a_off, *cf_aoff;
   const int32_t* cf_acell;
   double* hpart;
   int nd, P1, FMAX;
 };
 
+constexpr int kHcoItemsPerThread = 4;  // nd FMAX <= 125 * 8 items over 256 threads
+
 template <bool CPLX>
-__global__ __launch_bounds__(256) void hco_adapt_partial_kernel(HcoAdapt a) {
+__global__ __launch_bounds__(256) void hco_partial_kernel(HcoPart a, CellCoef<double> cd) {
   constexpr int E = CPLX ? 2 : 1;
+  constexpr int kQ = kMaxP1 * kMaxP1 * kMaxP1;
+  __shared__ double T[kQ * 8 * E], U[kQ * 8 * E];
+  __shared__ double Bl[3][kMaxP1][kMaxP1];
   const int64_t cf = blockIdx.x;
-  const int k = a.cf_acell[cf];
-  const int P1 = a.P1, nq3 = P1 * P1 * P1;
-  const int64_t p0 = a.a_off[k], l0 = p0 / nq3, l1 = a.a_off[k + 1] / nq3, r0 = a.cf_aoff[cf];
-  for (int it = threadIdx.x; it < a.nd * a.FMAX; it += blockDim.x) {
-    const int an = it / a.FMAX, f = it - an * a.FMAX;
-    const int ax = an % P1, ay = (an / P1) % P1, az = an / (P1 * P1);
-    double sr = 0.0, si = 0.0;
-    for (int64_t l = l0; l < l1; ++l) {
-      const double* lb = a.a_leafB + l * 3 * P1 * P1;
-      const int64_t gl = l * nq3, rl = r0 + (gl - p0);
-      int qi = 0;
-      for (int qz = 0; qz < P1; ++qz)
-        for (int qy = 0; qy < P1; ++qy) {
-          const double byz = lb[(P1 + qy) * P1 + ay] * lb[(2 * P1 + qz) * P1 + az];
-          for (int qx = 0; qx < P1; ++qx, ++qi) {
-            const double wv = lb[qx * P1 + ax] * byz * (a.a_w[gl + qi] * a.a_V[gl + qi]);
-            const double* ph = a.phiA + ((rl + qi) * a.FMAX + f) * E;
-            sr += wv * ph[0];
-            if (CPLX) si += wv * ph[1];
-          }
-        }
+  const int P1 = a.P1, nq = P1 * P1 * P1, F = a.FMAX;
+  const int nitem = nq * F;  // (point or node, function)
+  const bool adapt = a.a_off != nullptr;
+  int64_t l0 = 0, l1 = 1, p0 = 0, r0 = cf * nq;
+  int64_t e = 0;
+  if (adapt) {
+    const int k = a.cf_acell[cf];
+    p0 = a.a_off[k];
+    l0 = p0 / nq;
+    l1 = a.a_off[k + 1] / nq;
+    r0 = a.cf_aoff[cf];
+  } else {
+    e = a.cf_cell[cf];
+  }
+  double acc[kHcoItemsPerThread][E];
+  for (int j = 0; j < kHcoItemsPerThread; ++j)
+    for (int c = 0; c < E; ++c) acc[j][c] = 0.0;
+  for (int64_t l = l0; l < l1; ++l) {
+    __syncthreads();  // the previous leaf's last reads of T and Bl are done
+    for (int i = threadIdx.x; i < 3 * P1 * P1; i += blockDim.x) {
+      const int d = i / (P1 * P1), q = (i / P1) % P1, an = i % P1;
+      Bl[d][q][an] = adapt ? a.a_leafB[((l * 3 + d) * P1 + q) * P1 + an] : cd.B1[q][an];
     }
-    double* o = a.hpart + ((cf * a.nd + an) * a.FMAX + f) * E;
-    o[0] = sr;
-    if (CPLX) o[1] = si;
+    for (int i = threadIdx.x; i < nitem; i += blockDim.x) {
+      const int q = i / F, f = i - q * F;
+      double wv;
+      const double* ph;
+      if (adapt) {
+        const int64_t gp = l * nq + q;
+        wv = a.a_w[gp] * a.a_V[gp];
+        ph = a.phiA + ((r0 + (gp - p0)) * F + f) * E;
+      } else {
+        wv = a.W[e * nq + q] * a.V[e * nq + q];
+        ph = a.phi + ((r0 + q) * F + f) * E;
+      }
+      T[i * E] = wv * ph[0];
+      if (CPLX) T[i * E + 1] = wv * ph[1];
+    }
+    __syncthreads();
+    // x: U[(qz, qy, ax), f] = sum_qx B[qx][ax] T[(qz, qy, qx), f]
+    for (int i = threadIdx.x; i < nitem; i += blockDim.x) {
+      const int idx = i / F, f = i - idx * F;
+      const int ax = idx % P1, qyz = idx / P1;
+      double sr = 0.0, si = 0.0;
+      for (int qx = 0; qx < P1; ++qx) {
+        const double b = Bl[0][qx][ax];
+        const int j = ((qyz * P1 + qx) * F + f) * E;
+        sr += b * T[j];
+        if (CPLX) si += b * T[j + 1];
+      }
+      U[i * E] = sr;
+      if (CPLX) U[i * E + 1] = si;
+    }
+    __syncthreads();
+    // y: T[(qz, ay, ax), f] = sum_qy B[qy][ay] U[(qz, qy, ax), f]
+    for (int i = threadIdx.x; i < nitem; i += blockDim.x) {
+      const int idx = i / F, f = i - idx * F;
+      const int ax = idx % P1, ay = (idx / P1) % P1, qz = idx / (P1 * P1);
+      double sr = 0.0, si = 0.0;
+      for (int qy = 0; qy < P1; ++qy) {
+        const double b = Bl[1][qy][ay];
+        const int j = (((qz * P1 + qy) * P1 + ax) * F + f) * E;
+        sr += b * U[j];
+        if (CPLX) si += b * U[j + 1];
+      }
+      T[i * E] = sr;
+      if (CPLX) T[i * E + 1] = si;
+    }
+    __syncthreads();
+    // z: acc[(az, ay, ax), f] += sum_qz B[qz][az] T[(qz, ay, ax), f]
+    int slot = 0;
+    for (int i = threadIdx.x; i < nitem; i += blockDim.x, ++slot) {
+      const int idx = i / F, f = i - idx * F;
+      const int ax = idx % P1, ay = (idx / P1) % P1, az = idx / (P1 * P1);
+      double sr = 0.0, si = 0.0;
+      for (int qz = 0; qz < P1; ++qz) {
+        const double b = Bl[2][qz][az];
+        const int j = (((qz * P1 + ay) * P1 + ax) * F + f) * E;
+        sr += b * T[j];
+        if (CPLX) si += b * T[j + 1];
+      }
+      acc[slot][0] += sr;
+      if (CPLX) acc[slot][E - 1] += si;
+    }
+  }
+  int slot = 0;
+  for (int i = threadIdx.x; i < nitem; i += blockDim.x, ++slot) {
+    double* o = a.hpart + (cf * nitem + i) * E;  // (cf, local node, f): nitem = nd FMAX
+    o[0] = acc[slot][0];
+    if (CPLX) o[1] = acc[slot][E - 1];
   }
 }
 
 template <bool CPLX>
-__global__ __launch_bounds__(256) void hco_rebuild_kernel(HcoRebuild a, CellCoef<double> cd) {
+__global__ __launch_bounds__(256) void hco_rebuild_kernel(HcoRebuild a) {
   constexpr int E = CPLX ? 2 : 1;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_hrows * a.FMAX) return;
   const int64_t R = t / a.FMAX;
   const int f = (int)(t - R * a.FMAX);
   if (f >= a.blk_nf[a.row_blk[R]]) return;
-  const int P1 = a.P1, nq = a.nq;
+  const int P1 = a.P1;
   double sr = 0.0, si = 0.0;
   for (int64_t k = a.rr_ptr[R]; k < a.rr_ptr[R + 1]; ++k) {
     const int cf = a.rr_ent[k] >> 7, an = a.rr_ent[k] & 127;
     const int e = a.cf_cell[cf];
     const int ax = an % P1, ay = (an / P1) % P1, az = an / (P1 * P1);
-    double vr = 0.0, vi = 0.0;
-    if (a.hpart) {  // adaptive rule: the partial of this (support cell, node, function)
-      const double* hp = a.hpart + (((int64_t)cf * a.nd + an) * a.FMAX + f) * E;
-      vr = hp[0];
-      if (CPLX) vi = hp[1];
-    } else {
-      const double* Wc = a.W + (int64_t)e * nq;
-      const double* Vc = a.V + (int64_t)e * nq;
-      const double* pc = a.phi + ((int64_t)cf * nq * a.FMAX + f) * E;
-      for (int q = 0; q < nq; ++q) {
-        const int qx = q % P1, qy = (q / P1) % P1, qz = q / (P1 * P1);
-        const double w = cd.B1[qx][ax] * cd.B1[qy][ay] * cd.B1[qz][az] * (Wc[q] * Vc[q]);
-        vr += w * pc[(int64_t)q * a.FMAX * E];
-        if (CPLX) vi += w * pc[(int64_t)q * a.FMAX * E + 1];
-      }
-    }
+    // the partial of this (support cell, local node, function) (hco_partial_kernel)
+    const double* hp = a.hpart + (((int64_t)cf * a.nd + an) * a.FMAX + f) * E;
+    const double vr = hp[0], vi = CPLX ? hp[1] : 0.0;
     if constexpr (CPLX) {
       // conj(theta) of the periodic image the node is reached through
       const int cx = e % a.nc, cy = (e / a.nc) % a.nc, cz = e / (a.nc * a.nc);
@@ -802,87 +863,82 @@ __global__ __launch_bounds__(256) void hco_rebuild_kernel(HcoRebuild a, CellCoef
   }
 }
 
-// H^oo = kinetic part + sum over the common support cells (ascending) and quadrature points of
-// W V conj(N^O_i) N^O_j; one thread per entry (i, j)
-template <bool CPLX>
-__global__ __launch_bounds__(256) void hoo_rebuild_kernel(const double* __restrict__ W, const double* __restrict__ V,
-                                                          const double* __restrict__ phi, const double* __restrict__ Hoo_kin,
-                                                          const int64_t* __restrict__ hp_ptr, const int32_t* __restrict__ hp_i,
-                                                          const int32_t* __restrict__ hp_j, const int32_t* __restrict__ cf_cell,
-                                                          const int32_t* __restrict__ fn_blk, const int32_t* __restrict__ blk_fn0,
-                                                          int nO, int nb, int FMAX, int nq, double* __restrict__ Hoo,
-                                                          float* __restrict__ Hoof) {
-  constexpr int E = CPLX ? 2 : 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nO * nO) return;
-  const int i = t / nO, j = t - i * nO;
-  const int bi = fn_blk[i], bj = fn_blk[j];
-  const int f = i - blk_fn0[bi], g = j - blk_fn0[bj];
-  double sr = Hoo_kin[(int64_t)t * E], si = CPLX ? Hoo_kin[(int64_t)t * E + 1] : 0.0;
-  const int64_t pr = (int64_t)bi * nb + bj;
-  for (int64_t k = hp_ptr[pr]; k < hp_ptr[pr + 1]; ++k) {
-    const int ci = hp_i[k], cj = hp_j[k];
-    const int e = cf_cell[ci];
-    const double* pa = phi + ((int64_t)ci * nq * FMAX + f) * E;
-    const double* pb = phi + ((int64_t)cj * nq * FMAX + g) * E;
-    for (int q = 0; q < nq; ++q) {
-      const double wv = W[(int64_t)e * nq + q] * V[(int64_t)e * nq + q];
-      const double ar = pa[(int64_t)q * FMAX * E], ai = CPLX ? -pa[(int64_t)q * FMAX * E + 1] : 0.0;
-      const double br = pb[(int64_t)q * FMAX * E], bim = CPLX ? pb[(int64_t)q * FMAX * E + 1] : 0.0;
-      const double xr = wv * ar, xi = wv * ai;
-      sr += xr * br - xi * bim;
-      if (CPLX) si += xr * bim + xi * br;
-    }
-  }
-  Hoo[(int64_t)t * E] = sr;
-  Hoof[(int64_t)t * E] = (float)sr;
-  if (CPLX) {
-    Hoo[(int64_t)t * E + 1] = si;
-    Hoof[(int64_t)t * E + 1] = (float)si;
-  }
-}
-
-// Adaptive rule: H^oo = kinetic part + sum over the common support cells (ascending) and their
-// rule points of w V conj(N^O_i) N^O_j; one thread per entry (i, j)
-struct HooAdapt {
-  const double *a_w, *a_V, *phiA, *Hoo_kin;
-  const int64_t *a_off, *cf_aoff, *hp_ptr;
-  const int32_t *cf_acell, *hp_i, *hp_j, *fn_blk, *blk_fn0;
+// H^oo = kinetic part + sum over the common support cells (ascending) of two blocks and their
+// quadrature points (the Gauss points, or the adaptive rule's points) of w V conj(N^O_i) N^O_j.
+// One workgroup per block pair (bi, bj): thread t takes the entry item = t mod (nf_i nf_j) and
+// the point lane t / (nf_i nf_j), lanes striding over each cell's points; the lanes' sums are
+// added in lane order (a fixed summation order).
+struct HooPair {
+  const double *W, *V, *phi;  // the Gauss rule
+  const int32_t* cf_cell;
+  const double *a_w, *a_V, *phiA;  // the adaptive rule (a_off null: the Gauss rule)
+  const int64_t *a_off, *cf_aoff;
+  const int32_t* cf_acell;
+  const double* Hoo_kin;
+  const int64_t* hp_ptr;
+  const int32_t *hp_i, *hp_j, *blk_fn0, *blk_nf;
   double* Hoo;
   float* Hoof;
-  int nO, nb, FMAX;
+  int nO, nb, FMAX, nq;
 };
 
 template <bool CPLX>
-__global__ __launch_bounds__(256) void hoo_adapt_kernel(HooAdapt a) {
+__global__ __launch_bounds__(256) void hoo_pair_kernel(HooPair a) {
   constexpr int E = CPLX ? 2 : 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nO * a.nO) return;
-  const int i = t / a.nO, j = t - i * a.nO;
-  const int bi = a.fn_blk[i], bj = a.fn_blk[j];
-  const int f = i - a.blk_fn0[bi], g = j - a.blk_fn0[bj];
-  double sr = a.Hoo_kin[(int64_t)t * E], si = CPLX ? a.Hoo_kin[(int64_t)t * E + 1] : 0.0;
-  const int64_t pr = (int64_t)bi * a.nb + bj;
-  for (int64_t k = a.hp_ptr[pr]; k < a.hp_ptr[pr + 1]; ++k) {
-    const int ci = a.hp_i[k], cj = a.hp_j[k];
-    const int kc = a.cf_acell[ci];
-    const int64_t p0 = a.a_off[kc], np = a.a_off[kc + 1] - p0;
-    const double* pa = a.phiA + (a.cf_aoff[ci] * a.FMAX + f) * E;
-    const double* pb = a.phiA + (a.cf_aoff[cj] * a.FMAX + g) * E;
-    for (int64_t q = 0; q < np; ++q) {
-      const double wv = a.a_w[p0 + q] * a.a_V[p0 + q];
-      const double ar = pa[q * a.FMAX * E], ai = CPLX ? -pa[q * a.FMAX * E + 1] : 0.0;
-      const double br = pb[q * a.FMAX * E], bim = CPLX ? pb[q * a.FMAX * E + 1] : 0.0;
-      const double xr = wv * ar, xi = wv * ai;
-      sr += xr * br - xi * bim;
-      if (CPLX) si += xr * bim + xi * br;
+  __shared__ double red[256][E];
+  const int bi = blockIdx.x / a.nb, bj = blockIdx.x - bi * a.nb;
+  const int nfi = a.blk_nf[bi], nfj = a.blk_nf[bj], nit = nfi * nfj;
+  const int lanes = (int)blockDim.x / nit;
+  const int t = threadIdx.x, item = t % nit, lane = t / nit;
+  const int f = item / nfj, g = item - f * nfj;
+  const bool adapt = a.a_off != nullptr;
+  const int F = a.FMAX;
+  double sr = 0.0, si = 0.0;
+  if (lane < lanes) {
+    const int64_t pr = (int64_t)bi * a.nb + bj;
+    for (int64_t k = a.hp_ptr[pr]; k < a.hp_ptr[pr + 1]; ++k) {
+      const int ci = a.hp_i[k], cj = a.hp_j[k];
+      int64_t np, p0 = 0, e = 0;
+      const double *pa, *pb;
+      if (adapt) {
+        const int kc = a.cf_acell[ci];
+        p0 = a.a_off[kc];
+        np = a.a_off[kc + 1] - p0;
+        pa = a.phiA + (a.cf_aoff[ci] * F + f) * E;
+        pb = a.phiA + (a.cf_aoff[cj] * F + g) * E;
+      } else {
+        e = a.cf_cell[ci];
+        np = a.nq;
+        pa = a.phi + ((int64_t)ci * a.nq * F + f) * E;
+        pb = a.phi + ((int64_t)cj * a.nq * F + g) * E;
+      }
+      for (int64_t q = lane; q < np; q += lanes) {
+        const double wv = adapt ? a.a_w[p0 + q] * a.a_V[p0 + q] : a.W[e * a.nq + q] * a.V[e * a.nq + q];
+        const double ar = pa[q * F * E], ai = CPLX ? -pa[q * F * E + 1] : 0.0;
+        const double br = pb[q * F * E], bim = CPLX ? pb[q * F * E + 1] : 0.0;
+        const double xr = wv * ar, xi = wv * ai;
+        sr += xr * br - xi * bim;
+        if (CPLX) si += xr * bim + xi * br;
+      }
     }
   }
-  a.Hoo[(int64_t)t * E] = sr;
-  a.Hoof[(int64_t)t * E] = (float)sr;
-  if (CPLX) {
-    a.Hoo[(int64_t)t * E + 1] = si;
-    a.Hoof[(int64_t)t * E + 1] = (float)si;
+  red[t][0] = sr;
+  if (CPLX) red[t][E - 1] = si;
+  __syncthreads();
+  if (lane == 0) {
+    const int i = a.blk_fn0[bi] + f, j = a.blk_fn0[bj] + g;
+    const int64_t o = ((int64_t)i * a.nO + j) * E;
+    double tr = a.Hoo_kin[o], ti = CPLX ? a.Hoo_kin[o + 1] : 0.0;
+    for (int l = 0; l < lanes; ++l) {
+      tr += red[l * nit + item][0];
+      if (CPLX) ti += red[l * nit + item][E - 1];
+    }
+    a.Hoo[o] = tr;
+    a.Hoof[o] = (float)tr;
+    if (CPLX) {
+      a.Hoo[o + 1] = ti;
+      a.Hoof[o + 1] = (float)ti;
+    }
   }
 }
 
@@ -1310,19 +1366,22 @@ static int rebuild_potential_device(oefe_op op, hipStream_t s) {
   hipLaunchKernelGGL(wv_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s, op->d.W, op->d.V, op->d.WV,
                      op->d.WVf, nqt);
   if (op->n_enr > 0) {
-    if (op->adaptive) {
-      HcoAdapt h{};
+    const bool ad = op->adaptive;
+    HcoPart h{};
+    h.W = op->d.W; h.V = op->d.V; h.phi = op->d.phi; h.cf_cell = op->d.cf_cell;
+    if (ad) {
       h.a_w = op->d.a_w; h.a_V = op->d.a_V; h.a_leafB = op->d.a_leafB; h.phiA = op->d.phiA;
-      h.a_off = op->d.a_off; h.cf_aoff = op->d.cf_aoff; h.cf_acell = op->d.cf_acell; h.hpart = op->d.hpart;
-      h.nd = op->nd; h.P1 = op->P1; h.FMAX = op->FMAX;
-      if (op->cplx)
-        hipLaunchKernelGGL(hco_adapt_partial_kernel<true>, dim3((unsigned)op->n_cf), dim3(256), 0, s, h);
-      else
-        hipLaunchKernelGGL(hco_adapt_partial_kernel<false>, dim3((unsigned)op->n_cf), dim3(256), 0, s, h);
+      h.a_off = op->d.a_off; h.cf_aoff = op->d.cf_aoff; h.cf_acell = op->d.cf_acell;
     }
+    h.hpart = op->d.hpart;
+    h.nd = op->nd; h.P1 = op->P1; h.FMAX = op->FMAX;
+    if (op->cplx)
+      hipLaunchKernelGGL(hco_partial_kernel<true>, dim3((unsigned)op->n_cf), dim3(256), 0, s, h, op->cd);
+    else
+      hipLaunchKernelGGL(hco_partial_kernel<false>, dim3((unsigned)op->n_cf), dim3(256), 0, s, h, op->cd);
     HcoRebuild a{};
     a.W = op->d.W; a.V = op->d.V; a.phi = op->d.phi; a.msq = op->d.msq; a.hkin = op->d.hkin;
-    a.hpart = op->adaptive ? op->d.hpart : nullptr;
+    a.hpart = op->d.hpart;
     a.rr_ptr = op->d.rr_ptr; a.rpos = op->d.rpos; a.csr2tile = op->d.csr2tile;
     a.rr_ent = op->d.rr_ent; a.cf_cell = op->d.cf_cell; a.row_blk = op->d.row_blk; a.blk_nf = op->d.blk_nf;
     a.blk_rows = op->d.blk_rows;
@@ -1336,31 +1395,23 @@ static int rebuild_potential_device(oefe_op op, hipStream_t s) {
     }
     const unsigned g1 = (unsigned)((op->n_hrows * op->FMAX + 255) / 256);
     if (op->cplx)
-      hipLaunchKernelGGL(hco_rebuild_kernel<true>, dim3(g1), dim3(256), 0, s, a, op->cd);
+      hipLaunchKernelGGL(hco_rebuild_kernel<true>, dim3(g1), dim3(256), 0, s, a);
     else
-      hipLaunchKernelGGL(hco_rebuild_kernel<false>, dim3(g1), dim3(256), 0, s, a, op->cd);
-    const int nO = op->n_enr, nb = (int)op->blocks.size();
-    const unsigned g2 = (unsigned)(((int64_t)nO * nO + 255) / 256);
-    if (op->adaptive) {
-      HooAdapt o{};
-      o.a_w = op->d.a_w; o.a_V = op->d.a_V; o.phiA = op->d.phiA; o.Hoo_kin = op->d.Hoo_kin;
-      o.a_off = op->d.a_off; o.cf_aoff = op->d.cf_aoff; o.hp_ptr = op->d.hp_ptr;
-      o.cf_acell = op->d.cf_acell; o.hp_i = op->d.hp_i; o.hp_j = op->d.hp_j; o.fn_blk = op->d.fn_blk;
-      o.blk_fn0 = op->d.blk_fn0; o.Hoo = op->d.Hoo; o.Hoof = op->d.Hoof;
-      o.nO = nO; o.nb = nb; o.FMAX = op->FMAX;
-      if (op->cplx)
-        hipLaunchKernelGGL(hoo_adapt_kernel<true>, dim3(g2), dim3(256), 0, s, o);
-      else
-        hipLaunchKernelGGL(hoo_adapt_kernel<false>, dim3(g2), dim3(256), 0, s, o);
-    } else if (op->cplx) {
-      hipLaunchKernelGGL(hoo_rebuild_kernel<true>, dim3(g2), dim3(256), 0, s, op->d.W, op->d.V, op->d.phi,
-                         op->d.Hoo_kin, op->d.hp_ptr, op->d.hp_i, op->d.hp_j, op->d.cf_cell, op->d.fn_blk,
-                         op->d.blk_fn0, nO, nb, op->FMAX, op->nq, op->d.Hoo, op->d.Hoof);
-    } else {
-      hipLaunchKernelGGL(hoo_rebuild_kernel<false>, dim3(g2), dim3(256), 0, s, op->d.W, op->d.V, op->d.phi,
-                         op->d.Hoo_kin, op->d.hp_ptr, op->d.hp_i, op->d.hp_j, op->d.cf_cell, op->d.fn_blk,
-                         op->d.blk_fn0, nO, nb, op->FMAX, op->nq, op->d.Hoo, op->d.Hoof);
+      hipLaunchKernelGGL(hco_rebuild_kernel<false>, dim3(g1), dim3(256), 0, s, a);
+    HooPair o{};
+    o.W = op->d.W; o.V = op->d.V; o.phi = op->d.phi; o.cf_cell = op->d.cf_cell;
+    if (ad) {
+      o.a_w = op->d.a_w; o.a_V = op->d.a_V; o.phiA = op->d.phiA;
+      o.a_off = op->d.a_off; o.cf_aoff = op->d.cf_aoff; o.cf_acell = op->d.cf_acell;
     }
+    o.Hoo_kin = op->d.Hoo_kin; o.hp_ptr = op->d.hp_ptr; o.hp_i = op->d.hp_i; o.hp_j = op->d.hp_j;
+    o.blk_fn0 = op->d.blk_fn0; o.blk_nf = op->d.blk_nf; o.Hoo = op->d.Hoo; o.Hoof = op->d.Hoof;
+    const int nb = (int)op->blocks.size();
+    o.nO = op->n_enr; o.nb = nb; o.FMAX = op->FMAX; o.nq = op->nq;
+    if (op->cplx)
+      hipLaunchKernelGGL(hoo_pair_kernel<true>, dim3((unsigned)(nb * nb)), dim3(256), 0, s, o);
+    else
+      hipLaunchKernelGGL(hoo_pair_kernel<false>, dim3((unsigned)(nb * nb)), dim3(256), 0, s, o);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "potential rebuild");

@@ -13,6 +13,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "oefe_internal.h"
 
@@ -308,6 +309,8 @@ struct Geo {
 
 // ---- adaptive quadrature of the enrichment integrals (Sec. III.B)
 //
+constexpr int kSetupThreads = 16;  // host threads of the rule's refinement
+//
 // Whole-space integrals A = int psi~^2 and B = int |grad psi~|^2 of an atomic function
 // psi~ = g(r) (axis < 0) or d_axis g(r), g = r^pw exp(-zeta r) h(r), after the angular
 // integration: s-type 4 pi r^2 g^2 and 4 pi r^2 g'^2; p-type 4 pi r^4 g^2 / 3 and
@@ -494,21 +497,39 @@ int build_adaptive_rule(oefe_op_s* op, const oefe_system_desc* desc, const doubl
   // sqrt(A v), sqrt(B v) (v = 4/3 pi r1^3) for the ones with the FE functions
   const int nd = op->nd, nt = 2 + 2 * nd;
   const double vol = 4.0 / 3.0 * kPi * desc->r1 * desc->r1 * desc->r1;
-  for (int64_t e : op->ad_cells) {
-    const auto& fl = fns_of[e];
-    std::vector<double> bound(nt * fl.size());
-    for (size_t j = 0; j < fl.size(); ++j) {
-      const double A = scaleA[fl[j].second], B = scaleB[fl[j].second];
-      bound[j * nt] = op->ad_tol * A;
-      bound[j * nt + 1] = op->ad_tol * B;
-      for (int a = 0; a < nd; ++a) {
-        bound[j * nt + 2 + a] = op->ad_tol * std::sqrt(A * vol);
-        bound[j * nt + 2 + nd + a] = op->ad_tol * std::sqrt(B * vol);
+  // cells are refined independently: contiguous ranges of rule cells on host threads, each
+  // collecting its leaves, then appended in cell order (the rule does not depend on the split)
+  const int64_t nrc = (int64_t)op->ad_cells.size();
+  std::vector<std::vector<std::array<double, 4>>> cell_leaves(nrc);
+  auto work = [&](int64_t k0, int64_t k1) {
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t e = op->ad_cells[k];
+      const auto& fl = fns_of[e];
+      std::vector<double> bound(nt * fl.size());
+      for (size_t j = 0; j < fl.size(); ++j) {
+        const double A = scaleA[fl[j].second], B = scaleB[fl[j].second];
+        bound[j * nt] = op->ad_tol * A;
+        bound[j * nt + 1] = op->ad_tol * B;
+        for (int a = 0; a < nd; ++a) {
+          bound[j * nt + 2 + a] = op->ad_tol * std::sqrt(A * vol);
+          bound[j * nt + 2 + nd + a] = op->ad_tol * std::sqrt(B * vol);
+        }
       }
+      const double org[3] = {(double)(e % nc) * h, (double)((e / nc) % nc) * h, (double)(e / ((int64_t)nc * nc)) * h};
+      refine_box(op, desc, xi, org, fl, bound, org, h, 0, cell_leaves[k]);
     }
+  };
+  const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kSetupThreads,
+                                                              (int64_t)std::max(1u, std::thread::hardware_concurrency()),
+                                                              nrc}));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(work, nrc * t / nth, nrc * (t + 1) / nth);
+  work(0, nrc / nth);
+  for (auto& th : pool) th.join();
+  for (int64_t k = 0; k < nrc; ++k) {
+    const int64_t e = op->ad_cells[k];
     const double org[3] = {(double)(e % nc) * h, (double)((e / nc) % nc) * h, (double)(e / ((int64_t)nc * nc)) * h};
-    std::vector<std::array<double, 4>> leaves;
-    refine_box(op, desc, xi, org, fl, bound, org, h, 0, leaves);
+    const auto& leaves = cell_leaves[k];
     for (const auto& lf : leaves) {
       double t[3][8], wt[3][8];
       for (int d = 0; d < 3; ++d)
@@ -854,8 +875,6 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
       Dm[i * 8 + j] = op->D1[i][j];
     }
   const double s2h = 2.0 / h;
-  std::vector<cplx> dacc;   // [N][nf] accumulation of d (reused)
-  std::vector<char> touched;
   for (auto& b : op->blocks) {
     const double* R = &desc->pos[3 * b.atom];
     // core cells: box within r1 of the atom (nearest image); support: core dilated by one layer
@@ -891,150 +910,129 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
     if (int rc = build_adaptive_rule(op, desc, xi, err)) return rc;
   }
   const int nq3 = nq;
-  for (auto& b : op->blocks) {
-    const double* R = &desc->pos[3 * b.atom];
-    const int nf = b.nf;
-    const size_t ncb = b.cells.size();
-    // N^A and grad N^A at the quadrature points of the support cells
-    std::vector<cplx> NA(ncb * nq * nf), gNA(ncb * nq * nf * 3);
-    for (size_t ci = 0; ci < ncb; ++ci) {
-      int64_t e = b.cells[ci];
-      for (int q = 0; q < nq; ++q) {
-        double x[3], d[3], t[3];
-        geo.quad_point(e, q, x);
-        for (int k = 0; k < 3; ++k) {
-          double dr = x[k] - R[k];
-          t[k] = std::nearbyint(dr / op->L);
-          d[k] = dr - op->L * t[k];
-        }
-        cplx ph(1.0, 0.0);
-        if (uf) {  // exp(-i k . (x - R^x)) (eqnUOEFEAtomic)
-          double arg = -(op->kvec[0] * d[0] + op->kvec[1] * d[1] + op->kvec[2] * d[2]);
-          ph = cplx(std::cos(arg), std::sin(arg));
-        } else if (op->cplx) {
-          double arg = op->L * (op->kvec[0] * t[0] + op->kvec[1] * t[1] + op->kvec[2] * t[2]);
-          ph = cplx(std::cos(arg), std::sin(arg));
-        }
-        for (int f = 0; f < nf; ++f) {
-          int fn = b.fn0 + f;
-          double val, gr[3];
-          if (pois)
-            phi_aux_fn(d, desc->Z[b.atom], alpha_m[b.atom], op->rc_smear[b.atom], desc->r0, desc->r1, val, gr);
-          else
-            atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
-          NA[(ci * nq + q) * nf + f] = ph * val;
-          for (int k = 0; k < 3; ++k)  // the periodic-function form: grad (e^{-ik.d} f) = e^{-ik.d} (grad f - i k f)
-            gNA[((ci * nq + q) * nf + f) * 3 + k] = ph * (uf ? cplx(gr[k], -op->kvec[k] * val) : cplx(gr[k], 0.0));
-        }
-      }
-    }
-    // adaptive rule: N^A and grad N^A at the rule's points of the support cells
-    std::vector<cplx> NAa, gNAa;
-    if (ad) {
-      b.aoff.assign(ncb + 1, 0);
+  // blocks are independent: host threads over contiguous block ranges, each with its own scratch
+  auto block_work = [&](size_t b0, size_t b1) {
+    std::vector<cplx> dacc;   // [N][nf] accumulation of d (reused)
+    std::vector<char> touched;
+    for (size_t ib = b0; ib < b1; ++ib) {
+      auto& b = op->blocks[ib];
+      const double* R = &desc->pos[3 * b.atom];
+      const int nf = b.nf;
+      const size_t ncb = b.cells.size();
+      // N^A and grad N^A at the quadrature points of the support cells
+      std::vector<cplx> NA(ncb * nq * nf), gNA(ncb * nq * nf * 3);
       for (size_t ci = 0; ci < ncb; ++ci) {
-        const int32_t k = op->ad_index[b.cells[ci]];
-        b.aoff[ci + 1] = b.aoff[ci] + (op->ad_off[k + 1] - op->ad_off[k]);
-      }
-      NAa.assign((size_t)b.aoff[ncb] * nf, cplx(0, 0));
-      gNAa.assign((size_t)b.aoff[ncb] * nf * 3, cplx(0, 0));
-      for (size_t ci = 0; ci < ncb; ++ci) {
-        const int32_t k = op->ad_index[b.cells[ci]];
-        for (int64_t i = op->ad_off[k]; i < op->ad_off[k + 1]; ++i) {
-          const int64_t row = b.aoff[ci] + (i - op->ad_off[k]);
-          double d[3], t[3];
-          for (int kk = 0; kk < 3; ++kk) {
-            const double dr = op->ad_x[3 * i + kk] - R[kk];
-            t[kk] = std::nearbyint(dr / op->L);
-            d[kk] = dr - op->L * t[kk];
+        int64_t e = b.cells[ci];
+        for (int q = 0; q < nq; ++q) {
+          double x[3], d[3], t[3];
+          geo.quad_point(e, q, x);
+          for (int k = 0; k < 3; ++k) {
+            double dr = x[k] - R[k];
+            t[k] = std::nearbyint(dr / op->L);
+            d[k] = dr - op->L * t[k];
           }
           cplx ph(1.0, 0.0);
-          if (op->cplx) {
-            const double arg = op->L * (op->kvec[0] * t[0] + op->kvec[1] * t[1] + op->kvec[2] * t[2]);
+          if (uf) {  // exp(-i k . (x - R^x)) (eqnUOEFEAtomic)
+            double arg = -(op->kvec[0] * d[0] + op->kvec[1] * d[1] + op->kvec[2] * d[2]);
+            ph = cplx(std::cos(arg), std::sin(arg));
+          } else if (op->cplx) {
+            double arg = op->L * (op->kvec[0] * t[0] + op->kvec[1] * t[1] + op->kvec[2] * t[2]);
             ph = cplx(std::cos(arg), std::sin(arg));
           }
           for (int f = 0; f < nf; ++f) {
-            const int fn = b.fn0 + f;
+            int fn = b.fn0 + f;
             double val, gr[3];
-            atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
-            NAa[(size_t)row * nf + f] = ph * val;
-            for (int kk = 0; kk < 3; ++kk) gNAa[((size_t)row * nf + f) * 3 + kk] = ph * gr[kk];
+            if (pois)
+              phi_aux_fn(d, desc->Z[b.atom], alpha_m[b.atom], op->rc_smear[b.atom], desc->r0, desc->r1, val, gr);
+            else
+              atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
+            NA[(ci * nq + q) * nf + f] = ph * val;
+            for (int k = 0; k < 3; ++k)  // the periodic-function form: grad (e^{-ik.d} f) = e^{-ik.d} (grad f - i k f)
+              gNA[((ci * nq + q) * nf + f) * 3 + k] = ph * (uf ? cplx(gr[k], -op->kvec[k] * val) : cplx(gr[k], 0.0));
           }
         }
       }
-    }
-    // d_g = sum_{(e,a)->g} conj(theta_ea) sum_q W B[q,a] N^A ; c_g = d_g / m_g (the adaptive
-    // rule's points and weights in place of the cell's Gauss rule when it is in use)
-    dacc.assign((size_t)op->N * nf, cplx(0, 0));
-    std::vector<cplx> tin(nq), tout(nq);
-    for (size_t ci = 0; ad && ci < ncb; ++ci) {
-      const int64_t e = b.cells[ci];
-      const int32_t k = op->ad_index[e];
-      for (int f = 0; f < nf; ++f) {
-        std::vector<cplx> acc(op->nd, cplx(0, 0));
-        for (int64_t l = op->ad_off[k] / nq3; l < op->ad_off[k + 1] / nq3; ++l) {
-          double Mx[64], My[64], Mz[64];
-          leaf_matrix(op, l, 0, false, Mx);
-          leaf_matrix(op, l, 1, false, My);
-          leaf_matrix(op, l, 2, false, Mz);
-          const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
-          for (int q = 0; q < nq; ++q) tin[q] = op->ad_w[l * nq3 + q] * NAa[(size_t)(row0 + q) * nf + f];
-          tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
-          for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+      // adaptive rule: N^A and grad N^A at the rule's points of the support cells
+      std::vector<cplx> NAa, gNAa;
+      if (ad) {
+        b.aoff.assign(ncb + 1, 0);
+        for (size_t ci = 0; ci < ncb; ++ci) {
+          const int32_t k = op->ad_index[b.cells[ci]];
+          b.aoff[ci + 1] = b.aoff[ci] + (op->ad_off[k + 1] - op->ad_off[k]);
         }
-        for (int a = 0; a < op->nd; ++a) {
-          int64_t g;
-          cplx th;
-          geo.dof(e, a, g, th);
-          dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
-        }
-      }
-    }
-    for (size_t ci = 0; !ad && ci < ncb; ++ci) {
-      int64_t e = b.cells[ci];
-      for (int f = 0; f < nf; ++f) {
-        for (int q = 0; q < nq; ++q) tin[q] = op->W[e * nq + q] * NA[(ci * nq + q) * nf + f];
-        tp_backward<cplx>(P1, Bm, Bm, Bm, tin.data(), tout.data());
-        for (int a = 0; a < op->nd; ++a) {
-          int64_t g;
-          cplx th;
-          geo.dof(e, a, g, th);
-          dacc[(size_t)g * nf + f] += std::conj(th) * tout[a];
+        NAa.assign((size_t)b.aoff[ncb] * nf, cplx(0, 0));
+        gNAa.assign((size_t)b.aoff[ncb] * nf * 3, cplx(0, 0));
+        for (size_t ci = 0; ci < ncb; ++ci) {
+          const int32_t k = op->ad_index[b.cells[ci]];
+          for (int64_t i = op->ad_off[k]; i < op->ad_off[k + 1]; ++i) {
+            const int64_t row = b.aoff[ci] + (i - op->ad_off[k]);
+            double d[3], t[3];
+            for (int kk = 0; kk < 3; ++kk) {
+              const double dr = op->ad_x[3 * i + kk] - R[kk];
+              t[kk] = std::nearbyint(dr / op->L);
+              d[kk] = dr - op->L * t[kk];
+            }
+            cplx ph(1.0, 0.0);
+            if (op->cplx) {
+              const double arg = op->L * (op->kvec[0] * t[0] + op->kvec[1] * t[1] + op->kvec[2] * t[2]);
+              ph = cplx(std::cos(arg), std::sin(arg));
+            }
+            for (int f = 0; f < nf; ++f) {
+              const int fn = b.fn0 + f;
+              double val, gr[3];
+              atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
+              NAa[(size_t)row * nf + f] = ph * val;
+              for (int kk = 0; kk < 3; ++kk) gNAa[((size_t)row * nf + f) * 3 + kk] = ph * gr[kk];
+            }
+          }
         }
       }
-    }
-    // orthogonalized values and gradients
-    b.phi.assign(ncb * nq * nf, cplx(0, 0));
-    b.gphi.assign(ncb * nq * nf * 3, cplx(0, 0));
-    std::vector<cplx> ce(op->nd), o(nq);
-    for (size_t ci = 0; ci < ncb; ++ci) {
-      int64_t e = b.cells[ci];
-      for (int f = 0; f < nf; ++f) {
-        for (int a = 0; a < op->nd; ++a) {
-          int64_t g;
-          cplx th;
-          geo.dof(e, a, g, th);
-          ce[a] = th * (dacc[(size_t)g * nf + f] / op->mdiag[g]);
-        }
-        tp_forward<cplx>(P1, Bm, Bm, Bm, ce.data(), o.data());
-        for (int q = 0; q < nq; ++q) b.phi[(ci * nq + q) * nf + f] = NA[(ci * nq + q) * nf + f] - o[q];
-        for (int dd = 0; dd < 3; ++dd) {
-          const double* Mx = dd == 0 ? Dm : Bm;
-          const double* My = dd == 1 ? Dm : Bm;
-          const double* Mz = dd == 2 ? Dm : Bm;
-          tp_forward<cplx>(P1, Mx, My, Mz, ce.data(), o.data());
-          for (int q = 0; q < nq; ++q)
-            b.gphi[((ci * nq + q) * nf + f) * 3 + dd] = gNA[((ci * nq + q) * nf + f) * 3 + dd] - s2h * o[q];
-        }
-      }
-    }
-    // adaptive rule: N^O and grad N^O at its points with the same coefficients
-    if (ad) {
-      b.phiA.assign((size_t)b.aoff[ncb] * nf, cplx(0, 0));
-      b.gphiA.assign((size_t)b.aoff[ncb] * nf * 3, cplx(0, 0));
-      for (size_t ci = 0; ci < ncb; ++ci) {
+      // d_g = sum_{(e,a)->g} conj(theta_ea) sum_q W B[q,a] N^A ; c_g = d_g / m_g (the adaptive
+      // rule's points and weights in place of the cell's Gauss rule when it is in use)
+      dacc.assign((size_t)op->N * nf, cplx(0, 0));
+      std::vector<cplx> tin(nq), tout(nq);
+      for (size_t ci = 0; ad && ci < ncb; ++ci) {
         const int64_t e = b.cells[ci];
         const int32_t k = op->ad_index[e];
+        for (int f = 0; f < nf; ++f) {
+          std::vector<cplx> acc(op->nd, cplx(0, 0));
+          for (int64_t l = op->ad_off[k] / nq3; l < op->ad_off[k + 1] / nq3; ++l) {
+            double Mx[64], My[64], Mz[64];
+            leaf_matrix(op, l, 0, false, Mx);
+            leaf_matrix(op, l, 1, false, My);
+            leaf_matrix(op, l, 2, false, Mz);
+            const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
+            for (int q = 0; q < nq; ++q) tin[q] = op->ad_w[l * nq3 + q] * NAa[(size_t)(row0 + q) * nf + f];
+            tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
+            for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+          }
+          for (int a = 0; a < op->nd; ++a) {
+            int64_t g;
+            cplx th;
+            geo.dof(e, a, g, th);
+            dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
+          }
+        }
+      }
+      for (size_t ci = 0; !ad && ci < ncb; ++ci) {
+        int64_t e = b.cells[ci];
+        for (int f = 0; f < nf; ++f) {
+          for (int q = 0; q < nq; ++q) tin[q] = op->W[e * nq + q] * NA[(ci * nq + q) * nf + f];
+          tp_backward<cplx>(P1, Bm, Bm, Bm, tin.data(), tout.data());
+          for (int a = 0; a < op->nd; ++a) {
+            int64_t g;
+            cplx th;
+            geo.dof(e, a, g, th);
+            dacc[(size_t)g * nf + f] += std::conj(th) * tout[a];
+          }
+        }
+      }
+      // orthogonalized values and gradients
+      b.phi.assign(ncb * nq * nf, cplx(0, 0));
+      b.gphi.assign(ncb * nq * nf * 3, cplx(0, 0));
+      std::vector<cplx> ce(op->nd), o(nq);
+      for (size_t ci = 0; ci < ncb; ++ci) {
+        int64_t e = b.cells[ci];
         for (int f = 0; f < nf; ++f) {
           for (int a = 0; a < op->nd; ++a) {
             int64_t g;
@@ -1042,6 +1040,71 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
             geo.dof(e, a, g, th);
             ce[a] = th * (dacc[(size_t)g * nf + f] / op->mdiag[g]);
           }
+          tp_forward<cplx>(P1, Bm, Bm, Bm, ce.data(), o.data());
+          for (int q = 0; q < nq; ++q) b.phi[(ci * nq + q) * nf + f] = NA[(ci * nq + q) * nf + f] - o[q];
+          for (int dd = 0; dd < 3; ++dd) {
+            const double* Mx = dd == 0 ? Dm : Bm;
+            const double* My = dd == 1 ? Dm : Bm;
+            const double* Mz = dd == 2 ? Dm : Bm;
+            tp_forward<cplx>(P1, Mx, My, Mz, ce.data(), o.data());
+            for (int q = 0; q < nq; ++q)
+              b.gphi[((ci * nq + q) * nf + f) * 3 + dd] = gNA[((ci * nq + q) * nf + f) * 3 + dd] - s2h * o[q];
+          }
+        }
+      }
+      // adaptive rule: N^O and grad N^O at its points with the same coefficients
+      if (ad) {
+        b.phiA.assign((size_t)b.aoff[ncb] * nf, cplx(0, 0));
+        b.gphiA.assign((size_t)b.aoff[ncb] * nf * 3, cplx(0, 0));
+        for (size_t ci = 0; ci < ncb; ++ci) {
+          const int64_t e = b.cells[ci];
+          const int32_t k = op->ad_index[e];
+          for (int f = 0; f < nf; ++f) {
+            for (int a = 0; a < op->nd; ++a) {
+              int64_t g;
+              cplx th;
+              geo.dof(e, a, g, th);
+              ce[a] = th * (dacc[(size_t)g * nf + f] / op->mdiag[g]);
+            }
+            for (int64_t l = op->ad_off[k] / nq3; l < op->ad_off[k + 1] / nq3; ++l) {
+              double Bx[64], By[64], Bz[64], Dx[64], Dy[64], Dz[64];
+              leaf_matrix(op, l, 0, false, Bx);
+              leaf_matrix(op, l, 1, false, By);
+              leaf_matrix(op, l, 2, false, Bz);
+              leaf_matrix(op, l, 0, true, Dx);
+              leaf_matrix(op, l, 1, true, Dy);
+              leaf_matrix(op, l, 2, true, Dz);
+              const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
+              tp_forward<cplx>(P1, Bx, By, Bz, ce.data(), o.data());
+              for (int q = 0; q < nq; ++q) b.phiA[(size_t)(row0 + q) * nf + f] = NAa[(size_t)(row0 + q) * nf + f] - o[q];
+              for (int dd = 0; dd < 3; ++dd) {
+                tp_forward<cplx>(P1, dd == 0 ? Dx : Bx, dd == 1 ? Dy : By, dd == 2 ? Dz : Bz, ce.data(), o.data());
+                for (int q = 0; q < nq; ++q)
+                  b.gphiA[((size_t)(row0 + q) * nf + f) * 3 + dd] = gNAa[((size_t)(row0 + q) * nf + f) * 3 + dd] - s2h * o[q];
+              }
+            }
+          }
+        }
+      }
+      // rows of H^co: all FE nodes of the support cells
+      touched.assign(op->N, 0);
+      for (size_t ci = 0; ci < ncb; ++ci)
+        for (int a = 0; a < op->nd; ++a) {
+          int64_t g;
+          cplx th;
+          geo.dof(b.cells[ci], a, g, th);
+          touched[g] = 1;
+        }
+      b.rows.clear();
+      for (int64_t g = 0; g < op->N; ++g)
+        if (touched[g]) b.rows.push_back((int32_t)g);
+      // kinetic part of H^co: sum_q W kin (2/h) G_d[q,a] dPhi_d (the adaptive rule's points when in use)
+      dacc.assign((size_t)op->N * nf, cplx(0, 0));
+      for (size_t ci = 0; ad && ci < ncb; ++ci) {
+        const int64_t e = b.cells[ci];
+        const int32_t k = op->ad_index[e];
+        for (int f = 0; f < nf; ++f) {
+          std::vector<cplx> acc(op->nd, cplx(0, 0));
           for (int64_t l = op->ad_off[k] / nq3; l < op->ad_off[k + 1] / nq3; ++l) {
             double Bx[64], By[64], Bz[64], Dx[64], Dy[64], Dz[64];
             leaf_matrix(op, l, 0, false, Bx);
@@ -1051,154 +1114,140 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
             leaf_matrix(op, l, 1, true, Dy);
             leaf_matrix(op, l, 2, true, Dz);
             const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
-            tp_forward<cplx>(P1, Bx, By, Bz, ce.data(), o.data());
-            for (int q = 0; q < nq; ++q) b.phiA[(size_t)(row0 + q) * nf + f] = NAa[(size_t)(row0 + q) * nf + f] - o[q];
             for (int dd = 0; dd < 3; ++dd) {
-              tp_forward<cplx>(P1, dd == 0 ? Dx : Bx, dd == 1 ? Dy : By, dd == 2 ? Dz : Bz, ce.data(), o.data());
               for (int q = 0; q < nq; ++q)
-                b.gphiA[((size_t)(row0 + q) * nf + f) * 3 + dd] = gNAa[((size_t)(row0 + q) * nf + f) * 3 + dd] - s2h * o[q];
+                tin[q] = kin * s2h * op->ad_w[l * nq3 + q] * b.gphiA[((size_t)(row0 + q) * nf + f) * 3 + dd];
+              tp_backward<cplx>(P1, dd == 0 ? Dx : Bx, dd == 1 ? Dy : By, dd == 2 ? Dz : Bz, tin.data(), tout.data());
+              for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
             }
           }
+          for (int a = 0; a < op->nd; ++a) {
+            int64_t g;
+            cplx th;
+            geo.dof(e, a, g, th);
+            dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
+          }
         }
       }
-    }
-    // rows of H^co: all FE nodes of the support cells
-    touched.assign(op->N, 0);
-    for (size_t ci = 0; ci < ncb; ++ci)
-      for (int a = 0; a < op->nd; ++a) {
-        int64_t g;
-        cplx th;
-        geo.dof(b.cells[ci], a, g, th);
-        touched[g] = 1;
-      }
-    b.rows.clear();
-    for (int64_t g = 0; g < op->N; ++g)
-      if (touched[g]) b.rows.push_back((int32_t)g);
-    // kinetic part of H^co: sum_q W kin (2/h) G_d[q,a] dPhi_d (the adaptive rule's points when in use)
-    dacc.assign((size_t)op->N * nf, cplx(0, 0));
-    for (size_t ci = 0; ad && ci < ncb; ++ci) {
-      const int64_t e = b.cells[ci];
-      const int32_t k = op->ad_index[e];
-      for (int f = 0; f < nf; ++f) {
-        std::vector<cplx> acc(op->nd, cplx(0, 0));
-        for (int64_t l = op->ad_off[k] / nq3; l < op->ad_off[k + 1] / nq3; ++l) {
-          double Bx[64], By[64], Bz[64], Dx[64], Dy[64], Dz[64];
-          leaf_matrix(op, l, 0, false, Bx);
-          leaf_matrix(op, l, 1, false, By);
-          leaf_matrix(op, l, 2, false, Bz);
-          leaf_matrix(op, l, 0, true, Dx);
-          leaf_matrix(op, l, 1, true, Dy);
-          leaf_matrix(op, l, 2, true, Dz);
-          const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
+      for (size_t ci = 0; !ad && ci < ncb; ++ci) {
+        int64_t e = b.cells[ci];
+        for (int f = 0; f < nf; ++f) {
+          std::vector<cplx> acc(op->nd, cplx(0, 0));
           for (int dd = 0; dd < 3; ++dd) {
             for (int q = 0; q < nq; ++q)
-              tin[q] = kin * s2h * op->ad_w[l * nq3 + q] * b.gphiA[((size_t)(row0 + q) * nf + f) * 3 + dd];
-            tp_backward<cplx>(P1, dd == 0 ? Dx : Bx, dd == 1 ? Dy : By, dd == 2 ? Dz : Bz, tin.data(), tout.data());
-            for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
-          }
-        }
-        for (int a = 0; a < op->nd; ++a) {
-          int64_t g;
-          cplx th;
-          geo.dof(e, a, g, th);
-          dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
-        }
-      }
-    }
-    for (size_t ci = 0; !ad && ci < ncb; ++ci) {
-      int64_t e = b.cells[ci];
-      for (int f = 0; f < nf; ++f) {
-        std::vector<cplx> acc(op->nd, cplx(0, 0));
-        for (int dd = 0; dd < 3; ++dd) {
-          for (int q = 0; q < nq; ++q)
-            tin[q] = kin * s2h * op->W[e * nq + q] * b.gphi[((ci * nq + q) * nf + f) * 3 + dd];
-          const double* Mx = dd == 0 ? Dm : Bm;
-          const double* My = dd == 1 ? Dm : Bm;
-          const double* Mz = dd == 2 ? Dm : Bm;
-          tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
-          for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
-          if (uf) {
-            // the first-derivative term in Hermitian form (the enrichment function is not a
-            // polynomial): -i/2 k_d int N^C d_d Phi + i/2 k_d int (d_d N^C) Phi
-            const cplx mi(0.0, -0.5 * op->kvec[dd]), pi(0.0, 0.5 * op->kvec[dd]);
-            for (int q = 0; q < nq; ++q) tin[q] = mi * op->W[e * nq + q] * b.gphi[((ci * nq + q) * nf + f) * 3 + dd];
-            tp_backward<cplx>(P1, Bm, Bm, Bm, tin.data(), tout.data());
-            for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
-            for (int q = 0; q < nq; ++q) tin[q] = pi * s2h * op->W[e * nq + q] * b.phi[(ci * nq + q) * nf + f];
+              tin[q] = kin * s2h * op->W[e * nq + q] * b.gphi[((ci * nq + q) * nf + f) * 3 + dd];
+            const double* Mx = dd == 0 ? Dm : Bm;
+            const double* My = dd == 1 ? Dm : Bm;
+            const double* Mz = dd == 2 ? Dm : Bm;
             tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
             for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+            if (uf) {
+              // the first-derivative term in Hermitian form (the enrichment function is not a
+              // polynomial): -i/2 k_d int N^C d_d Phi + i/2 k_d int (d_d N^C) Phi
+              const cplx mi(0.0, -0.5 * op->kvec[dd]), pi(0.0, 0.5 * op->kvec[dd]);
+              for (int q = 0; q < nq; ++q) tin[q] = mi * op->W[e * nq + q] * b.gphi[((ci * nq + q) * nf + f) * 3 + dd];
+              tp_backward<cplx>(P1, Bm, Bm, Bm, tin.data(), tout.data());
+              for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+              for (int q = 0; q < nq; ++q) tin[q] = pi * s2h * op->W[e * nq + q] * b.phi[(ci * nq + q) * nf + f];
+              tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
+              for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+            }
+          }
+          for (int a = 0; a < op->nd; ++a) {
+            int64_t g;
+            cplx th;
+            geo.dof(e, a, g, th);
+            dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
           }
         }
-        for (int a = 0; a < op->nd; ++a) {
-          int64_t g;
-          cplx th;
-          geo.dof(e, a, g, th);
-          dacc[(size_t)g * nf + f] += std::conj(th) * acc[a];
-        }
       }
+      b.hkin.resize(b.rows.size() * nf);
+      for (size_t r = 0; r < b.rows.size(); ++r)
+        for (int f = 0; f < nf; ++f) b.hkin[r * nf + f] = dacc[(size_t)b.rows[r] * nf + f];
     }
-    b.hkin.resize(b.rows.size() * nf);
-    for (size_t r = 0; r < b.rows.size(); ++r)
-      for (int f = 0; f < nf; ++f) b.hkin[r * nf + f] = dacc[(size_t)b.rows[r] * nf + f];
+  };
+  {
+    const size_t nbk = op->blocks.size();
+    const size_t nth = std::max<size_t>(1, std::min<size_t>({(size_t)kSetupThreads,
+                                                            (size_t)std::max(1u, std::thread::hardware_concurrency()), nbk}));
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < nth; ++t) pool.emplace_back(block_work, nbk * t / nth, nbk * (t + 1) / nth);
+    block_work(0, nbk / nth);
+    for (auto& th : pool) th.join();
   }
   // ---- M^oo and the kinetic part of H^oo over common support cells
   const int nO = op->n_enr;
   op->Moo.assign((size_t)nO * nO, cplx(0, 0));
   op->Hoo_kin.assign((size_t)nO * nO, cplx(0, 0));
-  for (auto& bi : op->blocks)
-    for (auto& bj : op->blocks) {
-      size_t i = 0, j = 0;
-      while (i < bi.cells.size() && j < bj.cells.size()) {
-        if (bi.cells[i] < bj.cells[j]) { ++i; continue; }
-        if (bi.cells[i] > bj.cells[j]) { ++j; continue; }
-        int64_t e = bi.cells[i];
-        if (ad) {  // the adaptive rule's points of cell e (the same rows for both blocks' functions)
-          const int32_t k = op->ad_index[e];
-          const int64_t npt = op->ad_off[k + 1] - op->ad_off[k];
-          for (int64_t pt = 0; pt < npt; ++pt) {
-            const double Wq = op->ad_w[op->ad_off[k] + pt];
-            const int64_t ri = bi.aoff[i] + pt, rj = bj.aoff[j] + pt;
+  // one block's rows at a time (disjoint rows of M^oo and H^oo_kin: host threads over the blocks,
+  // every entry summed in the same order as on one thread)
+  auto pair_rows = [&](size_t b0, size_t b1) {
+    for (size_t ib = b0; ib < b1; ++ib) {
+      auto& bi = op->blocks[ib];
+      for (auto& bj : op->blocks) {
+        size_t i = 0, j = 0;
+        while (i < bi.cells.size() && j < bj.cells.size()) {
+          if (bi.cells[i] < bj.cells[j]) { ++i; continue; }
+          if (bi.cells[i] > bj.cells[j]) { ++j; continue; }
+          int64_t e = bi.cells[i];
+          if (ad) {  // the adaptive rule's points of cell e (the same rows for both blocks' functions)
+            const int32_t k = op->ad_index[e];
+            const int64_t npt = op->ad_off[k + 1] - op->ad_off[k];
+            for (int64_t pt = 0; pt < npt; ++pt) {
+              const double Wq = op->ad_w[op->ad_off[k] + pt];
+              const int64_t ri = bi.aoff[i] + pt, rj = bj.aoff[j] + pt;
+              for (int f = 0; f < bi.nf; ++f) {
+                const cplx a = std::conj(bi.phiA[(size_t)ri * bi.nf + f]);
+                const cplx* ga = &bi.gphiA[((size_t)ri * bi.nf + f) * 3];
+                for (int g2 = 0; g2 < bj.nf; ++g2) {
+                  const cplx bb = bj.phiA[(size_t)rj * bj.nf + g2];
+                  const cplx* gb = &bj.gphiA[((size_t)rj * bj.nf + g2) * 3];
+                  const size_t ix = (size_t)(bi.fn0 + f) * nO + (bj.fn0 + g2);
+                  op->Moo[ix] += Wq * a * bb;
+                  op->Hoo_kin[ix] +=
+                      kin * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
+                }
+              }
+            }
+            ++i;
+            ++j;
+            continue;
+          }
+          for (int q = 0; q < nq; ++q) {
+            double Wq = op->W[e * nq + q];
             for (int f = 0; f < bi.nf; ++f) {
-              const cplx a = std::conj(bi.phiA[(size_t)ri * bi.nf + f]);
-              const cplx* ga = &bi.gphiA[((size_t)ri * bi.nf + f) * 3];
+              cplx a = std::conj(bi.phi[(i * nq + q) * bi.nf + f]);
+              const cplx* ga = &bi.gphi[((i * nq + q) * bi.nf + f) * 3];
               for (int g2 = 0; g2 < bj.nf; ++g2) {
-                const cplx bb = bj.phiA[(size_t)rj * bj.nf + g2];
-                const cplx* gb = &bj.gphiA[((size_t)rj * bj.nf + g2) * 3];
-                const size_t ix = (size_t)(bi.fn0 + f) * nO + (bj.fn0 + g2);
+                cplx bb = bj.phi[(j * nq + q) * bj.nf + g2];
+                const cplx* gb = &bj.gphi[((j * nq + q) * bj.nf + g2) * 3];
+                size_t ix = (size_t)(bi.fn0 + f) * nO + (bj.fn0 + g2);
                 op->Moo[ix] += Wq * a * bb;
                 op->Hoo_kin[ix] +=
                     kin * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
+                if (uf) {  // -i/2 k . int (Phi_i^* grad Phi_j - grad Phi_i^* Phi_j)
+                  cplx t(0.0, 0.0);
+                  for (int k = 0; k < 3; ++k) t += op->kvec[k] * (a * gb[k] - std::conj(ga[k]) * bb);
+                  op->Hoo_kin[ix] += cplx(0.0, -0.5) * Wq * t;
+                }
               }
             }
           }
           ++i;
           ++j;
-          continue;
         }
-        for (int q = 0; q < nq; ++q) {
-          double Wq = op->W[e * nq + q];
-          for (int f = 0; f < bi.nf; ++f) {
-            cplx a = std::conj(bi.phi[(i * nq + q) * bi.nf + f]);
-            const cplx* ga = &bi.gphi[((i * nq + q) * bi.nf + f) * 3];
-            for (int g2 = 0; g2 < bj.nf; ++g2) {
-              cplx bb = bj.phi[(j * nq + q) * bj.nf + g2];
-              const cplx* gb = &bj.gphi[((j * nq + q) * bj.nf + g2) * 3];
-              size_t ix = (size_t)(bi.fn0 + f) * nO + (bj.fn0 + g2);
-              op->Moo[ix] += Wq * a * bb;
-              op->Hoo_kin[ix] +=
-                  kin * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
-              if (uf) {  // -i/2 k . int (Phi_i^* grad Phi_j - grad Phi_i^* Phi_j)
-                cplx t(0.0, 0.0);
-                for (int k = 0; k < 3; ++k) t += op->kvec[k] * (a * gb[k] - std::conj(ga[k]) * bb);
-                op->Hoo_kin[ix] += cplx(0.0, -0.5) * Wq * t;
-              }
-            }
-          }
-        }
-        ++i;
-        ++j;
       }
     }
+  };
+  {
+    const size_t nbk = op->blocks.size();
+    const size_t nth = std::max<size_t>(1, std::min<size_t>({(size_t)kSetupThreads,
+                                                            (size_t)std::max(1u, std::thread::hardware_concurrency()), nbk}));
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < nth; ++t) pool.emplace_back(pair_rows, nbk * t / nth, nbk * (t + 1) / nth);
+    pair_rows(0, nbk / nth);
+    for (auto& th : pool) th.join();
+  }
   for (auto& b : op->blocks) std::vector<cplx>().swap(b.gphiA);  // set-up only
   // ---- S = (M^oo)^-1/2; for the Poisson operator the block's own metric is A^oo, so that
   // S A^oo S = I (the enrichment rows' Jacobi factor of the preconditioned Laplacian)
