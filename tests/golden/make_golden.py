@@ -10,6 +10,8 @@ library.  The paper prints no values that apply to these synthetic operators.
     python tests/golden/make_golden.py kpoint_passes   (about 20 min)
     python tests/golden/make_golden.py diamond64_pass1 (about 40 min, ~20 GB of host memory)
     python tests/golden/make_golden.py poisson_diamond8 (about 2 min)
+    python tests/golden/make_golden.py uform_kpoints    (about 5 min)
+    python tests/golden/make_golden.py adaptive_diamond8 (about 10 min)
 """
 import os
 import sys
@@ -173,8 +175,55 @@ def poisson_diamond8():
     np.savez_compressed(os.path.join(HERE, "poisson_diamond8_oracle.npz"), rho=rho, phi=phi)
 
 
+def uform_kpoints():
+    """diamond8 in the periodic-function k-point form (oracle/uform.py) at the Monkhorst-Pack
+    k-points with the fewest and the most vectors: sampled rows of Ht_k X and column norms."""
+    from oracle.uform import UFormOperator
+    base = wl.config("diamond8").system
+    ks = wl.monkhorst_pack_2(base.L)
+    out = {}
+    t = time.time()
+    for q in (0, 7):
+        kv = ks[q]
+        op = UFormOperator(base.with_k(kv), kv)
+        nv = wl.KPOINT_NV[q]
+        X0 = wl.start_block(op.n_tot, nv, 10 + q, complex_=True)
+        rows = sample_rows(op.N, op.n_enr, 100, 50 + q)
+        hx_rows = np.empty((rows.size, nv), dtype=np.complex128)
+        colnorm = np.empty(nv)
+        for j0 in range(0, nv, 32):
+            HX = op.apply(X0[:, j0:j0 + 32])
+            hx_rows[:, j0:j0 + 32] = HX[rows]
+            colnorm[j0:j0 + 32] = np.linalg.norm(HX, axis=0)
+        out[f"k{q}"] = kv
+        out[f"rows{q}"] = rows
+        out[f"hx_rows{q}"] = hx_rows
+        out[f"hx_colnorm{q}"] = colnorm
+        print("u-form k-point", q, nv, time.time() - t, flush=True)
+    np.savez_compressed(os.path.join(HERE, "uform_kpoints_oracle.npz"), **out)
+
+
+def adaptive_diamond8():
+    """diamond8 with the enrichment integrals on the adaptive rule (oracle/adaptive.py, tol 1e-6,
+    depth 2): the rule's point count per cell, sampled rows of Ht X for 16 vectors, column norms,
+    and the eigenvalues of M^oo."""
+    from oracle.adaptive import AdaptiveOEFEOperator
+    cfg = wl.config("diamond8")
+    t = time.time()
+    op = AdaptiveOEFEOperator(cfg.system, 1e-6, 2)
+    print("adaptive operator", op.rule.n_points, time.time() - t, flush=True)
+    X0 = wl.start_block(op.n_tot, 16, cfg.x0_seed)
+    rows = sample_rows(op.N, op.n_enr, 200, 23)
+    HX = op.apply(X0)
+    counts = np.array([op.rule.points[e].shape[0] for e in op.rule.cells.tolist()], dtype=np.int64)
+    np.savez_compressed(os.path.join(HERE, "adaptive_diamond8_oracle.npz"), tol=1e-6, max_depth=2,
+                        cells=op.rule.cells, counts=counts, rows=rows, hx_rows=HX[rows],
+                        hx_colnorm=np.linalg.norm(HX, axis=0), Moo_eigs=op.enr.Moo_eigs)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["diamond8"]
     for w in which:
         {"diamond8": diamond8, "diamond64": diamond64, "kpoints": kpoints, "kpoint_passes": kpoint_passes,
-         "diamond64_pass1": diamond64_pass1, "poisson_diamond8": poisson_diamond8}[w]()
+         "diamond64_pass1": diamond64_pass1, "poisson_diamond8": poisson_diamond8, "uform_kpoints": uform_kpoints,
+         "adaptive_diamond8": adaptive_diamond8}[w]()

@@ -11,8 +11,12 @@
   (1e-10); the plain oefe_op_set_potential and dE/dV of band_energy_grad are refused.
 * Five ChFSI passes against the oracle's passes (Ritz values to 1e-9 relative), and the density
   at the Gauss points from the filtered block against the oracle's fields (1e-12).
+* diamond8 (tol 1e-6, depth 2; 601,000 rule points) against the oracle's stored values
+  (tests/golden/make_golden.py adaptive_diamond8): the rule's point count in every cell, sampled
+  rows of Ht X column by column and the column norms to 1e-10, the eigenvalues of M^oo to 1e-12.
 """
 import dataclasses
+import os
 
 import numpy as np
 import pytest
@@ -24,6 +28,7 @@ from paper_2010_09701_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 K = np.array([0.21, -0.13, 0.07])
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -130,3 +135,28 @@ def test_adaptive_chfsi_passes_and_density_vs_oracle(lib):
     rho = lib.density(g, X, torch.from_numpy(wts)).cpu().numpy()
     rho_o = oocc.density(o, X0, wts)
     assert np.abs(rho - rho_o).max() <= 1e-12 * np.abs(rho_o).max()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "adaptive_diamond8_oracle.npz")), reason="golden file missing")
+def test_adaptive_diamond8_vs_stored_oracle(lib):
+    import torch
+    g = np.load(os.path.join(GOLD, "adaptive_diamond8_oracle.npz"))
+    cfg = wl.config("diamond8")
+    s = cfg.system
+    op = lib.Operator(s, adaptive=(float(g["tol"]), int(g["max_depth"])))
+    n, xyz, _ = op.adaptive_points()
+    assert n == int(g["counts"].sum())
+    h = s.L / s.nc
+    c = np.floor(xyz / h).astype(np.int64)
+    cell = c[:, 0] + s.nc * (c[:, 1] + s.nc * c[:, 2])
+    per_cell = np.bincount(cell, minlength=s.nc ** 3)
+    assert np.array_equal(per_cell[g["cells"]], g["counts"])
+    X0 = wl.start_block(op.n_tot, 16, cfg.x0_seed)
+    Y = lib.ham_apply(op, torch.from_numpy(X0).cuda()).cpu().numpy()
+    rows, ref = g["rows"], g["hx_rows"]
+    err = np.abs(Y[rows] - ref).max(axis=0) / np.abs(ref).max(axis=0)
+    assert err.max() <= 1e-10, err.max()
+    cn = np.linalg.norm(Y, axis=0)
+    assert np.abs(cn - g["hx_colnorm"]).max() <= 1e-10 * cn.max()
+    _, eig = op.get_enrichment()
+    assert np.abs(eig - g["Moo_eigs"]).max() <= 1e-12 * np.abs(g["Moo_eigs"]).max()

@@ -10,7 +10,12 @@ oracle (oracle/uform.py).
 * Batches: two k-points of the form filtered in one batched call equal the per-operator filters
   bit for bit; a batch mixing the two forms is refused.
 * set_potential / get_potential take and return V without the form's |k|^2/2.
+* diamond8 at the Monkhorst-Pack k-points with the fewest and the most vectors (48, 96):
+  sampled rows of Ht_k X column by column to 1e-10 and the column norms of the whole product to
+  1e-10 against the oracle's stored values (tests/golden/make_golden.py uform_kpoints).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -20,6 +25,7 @@ from paper_2010_09701_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 K = np.array([0.21, -0.13, 0.07])
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -122,3 +128,20 @@ def test_uform_potential_round_trip(lib):
     gop.set_potential(V2)
     V3, _ = gop.get_potential()
     assert np.abs(V3 - V2).max() <= 1e-13 * np.abs(V2).max()
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "uform_kpoints_oracle.npz")), reason="golden file missing")
+def test_uform_diamond8_kpoint_rows(lib):
+    import torch
+    g = np.load(os.path.join(GOLD, "uform_kpoints_oracle.npz"))
+    base = wl.config("diamond8").system
+    for q in (0, 7):
+        kv = g[f"k{q}"]
+        op = lib.Operator(base.with_k(kv), uform=True)
+        X0 = wl.start_block(op.n_tot, wl.KPOINT_NV[q], 10 + q, complex_=True)
+        Y = lib.ham_apply(op, torch.from_numpy(X0).cuda()).cpu().numpy()
+        rows, ref = g[f"rows{q}"], g[f"hx_rows{q}"]
+        err = np.abs(Y[rows] - ref).max(axis=0) / np.abs(ref).max(axis=0)
+        assert err.max() <= 1e-10, (q, err.max())
+        cn = np.linalg.norm(Y, axis=0)
+        assert np.abs(cn - g[f"hx_colnorm{q}"]).max() <= 1e-10 * cn.max(), q
