@@ -338,3 +338,106 @@ class AdaptiveOEFEOperator(OEFEOperator):
             V_adapt = nuclear_potential(self.rule.all_points(), system.pos, system.Z, system.sigma, system.L)
         self.V_adapt = np.ascontiguousarray(V_adapt, dtype=np.float64)
         self.enr = AdaptiveEnrichment(self.mesh, system, self.m, self.kvec, self.rule, self.V_adapt)
+
+
+class AdaptiveUFormOperator:
+    """The k-point operator in the periodic-function form (oracle/uform.py: eqnksdftu,
+    eqnUOEFEAtomic, eqnHOEFEelelements with its k terms, the enrichment blocks' first-derivative
+    term in the Hermitian form) with the enrichment integrals on the adaptive rule: N^A =
+    exp(-i k.(x - R^x)) psi~ at the rule's points, the orthogonalization numerator, M^oo, H^oo
+    and H^co on the rule; H^cc on the Gauss rule.  V_adapt: V at the rule's points (without the
+    |k|^2/2, which is added here as on the Gauss points)."""
+
+    def __init__(self, system, kvec, tol: float, max_depth: int, V: np.ndarray | None = None,
+                 V_adapt: np.ndarray | None = None):
+        from .uform import UFormOperator
+        base = UFormOperator(system, kvec, V=V)
+        self.base = base
+        self.mesh = mesh = base.mesh
+        self.kvec = k = base.kvec
+        self.N, self.n_enr, self.n_tot = base.N, base.n_enr, base.n_tot
+        self.dm12, self.Hcc, self.V = base.dm12, base.Hcc, base.V
+        self.rule = rule = AdaptiveRule(mesh, system, tol, max_depth)
+        if V_adapt is None:
+            V_adapt = nuclear_potential(rule.all_points(), system.pos, system.Z, system.sigma, system.L)
+        self.V_adapt = np.ascontiguousarray(V_adapt, dtype=np.float64)
+        k2 = 0.5 * float(k @ k)
+        s = 2.0 / mesh.h
+        m = base.m
+        atom_of = np.array([f.atom for f in system.enr], dtype=np.int64)
+        fn = []
+        for I, cells in rule.support.items():
+            idx = np.nonzero(atom_of == I)[0]
+            F = idx.size
+            NA, gNA = [], []
+            for e in cells.tolist():
+                x = rule.points[e]
+                d = min_image(x - system.pos[I][None, :], mesh.L)
+                ph = np.exp(-1j * (d @ k))
+                v = np.zeros((x.shape[0], F), dtype=np.complex128)
+                g = np.zeros((x.shape[0], F, 3), dtype=np.complex128)
+                for j, i in enumerate(idx):
+                    f = system.enr[i]
+                    vv, gg = atomic_function(d, f.power, f.zeta, f.axis, system.r0, system.r1)
+                    v[:, j] = ph * vv
+                    g[:, j, :] = ph[:, None] * (gg - 1j * k[None, :] * vv[:, None])
+                NA.append(v)
+                gNA.append(g)
+            dnum = np.zeros((mesh.N, F), dtype=np.complex128)
+            for ci, e in enumerate(cells.tolist()):
+                np.add.at(dnum, mesh.cell_dofs[e], rule.B[e].T @ (rule.weights[e][:, None] * NA[ci]))
+            c = dnum / m[:, None]
+            Phi, gPhi = [], []
+            for ci, e in enumerate(cells.tolist()):
+                ce = c[mesh.cell_dofs[e]]  # periodic FE functions: no phase
+                Phi.append(NA[ci] - rule.B[e] @ ce)
+                gp = gNA[ci].copy()
+                for dd in range(3):
+                    gp[:, :, dd] -= s * (rule.G[e][dd] @ ce)
+                gPhi.append(gp)
+            fn.append((I, idx, cells, Phi, gPhi))
+        self.atom_fn_adapt = fn
+        nO = self.n_enr
+        Moo = np.zeros((nO, nO), dtype=np.complex128)
+        Hoo = np.zeros((nO, nO), dtype=np.complex128)
+        for (I, iI, cI, PI, gI) in fn:
+            for (J, iJ, cJ, PJ, gJ) in fn:
+                common, aI, aJ = np.intersect1d(cI, cJ, return_indices=True)
+                for e, i, j in zip(common.tolist(), aI.tolist(), aJ.tolist()):
+                    w = rule.weights[e]
+                    Ve = self.V_adapt[rule.cell_slice(e)] + k2
+                    a, b, ga, gb = PI[i], PJ[j], gI[i], gJ[j]
+                    Moo[np.ix_(iI, iJ)] += np.conj(a).T @ (w[:, None] * b)
+                    Hoo[np.ix_(iI, iJ)] += 0.5 * np.einsum("pfd,pgd->fg", np.conj(ga) * w[:, None, None], gb)
+                    Hoo[np.ix_(iI, iJ)] += -0.5j * np.einsum("pf,pgd,d->fg", np.conj(a) * w[:, None], gb, k)
+                    Hoo[np.ix_(iI, iJ)] += 0.5j * np.einsum("pfd,pg,d->fg", np.conj(ga) * w[:, None, None], b, k)
+                    Hoo[np.ix_(iI, iJ)] += np.conj(a).T @ ((w * Ve)[:, None] * b)
+        self.Moo, self.Hoo = Moo, Hoo
+        rows, cols, vals = [], [], []
+        for (I, idx, cells, Phi, gPhi) in fn:
+            for ci, e in enumerate(cells.tolist()):
+                w = rule.weights[e]
+                Ve = self.V_adapt[rule.cell_slice(e)] + k2
+                he = rule.B[e].T @ ((w * Ve)[:, None] * Phi[ci])
+                for dd in range(3):
+                    he += 0.5 * s * rule.G[e][dd].T @ (w[:, None] * gPhi[ci][:, :, dd])
+                    he += -0.5j * k[dd] * rule.B[e].T @ (w[:, None] * gPhi[ci][:, :, dd])
+                    he += 0.5j * k[dd] * s * rule.G[e][dd].T @ (w[:, None] * Phi[ci])
+                rows.append(np.repeat(mesh.cell_dofs[e], idx.size))
+                cols.append(np.tile(idx, mesh.nd))
+                vals.append(he.reshape(-1))
+        self.Hco = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                 shape=(mesh.N, nO)).tocsr()
+        self.Hco.sum_duplicates()
+        lam, U = np.linalg.eigh(Moo)
+        self.Moo_eigs = lam
+        self.S = (U / np.sqrt(lam)[None, :]) @ np.conj(U.T)
+
+    def apply(self, X: np.ndarray) -> np.ndarray:
+        """Ht_k X for a block X [n_tot, nv] (complex)."""
+        N = self.N
+        Zc = self.dm12[:, None] * X[:N].astype(np.complex128)
+        Zo = self.S @ X[N:].astype(np.complex128)
+        Yc = self.dm12[:, None] * (self.Hcc @ Zc + self.Hco @ Zo)
+        Yo = self.S @ (self.Hco.conj().T @ Zc + self.Hoo @ Zo)
+        return np.concatenate([Yc, Yo], axis=0)

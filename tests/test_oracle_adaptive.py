@@ -15,6 +15,9 @@
   the functions do not vanish split to the same depth) as tol falls: at tol = 1e-7 to 1e-8 with
   V = 0 (the trial integrals cover every integrand), to 2e-6 with the nuclear potential (V is
   not among the trial integrals); M^oo stays Hermitian positive definite.
+* The periodic-function k-point form on the rule: max_depth = 0 gives the blocks of
+  oracle/uform.py; at k = 0 the blocks equal the Gamma-point operator's on the same rule; M^oo
+  and H^oo are Hermitian.
 """
 import dataclasses
 
@@ -127,3 +130,23 @@ def test_blocks_approach_uniform_refinement(kvec, zero_v, bound):
         assert np.linalg.eigvalsh(M).min() > 0
     assert errs[0] > errs[1] > errs[2], errs
     assert errs[2] < bound, errs
+
+
+def test_uform_depth0_is_the_uform_operator():
+    from oracle.uform import UFormOperator
+    s = wl.tiny_system(nc=3, p=2, n_atoms=2, seed=7, L=5.0, r0=0.8, r1=2.0).with_k(K)
+    u = UFormOperator(s, K)
+    a = ad.AdaptiveUFormOperator(s, K, 1e-6, 0)
+    for X, Y in ((a.Moo, u.Moo), (a.Hoo, u.Hoo), (a.Hco.toarray(), u.Hco.toarray())):
+        assert np.abs(X - Y).max() <= 1e-13 * np.abs(Y).max()
+
+
+def test_uform_adaptive_hermitian_and_k0_is_gamma():
+    s = _sharp(nc=3, p=2)
+    a = ad.AdaptiveUFormOperator(s.with_k(K), K, 1e-5, 2)
+    assert np.abs(a.Hoo - a.Hoo.conj().T).max() <= 1e-13 * np.abs(a.Hoo).max()
+    assert np.abs(a.Moo - a.Moo.conj().T).max() <= 1e-14 * np.abs(a.Moo).max()
+    z = ad.AdaptiveUFormOperator(s.with_k(np.zeros(3)), np.zeros(3), 1e-5, 2)
+    g = ad.AdaptiveOEFEOperator(s, 1e-5, 2)
+    for X, Y in ((z.Moo, g.enr.Moo), (z.Hoo, g.enr.Hoo), (z.Hco.toarray(), g.enr.Hco.toarray())):
+        assert np.abs(X - Y).max() <= 1e-13 * np.abs(Y).max()
