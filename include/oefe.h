@@ -126,8 +126,18 @@ int oefe_op_create_uform(const oefe_system_desc* desc, oefe_op* out);
  * supports (cells ascending); the orthogonalization numerator (eqnorthC), M^oo, H^oo and H^co
  * use it, H^cc keeps the Gauss rule.  V at the rule's points is the nuclear potential of desc
  * at creation; oefe_op_set_potential_adaptive replaces it.  0 < tol < 1, 0 <= max_depth <= 5,
- * desc->n_enr >= 1.  Errors as oefe_op_create. */
+ * desc->n_enr >= 1.  Errors as oefe_op_create.  The periodic-function k-point form:
+ * oefe_op_create_uform_adaptive. */
 int oefe_op_create_adaptive(const oefe_system_desc* desc, double tol, int32_t max_depth, oefe_op* out);
+
+/* The k-point operator in the periodic-function form (as oefe_op_create_uform: Sec. II
+ * eqnksdftu; Sec. III.A eqnUOEFEAtomic, eqnHOEFEelelements) with its enrichment integrals on
+ * the adaptive rule of oefe_op_create_adaptive (Sec. III.B; the rule is built from the atomic
+ * functions without phase, the same for every k): exp(-i k.(x - R^x)) psi~ at the rule's
+ * points, the first-derivative terms and |k|^2/2 on the rule.  oefe_op_set_potential_adaptive
+ * takes both potentials without the |k|^2/2.  desc->kvec is required.  Errors as
+ * oefe_op_create_adaptive. */
+int oefe_op_create_uform_adaptive(const oefe_system_desc* desc, double tol, int32_t max_depth, oefe_op* out);
 
 /* The points of the adaptive rule of an operator from oefe_op_create_adaptive: *n_points, and
  * (host, either may be NULL) xyz [n_points x 3] and weights [n_points], in rule order (cells

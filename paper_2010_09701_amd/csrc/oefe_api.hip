@@ -1295,6 +1295,21 @@ int oefe_op_create_uform(const oefe_system_desc* desc, oefe_op* out) {
   return finish_create(op, desc, out);
 }
 
+int oefe_op_create_uform_adaptive(const oefe_system_desc* desc, double tol, int32_t max_depth, oefe_op* out) {
+  if (int rc = check_desc(desc, out)) return rc;
+  if (!desc->kvec) return fail(OEFE_EINVAL, "the periodic-function form needs a Bloch wavevector (kvec)");
+  if (!(tol > 0.0 && tol < 1.0) || max_depth < 0 || max_depth > kAdaptMaxDepth)
+    return fail(OEFE_EINVAL, "adaptive rule: need 0 < tol < 1 and 0 <= max_depth <= 5");
+  if (desc->n_enr < 1) return fail(OEFE_EINVAL, "adaptive rule: no enrichment functions");
+  oefe_op_s* op = new (std::nothrow) oefe_op_s();
+  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  op->uform = true;
+  op->adaptive = true;
+  op->ad_tol = tol;
+  op->ad_depth = max_depth;
+  return finish_create(op, desc, out);
+}
+
 int oefe_op_create_adaptive(const oefe_system_desc* desc, double tol, int32_t max_depth, oefe_op* out) {
   if (int rc = check_desc(desc, out)) return rc;
   if (!(tol > 0.0 && tol < 1.0) || max_depth < 0 || max_depth > kAdaptMaxDepth)
@@ -1437,6 +1452,10 @@ int oefe_op_set_potential_adaptive(oefe_op op, const double* V, const double* V_
   if (hipMemcpyAsync(op->d.V, V, (size_t)nqt * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
       hipMemcpyAsync(op->d.a_V, V_adapt, (size_t)np * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail(OEFE_EDEVICE, "oefe_op_set_potential_adaptive: copy of V failed");
+  if (op->vshift != 0.0) {  // the periodic-function form's |k|^2/2 rides on V
+    hipLaunchKernelGGL(shift_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s, op->d.V, op->vshift, nqt);
+    hipLaunchKernelGGL(shift_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, op->d.a_V, op->vshift, np);
+  }
   return rebuild_potential_device(op, s);
 }
 

@@ -572,7 +572,7 @@ int build_adaptive_rule(oefe_op_s* op, const oefe_system_desc* desc, const doubl
       }
       v -= desc->Z[I] * erf_over_r(std::sqrt(d2), desc->sigma);
     }
-    op->ad_V[i] = v;
+    op->ad_V[i] = v + op->vshift;  // the periodic-function form's |k|^2/2 rides on V
   }
   return OEFE_OK;
 }
@@ -903,8 +903,8 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
   // ---- adaptive quadrature of the enrichment integrals: the rule on the union of the supports
   const bool ad = op->adaptive;
   if (ad) {
-    if (pois || uf) {
-      err = "adaptive quadrature is built for the Kohn-Sham operator in the Bloch-function form";
+    if (pois) {
+      err = "adaptive quadrature is built for the Kohn-Sham operator";
       return OEFE_EUNSUPPORTED;
     }
     if (int rc = build_adaptive_rule(op, desc, xi, err)) return rc;
@@ -973,7 +973,10 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
               d[kk] = dr - op->L * t[kk];
             }
             cplx ph(1.0, 0.0);
-            if (op->cplx) {
+            if (uf) {  // exp(-i k . (x - R^x)) (eqnUOEFEAtomic)
+              const double arg = -(op->kvec[0] * d[0] + op->kvec[1] * d[1] + op->kvec[2] * d[2]);
+              ph = cplx(std::cos(arg), std::sin(arg));
+            } else if (op->cplx) {
               const double arg = op->L * (op->kvec[0] * t[0] + op->kvec[1] * t[1] + op->kvec[2] * t[2]);
               ph = cplx(std::cos(arg), std::sin(arg));
             }
@@ -982,7 +985,8 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
               double val, gr[3];
               atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
               NAa[(size_t)row * nf + f] = ph * val;
-              for (int kk = 0; kk < 3; ++kk) gNAa[((size_t)row * nf + f) * 3 + kk] = ph * gr[kk];
+              for (int kk = 0; kk < 3; ++kk)  // the periodic-function form: e^{-ik.d} (grad f - i k f)
+                gNAa[((size_t)row * nf + f) * 3 + kk] = ph * (uf ? cplx(gr[kk], -op->kvec[kk] * val) : cplx(gr[kk], 0.0));
             }
           }
         }
@@ -1115,10 +1119,23 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
             leaf_matrix(op, l, 2, true, Dz);
             const int64_t row0 = b.aoff[ci] + (l * nq3 - op->ad_off[k]);
             for (int dd = 0; dd < 3; ++dd) {
+              const double* Mx = dd == 0 ? Dx : Bx;
+              const double* My = dd == 1 ? Dy : By;
+              const double* Mz = dd == 2 ? Dz : Bz;
               for (int q = 0; q < nq; ++q)
                 tin[q] = kin * s2h * op->ad_w[l * nq3 + q] * b.gphiA[((size_t)(row0 + q) * nf + f) * 3 + dd];
-              tp_backward<cplx>(P1, dd == 0 ? Dx : Bx, dd == 1 ? Dy : By, dd == 2 ? Dz : Bz, tin.data(), tout.data());
+              tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
               for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+              if (uf) {  // the first-derivative term in Hermitian form, on the rule's points
+                const cplx mi(0.0, -0.5 * op->kvec[dd]), pi(0.0, 0.5 * op->kvec[dd]);
+                for (int q = 0; q < nq; ++q)
+                  tin[q] = mi * op->ad_w[l * nq3 + q] * b.gphiA[((size_t)(row0 + q) * nf + f) * 3 + dd];
+                tp_backward<cplx>(P1, Bx, By, Bz, tin.data(), tout.data());
+                for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+                for (int q = 0; q < nq; ++q) tin[q] = pi * s2h * op->ad_w[l * nq3 + q] * b.phiA[(size_t)(row0 + q) * nf + f];
+                tp_backward<cplx>(P1, Mx, My, Mz, tin.data(), tout.data());
+                for (int a = 0; a < op->nd; ++a) acc[a] += tout[a];
+              }
             }
           }
           for (int a = 0; a < op->nd; ++a) {
@@ -1206,6 +1223,11 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
                   op->Moo[ix] += Wq * a * bb;
                   op->Hoo_kin[ix] +=
                       kin * Wq * (std::conj(ga[0]) * gb[0] + std::conj(ga[1]) * gb[1] + std::conj(ga[2]) * gb[2]);
+                  if (uf) {  // -i/2 k . int (Phi_i^* grad Phi_j - grad Phi_i^* Phi_j)
+                    cplx t(0.0, 0.0);
+                    for (int kk = 0; kk < 3; ++kk) t += op->kvec[kk] * (a * gb[kk] - std::conj(ga[kk]) * bb);
+                    op->Hoo_kin[ix] += cplx(0.0, -0.5) * Wq * t;
+                  }
                 }
               }
             }

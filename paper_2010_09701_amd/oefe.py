@@ -60,6 +60,7 @@ def _load():
         "oefe_op_create_diagonal": ([vp, i64, ctypes.POINTER(vp)], i32),
         "oefe_op_create_uform": ([vp, ctypes.POINTER(vp)], i32),
         "oefe_op_create_adaptive": ([vp, dbl, i32, ctypes.POINTER(vp)], i32),
+        "oefe_op_create_uform_adaptive": ([vp, dbl, i32, ctypes.POINTER(vp)], i32),
         "oefe_op_adaptive_points": ([vp, vp, vp, vp], i32),
         "oefe_op_set_potential_adaptive": ([vp, vp, vp, vp], i32),
         "oefe_op_destroy": ([vp], i32),
@@ -105,6 +106,7 @@ _lib = _load()
 
 EXPORTED = [
     "oefe_op_create", "oefe_op_create_diagonal", "oefe_op_create_uform", "oefe_op_create_adaptive",
+    "oefe_op_create_uform_adaptive",
     "oefe_op_adaptive_points", "oefe_op_set_potential_adaptive", "oefe_op_destroy", "oefe_op_dims", "oefe_op_set_potential",
     "oefe_op_get_potential", "oefe_op_get_enrichment", "oefe_work_size", "ham_apply", "chebyshev_filter",
     "chebyshev_filter_mixed", "chebyshev_filter_dev", "chebyshev_filter_batched", "oefe_batched_work_size", "oefe_set_launch_shape",
@@ -183,6 +185,10 @@ class Operator:
             torch.cuda.current_device()
             if poisson:
                 _check(_lib.oefe_poisson_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_poisson_create")
+            elif uform and adaptive is not None:
+                tol, depth = adaptive
+                _check(_lib.oefe_op_create_uform_adaptive(ctypes.byref(d), float(tol), int(depth),
+                                                          ctypes.byref(self._h)), "oefe_op_create_uform_adaptive")
             elif uform:
                 _check(_lib.oefe_op_create_uform(ctypes.byref(d), ctypes.byref(self._h)), "oefe_op_create_uform")
             elif adaptive is not None:

@@ -11,6 +11,9 @@
   (1e-10); the plain oefe_op_set_potential and dE/dV of band_energy_grad are refused.
 * Five ChFSI passes against the oracle's passes (Ritz values to 1e-9 relative), and the density
   at the Gauss points from the filtered block against the oracle's fields (1e-12).
+* The periodic-function k-point form on the rule (oefe_op_create_uform_adaptive): ham_apply
+  against the oracle to 1e-10, after oefe_op_set_potential_adaptive too (potentials without the
+  |k|^2/2), and two k-points filtered in one batched call equal the per-operator filters.
 * diamond8 (tol 1e-6, depth 2; 601,000 rule points) against the oracle's stored values
   (tests/golden/make_golden.py adaptive_diamond8): the rule's point count in every cell, sampled
   rows of Ht X column by column and the column norms to 1e-10, the eigenvalues of M^oo to 1e-12.
@@ -160,3 +163,45 @@ def test_adaptive_diamond8_vs_stored_oracle(lib):
     assert np.abs(cn - g["hx_colnorm"]).max() <= 1e-10 * cn.max()
     _, eig = op.get_enrichment()
     assert np.abs(eig - g["Moo_eigs"]).max() <= 1e-12 * np.abs(g["Moo_eigs"]).max()
+
+
+def test_adaptive_uform_vs_oracle(lib):
+    import torch
+    s = _sharp(3, 3)
+    o = ad.AdaptiveUFormOperator(s.with_k(K), K, 1e-6, 2)
+    g = lib.Operator(s.with_k(K), uform=True, adaptive=(1e-6, 2))
+    n, xyz, _ = g.adaptive_points()
+    assert n == o.rule.n_points and np.abs(xyz - o.rule.all_points()).max() <= 1e-13 * s.L
+    X = _block(o.n_tot, 5, 7, True)
+    Y = lib.ham_apply(g, torch.from_numpy(X).cuda()).cpu().numpy()
+    Yo = o.apply(X)
+    err = np.abs(Y - Yo).max(axis=0) / np.abs(Yo).max(axis=0)
+    assert err.max() <= 1e-10, err
+    rng = np.random.default_rng(8)
+    V2 = o.V + rng.uniform(-1, 1, size=o.V.shape)
+    Va2 = o.V_adapt + rng.uniform(-1, 1, size=o.V_adapt.shape)
+    g.set_potential(V2, Va2)
+    o2 = ad.AdaptiveUFormOperator(s.with_k(K), K, 1e-6, 2, V=V2, V_adapt=Va2)
+    Y = lib.ham_apply(g, torch.from_numpy(X).cuda()).cpu().numpy()
+    Yo = o2.apply(X)
+    err = np.abs(Y - Yo).max(axis=0) / np.abs(Yo).max(axis=0)
+    assert err.max() <= 1e-10, err
+
+
+def test_adaptive_uform_batched_equals_single(lib):
+    import torch
+    s = _sharp(3, 3)
+    ks = [K, -0.5 * K]
+    ops = [lib.Operator(s.with_k(k), uform=True, adaptive=(1e-6, 2)) for k in ks]
+    X = [torch.from_numpy(_block(ops[0].n_tot, 4 + i, 11 + i, True)).cuda() for i in range(2)]
+    abc = []
+    for o in ops:
+        v0 = torch.from_numpy(wl.lanczos_start(o.n_tot, 2).astype(np.complex128)).cuda()
+        a0, b, a = lib.lanczos_bounds(o, v0, 8, with_cut=True)
+        abc.append((a, b, a0))
+    Xb = [x.clone() for x in X]
+    lib.chebyshev_filter_batched(ops, Xb, 6, abc)
+    for o, x, xb, (a, b, a0) in zip(ops, X, Xb, abc):
+        xs = x.clone()
+        lib.chebyshev_filter(o, xs, 6, a, b, a0)
+        assert torch.equal(xs, xb)
