@@ -566,6 +566,9 @@ int upload_operator(oefe_op_s* op, std::string& err) {
       // partials of the potential part of H^co per (flattened support cell, local node, function)
       if ((rc = dalloc(&op->d.hpart, (size_t)boff[nb] * op->nd * op->FMAX * E, err))) return rc;
       op->n_cf = boff[nb];
+      // H^oo's potential part in chunks of each block pair's common cells: about 2048 workgroups
+      op->hoo_nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, 2048 / ((int64_t)nb * nb)));
+      if ((rc = dalloc(&op->d.hoo_part, (size_t)nb * nb * op->hoo_nchunk * op->FMAX * op->FMAX * E, err))) return rc;
     }
     if ((rc = dput(&op->d.blk_fn0, fn0, err))) return rc;
     if ((rc = dput(&op->d.blk_nf, nf, err))) return rc;
@@ -607,7 +610,7 @@ void free_device(oefe_op_s* op) {
   dfree(d.lambda); dfree(d.lambdaf); dfree(d.bf_mats);
   dfree(d.W); dfree(d.V); dfree(d.msq); dfree(d.hkin); dfree(d.Hoo_kin); dfree(d.row_blk); dfree(d.rpos);
   dfree(d.a_w); dfree(d.a_V); dfree(d.a_leafB); dfree(d.a_off); dfree(d.cf_acell); dfree(d.cf_aoff);
-  dfree(d.phiA); dfree(d.hpart);
+  dfree(d.phiA); dfree(d.hpart); dfree(d.hoo_part);
   dfree(d.bsmear); dfree(d.blk_cf0); dfree(d.rr_ptr); dfree(d.rr_ent); dfree(d.cf_cell); dfree(d.csr2tile); dfree(d.hp_ptr); dfree(d.hp_i);
   dfree(d.hp_j);
 }
@@ -865,9 +868,10 @@ __global__ __launch_bounds__(256) void hco_rebuild_kernel(HcoRebuild a) {
 
 // H^oo = kinetic part + sum over the common support cells (ascending) of two blocks and their
 // quadrature points (the Gauss points, or the adaptive rule's points) of w V conj(N^O_i) N^O_j.
-// One workgroup per block pair (bi, bj): thread t takes the entry item = t mod (nf_i nf_j) and
-// the point lane t / (nf_i nf_j), lanes striding over each cell's points; the lanes' sums are
-// added in lane order (a fixed summation order).
+// One workgroup per (block pair (bi, bj), chunk of their common cells): thread t takes the entry
+// item = t mod (nf_i nf_j) and the point lane t / (nf_i nf_j), lanes striding over each cell's
+// points; the lanes' sums are added in lane order into the chunk's partial, and
+// hoo_sum_kernel adds the chunks in order (a fixed summation order throughout).
 struct HooPair {
   const double *W, *V, *phi;  // the Gauss rule
   const int32_t* cf_cell;
@@ -876,17 +880,19 @@ struct HooPair {
   const int32_t* cf_acell;
   const double* Hoo_kin;
   const int64_t* hp_ptr;
-  const int32_t *hp_i, *hp_j, *blk_fn0, *blk_nf;
+  const int32_t *hp_i, *hp_j, *blk_fn0, *blk_nf, *fn_blk;
   double* Hoo;
   float* Hoof;
-  int nO, nb, FMAX, nq;
+  double* part;  // [pair][chunk][FMAX^2] (complex: x2)
+  int nO, nb, FMAX, nq, nchunk;
 };
 
 template <bool CPLX>
 __global__ __launch_bounds__(256) void hoo_pair_kernel(HooPair a) {
   constexpr int E = CPLX ? 2 : 1;
   __shared__ double red[256][E];
-  const int bi = blockIdx.x / a.nb, bj = blockIdx.x - bi * a.nb;
+  const int pair = blockIdx.x / a.nchunk, chunk = blockIdx.x - pair * a.nchunk;
+  const int bi = pair / a.nb, bj = pair - bi * a.nb;
   const int nfi = a.blk_nf[bi], nfj = a.blk_nf[bj], nit = nfi * nfj;
   const int lanes = (int)blockDim.x / nit;
   const int t = threadIdx.x, item = t % nit, lane = t / nit;
@@ -896,7 +902,8 @@ __global__ __launch_bounds__(256) void hoo_pair_kernel(HooPair a) {
   double sr = 0.0, si = 0.0;
   if (lane < lanes) {
     const int64_t pr = (int64_t)bi * a.nb + bj;
-    for (int64_t k = a.hp_ptr[pr]; k < a.hp_ptr[pr + 1]; ++k) {
+    const int64_t k0 = a.hp_ptr[pr], nk = a.hp_ptr[pr + 1] - k0;
+    for (int64_t k = k0 + nk * chunk / a.nchunk; k < k0 + nk * (chunk + 1) / a.nchunk; ++k) {
       const int ci = a.hp_i[k], cj = a.hp_j[k];
       int64_t np, p0 = 0, e = 0;
       const double *pa, *pb;
@@ -926,19 +933,39 @@ __global__ __launch_bounds__(256) void hoo_pair_kernel(HooPair a) {
   if (CPLX) red[t][E - 1] = si;
   __syncthreads();
   if (lane == 0) {
-    const int i = a.blk_fn0[bi] + f, j = a.blk_fn0[bj] + g;
-    const int64_t o = ((int64_t)i * a.nO + j) * E;
-    double tr = a.Hoo_kin[o], ti = CPLX ? a.Hoo_kin[o + 1] : 0.0;
+    double tr = 0.0, ti = 0.0;
     for (int l = 0; l < lanes; ++l) {
       tr += red[l * nit + item][0];
       if (CPLX) ti += red[l * nit + item][E - 1];
     }
-    a.Hoo[o] = tr;
-    a.Hoof[o] = (float)tr;
-    if (CPLX) {
-      a.Hoo[o + 1] = ti;
-      a.Hoof[o + 1] = (float)ti;
-    }
+    double* o = a.part + (((int64_t)pair * a.nchunk + chunk) * a.FMAX * a.FMAX + item) * E;
+    o[0] = tr;
+    if (CPLX) o[1] = ti;
+  }
+}
+
+// H^oo[i][j] = kinetic part + the chunks' partials of the entry, in chunk order; one thread per entry.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void hoo_sum_kernel(HooPair a) {
+  constexpr int E = CPLX ? 2 : 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nO * a.nO) return;
+  const int i = t / a.nO, j = t - i * a.nO;
+  const int bi = a.fn_blk[i], bj = a.fn_blk[j];
+  const int f = i - a.blk_fn0[bi], g = j - a.blk_fn0[bj];
+  const int item = f * a.blk_nf[bj] + g;
+  const int64_t pair = (int64_t)bi * a.nb + bj;
+  double tr = a.Hoo_kin[(int64_t)t * E], ti = CPLX ? a.Hoo_kin[(int64_t)t * E + 1] : 0.0;
+  for (int c = 0; c < a.nchunk; ++c) {
+    const double* p = a.part + ((pair * a.nchunk + c) * a.FMAX * a.FMAX + item) * E;
+    tr += p[0];
+    if (CPLX) ti += p[1];
+  }
+  a.Hoo[(int64_t)t * E] = tr;
+  a.Hoof[(int64_t)t * E] = (float)tr;
+  if (CPLX) {
+    a.Hoo[(int64_t)t * E + 1] = ti;
+    a.Hoof[(int64_t)t * E + 1] = (float)ti;
   }
 }
 
@@ -1420,13 +1447,18 @@ static int rebuild_potential_device(oefe_op op, hipStream_t s) {
       o.a_off = op->d.a_off; o.cf_aoff = op->d.cf_aoff; o.cf_acell = op->d.cf_acell;
     }
     o.Hoo_kin = op->d.Hoo_kin; o.hp_ptr = op->d.hp_ptr; o.hp_i = op->d.hp_i; o.hp_j = op->d.hp_j;
-    o.blk_fn0 = op->d.blk_fn0; o.blk_nf = op->d.blk_nf; o.Hoo = op->d.Hoo; o.Hoof = op->d.Hoof;
+    o.blk_fn0 = op->d.blk_fn0; o.blk_nf = op->d.blk_nf; o.fn_blk = op->d.fn_blk; o.Hoo = op->d.Hoo; o.Hoof = op->d.Hoof;
+    o.part = op->d.hoo_part;
     const int nb = (int)op->blocks.size();
-    o.nO = op->n_enr; o.nb = nb; o.FMAX = op->FMAX; o.nq = op->nq;
-    if (op->cplx)
-      hipLaunchKernelGGL(hoo_pair_kernel<true>, dim3((unsigned)(nb * nb)), dim3(256), 0, s, o);
-    else
-      hipLaunchKernelGGL(hoo_pair_kernel<false>, dim3((unsigned)(nb * nb)), dim3(256), 0, s, o);
+    o.nO = op->n_enr; o.nb = nb; o.FMAX = op->FMAX; o.nq = op->nq; o.nchunk = op->hoo_nchunk;
+    const unsigned g3 = (unsigned)(((int64_t)op->n_enr * op->n_enr + 255) / 256);
+    if (op->cplx) {
+      hipLaunchKernelGGL(hoo_pair_kernel<true>, dim3((unsigned)(nb * nb * op->hoo_nchunk)), dim3(256), 0, s, o);
+      hipLaunchKernelGGL(hoo_sum_kernel<true>, dim3(g3), dim3(256), 0, s, o);
+    } else {
+      hipLaunchKernelGGL(hoo_pair_kernel<false>, dim3((unsigned)(nb * nb * op->hoo_nchunk)), dim3(256), 0, s, o);
+      hipLaunchKernelGGL(hoo_sum_kernel<false>, dim3(g3), dim3(256), 0, s, o);
+    }
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "potential rebuild");

@@ -190,6 +190,7 @@ struct DeviceArrays {
   int64_t* cf_aoff = nullptr;   // flattened support cell -> first row of phiA
   double* phiA = nullptr;       // N^O: phiA[(row * FMAX + f)] (complex: x2)
   double* hpart = nullptr;      // potential part of H^co per (flattened support cell, local node, f)
+  double* hoo_part = nullptr;   // potential part of H^oo per (block pair, chunk of common cells, f, g)
 };
 
 struct AtomBlock {
@@ -253,6 +254,7 @@ struct oefe_op_s {
   std::vector<double> ad_x, ad_w, ad_V;
   std::vector<double> ad_B, ad_D;   // leaf l, direction d: [(l * 3 + d) * P1 + q] * P1 + a
   int64_t n_cf = 0;                 // flattened (block, support cell) pairs
+  int hoo_nchunk = 1;               // chunks of each block pair's common cells (H^oo rebuild)
   int FMAX = 1;
   int64_t n_hrows = 0;  // total rows over blocks
   int64_t n_chunks = 0;
