@@ -330,6 +330,90 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const double* __restrict__
     }
 }
 
+// ---- C = A B on the matrix cores (real, float64): A [n x k] (row stride lda), B [k x m] (row
+// stride ldb, small), C [n x m] (row stride ldc), for the wide blocks' products X R (CholGS) and
+// Q U (Rayleigh-Ritz).  A workgroup takes 128 rows (32 per wave: two 16-row blocks) and 16 NBJ
+// output columns; the column blocks of the same rows are consecutive in the remapped launch
+// index and each XCD takes a contiguous range, so they read those rows of A through one L2.  B
+// is staged in LDS in chunks of kGemmKC rows (row stride 16 NBJ + 1); the A fragments of the
+// next k-step are loaded during the current one's MFMAs.  Fragment layouts as in
+// rowmul_mfma_kernel below.
+constexpr int kGemmKC = 64;
+
+template <int NBJ>
+__global__ __launch_bounds__(256) void gemm_nn_mfma_kernel(const double* __restrict__ A, int64_t lda,
+                                                           const double* __restrict__ B, int ldb, double* __restrict__ C,
+                                                           int64_t ldc, int64_t n, int k, int m, int ncb) {
+  constexpr int RS = 16 * NBJ + 1;
+  __shared__ double bs[kGemmKC * RS];
+  const int nbk = gridDim.x, bk = blockIdx.x, nb8 = nbk & ~7;
+  const int64_t L = bk < nb8 ? (int64_t)(bk & 7) * (nb8 >> 3) + (bk >> 3) : bk;
+  const int64_t rt = L / ncb;
+  const int c0 = (int)(L - rt * ncb) * 16 * NBJ;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = rt * 128 + w * 32;
+  const double* ar[2];
+  double mrow[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int64_t r = r0 + 16 * b + li;
+    mrow[b] = r < n ? 1.0 : 0.0;
+    ar[b] = A + (r < n ? r : n - 1) * lda;
+  }
+  dv4 acc[2][NBJ];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j) acc[b][j] = dv4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < k; k0 += kGemmKC) {
+    const int kc = min(kGemmKC, k - k0), nks = (kc + 3) / 4;
+    __syncthreads();  // the previous chunk's reads of bs are done
+    for (int t = threadIdx.x; t < nks * 4 * 16 * NBJ; t += 256) {
+      const int kk = t / (16 * NBJ), cc = t - kk * (16 * NBJ);
+      bs[kk * RS + cc] = (kk < kc && c0 + cc < m) ? B[(int64_t)(k0 + kk) * ldb + c0 + cc] : 0.0;
+    }
+    __syncthreads();
+    // A fragments of k-step s of this chunk (columns past k: clamped, zeroed)
+    auto load = [&](int s, double (&a)[2]) {
+      const int c = k0 + 4 * s + lk;
+      const double mk = c < k ? 1.0 : 0.0;
+      const int cc = c < k ? c : k - 1;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) a[b] = ar[b][cc] * (mk * mrow[b]);
+    };
+    auto mma = [&](int s, const double (&a)[2]) {
+      const double* bk4 = bs + (4 * s + lk) * RS + li;
+#pragma unroll
+      for (int j = 0; j < NBJ; ++j) {
+        const double bj = bk4[16 * j];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[b][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b], bj, acc[b][j], 0, 0, 0);
+      }
+    };
+    double a0[2], a1[2];
+    load(0, a0);
+    int s = 0;
+    for (; s + 1 < nks; s += 2) {
+      load(s + 1, a1);
+      mma(s, a0);
+      if (s + 2 < nks) load(s + 2, a0);
+      mma(s + 1, a1);
+    }
+    if (s < nks) mma(s, a0);
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int j = 0; j < NBJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + 16 * b + lk + 4 * v;
+        const int c = c0 + 16 * j + li;
+        if (r < n && c < m) C[r * ldc + c] = acc[b][j][v];
+      }
+}
+
 // ---- X <- X R in place on the matrix cores (real, X [n x nv] with nv <= 80, R [nv x nv]).
 // Row-local: each wave owns 16 * RB rows and accumulates all nv output columns (NBJ blocks
 // of 16) over the k-steps of 4; every k-step of its rows is read before the wave stores, so
@@ -1760,6 +1844,16 @@ int gram(bool cplx, const double* A, int64_t lda, int na, const double* B, int64
 
 int gemm_nn(bool cplx, const double* A, int64_t lda, const double* B, int ldb, double* C, int64_t ldc, int64_t n,
             int k, int m, hipStream_t s) {
+  if (!cplx && k >= 16 && m >= 64 && n >= 4096) {  // real wide blocks: on the matrix cores
+    const int nbj = m >= 80 ? 5 : cdiv(m, 16);
+    const int ncb = cdiv(m, 16 * nbj);
+    const dim3 g((unsigned)(cdiv(n, 128) * ncb));
+    switch (nbj) {
+      case 4: hipLaunchKernelGGL(gemm_nn_mfma_kernel<4>, g, dim3(256), 0, s, A, lda, B, ldb, C, ldc, n, k, m, ncb); break;
+      default: hipLaunchKernelGGL(gemm_nn_mfma_kernel<5>, g, dim3(256), 0, s, A, lda, B, ldb, C, ldc, n, k, m, ncb); break;
+    }
+    return check();
+  }
   dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(m, 64));
   if (cplx)
     hipLaunchKernelGGL(gemm_nn_kernel<true>, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, n, k, m);
