@@ -47,29 +47,53 @@ from .quadrature import gauss_rule
 CHILD_OFFSETS = np.array([[c & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], dtype=np.float64)
 
 
-def radial_scales(fn, r0: float, r1: float, panels: int = 64, order: int = 20):
-    """A = int psi~^2 and B = int |grad psi~|^2 over R^3 for one atomic function.
-
-    psi~ = g(r) (s-type) or d_axis g(r) (p-type), g = r^power exp(-zeta r) h(r).  Angular
-    integrals: 4 pi g^2 (s) or 4 pi r^2 g^2 / 3 (p) for the value;
-    4 pi g'^2 (s) or 4 pi (g^2 + 2/3 r g g' + r^2 g'^2 / 3) (p) for the gradient.
+def radial_scales_of(gfun, axis: int, r1: float, panels: int = 64, order: int = 20):
+    """A = int psi~^2 and B = int |grad psi~|^2 over R^3 for psi~ = g(r) (axis < 0) or d_axis g(r),
+    g(r), g'(r) = gfun(r) vanishing beyond r1.  Angular integrals: 4 pi g^2 (s) or 4 pi r^2 g^2 / 3
+    (p) for the value; 4 pi g'^2 (s) or 4 pi (g^2 + 2/3 r g g' + r^2 g'^2 / 3) (p) for the gradient.
     """
     x, w = gauss_rule(order)
     edges = np.linspace(0.0, r1, panels + 1)
     a, b = edges[:-1, None], edges[1:, None]
     r = (0.5 * (b - a) * (x[None, :] + 1.0) + a).ravel()
     wr = (0.5 * (b - a) * w[None, :]).ravel()
-    d = np.zeros((r.size, 3))
-    d[:, 0] = r
-    g, gg = atomic_function(d, fn.power, fn.zeta, -1, r0, r1)
-    gp = gg[:, 0]
-    if fn.axis < 0:
+    g, gp = gfun(r)
+    if axis < 0:
         A = np.sum(wr * 4.0 * np.pi * r * r * g * g)
         B = np.sum(wr * 4.0 * np.pi * r * r * gp * gp)
     else:
         A = np.sum(wr * 4.0 * np.pi * r ** 4 * g * g / 3.0)
         B = np.sum(wr * 4.0 * np.pi * r * r * (g * g + 2.0 / 3.0 * r * g * gp + r * r * gp * gp / 3.0))
     return A, B
+
+
+def radial_scales(fn, r0: float, r1: float, panels: int = 64, order: int = 20):
+    """radial_scales_of for an atomic function r^power exp(-zeta r) [d_axis] h(r)."""
+    def gfun(r):
+        d = np.zeros((r.size, 3))
+        d[:, 0] = r
+        g, gg = atomic_function(d, fn.power, fn.zeta, -1, r0, r1)
+        return g, gg[:, 0]
+    return radial_scales_of(gfun, fn.axis, r1, panels, order)
+
+
+class TrialFn:
+    """One function of the refinement's trial integrals: its atom, its value and gradient at
+    displacements d [..., 3] from the atom's nearest image, and its scales (A, B)."""
+
+    def __init__(self, atom: int, evaluate, scales):
+        self.atom = atom
+        self.evaluate = evaluate
+        self.scales = scales
+
+
+def kohn_sham_trials(system):
+    """The atomic functions of the system's enrichment list (no phase)."""
+    out = []
+    for fn in system.enr:
+        out.append(TrialFn(fn.atom, lambda d, fn=fn: atomic_function(d, fn.power, fn.zeta, fn.axis, system.r0, system.r1),
+                           radial_scales(fn, system.r0, system.r1)))
+    return out
 
 
 def lagrange_at(nodes: np.ndarray, t: np.ndarray):
@@ -100,12 +124,15 @@ def box_rule(lo: np.ndarray, size: float, q: int):
 class AdaptiveRule:
     """The adaptive rule on the union of the enrichment supports of `system`."""
 
-    def __init__(self, mesh: Mesh, system, tol: float, max_depth: int):
+    def __init__(self, mesh: Mesh, system, tol: float, max_depth: int, trials=None):
+        """trials: the TrialFn list (default: the system's atomic functions, kohn_sham_trials)."""
         self.mesh = mesh
         self.tol = float(tol)
         self.max_depth = int(max_depth)
         q = mesh.q1
-        atom_of = np.array([f.atom for f in system.enr], dtype=np.int64)
+        if trials is None:
+            trials = kohn_sham_trials(system)
+        atom_of = np.array([t.atom for t in trials], dtype=np.int64)
         self.support = {}  # atom -> support cells (ascending)
         fns_of_cell = {}
         for I in range(system.n_atoms):
@@ -119,8 +146,8 @@ class AdaptiveRule:
         scales = {}
         vol = 4.0 / 3.0 * np.pi * system.r1 ** 3
         nd = mesh.nd
-        for i, fn in enumerate(system.enr):
-            A, B = radial_scales(fn, system.r0, system.r1)
+        for i, t in enumerate(trials):
+            A, B = t.scales
             scales[i] = np.concatenate([[A, B], np.full(nd, np.sqrt(A * vol)), np.full(nd, np.sqrt(B * vol))])
         xi = mesh.ref.xi
         p1 = mesh.p1
@@ -141,9 +168,8 @@ class AdaptiveRule:
                            Vx[:, iax] * Vy[:, iay] * Dz[:, iaz]], axis=-1)  # [q^3, nd, 3]
             out = np.zeros((len(fl), 2 + 2 * nd))
             for j, (I, i) in enumerate(fl):
-                fn = system.enr[i]
                 d = min_image(pts - system.pos[I][None, :], mesh.L)
-                v, g = atomic_function(d, fn.power, fn.zeta, fn.axis, system.r0, system.r1)
+                v, g = trials[i].evaluate(d)
                 out[j, 0] = np.sum(wq * v * v)
                 out[j, 1] = np.sum(wq * (g * g).sum(-1))
                 out[j, 2:2 + nd] = (wq * v) @ Na
@@ -441,3 +467,145 @@ class AdaptiveUFormOperator:
         Yc = self.dm12[:, None] * (self.Hcc @ Zc + self.Hco @ Zo)
         Yo = self.S @ (self.Hco.conj().T @ Zc + self.Hoo @ Zo)
         return np.concatenate([Yc, Yo], axis=0)
+
+
+def poisson_trials(system, rc: np.ndarray, alpha: np.ndarray):
+    """The auxiliary-potential enrichment's atomic functions (V_H - Z v_g) h(r), one per atom
+    (oracle/poisson.py), as trial functions of the rule."""
+    from .enrichment import cutoff
+    from .poisson import phi_atomic
+    out = []
+    for I in range(system.n_atoms):
+        Z, a, r_c = float(system.Z[I]), float(alpha[I]), float(rc[I])
+
+        def gfun(r, Z=Z, a=a, r_c=r_c):
+            f, fp = phi_atomic(r, Z, a, r_c)
+            h, dh = cutoff(r, system.r0, system.r1)
+            return f * h, fp * h + f * dh
+
+        def evaluate(d, gfun=gfun):
+            r = np.sqrt((d * d).sum(-1))
+            g, gp = gfun(r)
+            rhat = d / np.where(r > 0, r, 1.0)[..., None]
+            return g, gp[..., None] * rhat
+
+        out.append(TrialFn(I, evaluate, radial_scales_of(gfun, -1, system.r1)))
+    return out
+
+
+class AdaptivePoissonOEFE:
+    """The auxiliary-potential Poisson problem (oracle/poisson.py: eqnpoissonaux, eqnPhiOEFE,
+    eqnpoissX, eqnDiscLaplace, eqnDiscForceVec) with the integrals of its enrichment functions on
+    the adaptive rule built from them: the orthogonalization numerator, A^co, A^oo and the
+    enrichment rows of the force vector, for which the charge is taken at the rule's points.
+    A^cc and the FE rows of the force vector keep the Gauss rule, and so does the background
+    (the Gauss-rule mean of b + rho)."""
+
+    def __init__(self, system, tol: float, max_depth: int):
+        from .poisson import FOUR_PI, PoissonOEFE
+        base = PoissonOEFE(system)
+        self.base = base
+        self.mesh = mesh = base.mesh
+        self.N, self.n_enr, self.n_tot, self.m = base.N, base.n_enr, base.n_tot, base.m
+        self.Acc, self.rc, self.alpha = base.Acc, base.rc, base.alpha
+        self.system = system
+        trials = poisson_trials(system, base.rc, base.alpha)
+        self.rule = rule = AdaptiveRule(mesh, system, tol, max_depth, trials=trials)
+        s = 2.0 / mesh.h
+        self.atoms = []  # (cells, [Phi per cell], [gradPhi per cell]) at the rule's points
+        self.atoms_gauss = []  # (cells, Phi [nc, nq]) at the Gauss points, same coefficients
+        for I in range(self.n_enr):
+            cells = rule.support[I]
+            NA, gNA = [], []
+            for e in cells.tolist():
+                v, g = trials[I].evaluate(min_image(rule.points[e] - system.pos[I][None, :], mesh.L))
+                NA.append(v)
+                gNA.append(g)
+            dnum = np.zeros(mesh.N)
+            for ci, e in enumerate(cells.tolist()):
+                np.add.at(dnum, mesh.cell_dofs[e], rule.B[e].T @ (rule.weights[e] * NA[ci]))
+            c = dnum / self.m
+            Phi, gPhi = [], []
+            for ci, e in enumerate(cells.tolist()):
+                ce = c[mesh.cell_dofs[e]]
+                Phi.append(NA[ci] - rule.B[e] @ ce)
+                gPhi.append(gNA[ci] - s * np.stack([rule.G[e][dd] @ ce for dd in range(3)], axis=-1))
+            self.atoms.append((cells, Phi, gPhi))
+            vg, _ = trials[I].evaluate(min_image(mesh.quad_points(cells) - system.pos[I], mesh.L))
+            self.atoms_gauss.append((cells, vg - c[mesh.cell_dofs[cells]] @ mesh.B.T))
+        rows, cols, vals = [], [], []
+        for I, (cells, Phi, gPhi) in enumerate(self.atoms):
+            for ci, e in enumerate(cells.tolist()):
+                w = rule.weights[e]
+                he = sum(s * rule.G[e][dd].T @ (w * gPhi[ci][:, dd]) for dd in range(3)) / FOUR_PI
+                rows.append(mesh.cell_dofs[e])
+                cols.append(np.full(mesh.nd, I))
+                vals.append(he)
+        self.Aco = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                 shape=(self.N, self.n_enr)).tocsr()
+        self.Aco.sum_duplicates()
+        Aoo = np.zeros((self.n_enr, self.n_enr))
+        for I, (cI, _, gI) in enumerate(self.atoms):
+            for J, (cJ, _, gJ) in enumerate(self.atoms):
+                common, iI, iJ = np.intersect1d(cI, cJ, return_indices=True)
+                for e, i, j in zip(common.tolist(), iI.tolist(), iJ.tolist()):
+                    Aoo[I, J] += np.sum(rule.weights[e][:, None] * gI[i] * gJ[j]) / FOUR_PI
+        self.Aoo = Aoo
+
+    def smeared_charge_at(self, x: np.ndarray) -> np.ndarray:
+        """b at points x [..., 3] (eqnsmeared, nearest image)."""
+        from .poisson import g_smeared
+        b = np.zeros(x.shape[:-1])
+        for I in range(self.n_enr):
+            d = min_image(x - self.system.pos[I], self.mesh.L)
+            b -= self.system.Z[I] * g_smeared(np.sqrt((d * d).sum(-1)), self.rc[I])
+        return b
+
+    def model_density_at(self, x: np.ndarray) -> np.ndarray:
+        """The model atomic densities at points x [..., 3] (nearest image)."""
+        from .poisson import model_density
+        rho = np.zeros(x.shape[:-1])
+        for I in range(self.n_enr):
+            d = min_image(x - self.system.pos[I], self.mesh.L)
+            rho += model_density(np.sqrt((d * d).sum(-1)), self.system.Z[I], self.alpha[I])
+        return rho
+
+    def force_vector(self, rho_q: np.ndarray, rho_adapt: np.ndarray) -> np.ndarray:
+        """c: FE rows int f N_m on the Gauss rule with f = b + rho - background (the Gauss-rule
+        mean of b + rho), enrichment rows int f N^O on the rule with f at its points."""
+        f_q = self.base.neutral_charge(rho_q)
+        tot = self.base.smeared_charge() + rho_q.reshape(f_q.shape)
+        W = self.mesh.Wcell[None, :]
+        mean = (W * tot).sum() / (W.sum() * self.mesh.n_cells)
+        cC = self.base.force_vector(f_q)[:self.N]
+        f_a = self.smeared_charge_at(self.rule.all_points()) + rho_adapt - mean
+        cO = np.zeros(self.n_enr)
+        for I, (cells, Phi, _) in enumerate(self.atoms):
+            for ci, e in enumerate(cells.tolist()):
+                cO[I] += np.sum(self.rule.weights[e] * f_a[self.rule.cell_slice(e)] * Phi[ci])
+        return np.concatenate([cC, cO])
+
+    def matrix(self) -> sp.csr_matrix:
+        return sp.bmat([[self.Acc, self.Aco], [self.Aco.T, sp.csr_matrix(self.Aoo)]], format="csr")
+
+    def solve(self, rho_q: np.ndarray, rho_adapt: np.ndarray) -> np.ndarray:
+        """phi with A phi = c (dense least squares on small systems, Jacobi CG otherwise), the FE part
+        with zero GLL-mass-weighted mean."""
+        import scipy.sparse.linalg as spla
+        c = self.force_vector(rho_q, rho_adapt)
+        A = self.matrix()
+        if self.n_tot <= 3000:
+            phi = np.linalg.lstsq(A.toarray(), c, rcond=None)[0]
+        else:
+            phi, info = spla.cg(A, c, rtol=1e-13, atol=0.0, maxiter=20000, M=sp.diags(1.0 / A.diagonal()))
+            if info != 0:
+                raise RuntimeError(f"oracle CG did not converge ({info})")
+        return self.base.fix_constant(phi)
+
+    def field_at_quad(self, phi: np.ndarray) -> np.ndarray:
+        """phi_aux^h at the Gauss points [n_cells, nq] (eqnPhiOEFE)."""
+        mesh = self.mesh
+        out = phi[mesh.cell_dofs] @ mesh.B.T
+        for I, (cells, Phi) in enumerate(self.atoms_gauss):
+            out[cells] += phi[self.N + I] * Phi
+        return out

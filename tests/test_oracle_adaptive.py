@@ -18,6 +18,11 @@
 * The periodic-function k-point form on the rule: max_depth = 0 gives the blocks of
   oracle/uform.py; at k = 0 the blocks equal the Gamma-point operator's on the same rule; M^oo
   and H^oo are Hermitian.
+* The auxiliary-potential Poisson problem on a rule built from its own enrichment functions:
+  max_depth = 0 gives oracle/poisson.py's A^co, A^oo and force vector; A stays symmetric and
+  annihilates the FE constant; A^co, A^oo and the enrichment rows of the force vector converge to
+  the fully refined rule's as tol falls (1e-6 at tol 1e-8: the charge is not among the trial
+  integrals), and the solution with them.
 """
 import dataclasses
 
@@ -150,3 +155,47 @@ def test_uform_adaptive_hermitian_and_k0_is_gamma():
     g = ad.AdaptiveOEFEOperator(s, 1e-5, 2)
     for X, Y in ((z.Moo, g.enr.Moo), (z.Hoo, g.enr.Hoo), (z.Hco.toarray(), g.enr.Hco.toarray())):
         assert np.abs(X - Y).max() <= 1e-13 * np.abs(Y).max()
+
+
+def _pois_sys(nc=3, p=3, Z=14.0):
+    s = wl.tiny_system(nc=nc, p=p, n_atoms=2, seed=5, L=8.0, r0=2.0, r1=3.5)
+    return dataclasses.replace(s, Z=np.full(2, Z))
+
+
+def test_poisson_depth0_is_the_gauss_rule_problem():
+    from oracle import poisson as po
+    s = _pois_sys()
+    g = po.PoissonOEFE(s)
+    a = ad.AdaptivePoissonOEFE(s, 1e-6, 0)
+    assert a.rule.n_points == a.rule.cells.size * a.mesh.nq
+    assert np.abs(a.Aco.toarray() - g.Aco.toarray()).max() <= 1e-13 * np.abs(g.Aco.toarray()).max()
+    assert np.abs(a.Aoo - g.Aoo).max() <= 1e-13 * np.abs(g.Aoo).max()
+    rho = g.model_electron_density()
+    c = a.force_vector(rho, a.model_density_at(a.rule.all_points()))
+    cg = g.force_vector(g.neutral_charge(rho))
+    assert np.abs(c - cg).max() <= 1e-12 * np.abs(cg).max()
+
+
+def test_poisson_adaptive_converges_and_keeps_the_null_space():
+    s = _pois_sys()
+    ref = ad.AdaptivePoissonOEFE(s, 0.0, 2)  # every box where the functions do not vanish split twice
+    rho = ref.base.model_electron_density()
+
+    def blocks_and_phi(P):
+        c = P.force_vector(rho, P.model_density_at(P.rule.all_points()))
+        return P.Aco.toarray(), P.Aoo, c[P.N:], P.solve(rho, P.model_density_at(P.rule.all_points()))
+
+    Ar, Or, cr, pr = blocks_and_phi(ref)
+    errs, perr = [], []
+    for tol in (1e-2, 1e-5, 1e-8):
+        P = ad.AdaptivePoissonOEFE(s, tol, 2)
+        A, O, c, phi = blocks_and_phi(P)
+        errs.append(max(np.abs(A - Ar).max() / np.abs(Ar).max(), np.abs(O - Or).max() / np.abs(Or).max(),
+                        np.abs(c - cr).max() / np.abs(cr).max()))
+        perr.append(np.abs(phi - pr).max() / np.abs(pr).max())
+        M = P.matrix().toarray()
+        assert np.abs(M - M.T).max() <= 1e-14 * np.abs(M).max()
+        one = np.concatenate([np.ones(P.N), np.zeros(P.n_enr)])
+        assert np.abs(M @ one).max() <= 1e-12 * np.abs(M).max()
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-6, errs  # the charge in c^O is not a trial integral
+    assert perr[0] > perr[2] and perr[2] < 1e-6, perr
