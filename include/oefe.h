@@ -375,6 +375,13 @@ int oefe_density(oefe_op op, oefe_prec prec, const void* X, int64_t ld, int32_t 
  * ENOMEM, EDEVICE. */
 int oefe_poisson_create(const oefe_system_desc* desc, oefe_op* out);
 
+/* The operator of oefe_poisson_create with the integrals of its enrichment functions on an
+ * adaptive rule (Sec. III.B; as oefe_op_create_adaptive, the trial functions being the phi
+ * enrichment's atomic parts (V_H - Z v_g) h): the orthogonalization numerator, A^co and A^oo on
+ * the rule, A^cc on the Gauss rule; solved with oefe_poisson_solve_adaptive.  Errors as
+ * oefe_poisson_create, EINVAL for tol outside (0, 1) or max_depth outside [0, 5]. */
+int oefe_poisson_create_adaptive(const oefe_system_desc* desc, double tol, int32_t max_depth, oefe_op* out);
+
 /* Work bytes of oefe_poisson_solve (0 for other operators). */
 size_t oefe_poisson_work_size(oefe_op pop);
 
@@ -392,6 +399,15 @@ size_t oefe_poisson_work_size(oefe_op pop);
  * a Poisson operator), ENOCONV (tolerance not met: phi holds the last iterate), EDEVICE. */
 int oefe_poisson_solve(oefe_op pop, const double* rho, double* phi, double tol, int32_t max_iter, double* info,
                        void* work, oefe_stream stream);
+
+/* oefe_poisson_solve for an operator of oefe_poisson_create_adaptive: rho at the Gauss points
+ * (the FE rows of the force vector and the background, as in oefe_poisson_solve) and rho_adapt at
+ * the rule's points (device float64 [n_points], rule order: oefe_op_adaptive_points) for the
+ * enrichment rows, c_I = int (b + rho - background) N^O_I on the rule with the smeared charge b
+ * evaluated at its points.  oefe_poisson_solve refuses such an operator.  Same results and
+ * errors otherwise. */
+int oefe_poisson_solve_adaptive(oefe_op pop, const double* rho, const double* rho_adapt, double* phi, double tol,
+                                int32_t max_iter, double* info, void* work, oefe_stream stream);
 
 /* Instrumentation.  While a kernel is selected, each of its launches inside
  * ham_apply / chebyshev_filter* is bracketed by HIP events on the stream it is

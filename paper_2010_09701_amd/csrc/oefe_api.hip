@@ -562,6 +562,7 @@ int upload_operator(oefe_op_s* op, std::string& err) {
         if ((rc = dput(&op->d.cf_acell, cf_acell, err))) return rc;
         if ((rc = dput(&op->d.cf_aoff, cf_aoff, err))) return rc;
         if ((rc = dput(&op->d.phiA, phiA, err))) return rc;
+        if (op->poisson && (rc = dput(&op->d.a_b, op->ad_b, err))) return rc;
       }
       // partials of the potential part of H^co per (flattened support cell, local node, function)
       if ((rc = dalloc(&op->d.hpart, (size_t)boff[nb] * op->nd * op->FMAX * E, err))) return rc;
@@ -610,7 +611,7 @@ void free_device(oefe_op_s* op) {
   dfree(d.lambda); dfree(d.lambdaf); dfree(d.bf_mats);
   dfree(d.W); dfree(d.V); dfree(d.msq); dfree(d.hkin); dfree(d.Hoo_kin); dfree(d.row_blk); dfree(d.rpos);
   dfree(d.a_w); dfree(d.a_V); dfree(d.a_leafB); dfree(d.a_off); dfree(d.cf_acell); dfree(d.cf_aoff);
-  dfree(d.phiA); dfree(d.hpart); dfree(d.hoo_part);
+  dfree(d.phiA); dfree(d.hpart); dfree(d.hoo_part); dfree(d.a_b);
   dfree(d.bsmear); dfree(d.blk_cf0); dfree(d.rr_ptr); dfree(d.rr_ent); dfree(d.cf_cell); dfree(d.csr2tile); dfree(d.hp_ptr); dfree(d.hp_i);
   dfree(d.hp_j);
 }
@@ -2287,6 +2288,36 @@ __global__ __launch_bounds__(256) void pois_rhs_fe_kernel(const double* __restri
 
 // enrichment rows of c: c_I = sum over the support cells of block I and their points of W f N^O_I
 // (one workgroup per block, one function per block, fixed order)
+// Adaptive rule: the enrichment rows c_I = sum over atom I's support cells and their rule points of
+// w (b + rho - background) N^O_I, with b and rho at the points (a_b, rho_a) and the background sc[0];
+// one workgroup per atom, threads striding over each cell's points, a fixed tree at the end.
+__global__ __launch_bounds__(256) void pois_rhs_enr_adapt_kernel(const double* __restrict__ a_b,
+                                                                 const double* __restrict__ rho_a,
+                                                                 const double* __restrict__ a_w,
+                                                                 const double* __restrict__ phiA,
+                                                                 const int64_t* __restrict__ a_off,
+                                                                 const int64_t* __restrict__ cf_aoff,
+                                                                 const int32_t* __restrict__ cf_acell,
+                                                                 const int64_t* __restrict__ blk_cf0,
+                                                                 const double* __restrict__ sc, double* __restrict__ cO) {
+  __shared__ double red[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const double bg = sc[0];
+  double a = 0.0;
+  for (int64_t cf = blk_cf0[b]; cf < blk_cf0[b + 1]; ++cf) {
+    const int k = cf_acell[cf];
+    const int64_t p0 = a_off[k], np = a_off[k + 1] - p0, r0 = cf_aoff[cf];
+    for (int64_t q = t; q < np; q += 256) a += a_w[p0 + q] * (a_b[p0 + q] + rho_a[p0 + q] - bg) * phiA[r0 + q];
+  }
+  red[t] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t == 0) cO[b] = red[0];
+}
+
 __global__ __launch_bounds__(256) void pois_rhs_enr_kernel(const double* __restrict__ f, const double* __restrict__ W,
                                                            const double* __restrict__ phi,
                                                            const int32_t* __restrict__ cf_cell,
@@ -2433,8 +2464,41 @@ size_t oefe_poisson_work_size(oefe_op pop) {
   return pois_layout(pop, nullptr).total + 256;
 }
 
+static int poisson_solve_impl(oefe_op pop, const double* rho, const double* rho_adapt, double* phi, double tol,
+                              int32_t max_iter, double* info, void* work, oefe_stream stream);
+
 int oefe_poisson_solve(oefe_op pop, const double* rho, double* phi, double tol, int32_t max_iter, double* info,
                        void* work, oefe_stream stream) {
+  if (pop && pop->adaptive) return fail(OEFE_EINVAL, "an operator with the adaptive rule takes rho at its points (oefe_poisson_solve_adaptive)");
+  return poisson_solve_impl(pop, rho, nullptr, phi, tol, max_iter, info, work, stream);
+}
+
+int oefe_poisson_solve_adaptive(oefe_op pop, const double* rho, const double* rho_adapt, double* phi, double tol,
+                                int32_t max_iter, double* info, void* work, oefe_stream stream) {
+  if (!pop || !pop->adaptive || !rho_adapt) return fail(OEFE_EINVAL, "bad arguments");
+  return poisson_solve_impl(pop, rho, rho_adapt, phi, tol, max_iter, info, work, stream);
+}
+
+int oefe_poisson_create_adaptive(const oefe_system_desc* desc, double tol, int32_t max_depth, oefe_op* out) {
+  if (!desc || !out) return fail(OEFE_EINVAL, "null argument");
+  *out = nullptr;
+  if (desc->n_atoms < 1 || !desc->pos || !desc->Z) return fail(OEFE_EINVAL, "the Poisson operator needs atoms");
+  if (desc->kvec) return fail(OEFE_EINVAL, "the Poisson operator is real (no Bloch wavevector)");
+  for (int I = 0; I < desc->n_atoms; ++I)
+    if (!(desc->Z[I] > 0)) return fail(OEFE_EINVAL, "atomic numbers must be positive");
+  if (!(tol > 0.0 && tol < 1.0) || max_depth < 0 || max_depth > kAdaptMaxDepth)
+    return fail(OEFE_EINVAL, "adaptive rule: need 0 < tol < 1 and 0 <= max_depth <= 5");
+  oefe_op_s* op = new (std::nothrow) oefe_op_s();
+  if (!op) return fail(OEFE_ENOMEM, "host allocation failed");
+  op->poisson = true;
+  op->adaptive = true;
+  op->ad_tol = tol;
+  op->ad_depth = max_depth;
+  return finish_create(op, desc, out);
+}
+
+static int poisson_solve_impl(oefe_op pop, const double* rho, const double* rho_adapt, double* phi, double tol,
+                              int32_t max_iter, double* info, void* work, oefe_stream stream) {
   if (!pop || !rho || !phi || !work || !info || max_iter < 1 || !(tol > 0.0))
     return fail(OEFE_EINVAL, "bad arguments");
   if (!pop->poisson) return fail(OEFE_EINVAL, "not an operator of oefe_poisson_create");
@@ -2453,8 +2517,12 @@ int oefe_poisson_solve(oefe_op pop, const double* rho, double* phi, double tol, 
   // v = P^T c, projected off the null vector z = (m^1/2, 0)
   hipLaunchKernelGGL(pois_rhs_fe_kernel, blocks(N), dim3(256), 0, s, L.f, op->d.W, op->cd, op->d.msq, op->nc, op->p,
                      op->n, op->P1, op->nq, N, L.v, L.z);
-  hipLaunchKernelGGL(pois_rhs_enr_kernel, dim3((unsigned)nO), dim3(256), 0, s, L.f, op->d.W, op->d.phi,
-                     op->d.cf_cell, op->d.blk_cf0, op->nq, L.cO);
+  if (rho_adapt)  // the enrichment rows on the adaptive rule, the charge at its points
+    hipLaunchKernelGGL(pois_rhs_enr_adapt_kernel, dim3((unsigned)nO), dim3(256), 0, s, op->d.a_b, rho_adapt, op->d.a_w,
+                       op->d.phiA, op->d.a_off, op->d.cf_aoff, op->d.cf_acell, op->d.blk_cf0, L.sc + 8, L.cO);
+  else
+    hipLaunchKernelGGL(pois_rhs_enr_kernel, dim3((unsigned)nO), dim3(256), 0, s, L.f, op->d.W, op->d.phi,
+                       op->d.cf_cell, op->d.blk_cf0, op->nq, L.cO);
   hipLaunchKernelGGL(pois_small_mv_kernel, blocks(nO), dim3(256), 0, s, op->d.S, L.cO, nO, L.v + N);
   int rc = dot_columns<double>(false, L.z, 1, L.v, 1, N, 1, nullptr, L.sc + 4, L.dscr, s);  // z . v
   if (!rc) rc = dot_columns<double>(false, L.z, 1, L.z, 1, N, 1, nullptr, L.sc + 5, L.dscr, s);  // z . z

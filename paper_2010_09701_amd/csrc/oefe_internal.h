@@ -191,6 +191,7 @@ struct DeviceArrays {
   double* phiA = nullptr;       // N^O: phiA[(row * FMAX + f)] (complex: x2)
   double* hpart = nullptr;      // potential part of H^co per (flattened support cell, local node, f)
   double* hoo_part = nullptr;   // potential part of H^oo per (block pair, chunk of common cells, f, g)
+  double* a_b = nullptr;        // Poisson operator: the smeared nuclear charge at the rule's points
 };
 
 struct AtomBlock {
@@ -252,6 +253,7 @@ struct oefe_op_s {
   std::vector<int32_t> ad_index;    // mesh cell -> rule cell or -1 [n_cells]
   std::vector<int64_t> ad_off;      // rule cell -> first point [n_rule_cells + 1]
   std::vector<double> ad_x, ad_w, ad_V;
+  std::vector<double> ad_b;         // Poisson operator: the smeared nuclear charge at the points
   std::vector<double> ad_B, ad_D;   // leaf l, direction d: [(l * 3 + d) * P1 + q] * P1 + a
   int64_t n_cf = 0;                 // flattened (block, support cell) pairs
   int hoo_nchunk = 1;               // chunks of each block pair's common cells (H^oo rebuild)

@@ -13,6 +13,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <thread>
 
 #include "oefe_internal.h"
@@ -316,7 +317,12 @@ constexpr int kSetupThreads = 16;  // host threads of the rule's refinement
 // integration: s-type 4 pi r^2 g^2 and 4 pi r^2 g'^2; p-type 4 pi r^4 g^2 / 3 and
 // 4 pi r^2 (g^2 + 2/3 r g g' + r^2 g'^2 / 3); radial integrals by 64 panels of 20-point
 // Gauss-Legendre on [0, r1] (g vanishes beyond r1).
-void radial_scales(int pw, double zeta, int axis, double r0, double r1, double& A, double& B) {
+// The radial function g(r), g'(r) of a trial function (gfun), vanishing beyond r1.
+using RadialFn = std::function<void(double r, double& g, double& gp)>;
+// The value and gradient of trial function fn of atom I at displacement d.
+using TrialEval = std::function<void(int I, int fn, const double d[3], double& v, double g[3])>;
+
+void radial_scales(const RadialFn& gfun, int axis, double r1, double& A, double& B) {
   constexpr int kPanels = 64, kOrder = 20;
   double x[kOrder], w[kOrder];
   gauss_rule(kOrder, x, w);
@@ -326,10 +332,8 @@ void radial_scales(int pw, double zeta, int axis, double r0, double r1, double& 
     const double a = r1 * k / kPanels, b = r1 * (k + 1) / kPanels;
     for (int j = 0; j < kOrder; ++j) {
       const double r = 0.5 * (b - a) * (x[j] + 1.0) + a, wr = 0.5 * (b - a) * w[j];
-      const double d[3] = {r, 0.0, 0.0};
-      double g, gr[3];
-      atomic_fn(d, pw, zeta, -1, r0, r1, g, gr);
-      const double gp = gr[0];
+      double g, gp;
+      gfun(r, g, gp);
       if (axis < 0) {
         A += wr * 4.0 * kPi * r * r * g * g;
         B += wr * 4.0 * kPi * r * r * gp * gp;
@@ -347,8 +351,9 @@ void radial_scales(int pw, double zeta, int axis, double r0, double r1, double& 
 // int psi~^2, [1] = int |grad psi~|^2, [2 + a] = int psi~ N_a, [2 + nd + a] =
 // int grad psi~ . grad^ N_a (grad^: the gradient in the cell's reference coordinates), a over
 // the cell's nd local nodes; nt = 2 + 2 nd.
-void box_trials(const oefe_op_s* op, const oefe_system_desc* desc, const double* xi, const double org[3],
-                const double lo[3], double size, const std::vector<std::pair<int, int>>& fl, std::vector<double>& out) {
+void box_trials(const oefe_op_s* op, const oefe_system_desc* desc, const TrialEval& eval, const double* xi,
+                const double org[3], const double lo[3], double size, const std::vector<std::pair<int, int>>& fl,
+                std::vector<double>& out) {
   const int P1 = op->P1, nd = op->nd, nt = 2 + 2 * nd;
   const double h = op->h;
   double t[3][8], wt[3][8], Lv[3][8][8], Ld[3][8][8];
@@ -373,7 +378,7 @@ void box_trials(const oefe_op_s* op, const oefe_system_desc* desc, const double*
             dd[k] = dr - op->L * std::nearbyint(dr / op->L);
           }
           double v, g[3];
-          atomic_fn(dd, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, v, g);
+          eval(I, fn, dd, v, g);
           double* o = &out[j * nt];
           o[0] += w * v * v;
           o[1] += w * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
@@ -436,9 +441,9 @@ bool blind_box(const oefe_op_s* op, const oefe_system_desc* desc, const std::vec
 // rules (children in the order cx + 2 cy + 4 cz) differ by at most bound[], else its children
 // are refined in that order; at max_depth levels boxes are kept.  Leaves are appended depth
 // first as {lo_x, lo_y, lo_z, size}.
-void refine_box(const oefe_op_s* op, const oefe_system_desc* desc, const double* xi, const double org[3],
-                const std::vector<std::pair<int, int>>& fl, const std::vector<double>& bound, const double lo[3],
-                double size, int depth, std::vector<std::array<double, 4>>& leaves) {
+void refine_box(const oefe_op_s* op, const oefe_system_desc* desc, const TrialEval& eval, const double* xi,
+                const double org[3], const std::vector<std::pair<int, int>>& fl, const std::vector<double>& bound,
+                const double lo[3], double size, int depth, std::vector<std::array<double, 4>>& leaves) {
   if (depth == op->ad_depth) {
     leaves.push_back({lo[0], lo[1], lo[2], size});
     return;
@@ -451,10 +456,10 @@ void refine_box(const oefe_op_s* op, const oefe_system_desc* desc, const double*
   bool split = blind_box(op, desc, fl, lo, size);
   if (!split) {
     std::vector<double> own, kid, ksum;
-    box_trials(op, desc, xi, org, lo, size, fl, own);
+    box_trials(op, desc, eval, xi, org, lo, size, fl, own);
     ksum.assign(own.size(), 0.0);
     for (int c = 0; c < 8; ++c) {
-      box_trials(op, desc, xi, org, clo[c], 0.5 * size, fl, kid);
+      box_trials(op, desc, eval, xi, org, clo[c], 0.5 * size, fl, kid);
       for (size_t j = 0; j < kid.size(); ++j) ksum[j] += kid[j];
     }
     for (size_t j = 0; j < own.size() && !split; ++j) split = !(std::fabs(own[j] - ksum[j]) <= bound[j]);
@@ -463,19 +468,16 @@ void refine_box(const oefe_op_s* op, const oefe_system_desc* desc, const double*
     leaves.push_back({lo[0], lo[1], lo[2], size});
     return;
   }
-  for (int c = 0; c < 8; ++c) refine_box(op, desc, xi, org, fl, bound, clo[c], 0.5 * size, depth + 1, leaves);
+  for (int c = 0; c < 8; ++c) refine_box(op, desc, eval, xi, org, fl, bound, clo[c], 0.5 * size, depth + 1, leaves);
 }
 
 // The adaptive rule on the union of the blocks' support cells (cells ascending): leaves, their
 // points and weights, the 1D GLL Lagrange values and derivatives at each leaf's points (in the
 // cell's reference coordinates), and the potential at the points.
-int build_adaptive_rule(oefe_op_s* op, const oefe_system_desc* desc, const double* xi, std::string& err) {
+int build_adaptive_rule(oefe_op_s* op, const oefe_system_desc* desc, const double* xi, const TrialEval& eval,
+                        const std::vector<double>& scaleA, const std::vector<double>& scaleB, std::string& err) {
   const int P1 = op->P1, nq = op->nq;
   const double h = op->h;
-  std::vector<double> scaleA(op->n_enr), scaleB(op->n_enr);
-  for (int fn = 0; fn < op->n_enr; ++fn)
-    radial_scales(desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, scaleA[fn],
-                  scaleB[fn]);
   std::vector<std::vector<std::pair<int, int>>> fns_of(op->n_cells);
   for (auto& b : op->blocks)
     for (int64_t e : b.cells)
@@ -516,7 +518,7 @@ int build_adaptive_rule(oefe_op_s* op, const oefe_system_desc* desc, const doubl
         }
       }
       const double org[3] = {(double)(e % nc) * h, (double)((e / nc) % nc) * h, (double)(e / ((int64_t)nc * nc)) * h};
-      refine_box(op, desc, xi, org, fl, bound, org, h, 0, cell_leaves[k]);
+      refine_box(op, desc, eval, xi, org, fl, bound, org, h, 0, cell_leaves[k]);
     }
   };
   const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kSetupThreads,
@@ -561,6 +563,23 @@ int build_adaptive_rule(oefe_op_s* op, const oefe_system_desc* desc, const doubl
     return OEFE_EUNSUPPORTED;
   }
   op->ad_V.assign(np, 0.0);
+  if (op->poisson) {  // no potential; the smeared nuclear charge at the points (eqnsmeared)
+    op->ad_b.assign(np, 0.0);
+    for (int64_t i = 0; i < np; ++i) {
+      double b = 0.0;
+      for (int I = 0; I < desc->n_atoms; ++I) {
+        double d2 = 0;
+        for (int k = 0; k < 3; ++k) {
+          double dd = op->ad_x[3 * i + k] - desc->pos[3 * I + k];
+          dd -= op->L * std::nearbyint(dd / op->L);
+          d2 += dd * dd;
+        }
+        b -= desc->Z[I] * smeared_g(std::sqrt(d2), op->rc_smear[I]);
+      }
+      op->ad_b[i] = b;
+    }
+    return OEFE_OK;
+  }
   for (int64_t i = 0; i < np; ++i) {
     double v = 0.0;
     for (int I = 0; I < desc->n_atoms; ++I) {
@@ -903,11 +922,37 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
   // ---- adaptive quadrature of the enrichment integrals: the rule on the union of the supports
   const bool ad = op->adaptive;
   if (ad) {
+    // trial functions: the atomic functions without phase, or the auxiliary-potential enrichment
+    std::vector<double> sA(op->n_enr), sB(op->n_enr);
+    TrialEval eval;
     if (pois) {
-      err = "adaptive quadrature is built for the Kohn-Sham operator";
-      return OEFE_EUNSUPPORTED;
+      eval = [&](int I, int, const double d[3], double& v, double g[3]) {
+        phi_aux_fn(d, desc->Z[I], alpha_m[I], op->rc_smear[I], desc->r0, desc->r1, v, g);
+      };
+      for (int I = 0; I < op->n_enr; ++I)
+        radial_scales(
+            [&](double r, double& g, double& gp) {
+              const double d[3] = {r, 0.0, 0.0};
+              double gr[3];
+              phi_aux_fn(d, desc->Z[I], alpha_m[I], op->rc_smear[I], desc->r0, desc->r1, g, gr);
+              gp = gr[0];
+            },
+            -1, desc->r1, sA[I], sB[I]);
+    } else {
+      eval = [&](int, int fn, const double d[3], double& v, double g[3]) {
+        atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, v, g);
+      };
+      for (int fn = 0; fn < op->n_enr; ++fn)
+        radial_scales(
+            [&](double r, double& g, double& gp) {
+              const double d[3] = {r, 0.0, 0.0};
+              double gr[3];
+              atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], -1, desc->r0, desc->r1, g, gr);
+              gp = gr[0];
+            },
+            desc->enr_axis[fn], desc->r1, sA[fn], sB[fn]);
     }
-    if (int rc = build_adaptive_rule(op, desc, xi, err)) return rc;
+    if (int rc = build_adaptive_rule(op, desc, xi, eval, sA, sB, err)) return rc;
   }
   const int nq3 = nq;
   // blocks are independent: host threads over contiguous block ranges, each with its own scratch
@@ -983,7 +1028,10 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
             for (int f = 0; f < nf; ++f) {
               const int fn = b.fn0 + f;
               double val, gr[3];
-              atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
+              if (pois)
+                phi_aux_fn(d, desc->Z[b.atom], alpha_m[b.atom], op->rc_smear[b.atom], desc->r0, desc->r1, val, gr);
+              else
+                atomic_fn(d, desc->enr_power[fn], desc->enr_zeta[fn], desc->enr_axis[fn], desc->r0, desc->r1, val, gr);
               NAa[(size_t)row * nf + f] = ph * val;
               for (int kk = 0; kk < 3; ++kk)  // the periodic-function form: e^{-ik.d} (grad f - i k f)
                 gNAa[((size_t)row * nf + f) * 3 + kk] = ph * (uf ? cplx(gr[kk], -op->kvec[kk] * val) : cplx(gr[kk], 0.0));

@@ -87,6 +87,8 @@ def _load():
         "oefe_fermi_occupations": ([i32, vp, vp, vp, dbl, dbl, vp, vp, vp, vp], i32),
         "oefe_density": ([vp, i32, vp, i64, i32, vp, vp, i32, vp, vp], i32),
         "oefe_poisson_create": ([vp, ctypes.POINTER(vp)], i32),
+        "oefe_poisson_create_adaptive": ([vp, dbl, i32, ctypes.POINTER(vp)], i32),
+        "oefe_poisson_solve_adaptive": ([vp, vp, vp, vp, dbl, i32, vp, vp, vp], i32),
         "oefe_poisson_work_size": ([vp], ctypes.c_size_t),
         "oefe_poisson_solve": ([vp, vp, vp, dbl, i32, vp, vp, vp], i32),
         "oefe_kernel_timer": ([vp, i32], i32),
@@ -113,6 +115,7 @@ EXPORTED = [
     "oefe_autotune",
     "lanczos_bounds", "cholgs", "cholgs_async", "cholgs_noalloc", "rayleigh_ritz", "oefe_set_eig_sweep_limit", "band_energy_grad",
     "oefe_fermi_occupations", "oefe_density", "oefe_poisson_create", "oefe_poisson_work_size", "oefe_poisson_solve",
+    "oefe_poisson_create_adaptive", "oefe_poisson_solve_adaptive",
     "oefe_kernel_timer",
     "oefe_kernel_timer_read", "oefe_copy_rate", "oefe_strerror", "oefe_last_error",
 ]
@@ -183,7 +186,11 @@ class Operator:
             if not torch.cuda.is_available():
                 raise RuntimeError("no HIP device")
             torch.cuda.current_device()
-            if poisson:
+            if poisson and adaptive is not None:
+                tol, depth = adaptive
+                _check(_lib.oefe_poisson_create_adaptive(ctypes.byref(d), float(tol), int(depth), ctypes.byref(self._h)),
+                       "oefe_poisson_create_adaptive")
+            elif poisson:
                 _check(_lib.oefe_poisson_create(ctypes.byref(d), ctypes.byref(self._h)), "oefe_poisson_create")
             elif uform and adaptive is not None:
                 tol, depth = adaptive
@@ -606,10 +613,12 @@ def density(op: Operator, X: torch.Tensor, weights: torch.Tensor, rho: Optional[
     return rho
 
 
-def poisson_solve(pop: Operator, rho: torch.Tensor, tol: float = 1e-10, max_iter: int = 2000):
+def poisson_solve(pop: Operator, rho: torch.Tensor, tol: float = 1e-10, max_iter: int = 2000,
+                  rho_adapt: Optional[torch.Tensor] = None):
     """phi_aux coefficients (device float64 [n_tot]: FE part with zero mass-weighted mean, then one
     per atom) for the electron density rho at the quadrature points ([n_cells, nq] float64, device)
-    and the smeared nuclear charges; returns (phi, iterations, relative residual)."""
+    and the smeared nuclear charges; returns (phi, iterations, relative residual).  An operator with
+    the adaptive rule also takes rho_adapt at the rule's points (oefe_poisson_solve_adaptive)."""
     if not pop.is_poisson:
         raise ValueError("not a Poisson operator (Operator(system, poisson=True))")
     if not rho.is_cuda or rho.dtype != torch.float64 or rho.numel() != pop.n_cells * pop.nq:
@@ -621,6 +630,11 @@ def poisson_solve(pop: Operator, rho: torch.Tensor, tol: float = 1e-10, max_iter
         w = torch.empty(int(_lib.oefe_poisson_work_size(pop.handle)), dtype=torch.uint8, device=rho.device)
         pop._work["poisson"] = w
     info = (ctypes.c_double * 2)()
+    if rho_adapt is not None:
+        ra = rho_adapt.to(device=rho.device, dtype=torch.float64).contiguous()
+        _check(_lib.oefe_poisson_solve_adaptive(pop.handle, _ptr(rho), _ptr(ra), _ptr(phi), float(tol), int(max_iter),
+                                                info, _ptr(w), _stream()), "oefe_poisson_solve_adaptive")
+        return phi, int(info[0]), float(info[1])
     _check(_lib.oefe_poisson_solve(pop.handle, _ptr(rho), _ptr(phi), float(tol), int(max_iter), info, _ptr(w),
                                    _stream()), "oefe_poisson_solve")
     return phi, int(info[0]), float(info[1])

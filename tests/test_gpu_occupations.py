@@ -84,26 +84,30 @@ def test_occupations_reject_unreachable_count(lib):
 
 @pytest.mark.parametrize("kvec", [None, (0.3, -0.2, 0.1)])
 def test_density_and_band_energy_from_ritz_pairs(lib, kvec):
-    """single_atom after five ChFSI passes on the GPU: occupations of its Ritz values, the density
-    of its Ritz vectors against the oracle's, accumulated over two calls, and the band energy of the
-    Ritz values against the Rayleigh quotients (band_energy_grad) with the same weights."""
+    """single_atom after five oracle ChFSI passes: the GPU's occupations of the oracle's Ritz values,
+    the GPU's density of the oracle's Ritz vectors (weights 2 f from the oracle's occupations) against
+    the oracle's density, accumulated over two calls, and the GPU's band energy of those vectors
+    (band_energy_grad) against the oracle's band energy of the Ritz values with the same weights."""
     import torch
-    from paper_2010_09701_amd.chfsi import chfsi_run
+    from oracle import chfsi as och
     cfg = wl.config("single_atom")
     sysm = cfg.system if kvec is None else cfg.system.with_k(np.array(kvec))
     op = OEFEOperator(sysm)
     gop = lib.Operator(sysm)
     X0 = wl.start_block(op.n_tot, cfg.nv, 0, complex_=kvec is not None)
     v0 = wl.lanczos_start(op.n_tot, 2)
-    r = chfsi_run(gop, torch.from_numpy(X0).cuda(), torch.from_numpy(v0).cuda(), cfg.m, cfg.passes, cfg.lanczos_k)
-    th = r["theta"]
-    f, mu, eb = _check(lib, [th], [1.0], 6.0)
-    wts = 2.0 * f[0]
-    rho = lib.density(gop, r["X"], wts)
-    Xh = r["X"].cpu().numpy()
-    rho_o = occ.density(op, Xh, wts.cpu().numpy())
+    r = och.chfsi(op.apply, X0, v0, cfg.m, cfg.passes, cfg.lanczos_k)
+    th, Xo = r["theta"], r["X"]
+    _check(lib, [th], [1.0], 6.0)
+    mu_o, _ = occ.fermi_level([th], [1.0], 6.0, KT)
+    wts = 2.0 * occ.fermi_dirac(th, mu_o, KT)
+    eb_o = occ.band_energy([th], [1.0], [wts / 2.0])
+    Xd = torch.from_numpy(np.ascontiguousarray(Xo)).cuda()
+    wd = torch.from_numpy(wts).cuda()
+    rho = lib.density(gop, Xd, wd)
+    rho_o = occ.density(op, Xo, wts)
     assert np.abs(rho.cpu().numpy() - rho_o).max() <= 1e-10 * np.abs(rho_o).max()
-    lib.density(gop, r["X"], wts, rho=rho, accumulate=True)
+    lib.density(gop, Xd, wd, rho=rho, accumulate=True)
     assert np.abs(rho.cpu().numpy() - 2.0 * rho_o).max() <= 1e-10 * np.abs(rho_o).max()
-    E, _, _ = lib.band_energy_grad(gop, r["X"], wts, want_dV=False, want_dX=False)
-    assert abs(float(E) - eb) <= 1e-9 * abs(eb)
+    E, _, _ = lib.band_energy_grad(gop, Xd, wd, want_dV=False, want_dX=False)
+    assert abs(float(E) - eb_o) <= 1e-9 * abs(eb_o)

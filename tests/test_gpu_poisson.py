@@ -10,6 +10,8 @@ against the oracle (oracle/poisson.py).
   of their largest magnitude, the bound used.
 * diamond8 (12^3 cells p = 4, 8 atoms): the oracle's solution stored by tests/golden/make_golden.py.
 * Errors: a Kohn-Sham operator is refused; a tolerance not met reports ENOCONV.
+* The enrichment integrals on the adaptive rule (oefe_poisson_create_adaptive,
+  oefe_poisson_solve_adaptive) against oracle/adaptive.py's AdaptivePoissonOEFE.
 """
 import dataclasses
 import os
@@ -104,3 +106,37 @@ def test_poisson_errors(lib):
         lib.poisson_solve(pop, rho + 1e-3 * torch.arange(rho.numel(), dtype=torch.float64, device="cuda").reshape(rho.shape),
                           tol=1e-14, max_iter=2)
     assert ei.value.code == -5  # OEFE_ENOCONV
+
+
+def test_poisson_adaptive_operator_and_solve_vs_oracle(lib):
+    """The Poisson operator with its enrichment integrals on the adaptive rule
+    (oefe_poisson_create_adaptive) against oracle/adaptive.py: the rule's points, the
+    preconditioned operator column by column to 1e-10, the solution (the charge at the rule's
+    points for the enrichment rows, oefe_poisson_solve_adaptive) to 1e-8; the plain solve refuses
+    such an operator."""
+    import torch
+    from oracle import adaptive as ad
+    s = dataclasses.replace(wl.tiny_system(nc=3, p=3, n_atoms=2, seed=5, L=8.0, r0=2.0, r1=3.5), Z=np.full(2, 14.0))
+    P = ad.AdaptivePoissonOEFE(s, 1e-8, 2)
+    pop = lib.Operator(s, poisson=True, adaptive=(1e-8, 2))
+    n, xyz, _ = pop.adaptive_points()
+    assert n == P.rule.n_points and np.abs(xyz - P.rule.all_points()).max() <= 1e-13 * s.L
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1.0, 1.0, size=(P.n_tot, 4))
+    Y = lib.ham_apply(pop, torch.from_numpy(X).cuda()).cpu().numpy()
+    lam, U = np.linalg.eigh(P.Aoo)
+    S = (U / np.sqrt(lam)[None, :]) @ U.T
+    d = 1.0 / np.sqrt(P.m)
+    AZ = P.matrix() @ np.concatenate([d[:, None] * X[:P.N], S @ X[P.N:]])
+    Yo = np.concatenate([d[:, None] * AZ[:P.N], S @ AZ[P.N:]])
+    err = np.abs(Y - Yo).max(axis=0) / np.abs(Yo).max(axis=0)
+    assert err.max() <= 1e-10, err
+    rho = P.base.model_electron_density()
+    rho_a = P.model_density_at(P.rule.all_points())
+    phi_o = P.solve(rho, rho_a)
+    rho_d = torch.from_numpy(np.ascontiguousarray(rho)).cuda()
+    phi, it, rel = lib.poisson_solve(pop, rho_d, tol=1e-12, max_iter=5000, rho_adapt=torch.from_numpy(rho_a).cuda())
+    assert rel <= 1e-12
+    assert np.abs(phi.cpu().numpy() - phi_o).max() <= 1e-8 * np.abs(phi_o).max()
+    with pytest.raises(lib.OefeError):
+        lib.poisson_solve(pop, rho_d, tol=1e-12, max_iter=5000)
