@@ -475,6 +475,31 @@ def adaptive_bench(oefe, wl, torch, reps):
               f"lowest Ritz value {thetas[name][0]:.6f}")
         del op
         torch.cuda.empty_cache()
+    # the auxiliary-potential solve (smeared nuclear charges, no electron density) with the Gauss rule
+    # and with the adaptive rule on the phi enrichment (tol 1e-6, depth 2)
+    pois = {}
+    for name, spec in (("gauss", None), ("tol1e-6_d2", (1e-6, 2))):
+        t = time.time()
+        pop = oefe.Operator(cfg.system, poisson=True, adaptive=spec)
+        torch.cuda.synchronize()
+        setup_s = time.time() - t
+        rho = torch.zeros(pop.n_cells, pop.nq, dtype=torch.float64, device="cuda")
+        ra = None
+        if spec is not None:
+            ra = torch.zeros(pop.adaptive_points(coords=False)[0], dtype=torch.float64, device="cuda")
+        oefe.poisson_solve(pop, rho, tol=1e-10, max_iter=20000, rho_adapt=ra)  # warm-up
+        torch.cuda.synchronize()
+        t = time.time()
+        phi, iters, rel = oefe.poisson_solve(pop, rho, tol=1e-10, max_iter=20000, rho_adapt=ra)
+        torch.cuda.synchronize()
+        ms = (time.time() - t) * 1e3
+        coef = phi[pop.n_fe:].cpu().numpy()
+        pois[name] = {"setup_s": setup_s, "solve_ms": ms, "cg_iterations": iters, "relative_residual": rel,
+                      "enrichment_coefficients": [float(x) for x in coef]}
+        log(f"diamond8 Poisson {name}: set-up {setup_s:.1f} s, solve {ms:.1f} ms ({iters} CG iterations), "
+            f"enrichment coefficients {coef.min():.6f} .. {coef.max():.6f}")
+        del pop
+    res["poisson"] = pois
     res["ritz_diff_pass5_Ha"] = {
         "adaptive_d2_vs_gauss": float(np.abs(thetas["tol1e-6_d2"] - thetas["gauss"]).max()),
         "adaptive_d3_vs_d2": float(np.abs(thetas["tol1e-7_d3"] - thetas["tol1e-6_d2"]).max()),
@@ -494,6 +519,11 @@ def profile_run(oefe, wl, torch, cfg, args):
     oefe.chebyshev_filter(gop, X, cfg.m, a, b, a0)
     torch.cuda.synchronize()
     log(f"profile: {cfg.system.name} float64 filter done")
+    if args.profile_extra:  # the rest of the pass: CholGS and Rayleigh-Ritz of the filtered block
+        oefe.cholgs(gop, X)
+        oefe.rayleigh_ritz(gop, X)
+        torch.cuda.synchronize()
+        log(f"profile: {cfg.system.name} CholGS and Rayleigh-Ritz done")
     del X, gop
     if args.profile_extra:
         from paper_2010_09701_amd.chfsi import chfsi_run
@@ -505,6 +535,19 @@ def profile_run(oefe, wl, torch, cfg, args):
         chfsi_run(g8, X8, v8, c8.m, 1, c8.lanczos_k, "bf16")
         torch.cuda.synchronize()
         log("profile: diamond8 float64 pass and bf16 pass done")
+        # two Monkhorst-Pack k-points (48 and 96 vectors), one batched complex128 filter of degree 4
+        ks = wl.monkhorst_pack_2(c8.system.L)
+        kops = [oefe.Operator(c8.system.with_k(ks[q])) for q in (0, 7)]
+        kX = [torch.from_numpy(wl.start_block(o.n_tot, wl.KPOINT_NV[q], 10 + q, complex_=True)).cuda()
+              for o, q in zip(kops, (0, 7))]
+        kabc = []
+        for o in kops:
+            kv0 = torch.from_numpy(wl.lanczos_start(o.n_tot, 2)).cuda()
+            ka0, kb_, ka = oefe.lanczos_bounds(o, kv0, 10, with_cut=True)
+            kabc.append((ka, kb_, ka0))
+        oefe.chebyshev_filter_batched(kops, kX, 4, kabc)
+        torch.cuda.synchronize()
+        log("profile: diamond8 two k-points batched filter done")
     if args.calib_copy:
         a_ = torch.empty(CALIB_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
         c_ = torch.empty_like(a_)
