@@ -100,6 +100,7 @@ def parse():
                     help="short run for a kernel trace: two auxiliary-potential solves of the workload (smeared "
                          "nuclear charges with a uniform background, no electron density)")
     ap.add_argument("--summarize-trace", metavar="DIR")
+    ap.add_argument("--match", help="with --summarize-trace: only kernels whose name holds one of these (comma-separated)")
     ap.add_argument("--summarize-gaps", nargs=2, metavar=("DIR", "KERNEL"),
                     help="per filter degree (between successive launches of KERNEL): period, time with a "
                          "kernel running on any stream, idle remainder, launches")
@@ -556,13 +557,17 @@ def profile_run(oefe, wl, torch, cfg, args):
         torch.cuda.synchronize()
 
 
-def summarize_trace(d):
+def summarize_trace(d, match=None):
+    """Top 24 kernels of a rocprofv3 --stats run, or (match: comma-separated name parts) every kernel
+    whose name holds one of them."""
     f = sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True))
     if not f:
         sys.exit(f"no kernel_stats.csv under {d}")
     print("| kernel | calls | avg us | min us | max us | share % |")
     print("|---|---:|---:|---:|---:|---:|")
-    for r in list(csv.DictReader(open(f[0])))[:24]:
+    rows = list(csv.DictReader(open(f[0])))
+    rows = [r for r in rows if any(m in r["Name"] for m in match.split(","))] if match else rows[:24]
+    for r in rows:
         print(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
               f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
 
@@ -699,7 +704,7 @@ def summarize_traffic(fetch_dir, write_dir, prefix):
 def main():
     args = parse()
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace)
+        summarize_trace(args.summarize_trace, args.match)
         return
     if args.summarize_gaps:
         summarize_gaps(*args.summarize_gaps)
