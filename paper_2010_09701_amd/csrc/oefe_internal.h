@@ -86,6 +86,18 @@ constexpr int kTileFunctionsMax = 144;
 
 using cplx = std::complex<double>;
 
+// A 5 x 5 matrix M that a reflection of both indices leaves unchanged (M[4-q][4-a] = M[q][a]:
+// the 1D operators of degree 4 on the symmetric GLL nodes and Gauss points), by its even and
+// odd halves: e[q][a] = (M[q][a] + M[q][4-a]) / 2 for a < 2 and e[q][2] = M[q][2] (q <= 2),
+// o[q][a] = (M[q][a] - M[q][4-a]) / 2 (q, a < 2).  Then, with e_a = v_a + v_4-a and
+// o_a = v_a - v_4-a, (M v)_q = E_q + O_q and (M v)_4-q = E_q - O_q, E = e (e_0, e_1, v_2) and
+// O = o (o_0, o_1): 13 products and 8 additions in place of 25 products.
+template <typename T>
+struct EO5 {
+  T e[3][3];
+  T o[2][2];
+};
+
 // 1D reference data in the form the cell kernel uses (q = p + 1 Gauss points).
 //  B1[qi][a]   Lagrange basis on GLL nodes at Gauss point qi
 //  L1[qi][qj]  collocation Laplacian at Gauss points: Dh^T diag(w) Dh, Dh = D1 B1^-1
@@ -106,6 +118,8 @@ struct CellCoef {
   // the derivative at the Gauss points of the interpolant of values there (reference
   // coordinates): the first-derivative term of the periodic-function k-point form
   T Dh[kMaxP1][kMaxP1];
+  // degree 4 only: the halves of B1, B1^T, L1, BtW and kappa BtW
+  EO5<T> eB1, eB1t, eL1, eBtW, ekBtW;
 };
 
 struct DeviceArrays {

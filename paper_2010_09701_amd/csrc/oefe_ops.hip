@@ -88,6 +88,162 @@ struct KBatch {
   KP<T> k[KMAX];
 };
 
+
+// ---------------------------------------------------------------------------
+// 1D passes of the sum-factorized cell operator, shared by the cell kernels so that every
+// launch shape does the same arithmetic.  EO (degree 4): each 5-point contraction through
+// the even and odd halves of its matrix (EO5); otherwise plain sums in index order.
+// ---------------------------------------------------------------------------
+// out(q, (M v)_q) for q < 5 from in(a) = v_a, M given by its halves
+template <typename T, typename In, typename Out>
+__device__ __forceinline__ void eo5_apply(const EO5<T>& m, In in, Out out) {
+  const T v0 = in(0), v1 = in(1), v2 = in(2), v3 = in(3), v4 = in(4);
+  const T e0 = v0 + v4, e1 = v1 + v3, o0 = v0 - v4, o1 = v1 - v3;
+  const T E0 = m.e[0][0] * e0 + m.e[0][1] * e1 + m.e[0][2] * v2;
+  const T E1 = m.e[1][0] * e0 + m.e[1][1] * e1 + m.e[1][2] * v2;
+  const T E2 = m.e[2][0] * e0 + m.e[2][1] * e1 + m.e[2][2] * v2;
+  const T O0 = m.o[0][0] * o0 + m.o[0][1] * o1;
+  const T O1 = m.o[1][0] * o0 + m.o[1][1] * o1;
+  out(0, E0 + O0);
+  out(1, E1 + O1);
+  out(2, E2);
+  out(3, E1 - O1);
+  out(4, E0 - O0);
+}
+
+// x- then y-pass with B1 on a z-plane: v[ay][ax] -> v[qy][qx] (t is scratch)
+template <typename T, int P1, bool EO>
+__device__ __forceinline__ void cell_pass_xy(const CellCoef<T>& cf, T (&v)[P1 * P1], T (&t)[P1 * P1]) {
+  if constexpr (EO) {
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay)
+      eo5_apply(cf.eB1, [&](int a) { return v[ay * P1 + a]; }, [&](int q, T r) { t[ay * P1 + q] = r; });
+#pragma unroll
+    for (int qx = 0; qx < P1; ++qx)
+      eo5_apply(cf.eB1, [&](int a) { return t[a * P1 + qx]; }, [&](int q, T r) { v[q * P1 + qx] = r; });
+  } else {
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay)
+#pragma unroll
+      for (int qx = 0; qx < P1; ++qx) {
+        T s = 0;
+#pragma unroll
+        for (int ax = 0; ax < P1; ++ax) s += cf.B1[qx][ax] * v[ay * P1 + ax];
+        t[ay * P1 + qx] = s;
+      }
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < P1; ++qx) {
+        T s = 0;
+#pragma unroll
+        for (int ay = 0; ay < P1; ++ay) s += cf.B1[qy][ay] * t[ay * P1 + qx];
+        v[qy * P1 + qx] = s;
+      }
+  }
+}
+
+// z-pass with B1 on an x-plane: t[az][qy] -> u[qz][qy]
+template <typename T, int P1, bool EO>
+__device__ __forceinline__ void cell_pass_z(const CellCoef<T>& cf, const T (&t)[P1 * P1], T (&u)[P1 * P1]) {
+  if constexpr (EO) {
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy)
+      eo5_apply(cf.eB1, [&](int a) { return t[a * P1 + qy]; }, [&](int q, T r) { u[q * P1 + qy] = r; });
+  } else {
+#pragma unroll
+    for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+      for (int qy = 0; qy < P1; ++qy) {
+        T s = 0;
+#pragma unroll
+        for (int az = 0; az < P1; ++az) s += cf.B1[qz][az] * t[az * P1 + qy];
+        u[qz * P1 + qy] = s;
+      }
+  }
+}
+
+// t' = (B^T)_y (B^T)_z t: t[qz][qy] -> tp[az][ay] (v is scratch)
+template <typename T, int P1, bool EO>
+__device__ __forceinline__ void cell_back_yz(const CellCoef<T>& cf, const T (&t)[P1 * P1], T (&v)[P1 * P1],
+                                             T (&tp)[P1 * P1]) {
+  if constexpr (EO) {
+#pragma unroll
+    for (int qz = 0; qz < P1; ++qz)
+      eo5_apply(cf.eB1t, [&](int q) { return t[qz * P1 + q]; }, [&](int ay, T r) { v[qz * P1 + ay] = r; });
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay)
+      eo5_apply(cf.eB1t, [&](int q) { return v[q * P1 + ay]; }, [&](int az, T r) { tp[az * P1 + ay] = r; });
+  } else {
+#pragma unroll
+    for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+      for (int ay = 0; ay < P1; ++ay) {
+        T s = 0;
+#pragma unroll
+        for (int qy = 0; qy < P1; ++qy) s += cf.B1[qy][ay] * t[qz * P1 + qy];
+        v[qz * P1 + ay] = s;
+      }
+#pragma unroll
+    for (int az = 0; az < P1; ++az)
+#pragma unroll
+      for (int ay = 0; ay < P1; ++ay) {
+        T s = 0;
+#pragma unroll
+        for (int qz = 0; qz < P1; ++qz) s += cf.B1[qz][az] * v[qz * P1 + ay];
+        tp[az * P1 + ay] = s;
+      }
+  }
+}
+
+// the x kinetic term before its x-pass: u <- kappa (B^T W)_y (B^T W)_z u (v is scratch)
+template <typename T, int P1, bool EO>
+__device__ __forceinline__ void cell_xkin_yz(const CellCoef<T>& cf, T (&u)[P1 * P1], T (&v)[P1 * P1]) {
+  if constexpr (EO) {
+#pragma unroll
+    for (int qz = 0; qz < P1; ++qz)
+      eo5_apply(cf.eBtW, [&](int q) { return u[qz * P1 + q]; }, [&](int ay, T r) { v[qz * P1 + ay] = r; });
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay)
+      eo5_apply(cf.ekBtW, [&](int q) { return v[q * P1 + ay]; }, [&](int az, T r) { u[az * P1 + ay] = r; });
+  } else {
+#pragma unroll
+    for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+      for (int ay = 0; ay < P1; ++ay) {
+        T s = 0;
+#pragma unroll
+        for (int qy = 0; qy < P1; ++qy) s += cf.BtW[ay][qy] * u[qz * P1 + qy];
+        v[qz * P1 + ay] = s;
+      }
+#pragma unroll
+    for (int az = 0; az < P1; ++az)
+#pragma unroll
+      for (int ay = 0; ay < P1; ++ay) {
+        T s = 0;
+#pragma unroll
+        for (int qz = 0; qz < P1; ++qz) s += cf.BtW[az][qz] * v[qz * P1 + ay];
+        u[az * P1 + ay] = cf.kappa * s;
+      }
+  }
+}
+
+// x-pass with B^T of one row: y[ax] = sum_q B1[q][ax] r[q]
+template <typename T, int P1, bool EO>
+__device__ __forceinline__ void cell_back_x(const CellCoef<T>& cf, const T (&r)[P1], T* y) {
+  if constexpr (EO) {
+    eo5_apply(cf.eB1t, [&](int q) { return r[q]; }, [&](int ax, T o) { y[ax] = o; });
+  } else {
+#pragma unroll
+    for (int ax = 0; ax < P1; ++ax) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < P1; ++q) s += cf.B1[q][ax] * r[q];
+      y[ax] = s;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Cell kernel.
 //
@@ -106,6 +262,7 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, CellCoef
                                                           int64_t n_cells) {
   constexpr int NP = P1 * P1;
   constexpr int CPT = 64 / CW;
+  constexpr bool EO = P1 == 5;  // the same passes as the planes-in-lanes kernel
   __shared__ T lds[NP * P1][64];
   const KP<T>& P = kb.k[blockIdx.z];
   const int ncr = P.ncr;
@@ -162,24 +319,7 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, CellCoef
   }
   // 2. x- then y-pass with B1 (in registers)
   T t[NP];
-#pragma unroll
-  for (int ay = 0; ay < P1; ++ay)
-#pragma unroll
-    for (int qx = 0; qx < P1; ++qx) {
-      T s = 0;
-#pragma unroll
-      for (int ax = 0; ax < P1; ++ax) s += cf.B1[qx][ax] * v[ay * P1 + ax];
-      t[ay * P1 + qx] = s;
-    }
-#pragma unroll
-  for (int qy = 0; qy < P1; ++qy)
-#pragma unroll
-    for (int qx = 0; qx < P1; ++qx) {
-      T s = 0;
-#pragma unroll
-      for (int ay = 0; ay < P1; ++ay) s += cf.B1[qy][ay] * t[ay * P1 + qx];
-      v[qy * P1 + qx] = s;
-    }
+  cell_pass_xy<T, P1, EO>(cf, v, t);
   // 3. transpose z-planes -> x-planes: lds[(az*P1 + qy)*P1 + qx]
 #pragma unroll
   for (int qy = 0; qy < P1; ++qy)
@@ -193,15 +333,7 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, CellCoef
     for (int qy = 0; qy < P1; ++qy) t[az * P1 + qy] = lds[(az * P1 + qy) * P1 + w][lane];
   // 4. z-pass -> u[qz][qy]
   T u[NP];
-#pragma unroll
-  for (int qz = 0; qz < P1; ++qz)
-#pragma unroll
-    for (int qy = 0; qy < P1; ++qy) {
-      T s = 0;
-#pragma unroll
-      for (int az = 0; az < P1; ++az) s += cf.B1[qz][az] * t[az * P1 + qy];
-      u[qz * P1 + qy] = s;
-    }
+  cell_pass_z<T, P1, EO>(cf, t, u);
   // 5. quadrature-point terms: potential + y/z kinetic
   const int qx = w;
   const T kx = cf.kappa * cf.w[qx];
@@ -220,43 +352,9 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, CellCoef
     }
   // 6. t' = (B^T)_y (B^T)_z t  -> indexed [az][ay]
   T tp[NP];
-#pragma unroll
-  for (int qz = 0; qz < P1; ++qz)
-#pragma unroll
-    for (int ay = 0; ay < P1; ++ay) {
-      T s = 0;
-#pragma unroll
-      for (int qy = 0; qy < P1; ++qy) s += cf.B1[qy][ay] * t[qz * P1 + qy];
-      v[qz * P1 + ay] = s;
-    }
-#pragma unroll
-  for (int az = 0; az < P1; ++az)
-#pragma unroll
-    for (int ay = 0; ay < P1; ++ay) {
-      T s = 0;
-#pragma unroll
-      for (int qz = 0; qz < P1; ++qz) s += cf.B1[qz][az] * v[qz * P1 + ay];
-      tp[az * P1 + ay] = s;
-    }
+  cell_back_yz<T, P1, EO>(cf, t, v, tp);
   // 7. s = kappa (B^T W)_y (B^T W)_z u  (the x kinetic term before its x-pass)
-#pragma unroll
-  for (int qz = 0; qz < P1; ++qz)
-#pragma unroll
-    for (int ay = 0; ay < P1; ++ay) {
-      T s = 0;
-#pragma unroll
-      for (int qy = 0; qy < P1; ++qy) s += cf.BtW[ay][qy] * u[qz * P1 + qy];
-      v[qz * P1 + ay] = s;
-    }
-#pragma unroll
-  for (int az = 0; az < P1; ++az)
-#pragma unroll
-    for (int ay = 0; ay < P1; ++ay) {
-      T s = 0;
-#pragma unroll
-      for (int qz = 0; qz < P1; ++qz) s += cf.BtW[az][qz] * v[qz * P1 + ay];
-      u[az * P1 + ay] = cf.kappa * s;
-    }
+  cell_xkin_yz<T, P1, EO>(cf, u, v);
   // 8. transpose t' back to z-planes, x-pass with B^T
   __syncthreads();
 #pragma unroll
@@ -270,13 +368,7 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, CellCoef
     T r[P1];
 #pragma unroll
     for (int q = 0; q < P1; ++q) r[q] = lds[(w * P1 + ay) * P1 + q][lane];
-#pragma unroll
-    for (int ax = 0; ax < P1; ++ax) {
-      T s = 0;
-#pragma unroll
-      for (int q = 0; q < P1; ++q) s += cf.B1[q][ax] * r[q];
-      y[ay * P1 + ax] = s;
-    }
+    cell_back_x<T, P1, EO>(cf, r, y + ay * P1);
   }
   // 9. transpose s, x-pass with B^T L1, accumulate
   __syncthreads();
@@ -339,11 +431,14 @@ constexpr int lanes_cw() { return (64 / P1) & ~1; }
 // the complex partner lane (real <-> imaginary part) with the sign of -i, into the values that
 // the backward passes project.
 template <typename T, int P1, bool CPLX, bool UF = false>
-__global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCoef<T> cf, int nc, int p, int n,
+__global__ __launch_bounds__(256, 3) void fe_cell_lanes_kernel(KBatch<T> kb, CellCoef<T> cf, int nc, int p, int n,
                                                             int64_t n_cells, int nch) {
   static_assert(!UF || CPLX, "the first-derivative term acts on complex columns");
   constexpr int NP = P1 * P1;
   constexpr int CWc = lanes_cw<P1>();
+  // degree 4: the even-odd passes (the periodic-function form, which runs in this kernel only,
+  // keeps the plain sums: its first-derivative term needs the registers)
+  constexpr bool EO = P1 == 5 && !UF;
   // launch order: the column chunks of a group of 4 cells are consecutive in L, and each
   // XCD (workgroups bk = x mod 8) takes a contiguous range of L, so that the chunks reading
   // the same node rows, and neighbouring cells, share one L2
@@ -423,24 +518,7 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCo
   }
   // 2. x- then y-pass with B1 (in registers)
   T t[NP];
-#pragma unroll
-  for (int ay = 0; ay < P1; ++ay)
-#pragma unroll
-    for (int qx = 0; qx < P1; ++qx) {
-      T s = 0;
-#pragma unroll
-      for (int ax = 0; ax < P1; ++ax) s += cf.B1[qx][ax] * v[ay * P1 + ax];
-      t[ay * P1 + qx] = s;
-    }
-#pragma unroll
-  for (int qy = 0; qy < P1; ++qy)
-#pragma unroll
-    for (int qx = 0; qx < P1; ++qx) {
-      T s = 0;
-#pragma unroll
-      for (int ay = 0; ay < P1; ++ay) s += cf.B1[qy][ay] * t[ay * P1 + qx];
-      v[qy * P1 + qx] = s;
-    }
+  cell_pass_xy<T, P1, EO>(cf, v, t);
   // UF: x-derivative of the x-y plane (transposed after step 3, z-interpolated after step 4)
   T dxv[UF ? NP : 1];
   if constexpr (UF) {
@@ -478,15 +556,7 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCo
   }
   // 4. z-pass -> u[qz][qy]
   T u[NP];
-#pragma unroll
-  for (int qz = 0; qz < P1; ++qz)
-#pragma unroll
-    for (int qy = 0; qy < P1; ++qy) {
-      T s = 0;
-#pragma unroll
-      for (int az = 0; az < P1; ++az) s += cf.B1[qz][az] * t[az * P1 + qy];
-      u[qz * P1 + qy] = s;
-    }
+  cell_pass_z<T, P1, EO>(cf, t, u);
   // UF: t = W' uk . grad u at this lane's Gauss points (W' the product of the 1D weights; t is
   // free after step 4), taken from the complex partner with the sign of -i: real part
   // += (k.G) imag, imag -= (k.G) real; the x-derivative read from the transposed plane in LDS
@@ -534,43 +604,9 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCo
     }
   // 6. t' = (B^T)_y (B^T)_z t  -> indexed [az][ay]
   T tp[NP];
-#pragma unroll
-  for (int qz = 0; qz < P1; ++qz)
-#pragma unroll
-    for (int ay = 0; ay < P1; ++ay) {
-      T s = 0;
-#pragma unroll
-      for (int qy = 0; qy < P1; ++qy) s += cf.B1[qy][ay] * t[qz * P1 + qy];
-      v[qz * P1 + ay] = s;
-    }
-#pragma unroll
-  for (int az = 0; az < P1; ++az)
-#pragma unroll
-    for (int ay = 0; ay < P1; ++ay) {
-      T s = 0;
-#pragma unroll
-      for (int qz = 0; qz < P1; ++qz) s += cf.B1[qz][az] * v[qz * P1 + ay];
-      tp[az * P1 + ay] = s;
-    }
+  cell_back_yz<T, P1, EO>(cf, t, v, tp);
   // 7. s = kappa (B^T W)_y (B^T W)_z u  (the x kinetic term before its x-pass)
-#pragma unroll
-  for (int qz = 0; qz < P1; ++qz)
-#pragma unroll
-    for (int ay = 0; ay < P1; ++ay) {
-      T s = 0;
-#pragma unroll
-      for (int qy = 0; qy < P1; ++qy) s += cf.BtW[ay][qy] * u[qz * P1 + qy];
-      v[qz * P1 + ay] = s;
-    }
-#pragma unroll
-  for (int az = 0; az < P1; ++az)
-#pragma unroll
-    for (int ay = 0; ay < P1; ++ay) {
-      T s = 0;
-#pragma unroll
-      for (int qz = 0; qz < P1; ++qz) s += cf.BtW[az][qz] * v[qz * P1 + ay];
-      u[az * P1 + ay] = cf.kappa * s;
-    }
+  cell_xkin_yz<T, P1, EO>(cf, u, v);
   // 8. transpose t' back to z-planes, x-pass with B^T
   wave_sync();
 #pragma unroll
@@ -584,13 +620,7 @@ __global__ __launch_bounds__(256) void fe_cell_lanes_kernel(KBatch<T> kb, CellCo
     T r[P1];
 #pragma unroll
     for (int q = 0; q < P1; ++q) r[q] = lds[((w * P1 + ay) * P1 + q) * CWc + g];
-#pragma unroll
-    for (int ax = 0; ax < P1; ++ax) {
-      T s = 0;
-#pragma unroll
-      for (int q = 0; q < P1; ++q) s += cf.B1[q][ax] * r[q];
-      y[ay * P1 + ax] = s;
-    }
+    cell_back_x<T, P1, EO>(cf, r, y + ay * P1);
   }
   // 9. transpose s, x-pass with B^T L1, accumulate
   wave_sync();

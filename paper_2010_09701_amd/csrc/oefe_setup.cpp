@@ -756,6 +756,35 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
   op->cd.mscale = std::pow(h / 2.0, -1.5);
   for (int i = 0; i < P1; ++i)
     for (int j = 0; j < P1; ++j) op->cd.Dh[i][j] = Dh[i * P1 + j];
+  if (P1 == 5) {
+    // even and odd halves for the degree-4 cell kernel; the matrices are unchanged by the
+    // reflection of both indices up to rounding (symmetric nodes and points)
+    auto halves = [&](auto at, double scale, EO5<double>& r) {
+      double big = 0, asym = 0;
+      for (int q = 0; q < 5; ++q)
+        for (int a = 0; a < 5; ++a) {
+          big = std::max(big, std::fabs(at(q, a)));
+          asym = std::max(asym, std::fabs(at(q, a) - at(4 - q, 4 - a)));
+        }
+      for (int q = 0; q < 3; ++q) {
+        for (int a = 0; a < 2; ++a) r.e[q][a] = scale * 0.5 * (at(q, a) + at(q, 4 - a));
+        r.e[q][2] = scale * at(q, 2);
+      }
+      for (int q = 0; q < 2; ++q)
+        for (int a = 0; a < 2; ++a) r.o[q][a] = scale * 0.5 * (at(q, a) - at(q, 4 - a));
+      return asym <= 1e-12 * big;
+    };
+    auto& c = op->cd;
+    const bool sym = halves([&](int q, int a) { return c.B1[q][a]; }, 1.0, c.eB1) &&
+                     halves([&](int q, int a) { return c.B1[a][q]; }, 1.0, c.eB1t) &&
+                     halves([&](int q, int a) { return c.L1[q][a]; }, 1.0, c.eL1) &&
+                     halves([&](int q, int a) { return c.BtW[q][a]; }, 1.0, c.eBtW) &&
+                     halves([&](int q, int a) { return c.BtW[q][a]; }, c.kappa, c.ekBtW);
+    if (!sym) {
+      err = "the 1D cell matrices of degree 4 are not reflection-symmetric";
+      return OEFE_EINVAL;
+    }
+  }
   for (int d = 0; d < 3; ++d) op->uk[d] = uf ? std::pow(h / 2.0, 3) * (2.0 / h) * op->kvec[d] : 0.0;
   {
     auto& f = op->cf;
@@ -774,6 +803,17 @@ int build_operator(oefe_op_s* op, const oefe_system_desc* desc, std::string& err
     f.mscale = (float)c.mscale;
     for (int i = 0; i < kMaxP1; ++i)
       for (int j = 0; j < kMaxP1; ++j) f.Dh[i][j] = (float)c.Dh[i][j];
+    auto to_f = [](const EO5<double>& d, EO5<float>& r) {
+      for (int q = 0; q < 3; ++q)
+        for (int a = 0; a < 3; ++a) r.e[q][a] = (float)d.e[q][a];
+      for (int q = 0; q < 2; ++q)
+        for (int a = 0; a < 2; ++a) r.o[q][a] = (float)d.o[q][a];
+    };
+    to_f(c.eB1, f.eB1);
+    to_f(c.eB1t, f.eB1t);
+    to_f(c.eL1, f.eL1);
+    to_f(c.eBtW, f.eBtW);
+    to_f(c.ekBtW, f.ekBtW);
   }
   // ---- lumped GLL mass m_g = (h/2)^3 prod_d w'(i_d mod p)
   const int n = op->n;
