@@ -228,6 +228,35 @@ __device__ __forceinline__ void cell_xkin_yz(const CellCoef<T>& cf, T (&u)[P1 * 
   }
 }
 
+// the quadrature-point terms: t = W V u + kappa w_x (w_z L1_y u + w_y L1_z u); wvq(qz, qy) is
+// W V at the point (qx, qy, qz) of this plane
+template <typename T, int P1, bool EO, typename WV>
+__device__ __forceinline__ void cell_point_terms(const CellCoef<T>& cf, const T (&u)[P1 * P1], T (&t)[P1 * P1],
+                                                 WV wvq, T kx) {
+#pragma unroll
+  for (int qz = 0; qz < P1; ++qz) {
+    T ly[P1];
+    if constexpr (EO) {
+      eo5_apply(cf.eL1, [&](int k) { return u[qz * P1 + k]; }, [&](int q, T r) { ly[q] = r; });
+    } else {
+#pragma unroll
+      for (int qy = 0; qy < P1; ++qy) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < P1; ++k) s += cf.L1[qy][k] * u[qz * P1 + k];
+        ly[qy] = s;
+      }
+    }
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy) {
+      T lz = 0;
+#pragma unroll
+      for (int k = 0; k < P1; ++k) lz += cf.L1[qz][k] * u[k * P1 + qy];
+      t[qz * P1 + qy] = wvq(qz, qy) * u[qz * P1 + qy] + kx * (cf.w[qz] * ly[qy] + cf.w[qy] * lz);
+    }
+  }
+}
+
 // x-pass with B^T of one row: y[ax] = sum_q B1[q][ax] r[q]
 template <typename T, int P1, bool EO>
 __device__ __forceinline__ void cell_back_x(const CellCoef<T>& cf, const T (&r)[P1], T* y) {
@@ -338,18 +367,7 @@ __global__ __launch_bounds__(64 * P1) void fe_cell_kernel(KBatch<T> kb, CellCoef
   const int qx = w;
   const T kx = cf.kappa * cf.w[qx];
   const T* wv = P.wv + ee * (NP * P1);
-#pragma unroll
-  for (int qz = 0; qz < P1; ++qz)
-#pragma unroll
-    for (int qy = 0; qy < P1; ++qy) {
-      T ly = 0, lz = 0;
-#pragma unroll
-      for (int k = 0; k < P1; ++k) {
-        ly += cf.L1[qy][k] * u[qz * P1 + k];
-        lz += cf.L1[qz][k] * u[k * P1 + qy];
-      }
-      t[qz * P1 + qy] = wv[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
-    }
+  cell_point_terms<T, P1, EO>(cf, u, t, [&](int qz, int qy) { return wv[(qz * P1 + qy) * P1 + qx]; }, kx);
   // 6. t' = (B^T)_y (B^T)_z t  -> indexed [az][ay]
   T tp[NP];
   cell_back_yz<T, P1, EO>(cf, t, v, tp);
@@ -585,23 +603,23 @@ __global__ __launch_bounds__(256, 3) void fe_cell_lanes_kernel(KBatch<T> kb, Cel
   // 5. quadrature-point terms: potential + y/z kinetic
   const int qx = w;
   const T kx = cf.kappa * cf.w[qx];
+  if constexpr (UF) {
 #pragma unroll
-  for (int qz = 0; qz < P1; ++qz)
+    for (int qz = 0; qz < P1; ++qz)
 #pragma unroll
-    for (int qy = 0; qy < P1; ++qy) {
-      T ly = 0, lz = 0;
+      for (int qy = 0; qy < P1; ++qy) {
+        T ly = 0, lz = 0;
 #pragma unroll
-      for (int k = 0; k < P1; ++k) {
-        ly += cf.L1[qy][k] * u[qz * P1 + k];
-        lz += cf.L1[qz][k] * u[k * P1 + qy];
-      }
-      const T tq = wvs[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
-      if constexpr (UF) {
+        for (int k = 0; k < P1; ++k) {
+          ly += cf.L1[qy][k] * u[qz * P1 + k];
+          lz += cf.L1[qz][k] * u[k * P1 + qy];
+        }
+        const T tq = wvs[(qz * P1 + qy) * P1 + qx] * u[qz * P1 + qy] + kx * (cf.w[qz] * ly + cf.w[qy] * lz);
         t[qz * P1 + qy] = tq + t[qz * P1 + qy];
-      } else {
-        t[qz * P1 + qy] = tq;
       }
-    }
+  } else {
+    cell_point_terms<T, P1, EO>(cf, u, t, [&](int qz, int qy) { return wvs[(qz * P1 + qy) * P1 + qx]; }, kx);
+  }
   // 6. t' = (B^T)_y (B^T)_z t  -> indexed [az][ay]
   T tp[NP];
   cell_back_yz<T, P1, EO>(cf, t, v, tp);
