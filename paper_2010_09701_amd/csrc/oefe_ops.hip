@@ -455,8 +455,8 @@ __global__ __launch_bounds__(256, 3) void fe_cell_lanes_kernel(KBatch<T> kb, Cel
   constexpr int NP = P1 * P1;
   constexpr int CWc = lanes_cw<P1>();
   // degree 4: the even-odd passes (the periodic-function form, which runs in this kernel only,
-  // keeps the plain sums: its first-derivative term needs the registers)
-  constexpr bool EO = P1 == 5 && !UF;
+  // keeps the plain sums in float64: there its first-derivative term needs the registers)
+  constexpr bool EO = P1 == 5 && (!UF || sizeof(T) == 4);
   // launch order: the column chunks of a group of 4 cells are consecutive in L, and each
   // XCD (workgroups bk = x mod 8) takes a contiguous range of L, so that the chunks reading
   // the same node rows, and neighbouring cells, share one L2
