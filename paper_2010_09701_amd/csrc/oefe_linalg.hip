@@ -2138,51 +2138,62 @@ __global__ __launch_bounds__(1024) void jbig_norm_kernel(const double* __restric
   ctl->sweeps += 1;
 }
 
+// The 2 x 2 diagonal block of pair k (entries 2k and 2k+1 of the current matrix)
 template <bool CPLX>
-__device__ __forceinline__ void jbig_table(const double* __restrict__ Ac, int NN, int npair, int m, int st, int k,
-                                           double nrm_n, Z* g, bool& on) {
+struct PairBlock {
+  double a00, a11;
+  Z b;
+};
+template <bool CPLX>
+__device__ __forceinline__ PairBlock<CPLX> jbig_pair_load(const double* __restrict__ Ac, int NN, int k) {
   constexpr int E = CPLX ? 2 : 1;
   const int p0 = 2 * k, p1 = 2 * k + 1;
-  const double a00 = Ac[((size_t)p0 * NN + p0) * E], a11 = Ac[((size_t)p1 * NN + p1) * E];
-  const Z b = jz_load<CPLX>(Ac + ((size_t)p0 * NN + p1) * E);
+  return {Ac[((size_t)p0 * NN + p0) * E], Ac[((size_t)p1 * NN + p1) * E], jz_load<CPLX>(Ac + ((size_t)p0 * NN + p1) * E)};
+}
+
+// The rotation of pair k at round st from its diagonal block
+template <bool CPLX>
+__device__ __forceinline__ void jbig_table(const PairBlock<CPLX>& pb, int m, int st, int k, double nrm_n, Z* g,
+                                           bool& on) {
   // position 2k holds the larger index q of the pair at this round (as in the LDS kernels)
   const int sa = (k + st) % m, sb = (m - k + st) % m;
   const bool sw = k >= 1 && sa > sb;
-  const JacobiRot R = jacobi_rotation<CPLX>(sw ? a11 : a00, sw ? a00 : a11, b.r, sw ? -b.i : b.i, nrm_n);
+  const JacobiRot R = jacobi_rotation<CPLX>(sw ? pb.a11 : pb.a00, sw ? pb.a00 : pb.a11, pb.b.r, sw ? -pb.b.i : pb.b.i, nrm_n);
   const Z g00{R.c, 0.0}, g01{R.s, 0.0}, g10{-R.s * R.er, R.s * R.ei}, g11{R.c * R.er, -R.c * R.ei};
   g[0] = sw ? g11 : g00;
   g[1] = sw ? g10 : g01;
   g[2] = sw ? g01 : g10;
   g[3] = sw ? g00 : g11;
   on = R.on;
-  (void)npair;
 }
 
+// One round: every 2 x 2 block (k1, k2) of the matrix (one thread each, k1 <= k2, from a
+// square index range of npair^2 threads of which those with k2 < k1 do nothing) and every
+// (row, pair) of V.  Each thread issues all its loads (the sweep state, the diagonal blocks
+// of its pairs, its own block or V entries) before any arithmetic: the round is a chain of
+// memory latencies, not of work.
 template <bool CPLX>
 __global__ __launch_bounds__(256) void jbig_round_kernel(const double* __restrict__ Ac, double* __restrict__ An,
                                                          const double* __restrict__ Vc, double* __restrict__ Vn,
                                                          int n, int st, JacobiCtl* __restrict__ ctl) {
   constexpr int E = CPLX ? 2 : 1;
-  if (ctl->done) return;
   const int NN = (n % 2) ? n + 1 : n, npair = NN / 2, m = NN - 1;
-  const int nblk = npair * (npair + 1) / 2;
-  const double nrm_n = ctl->nrm_n;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < nblk) {
-    // block b -> (k1, k2), k1 <= k2, row-major over the upper triangle of pairs
-    int k1 = (int)((2.0 * npair + 1.0 - sqrt((2.0 * npair + 1.0) * (2.0 * npair + 1.0) - 8.0 * (double)t)) * 0.5);
-    k1 = max(0, min(k1, npair - 1));
-    auto first = [npair](int k) { return k * npair - k * (k - 1) / 2; };
-    while (k1 > 0 && first(k1) > t) --k1;
-    while (k1 + 1 < npair && first(k1 + 1) <= t) ++k1;
-    const int k2 = k1 + (int)(t - first(k1));
-    Z u[4], v[4], bl[4], d[4];
-    bool on1, on2;
-    jbig_table<CPLX>(Ac, NN, npair, m, st, k1, nrm_n, u, on1);
-    jbig_table<CPLX>(Ac, NN, npair, m, st, k2, nrm_n, v, on2);
+  const int nsq = npair * npair;
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t < nsq) {
+    const int k1 = t / npair, k2 = t - k1 * npair;
+    if (k2 < k1) return;
+    const PairBlock<CPLX> p1 = jbig_pair_load<CPLX>(Ac, NN, k1), p2 = jbig_pair_load<CPLX>(Ac, NN, k2);
+    Z bl[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       bl[e] = jz_load<CPLX>(Ac + ((size_t)(2 * k1 + (e >> 1)) * NN + 2 * k2 + (e & 1)) * E);
+    const double nrm_n = ctl->nrm_n;
+    if (ctl->done) return;
+    Z u[4], v[4], d[4];
+    bool on1, on2;
+    jbig_table<CPLX>(p1, m, st, k1, nrm_n, u, on1);
+    jbig_table<CPLX>(p2, m, st, k2, nrm_n, v, on2);
 #pragma unroll
     for (int e = 0; e < 4; ++e) d[e] = jz_entry<CPLX>(u, bl, v, e >> 1, e & 1);
     if (k1 == k2) {
@@ -2201,15 +2212,18 @@ __global__ __launch_bounds__(256) void jbig_round_kernel(const double* __restric
     }
     return;
   }
-  const int64_t tv = t - nblk;
-  if (tv >= (int64_t)n * npair) return;
+  const int tv = t - nsq;
+  if (tv >= n * npair) return;
   // row r of V, pair k: (v_2k, v_2k+1) <- (v_2k, v_2k+1) G_k, moved along the ring
-  const int r = (int)(tv / npair), k = (int)(tv - (int64_t)r * npair);
-  Z g[4];
-  bool on;
-  jbig_table<CPLX>(Ac, NN, npair, m, st, k, nrm_n, g, on);
+  const int r = tv / npair, k = tv - r * npair;
+  const PairBlock<CPLX> pk = jbig_pair_load<CPLX>(Ac, NN, k);
   const double* vr = Vc + (size_t)r * NN * E;
   const Z v0 = jz_load<CPLX>(vr + (size_t)(2 * k) * E), v1 = jz_load<CPLX>(vr + (size_t)(2 * k + 1) * E);
+  const double nrm_n = ctl->nrm_n;
+  if (ctl->done) return;
+  Z g[4];
+  bool on;
+  jbig_table<CPLX>(pk, m, st, k, nrm_n, g, on);
   const Z w0 = jz_fma<CPLX>(v1, g[2], jz_mul<CPLX>(v0, g[0]));
   const Z w1 = jz_fma<CPLX>(v1, g[3], jz_mul<CPLX>(v0, g[1]));
   double* vn = Vn + (size_t)r * NN * E;
@@ -2281,8 +2295,7 @@ int jbig_eig(bool cplx, double* A, int n, double* lam, double* U, double* scratc
     hipLaunchKernelGGL(jbig_init_kernel<true>, dim3((unsigned)cdiv(ninit, 256)), dim3(256), 0, s, A, n, Ab[0], Vb[0], ctl);
   else
     hipLaunchKernelGGL(jbig_init_kernel<false>, dim3((unsigned)cdiv(ninit, 256)), dim3(256), 0, s, A, n, Ab[0], Vb[0], ctl);
-  const int nblk = npair * (npair + 1) / 2;
-  const unsigned grid = (unsigned)cdiv((int64_t)nblk + (int64_t)n * npair, 256);
+  const unsigned grid = (unsigned)cdiv((int64_t)npair * npair + (int64_t)n * npair, 256);
   // a pinned host word per host thread for the convergence flag (allocated once, kept)
   static thread_local int32_t* done_h = nullptr;
   if (!done_h && hipHostMalloc((void**)&done_h, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) done_h = nullptr;
