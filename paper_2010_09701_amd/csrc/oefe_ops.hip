@@ -684,6 +684,133 @@ __global__ __launch_bounds__(256, 3) void fe_cell_lanes_kernel(KBatch<T> kb, Cel
   }
 }
 
+// Cell stage at one real column (the auxiliary potential's conjugate gradients, Lanczos): the
+// planes-in-lanes kernel with cells in the place of columns, lane = plane x CWc + cell of the
+// wave, where the column layout would leave 11 of its 12 lane groups idle.  Every lane forms its
+// own cell's addresses (64-bit), reads W V of its cell's points from device memory, and runs the
+// same passes in the same order, so each cell's values equal the column layout's bit for bit.
+template <typename T, int P1>
+__global__ __launch_bounds__(256, 3) void fe_cell_cells_kernel(KBatch<T> kb, CellCoef<T> cf, int nc, int p, int n,
+                                                               int64_t n_cells) {
+  constexpr int NP = P1 * P1;
+  constexpr int CWc = lanes_cw<P1>();
+  constexpr bool EO = P1 == 5;
+  __shared__ T lds_all[4][NP * P1 * CWc];
+  const KP<T>& P = kb.k[blockIdx.z];
+  const T* __restrict__ X = P.x;
+  const int64_t ldx = P.ldx, ldc = P.ldc;
+  T* __restrict__ Yc = P.ycell;
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const bool active = lane < P1 * CWc;
+  const int w = min(lane / CWc, P1 - 1);                // plane of this lane
+  const int g = active ? lane % CWc : lane - P1 * CWc;  // cell of the wave; spare lanes repeat a last-plane lane
+  T* lds = lds_all[wid];
+  const int64_t e = ((int64_t)blockIdx.x * 4 + wid) * CWc + g;
+  const bool valid = e < n_cells;
+  const int64_t eu = valid ? e : n_cells - 1;  // a lane past the last cell works on the last cell and stores nothing
+  const int cx = (int)(eu % nc), cy = (int)((eu / nc) % nc), cz = (int)(eu / ((int64_t)nc * nc));
+  const T vmask = valid ? T(1) : T(0);
+
+  // 1. gather plane az = w with the m^-1/2 pre-scale
+  T v[NP];
+  {
+    const int az = w;
+    int iz = cz * p + az;
+    if (iz >= n) iz -= n;
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) {
+      int iy = cy * p + ay;
+      if (iy >= n) iy -= n;
+#pragma unroll
+      for (int ax = 0; ax < P1; ++ax) {
+        int ix = cx * p + ax;
+        if (ix >= n) ix -= n;
+        const T sc = cf.mscale * cf.om[ax] * cf.om[ay] * cf.om[az];
+        const T val = X[(ix + (int64_t)n * (iy + (int64_t)n * iz)) * ldx];
+        v[ay * P1 + ax] = sc * (val * vmask);
+      }
+    }
+  }
+  // 2. x- then y-pass
+  T t[NP];
+  cell_pass_xy<T, P1, EO>(cf, v, t);
+  // 3. transpose z-planes -> x-planes
+#pragma unroll
+  for (int qy = 0; qy < P1; ++qy)
+#pragma unroll
+    for (int qx = 0; qx < P1; ++qx) lds[((w * P1 + qy) * P1 + qx) * CWc + g] = v[qy * P1 + qx];
+  wave_sync();
+#pragma unroll
+  for (int az = 0; az < P1; ++az)
+#pragma unroll
+    for (int qy = 0; qy < P1; ++qy) t[az * P1 + qy] = lds[((az * P1 + qy) * P1 + w) * CWc + g];
+  // 4. z-pass
+  T u[NP];
+  cell_pass_z<T, P1, EO>(cf, t, u);
+  // 5. quadrature-point terms (W V of this lane's cell at the points of its plane)
+  const int qx = w;
+  const T kx = cf.kappa * cf.w[qx];
+  const T* __restrict__ wvc = P.wv + eu * (NP * P1);
+  cell_point_terms<T, P1, EO>(cf, u, t, [&](int qz, int qy) { return wvc[(qz * P1 + qy) * P1 + qx]; }, kx);
+  // 6. t' = (B^T)_y (B^T)_z t; 7. the x kinetic term before its x-pass
+  T tp[NP];
+  cell_back_yz<T, P1, EO>(cf, t, v, tp);
+  cell_xkin_yz<T, P1, EO>(cf, u, v);
+  // 8. transpose t' back to z-planes, x-pass with B^T
+  wave_sync();
+#pragma unroll
+  for (int az = 0; az < P1; ++az)
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) lds[((az * P1 + ay) * P1 + w) * CWc + g] = tp[az * P1 + ay];
+  wave_sync();
+  T y[NP];
+#pragma unroll
+  for (int ay = 0; ay < P1; ++ay) {
+    T r[P1];
+#pragma unroll
+    for (int q = 0; q < P1; ++q) r[q] = lds[((w * P1 + ay) * P1 + q) * CWc + g];
+    cell_back_x<T, P1, EO>(cf, r, y + ay * P1);
+  }
+  // 9. transpose s, x-pass with B^T L1, accumulate
+  wave_sync();
+#pragma unroll
+  for (int az = 0; az < P1; ++az)
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) lds[((az * P1 + ay) * P1 + w) * CWc + g] = u[az * P1 + ay];
+  wave_sync();
+#pragma unroll
+  for (int ay = 0; ay < P1; ++ay) {
+    T r[P1];
+#pragma unroll
+    for (int q = 0; q < P1; ++q) r[q] = lds[((w * P1 + ay) * P1 + q) * CWc + g];
+#pragma unroll
+    for (int ax = 0; ax < P1; ++ax) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < P1; ++q) s += cf.BtL[ax][q] * r[q];
+      y[ay * P1 + ax] += s;
+    }
+  }
+  // 10. store plane az = w of the cell's result into the node-slot grid (column 0)
+  if (valid && active) {
+    const int S = nc * P1;
+    int sz = cz * P1 + w + 1;
+    if (sz >= S) sz -= S;
+#pragma unroll
+    for (int ay = 0; ay < P1; ++ay) {
+      int sy = cy * P1 + ay + 1;
+      if (sy >= S) sy -= S;
+#pragma unroll
+      for (int ax = 0; ax < P1; ++ax) {
+        int sx = cx * P1 + ax + 1;
+        if (sx >= S) sx -= S;
+        Yc[(sx + (int64_t)S * (sy + (int64_t)S * sz)) * ldc] = y[ay * P1 + ax];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // BF16 cell kernel (real operators, float32 vectors): the cell operator in dense form
 //   U = B Z,  T = (W V) o U,  Y = K Z + B^T T
@@ -1608,6 +1735,70 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
   }
 }
 
+// Node stage of real operators at one column (the auxiliary-potential conjugate gradients,
+// Lanczos): one wave per coupling tile, lane = tile row, no LDS.  The slot gather takes the
+// same slots in the same order as fe_node_fused_kernel; the tile's coupling row is applied with
+// one product per function in list order, and each function's partial of H^co* x is a fixed
+// butterfly over the 64 rows.  Launched only when every operator of the step has one column.
+constexpr int kCol1MaxFunctions = 24;  // functions per tile up to which one column takes fe_node_col1_kernel
+template <typename T>
+__global__ __launch_bounds__(256) void fe_node_col1_kernel(KBatch<T> kb, int nc, int p, int n, int P1, CellCoef<T> cf,
+                                                           const int32_t* __restrict__ tile_fptr,
+                                                           const int32_t* __restrict__ tile_fns, int ntiles, int tm) {
+  constexpr int TR = kTileRows;
+  const KP<T>& P = kb.k[blockIdx.z];
+  const int t = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (t >= ntiles) return;  // the whole wave
+  const int r = (int)threadIdx.x & 63;
+  int x0, y0, z0, ix, iy, iz;
+  tile_origin(t, n, tm, x0, y0, z0);
+  const int gv = tile_row_coords(x0, y0, z0, r, n, tm, ix, iy, iz);
+  const bool ok = gv >= 0;
+  const int g = ok ? gv : 0;
+  T alpha, c, beta;
+  step_scalars(P, alpha, c, beta);
+  const T xv = ok ? P.x[(int64_t)g * P.ldx] : T(0);
+  const T pv = beta != T(0) ? P.prev[(int64_t)g * P.ldo] : T(0);
+  // slots of the node: (bx + {0, x2}) x (by + {0, y2}) x (bz + {0, z2}), as in the fused kernel
+  const int qx = div_p(ix, p), rx = ix - qx * p, qy = div_p(iy, p), ry = iy - qy * p, qz = div_p(iz, p),
+            rz = iz - qz * p;
+  const int bx = qx * P1 + (rx ? rx + 1 : 0), by = qy * P1 + (ry ? ry + 1 : 0), bz = qz * P1 + (rz ? rz + 1 : 0);
+  const bool x2 = rx == 0, y2 = ry == 0, z2 = rz == 0;
+  const T msc = cf.mscale * cf.om[rx] * cf.om[ry] * cf.om[rz];
+  const int S = nc * P1;
+  const int64_t ldc = P.ldc, Sl = (int64_t)S * ldc, S2l = Sl * S;
+  const T* __restrict__ Y0 = P.ycell + (bx + (int64_t)S * (by + (int64_t)S * bz)) * ldc;
+  const T m2 = x2 ? T(1) : T(0);
+  T sum = 0;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int ky = kk & 1, kz = kk >> 1;
+    const bool need = ok && (ky == 0 || y2) && (kz == 0 || z2);
+    const T* ya = Y0 + (need ? ky * Sl + kz * S2l : 0);
+    const T* yb = x2 ? ya + ldc : ya;
+    const T mn = need ? T(1) : T(0);
+    sum = fma(fma(yb[0], m2, ya[0]), mn, sum);
+  }
+  T acc = msc * sum - c * xv;
+  if (tile_fptr) {
+    const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;
+    const T* __restrict__ tv = P.tv + (int64_t)f0 * TR + (int64_t)r * FP;  // this row of the [TR][FP] block
+    for (int f = 0; f < FP; ++f) {
+      const T h = tv[f];
+      acc = fma(h, P.zo[(int64_t)tile_fns[f0 + f] * P.ncr], acc);
+      T q = h * xv;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
+      if (r == 0) P.part[(int64_t)(f0 + f) * P.ncr] = q;
+    }
+  }
+  if (ok) {
+    T o = alpha * acc;
+    if (beta != T(0)) o -= beta * pv;
+    P.out[(int64_t)g * P.ldo] = o;
+  }
+}
+
 // First fold of the tile partials: part2[nu][ch][j] = sum of the partials of function
 // nu with list positions in chunk ch (kReduceChunk entries), in list order within
 // 4 interleaved groups and a fixed 4-way tree.  Chunks past the list hold 0.
@@ -2099,8 +2290,25 @@ bool lanes_offsets_fit(const oefe_op_s* op, const KBatch<T>& kb) {
 }
 
 // cw = 0: planes-in-lanes kernel; 8, 16, 32, 64: plane-per-wave kernel with cw columns per cell
+template <typename T, int P1>
+void launch_cell_cells(const oefe_op_s* op, const KBatch<T>& kb, hipStream_t s) {
+  constexpr int CWc = lanes_cw<P1>();
+  hipLaunchKernelGGL((fe_cell_cells_kernel<T, P1>), dim3((unsigned)cdiv(op->n_cells, 4 * CWc), 1, (unsigned)kb.nk),
+                     dim3(256), 0, s, kb, coef<T>(op), op->nc, op->p, op->n, op->n_cells);
+}
+
 template <typename T, bool CPLX>
 void launch_cell(const oefe_op_s* op, const KBatch<T>& kb, int max_ncr, int cw, hipStream_t s) {
+  if constexpr (!CPLX) {
+    if (max_ncr == 1) {  // one real column: cells in the lanes, whatever the tuned shape
+      switch (op->P1) {
+        case 3: launch_cell_cells<T, 3>(op, kb, s); break;
+        case 4: launch_cell_cells<T, 4>(op, kb, s); break;
+        default: launch_cell_cells<T, 5>(op, kb, s); break;
+      }
+      return;
+    }
+  }
   if (op->uform) {
     // only the planes-in-lanes kernel carries the periodic-function form's first-derivative
     // term; oefe_op_create_uform checks that its 32-bit offsets fit the mesh
@@ -2253,7 +2461,19 @@ int apply_step_batch_impl(const oefe_op_s* const* ops, const KBatch<T>& kb, hipS
     const int ncb = (int)cdiv(nb_all, nbcap);
     const int NB = (int)cdiv(nb_all, ncb);
     if (ovl && !ov->first) (void)hipStreamWaitEvent(s, ov->ev_zo, 0);  // this step's Z^O
-    timed(OEFE_TIMER_NODE, s, [&] { launch_node_fused<T>(op, kb, NB, ncb, s); });
+    // one column: the flat kernel where tiles couple to few functions (the auxiliary-potential
+    // operator, one function per atom: 23 % less time per conjugate-gradient iteration on
+    // diamond64); the Kohn-Sham operator's ~50 functions per tile stay on the matrix cores
+    if (max_ncr == 1 && op->tile_fpmax <= kCol1MaxFunctions) {
+      const int ntiles = tile_count(op->n, op->tile_mode);
+      timed(OEFE_TIMER_NODE, s, [&] {
+        hipLaunchKernelGGL((fe_node_col1_kernel<T>), dim3((unsigned)cdiv(ntiles, 4), 1u, (unsigned)kb.nk), dim3(256), 0, s,
+                           kb, op->nc, op->p, op->n, op->P1, coef<T>(op), op->n_enr > 0 ? op->d.tile_fptr : nullptr,
+                           op->d.tile_fns, ntiles, op->tile_mode);
+      });
+    } else {
+      timed(OEFE_TIMER_NODE, s, [&] { launch_node_fused<T>(op, kb, NB, ncb, s); });
+    }
     if (nO > 0) {
       hipStream_t se = s;
       if (ovl) {

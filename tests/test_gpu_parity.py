@@ -52,7 +52,8 @@ SYSTEMS = {
 
 
 @pytest.mark.parametrize("name,nv", [("single_atom", 8), ("single_atom", 13), ("tiny2", 5), ("p3", 24),
-                                     ("diamond_nc4", 72), ("diamond_nc4", 17)])
+                                     ("diamond_nc4", 72), ("diamond_nc4", 17),
+                                     ("single_atom", 1), ("tiny2", 1), ("p3", 1), ("diamond_nc4", 1)])
 def test_ham_apply_f64(lib, name, nv):
     sysm = SYSTEMS[name]()
     op = OEFEOperator(sysm)
@@ -61,6 +62,20 @@ def test_ham_apply_f64(lib, name, nv):
     X = wl.start_block(op.n_tot, nv, 0)
     Y = lib.ham_apply(gop, _dev(X)).cpu().numpy()
     assert _colrel(Y, op.apply(X)) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["single_atom", "tiny2", "p3", "diamond_nc4"])
+def test_ham_apply_one_column_matches_block(lib, name):
+    """One column (cells in the lanes of the cell stage; at few coupled functions per tile, one wave
+    per tile in the node stage) against the same column inside a block of 9 (columns in the lanes,
+    matrix-core coupling): equal up to the order of the coupling sums."""
+    sysm = SYSTEMS[name]()
+    gop = lib.Operator(sysm)
+    X = wl.start_block(gop.n_tot, 9, 4)
+    Yb = lib.ham_apply(gop, _dev(X)).cpu().numpy()
+    for j in (0, 5):
+        y1 = lib.ham_apply(gop, _dev(np.ascontiguousarray(X[:, j:j + 1]))).cpu().numpy()[:, 0]
+        assert np.abs(y1 - Yb[:, j]).max() <= 1e-13 * np.abs(Yb[:, j]).max(), (name, j)
 
 
 def test_ham_apply_leading_dimension(lib):
@@ -86,12 +101,13 @@ def test_ham_apply_bloch_c128(lib, name, nv):
     assert _colrel(Y, op.apply(X)) < 1e-10
 
 
-def test_ham_apply_f32(lib):
+@pytest.mark.parametrize("nv", [40, 1])
+def test_ham_apply_f32(lib, nv):
     import torch
     sysm = SYSTEMS["diamond_nc4"]()
     op = OEFEOperator(sysm)
     gop = lib.Operator(sysm)
-    X = wl.start_block(op.n_tot, 40, 0)
+    X = wl.start_block(op.n_tot, nv, 0)
     Y = lib.ham_apply(gop, _dev(X, torch.float32)).cpu().numpy().astype(np.float64)
     # float32 arithmetic: relative error a few 1e-7 times the operator's spread
     assert _colrel(Y, op.apply(X.astype(np.float32).astype(np.float64))) < 5e-5
