@@ -1747,7 +1747,7 @@ __global__ __launch_bounds__(256) void fe_node_col1_kernel(KBatch<T> kb, int nc,
                                                            const int32_t* __restrict__ tile_fns, int ntiles, int tm) {
   constexpr int TR = kTileRows;
   const KP<T>& P = kb.k[blockIdx.z];
-  const int t = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  const int t = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform per wave
   if (t >= ntiles) return;  // the whole wave
   const int r = (int)threadIdx.x & 63;
   int x0, y0, z0, ix, iy, iz;
@@ -1781,15 +1781,32 @@ __global__ __launch_bounds__(256) void fe_node_col1_kernel(KBatch<T> kb, int nc,
   }
   T acc = msc * sum - c * xv;
   if (tile_fptr) {
-    const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;
+    const int f0 = tile_fptr[t], FP = tile_fptr[t + 1] - f0;  // a multiple of 4 (padded list)
     const T* __restrict__ tv = P.tv + (int64_t)f0 * TR + (int64_t)r * FP;  // this row of the [TR][FP] block
-    for (int f = 0; f < FP; ++f) {
-      const T h = tv[f];
-      acc = fma(h, P.zo[(int64_t)tile_fns[f0 + f] * P.ncr], acc);
-      T q = h * xv;
+    // four functions at a time: their loads issued together, their butterflies interleaved
+    for (int fb = 0; fb < FP; fb += 4) {
+      T h[4], z[4], q[4];
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
-      if (r == 0) P.part[(int64_t)(f0 + f) * P.ncr] = q;
+      for (int i = 0; i < 4; ++i) {
+        // padding entries of the list hold -1 (and zero coupling values): Z^O row 0, replaced by 0
+        const int fn = tile_fns[f0 + fb + i];
+        h[i] = tv[fb + i];
+        const T zl = P.zo[(int64_t)max(fn, 0) * P.ncr];
+        z[i] = fn >= 0 ? zl : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc = fma(h[i], z[i], acc);
+        q[i] = h[i] * xv;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] += __shfl_xor(q[i], o);
+      if (r == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) P.part[(int64_t)(f0 + fb + i) * P.ncr] = q[i];
+      }
     }
   }
   if (ok) {
