@@ -1629,14 +1629,21 @@ __global__ __launch_bounds__(256) void dot1_partial_kernel(const T* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// out = sum_j f_j sum_c part[c][j]: one thread per column, the chunks in order; a single column
+// (the conjugate-gradient and Lanczos dots) spreads its chunks over the threads instead (thread t
+// adds chunks t, t + 256, ... in order), both followed by the same fixed tree
 __global__ void dot_final_kernel(const double* __restrict__ part, int nchunks, int nv, const double* __restrict__ f,
                                  double* __restrict__ out) {
   __shared__ double red[256];
   double s = 0;
-  for (int j = threadIdx.x; j < nv; j += blockDim.x) {
-    double cs = 0;
-    for (int c = 0; c < nchunks; ++c) cs += part[(int64_t)c * nv + j];
-    s += (f ? f[j] : 1.0) * cs;
+  if (nv == 1) {
+    for (int c = threadIdx.x; c < nchunks; c += blockDim.x) s += part[c];
+  } else {
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
+      double cs = 0;
+      for (int c = 0; c < nchunks; ++c) cs += part[(int64_t)c * nv + j];
+      s += (f ? f[j] : 1.0) * cs;
+    }
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -1644,7 +1651,7 @@ __global__ void dot_final_kernel(const double* __restrict__ part, int nchunks, i
     if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) *out = nv == 1 && f ? f[0] * red[0] : red[0];
 }
 
 template <typename S, typename D>
