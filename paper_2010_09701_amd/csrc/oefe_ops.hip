@@ -1433,7 +1433,7 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
     colok[nb] = col < ncr;
     colc[nb] = colok[nb] ? col : ncr - 1;
   }
-  // node-slot grid columns, not clamped: a row of the grid (ldc >= ncr, a multiple of 8) is
+  // node-slot grid columns, not clamped: a row of the grid (ldc >= ncr; a multiple of 8, or 1) is
   // followed by the next row or by the grid's padding (one row plus 16 kNodeNBMax elements,
   // slot_grid_elems), so every column this block reads, below ncr + 16 NB, stays in the
   // allocation; values past ncr only reach lanes whose output is not stored.  The loads of a
@@ -2592,7 +2592,10 @@ static size_t slot_grid_elems(const oefe_op_s* op, int ldc) {
 
 size_t step_work_bytes(const oefe_op_s* op, int elem_bytes, bool cplx, int nv, int* ldc_out) {
   const int ncr = cplx ? 2 * nv : nv;
-  const int ldc = (int)cdiv(ncr, 8) * 8;
+  // rows of the node-slot grid: a multiple of 8 columns, except one real column, whose slots
+  // are then contiguous (every cell kernel stores only columns below ncr; the node kernels'
+  // reads past the column stay inside the grid's padding)
+  const int ldc = ncr == 1 ? 1 : (int)cdiv(ncr, 8) * 8;
   if (ldc_out) *ldc_out = ldc;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   size_t bytes = 0;
