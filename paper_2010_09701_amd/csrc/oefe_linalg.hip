@@ -1607,26 +1607,39 @@ __global__ void dot_partial_kernel(const T* __restrict__ A, int64_t lda, const T
 }
 
 // one column: workgroup b sums the rows of its contiguous chunk (thread-strided, then a fixed tree)
+// One column's dot product over a chunk of rows: 1024 threads, each adding rows t, t + 2048, ...
+// and t + 1024, t + 3072, ... into two sums (two loads in flight), then a fixed butterfly per
+// wave and the 16 wave sums in order by one thread
 template <typename T, bool CPLX>
-__global__ __launch_bounds__(256) void dot1_partial_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
-                                                           int64_t ldb, int64_t n, int64_t rows_per_chunk,
-                                                           double* __restrict__ part) {
+__global__ __launch_bounds__(1024) void dot1_partial_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                                            int64_t ldb, int64_t n, int64_t rows_per_chunk,
+                                                            double* __restrict__ part) {
   constexpr int E = CPLX ? 2 : 1;
-  __shared__ double red[256];
+  __shared__ double red[16];
   const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk, g1 = min(n, g0 + rows_per_chunk);
-  double s = 0;
-  for (int64_t g = g0 + threadIdx.x; g < g1; g += 256) {
+  auto term = [&](int64_t g) {
     const T* a = A + g * lda * E;
     const T* b = B + g * ldb * E;
-    s += (double)a[0] * (double)b[0] + (CPLX ? (double)a[E - 1] * (double)b[E - 1] : 0.0);
+    return (double)a[0] * (double)b[0] + (CPLX ? (double)a[E - 1] * (double)b[E - 1] : 0.0);
+  };
+  double s0 = 0, s1 = 0;
+  int64_t g = g0 + threadIdx.x;
+  for (; g + 1024 < g1; g += 2048) {
+    s0 += term(g);
+    s1 += term(g + 1024);
   }
-  red[threadIdx.x] = s;
+  if (g < g1) s0 += term(g);
+  double s = s0 + s1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += red[w];
+    part[blockIdx.x] = t;
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // out = sum_j f_j sum_c part[c][j]: one thread per column, the chunks in order; a single column
@@ -2423,13 +2436,13 @@ template <typename T>
 int dot_columns(bool cplx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n, int nv, const double* f,
                 double* out, double* scratch, hipStream_t s) {
   if (nv == 1) {
-    // a single column: 256 threads per chunk (the per-column kernel would use one lane of 64)
+    // a single column: 1024 threads per chunk (the per-column kernel would use one lane of 64)
     const int nch = gram_chunks(n);
     const int64_t rpc = cdiv(n, nch);
     if (cplx)
-      hipLaunchKernelGGL((dot1_partial_kernel<T, true>), dim3(nch), dim3(256), 0, s, A, lda, B, ldb, n, rpc, scratch);
+      hipLaunchKernelGGL((dot1_partial_kernel<T, true>), dim3(nch), dim3(1024), 0, s, A, lda, B, ldb, n, rpc, scratch);
     else
-      hipLaunchKernelGGL((dot1_partial_kernel<T, false>), dim3(nch), dim3(256), 0, s, A, lda, B, ldb, n, rpc, scratch);
+      hipLaunchKernelGGL((dot1_partial_kernel<T, false>), dim3(nch), dim3(1024), 0, s, A, lda, B, ldb, n, rpc, scratch);
     hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, scratch, nch, 1, f, out);
     return check();
   }
