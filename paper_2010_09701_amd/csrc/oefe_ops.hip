@@ -1739,7 +1739,9 @@ __global__ __launch_bounds__(256, NB == 4 ? 3 : 2) void fe_node_fused_kernel(KBa
 // Lanczos): one wave per coupling tile, lane = tile row, no LDS.  The slot gather takes the
 // same slots in the same order as fe_node_fused_kernel; the tile's coupling row is applied with
 // one product per function in list order, and each function's partial of H^co* x is a fixed
-// butterfly over the 64 rows.  Launched only when every operator of the step has one column.
+// butterfly over the 64 rows.  Launched when every operator of the step has one column and the
+// tiles couple to at most kCol1MaxFunctions functions (per-function butterflies cost more than
+// the matrix-core products beyond that).
 constexpr int kCol1MaxFunctions = 24;  // functions per tile up to which one column takes fe_node_col1_kernel
 template <typename T>
 __global__ __launch_bounds__(256) void fe_node_col1_kernel(KBatch<T> kb, int nc, int p, int n, int P1, CellCoef<T> cf,
@@ -1994,6 +1996,34 @@ __global__ __launch_bounds__(1024) void enr_chain_kernel(KBatch<T> kb, int64_t N
     }
   };
   // W'
+  if (m == 1) {
+    // one column: the TC threads of a row, which would all compute the same entry, split its
+    // chunks (thread jl adds chunks jl, jl + TC, ... in order) into Os, then add them in order
+    for (int t = tid; t < n * TC; t += nth) {
+      const int i = t / TC, jl = t - i * TC;
+      const T* p2 = P.part2 + (int64_t)i * P.nch * ncr;
+      T wr = 0, wi = 0;
+      for (int ch = jl; ch < P.nch; ch += TC) {
+        wr += p2[(int64_t)ch * ncr];
+        if (CPLX) wi += p2[(int64_t)ch * ncr + 1];
+      }
+      Os[(size_t)t * E] = wr;
+      if (CPLX) Os[(size_t)t * E + 1] = wi;
+    }
+    __syncthreads();
+    for (int t = tid; t < n * TC; t += nth) {
+      const int i = t / TC, jl = t - i * TC;
+      T wr = 0, wi = 0;
+      for (int q = 0; q < TC; ++q) {
+        wr += Os[((size_t)i * TC + q) * E];
+        if (CPLX) wi += Os[((size_t)i * TC + q) * E + 1];
+      }
+      T sr, si;
+      dot(Hs, Zs, i, jl, sr, si);
+      Ws[(size_t)t * E] = wr + sr;
+      if (CPLX) Ws[(size_t)t * E + 1] = wi + si;
+    }
+  } else {
   for (int t = tid; t < n * TC; t += nth) {
     const int i = t / TC, jl = t - i * TC, j = min(j0 + jl, m - 1);
     const T* p2 = P.part2 + (int64_t)i * P.nch * ncr + (int64_t)j * E;
@@ -2020,6 +2050,7 @@ __global__ __launch_bounds__(1024) void enr_chain_kernel(KBatch<T> kb, int64_t N
     dot(Hs, Zs, i, jl, sr, si);
     Ws[(size_t)t * E] = wr + sr;
     if (CPLX) Ws[(size_t)t * E + 1] = wi + si;
+  }
   }
   __syncthreads();
   // out^O
