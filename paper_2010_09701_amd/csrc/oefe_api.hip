@@ -2368,15 +2368,40 @@ __global__ void pois_start_kernel(const double* __restrict__ v, double* __restri
   pv[i] = v[i];
 }
 
-// x += alpha p, r -= alpha q with alpha = rr / pq (0 when pq <= 0)
-__global__ void pois_step_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ pv,
-                                 const double* __restrict__ q, const double* __restrict__ rr,
-                                 const double* __restrict__ pq, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// x += alpha p, r -= alpha q with alpha = rr / pq (0 when pq <= 0), and the chunk partials of
+// r_new . r_new in the chunking and summation order of the one-column dot product
+// (dot1_chunk_count, dot1_final): the step and the dot in one pass over r, the dot's bits
+__global__ __launch_bounds__(1024) void pois_step_rr_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                            const double* __restrict__ pv, const double* __restrict__ q,
+                                                            const double* __restrict__ rr, const double* __restrict__ pq,
+                                                            int64_t n, int64_t rows_per_chunk, double* __restrict__ part) {
+  __shared__ double red[16];
   const double al = pq[0] > 0.0 ? rr[0] / pq[0] : 0.0;
-  x[i] += al * pv[i];
-  r[i] -= al * q[i];
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per_chunk, g1 = min(n, g0 + rows_per_chunk);
+  auto step = [&](int64_t g) {
+    x[g] += al * pv[g];
+    const double rn = r[g] - al * q[g];
+    r[g] = rn;
+    return rn * rn + 0.0;  // the dot kernel's term, written the same way
+  };
+  double s0 = 0, s1 = 0;
+  int64_t g = g0 + threadIdx.x;
+  for (; g + 1024 < g1; g += 2048) {
+    s0 += step(g);
+    s1 += step(g + 1024);
+  }
+  if (g < g1) s0 += step(g);
+  double s = s0 + s1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
 }
 
 // p = r + beta p with beta = rr_new / rr
@@ -2542,13 +2567,15 @@ static int poisson_solve_impl(oefe_op pop, const double* rho, const double* rho_
   int it = 0;
   double rel = 1.0;
   bool done = false;
+  const int nch1 = dot1_chunk_count(n);  // the r . r partials of pois_step_rr_kernel fill nch1 <= 128 of dscr
   while (!done && it < max_iter) {
     const int k = it & 1;
     rc = apply_step<double>(op, false, L.p, 1, nullptr, L.q, 1, 1, 1.0, 0.0, 0.0, L.step, s);
     if (!rc) rc = dot_columns<double>(false, L.p, 1, L.q, 1, n, 1, nullptr, L.sc + 2, L.dscr, s);
     if (rc) return fail(rc, "oefe_poisson_solve: kernel launch failed");
-    hipLaunchKernelGGL(pois_step_kernel, blocks(n), dim3(256), 0, s, L.x, L.r, L.p, L.q, L.sc + k, L.sc + 2, n);
-    rc = dot_columns<double>(false, L.r, 1, L.r, 1, n, 1, nullptr, L.sc + (k ^ 1), L.dscr, s);
+    hipLaunchKernelGGL(pois_step_rr_kernel, dim3((unsigned)nch1), dim3(1024), 0, s, L.x, L.r, L.p, L.q, L.sc + k,
+                       L.sc + 2, n, (n + nch1 - 1) / nch1, L.dscr);
+    rc = dot1_final(L.dscr, nch1, L.sc + (k ^ 1), s);
     if (rc) return fail(rc, "oefe_poisson_solve: kernel launch failed");
     hipLaunchKernelGGL(pois_dir_kernel, blocks(n), dim3(256), 0, s, L.p, L.r, L.sc + (k ^ 1), L.sc + k, n);
     ++it;

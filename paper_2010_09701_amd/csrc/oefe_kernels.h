@@ -104,6 +104,12 @@ int copy_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t
 template <typename T>
 int dot_columns(bool cplx, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n, int nv, const double* f,
                 double* out, double* scratch, hipStream_t s);
+// the one-column dot product of dot_columns in two parts, for kernels that form its chunk
+// partials themselves: the number of row chunks (each cdiv(n, chunks) rows; the partial of a chunk
+// sums rows t, t + 2048, ... and t + 1024, t + 3072, ... of thread t of 1024, then the 16 wave
+// sums of fixed butterflies in order), and the final sum of the partials into *out
+int dot1_chunk_count(int64_t n);
+int dot1_final(const double* part, int nch, double* out, hipStream_t s);
 // dst (ldd) <- src (lds), n_rows x ncols real elements, with float/double conversion
 int cast_block(const void* src, bool src_f32, void* dst, bool dst_f32, int64_t n_rows, int64_t lds, int64_t ldd,
                int ncols, hipStream_t s);

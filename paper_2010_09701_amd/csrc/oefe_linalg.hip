@@ -2456,6 +2456,13 @@ int dot_columns(bool cplx, const T* A, int64_t lda, const T* B, int64_t ldb, int
   hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, scratch, nch, nv, f, out);
   return check();
 }
+int dot1_chunk_count(int64_t n) { return gram_chunks(n); }
+
+int dot1_final(const double* part, int nch, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(256), 0, s, part, nch, 1, nullptr, out);
+  return check();
+}
+
 template int dot_columns<double>(bool, const double*, int64_t, const double*, int64_t, int64_t, int, const double*,
                                  double*, double*, hipStream_t);
 template int dot_columns<float>(bool, const float*, int64_t, const float*, int64_t, int64_t, int, const double*,
