@@ -2195,37 +2195,90 @@ __global__ __launch_bounds__(64 * P1) void density_kernel(
       for (int az = 0; az < P1; ++az) s += cf.B1[qz][az] * t[az * P1 + qy];
       psi[qz * P1 + qy] = (double)s;
     }
-  // enrichment part
-  if (valid) {
-    for (int64_t k = cph_ptr[e]; k < cph_ptr[e + 1]; ++k) {
+  // enrichment part: the support blocks of the cell in turn; a block's values at the cell's points
+  // (all its functions) are staged in LDS by the whole workgroup, double-buffered: the next
+  // block's values and Z^O entries are loaded while this block's are summed; the sums run in the
+  // same order as one function after the other
+  {
+    constexpr int E = CPLX ? 2 : 1;
+    constexpr int kFn = 8;                                     // enrichment functions per atom at most
+    constexpr int kPer = (NQ * kFn * E + 64 * P1 - 1) / (64 * P1);  // staged values per thread at most
+    // two buffers of NQ FMAX E doubles: 2 x 125 x 8 x 2 x 8 B <= NQ x 64 x sizeof(T) for float and double
+    double* stg = reinterpret_cast<double*>(&lds[0][0]);
+    const int64_t k0 = cph_ptr[e], k1 = cph_ptr[e + 1];
+    const int cnt = NQ * FMAX * E, nth = 64 * P1, tid = (int)threadIdx.x;
+    double pre[kPer], zr[kFn], zi[kFn], zrn[kFn], zin[kFn];
+    int fn_next0 = 0, nf_next = 0;
+    auto fetch = [&](int64_t k) {  // block k's values into pre[], its Z^O entries into zrn / zin
       const int b = cph_blk[k];
       const int64_t off = cph_off[k];
-      const int f0 = blk_fn0[b], nf = blk_nf[b];
-      for (int f = 0; f < nf; ++f) {
-        if constexpr (!CPLX) {
-          const double z = (double)zo[(int64_t)(f0 + f) * ncr + j];
 #pragma unroll
-          for (int qz = 0; qz < P1; ++qz)
+      for (int i = 0; i < kPer; ++i) {
+        const int idx = tid + i * nth;
+        pre[i] = idx < cnt ? phi[off * cnt + idx] : 0.0;
+      }
+      fn_next0 = blk_fn0[b];
+      nf_next = blk_nf[b];
 #pragma unroll
-            for (int qy = 0; qy < P1; ++qy) {
-              const int q = (qz * P1 + qy) * P1 + qx;
-              psi[qz * P1 + qy] += phi[(off * NQ + q) * FMAX + f] * z;
-            }
-        } else {
-          const int v2 = j & ~1;
-          const double zr = (double)zo[(int64_t)(f0 + f) * ncr + v2];
-          const double zi = (double)zo[(int64_t)(f0 + f) * ncr + v2 + 1];
-#pragma unroll
-          for (int qz = 0; qz < P1; ++qz)
-#pragma unroll
-            for (int qy = 0; qy < P1; ++qy) {
-              const int q = (qz * P1 + qy) * P1 + qx;
-              const double pr = phi[2 * ((off * NQ + q) * FMAX + f)];
-              const double pi = phi[2 * ((off * NQ + q) * FMAX + f) + 1];
-              psi[qz * P1 + qy] += (j & 1) ? (pr * zi + pi * zr) : (pr * zr - pi * zi);
-            }
+      for (int f = 0; f < kFn; ++f) {
+        zrn[f] = zin[f] = 0.0;
+        if (valid && f < nf_next) {
+          if constexpr (!CPLX) {
+            zrn[f] = (double)zo[(int64_t)(fn_next0 + f) * ncr + j];
+          } else {
+            zrn[f] = (double)zo[(int64_t)(fn_next0 + f) * ncr + (j & ~1)];
+            zin[f] = (double)zo[(int64_t)(fn_next0 + f) * ncr + (j & ~1) + 1];
+          }
         }
       }
+    };
+    auto park = [&](double* buf) {
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int idx = tid + i * nth;
+        if (idx < cnt) buf[idx] = pre[i];
+      }
+    };
+    if (k0 < k1) fetch(k0);
+    __syncthreads();  // the transpose is no longer read
+    if (k0 < k1) park(stg);
+    for (int64_t k = k0; k < k1; ++k) {
+      double* cur = stg + ((k - k0) & 1) * cnt;
+      const int nf = nf_next;
+#pragma unroll
+      for (int f = 0; f < kFn; ++f) {
+        zr[f] = zrn[f];
+        zi[f] = zin[f];
+      }
+      __syncthreads();  // block k's values parked; the other buffer (block k - 1) no longer read
+      if (k + 1 < k1) fetch(k + 1);
+      if (valid) {
+#pragma unroll
+        for (int f = 0; f < kFn; ++f) {
+          if (f >= nf) break;
+          if constexpr (!CPLX) {
+            const double z = zr[f];
+#pragma unroll
+            for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+              for (int qy = 0; qy < P1; ++qy) {
+                const int q = (qz * P1 + qy) * P1 + qx;
+                psi[qz * P1 + qy] += cur[q * FMAX + f] * z;
+              }
+          } else {
+#pragma unroll
+            for (int qz = 0; qz < P1; ++qz)
+#pragma unroll
+              for (int qy = 0; qy < P1; ++qy) {
+                const int q = (qz * P1 + qy) * P1 + qx;
+                const double pr = cur[2 * (q * FMAX + f)];
+                const double pi = cur[2 * (q * FMAX + f) + 1];
+                psi[qz * P1 + qy] += (j & 1) ? (pr * zi[f] + pi * zr[f]) : (pr * zr[f] - pi * zi[f]);
+              }
+          }
+        }
+      }
+      if (k + 1 < k1) park(stg + ((k + 1 - k0) & 1) * cnt);
     }
   }
   const double fv = valid ? fw[CPLX ? (j >> 1) : j] : 0.0;
