@@ -37,7 +37,8 @@ def _colrel(A, B):
     return float((np.linalg.norm(A - B, axis=0) / np.linalg.norm(B, axis=0)).max())
 
 
-@pytest.mark.parametrize("name,nv", [("single_atom", 8), ("p3", 24), ("diamond_nc4", 40)])
+@pytest.mark.parametrize("name,nv", [("single_atom", 8), ("p3", 24), ("diamond_nc4", 40), ("single_atom", 1),
+                                     ("diamond_nc4", 1)])
 def test_ham_apply_bf16(lib, name, nv):
     import torch
     sysm = {"single_atom": lambda: wl.single_atom(),
